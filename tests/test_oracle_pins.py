@@ -1,0 +1,344 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+Each check below is either a value printed in the paper (worked examples under
+tests/golden/), a closed form, a textbook special case (Johnson's rule for two
+machines, the critical-path characterisation of the makespan), or brute force
+over all schedules of tiny instances.  A dropped term, a wrong sign or index,
+or a transposed operand in the oracle fails at least one of them.
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2012_09511_amd import inputs
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _all_nodes(n, rng, count):
+    """Random nodes (perm, d1, d2) with at least one unscheduled job."""
+    out = []
+    for _ in range(count):
+        perm = rng.permutation(n).astype(np.uint8)
+        d = int(rng.integers(0, n))
+        d1 = int(rng.integers(0, d + 1))
+        out.append((perm, d1, d - d1))
+    return out
+
+
+def _path_makespan(p, seq):
+    """Makespan as the longest monotone lattice path through the (job, machine)
+    grid of the sequence: the critical-path characterisation, enumerated."""
+    n, m = len(seq), p.shape[1]
+    best = 0
+    # a path from (0,0) to (n-1,m-1) is fixed by the n-1 'next job' moves
+    # interleaved among n+m-2 moves
+    for downs in itertools.combinations(range(n + m - 2), n - 1):
+        i = k = 0
+        tot = int(p[seq[0], 0])
+        ds = set(downs)
+        for s in range(n + m - 2):
+            if s in ds:
+                i += 1
+            else:
+                k += 1
+            tot += int(p[seq[i], k])
+        best = max(best, tot)
+    return best
+
+
+def _johnson2(p):
+    """Johnson's two-machine rule (textbook): jobs with a <= b first in
+    ascending a, then the rest in descending b."""
+    n = p.shape[0]
+    s1 = sorted([j for j in range(n) if p[j, 0] <= p[j, 1]], key=lambda j: p[j, 0])
+    s2 = sorted([j for j in range(n) if p[j, 0] > p[j, 1]], key=lambda j: -p[j, 1])
+    return np.array(s1 + s2, dtype=np.uint8)
+
+
+# ---------------------------------------------------------------- makespan
+
+@pytest.mark.parametrize("n,m,seed", [(4, 3, 1), (5, 4, 2), (3, 6, 3), (6, 2, 4), (1, 5, 5)])
+def test_makespan_is_longest_grid_path(n, m, seed):
+    p = inputs.instance(n, m, seed)
+    rng = np.random.default_rng(seed)
+    for _ in range(5):
+        seq = rng.permutation(n).astype(np.uint8)
+        assert oracle.makespan(p, seq) == _path_makespan(p, seq)
+
+
+def test_makespan_closed_forms():
+    p = inputs.instance(7, 1, 11)
+    assert oracle.makespan(p, np.arange(7)) == int(p.sum())           # one machine
+    p = inputs.instance(1, 9, 12)
+    assert oracle.makespan(p, [0]) == int(p.sum())                     # one job
+    p = inputs.instance(6, 2, 13)                                      # two machines
+    seq = np.random.default_rng(0).permutation(6)
+    a, b = p[seq, 0].astype(int), p[seq, 1].astype(int)
+    closed = max(a[: k + 1].sum() + b[k:].sum() for k in range(6))
+    assert oracle.makespan(p, seq) == closed
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_reversibility(seed):
+    # makespan of pi on p equals that of reverse(pi) with the machine order reversed
+    p = inputs.instance(8, 5, seed)
+    seq = np.random.default_rng(seed).permutation(8).astype(np.uint8)
+    assert oracle.makespan(p, seq) == oracle.makespan(p[:, ::-1], seq[::-1])
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_front_back_split(seed):
+    # C_max(sigma1 sigma2) = max_k front(sigma1)[k] + back(sigma2)[k]  (path decomposition)
+    n, m = 9, 6
+    p = inputs.instance(n, m, seed)
+    seq = np.random.default_rng(seed).permutation(n).astype(np.uint8)
+    for cut in range(n + 1):
+        f = oracle.front(p, seq[:cut])
+        b = oracle.back(p, seq[cut:])
+        assert int((f + b).max()) == oracle.makespan(p, seq)
+    # back of one job = remaining row sums; back(s)[0] = makespan of s alone
+    j = seq[0]
+    assert list(oracle.back(p, [j])) == list(np.cumsum(p[j, ::-1])[::-1])
+    assert oracle.back(p, seq)[0] == oracle.makespan(p, seq)
+
+
+def test_johnson_two_machines_is_optimal():
+    for seed in range(6):
+        p = inputs.instance(7, 2, 100 + seed)
+        opt, _ = oracle.bruteforce(p)
+        assert oracle.makespan(p, _johnson2(p)) == opt
+
+
+# ------------------------------------------------------------------- LB1
+
+def test_lb1_worked_example_fig3():
+    g = json.load(open(os.path.join(GOLD, "lb1_fig3.json")))
+    assert oracle.lb1_parts(g["front"], g["remaining"], g["back"]) == g["expected_lb1"]
+
+
+@pytest.mark.parametrize("n,m,seed", [(6, 3, 1), (7, 4, 2), (6, 5, 3), (5, 1, 4)])
+def test_bounds_valid_against_brute_force(n, m, seed):
+    """LB <= best completion of every node; LB2 >= LB1; leaf LB = C_max."""
+    p = inputs.instance(n, m, seed)
+    rng = np.random.default_rng(seed)
+    for perm, d1, d2 in _all_nodes(n, rng, 40):
+        best, _ = oracle.best_completion(p, perm, d1, d2)
+        l1 = oracle.node_bound(p, perm, d1, d2, oracle.LB1)
+        assert l1 <= best
+        if m >= 2:
+            l2 = oracle.node_bound(p, perm, d1, d2, oracle.LB2_FULL)
+            assert l1 <= l2 <= best
+        # the leaf reached by scheduling U in list order
+        leaf = oracle.node_bound(p, perm, n - d2, d2, oracle.LB1)
+        assert leaf == oracle.makespan(p, perm)
+        if m >= 2:
+            assert oracle.node_bound(p, perm, d1 + (n - d1 - d2), d2,
+                                     oracle.LB2_FULL) == oracle.makespan(p, perm)
+
+
+@pytest.mark.parametrize("kind", [oracle.LB1, oracle.LB2_FULL])
+def test_bounds_monotone_parent_to_child(kind):
+    n, m = 8, 5
+    p = inputs.instance(n, m, 77)
+    perm, d1, d2 = inputs.random_pool(n, 60, 78)
+    for i in range(60):
+        lb, _, _ = oracle.bound_children(p, perm[i:i + 1], d1[i:i + 1], d2[i:i + 1], kind)
+        parent = oracle.node_bound(p, perm[i], int(d1[i]), int(d2[i]), kind)
+        r = n - int(d1[i]) - int(d2[i])
+        assert (lb[0, :, :r] >= parent).all()
+
+
+# ------------------------------------------------------------------- LB2
+
+def test_lb2_exact_for_two_machines():
+    """m = 2: one pair, no lag; Johnson is optimal, so LB2 is the best completion."""
+    for seed in range(4):
+        n = 7
+        p = inputs.instance(n, 2, 200 + seed)
+        rng = np.random.default_rng(seed)
+        for perm, d1, d2 in _all_nodes(n, rng, 25):
+            best, _ = oracle.best_completion(p, perm, d1, d2)
+            assert oracle.node_bound(p, perm, d1, d2, oracle.LB2_FULL) == best
+        opt, _ = oracle.bruteforce(p)
+        assert oracle.node_bound(p, np.arange(n), 0, 0, oracle.LB2_FULL) == opt
+
+
+def test_pair_johnson_with_lags_is_optimal():
+    """The sorted two-machine value equals the minimum over every job order."""
+    rng = np.random.default_rng(5)
+    for t in range(60):
+        n, m = 7, int(rng.integers(2, 7))
+        p = inputs.instance(n, m, 300 + t, "correlated" if t % 3 == 0 else "uniform")
+        u = int(rng.integers(0, m - 1))
+        v = int(rng.integers(u + 1, m))
+        jobs = rng.permutation(n)[: int(rng.integers(1, n + 1))]
+        hu, hv, tu, tv = (int(x) for x in rng.integers(0, 200, size=4))
+        hv += hu
+        a = oracle.pair_value(p, jobs, u, v, hu, hv, tu, tv)
+        b = oracle.pair_value(p, jobs, u, v, hu, hv, tu, tv, brute=True)
+        assert a == b
+
+
+def test_pair_value_tie_invariance():
+    """Equal Johnson keys in any order give the same value (ties on purpose)."""
+    rng = np.random.default_rng(9)
+    for t in range(30):
+        n, m = 7, 4
+        p = rng.integers(1, 4, size=(n, m)).astype(np.int32)   # many equal keys
+        jobs = rng.permutation(n)
+        for u, v in [(0, 1), (0, 3), (1, 3)]:
+            a = oracle.pair_value(p, jobs, u, v, 3, 5, 2, 0)
+            b = oracle.pair_value(p, jobs, u, v, 3, 5, 2, 0, brute=True)
+            assert a == b
+
+
+def test_pairs_alone_cover_lb1():
+    """Every machine's LB1 term is the u-tail or v-tail term of some pair, so
+    the maximum over all pair values alone (without LB1) is >= LB1 (m >= 2)."""
+    n, m = 8, 5
+    p = inputs.instance(n, m, 61)
+    perm, d1, d2 = inputs.random_pool(n, 40, 62)
+    for i in range(40):
+        a, b = int(d1[i]), int(d2[i])
+        U = perm[i, a:n - b]
+        C1 = oracle.front(p, perm[i, :a])
+        C2 = oracle.back(p, perm[i, n - b:])
+        best = max(oracle.pair_value(p, U, u, v, C1[u], C1[v], C2[u], C2[v])
+                   for u in range(m) for v in range(u + 1, m))
+        assert best >= oracle.node_bound(p, perm[i], a, b, oracle.LB1)
+        assert best == oracle.node_bound(p, perm[i], a, b, oracle.LB2_FULL)
+
+
+def test_subset_between_lb1_and_full():
+    n, m = 9, 6
+    p = inputs.instance(n, m, 41)
+    perm, d1, d2 = inputs.random_pool(n, 50, 42)
+    rng = np.random.default_rng(43)
+    P = m * (m - 1) // 2
+    for i in range(50):
+        mask = np.zeros(1, dtype=np.uint32)
+        for b in rng.choice(P, size=int(rng.integers(0, P + 1)), replace=False):
+            mask[0] |= np.uint32(1 << int(b))
+        l1 = oracle.node_bound(p, perm[i], int(d1[i]), int(d2[i]), oracle.LB1)
+        ls = oracle.node_bound(p, perm[i], int(d1[i]), int(d2[i]), oracle.LB2_SUBSET, mask)
+        lf, ap = oracle.node_bound(p, perm[i], int(d1[i]), int(d2[i]), oracle.LB2_FULL,
+                                   with_argpair=True)
+        assert l1 <= ls <= lf
+        # a subset holding the full bound's argmax pair reaches the full bound
+        one = np.zeros(1, dtype=np.uint32)
+        one[0] = np.uint32(1 << ap)
+        assert oracle.node_bound(p, perm[i], int(d1[i]), int(d2[i]), oracle.LB2_SUBSET,
+                                 one) == lf
+
+
+# ----------------------------------------------------------- MinMin / prune
+
+def test_minmin_worked_example_fig2():
+    g = json.load(open(os.path.join(GOLD, "minmin_fig2.json")))
+    d = oracle.minmin(g["lb_fwd"], g["lb_bwd"])
+    assert d == (1 if g["expected_dir"] == "backward" else 0)
+    chosen = g["lb_bwd"] if d == 1 else g["lb_fwd"]
+    other = g["lb_fwd"] if d == 1 else g["lb_bwd"]
+    assert sum(x >= g["ub"] for x in chosen) == g["expected_pruned_chosen"]
+    assert sum(x >= g["ub"] for x in other) == g["expected_pruned_other"]
+
+
+def test_minmin_tie_rules():
+    # equal counts of the minimum: larger sum wins; equal sums: forward
+    assert oracle.minmin([5, 9], [5, 10]) == 1
+    assert oracle.minmin([5, 10], [5, 9]) == 0
+    assert oracle.minmin([5, 9], [5, 9]) == 0
+    assert oracle.minmin([7], [7]) == 0
+
+
+def test_prune_at_equality():
+    """A child whose LB equals the incumbent is pruned: only strictly better
+    schedules are sought (the critical tree holds the nodes with LB < optimum)."""
+    n, m = 7, 4
+    p = inputs.instance(n, m, 5)
+    perm, d1, d2 = inputs.random_pool(n, 20, 6)
+    for kind in (oracle.LB1, oracle.LB2_FULL):
+        lb, _, _ = oracle.bound_children(p, perm, d1, d2, kind)
+        for i in range(20):
+            ub = int(lb[i, 0, 0])
+            _, pr, _ = oracle.bound_children(p, perm[i:i + 1], d1[i:i + 1], d2[i:i + 1], kind,
+                                             ub=ub)
+            assert pr[0, 0, 0] == 1
+            _, pr, _ = oracle.bound_children(p, perm[i:i + 1], d1[i:i + 1], d2[i:i + 1], kind,
+                                             ub=ub + 1)
+            assert pr[0, 0, 0] == 0
+
+
+def test_bound_children_layout_and_prune():
+    n, m = 7, 4
+    p = inputs.instance(n, m, 3)
+    perm, d1, d2 = inputs.random_pool(n, 30, 4)
+    for kind in (oracle.LB1, oracle.LB2_FULL):
+        lb, pr, dr = oracle.bound_children(p, perm, d1, d2, kind, ub=300)
+        for i in range(30):
+            r = n - int(d1[i]) - int(d2[i])
+            assert (lb[i, :, r:] == oracle.INT32_MAX).all() and (pr[i, :, r:] == 1).all()
+            assert ((lb[i, :, :r] >= 300) == (pr[i, :, :r] == 1)).all()
+            assert dr[i] == oracle.minmin(lb[i, 0, :r], lb[i, 1, :r])
+            # forward child of slot 0 is (sigma1 j, sigma2) with j = perm[d1]
+            j = perm[i, d1[i]]
+            child = np.concatenate([perm[i, :d1[i]], [j],
+                                    np.delete(perm[i, d1[i]:n - d2[i]], 0),
+                                    perm[i, n - d2[i]:]]).astype(np.uint8)
+            assert lb[i, 0, 0] == oracle.node_bound(p, child, int(d1[i]) + 1, int(d2[i]), kind)
+
+
+# --------------------------------------------------------------- search
+
+@pytest.mark.parametrize("seed", range(1, 33))
+def test_search_optimum_equals_brute_force_10x5(seed):
+    """Plain B&B with LB1 on n=10, m=5, uniform [1,99], incumbent from NEH."""
+    p = inputs.instance(10, 5, seed)
+    opt, _ = oracle.bruteforce(p)
+    ub0, _ = oracle.neh(p)
+    assert ub0 >= opt
+    r = oracle.search(p, ub0 + 1, oracle.LB1)
+    assert r["proven"] and r["found"] and r["best"] == opt
+    assert oracle.makespan(p, r["perm"]) == opt
+    assert sorted(r["perm"]) == list(range(10))
+    if seed <= 8:
+        r2 = oracle.search(p, ub0 + 1, oracle.LB2_FULL)
+        assert r2["best"] == opt and r2["nodes"] <= r["nodes"]
+
+
+def test_search_two_machines_equals_johnson():
+    for seed in range(3):
+        p = inputs.instance(9, 2, 400 + seed)
+        opt = oracle.makespan(p, _johnson2(p))
+        for kind in (oracle.LB1, oracle.LB2_FULL):
+            r = oracle.search(p, 10**9, kind)
+            assert r["best"] == opt and r["proven"]
+        # LB2 is exact at m = 2: the root alone proves it
+        r = oracle.search(p, opt, oracle.LB2_FULL)
+        assert not r["found"] and r["proven"] and r["nodes"] == 1
+
+
+def test_search_critical_tree_and_budget():
+    p = inputs.instance(10, 5, 7)
+    opt, _ = oracle.bruteforce(p)
+    r = oracle.search(p, opt, oracle.LB1)       # incumbent = optimum: nothing better exists
+    assert r["proven"] and not r["found"] and r["best"] == opt
+    small = oracle.search(p, opt, oracle.LB1, budget=3)
+    assert not small["proven"] and small["nodes"] == 3
+    # the critical tree is independent of visit order: the mirrored instance
+    # (reversed machines) has the same optimum
+    rm = oracle.search(p[:, ::-1], opt + 1, oracle.LB1)
+    assert rm["best"] == opt
+
+
+def test_neh_is_a_feasible_upper_bound():
+    for seed in range(5):
+        p = inputs.instance(8, 4, 500 + seed)
+        c, perm = oracle.neh(p)
+        assert sorted(perm) == list(range(8))
+        assert c == oracle.makespan(p, perm) >= oracle.bruteforce(p)[0]

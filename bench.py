@@ -1,0 +1,158 @@
+"""Benchmark of the flow-shop bounding path on one MI355X.
+
+Default workload (the headline): one decomposition step = pfsp_bound_children
+with the full two-machine bound LB2 (all 190 machine pairs) over 1,048,576
+random bidirectional partial schedules of one n=20 x m=20 instance with
+p ~ U[1,99], including the MinMin branching decision and the prune flags.
+The metric is children bounded per second.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+
+Prints one JSON line.  The dominant kernel's roofline entry divides the
+kernel's algorithmic integer operations (formula in alg_ops_lb2) by its mean
+duration measured with HIP events on the library stream over the timed
+steps.  The CPU baseline is the plain oracle on a bounded sample of the same
+pool, on all host cores available to this process.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "children bounded/sec (LB2) on 1 MI355X + time-to-optimal; learned-pair vs full LB2"
+# MI355X: 256 CUs x 4 SIMD16 = 64 int32 lanes per CU per clock at 2.4 GHz
+PEAK_INT32_OPS = 256 * 64 * 2.4e9
+PEAK_HBM = 8e12
+
+
+def alg_ops_lb2(n, m, d1, d2):
+    """Algorithmic int32 operations of k_lb2 for the given parents.
+
+    Per (parent, pair): forward scan 5 ops and backward scan 9 ops per
+    unscheduled job, 4 setup ops, and 15 ops per unscheduled job for its two
+    children's O(1) pair values and running maxima: 29 r + 4.  Per parent:
+    children fronts/backs and LB1 terms 14 r m, MinMin and prune 8 r.
+    """
+    P = m * (m - 1) // 2
+    r = n - d1.astype(np.int64) - d2.astype(np.int64)
+    return int((P * (29 * r + 4) + 14 * r * m + 8 * r).sum())
+
+
+def bytes_lb2(n, m, count):
+    """Algorithmic HBM bytes of k_lb2: node records and parent costs in,
+    bounds, prune flags and directions out."""
+    per = (n + 2) + 3 * m * 4 + 2 * n * 4 + 2 * n + 1
+    return per * count
+
+
+def cpu_baseline(p, perm, d1, d2, kind, target_s=12.0):
+    import oracle
+    threads = len(os.sched_getaffinity(0))
+    threads = max(1, min(threads, 16))
+    # calibrate on a small sample, then run ~target_s of work
+    k = 64
+    t = time.perf_counter()
+    oracle.bound_children(p, perm[:k], d1[:k], d2[:k], kind, threads=threads)
+    dt = max(time.perf_counter() - t, 1e-3)
+    k2 = int(min(len(perm), max(k, k * target_s / dt)))
+    t = time.perf_counter()
+    oracle.bound_children(p, perm[:k2], d1[:k2], d2[:k2], kind, threads=threads)
+    dt = time.perf_counter() - t
+    n = p.shape[0]
+    children = int((2 * (n - d1[:k2].astype(np.int64) - d2[:k2].astype(np.int64))).sum())
+    return dict(value=children / dt, unit="children/s", cores=threads, kind="oracle",
+                sample=f"first {k2} parents of the same pool ({children} children), "
+                       f"{dt:.1f} s, OpenMP over parents")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--parents", type=int, default=1 << 20)
+    ap.add_argument("--kind", default="LB2_FULL", choices=["LB1", "LB2_FULL"])
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the bounding path has no multi-GPU mode in this "
+              "build (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2012_09511_amd import binding, inputs
+
+    n, m, N = 20, 20, args.parents
+    p = inputs.instance(n, m, 2012)
+    perm, d1, d2 = inputs.random_pool(n, N, 9511)
+    ctx = binding.Context(0)
+    ctx.load_instance(p)
+    ub, _ = ctx.neh()
+    kind = getattr(binding, args.kind)
+    dev = [torch.from_numpy(a).cuda() for a in (perm, d1, d2)]
+    out_lb = torch.empty((N, 2, n), dtype=torch.int32, device="cuda")
+    out_pr = torch.empty((N, 2, n), dtype=torch.uint8, device="cuda")
+    out_dir = torch.empty(N, dtype=torch.uint8, device="cuda")
+    children = int((2 * (n - d1.astype(np.int64) - d2.astype(np.int64))).sum())
+
+    for _ in range(args.warmup):
+        ctx.bound_children(*dev, kind=kind, ub=ub, out_lb=out_lb, out_prune=out_pr,
+                           dir_out=out_dir)
+    torch.cuda.synchronize()
+    ctx.check()
+    ctx.set_option("timing", 1)
+    ctx.kernel_time("k_lb2", reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.bound_children(*dev, kind=kind, ub=ub, out_lb=out_lb, out_prune=out_pr,
+                           dir_out=out_dir)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.check()
+    dom = "k_lb2" if kind != binding.LB1 else "k_lb1"
+    ms_dom, launches = ctx.kernel_time(dom)
+    ms_lb1, l1 = ctx.kernel_time("k_lb1", reset=True)
+    ctx.set_option("timing", 0)
+    elapsed = t1 - t0
+    value = children * args.steps / elapsed
+    dom_ms = ms_dom / max(launches, 1)
+    if kind != binding.LB1:
+        ops = alg_ops_lb2(n, m, d1, d2)
+        achieved = ops / (dom_ms * 1e-3)
+        roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_INT32_OPS / 1e12,
+                    unit="TOP/s", frac=achieved / PEAK_INT32_OPS, traffic=None,
+                    kernel=dom, kernel_ms=dom_ms, alg_ops_per_launch=ops,
+                    op_count="reformulated LB2 (O(1) per child per pair)")
+    else:
+        b = bytes_lb2(n, m, N)
+        achieved = b / (dom_ms * 1e-3)
+        roof = dict(bound="hbm", achieved=achieved / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s",
+                    frac=achieved / PEAK_HBM, traffic=None, kernel=dom, kernel_ms=dom_ms)
+    out = dict(metric=METRIC, value=value, unit="children/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=elapsed / args.steps * 1e3,
+               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="int32",
+               data="synthetic",
+               config=dict(workload=f"{args.kind} decomposition of {N} random bidirectional "
+                                    f"partial schedules, one n=20 x m=20 instance, p~U[1,99]",
+                           n=n, m=m, parents=N, children=children, lb_kind=args.kind, ub=ub,
+                           instance_seed=2012, pool_seed=9511),
+               roofline=roof,
+               kernels_ms=dict(k_lb1=ms_lb1 / max(l1, 1), **({dom: dom_ms} if dom != "k_lb1"
+                                                             else {})))
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(p, perm, d1, d2, kind)
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

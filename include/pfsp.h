@@ -1,0 +1,168 @@
+/* pfsp.h - C ABI of the MI355X (gfx950) flow-shop bounding library.
+ *
+ * The library evaluates, on one GPU, the lower bounds of all children of a
+ * batch of partial permutation flow-shop schedules, takes the MinMin
+ * branching decision and the pruning decision for each parent, and runs a
+ * depth-first branch-and-bound built from those steps.  The method is the one
+ * of Gmys (2020), "Solving large permutation flow-shop scheduling problems on
+ * GPU-accelerated supercomputers":
+ *   - problem and makespan recursion:            Section 2.1, Eq. (1)
+ *   - nodes (sigma1, sigma2), dynamic branching:  Section 2.3
+ *   - MinMin branching heuristic:                 Section 2.3 (Figure 2)
+ *   - LB1 (front + remaining + back):             Section 2.4 (Figure 3)
+ *   - LB2 (two-machine Johnson bound over machine pairs, pre-sorted orders,
+ *     between m and m(m-1)/2 pairs):             Section 2.4
+ *   - bounding / pruning / depth-first search:    Sections 2.2, 2.5
+ *
+ * Conventions shared by every call
+ *   - Return value: PFSP_OK (0) on success, a negative PFSP_E* code on error,
+ *     PFSP_BUDGET (+1) from pfsp_search when the node budget ran out first.
+ *     pfsp_last_error() gives a message for the last failing call on a ctx.
+ *   - Processing times are int32 >= 0, row-major p[j*m + k] (job j, machine k).
+ *     n in [2, 255], m in [1, 64]; LB2 kinds need m >= 2.  An instance whose
+ *     longest possible path (n + m - 1) * max(p) reaches 2^30 is rejected
+ *     (PFSP_ERANGE): all bound arithmetic is exact int32 below that limit.
+ *   - A node is (perm[n], d1, d2): sigma1 = perm[0, d1), the unscheduled jobs
+ *     U = perm[d1, n - d2) in list order, sigma2 = perm[n - d2, n);
+ *     d1 + d2 <= n - 1.
+ *   - Machine pairs u < v are numbered lexicographically:
+ *     idx(u, v) = u*(2m - u - 1)/2 + (v - u - 1), P = m(m-1)/2 pairs.
+ *   - Pool and output buffers are DEVICE pointers (e.g. torch tensors on the
+ *     ctx's device) owned by the caller; the library never frees them.  Calls
+ *     that take device buffers are asynchronous on the ctx stream unless said
+ *     otherwise.  The instance is copied into library-owned device memory.
+ *   - One ctx per host thread; calls on one ctx must not overlap.
+ */
+#ifndef PFSP_H
+#define PFSP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  PFSP_OK = 0,
+  PFSP_BUDGET = 1,   /* pfsp_search: budget exhausted without a proof */
+  PFSP_EINVAL = -1,  /* null pointer, size mismatch, d1 + d2 >= n, bad option */
+  PFSP_ENOINST = -2, /* no instance loaded */
+  PFSP_ERANGE = -3,  /* n, m, p or a size out of the supported range */
+  PFSP_ENOMEM = -4,  /* device or host allocation failed */
+  PFSP_EDEVICE = -5  /* a HIP runtime error (message in pfsp_last_error) */
+};
+
+typedef enum {
+  PFSP_LB1 = 1,         /* one-machine bound (Section 2.4, steps 1-4) */
+  PFSP_LB2_FULL = 2,    /* max(LB1, two-machine bound over all P pairs) */
+  PFSP_LB2_SUBSET = 3,  /* max(LB1, two-machine bound over the pairs in pair_mask) */
+  PFSP_LB2_LEARNED = 4  /* subset chosen per parent by the loaded pair selector */
+} pfsp_lb_kind;
+
+typedef struct pfsp_ctx pfsp_ctx;
+
+/* A batch of parent nodes, structure-of-arrays, all device pointers. */
+typedef struct {
+  int32_t count;              /* number of parents N >= 0 */
+  int32_t n;                  /* row stride of perm; must equal the loaded n */
+  const uint8_t *perm;        /* [N][n] job ids 0..n-1, each row a permutation */
+  const uint8_t *d1;          /* [N] prefix lengths */
+  const uint8_t *d2;          /* [N] suffix lengths */
+  const uint32_t *pair_mask;  /* PFSP_LB2_SUBSET: [N][mask_words], bit idx(u,v)
+                                 selects pair (u, v); otherwise ignored */
+  int32_t mask_words;         /* words per row of pair_mask, >= ceil(P / 32) */
+  uint8_t *dir_out;           /* [N] or NULL: MinMin choice, 0 = forward, 1 = backward */
+  int16_t *argpair_out;       /* [N][2][n] or NULL (LB2 kinds): lowest pair index
+                                 attaining each child's pair maximum, -1 if none */
+} pfsp_pool;
+
+typedef struct {
+  int32_t best_cmax;          /* best makespan found (< ub0) if found, else ub0 */
+  int32_t found;              /* 1 iff a schedule with C_max < ub0 was found */
+  int32_t proven;             /* 1 iff the tree was exhausted (optimal if found,
+                                 otherwise the optimum is >= ub0) */
+  int32_t steps;              /* batch steps executed */
+  int64_t nodes_decomposed;   /* decomposed nodes, root included */
+  int64_t children_bounded;   /* sum over decomposed nodes of 2(n - d) */
+  int64_t max_pool;           /* largest pool size seen at a poll */
+  double seconds;             /* wall time of the search loop */
+  int32_t *best_perm;         /* caller-owned HOST [n], filled when found */
+} pfsp_result;
+
+/* Creates a context on HIP device `device`.  hip_stream is a hipStream_t
+ * (NULL = the device's null stream) on which every kernel is launched.
+ * *out receives the context; it owns all library device memory. */
+int pfsp_create(pfsp_ctx **out, int device, void *hip_stream);
+
+/* Releases a context and its device memory (waits for its stream first). */
+void pfsp_destroy(pfsp_ctx *c);
+
+/* Message of the last failing call on c (static text if c is NULL). */
+const char *pfsp_last_error(pfsp_ctx *c);
+
+/* Loads an instance from HOST memory p[n*m] (Section 2.1) and stages its
+ * device tables: per-machine totals, and for every machine pair the
+ * Johnson-with-lags order of all n jobs with their (a, b, lag) times
+ * (Section 2.4: LB2 uses pre-sorted two-machine schedules).  Synchronous. */
+int pfsp_load_instance(pfsp_ctx *c, int32_t n, int32_t m, const int32_t *p);
+
+/* Number of machine pairs P = m(m-1)/2 of the loaded instance, or < 0. */
+int pfsp_pair_count(pfsp_ctx *c);
+
+/* Decomposition of every parent of the pool (Section 2.3, Figure 2; Section
+ * 2.2 bounding and pruning): both children sets are bounded with `lb_kind`,
+ * MinMin chooses the direction, and a child is flagged pruned iff LB >= ub.
+ * out_lb [N][2][n] int32 and out_prune [N][2][n] uint8 (device): entry
+ * [i][dir][q] is the child of parent i that puts the job perm[i][d1 + q] at
+ * the end of sigma1 (dir 0) or the front of sigma2 (dir 1); slots q >= n-d1-d2
+ * hold INT32_MAX and prune 1.  A leaf child's LB is its makespan.
+ * Asynchronous on the ctx stream.  A row that is not a valid node (d1 + d2 >=
+ * n, or perm not a permutation of 0..n-1) gets INT32_MAX / prune 1 in every
+ * slot and dir 0, and makes the next pfsp_check report PFSP_EINVAL. */
+int pfsp_bound_children(pfsp_ctx *c, const pfsp_pool *pool, int lb_kind, int32_t ub,
+                        int32_t *out_lb, uint8_t *out_prune);
+
+/* Waits for the ctx stream and reports PFSP_EINVAL if any pool row seen by
+ * pfsp_bound_children since the last check had d1 + d2 >= n (such rows are
+ * filled with INT32_MAX / prune 1).  Clears the condition.  Synchronous. */
+int pfsp_check(pfsp_ctx *c);
+
+/* Depth-first branch-and-bound on the device (Sections 2.2-2.5) from the
+ * root (empty sigma1, sigma2): pools of up to `pool_batch` (option) nodes are
+ * popped from a device stack, decomposed with pfsp_bound_children's step,
+ * and their surviving children pushed back (leftmost on top).  Looks for a
+ * schedule with C_max < ub0 (INT32_MAX: none known).  budget_nodes > 0 stops
+ * after about that many decomposed nodes (returns PFSP_BUDGET).  lb_kind as
+ * above except PFSP_LB2_SUBSET.  Synchronous; res must not be NULL. */
+int pfsp_search(pfsp_ctx *c, int32_t ub0, int64_t budget_nodes, int lb_kind,
+                pfsp_result *res);
+
+/* Nawaz-Enscore-Ham constructive heuristic on the loaded instance, used for
+ * the initial incumbent: jobs by decreasing total time (ties: lower id), each
+ * inserted at the first position minimising the partial makespan.  HOST
+ * outputs perm_out[n] and *cmax_out.  Synchronous. */
+int pfsp_neh(pfsp_ctx *c, int32_t *perm_out, int32_t *cmax_out);
+
+/* Integer options: "pool_batch" (nodes popped per search step, default
+ * 65536), "poll_every" (search steps between host polls, default 8),
+ * "pool_capacity" (max stacked nodes, default derived from n and pool_batch),
+ * "use_graph" (1 = replay the search step as a HIP graph, default 1),
+ * "learned_topk" (pairs kept by the selector, default 16),
+ * "learned_exact" (1 = re-bound subset survivors with all pairs, default 0),
+ * "timing" (1 = bracket every kernel launch with HIP events on the ctx
+ * stream, default 0). */
+int pfsp_set_option(pfsp_ctx *c, const char *key, int64_t value);
+int pfsp_get_option(pfsp_ctx *c, const char *key, int64_t *value);
+
+/* Instrumentation (option "timing" = 1): total milliseconds and number of
+ * launches of the kernel named `kernel` ("k_lb1", "k_lb2", ...) since the last
+ * reset, measured with HIP events recorded on the ctx stream around each
+ * launch.  Waits for the ctx stream.  reset != 0 clears all counters after
+ * reading. */
+int pfsp_kernel_time(pfsp_ctx *c, const char *kernel, double *total_ms, int64_t *launches,
+                     int reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PFSP_H */

@@ -1,0 +1,190 @@
+"""Thin ctypes binding of libpfsp.so (include/pfsp.h).
+
+Only argument marshalling happens here: torch tensors provide device memory
+and the stream; every step of the bounding path runs in the library's HIP
+kernels.  Importing this module fails loudly if the library is not built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libpfsp.so")
+
+PFSP_OK, PFSP_BUDGET = 0, 1
+PFSP_EINVAL, PFSP_ENOINST, PFSP_ERANGE, PFSP_ENOMEM, PFSP_EDEVICE = -1, -2, -3, -4, -5
+LB1, LB2_FULL, LB2_SUBSET, LB2_LEARNED = 1, 2, 3, 4
+INT32_MAX = 2**31 - 1
+
+# every symbol declared in include/pfsp.h
+EXPORTS = ["pfsp_create", "pfsp_destroy", "pfsp_last_error", "pfsp_load_instance",
+           "pfsp_pair_count", "pfsp_bound_children", "pfsp_check", "pfsp_search", "pfsp_neh",
+           "pfsp_set_option", "pfsp_get_option", "pfsp_kernel_time"]
+
+
+class PfspError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"pfsp error {code}: {msg}")
+        self.code = code
+
+
+class Pool(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("perm", ctypes.c_void_p), ("d1", ctypes.c_void_p), ("d2", ctypes.c_void_p),
+                ("pair_mask", ctypes.c_void_p), ("mask_words", ctypes.c_int32),
+                ("dir_out", ctypes.c_void_p), ("argpair_out", ctypes.c_void_p)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("best_cmax", ctypes.c_int32), ("found", ctypes.c_int32),
+                ("proven", ctypes.c_int32), ("steps", ctypes.c_int32),
+                ("nodes_decomposed", ctypes.c_int64), ("children_bounded", ctypes.c_int64),
+                ("max_pool", ctypes.c_int64), ("seconds", ctypes.c_double),
+                ("best_perm", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2012_09511_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.pfsp_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, vp]
+        L.pfsp_create.restype = ctypes.c_int
+        L.pfsp_destroy.argtypes = [vp]
+        L.pfsp_destroy.restype = None
+        L.pfsp_last_error.argtypes = [vp]
+        L.pfsp_last_error.restype = ctypes.c_char_p
+        L.pfsp_load_instance.argtypes = [vp, i32, i32, vp]
+        L.pfsp_pair_count.argtypes = [vp]
+        L.pfsp_bound_children.argtypes = [vp, ctypes.POINTER(Pool), ctypes.c_int, i32, vp, vp]
+        L.pfsp_check.argtypes = [vp]
+        L.pfsp_search.argtypes = [vp, i32, i64, ctypes.c_int, ctypes.POINTER(Result)]
+        L.pfsp_neh.argtypes = [vp, vp, vp]
+        L.pfsp_set_option.argtypes = [vp, ctypes.c_char_p, i64]
+        L.pfsp_get_option.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(i64)]
+        L.pfsp_kernel_time.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(i64), ctypes.c_int]
+        for name in EXPORTS:
+            if name not in ("pfsp_destroy", "pfsp_last_error"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One library context on one device, launching on the current torch stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        rc = lib().pfsp_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream))
+        if rc != 0:
+            raise PfspError(rc, "pfsp_create failed")
+        self.h = h
+        self.n = self.m = None
+
+    def close(self):
+        if self.h:
+            lib().pfsp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc < 0:
+            raise PfspError(rc, lib().pfsp_last_error(self.h).decode())
+        return rc
+
+    def load_instance(self, p):
+        p = np.ascontiguousarray(p, dtype=np.int32)
+        n, m = p.shape
+        self._check(lib().pfsp_load_instance(self.h, n, m, p.ctypes.data_as(ctypes.c_void_p)))
+        self.n, self.m = n, m
+        self.P = self._check(lib().pfsp_pair_count(self.h))
+        self.mask_words = max(1, (self.P + 31) // 32)
+
+    def bound_children(self, perm, d1, d2, kind=LB1, ub=INT32_MAX, pair_mask=None,
+                       out_lb=None, out_prune=None, dir_out=None, argpair_out=None,
+                       want_dir=True, want_argpair=False):
+        """Device tensors in, device tensors out: (lb [N,2,n] int32, prune [N,2,n] uint8,
+        dir [N] uint8 or None, argpair [N,2,n] int16 or None)."""
+        torch = self.torch
+        N = perm.shape[0]
+        n = self.n
+        if out_lb is None:
+            out_lb = torch.empty((N, 2, n), dtype=torch.int32, device=self.device)
+        if out_prune is None:
+            out_prune = torch.empty((N, 2, n), dtype=torch.uint8, device=self.device)
+        if dir_out is None and want_dir:
+            dir_out = torch.empty(N, dtype=torch.uint8, device=self.device)
+        if argpair_out is None and want_argpair:
+            argpair_out = torch.empty((N, 2, n), dtype=torch.int16, device=self.device)
+        for t, dt in ((perm, torch.uint8), (d1, torch.uint8), (d2, torch.uint8)):
+            if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("perm/d1/d2 must be contiguous uint8 device tensors")
+        pool = Pool(N, perm.shape[1] if perm.dim() == 2 else n, _ptr(perm), _ptr(d1), _ptr(d2),
+                    _ptr(pair_mask), 0 if pair_mask is None else pair_mask.shape[-1],
+                    _ptr(dir_out), _ptr(argpair_out))
+        self._check(lib().pfsp_bound_children(self.h, ctypes.byref(pool), kind, int(ub),
+                                              _ptr(out_lb), _ptr(out_prune)))
+        return out_lb, out_prune, dir_out, argpair_out
+
+    def check(self):
+        return self._check(lib().pfsp_check(self.h))
+
+    def search(self, ub0=INT32_MAX, budget=0, kind=LB1):
+        perm = np.zeros(self.n, dtype=np.int32)
+        res = Result()
+        res.best_perm = perm.ctypes.data_as(ctypes.c_void_p)
+        rc = self._check(lib().pfsp_search(self.h, int(ub0), int(budget), kind,
+                                           ctypes.byref(res)))
+        return dict(best=res.best_cmax, found=bool(res.found), proven=bool(res.proven),
+                    steps=res.steps, nodes=res.nodes_decomposed,
+                    children=res.children_bounded, max_pool=res.max_pool,
+                    seconds=res.seconds, perm=perm.astype(np.uint8), budget_hit=rc == 1)
+
+    def neh(self):
+        perm = np.zeros(self.n, dtype=np.int32)
+        c = np.zeros(1, dtype=np.int32)
+        self._check(lib().pfsp_neh(self.h, perm.ctypes.data_as(ctypes.c_void_p),
+                                   c.ctypes.data_as(ctypes.c_void_p)))
+        return int(c[0]), perm.astype(np.uint8)
+
+    def set_option(self, key: str, value: int):
+        self._check(lib().pfsp_set_option(self.h, key.encode(), int(value)))
+
+    def get_option(self, key: str) -> int:
+        v = ctypes.c_int64()
+        self._check(lib().pfsp_get_option(self.h, key.encode(), ctypes.byref(v)))
+        return v.value
+
+    def kernel_time(self, kernel: str, reset: bool = False):
+        """(total ms, launches) of a kernel since the last reset (option "timing")."""
+        ms = ctypes.c_double()
+        k = ctypes.c_int64()
+        self._check(lib().pfsp_kernel_time(self.h, kernel.encode(), ctypes.byref(ms),
+                                           ctypes.byref(k), int(reset)))
+        return ms.value, k.value

@@ -1,0 +1,491 @@
+// Bounding, MinMin branching and pruning of a batch of parents (Sections
+// 2.3-2.4 and the decomposition step of Section 3.3).
+//
+// k_lb1: one lane per parent.  Computes the parent's front C1 (completion
+//   times of sigma1 on every machine, Eq. (1)), back C2 (sigma2 scheduled in
+//   reverse on reversed machines) and remaining work R = T - scheduled work.
+//   In LB1 mode it then derives every child's LB1 in O(m) (Section 2.4:
+//   the incremental evaluation of the 2(n-d) children):
+//     forward child j:  C1'[k] = max(C1'[k-1], C1[k]) + p[j][k],
+//                       LB = max_k C1'[k] + R[k] - p[j][k] + C2[k]
+//     backward child j: C2'[k] = max(C2'[k+1], C2[k]) + p[j][k],
+//                       LB = max_k C1[k] + R[k] - p[j][k] + C2'[k]
+//   followed by MinMin and the prune flags.  In LB2 mode it only writes
+//   (C1, C2, R) to the workspace for k_lb2.
+//
+// k_lb2: one wave per parent, lanes = machine pairs (64 per pass).  For a
+//   pair (u, v) the two-machine value of a child whose unscheduled set is
+//   U \ {j}, with heads h and tails t, is
+//     t_u = h_u + A(U\j),  t_v = max(h_v + B(U\j), h_u + max_i term_i(U\j)),
+//     value = max(t_u + t_u', t_v + t_v'),
+//   where A, B sum a = p[.][u], b = p[.][v] and term_i = A(<= i) + lag_i + B(>= i)
+//   along the pair's Johnson order.  Removing j lowers the terms before j by
+//   b_j and those after j by a_j, so with the parent's exclusive prefix and
+//   suffix maxima PM, SM of term over U:
+//     max_i term_i(U\j) = max(PM(j) - b_j, SM(j) - a_j).
+//   Two scans per (parent, pair) produce X(j) = that maximum for every j in
+//   U; each child then costs O(1) per pair.  The result is exactly the value
+//   of running the Johnson recurrence over the child's jobs (proof: the
+//   recurrence unrolls to max(h_v + B, h_u + max_i term_i)).  The maxima over
+//   pairs are kept per child in registers and reduced across lanes by a
+//   transposing exchange at the end.
+#include "internal.h"
+#include "wave.h"
+
+namespace pfsp {
+
+namespace {
+
+__host__ __device__ constexpr size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
+
+struct Narrow {
+  using T = uint2;
+  __device__ __forceinline__ static void get(const uint2 e, int &a, int &b, int &l, int &k) {
+    a = (int)(e.x & 0xffffu);
+    b = (int)(e.x >> 16);
+    l = (int)(e.y & 0xffffffu);
+    k = (int)(e.y >> 24);
+  }
+};
+struct Wide {
+  using T = uint4;
+  __device__ __forceinline__ static void get(const uint4 e, int &a, int &b, int &l, int &k) {
+    a = (int)e.x;
+    b = (int)e.y;
+    l = (int)e.z;
+    k = (int)e.w;
+  }
+};
+
+__device__ __forceinline__ void fill_invalid(int *lbrow, uint8_t *prow, int16_t *arow, int n,
+                                             int from, int lane, int step) {
+  for (int x = lane; x < 2 * n; x += step) {
+    const int q = x < n ? x : x - n;
+    if (q >= from) {
+      lbrow[x] = kInt32Max;
+      prow[x] = 1;
+      if (arow) arow[x] = -1;
+    }
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- LB1 / costs
+__global__ void __launch_bounds__(128)
+k_lb1(DevInst I, DevPool pool, int ub, int *__restrict__ out_lb, uint8_t *__restrict__ out_prune,
+      int *__restrict__ costs, int write_out, int *__restrict__ flag) {
+  extern __shared__ int sh[];
+  const int n = I.n, m = I.m, B = blockDim.x, t = threadIdx.x;
+  int *sp = sh;  // p[n][m]
+  for (int x = t; x < n * m; x += B) sp[x] = I.p[x];
+  __syncthreads();
+  const int i = blockIdx.x * B + t;
+  if (i >= pool.count) return;
+  int *C1 = sh + n * m + t;  // per-lane arrays, stride B (bank-conflict free)
+  int *C2 = C1 + m * B;
+  int *R = C2 + m * B;
+  const uint8_t *row = pool.perm + (size_t)i * n;
+  const int a = pool.d1[i], b = pool.d2[i], r = n - a - b;
+  int *lbrow = out_lb + (size_t)i * 2 * n;
+  uint8_t *prow = out_prune + (size_t)i * 2 * n;
+  int16_t *arow = pool.argpair ? pool.argpair + (size_t)i * 2 * n : nullptr;
+  // a row must be a permutation of 0..n-1 with d1 + d2 < n
+  bool bad = r < 1;
+  uint32_t seen[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int x = 0; x < n && !bad; ++x) {
+    const int j = row[x];
+    const uint32_t bit = 1u << (j & 31);
+    if (j >= n || (seen[j >> 5] & bit)) bad = true;
+    seen[j >> 5] |= bit;
+  }
+  if (bad) {
+    flag[0] = 1;
+    fill_invalid(lbrow, prow, arow, n, 0, 0, 1);
+    if (pool.dir) pool.dir[i] = 0;
+    if (costs) {
+      for (int k = 0; k < 3 * m; ++k) costs[(size_t)i * 3 * m + k] = 0;
+      costs[(size_t)i * 3 * m] = -1;  // marks the row invalid for k_lb2
+    }
+    return;
+  }
+  for (int k = 0; k < m; ++k) {
+    C1[k * B] = 0;
+    C2[k * B] = 0;
+    R[k * B] = I.T[k];
+  }
+  for (int x = 0; x < a; ++x) {  // front of sigma1, Eq. (1)
+    const int *pj = sp + row[x] * m;
+    int c = 0;
+    for (int k = 0; k < m; ++k) {
+      c = max(c, C1[k * B]) + pj[k];
+      C1[k * B] = c;
+      R[k * B] -= pj[k];
+    }
+  }
+  for (int x = n - 1; x >= n - b; --x) {  // back of sigma2: reverse jobs, reverse machines
+    const int *pj = sp + row[x] * m;
+    int c = 0;
+    for (int k = m - 1; k >= 0; --k) {
+      c = max(c, C2[k * B]) + pj[k];
+      C2[k * B] = c;
+      R[k * B] -= pj[k];
+    }
+  }
+  if (costs) {
+    int *o = costs + (size_t)i * 3 * m;
+    for (int k = 0; k < m; ++k) {
+      o[k] = C1[k * B];
+      o[m + k] = C2[k * B];
+      o[2 * m + k] = R[k * B];
+    }
+  }
+  if (!write_out) return;
+  MinMin mm;
+  mm.init();
+  for (int q = 0; q < r; ++q) {
+    const int *pj = sp + row[a + q] * m;
+    int c = 0, lbf = 0;
+    for (int k = 0; k < m; ++k) {
+      c = max(c, C1[k * B]) + pj[k];
+      lbf = max(lbf, c + R[k * B] - pj[k] + C2[k * B]);
+    }
+    c = 0;
+    int lbb = 0;
+    for (int k = m - 1; k >= 0; --k) {
+      c = max(c, C2[k * B]) + pj[k];
+      lbb = max(lbb, C1[k * B] + R[k * B] - pj[k] + c);
+    }
+    lbrow[q] = lbf;
+    lbrow[n + q] = lbb;
+    prow[q] = lbf >= ub;
+    prow[n + q] = lbb >= ub;
+    mm.add(lbf, false);
+    mm.add(lbb, true);
+  }
+  for (int q = r; q < n; ++q) {
+    lbrow[q] = kInt32Max;
+    lbrow[n + q] = kInt32Max;
+    prow[q] = 1;
+    prow[n + q] = 1;
+  }
+  if (pool.dir) pool.dir[i] = (uint8_t)mm.dir();
+}
+
+// ------------------------------------------------------------------------ LB2
+template <class E, bool ENT_LDS, bool SUBSET, bool LOG>
+__global__ void __launch_bounds__(512)
+k_lb2(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__restrict__ out_lb,
+      uint8_t *__restrict__ out_prune, int xrows) {
+  extern __shared__ __align__(16) unsigned char sm[];
+  using ET = typename E::T;
+  const int n = I.n, m = I.m, P = I.P;
+  const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const ET *ent_g = (const ET *)(I.narrow ? (const void *)I.ent : (const void *)I.entw);
+  size_t off = 0;
+  ET *ent_s = (ET *)sm;
+  if (ENT_LDS) off += align16((size_t)n * P * sizeof(ET));
+  int *sp = (int *)(sm + off);
+  off += align16((size_t)n * m * 4);
+  const size_t per_wave = align16((size_t)xrows * 64 * 8) + align16((size_t)xrows * m * 8) +
+                          align16((size_t)3 * m * 4) + align16((size_t)2 * n * 4);
+  unsigned char *wb = sm + off + w * per_wave;
+  int2 *X = (int2 *)wb;  // [xrows][64]: per child slot, per lane (pair)
+  wb += align16((size_t)xrows * 64 * 8);
+  int2 *FB = (int2 *)wb;  // [xrows][m]: (fwd child front - p, bwd child back - p)
+  wb += align16((size_t)xrows * m * 8);
+  int *c1 = (int *)wb, *c2 = c1 + m, *rr = c2 + m;
+  wb += align16((size_t)3 * m * 4);
+  int *slot = (int *)wb, *jobs = slot + n;
+
+  if (ENT_LDS)
+    for (int x = threadIdx.x; x < n * P; x += blockDim.x) ent_s[x] = ent_g[x];
+  for (int x = threadIdx.x; x < n * m; x += blockDim.x) sp[x] = I.p[x];
+  __syncthreads();
+  const ET *ent = ENT_LDS ? ent_s : ent_g;
+
+  for (int par = blockIdx.x * nw + w; par < pool.count; par += gridDim.x * nw) {
+    const int a = pool.d1[par], b = pool.d2[par], r = n - a - b;
+    int *lbrow = out_lb + (size_t)par * 2 * n;
+    uint8_t *prow = out_prune + (size_t)par * 2 * n;
+    int16_t *arow = LOG ? pool.argpair + (size_t)par * 2 * n : nullptr;
+    // k_lb1 flagged and filled rows that are not valid nodes (a front value
+    // is never negative otherwise)
+    if (r < 1 || costs[(size_t)par * 3 * m] < 0) continue;
+    for (int x = lane; x < n; x += 64) {
+      jobs[x] = pool.perm[(size_t)par * n + x];
+      slot[x] = -1;
+    }
+    for (int x = lane; x < m; x += 64) {
+      const int *cs = costs + (size_t)par * 3 * m;
+      c1[x] = cs[x];
+      c2[x] = cs[m + x];
+      rr[x] = cs[2 * m + x];
+    }
+    wave_sync();
+    for (int x = lane; x < r; x += 64) slot[jobs[a + x]] = x;
+    wave_sync();
+    MinMin mm;
+    mm.init();
+    for (int cb = 0; cb < r; cb += 32) {
+      const int nq = min(32, r - cb);
+      // children fronts/backs of this chunk: lanes [0,32) forward, [32,64) backward
+      int lb1 = kNeg;
+      const int ql = lane & 31;
+      if (ql < nq) {
+        const int *pj = sp + jobs[a + cb + ql] * m;
+        int c = 0, l = 0;
+        if (lane < 32) {
+          for (int k = 0; k < m; ++k) {
+            c = max(c, c1[k]) + pj[k];
+            FB[ql * m + k].x = c - pj[k];
+            l = max(l, c + rr[k] - pj[k] + c2[k]);
+          }
+        } else {
+          for (int k = m - 1; k >= 0; --k) {
+            c = max(c, c2[k]) + pj[k];
+            FB[ql * m + k].y = c - pj[k];
+            l = max(l, c1[k] + rr[k] - pj[k] + c);
+          }
+        }
+        lb1 = l;
+      }
+      wave_sync();
+      int acc[64];
+      int arg[LOG ? 64 : 1];
+#pragma unroll
+      for (int q = 0; q < 64; ++q) acc[q] = kNeg;
+      if (LOG) {
+#pragma unroll
+        for (int q = 0; q < 64; ++q) arg[LOG ? q : 0] = 0x7fffffff;
+      }
+      for (int pc = 0; pc < P; pc += 64) {
+        const int pi = pc + lane;
+        bool act = pi < P;
+        if (SUBSET && act)
+          act = (pool.mask[(size_t)par * pool.mask_words + (pi >> 5)] >> (pi & 31)) & 1u;
+        if (act) {
+          const int u = I.pu[pi], v = I.pv[pi];
+          const int RU = rr[u], RV = rr[v], C1u = c1[u], C1v = c1[v], C2u = c2[u], C2v = c2[v];
+          // forward scan: exclusive prefix maximum of term (minus B(U)), minus b_j
+          int Y = 0, Pm = kNeg;
+          for (int i = 0; i < n; ++i) {
+            int ea, eb, el, ek;
+            E::get(ent[(size_t)i * P + pi], ea, eb, el, ek);
+            const int s = slot[ek];
+            if (s >= 0) {
+              Y += ea;
+              const int tt = Y + el;
+              const int sq = s - cb;
+              if ((unsigned)sq < (unsigned)nq) X[sq * 64 + lane].x = Pm - eb;
+              Pm = max(Pm, tt);
+              Y -= eb;
+            }
+          }
+          // backward scan: exclusive suffix maximum, combined into X(j)
+          const int c0 = RU - RV;
+          int Wb = 0, Sm = kNeg;
+          for (int i = n - 1; i >= 0; --i) {
+            int ea, eb, el, ek;
+            E::get(ent[(size_t)i * P + pi], ea, eb, el, ek);
+            const int s = slot[ek];
+            if (s >= 0) {
+              Wb += eb;
+              const int tp = Wb + el + c0;
+              const int sq = s - cb;
+              if ((unsigned)sq < (unsigned)nq) {
+                const int x = max(X[sq * 64 + lane].x, Sm - ea);
+                X[sq * 64 + lane] = make_int2(x + ea, x + eb);
+              }
+              Sm = max(Sm, tp);
+              Wb -= ea;
+            }
+          }
+          const int K1 = RU + C2u, K2 = C1u + RU, K3 = C1v + RV;
+#pragma unroll
+          for (int q = 0; q < 32; ++q) {
+            if (q < nq) {
+              const int2 xab = X[q * 64 + lane];
+              const int2 fu = FB[q * m + u], fv = FB[q * m + v];
+              const int xa = xab.x + RV, xb = xab.y + RV;
+              const int lbf = max(fu.x + K1, max(fv.x + RV, fu.x + xa) + C2v);
+              const int lbb = max(fu.y + K2, max(K3, C1u + xb) + fv.y);
+              if (LOG) {
+                if (lbf > acc[q]) { acc[q] = lbf; arg[LOG ? q : 0] = pi; }
+                if (lbb > acc[32 + q]) { acc[32 + q] = lbb; arg[LOG ? 32 + q : 0] = pi; }
+              } else {
+                acc[q] = max(acc[q], lbf);
+                acc[32 + q] = max(acc[32 + q], lbb);
+              }
+            }
+          }
+        }
+      }
+      if (LOG) {
+        int (&argr)[64] = *reinterpret_cast<int (*)[64]>(&arg[0]);
+        transpose_argmax64(acc, argr, lane);
+      } else {
+        transpose_max64(acc, lane);
+      }
+      // lane q < 32 now holds forward child cb+q, lane 32+q backward child cb+q
+      const bool mine = ql < nq;
+      const bool bwd = lane >= 32;
+      const int val = mine ? max(lb1, acc[0]) : kInt32Max;
+      if (mine) {
+        const int o = (bwd ? n : 0) + cb + ql;
+        lbrow[o] = val;
+        prow[o] = val >= ub;
+        if (LOG) arow[o] = (int16_t)(acc[0] > kNeg ? arg[0] : -1);
+      }
+      // MinMin over this chunk
+      const int cmn = wave_min(val);
+      const int ccf = wave_popc(mine && !bwd && val == cmn);
+      const int ccb = wave_popc(mine && bwd && val == cmn);
+      const long long csf = wave_sum64(mine && !bwd ? (long long)val : 0);
+      const long long csb = wave_sum64(mine && bwd ? (long long)val : 0);
+      mm.merge(cmn, ccf, ccb, csf, csb);
+      wave_sync();
+    }
+    fill_invalid(lbrow, prow, arow, n, r, lane, 64);
+    if (pool.dir && lane == 0) pool.dir[par] = (uint8_t)mm.dir();
+  }
+}
+
+// -------------------------------------------------------------------- host
+int ensure_costs(Ctx *c, int count) {
+  const size_t need = (size_t)(count > 0 ? count : 1) * 3 * c->m;
+  if (need > c->costs_cap) {
+    if (c->d_costs) {
+      PFSP_HIP(c, hipStreamSynchronize(c->stream));
+      (void)hipFree(c->d_costs);
+      c->d_costs = nullptr;
+      c->costs_cap = 0;
+    }
+    size_t cap = need + need / 4;
+    if (hipMalloc(&c->d_costs, cap * 4) != hipSuccess) {
+      c->d_costs = nullptr;
+      return set_err(c, PFSP_ENOMEM, "workspace allocation failed");
+    }
+    c->costs_cap = cap;
+  }
+  return PFSP_OK;
+}
+
+static size_t lb2_lds(const Ctx *c, int waves, bool ent_lds, int xrows) {
+  const int n = c->n, m = c->m, P = c->P;
+  const size_t esz = c->narrow ? 8 : 16;
+  size_t s = ent_lds ? align16((size_t)n * P * esz) : 0;
+  s += align16((size_t)n * m * 4);
+  const size_t pw = align16((size_t)xrows * 64 * 8) + align16((size_t)xrows * m * 8) +
+                    align16((size_t)3 * m * 4) + align16((size_t)2 * n * 4);
+  return s + waves * pw;
+}
+
+size_t lb2_lds_bytes(const Ctx *c, int waves) {
+  const int xrows = c->n < 32 ? c->n : 32;
+  return lb2_lds(c, waves, true, xrows);
+}
+
+template <class E, bool ENT_LDS>
+static void launch_lb2_e(bool subset, bool log, dim3 g, dim3 b, size_t lds, hipStream_t s,
+                         const DevInst &I, const DevPool &pool, int ub, const int *costs,
+                         int *out_lb, uint8_t *out_prune, int xrows) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    const int mx = 160 * 1024;
+    (void)hipFuncSetAttribute((const void *)k_lb2<E, ENT_LDS, true, true>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+    (void)hipFuncSetAttribute((const void *)k_lb2<E, ENT_LDS, true, false>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+    (void)hipFuncSetAttribute((const void *)k_lb2<E, ENT_LDS, false, true>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+    (void)hipFuncSetAttribute((const void *)k_lb2<E, ENT_LDS, false, false>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+    attr_set = true;
+  }
+  if (subset) {
+    if (log)
+      hipLaunchKernelGGL((k_lb2<E, ENT_LDS, true, true>), g, b, lds, s, I, pool, ub, costs,
+                         out_lb, out_prune, xrows);
+    else
+      hipLaunchKernelGGL((k_lb2<E, ENT_LDS, true, false>), g, b, lds, s, I, pool, ub, costs,
+                         out_lb, out_prune, xrows);
+  } else {
+    if (log)
+      hipLaunchKernelGGL((k_lb2<E, ENT_LDS, false, true>), g, b, lds, s, I, pool, ub, costs,
+                         out_lb, out_prune, xrows);
+    else
+      hipLaunchKernelGGL((k_lb2<E, ENT_LDS, false, false>), g, b, lds, s, I, pool, ub, costs,
+                         out_lb, out_prune, xrows);
+  }
+}
+
+int launch_bound(Ctx *c, const DevPool &pool, int kind, int ub, int *out_lb, uint8_t *out_prune,
+                 hipStream_t s) {
+  if (pool.count <= 0) return PFSP_OK;
+  const DevInst I = c->inst();
+  const int n = c->n, m = c->m;
+  // k_lb1: per-lane arrays of 3m ints in LDS plus the staged p
+  int b1 = 128;
+  size_t lds1 = ((size_t)n * m + 3 * (size_t)m * b1) * 4;
+  if (lds1 > 64 * 1024) {
+    b1 = 64;
+    lds1 = ((size_t)n * m + 3 * (size_t)m * b1) * 4;
+  }
+  const int g1 = (pool.count + b1 - 1) / b1;
+  static bool attr1 = false;
+  if (!attr1) {
+    (void)hipFuncSetAttribute((const void *)k_lb1, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    attr1 = true;
+  }
+  if (kind == PFSP_LB1) {
+    KTimer kt(c, s, "k_lb1");
+    hipLaunchKernelGGL(k_lb1, dim3(g1), dim3(b1), lds1, s, I, pool, ub, out_lb, out_prune,
+                       (int *)nullptr, 1, c->d_flag);
+    PFSP_HIP(c, hipGetLastError());
+    return PFSP_OK;
+  }
+  int rc = ensure_costs(c, pool.count);
+  if (rc) return rc;
+  {
+    KTimer kt(c, s, "k_lb1");
+    hipLaunchKernelGGL(k_lb1, dim3(g1), dim3(b1), lds1, s, I, pool, ub, out_lb, out_prune,
+                       c->d_costs, 0, c->d_flag);
+  }
+  PFSP_HIP(c, hipGetLastError());
+  const bool subset = kind == PFSP_LB2_SUBSET;
+  const bool log = pool.argpair != nullptr;
+  const int xrows = n < 32 ? n : 32;
+  int waves = 8;
+  bool ent_lds = lb2_lds(c, 1, true, xrows) <= 64 * 1024;
+  size_t lds = lb2_lds(c, waves, ent_lds, xrows);
+  while (lds > 160 * 1024 && waves > 1) {
+    waves >>= 1;
+    lds = lb2_lds(c, waves, ent_lds, xrows);
+  }
+  int grid = (pool.count + waves - 1) / waves;
+  const int cap = c->cu_count * 8;
+  if (grid > cap) grid = cap;
+  const dim3 g(grid), bl(64 * waves);
+  KTimer kt(c, s, "k_lb2");
+  if (c->narrow) {
+    if (ent_lds)
+      launch_lb2_e<Narrow, true>(subset, log, g, bl, lds, s, I, pool, ub, c->d_costs, out_lb,
+                                 out_prune, xrows);
+    else
+      launch_lb2_e<Narrow, false>(subset, log, g, bl, lds, s, I, pool, ub, c->d_costs, out_lb,
+                                  out_prune, xrows);
+  } else {
+    if (ent_lds)
+      launch_lb2_e<Wide, true>(subset, log, g, bl, lds, s, I, pool, ub, c->d_costs, out_lb,
+                               out_prune, xrows);
+    else
+      launch_lb2_e<Wide, false>(subset, log, g, bl, lds, s, I, pool, ub, c->d_costs, out_lb,
+                                out_prune, xrows);
+  }
+  PFSP_HIP(c, hipGetLastError());
+  return PFSP_OK;
+}
+
+}  // namespace pfsp

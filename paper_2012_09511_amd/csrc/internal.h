@@ -1,0 +1,143 @@
+// Internal declarations of the gfx950 flow-shop bounding library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/pfsp.h"
+
+namespace pfsp {
+
+constexpr int kMaxN = 255;
+constexpr int kMaxM = 64;
+// Sentinel below every reachable bound value: instances are limited to
+// (n + m - 1) * max(p) < 2^30, so NEG minus any processing time stays above
+// INT32_MIN and NEG plus any path length stays negative.
+constexpr int kNeg = -(1 << 30);
+constexpr int kInt32Max = 0x7fffffff;
+
+// Device view of a staged instance (Section 2.4: pre-sorted two-machine
+// schedules for every machine pair).
+struct DevInst {
+  int n, m, P;
+  int narrow;              // 1: ent holds packed 8-byte entries, else entw
+  const int *p;            // [n][m] processing times
+  const int *T;            // [m] per-machine totals
+  const uint2 *ent;        // [n][P] narrow entries: x = a | b << 16, y = lag | k << 24
+  const uint4 *entw;       // [n][P] wide entries: {a, b, lag, k}
+  const uint8_t *pu;       // [P] first machine of pair
+  const uint8_t *pv;       // [P] second machine of pair
+};
+
+// Parent batch as seen by the kernels.
+struct DevPool {
+  int count, n;
+  const uint8_t *perm, *d1, *d2;
+  const uint32_t *mask;
+  int mask_words;
+  uint8_t *dir;
+  int16_t *argpair;
+};
+
+struct Selector;   // learned pair selector state (selector.hip)
+struct SearchState;
+
+struct Ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  // instance
+  int n = 0, m = 0, P = 0;
+  int maxp = 0;
+  int *p_host = nullptr;
+  int *d_p = nullptr, *d_T = nullptr;
+  uint2 *d_ent = nullptr;
+  uint4 *d_entw = nullptr;
+  uint8_t *d_pu = nullptr, *d_pv = nullptr;
+  int narrow = 1;
+  // workspace: parent front/back/remaining [count][3][m]
+  int *d_costs = nullptr;
+  size_t costs_cap = 0;
+  int *d_flag = nullptr;   // [4] device status words: [0] invalid-row flag
+  // options
+  int64_t pool_batch = 65536;
+  int64_t poll_every = 8;
+  int64_t pool_capacity = 0;
+  int64_t use_graph = 1;
+  int64_t learned_topk = 16;
+  int64_t learned_exact = 0;
+  int64_t timing = 0;
+  struct Pending {
+    const char *name;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;              // launches whose events are not read yet
+  std::map<std::string, std::pair<double, int64_t>> ktime;  // name -> (ms, launches)
+  int capturing = 0;                         // a HIP graph capture is in progress
+  Selector *sel = nullptr;
+  SearchState *search = nullptr;
+  int cu_count = 256;
+  DevInst inst() const {
+    DevInst I;
+    I.n = n; I.m = m; I.P = P; I.narrow = narrow;
+    I.p = d_p; I.T = d_T; I.ent = d_ent; I.entw = d_entw; I.pu = d_pu; I.pv = d_pv;
+    return I;
+  }
+};
+
+int set_err(Ctx *c, int code, const std::string &msg);
+int hip_err(Ctx *c, hipError_t e, const char *what);
+#define PFSP_HIP(c, call)                         \
+  do {                                            \
+    hipError_t e_ = (call);                       \
+    if (e_ != hipSuccess) return hip_err((c), e_, #call); \
+  } while (0)
+
+// Event bracketing of kernel launches (option "timing"); no-ops otherwise or
+// while a graph is being captured.
+struct KTimer {
+  Ctx *c;
+  hipStream_t s;
+  const char *name;
+  hipEvent_t a = nullptr, b = nullptr;
+  KTimer(Ctx *c_, hipStream_t s_, const char *name_) : c(c_), s(s_), name(name_) {
+    if (c->timing && !c->capturing && hipEventCreate(&a) == hipSuccess &&
+        hipEventCreate(&b) == hipSuccess)
+      (void)hipEventRecord(a, s);
+    else
+      a = b = nullptr;
+  }
+  ~KTimer() {
+    if (a && b) {
+      (void)hipEventRecord(b, s);
+      c->pending.push_back({name, a, b});
+    }
+  }
+};
+void collect_timings(Ctx *c);
+
+// stage.hip
+int stage_instance(Ctx *c);
+// bound.hip
+int ensure_costs(Ctx *c, int count);
+int launch_bound(Ctx *c, const DevPool &pool, int kind, int ub, int *out_lb,
+                 uint8_t *out_prune, hipStream_t s);
+size_t lb2_lds_bytes(const Ctx *c, int waves);
+// selector.hip
+int launch_learned(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8_t *out_prune,
+                   hipStream_t s);
+void selector_free(Ctx *c);
+// search.hip
+void search_free(Ctx *c);
+// neh.cpp
+int neh_host(int n, int m, const int *p, int *perm_out, int *cmax_out);
+
+}  // namespace pfsp
+
+struct pfsp_ctx {
+  pfsp::Ctx impl;
+};

@@ -1,0 +1,119 @@
+// Wave64 helpers for gfx950 (CDNA4): 64 lanes execute in lockstep, so
+// exchanging data through LDS inside one wave needs no workgroup barrier,
+// only ordering of the LDS accesses.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace pfsp {
+
+constexpr int kWave = 64;
+
+// Orders this wave's LDS accesses around the call (no cross-wave effect).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int wave_min(int x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x = min(x, __shfl_xor(x, o, kWave));
+  return x;
+}
+
+__device__ __forceinline__ int wave_max(int x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x = max(x, __shfl_xor(x, o, kWave));
+  return x;
+}
+
+__device__ __forceinline__ long long wave_sum64(long long x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, kWave);
+  return x;
+}
+
+__device__ __forceinline__ int wave_popc(bool pred) {
+  return __popcll(__ballot(pred));
+}
+
+// Transposing max-reduction: lane L holds acc[0..63]; on return lane L holds
+// in acc[0] the maximum over all lanes of the original acc[L].  63 exchanges
+// instead of 64 separate 6-step reductions.
+__device__ __forceinline__ void transpose_max64(int (&acc)[64], int lane) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const bool hi = (lane & o) != 0;
+#pragma unroll
+    for (int j = 0; j < o; ++j) {
+      const int send = hi ? acc[j] : acc[o + j];
+      const int keep = hi ? acc[o + j] : acc[j];
+      acc[j] = max(keep, __shfl_xor(send, o, kWave));
+    }
+  }
+}
+
+// Same reduction carrying an argument: the larger value wins, equal values
+// keep the smaller argument.
+__device__ __forceinline__ void transpose_argmax64(int (&acc)[64], int (&arg)[64], int lane) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const bool hi = (lane & o) != 0;
+#pragma unroll
+    for (int j = 0; j < o; ++j) {
+      const int sv = hi ? acc[j] : acc[o + j];
+      const int sa = hi ? arg[j] : arg[o + j];
+      const int kv = hi ? acc[o + j] : acc[j];
+      const int ka = hi ? arg[o + j] : arg[j];
+      const int rv = __shfl_xor(sv, o, kWave);
+      const int ra = __shfl_xor(sa, o, kWave);
+      const bool take = rv > kv || (rv == kv && ra < ka);
+      acc[j] = take ? rv : kv;
+      arg[j] = take ? ra : ka;
+    }
+  }
+}
+
+// MinMin accumulator (Section 2.3): minimum LB over both children sets,
+// how often each set attains it, and the LB sums.
+struct MinMin {
+  int mn;
+  int cf, cb;
+  long long sf, sb;
+  __device__ __forceinline__ void init() {
+    mn = 0x7fffffff;
+    cf = cb = 0;
+    sf = sb = 0;
+  }
+  __device__ __forceinline__ void add(int x, bool backward) {
+    if (x < mn) {
+      mn = x;
+      cf = cb = 0;
+    }
+    if (x == mn) {
+      if (backward) ++cb; else ++cf;
+    }
+    if (backward) sb += x; else sf += x;
+  }
+  // merge a partial state (same definitions) into this one
+  __device__ __forceinline__ void merge(int mn2, int cf2, int cb2, long long sf2, long long sb2) {
+    if (mn2 < mn) {
+      mn = mn2;
+      cf = cf2;
+      cb = cb2;
+    } else if (mn2 == mn) {
+      cf += cf2;
+      cb += cb2;
+    }
+    sf += sf2;
+    sb += sb2;
+  }
+  // 0 = forward, 1 = backward: fewer occurrences of the minimum wins, then
+  // the larger sum, then forward.
+  __device__ __forceinline__ int dir() const {
+    if (cf != cb) return cb < cf ? 1 : 0;
+    return sb > sf ? 1 : 0;
+  }
+};
+
+}  // namespace pfsp

@@ -1,0 +1,169 @@
+"""GPU parity of pfsp_bound_children against the CPU oracle.
+
+Bounds, prune flags, MinMin directions and logged argmax pairs are integers:
+the bar is bit-exact equality on the same seeded inputs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2012_09511_amd import binding, inputs
+
+pytestmark = pytest.mark.gpu
+
+INT32_MAX = binding.INT32_MAX
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = binding.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(ctx, *arrays):
+    import torch
+    return [torch.from_numpy(np.ascontiguousarray(a)).to(ctx.device) for a in arrays]
+
+
+def _check(ctx, p, perm, d1, d2, kind, ub, mask=None, argpair=False, threads=8):
+    import torch
+    ctx.load_instance(p)
+    tp, t1, t2 = _dev(ctx, perm, d1, d2)
+    tm = None if mask is None else _dev(ctx, mask)[0]
+    lb, pr, dr, ap = ctx.bound_children(tp, t1, t2, kind, ub, pair_mask=tm,
+                                        want_argpair=argpair)
+    torch.cuda.synchronize()
+    ctx.check()
+    olb, opr, odr, oap = oracle.bound_children(p, perm, d1, d2, kind, ub, pair_mask=mask,
+                                               with_argpair=True, threads=threads)
+    np.testing.assert_array_equal(lb.cpu().numpy(), olb)
+    np.testing.assert_array_equal(pr.cpu().numpy(), opr)
+    np.testing.assert_array_equal(dr.cpu().numpy(), odr)
+    if argpair:
+        np.testing.assert_array_equal(ap.cpu().numpy().astype(np.int32), oap)
+    return olb
+
+
+SHAPES = [(2, 1), (2, 2), (3, 2), (5, 3), (10, 5), (20, 20), (20, 10), (33, 7), (50, 20),
+          (64, 4), (100, 20), (130, 3)]
+
+
+@pytest.mark.parametrize("n,m", SHAPES)
+def test_lb1_parity(ctx, n, m):
+    p = inputs.instance(n, m, 1000 + n * 64 + m)
+    count = 300 if n <= 50 else 40
+    perm, d1, d2 = inputs.random_pool(n, count, 7 + n)
+    olb = _check(ctx, p, perm, d1, d2, binding.LB1, INT32_MAX)
+    # a mid-range incumbent so that prune flags vary
+    ub = int(np.median(olb[olb < INT32_MAX]))
+    _check(ctx, p, perm, d1, d2, binding.LB1, ub)
+
+
+@pytest.mark.parametrize("n,m", [s for s in SHAPES if s[1] >= 2])
+def test_lb2_full_parity(ctx, n, m):
+    p = inputs.instance(n, m, 2000 + n * 64 + m)
+    count = 200 if n <= 33 else 6
+    perm, d1, d2 = inputs.random_pool(n, count, 11 + n)
+    olb = _check(ctx, p, perm, d1, d2, binding.LB2_FULL, INT32_MAX, argpair=True)
+    ub = int(np.median(olb[olb < INT32_MAX]))
+    _check(ctx, p, perm, d1, d2, binding.LB2_FULL, ub)
+
+
+@pytest.mark.parametrize("n,m", [(10, 5), (20, 20), (20, 10), (33, 7), (50, 20)])
+def test_lb2_subset_parity(ctx, n, m):
+    p = inputs.instance(n, m, 3000 + n + m)
+    count = 150 if n <= 33 else 8
+    perm, d1, d2 = inputs.random_pool(n, count, 13 + n)
+    P = m * (m - 1) // 2
+    words = (P + 31) // 32
+    rng = np.random.default_rng(n * m)
+    mask = np.zeros((count, words), dtype=np.uint32)
+    for i in range(count):
+        k = [0, 1, 16, P][i % 4] if P >= 16 else [0, 1, P][i % 3]
+        for b in rng.choice(P, size=min(k, P), replace=False):
+            mask[i, b >> 5] |= np.uint32(1 << (int(b) & 31))
+    _check(ctx, p, perm, d1, d2, binding.LB2_SUBSET, INT32_MAX, mask=mask, argpair=True)
+    _check(ctx, p, perm, d1, d2, binding.LB2_SUBSET, 1500, mask=mask)
+
+
+@pytest.mark.parametrize("kind", [binding.LB1, binding.LB2_FULL])
+def test_edge_depths(ctx, kind):
+    """Root nodes, leaf-parents (one unscheduled job) and every depth in between."""
+    n, m = 12, 6
+    p = inputs.instance(n, m, 4242)
+    rows = []
+    for d in range(n):
+        perm, d1, d2 = inputs.random_pool(n, 6, 100 + d, depth=d)
+        rows.append((perm, d1, d2))
+    perm = np.concatenate([r[0] for r in rows])
+    d1 = np.concatenate([r[1] for r in rows])
+    d2 = np.concatenate([r[2] for r in rows])
+    olb = _check(ctx, p, perm, d1, d2, kind, INT32_MAX)
+    # leaf children carry their makespan
+    leaf = np.where(d1.astype(int) + d2.astype(int) == n - 1)[0]
+    for i in leaf:
+        assert olb[i, 0, 0] == oracle.makespan(p, perm[i])
+    _check(ctx, p, perm, d1, d2, kind, int(olb[olb < INT32_MAX].min()))
+
+
+def test_wide_processing_times(ctx):
+    """Processing times above 2^16 use the wide pair-table format."""
+    n, m = 9, 6
+    rng = np.random.default_rng(5)
+    p = rng.integers(1, (1 << 30) // (n + m) - 1, size=(n, m)).astype(np.int32)
+    perm, d1, d2 = inputs.random_pool(n, 120, 6)
+    for kind in (binding.LB1, binding.LB2_FULL):
+        _check(ctx, p, perm, d1, d2, kind, INT32_MAX)
+
+
+def test_empty_and_invalid_rows(ctx):
+    import torch
+    n, m = 8, 4
+    p = inputs.instance(n, m, 9)
+    ctx.load_instance(p)
+    e = torch.empty((0, n), dtype=torch.uint8, device=ctx.device)
+    e1 = torch.empty(0, dtype=torch.uint8, device=ctx.device)
+    ctx.bound_children(e, e1, e1, binding.LB2_FULL, 100)
+    ctx.check()
+    perm, d1, d2 = inputs.random_pool(n, 4, 10)
+    d1[1], d2[1] = 5, 3          # d1 + d2 = n
+    perm[2, 3] = perm[2, 4]      # not a permutation
+    perm[3, 0] = 200             # job id out of range
+    for kind in (binding.LB1, binding.LB2_FULL):
+        tp, t1, t2 = _dev(ctx, perm, d1, d2)
+        lb, pr, dr, _ = ctx.bound_children(tp, t1, t2, kind, 1000)
+        with pytest.raises(binding.PfspError):
+            ctx.check()
+        lb = lb.cpu().numpy()
+        assert (lb[1:] == INT32_MAX).all() and (pr.cpu().numpy()[1:] == 1).all()
+        olb, _, _ = oracle.bound_children(p, perm[:1], d1[:1], d2[:1], kind, 1000)
+        np.testing.assert_array_equal(lb[:1], olb)
+        ctx.check()   # the condition was cleared
+
+
+def test_full_size_pool_sampled(ctx):
+    """The bound-kernel benchmark workload: n=20, m=20, 1,048,576 parents, in the
+    launch configuration the benchmark uses; 1500 sampled rows against the oracle."""
+    import torch
+    n, m, N = 20, 20, 1 << 20
+    p = inputs.instance(n, m, 2012)
+    perm, d1, d2 = inputs.random_pool(n, N, 9511)
+    ctx.load_instance(p)
+    tp, t1, t2 = _dev(ctx, perm, d1, d2)
+    rng = np.random.default_rng(1)
+    idx = np.sort(rng.choice(N, size=1500, replace=False))
+    for kind in (binding.LB1, binding.LB2_FULL):
+        lb, pr, dr, _ = ctx.bound_children(tp, t1, t2, kind, INT32_MAX)
+        torch.cuda.synchronize()
+        ctx.check()
+        olb, opr, odr = oracle.bound_children(p, perm[idx], d1[idx], d2[idx], kind, INT32_MAX,
+                                              threads=8)
+        np.testing.assert_array_equal(lb.cpu().numpy()[idx], olb)
+        np.testing.assert_array_equal(pr.cpu().numpy()[idx], opr)
+        np.testing.assert_array_equal(dr.cpu().numpy()[idx], odr)
+        # properties that hold at every row: valid slots are finite and exactly
+        # 2(n - d) children per parent are bounded
+        r = n - d1.astype(np.int64) - d2.astype(np.int64)
+        fin = (lb.cpu().numpy() < INT32_MAX).sum(axis=(1, 2))
+        np.testing.assert_array_equal(fin, 2 * r)

@@ -81,6 +81,8 @@ def main():
     ap.add_argument("--parents", type=int, default=1 << 20)
     ap.add_argument("--kind", default="LB2_FULL", choices=["LB1", "LB2_FULL"])
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the bounding path has no multi-GPU mode in this "
@@ -103,6 +105,12 @@ def main():
     out_dir = torch.empty(N, dtype=torch.uint8, device="cuda")
     children = int((2 * (n - d1.astype(np.int64) - d2.astype(np.int64))).sum())
 
+    if args.copy_probe:
+        src = torch.ones(64 << 20, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         ctx.bound_children(*dev, kind=kind, ub=ub, out_lb=out_lb, out_prune=out_pr,
                            dir_out=out_dir)

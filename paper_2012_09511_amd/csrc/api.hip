@@ -219,6 +219,8 @@ static int64_t *opt_slot(Ctx *c, const char *key) {
   if (!strcmp(key, "learned_topk")) return &c->learned_topk;
   if (!strcmp(key, "learned_exact")) return &c->learned_exact;
   if (!strcmp(key, "timing")) return &c->timing;
+  if (!strcmp(key, "force_generic")) return &c->force_generic;
+  if (!strcmp(key, "lb2_waves")) return &c->lb2_waves;
   return nullptr;
 }
 
@@ -233,9 +235,12 @@ int pfsp_set_option(pfsp_ctx *h, const char *key, int64_t value) {
     return set_err(c, PFSP_ERANGE, "poll_every must be in [1, 4096]");
   if (!strcmp(key, "pool_capacity") && value < 0)
     return set_err(c, PFSP_ERANGE, "pool_capacity must be >= 0");
+  if (!strcmp(key, "lb2_waves") && (value < 0 || value > 8))
+    return set_err(c, PFSP_ERANGE, "lb2_waves must be in [0, 8]");
   if (!strcmp(key, "learned_topk") && (value < 1 || value > 2016))
     return set_err(c, PFSP_ERANGE, "learned_topk must be in [1, 2016]");
-  if ((!strcmp(key, "use_graph") || !strcmp(key, "learned_exact") || !strcmp(key, "timing")) &&
+  if ((!strcmp(key, "use_graph") || !strcmp(key, "learned_exact") || !strcmp(key, "timing") ||
+       !strcmp(key, "force_generic")) &&
       value != 0 && value != 1)
     return set_err(c, PFSP_EINVAL, "flag options take 0 or 1");
   if (!strcmp(key, "pool_batch") || !strcmp(key, "pool_capacity")) search_free(c);

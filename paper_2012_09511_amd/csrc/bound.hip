@@ -29,6 +29,8 @@
 //   recurrence unrolls to max(h_v + B, h_u + max_i term_i)).  The maxima over
 //   pairs are kept per child in registers and reduced across lanes by a
 //   transposing exchange at the end.
+#include <type_traits>
+
 #include "internal.h"
 #include "wave.h"
 
@@ -351,6 +353,281 @@ k_lb2(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__res
   }
 }
 
+// ------------------------------------------------------------- LB2, fast path
+// Same computation as k_lb2 for instances with n <= NMAX <= 64 and packed
+// (narrow) pair entries.  The pair table is staged in LDS padded to NMAX rows
+// and to whole waves of pairs, so the two scans are fully unrolled and free
+// of branches: membership of each job in the parent's unscheduled set comes
+// from a wave-uniform bit mask, non-members contribute zeros, and the prefix
+// maxima of the forward scan stay in registers.  X(j) is kept per lane in an
+// LDS column indexed by job id.
+template <int NMAX>
+struct MaskT {
+  using T = typename std::conditional<(NMAX <= 32), uint32_t, uint64_t>::type;
+  __device__ __forceinline__ static int neg(T mask, int k) {  // -1 if k is a member, else 0
+    if constexpr (NMAX <= 32)
+      return __builtin_amdgcn_sbfe((int)mask, k, 1);
+    else
+      return -(int)((mask >> k) & 1u);
+  }
+};
+
+template <int NMAX, bool SUBSET, bool LOG>
+__global__ void __launch_bounds__(512)
+k_lb2f(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__restrict__ out_lb,
+       uint8_t *__restrict__ out_prune, int Ppad) {
+  extern __shared__ __align__(16) unsigned char sm[];
+  using M = MaskT<NMAX>;
+  using MT = typename M::T;
+  // pair entries stay in registers between the two scans when they fit
+  constexpr bool KEEP = NMAX <= 20 && !LOG && !SUBSET;
+  constexpr bool PMB_REG = NMAX <= 24 && !LOG;
+  const int n = I.n, m = I.m, P = I.P;
+  const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int xr = NMAX < 32 ? NMAX : 32;
+  uint2 *ent = (uint2 *)sm;  // [NMAX][Ppad]
+  size_t off = align16((size_t)NMAX * Ppad * 8);
+  int *uv = (int *)(sm + off);  // [Ppad]: u | v << 8
+  off += align16((size_t)Ppad * 4);
+  int *sp = (int *)(sm + off);  // p[n][m]
+  off += align16((size_t)n * m * 4);
+  const size_t per_wave = align16((size_t)NMAX * 64 * 8) + align16((size_t)xr * m * 8) +
+                          align16((size_t)3 * m * 4) + align16((size_t)NMAX * 4);
+  unsigned char *wb = sm + off + w * per_wave;
+  int2 *X = (int2 *)wb;  // [NMAX][64]: per job, per lane
+  wb += align16((size_t)NMAX * 64 * 8);
+  int2 *FB = (int2 *)wb;  // [xr][m]
+  wb += align16((size_t)xr * m * 8);
+  int *c1 = (int *)wb, *c2 = c1 + m, *rr = c2 + m;
+  wb += align16((size_t)3 * m * 4);
+  int *jobs = (int *)wb;  // [NMAX]
+
+  // stage the padded pair table: rows >= n and pairs >= P hold a job id that
+  // is never a member (NMAX - 1 >= n whenever such rows exist) and zero times
+  const unsigned kpad = (unsigned)(NMAX - 1) << 24;
+  for (int x = threadIdx.x; x < NMAX * Ppad; x += blockDim.x) {
+    const int i = x / Ppad, pi = x - i * Ppad;
+    ent[x] = (i < n && pi < P) ? I.ent[(size_t)i * P + pi] : make_uint2(0u, kpad);
+  }
+  for (int x = threadIdx.x; x < Ppad; x += blockDim.x)
+    uv[x] = x < P ? ((int)I.pu[x] | ((int)I.pv[x] << 8)) : 0;
+  for (int x = threadIdx.x; x < n * m; x += blockDim.x) sp[x] = I.p[x];
+  __syncthreads();
+
+  for (int par = blockIdx.x * nw + w; par < pool.count; par += gridDim.x * nw) {
+    const int a = pool.d1[par], b = pool.d2[par], r = n - a - b;
+    int *lbrow = out_lb + (size_t)par * 2 * n;
+    uint8_t *prow = out_prune + (size_t)par * 2 * n;
+    int16_t *arow = LOG ? pool.argpair + (size_t)par * 2 * n : nullptr;
+    if (r < 1 || costs[(size_t)par * 3 * m] < 0) continue;  // flagged by k_lb1
+    MT bits = 0;
+    for (int x = lane; x < n; x += 64) {
+      const int j = pool.perm[(size_t)par * n + x];
+      jobs[x] = j;
+      if (x >= a && x < a + r) bits |= (MT)1 << j;
+    }
+    for (int x = lane; x < m; x += 64) {
+      const int *cs = costs + (size_t)par * 3 * m;
+      c1[x] = cs[x];
+      c2[x] = cs[m + x];
+      rr[x] = cs[2 * m + x];
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) bits |= __shfl_xor(bits, o, kWave);
+    MT umask;
+    if constexpr (NMAX <= 32) {
+      umask = (MT)__builtin_amdgcn_readfirstlane((int)bits);
+    } else {
+      const uint32_t lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)bits);
+      const uint32_t hi = __builtin_amdgcn_readfirstlane((int)(uint32_t)(bits >> 32));
+      umask = ((MT)hi << 32) | lo;
+    }
+    wave_sync();
+    MinMin mm;
+    mm.init();
+    for (int cb = 0; cb < r; cb += 32) {
+      const int nq = min(32, r - cb);
+      int lb1 = kNeg;
+      const int ql = lane & 31;
+      const int myjob = ql < nq ? jobs[a + cb + ql] : 0;
+      if (ql < nq) {
+        const int *pj = sp + myjob * m;
+        int c = 0, l = 0;
+        if (lane < 32) {
+          for (int k = 0; k < m; ++k) {
+            c = max(c, c1[k]) + pj[k];
+            FB[ql * m + k].x = c - pj[k];
+            l = max(l, c + rr[k] - pj[k] + c2[k]);
+          }
+        } else {
+          for (int k = m - 1; k >= 0; --k) {
+            c = max(c, c2[k]) + pj[k];
+            FB[ql * m + k].y = c - pj[k];
+            l = max(l, c1[k] + rr[k] - pj[k] + c);
+          }
+        }
+        lb1 = l;
+      }
+      wave_sync();
+      int acc[64];
+      int arg[LOG ? 64 : 1];
+#pragma unroll
+      for (int q = 0; q < 64; ++q) acc[q] = kNeg;
+      if constexpr (LOG) {
+#pragma unroll
+        for (int q = 0; q < 64; ++q) arg[q] = 0x7fffffff;
+      }
+      for (int pc = 0; pc < Ppad; pc += 64) {
+        const int pi = pc + lane;
+        bool act = pi < P;
+        if (SUBSET && act)
+          act = (pool.mask[(size_t)par * pool.mask_words + (pi >> 5)] >> (pi & 31)) & 1u;
+        const int uvp = uv[pi];
+        const int u = uvp & 0xff, v = uvp >> 8;
+        const int RU = rr[u], RV = rr[v], C1u = c1[u], C1v = c1[v], C2u = c2[u], C2v = c2[v];
+        uint2 e[KEEP ? NMAX : 1];
+        if constexpr (KEEP) {
+#pragma unroll
+          for (int i = 0; i < NMAX; ++i) e[i] = ent[i * Ppad + pi];
+        }
+        // forward scan: exclusive prefix maxima of term - B(U), minus b (kept in
+        // registers when they fit, else in the lane's X column)
+        int pmb[PMB_REG ? NMAX : 1];
+        int Y = 0, Pm = kNeg;
+#pragma unroll
+        for (int i = 0; i < NMAX; ++i) {
+          const uint2 ei = KEEP ? e[KEEP ? i : 0] : ent[i * Ppad + pi];
+          const int ea = (int)(ei.x & 0xffffu), eb = (int)(ei.x >> 16);
+          const int el = (int)(ei.y & 0xffffffu), ek = (int)(ei.y >> 24);
+          const int ng = M::neg(umask, ek);
+          Y += ea & ng;
+          const int tt = Y + el;
+          if constexpr (PMB_REG)
+            pmb[PMB_REG ? i : 0] = Pm - eb;
+          else
+            X[ek * 64 + lane].x = Pm - eb;
+          Pm = max(Pm, ng ? tt : kNeg);
+          Y -= eb & ng;
+        }
+        // backward scan: exclusive suffix maxima; X(j) = max(PM - b, SM - a)
+        const int c0 = RU - RV;
+        int Wb = 0, Sm = kNeg;
+#pragma unroll
+        for (int i = NMAX - 1; i >= 0; --i) {
+          const uint2 ei = KEEP ? e[KEEP ? i : 0] : ent[i * Ppad + pi];
+          const int ea = (int)(ei.x & 0xffffu), eb = (int)(ei.x >> 16);
+          const int el = (int)(ei.y & 0xffffffu), ek = (int)(ei.y >> 24);
+          const int ng = M::neg(umask, ek);
+          Wb += eb & ng;
+          const int tp = Wb + el + c0;
+          const int pm = PMB_REG ? pmb[PMB_REG ? i : 0] : X[ek * 64 + lane].x;
+          const int x = max(pm, Sm - ea);
+          X[ek * 64 + lane] = make_int2(x + ea, x + eb);
+          Sm = max(Sm, ng ? tp : kNeg);
+          Wb -= ea & ng;
+        }
+        const int K1 = RU + C2u, K2 = C1u + RU, K3 = C1v + RV;
+#pragma unroll
+        for (int q = 0; q < 32; ++q) {
+          if (q < nq) {
+            const int kq = __builtin_amdgcn_readlane(myjob, q);
+            const int2 xab = X[kq * 64 + lane];
+            const int2 fu = FB[q * m + u], fv = FB[q * m + v];
+            const int xa = xab.x + RV, xb = xab.y + RV;
+            int lbf = max(fu.x + K1, max(fv.x + RV, fu.x + xa) + C2v);
+            int lbb = max(fu.y + K2, max(K3, C1u + xb) + fv.y);
+            lbf = act ? lbf : kNeg;
+            lbb = act ? lbb : kNeg;
+            if constexpr (LOG) {
+              if (lbf > acc[q]) { acc[q] = lbf; arg[q] = pi; }
+              if (lbb > acc[32 + q]) { acc[32 + q] = lbb; arg[32 + q] = pi; }
+            } else {
+              acc[q] = max(acc[q], lbf);
+              acc[32 + q] = max(acc[32 + q], lbb);
+            }
+          }
+        }
+      }
+      if constexpr (LOG) {
+        transpose_argmax64(acc, arg, lane);
+      } else {
+        transpose_max64(acc, lane);
+      }
+      const bool mine = ql < nq;
+      const bool bwd = lane >= 32;
+      const int val = mine ? max(lb1, acc[0]) : kInt32Max;
+      if (mine) {
+        const int o = (bwd ? n : 0) + cb + ql;
+        lbrow[o] = val;
+        prow[o] = val >= ub;
+        if constexpr (LOG) arow[o] = (int16_t)(acc[0] > kNeg ? arg[0] : -1);
+      }
+      const int cmn = wave_min(val);
+      const int ccf = wave_popc(mine && !bwd && val == cmn);
+      const int ccb = wave_popc(mine && bwd && val == cmn);
+      const long long csf = wave_sum64(mine && !bwd ? (long long)val : 0);
+      const long long csb = wave_sum64(mine && bwd ? (long long)val : 0);
+      mm.merge(cmn, ccf, ccb, csf, csb);
+      wave_sync();
+    }
+    fill_invalid(lbrow, prow, arow, n, r, lane, 64);
+    if (pool.dir && lane == 0) pool.dir[par] = (uint8_t)mm.dir();
+  }
+}
+
+static size_t lb2f_lds(const Ctx *c, int nmax, int waves) {
+  const int m = c->m, n = c->n;
+  const int Ppad = (c->P + 63) / 64 * 64;
+  const int xr = nmax < 32 ? nmax : 32;
+  size_t s = align16((size_t)nmax * Ppad * 8) + align16((size_t)Ppad * 4) +
+             align16((size_t)n * m * 4);
+  const size_t pw = align16((size_t)nmax * 64 * 8) + align16((size_t)xr * m * 8) +
+                    align16((size_t)3 * m * 4) + align16((size_t)nmax * 4);
+  return s + waves * pw;
+}
+
+template <int NMAX>
+static void launch_lb2f_n(bool subset, bool log, dim3 g, dim3 b, size_t lds, hipStream_t s,
+                          const DevInst &I, const DevPool &pool, int ub, const int *costs,
+                          int *out_lb, uint8_t *out_prune, int Ppad) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    const int mx = 160 * 1024;
+    (void)hipFuncSetAttribute((const void *)k_lb2f<NMAX, true, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+    (void)hipFuncSetAttribute((const void *)k_lb2f<NMAX, true, false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+    (void)hipFuncSetAttribute((const void *)k_lb2f<NMAX, false, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+    (void)hipFuncSetAttribute((const void *)k_lb2f<NMAX, false, false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+    attr_set = true;
+  }
+  if (subset) {
+    if (log)
+      hipLaunchKernelGGL((k_lb2f<NMAX, true, true>), g, b, lds, s, I, pool, ub, costs, out_lb,
+                         out_prune, Ppad);
+    else
+      hipLaunchKernelGGL((k_lb2f<NMAX, true, false>), g, b, lds, s, I, pool, ub, costs, out_lb,
+                         out_prune, Ppad);
+  } else {
+    if (log)
+      hipLaunchKernelGGL((k_lb2f<NMAX, false, true>), g, b, lds, s, I, pool, ub, costs, out_lb,
+                         out_prune, Ppad);
+    else
+      hipLaunchKernelGGL((k_lb2f<NMAX, false, false>), g, b, lds, s, I, pool, ub, costs,
+                         out_lb, out_prune, Ppad);
+  }
+}
+
+// Smallest compiled NMAX >= n (0 if none).
+static int fast_nmax(int n) {
+  static const int sizes[] = {8, 12, 16, 20, 24, 32, 64};
+  for (int s : sizes)
+    if (n <= s) return s;
+  return 0;
+}
+
 // -------------------------------------------------------------------- host
 int ensure_costs(Ctx *c, int count) {
   const size_t need = (size_t)(count > 0 ? count : 1) * 3 * c->m;
@@ -456,6 +733,43 @@ int launch_bound(Ctx *c, const DevPool &pool, int kind, int ub, int *out_lb, uin
   PFSP_HIP(c, hipGetLastError());
   const bool subset = kind == PFSP_LB2_SUBSET;
   const bool log = pool.argpair != nullptr;
+  const int nmax = c->narrow && !c->force_generic ? fast_nmax(n) : 0;
+  if (nmax) {
+    // waves per block: the most resident waves per CU within 160 KiB of LDS
+    int waves = 0, best = 0;
+    for (int w = 8; w >= 1; --w) {
+      const size_t l = lb2f_lds(c, nmax, w);
+      const int per_cu = l <= 160 * 1024 ? (int)((160 * 1024) / l) * w : 0;
+      if (per_cu > best) {
+        best = per_cu;
+        waves = w;
+      }
+    }
+    if (c->lb2_waves > 0 && lb2f_lds(c, nmax, (int)c->lb2_waves) <= 160 * 1024)
+      waves = (int)c->lb2_waves;
+    const size_t lds = waves ? lb2f_lds(c, nmax, waves) : 0;
+    if (waves) {
+      const int Ppad = (c->P + 63) / 64 * 64;
+      int grid = (pool.count + waves - 1) / waves;
+      const int cap = c->cu_count * 16;
+      if (grid > cap) grid = cap;
+      const dim3 g(grid), bl(64 * waves);
+      KTimer kt(c, s, "k_lb2");
+      switch (nmax) {
+#define PFSP_CASE(N)                                                                         \
+  case N:                                                                                    \
+    launch_lb2f_n<N>(subset, log, g, bl, lds, s, I, pool, ub, c->d_costs, out_lb, out_prune, \
+                     Ppad);                                                                  \
+    break;
+        PFSP_CASE(8) PFSP_CASE(12) PFSP_CASE(16) PFSP_CASE(20) PFSP_CASE(24) PFSP_CASE(32)
+        PFSP_CASE(64)
+#undef PFSP_CASE
+        default: break;
+      }
+      PFSP_HIP(c, hipGetLastError());
+      return PFSP_OK;
+    }
+  }
   const int xrows = n < 32 ? n : 32;
   int waves = 8;
   bool ent_lds = lb2_lds(c, 1, true, xrows) <= 64 * 1024;

@@ -71,6 +71,8 @@ struct Ctx {
   int64_t learned_topk = 16;
   int64_t learned_exact = 0;
   int64_t timing = 0;
+  int64_t force_generic = 0;
+  int64_t lb2_waves = 0;      // waves per block of the LB2 kernel (0 = automatic)  // 1: always use the generic LB2 kernel
   struct Pending {
     const char *name;
     hipEvent_t a, b;

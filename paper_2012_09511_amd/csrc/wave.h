@@ -39,39 +39,47 @@ __device__ __forceinline__ int wave_popc(bool pred) {
 
 // Transposing max-reduction: lane L holds acc[0..63]; on return lane L holds
 // in acc[0] the maximum over all lanes of the original acc[L].  63 exchanges
-// instead of 64 separate 6-step reductions.
-__device__ __forceinline__ void transpose_max64(int (&acc)[64], int lane) {
+// instead of 64 separate 6-step reductions.  Each step is a template
+// instance so that every array index is a compile-time constant (the array
+// stays in registers).
+template <int O>
+__device__ __forceinline__ void transpose_max_step(int (&acc)[64], int lane) {
+  const bool hi = (lane & O) != 0;
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    const bool hi = (lane & o) != 0;
-#pragma unroll
-    for (int j = 0; j < o; ++j) {
-      const int send = hi ? acc[j] : acc[o + j];
-      const int keep = hi ? acc[o + j] : acc[j];
-      acc[j] = max(keep, __shfl_xor(send, o, kWave));
-    }
+  for (int j = 0; j < O; ++j) {
+    const int send = hi ? acc[j] : acc[O + j];
+    const int keep = hi ? acc[O + j] : acc[j];
+    acc[j] = max(keep, __shfl_xor(send, O, kWave));
   }
+  if constexpr (O > 1) transpose_max_step<O / 2>(acc, lane);
+}
+
+__device__ __forceinline__ void transpose_max64(int (&acc)[64], int lane) {
+  transpose_max_step<32>(acc, lane);
 }
 
 // Same reduction carrying an argument: the larger value wins, equal values
 // keep the smaller argument.
-__device__ __forceinline__ void transpose_argmax64(int (&acc)[64], int (&arg)[64], int lane) {
+template <int O>
+__device__ __forceinline__ void transpose_argmax_step(int (&acc)[64], int (&arg)[64], int lane) {
+  const bool hi = (lane & O) != 0;
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    const bool hi = (lane & o) != 0;
-#pragma unroll
-    for (int j = 0; j < o; ++j) {
-      const int sv = hi ? acc[j] : acc[o + j];
-      const int sa = hi ? arg[j] : arg[o + j];
-      const int kv = hi ? acc[o + j] : acc[j];
-      const int ka = hi ? arg[o + j] : arg[j];
-      const int rv = __shfl_xor(sv, o, kWave);
-      const int ra = __shfl_xor(sa, o, kWave);
-      const bool take = rv > kv || (rv == kv && ra < ka);
-      acc[j] = take ? rv : kv;
-      arg[j] = take ? ra : ka;
-    }
+  for (int j = 0; j < O; ++j) {
+    const int sv = hi ? acc[j] : acc[O + j];
+    const int sa = hi ? arg[j] : arg[O + j];
+    const int kv = hi ? acc[O + j] : acc[j];
+    const int ka = hi ? arg[O + j] : arg[j];
+    const int rv = __shfl_xor(sv, O, kWave);
+    const int ra = __shfl_xor(sa, O, kWave);
+    const bool take = rv > kv || (rv == kv && ra < ka);
+    acc[j] = take ? rv : kv;
+    arg[j] = take ? ra : ka;
   }
+  if constexpr (O > 1) transpose_argmax_step<O / 2>(acc, arg, lane);
+}
+
+__device__ __forceinline__ void transpose_argmax64(int (&acc)[64], int (&arg)[64], int lane) {
+  transpose_argmax_step<32>(acc, arg, lane);
 }
 
 // MinMin accumulator (Section 2.3): minimum LB over both children sets,

@@ -167,3 +167,16 @@ def test_full_size_pool_sampled(ctx):
         r = n - d1.astype(np.int64) - d2.astype(np.int64)
         fin = (lb.cpu().numpy() < INT32_MAX).sum(axis=(1, 2))
         np.testing.assert_array_equal(fin, 2 * r)
+
+
+@pytest.mark.parametrize("n,m", [(20, 20), (12, 6), (64, 4)])
+def test_generic_kernel_parity(ctx, n, m):
+    """The generic LB2 kernel (used for n > 64 or wide times) on shapes the
+    fast kernel normally takes."""
+    p = inputs.instance(n, m, 5000 + n + m)
+    perm, d1, d2 = inputs.random_pool(n, 60, 17 + n)
+    ctx.set_option("force_generic", 1)
+    try:
+        _check(ctx, p, perm, d1, d2, binding.LB2_FULL, INT32_MAX, argpair=True)
+    finally:
+        ctx.set_option("force_generic", 0)

@@ -162,6 +162,57 @@ int pfsp_get_option(pfsp_ctx *c, const char *key, int64_t *value);
 int pfsp_kernel_time(pfsp_ctx *c, const char *kernel, double *total_ms, int64_t *launches,
                      int reset);
 
+/* ------------------------------------------------------------------------
+ * Learned machine-pair selector (PFSP_LB2_LEARNED).  Section 2.4 allows LB2
+ * variants over any number of machine pairs between m and m(m-1)/2; the
+ * maximum over any subset still bounds from below.  The selector scores the
+ * 190 pairs of a 20-machine layout from 64 features of a parent node with an
+ * MLP 64 -> 64 -> 64 -> 190 (ReLU, weights rounded to bfloat16, fp32
+ * accumulation); the `learned_topk` best pairs present on the instance (m <= 20)
+ * are bounded exactly.  Parameter layout (fp32, 20670 values): W1[64][64],
+ * b1[64], W2[64][64], b2[64], W3[190][64], b3[190]; W[o][i] maps input i to
+ * output o.  Layout pair of machines u < v: u*(39 - u)/2 + (v - u - 1).
+ * Features of a parent (norm = largest machine load of the instance):
+ * [0,20) C1[k]/norm, [20,40) C2[k]/norm, [40,60) R[k]/norm (k < min(m,20),
+ * zero beyond), d1/n, d2/n, (n-d1-d2)/n, LB1(parent)/norm.
+ * ------------------------------------------------------------------------ */
+
+/* Sets the fp32 master parameters from HOST memory and resets the optimiser. */
+int pfsp_selector_set(pfsp_ctx *c, const float *params, int64_t count);
+
+/* Copies the fp32 master parameters to HOST memory (synchronous). */
+int pfsp_selector_get(pfsp_ctx *c, float *params, int64_t count);
+
+/* Features of every parent of the pool into DEVICE feat_out[N][64]. */
+int pfsp_selector_features(pfsp_ctx *c, const pfsp_pool *pool, float *feat_out);
+
+/* Scores DEVICE x[rows][64] -> DEVICE scores_out[rows][190] (layout pairs not
+ * present on the loaded instance get -inf). */
+int pfsp_selector_forward(pfsp_ctx *c, const float *x, int32_t rows, float *scores_out);
+
+/* Top-k (k in [1, 32]) of DEVICE scores[rows][190] (larger first, ties to the
+ * lower layout index) as DEVICE bit masks mask_out[rows][ceil(P/32)] over the
+ * instance's pair indices, the pair_mask format of PFSP_LB2_SUBSET. */
+int pfsp_selector_select(pfsp_ctx *c, const float *scores, int32_t rows, int32_t k,
+                         uint32_t *mask_out);
+
+/* Training targets from argpair_out of an LB2_FULL pfsp_bound_children call on
+ * the same pool: DEVICE target_out[N][190] = share of the parent's 2(n-d)
+ * children whose LB2 is attained first by each layout pair (all zero if none).
+ * Synchronous. */
+int pfsp_selector_targets(pfsp_ctx *c, const pfsp_pool *pool, const int16_t *argpair,
+                          float *target_out);
+
+/* One training step on DEVICE x[rows][64] and targets[rows][190]: mean soft-
+ * target cross-entropy over rows with a non-empty target (masked softmax over
+ * present pairs), gradients by backpropagation through the bf16-rounded
+ * weights, then one Adam step (beta 0.9/0.999, eps 1e-8) of size lr on the
+ * master parameters if lr > 0.  *loss_out (HOST, may be NULL) receives the loss
+ * before the update; grad_out (DEVICE [20670], may be NULL) the gradient.
+ * Synchronous. */
+int pfsp_selector_train_step(pfsp_ctx *c, const float *x, const float *target, int32_t rows,
+                             float lr, float *loss_out, float *grad_out);
+
 #ifdef __cplusplus
 }
 #endif

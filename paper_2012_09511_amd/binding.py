@@ -22,7 +22,10 @@ INT32_MAX = 2**31 - 1
 # every symbol declared in include/pfsp.h
 EXPORTS = ["pfsp_create", "pfsp_destroy", "pfsp_last_error", "pfsp_load_instance",
            "pfsp_pair_count", "pfsp_bound_children", "pfsp_check", "pfsp_search", "pfsp_neh",
-           "pfsp_set_option", "pfsp_get_option", "pfsp_kernel_time"]
+           "pfsp_set_option", "pfsp_get_option", "pfsp_kernel_time", "pfsp_selector_set",
+           "pfsp_selector_get", "pfsp_selector_features", "pfsp_selector_forward",
+           "pfsp_selector_select", "pfsp_selector_targets", "pfsp_selector_train_step"]
+SELECTOR_PARAMS = 20670
 
 
 class PfspError(RuntimeError):
@@ -74,6 +77,14 @@ def lib():
         L.pfsp_get_option.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(i64)]
         L.pfsp_kernel_time.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(i64), ctypes.c_int]
+        L.pfsp_selector_set.argtypes = [vp, vp, i64]
+        L.pfsp_selector_get.argtypes = [vp, vp, i64]
+        L.pfsp_selector_features.argtypes = [vp, ctypes.POINTER(Pool), vp]
+        L.pfsp_selector_forward.argtypes = [vp, vp, i32, vp]
+        L.pfsp_selector_select.argtypes = [vp, vp, i32, i32, vp]
+        L.pfsp_selector_targets.argtypes = [vp, ctypes.POINTER(Pool), vp, vp]
+        L.pfsp_selector_train_step.argtypes = [vp, vp, vp, i32, ctypes.c_float,
+                                               ctypes.POINTER(ctypes.c_float), vp]
         for name in EXPORTS:
             if name not in ("pfsp_destroy", "pfsp_last_error"):
                 getattr(L, name).restype = ctypes.c_int
@@ -188,3 +199,59 @@ class Context:
         self._check(lib().pfsp_kernel_time(self.h, kernel.encode(), ctypes.byref(ms),
                                            ctypes.byref(k), int(reset)))
         return ms.value, k.value
+
+    # ---------------------------------------------------------------- selector
+    def _pool(self, perm, d1, d2):
+        return Pool(perm.shape[0], self.n, _ptr(perm), _ptr(d1), _ptr(d2), None, 0, None, None)
+
+    def selector_set(self, params):
+        """params: list [W1, b1, W2, b2, W3, b3] (float32) or a flat array of 20670."""
+        flat = np.concatenate([np.asarray(p, dtype=np.float32).reshape(-1) for p in params]) \
+            if isinstance(params, (list, tuple)) else np.asarray(params, dtype=np.float32)
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        self._check(lib().pfsp_selector_set(self.h, flat.ctypes.data_as(ctypes.c_void_p),
+                                            flat.size))
+
+    def selector_get(self):
+        out = np.empty(SELECTOR_PARAMS, dtype=np.float32)
+        self._check(lib().pfsp_selector_get(self.h, out.ctypes.data_as(ctypes.c_void_p),
+                                            out.size))
+        return out
+
+    def selector_features(self, perm, d1, d2):
+        torch = self.torch
+        out = torch.empty((perm.shape[0], 64), dtype=torch.float32, device=self.device)
+        pool = self._pool(perm, d1, d2)
+        self._check(lib().pfsp_selector_features(self.h, ctypes.byref(pool), _ptr(out)))
+        return out
+
+    def selector_forward(self, x):
+        torch = self.torch
+        out = torch.empty((x.shape[0], 190), dtype=torch.float32, device=self.device)
+        self._check(lib().pfsp_selector_forward(self.h, _ptr(x), x.shape[0], _ptr(out)))
+        return out
+
+    def selector_select(self, scores, k):
+        torch = self.torch
+        out = torch.empty((scores.shape[0], self.mask_words), dtype=torch.int32,
+                          device=self.device)
+        self._check(lib().pfsp_selector_select(self.h, _ptr(scores), scores.shape[0], int(k),
+                                               _ptr(out)))
+        return out
+
+    def selector_targets(self, perm, d1, d2, argpair):
+        torch = self.torch
+        out = torch.empty((perm.shape[0], 190), dtype=torch.float32, device=self.device)
+        pool = self._pool(perm, d1, d2)
+        self._check(lib().pfsp_selector_targets(self.h, ctypes.byref(pool), _ptr(argpair),
+                                                _ptr(out)))
+        return out
+
+    def selector_train_step(self, x, target, lr, want_grad=False):
+        torch = self.torch
+        loss = ctypes.c_float()
+        g = torch.empty(SELECTOR_PARAMS, dtype=torch.float32, device=self.device) \
+            if want_grad else None
+        self._check(lib().pfsp_selector_train_step(self.h, _ptr(x), _ptr(target), x.shape[0],
+                                                   float(lr), ctypes.byref(loss), _ptr(g)))
+        return loss.value, g

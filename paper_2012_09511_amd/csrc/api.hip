@@ -77,6 +77,11 @@ int pfsp_create(pfsp_ctx **out, int device, void *hip_stream) {
     return PFSP_EDEVICE;
   }
   c->stream = (hipStream_t)hip_stream;
+  static bool attrs = false;
+  if (!attrs) {
+    init_bound_attributes();
+    attrs = true;
+  }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     c->cu_count = prop.multiProcessorCount;

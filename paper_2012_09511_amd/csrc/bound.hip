@@ -83,7 +83,9 @@ k_lb1(DevInst I, DevPool pool, int ub, int *__restrict__ out_lb, uint8_t *__rest
   for (int x = t; x < n * m; x += B) sp[x] = I.p[x];
   __syncthreads();
   const int i = blockIdx.x * B + t;
-  if (i >= pool.count) return;
+  const int count = pool.count_dev ? *pool.count_dev : pool.count;
+  if (i >= count) return;
+  if (pool.ub_dev) ub = *pool.ub_dev;
   int *C1 = sh + n * m + t;  // per-lane arrays, stride B (bank-conflict free)
   int *C2 = C1 + m * B;
   int *R = C2 + m * B;
@@ -103,11 +105,13 @@ k_lb1(DevInst I, DevPool pool, int ub, int *__restrict__ out_lb, uint8_t *__rest
   }
   if (bad) {
     flag[0] = 1;
-    fill_invalid(lbrow, prow, arow, n, 0, 0, 1);
-    if (pool.dir) pool.dir[i] = 0;
+    if (write_out) {  // in costs mode the LB2 kernel fills the outputs of this row
+      fill_invalid(lbrow, prow, arow, n, 0, 0, 1);
+      if (pool.dir) pool.dir[i] = 0;
+    }
     if (costs) {
       for (int k = 0; k < 3 * m; ++k) costs[(size_t)i * 3 * m + k] = 0;
-      costs[(size_t)i * 3 * m] = -1;  // marks the row invalid for k_lb2
+      costs[(size_t)i * 3 * m] = -1;  // marks the row invalid for the LB2 kernels
     }
     return;
   }
@@ -205,15 +209,21 @@ k_lb2(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__res
   for (int x = threadIdx.x; x < n * m; x += blockDim.x) sp[x] = I.p[x];
   __syncthreads();
   const ET *ent = ENT_LDS ? ent_s : ent_g;
+  const int count = pool.count_dev ? *pool.count_dev : pool.count;
+  if (pool.ub_dev) ub = *pool.ub_dev;
 
-  for (int par = blockIdx.x * nw + w; par < pool.count; par += gridDim.x * nw) {
+  for (int par = blockIdx.x * nw + w; par < count; par += gridDim.x * nw) {
     const int a = pool.d1[par], b = pool.d2[par], r = n - a - b;
     int *lbrow = out_lb + (size_t)par * 2 * n;
     uint8_t *prow = out_prune + (size_t)par * 2 * n;
     int16_t *arow = LOG ? pool.argpair + (size_t)par * 2 * n : nullptr;
-    // k_lb1 flagged and filled rows that are not valid nodes (a front value
-    // is never negative otherwise)
-    if (r < 1 || costs[(size_t)par * 3 * m] < 0) continue;
+    // rows that are not valid nodes were flagged by k_lb1 (a front value is
+    // never negative otherwise): every slot gets INT32_MAX / prune 1
+    if (r < 1 || costs[(size_t)par * 3 * m] < 0) {
+      fill_invalid(lbrow, prow, arow, n, 0, lane, 64);
+      if (pool.dir && lane == 0) pool.dir[par] = 0;
+      continue;
+    }
     for (int x = lane; x < n; x += 64) {
       jobs[x] = pool.perm[(size_t)par * n + x];
       slot[x] = -1;
@@ -413,13 +423,19 @@ k_lb2f(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
     uv[x] = x < P ? ((int)I.pu[x] | ((int)I.pv[x] << 8)) : 0;
   for (int x = threadIdx.x; x < n * m; x += blockDim.x) sp[x] = I.p[x];
   __syncthreads();
+  const int count = pool.count_dev ? *pool.count_dev : pool.count;
+  if (pool.ub_dev) ub = *pool.ub_dev;
 
-  for (int par = blockIdx.x * nw + w; par < pool.count; par += gridDim.x * nw) {
+  for (int par = blockIdx.x * nw + w; par < count; par += gridDim.x * nw) {
     const int a = pool.d1[par], b = pool.d2[par], r = n - a - b;
     int *lbrow = out_lb + (size_t)par * 2 * n;
     uint8_t *prow = out_prune + (size_t)par * 2 * n;
     int16_t *arow = LOG ? pool.argpair + (size_t)par * 2 * n : nullptr;
-    if (r < 1 || costs[(size_t)par * 3 * m] < 0) continue;  // flagged by k_lb1
+    if (r < 1 || costs[(size_t)par * 3 * m] < 0) {  // flagged by k_lb1: not a valid node
+      fill_invalid(lbrow, prow, arow, n, 0, lane, 64);
+      if (pool.dir && lane == 0) pool.dir[par] = 0;
+      continue;
+    }
     MT bits = 0;
     for (int x = lane; x < n; x += 64) {
       const int j = pool.perm[(size_t)par * n + x];
@@ -590,19 +606,6 @@ template <int NMAX>
 static void launch_lb2f_n(bool subset, bool log, dim3 g, dim3 b, size_t lds, hipStream_t s,
                           const DevInst &I, const DevPool &pool, int ub, const int *costs,
                           int *out_lb, uint8_t *out_prune, int Ppad) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    const int mx = 160 * 1024;
-    (void)hipFuncSetAttribute((const void *)k_lb2f<NMAX, true, true>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-    (void)hipFuncSetAttribute((const void *)k_lb2f<NMAX, true, false>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-    (void)hipFuncSetAttribute((const void *)k_lb2f<NMAX, false, true>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-    (void)hipFuncSetAttribute((const void *)k_lb2f<NMAX, false, false>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-    attr_set = true;
-  }
   if (subset) {
     if (log)
       hipLaunchKernelGGL((k_lb2f<NMAX, true, true>), g, b, lds, s, I, pool, ub, costs, out_lb,
@@ -667,19 +670,6 @@ template <class E, bool ENT_LDS>
 static void launch_lb2_e(bool subset, bool log, dim3 g, dim3 b, size_t lds, hipStream_t s,
                          const DevInst &I, const DevPool &pool, int ub, const int *costs,
                          int *out_lb, uint8_t *out_prune, int xrows) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    const int mx = 160 * 1024;
-    (void)hipFuncSetAttribute((const void *)k_lb2<E, ENT_LDS, true, true>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-    (void)hipFuncSetAttribute((const void *)k_lb2<E, ENT_LDS, true, false>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-    (void)hipFuncSetAttribute((const void *)k_lb2<E, ENT_LDS, false, true>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-    (void)hipFuncSetAttribute((const void *)k_lb2<E, ENT_LDS, false, false>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-    attr_set = true;
-  }
   if (subset) {
     if (log)
       hipLaunchKernelGGL((k_lb2<E, ENT_LDS, true, true>), g, b, lds, s, I, pool, ub, costs,
@@ -697,40 +687,100 @@ static void launch_lb2_e(bool subset, bool log, dim3 g, dim3 b, size_t lds, hipS
   }
 }
 
-int launch_bound(Ctx *c, const DevPool &pool, int kind, int ub, int *out_lb, uint8_t *out_prune,
-                 hipStream_t s) {
-  if (pool.count <= 0) return PFSP_OK;
-  const DevInst I = c->inst();
+// Allows every bound kernel to use up to 160 KiB of dynamic LDS (the gfx950
+// per-CU size); called once per process, before any launch or graph capture.
+template <class E, bool ENT_LDS>
+static void attr_lb2() {
+  const int mx = 160 * 1024;
+  (void)hipFuncSetAttribute((const void *)k_lb2<E, ENT_LDS, true, true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+  (void)hipFuncSetAttribute((const void *)k_lb2<E, ENT_LDS, true, false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+  (void)hipFuncSetAttribute((const void *)k_lb2<E, ENT_LDS, false, true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+  (void)hipFuncSetAttribute((const void *)k_lb2<E, ENT_LDS, false, false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+}
+
+template <int NMAX>
+static void attr_lb2f() {
+  const int mx = 160 * 1024;
+  (void)hipFuncSetAttribute((const void *)k_lb2f<NMAX, true, true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+  (void)hipFuncSetAttribute((const void *)k_lb2f<NMAX, true, false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+  (void)hipFuncSetAttribute((const void *)k_lb2f<NMAX, false, true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+  (void)hipFuncSetAttribute((const void *)k_lb2f<NMAX, false, false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+}
+
+void init_bound_attributes() {
+  (void)hipFuncSetAttribute((const void *)k_lb1, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+  attr_lb2<Narrow, true>();
+  attr_lb2<Narrow, false>();
+  attr_lb2<Wide, true>();
+  attr_lb2<Wide, false>();
+  attr_lb2f<8>();
+  attr_lb2f<12>();
+  attr_lb2f<16>();
+  attr_lb2f<20>();
+  attr_lb2f<24>();
+  attr_lb2f<32>();
+  attr_lb2f<64>();
+}
+
+static void lb1_shape(const Ctx *c, int count, int &b1, size_t &lds1, int &g1) {
   const int n = c->n, m = c->m;
-  // k_lb1: per-lane arrays of 3m ints in LDS plus the staged p
-  int b1 = 128;
-  size_t lds1 = ((size_t)n * m + 3 * (size_t)m * b1) * 4;
+  b1 = 128;
+  lds1 = ((size_t)n * m + 3 * (size_t)m * b1) * 4;
   if (lds1 > 64 * 1024) {
     b1 = 64;
     lds1 = ((size_t)n * m + 3 * (size_t)m * b1) * 4;
   }
-  const int g1 = (pool.count + b1 - 1) / b1;
-  static bool attr1 = false;
-  if (!attr1) {
-    (void)hipFuncSetAttribute((const void *)k_lb1, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              160 * 1024);
-    attr1 = true;
-  }
+  g1 = (count + b1 - 1) / b1;
+}
+
+// Parent front/back/remaining into the workspace (k_lb1 without outputs).
+int launch_costs(Ctx *c, const DevPool &pool, hipStream_t s) {
+  if (pool.count <= 0) return PFSP_OK;
+  int rc = ensure_costs(c, pool.count);
+  if (rc) return rc;
+  int b1, g1;
+  size_t lds1;
+  lb1_shape(c, pool.count, b1, lds1, g1);
+  KTimer kt(c, s, "k_lb1");
+  hipLaunchKernelGGL(k_lb1, dim3(g1), dim3(b1), lds1, s, c->inst(), pool, 0, (int *)nullptr,
+                     (uint8_t *)nullptr, c->d_costs, 0, c->d_flag);
+  PFSP_HIP(c, hipGetLastError());
+  return PFSP_OK;
+}
+
+int launch_bound(Ctx *c, const DevPool &pool, int kind, int ub, int *out_lb, uint8_t *out_prune,
+                 hipStream_t s) {
+  if (pool.count <= 0) return PFSP_OK;
   if (kind == PFSP_LB1) {
+    int b1, g1;
+    size_t lds1;
+    lb1_shape(c, pool.count, b1, lds1, g1);
     KTimer kt(c, s, "k_lb1");
-    hipLaunchKernelGGL(k_lb1, dim3(g1), dim3(b1), lds1, s, I, pool, ub, out_lb, out_prune,
-                       (int *)nullptr, 1, c->d_flag);
+    hipLaunchKernelGGL(k_lb1, dim3(g1), dim3(b1), lds1, s, c->inst(), pool, ub, out_lb,
+                       out_prune, (int *)nullptr, 1, c->d_flag);
     PFSP_HIP(c, hipGetLastError());
     return PFSP_OK;
   }
-  int rc = ensure_costs(c, pool.count);
+  int rc = launch_costs(c, pool, s);
   if (rc) return rc;
-  {
-    KTimer kt(c, s, "k_lb1");
-    hipLaunchKernelGGL(k_lb1, dim3(g1), dim3(b1), lds1, s, I, pool, ub, out_lb, out_prune,
-                       c->d_costs, 0, c->d_flag);
-  }
-  PFSP_HIP(c, hipGetLastError());
+  return launch_bound_costs_ready(c, pool, kind, ub, out_lb, out_prune, s);
+}
+
+// LB2 kinds once launch_costs has run for the same pool.
+int launch_bound_costs_ready(Ctx *c, const DevPool &pool, int kind, int ub, int *out_lb,
+                             uint8_t *out_prune, hipStream_t s) {
+  if (pool.count <= 0) return PFSP_OK;
+  const DevInst I = c->inst();
+  const int n = c->n;
   const bool subset = kind == PFSP_LB2_SUBSET;
   const bool log = pool.argpair != nullptr;
   const int nmax = c->narrow && !c->force_generic ? fast_nmax(n) : 0;

@@ -35,7 +35,9 @@ struct DevInst {
 
 // Parent batch as seen by the kernels.
 struct DevPool {
-  int count, n;
+  int count, n;                 // count: rows (grid size); see count_dev
+  const int *count_dev = nullptr;  // if set, the number of valid rows is *count_dev (<= count)
+  const int *ub_dev = nullptr;     // if set, the prune threshold is *ub_dev
   const uint8_t *perm, *d1, *d2;
   const uint32_t *mask;
   int mask_words;
@@ -128,10 +130,15 @@ int stage_instance(Ctx *c);
 int ensure_costs(Ctx *c, int count);
 int launch_bound(Ctx *c, const DevPool &pool, int kind, int ub, int *out_lb,
                  uint8_t *out_prune, hipStream_t s);
+int launch_costs(Ctx *c, const DevPool &pool, hipStream_t s);
+int launch_bound_costs_ready(Ctx *c, const DevPool &pool, int kind, int ub, int *out_lb,
+                             uint8_t *out_prune, hipStream_t s);
 size_t lb2_lds_bytes(const Ctx *c, int waves);
+void init_bound_attributes();
 // selector.hip
 int launch_learned(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8_t *out_prune,
                    hipStream_t s);
+int learned_prepare(Ctx *c, int rows);
 void selector_free(Ctx *c);
 // search.hip
 void search_free(Ctx *c);

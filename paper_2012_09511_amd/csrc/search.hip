@@ -1,13 +1,499 @@
-// Device depth-first search (filled in below).
+// Depth-first branch-and-bound on the device (Sections 2.2-2.5).
+//
+// The paper keeps K integer-vector-matrix explorers per GPU and balances them
+// by work stealing (Sections 2.5, 3.1-3.4).  Here the open subproblems live in
+// one device stack of node records (perm[n], d1, d2, lb); every step pops the
+// top `pool_batch` records, decomposes them with the bounding kernels of
+// bound.hip (both children sets, MinMin, prune flags), and pushes each
+// parent's surviving children back in list order with the leftmost child on
+// top, parents nearer the top of the stack ending nearer the top.  Popping
+// from the top keeps the search depth-first while every step still feeds the
+// GPU a full batch; balancing is implicit because all parents share the stack.
+//
+// Step = k_pop -> k_gather -> k_lb1 [-> k_lb2] -> k_count -> k_scan_local ->
+// k_scan_top -> k_push.  All sizes and the incumbent are read from a control
+// block in device memory, so the step is captured once as a HIP graph and
+// replayed; the host reads the control block every `poll_every` steps.
+//
+// Pruning (Section 2.2): a child is discarded iff LB >= incumbent.  A popped
+// record whose stored LB is no longer below the incumbent is dropped without
+// being decomposed (lazy re-check).  A leaf child (no unscheduled job left)
+// carries its makespan as LB; if it is below the step's incumbent it lowers
+// the incumbent with atomicMin and the best leaf of the step is recorded.
+#include <chrono>
+
 #include "internal.h"
 
 namespace pfsp {
-void search_free(Ctx *c) { (void)c; }
+
+struct SearchCtl {
+  int top;         // records on the stack
+  int count;       // records popped this step
+  int base;        // stack index of the first popped record
+  int ub;          // incumbent (lowered by atomicMin)
+  int ub_step;     // incumbent at the start of the step: prune threshold
+  int overflow;    // a push would have exceeded the capacity
+  int newbest;     // a leaf improved the incumbent since the last poll
+  int pad0;
+  unsigned long long step_best;  // (makespan << 32) | batch index of the step's best leaf
+  long long nodes;               // decomposed nodes
+  long long children;            // bounded children
+  long long steps;               // steps that popped at least one record
+};
+
+struct SearchState {
+  int n = 0, N = 0;
+  long long cap = 0;
+  hipStream_t stream = nullptr;
+  // stack
+  uint8_t *s_perm = nullptr, *s_d1 = nullptr, *s_d2 = nullptr;
+  int *s_lb = nullptr;
+  // batch
+  uint8_t *b_perm = nullptr, *b_d1 = nullptr, *b_d2 = nullptr, *b_dir = nullptr;
+  int *b_lb = nullptr;
+  uint8_t *b_alive = nullptr;
+  int *out_lb = nullptr;
+  uint8_t *out_prune = nullptr;
+  int *cnt = nullptr, *offs = nullptr, *bsum = nullptr;
+  uint8_t *best_perm = nullptr;
+  SearchCtl *ctl = nullptr, *ctl_host = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int graph_kind = 0;
+};
+
+constexpr int kScanBlock = 1024;  // parents per k_scan_local block (256 threads x 4)
+
+__global__ void k_pop(SearchCtl *c, int N) {
+  const int top = c->top;
+  const int count = top < N ? top : N;
+  c->count = count;
+  c->base = top - count;
+  c->top = top - count;
+  c->ub_step = c->ub;
+  c->step_best = ~0ull;
+  if (count > 0) c->steps += 1;
+}
+
+__global__ void k_gather(const SearchCtl *__restrict__ c, int n, const uint8_t *__restrict__ s_perm,
+                         const uint8_t *__restrict__ s_d1, const uint8_t *__restrict__ s_d2,
+                         const int *__restrict__ s_lb, uint8_t *__restrict__ b_perm,
+                         uint8_t *__restrict__ b_d1, uint8_t *__restrict__ b_d2,
+                         int *__restrict__ b_lb, uint8_t *__restrict__ b_alive) {
+  const int count = c->count, base = c->base, ub = c->ub_step;
+  const long long total = (long long)count * n;
+  const uint8_t *src = s_perm + (size_t)base * n;
+  for (long long x = blockIdx.x * (long long)blockDim.x + threadIdx.x; x < total;
+       x += (long long)gridDim.x * blockDim.x)
+    b_perm[x] = src[x];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+    b_d1[i] = s_d1[base + i];
+    b_d2[i] = s_d2[base + i];
+    const int lb = s_lb[base + i];
+    b_lb[i] = lb;
+    b_alive[i] = lb < ub;  // lazy re-check against the current incumbent
+  }
+}
+
+// Per parent: node statistics, leaf incumbent updates, and the number of
+// surviving non-leaf children of the chosen direction.
+__global__ void __launch_bounds__(256)
+k_count(SearchCtl *__restrict__ c, int n, const uint8_t *__restrict__ b_d1,
+        const uint8_t *__restrict__ b_d2, const uint8_t *__restrict__ b_alive,
+        const uint8_t *__restrict__ b_dir, const int *__restrict__ out_lb,
+        const uint8_t *__restrict__ out_prune, int *__restrict__ cnt) {
+  __shared__ long long sn[256], sc[256];
+  const int count = c->count, ub = c->ub_step;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  long long nodes = 0, children = 0;
+  if (i < count) {
+    int s = 0;
+    if (b_alive[i]) {
+      const int r = n - b_d1[i] - b_d2[i];
+      const int dir = b_dir[i];
+      nodes = 1;
+      children = 2 * r;
+      const int *lb = out_lb + ((size_t)i * 2 + dir) * n;
+      const uint8_t *pr = out_prune + ((size_t)i * 2 + dir) * n;
+      if (r == 1) {
+        const int v = lb[0];
+        if (v < ub) {
+          atomicMin(&c->ub, v);
+          atomicMin(&c->step_best, ((unsigned long long)(unsigned)v << 32) | (unsigned)i);
+        }
+      } else {
+        for (int q = 0; q < r; ++q) s += pr[q] == 0;
+      }
+    }
+    cnt[i] = s;
+  }
+  sn[threadIdx.x] = nodes;
+  sc[threadIdx.x] = children;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      sn[threadIdx.x] += sn[threadIdx.x + o];
+      sc[threadIdx.x] += sc[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && sn[0]) {
+    atomicAdd((unsigned long long *)&c->nodes, (unsigned long long)sn[0]);
+    atomicAdd((unsigned long long *)&c->children, (unsigned long long)sc[0]);
+  }
+}
+
+// Exclusive scan of cnt within blocks of kScanBlock parents.
+__global__ void __launch_bounds__(256)
+k_scan_local(const SearchCtl *__restrict__ c, const int *__restrict__ cnt, int *__restrict__ offs,
+             int *__restrict__ bsum) {
+  __shared__ int sh[256];
+  const int count = c->count;
+  const int base = blockIdx.x * kScanBlock;
+  if (base >= count) return;
+  int v[4], tot = 0;
+  for (int k = 0; k < 4; ++k) {
+    const int i = base + threadIdx.x * 4 + k;
+    v[k] = i < count ? cnt[i] : 0;
+    tot += v[k];
+  }
+  sh[threadIdx.x] = tot;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {  // inclusive Hillis-Steele scan of thread totals
+    const int x = (int)threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += x;
+    __syncthreads();
+  }
+  int run = sh[threadIdx.x] - tot;
+  for (int k = 0; k < 4; ++k) {
+    const int i = base + threadIdx.x * 4 + k;
+    if (i < count) offs[i] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == 255) bsum[blockIdx.x] = sh[255];
+}
+
+// Exclusive scan of the block sums; sets the new stack top (or the overflow flag).
+__global__ void __launch_bounds__(1024)
+k_scan_top(SearchCtl *__restrict__ c, int *__restrict__ bsum, long long cap) {
+  __shared__ int sh[1024];
+  const int count = c->count;
+  const int nb = (count + kScanBlock - 1) / kScanBlock;
+  const int per = (nb + 1023) / 1024;
+  int tot = 0;
+  for (int k = 0; k < per; ++k) {
+    const int b = threadIdx.x * per + k;
+    if (b < nb) tot += bsum[b];
+  }
+  sh[threadIdx.x] = tot;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int x = (int)threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += x;
+    __syncthreads();
+  }
+  int run = sh[threadIdx.x] - tot;
+  for (int k = 0; k < per; ++k) {
+    const int b = threadIdx.x * per + k;
+    if (b < nb) {
+      const int x = bsum[b];
+      bsum[b] = run;
+      run += x;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const long long top = (long long)c->base + sh[1023];
+    if (top > cap) {
+      c->overflow = 1;
+      c->top = c->base;
+    } else {
+      c->top = (int)top;
+    }
+  }
+}
+
+// One wave per parent: writes the surviving children of the chosen direction
+// as new stack records (leftmost child on top), and the step's best leaf.
+__global__ void __launch_bounds__(256)
+k_push(SearchCtl *__restrict__ c, int n, const uint8_t *__restrict__ b_perm,
+       const uint8_t *__restrict__ b_d1, const uint8_t *__restrict__ b_d2,
+       const uint8_t *__restrict__ b_dir, const int *__restrict__ out_lb,
+       const uint8_t *__restrict__ out_prune, const int *__restrict__ cnt,
+       const int *__restrict__ offs, const int *__restrict__ bsum, uint8_t *__restrict__ s_perm,
+       uint8_t *__restrict__ s_d1, uint8_t *__restrict__ s_d2, int *__restrict__ s_lb,
+       uint8_t *__restrict__ best_perm) {
+  const int count = c->count;
+  if (c->overflow) return;
+  const int lane = threadIdx.x & 63;
+  const int waves = (gridDim.x * blockDim.x) >> 6;
+  const unsigned long long sb = c->step_best;
+  for (int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < count; i += waves) {
+    const uint8_t *row = b_perm + (size_t)i * n;
+    if (sb != ~0ull && (int)(sb & 0xffffffffu) == i) {
+      // the step's best leaf: a one-job parent's only child is its own permutation
+      for (int x = lane; x < n; x += 64) best_perm[x] = row[x];
+      if (lane == 0) c->newbest = 1;
+    }
+    const int s = cnt[i];
+    if (s == 0) continue;
+    const int a = b_d1[i], b = b_d2[i], r = n - a - b, dir = b_dir[i];
+    const int *lb = out_lb + ((size_t)i * 2 + dir) * n;
+    const uint8_t *pr = out_prune + ((size_t)i * 2 + dir) * n;
+    const long long dst = (long long)c->base + bsum[i / kScanBlock] + offs[i];
+    int t = 0;
+    for (int q = 0; q < r; ++q) {
+      if (pr[q]) continue;
+      const long long pos = dst + (s - 1 - t);
+      ++t;
+      uint8_t *out = s_perm + pos * n;
+      const int j = row[a + q];
+      for (int x = lane; x < n; x += 64) {
+        int v;
+        if (x < a || x >= a + r) {
+          v = row[x];
+        } else if (dir == 0) {  // sigma1 j | U \ j | sigma2
+          v = x == a ? j : (x <= a + q ? row[x - 1] : row[x]);
+        } else {  // sigma1 | U \ j | j sigma2
+          v = x == a + r - 1 ? j : (x < a + q ? row[x] : row[x + 1]);
+        }
+        out[x] = (uint8_t)v;
+      }
+      if (lane == 0) {
+        s_d1[pos] = (uint8_t)(a + (dir == 0));
+        s_d2[pos] = (uint8_t)(b + (dir == 1));
+        s_lb[pos] = lb[q];
+      }
+    }
+  }
+}
+
+__global__ void k_init_root(SearchCtl *c, int n, int ub0, uint8_t *s_perm, uint8_t *s_d1,
+                            uint8_t *s_d2, int *s_lb) {
+  const int x = threadIdx.x;
+  for (int j = x; j < n; j += blockDim.x) s_perm[j] = (uint8_t)j;
+  if (x == 0) {
+    s_d1[0] = 0;
+    s_d2[0] = 0;
+    s_lb[0] = (int)0x80000000;  // the root is always decomposed
+    c->top = 1;
+    c->count = 0;
+    c->base = 0;
+    c->ub = ub0;
+    c->ub_step = ub0;
+    c->overflow = 0;
+    c->newbest = 0;
+    c->step_best = ~0ull;
+    c->nodes = 0;
+    c->children = 0;
+    c->steps = 0;
+  }
+}
+
+void search_free(Ctx *c) {
+  SearchState *S = c->search;
+  if (!S) return;
+  if (S->stream) (void)hipStreamSynchronize(S->stream);
+  if (S->gexec) (void)hipGraphExecDestroy(S->gexec);
+  if (S->graph) (void)hipGraphDestroy(S->graph);
+  void *bufs[] = {S->s_perm, S->s_d1, S->s_d2, S->s_lb, S->b_perm, S->b_d1, S->b_d2, S->b_dir,
+                  S->b_lb, S->b_alive, S->out_lb, S->out_prune, S->cnt, S->offs, S->bsum,
+                  S->best_perm, S->ctl};
+  for (void *p : bufs) (void)hipFree(p);
+  if (S->ctl_host) (void)hipHostFree(S->ctl_host);
+  if (S->stream) (void)hipStreamDestroy(S->stream);
+  delete S;
+  c->search = nullptr;
+}
+
+static int search_alloc(Ctx *c) {
+  const int n = c->n;
+  const int N = (int)c->pool_batch;
+  long long cap = c->pool_capacity;
+  if (cap <= 0) cap = (long long)N * (n * (n + 1) / 2 + 1);
+  if (cap > 0x7fffffffLL) cap = 0x7fffffffLL;
+  SearchState *S = c->search;
+  if (S && S->n == n && S->N == N && S->cap == cap) return PFSP_OK;
+  search_free(c);
+  S = new (std::nothrow) SearchState();
+  if (!S) return set_err(c, PFSP_ENOMEM, "host allocation failed");
+  c->search = S;
+  S->n = n;
+  S->N = N;
+  S->cap = cap;
+  const int nb = (N + kScanBlock - 1) / kScanBlock;
+  bool ok = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) == hipSuccess;
+  auto alloc = [&](void **p, size_t bytes) {
+    if (ok && hipMalloc(p, bytes ? bytes : 1) != hipSuccess) ok = false;
+  };
+  alloc((void **)&S->s_perm, (size_t)cap * n);
+  alloc((void **)&S->s_d1, (size_t)cap);
+  alloc((void **)&S->s_d2, (size_t)cap);
+  alloc((void **)&S->s_lb, (size_t)cap * 4);
+  alloc((void **)&S->b_perm, (size_t)N * n);
+  alloc((void **)&S->b_d1, (size_t)N);
+  alloc((void **)&S->b_d2, (size_t)N);
+  alloc((void **)&S->b_dir, (size_t)N);
+  alloc((void **)&S->b_lb, (size_t)N * 4);
+  alloc((void **)&S->b_alive, (size_t)N);
+  alloc((void **)&S->out_lb, (size_t)N * 2 * n * 4);
+  alloc((void **)&S->out_prune, (size_t)N * 2 * n);
+  alloc((void **)&S->cnt, (size_t)N * 4);
+  alloc((void **)&S->offs, (size_t)N * 4);
+  alloc((void **)&S->bsum, (size_t)nb * 4);
+  alloc((void **)&S->best_perm, (size_t)n);
+  alloc((void **)&S->ctl, sizeof(SearchCtl));
+  if (ok && hipHostMalloc((void **)&S->ctl_host, sizeof(SearchCtl), hipHostMallocDefault) !=
+                hipSuccess)
+    ok = false;
+  if (!ok) {
+    search_free(c);
+    return set_err(c, PFSP_ENOMEM, "search buffers do not fit in device memory");
+  }
+  // the bound workspace is sized here: nothing may allocate during capture
+  return ensure_costs(c, N);
+}
+
+// Enqueues one search step on the search stream.
+static int enqueue_step(Ctx *c, int kind) {
+  SearchState *S = c->search;
+  const int n = c->n, N = S->N;
+  hipStream_t s = S->stream;
+  const int nb = (N + kScanBlock - 1) / kScanBlock;
+  hipLaunchKernelGGL(k_pop, dim3(1), dim3(1), 0, s, S->ctl, N);
+  const int gg = (int)(((long long)N * n + 255) / 256 < 4096 ? ((long long)N * n + 255) / 256 : 4096);
+  hipLaunchKernelGGL(k_gather, dim3(gg), dim3(256), 0, s, S->ctl, n, S->s_perm, S->s_d1, S->s_d2,
+                     S->s_lb, S->b_perm, S->b_d1, S->b_d2, S->b_lb, S->b_alive);
+  DevPool pool;
+  pool.count = N;
+  pool.n = n;
+  pool.count_dev = &S->ctl->count;
+  pool.ub_dev = &S->ctl->ub_step;
+  pool.perm = S->b_perm;
+  pool.d1 = S->b_d1;
+  pool.d2 = S->b_d2;
+  pool.mask = nullptr;
+  pool.mask_words = 0;
+  pool.dir = S->b_dir;
+  pool.argpair = nullptr;
+  int rc;
+  if (kind == PFSP_LB2_LEARNED)
+    rc = launch_learned(c, pool, 0, S->out_lb, S->out_prune, s);
+  else
+    rc = launch_bound(c, pool, kind, 0, S->out_lb, S->out_prune, s);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_count, dim3((N + 255) / 256), dim3(256), 0, s, S->ctl, n, S->b_d1, S->b_d2,
+                     S->b_alive, S->b_dir, S->out_lb, S->out_prune, S->cnt);
+  hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(256), 0, s, S->ctl, S->cnt, S->offs, S->bsum);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, S->ctl, S->bsum, S->cap);
+  const int pw = (N + 3) / 4 < 8192 ? (N + 3) / 4 : 8192;
+  hipLaunchKernelGGL(k_push, dim3(pw), dim3(256), 0, s, S->ctl, n, S->b_perm, S->b_d1, S->b_d2,
+                     S->b_dir, S->out_lb, S->out_prune, S->cnt, S->offs, S->bsum, S->s_perm,
+                     S->s_d1, S->s_d2, S->s_lb, S->best_perm);
+  PFSP_HIP(c, hipGetLastError());
+  return PFSP_OK;
+}
+
+static int build_graph(Ctx *c, int kind) {
+  SearchState *S = c->search;
+  if (S->gexec && S->graph_kind == kind) return PFSP_OK;
+  if (S->gexec) (void)hipGraphExecDestroy(S->gexec);
+  if (S->graph) (void)hipGraphDestroy(S->graph);
+  S->gexec = nullptr;
+  S->graph = nullptr;
+  PFSP_HIP(c, hipStreamBeginCapture(S->stream, hipStreamCaptureModeThreadLocal));
+  c->capturing = 1;
+  int rc = enqueue_step(c, kind);
+  c->capturing = 0;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(S->stream, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_err(c, e, "hipStreamEndCapture");
+  S->graph = g;
+  PFSP_HIP(c, hipGraphInstantiate(&S->gexec, g, nullptr, nullptr, 0));
+  S->graph_kind = kind;
+  return PFSP_OK;
+}
+
 }  // namespace pfsp
+
+using namespace pfsp;
 
 extern "C" int pfsp_search(pfsp_ctx *h, int32_t ub0, int64_t budget_nodes, int lb_kind,
                            pfsp_result *res) {
-  (void)ub0; (void)budget_nodes; (void)lb_kind; (void)res;
   if (!h) return PFSP_EINVAL;
-  return pfsp::set_err(&h->impl, PFSP_EINVAL, "search not available yet");
+  Ctx *c = &h->impl;
+  if (c->n == 0) return set_err(c, PFSP_ENOINST, "no instance loaded");
+  if (!res) return set_err(c, PFSP_EINVAL, "res is NULL");
+  if (lb_kind != PFSP_LB1 && lb_kind != PFSP_LB2_FULL && lb_kind != PFSP_LB2_LEARNED)
+    return set_err(c, PFSP_EINVAL, "search supports PFSP_LB1, PFSP_LB2_FULL, PFSP_LB2_LEARNED");
+  if (lb_kind != PFSP_LB1 && c->m < 2) return set_err(c, PFSP_ERANGE, "LB2 kinds need m >= 2");
+  if (budget_nodes < 0) return set_err(c, PFSP_EINVAL, "negative budget");
+  PFSP_HIP(c, hipSetDevice(c->device));
+  int rc = search_alloc(c);
+  if (rc) return rc;
+  SearchState *S = c->search;
+  if (lb_kind == PFSP_LB2_LEARNED) {  // size the selector workspaces before any capture
+    rc = learned_prepare(c, S->N);
+    if (rc) return rc;
+  }
+  const int n = c->n;
+  const auto t0 = std::chrono::steady_clock::now();
+  hipLaunchKernelGGL(k_init_root, dim3(1), dim3(256), 0, S->stream, S->ctl, n, (int)ub0,
+                     S->s_perm, S->s_d1, S->s_d2, S->s_lb);
+  PFSP_HIP(c, hipGetLastError());
+  if (c->use_graph) {
+    rc = build_graph(c, lb_kind);
+    if (rc) return rc;
+  }
+  const int k = (int)c->poll_every;
+  int status = PFSP_OK;
+  long long max_pool = 1;
+  int steps = 0;
+  for (;;) {
+    for (int t = 0; t < k; ++t) {
+      if (c->use_graph) {
+        PFSP_HIP(c, hipGraphLaunch(S->gexec, S->stream));
+      } else {
+        rc = enqueue_step(c, lb_kind);
+        if (rc) return rc;
+      }
+    }
+    PFSP_HIP(c, hipMemcpyAsync(S->ctl_host, S->ctl, sizeof(SearchCtl), hipMemcpyDeviceToHost,
+                               S->stream));
+    PFSP_HIP(c, hipStreamSynchronize(S->stream));
+    const SearchCtl &hc = *S->ctl_host;
+    steps = (int)hc.steps;
+    if (hc.top > max_pool) max_pool = hc.top;
+    if (hc.overflow) {
+      status = set_err(c, PFSP_ENOMEM, "search stack capacity exceeded (raise pool_capacity)");
+      break;
+    }
+    if (hc.top == 0) break;
+    if (budget_nodes > 0 && hc.nodes >= budget_nodes) {
+      status = PFSP_BUDGET;
+      break;
+    }
+  }
+  const SearchCtl hc = *S->ctl_host;
+  const auto t1 = std::chrono::steady_clock::now();
+  res->found = hc.ub < ub0;
+  res->best_cmax = res->found ? hc.ub : ub0;
+  res->proven = status == PFSP_OK;
+  res->steps = steps;
+  res->nodes_decomposed = hc.nodes;
+  res->children_bounded = hc.children;
+  res->max_pool = max_pool;
+  res->seconds = std::chrono::duration<double>(t1 - t0).count();
+  if (res->found && res->best_perm) {
+    uint8_t tmp[kMaxN];
+    PFSP_HIP(c, hipMemcpy(tmp, S->best_perm, n, hipMemcpyDeviceToHost));
+    for (int j = 0; j < n; ++j) res->best_perm[j] = tmp[j];
+  }
+  return status;
 }

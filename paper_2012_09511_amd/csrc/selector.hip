@@ -1,11 +1,651 @@
-// Learned machine-pair selector (filled in below).
+// Learned machine-pair selector for LB2.
+//
+// Section 2.4 allows LB2 variants that evaluate anywhere between m and
+// m(m-1)/2 machine pairs; a maximum over any subset of pairs is still a valid
+// lower bound (max(LB1, subset maximum) <= full LB2).  The selector chooses
+// the subset per parent: an MLP 64 -> 64 -> 64 -> 190 (ReLU; weights rounded to
+// bfloat16, fp32 accumulation) scores the pairs of a 20-machine layout from 64
+// features of the parent, and the `learned_topk` best pairs that exist on the
+// instance are bounded exactly.  It is trained on the GPU from logged nodes:
+// the target of a node is the share of its children whose full LB2 is
+// attained first by each pair.
+//
+// Features (per parent, norm = the largest machine load of the instance):
+//   [0,20) front C1[k]/norm, [20,40) back C2[k]/norm, [40,60) remaining
+//   R[k]/norm for machines k < min(m, 20) (zero beyond), 60: d1/n, 61: d2/n,
+//   62: (n - d1 - d2)/n, 63: LB1(parent)/norm.
+#include <math.h>
+
+#include <vector>
+
 #include "internal.h"
 
 namespace pfsp {
-void selector_free(Ctx *c) { (void)c; }
+
+constexpr int kIn = 64, kHid = 64, kOut = 190, kMMax = 20;
+constexpr int kOffW1 = 0, kOffB1 = kOffW1 + kHid * kIn, kOffW2 = kOffB1 + kHid,
+              kOffB2 = kOffW2 + kHid * kHid, kOffW3 = kOffB2 + kHid, kOffB3 = kOffW3 + kOut * kHid,
+              kParams = kOffB3 + kOut;
+constexpr int kTopKMax = 32;
+
+struct Selector {
+  float *master = nullptr;  // fp32 parameters, layout W1[64][64] b1 W2[64][64] b2 W3[190][64] b3
+  float *wq = nullptr;      // same layout, weights rounded to bfloat16 (biases copied)
+  float *grad = nullptr, *am = nullptr, *av = nullptr;
+  long long step = 0;
+  int loaded = 0;
+  // per-batch workspaces (grown on demand)
+  float *feat = nullptr, *scores = nullptr;
+  uint32_t *mask = nullptr;
+  size_t rows_cap = 0;
+  int mask_words = 0;
+  // training workspaces
+  float *h1 = nullptr, *h2 = nullptr, *ds = nullptr, *dh1 = nullptr, *dh2 = nullptr,
+        *rowloss = nullptr, *loss = nullptr;
+  size_t train_cap = 0;
+  int *to_inst = nullptr;  // [190]: instance pair index of each layout pair, -1 if absent
+  int to_inst_m = -1;
+};
+
+// round to nearest even bfloat16, kept as float
+__device__ __forceinline__ float bf16r(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x7fffffu)) return x;  // NaN
+  u = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
+  return __uint_as_float(u);
+}
+
+__global__ void k_round_weights(const float *__restrict__ master, float *__restrict__ wq) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kParams) return;
+  const bool bias = (i >= kOffB1 && i < kOffW2) || (i >= kOffB2 && i < kOffW3) || i >= kOffB3;
+  wq[i] = bias ? master[i] : bf16r(master[i]);
+}
+
+__global__ void k_features(DevInst I, DevPool pool, const int *__restrict__ costs, float norm,
+                           float *__restrict__ feat) {
+  const int count = pool.count_dev ? *pool.count_dev : pool.count;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int n = I.n, m = I.m;
+  const int *cs = costs + (size_t)i * 3 * m;
+  float *f = feat + (size_t)i * kIn;
+  const int a = pool.d1[i], b = pool.d2[i];
+  const bool bad = cs[0] < 0;  // invalid row flagged by k_lb1
+  int lb1 = 0;
+  for (int k = 0; k < m; ++k) lb1 = max(lb1, cs[k] + cs[2 * m + k] + cs[m + k]);
+  for (int k = 0; k < kMMax; ++k) {
+    const bool on = k < m && !bad;
+    f[k] = on ? (float)cs[k] / norm : 0.f;
+    f[20 + k] = on ? (float)cs[m + k] / norm : 0.f;
+    f[40 + k] = on ? (float)cs[2 * m + k] / norm : 0.f;
+  }
+  f[60] = (float)a / (float)n;
+  f[61] = (float)b / (float)n;
+  f[62] = (float)(n - a - b) / (float)n;
+  f[63] = bad ? 0.f : (float)lb1 / norm;
+}
+
+// Forward pass, one thread per row; the weights are read at wave-uniform
+// addresses (scalar loads).  valid20[o] masks layout pairs absent on the
+// instance (their score is -inf).
+__global__ void __launch_bounds__(256)
+k_mlp_forward(const float *__restrict__ wq, const float *__restrict__ x, int rows,
+              const int *__restrict__ rows_dev, float *__restrict__ scores,
+              const int *__restrict__ to_inst) {
+  const int B = rows_dev ? *rows_dev : rows;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B) return;
+  const float *xi = x + (size_t)i * kIn;
+  float h1[kHid], h2[kHid];
+#pragma unroll
+  for (int o = 0; o < kHid; ++o) h1[o] = wq[kOffB1 + o];
+  for (int j = 0; j < kIn; ++j) {
+    const float xj = xi[j];
+#pragma unroll
+    for (int o = 0; o < kHid; ++o) h1[o] = fmaf(wq[kOffW1 + o * kIn + j], xj, h1[o]);
+  }
+#pragma unroll
+  for (int o = 0; o < kHid; ++o) {
+    h1[o] = fmaxf(h1[o], 0.f);
+    h2[o] = wq[kOffB2 + o];
+  }
+#pragma unroll
+  for (int j = 0; j < kHid; ++j) {
+#pragma unroll
+    for (int o = 0; o < kHid; ++o) h2[o] = fmaf(wq[kOffW2 + o * kHid + j], h1[j], h2[o]);
+  }
+#pragma unroll
+  for (int o = 0; o < kHid; ++o) h2[o] = fmaxf(h2[o], 0.f);
+  float *si = scores + (size_t)i * kOut;
+  for (int o = 0; o < kOut; ++o) {
+    float s = wq[kOffB3 + o];
+#pragma unroll
+    for (int j = 0; j < kHid; ++j) s = fmaf(wq[kOffW3 + o * kHid + j], h2[j], s);
+    si[o] = to_inst[o] >= 0 ? s : -INFINITY;
+  }
+}
+
+// Top-k layout pairs per row (larger score first; equal scores: lower index),
+// written as a bit mask over the instance's pair indices.
+__global__ void k_select(const float *__restrict__ scores, int rows, const int *__restrict__ rows_dev,
+                         int k, const int *__restrict__ to_inst, int words,
+                         uint32_t *__restrict__ mask) {
+  const int B = rows_dev ? *rows_dev : rows;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B) return;
+  const float *si = scores + (size_t)i * kOut;
+  float best[kTopKMax];
+  int idx[kTopKMax];
+#pragma unroll
+  for (int t = 0; t < kTopKMax; ++t) {
+    best[t] = -INFINITY;
+    idx[t] = -1;
+  }
+  for (int o = 0; o < kOut; ++o) {
+    if (to_inst[o] < 0) continue;
+    float v = si[o];
+    int id = o;
+    // insertion into the descending list best[0..k); scanning o upwards and
+    // moving an entry down only past strictly smaller ones keeps lower indices
+    // first among equal scores
+#pragma unroll
+    for (int t = 0; t < kTopKMax; ++t) {
+      if (t < k && (idx[t] < 0 || v > best[t])) {
+        const float tv = best[t];
+        const int ti = idx[t];
+        best[t] = v;
+        idx[t] = id;
+        v = tv;
+        id = ti;
+      }
+    }
+  }
+  uint32_t *mi = mask + (size_t)i * words;
+  for (int w = 0; w < words; ++w) mi[w] = 0;
+#pragma unroll
+  for (int t = 0; t < kTopKMax; ++t)
+    if (t < k && idx[t] >= 0) {
+      const int pi = to_inst[idx[t]];
+      mi[pi >> 5] |= 1u << (pi & 31);
+    }
+}
+
+// Training targets from logged argmax pairs: share of the node's children
+// whose LB2 is attained first by each layout pair.
+__global__ void k_targets(DevInst I, DevPool pool, const int16_t *__restrict__ argpair,
+                          const int *__restrict__ inst_to20, float *__restrict__ target) {
+  const int count = pool.count_dev ? *pool.count_dev : pool.count;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int n = I.n;
+  float *t = target + (size_t)i * kOut;
+  for (int o = 0; o < kOut; ++o) t[o] = 0.f;
+  const int r = n - pool.d1[i] - pool.d2[i];
+  int tot = 0;
+  for (int dir = 0; dir < 2; ++dir)
+    for (int q = 0; q < r && q < n; ++q) tot += argpair[((size_t)i * 2 + dir) * n + q] >= 0;
+  if (tot == 0) return;
+  const float w = 1.f / (float)tot;
+  for (int dir = 0; dir < 2; ++dir)
+    for (int q = 0; q < r && q < n; ++q) {
+      const int a = argpair[((size_t)i * 2 + dir) * n + q];
+      if (a >= 0) t[inst_to20[a]] += w;
+    }
+}
+
+// Training, phase 1 (one thread per row): forward pass, soft-target
+// cross-entropy, and the backpropagated row errors ds = (softmax - t)/B,
+// dh2, dh1.  Rows whose target is all zero are ignored.
+__global__ void __launch_bounds__(256)
+k_train_rows(const float *__restrict__ wq, const float *__restrict__ x,
+             const float *__restrict__ target, int B, int nvalid,
+             const int *__restrict__ to_inst, float *__restrict__ H1, float *__restrict__ H2,
+             float *__restrict__ DS, float *__restrict__ DH1, float *__restrict__ DH2,
+             float *__restrict__ rowloss) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B) return;
+  const float *xi = x + (size_t)i * kIn;
+  const float *ti = target + (size_t)i * kOut;
+  float h1[kHid], h2[kHid];
+#pragma unroll
+  for (int o = 0; o < kHid; ++o) h1[o] = wq[kOffB1 + o];
+  for (int j = 0; j < kIn; ++j) {
+    const float xj = xi[j];
+#pragma unroll
+    for (int o = 0; o < kHid; ++o) h1[o] = fmaf(wq[kOffW1 + o * kIn + j], xj, h1[o]);
+  }
+#pragma unroll
+  for (int o = 0; o < kHid; ++o) {
+    h1[o] = fmaxf(h1[o], 0.f);
+    h2[o] = wq[kOffB2 + o];
+  }
+#pragma unroll
+  for (int j = 0; j < kHid; ++j) {
+#pragma unroll
+    for (int o = 0; o < kHid; ++o) h2[o] = fmaf(wq[kOffW2 + o * kHid + j], h1[j], h2[o]);
+  }
+#pragma unroll
+  for (int o = 0; o < kHid; ++o) h2[o] = fmaxf(h2[o], 0.f);
+  float tsum = 0.f;
+  for (int o = 0; o < kOut; ++o) tsum += ti[o];
+  const bool use = tsum > 0.f;
+  // scores and log-sum-exp over valid pairs
+  float *dsi = DS + (size_t)i * kOut;
+  float mx = -INFINITY;
+  for (int o = 0; o < kOut; ++o) {
+    if (to_inst[o] < 0) continue;
+    float s = wq[kOffB3 + o];
+#pragma unroll
+    for (int j = 0; j < kHid; ++j) s = fmaf(wq[kOffW3 + o * kHid + j], h2[j], s);
+    dsi[o] = s;
+    mx = fmaxf(mx, s);
+  }
+  float se = 0.f;
+  for (int o = 0; o < kOut; ++o)
+    if (to_inst[o] >= 0) se += expf(dsi[o] - mx);
+  const float lse = mx + logf(se);
+  float loss = 0.f;
+  const float scale = use ? 1.f / (float)nvalid : 0.f;
+  float dh2[kHid];
+#pragma unroll
+  for (int j = 0; j < kHid; ++j) dh2[j] = 0.f;
+  for (int o = 0; o < kOut; ++o) {
+    float d = 0.f;
+    if (to_inst[o] >= 0) {
+      const float ls = dsi[o] - lse;
+      loss -= ti[o] * ls;
+      d = (expf(ls) - ti[o]) * scale;
+#pragma unroll
+      for (int j = 0; j < kHid; ++j) dh2[j] = fmaf(wq[kOffW3 + o * kHid + j], d, dh2[j]);
+    }
+    dsi[o] = d;
+  }
+  rowloss[i] = use ? loss : 0.f;
+  float *h1o = H1 + (size_t)i * kHid, *h2o = H2 + (size_t)i * kHid;
+  float *d1o = DH1 + (size_t)i * kHid, *d2o = DH2 + (size_t)i * kHid;
+#pragma unroll
+  for (int j = 0; j < kHid; ++j) {
+    dh2[j] = h2[j] > 0.f ? dh2[j] : 0.f;
+    h1o[j] = h1[j];
+    h2o[j] = h2[j];
+    d2o[j] = dh2[j];
+  }
+  for (int j = 0; j < kHid; ++j) {
+    float d = 0.f;
+#pragma unroll
+    for (int o = 0; o < kHid; ++o) d = fmaf(wq[kOffW2 + o * kHid + j], dh2[o], d);
+    d1o[j] = h1[j] > 0.f ? d : 0.f;
+  }
+}
+
+// Training, phase 2 (one thread per parameter): weight gradients as sums over
+// the batch rows in row order (deterministic), bias gradients as row sums.
+__global__ void k_train_wgrad(const float *__restrict__ x, const float *__restrict__ H1,
+                              const float *__restrict__ H2, const float *__restrict__ DS,
+                              const float *__restrict__ DH1, const float *__restrict__ DH2, int B,
+                              float *__restrict__ grad) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= kParams) return;
+  const float *D, *A;
+  int dstride, astride, o, j = -1;
+  if (p < kOffB1) {
+    o = p / kIn; j = p % kIn; D = DH1; dstride = kHid; A = x; astride = kIn;
+  } else if (p < kOffW2) {
+    o = p - kOffB1; D = DH1; dstride = kHid; A = nullptr; astride = 0;
+  } else if (p < kOffB2) {
+    o = (p - kOffW2) / kHid; j = (p - kOffW2) % kHid; D = DH2; dstride = kHid; A = H1; astride = kHid;
+  } else if (p < kOffW3) {
+    o = p - kOffB2; D = DH2; dstride = kHid; A = nullptr; astride = 0;
+  } else if (p < kOffB3) {
+    o = (p - kOffW3) / kHid; j = (p - kOffW3) % kHid; D = DS; dstride = kOut; A = H2; astride = kHid;
+  } else {
+    o = p - kOffB3; D = DS; dstride = kOut; A = nullptr; astride = 0;
+  }
+  float g = 0.f;
+  if (j >= 0) {
+    for (int r = 0; r < B; ++r) g = fmaf(D[(size_t)r * dstride + o], A[(size_t)r * astride + j], g);
+  } else {
+    for (int r = 0; r < B; ++r) g += D[(size_t)r * dstride + o];
+  }
+  grad[p] = g;
+}
+
+__global__ void k_sum(const float *__restrict__ v, int B, float *__restrict__ out) {
+  __shared__ float sh[256];
+  float s = 0.f;
+  for (int i = threadIdx.x; i < B; i += 256) s += v[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+__global__ void k_adam(float *__restrict__ master, const float *__restrict__ grad,
+                       float *__restrict__ am, float *__restrict__ av, float lr, float bc1,
+                       float bc2) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= kParams) return;
+  const float g = grad[p];
+  const float mm = 0.9f * am[p] + 0.1f * g;
+  const float vv = 0.999f * av[p] + 0.001f * g * g;
+  am[p] = mm;
+  av[p] = vv;
+  master[p] -= lr * (mm / bc1) / (sqrtf(vv / bc2) + 1e-8f);
+}
+
+// ----------------------------------------------------------------- host side
+static int sel_get(Ctx *c, Selector **out) {
+  if (!c->sel) {
+    Selector *S = new (std::nothrow) Selector();
+    if (!S) return set_err(c, PFSP_ENOMEM, "host allocation failed");
+    bool ok = true;
+    for (float **p : {&S->master, &S->wq, &S->grad, &S->am, &S->av})
+      ok = ok && hipMalloc(p, kParams * sizeof(float)) == hipSuccess;
+    ok = ok && hipMalloc(&S->to_inst, kOut * sizeof(int)) == hipSuccess;
+    ok = ok && hipMalloc(&S->loss, sizeof(float)) == hipSuccess;
+    c->sel = S;
+    if (!ok) {
+      selector_free(c);
+      return set_err(c, PFSP_ENOMEM, "selector allocation failed");
+    }
+  }
+  *out = c->sel;
+  return PFSP_OK;
+}
+
+void selector_free(Ctx *c) {
+  Selector *S = c->sel;
+  if (!S) return;
+  void *bufs[] = {S->master, S->wq, S->grad, S->am, S->av, S->feat, S->scores, S->mask, S->h1,
+                  S->h2, S->ds, S->dh1, S->dh2, S->rowloss, S->loss, S->to_inst};
+  for (void *p : bufs) (void)hipFree(p);
+  delete S;
+  c->sel = nullptr;
+}
+
+// layout pair -> instance pair index table for the loaded instance
+static int sel_tables(Ctx *c, Selector *S) {
+  if (S->to_inst_m == c->m) return PFSP_OK;
+  int h[kOut];
+  for (int o = 0; o < kOut; ++o) h[o] = -1;
+  const int m = c->m;
+  for (int u = 0; u < m && u < kMMax; ++u)
+    for (int v = u + 1; v < m && v < kMMax; ++v)
+      h[u * (2 * kMMax - u - 1) / 2 + (v - u - 1)] = u * (2 * m - u - 1) / 2 + (v - u - 1);
+  PFSP_HIP(c, hipMemcpy(S->to_inst, h, sizeof(h), hipMemcpyHostToDevice));
+  S->to_inst_m = m;
+  return PFSP_OK;
+}
+
+static int sel_rows(Ctx *c, Selector *S, size_t rows) {
+  const int words = (c->P + 31) / 32;
+  if (rows <= S->rows_cap && words <= S->mask_words) return PFSP_OK;
+  PFSP_HIP(c, hipStreamSynchronize(c->stream));
+  (void)hipFree(S->feat);
+  (void)hipFree(S->scores);
+  (void)hipFree(S->mask);
+  S->feat = S->scores = nullptr;
+  S->mask = nullptr;
+  S->rows_cap = 0;
+  const size_t cap = rows > S->rows_cap ? rows : S->rows_cap;
+  const int w = words > S->mask_words ? words : S->mask_words;
+  if (hipMalloc(&S->feat, cap * kIn * 4) != hipSuccess ||
+      hipMalloc(&S->scores, cap * kOut * 4) != hipSuccess ||
+      hipMalloc(&S->mask, cap * (size_t)w * 4) != hipSuccess)
+    return set_err(c, PFSP_ENOMEM, "selector workspace allocation failed");
+  S->rows_cap = cap;
+  S->mask_words = w;
+  return PFSP_OK;
+}
+
+static float instance_norm(const Ctx *c) {
+  long long best = 1;
+  for (int k = 0; k < c->m; ++k) {
+    long long s = 0;
+    for (int j = 0; j < c->n; ++j) s += c->p_host[(size_t)j * c->m + k];
+    if (s > best) best = s;
+  }
+  return (float)best;
+}
+
+int learned_prepare(Ctx *c, int rows) {
+  if (!c->sel || !c->sel->loaded) return set_err(c, PFSP_EINVAL, "no selector parameters set");
+  if (c->m > kMMax) return set_err(c, PFSP_ERANGE, "the learned selector covers m <= 20");
+  if (c->learned_topk > kTopKMax)
+    return set_err(c, PFSP_ERANGE, "learned_topk must be <= 32 for the learned bound");
+  int rc = sel_tables(c, c->sel);
+  if (rc) return rc;
+  return sel_rows(c, c->sel, rows > 0 ? rows : 1);
+}
+
 int launch_learned(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8_t *out_prune,
                    hipStream_t s) {
-  (void)pool; (void)ub; (void)out_lb; (void)out_prune; (void)s;
-  return set_err(c, PFSP_EINVAL, "no selector loaded");
+  int rc = learned_prepare(c, pool.count);
+  if (rc) return rc;
+  Selector *S = c->sel;
+  if (pool.count <= 0) return PFSP_OK;
+  rc = ensure_costs(c, pool.count);
+  if (rc) return rc;
+  const DevInst I = c->inst();
+  // parent costs (front, back, remaining) for the features
+  rc = launch_costs(c, pool, s);
+  if (rc) return rc;
+  const int g = (pool.count + 255) / 256;
+  {
+    KTimer kt(c, s, "k_features");
+    hipLaunchKernelGGL(k_features, dim3(g), dim3(256), 0, s, I, pool, c->d_costs,
+                       instance_norm(c), S->feat);
+  }
+  {
+    KTimer kt(c, s, "k_mlp_forward");
+    hipLaunchKernelGGL(k_mlp_forward, dim3(g), dim3(256), 0, s, S->wq, S->feat, pool.count,
+                       pool.count_dev, S->scores, S->to_inst);
+  }
+  const int words = (c->P + 31) / 32;
+  {
+    KTimer kt(c, s, "k_select");
+    hipLaunchKernelGGL(k_select, dim3(g), dim3(256), 0, s, S->scores, pool.count,
+                       pool.count_dev, (int)c->learned_topk, S->to_inst, words, S->mask);
+  }
+  PFSP_HIP(c, hipGetLastError());
+  DevPool sp = pool;
+  sp.mask = S->mask;
+  sp.mask_words = words;
+  return launch_bound_costs_ready(c, sp, PFSP_LB2_SUBSET, ub, out_lb, out_prune, s);
 }
+
 }  // namespace pfsp
+
+using namespace pfsp;
+
+extern "C" {
+
+int pfsp_selector_set(pfsp_ctx *h, const float *params, int64_t count) {
+  if (!h || !params) return PFSP_EINVAL;
+  Ctx *c = &h->impl;
+  if (count != kParams) return set_err(c, PFSP_EINVAL, "selector expects 20670 parameters");
+  PFSP_HIP(c, hipSetDevice(c->device));
+  Selector *S;
+  int rc = sel_get(c, &S);
+  if (rc) return rc;
+  PFSP_HIP(c, hipMemcpy(S->master, params, kParams * 4, hipMemcpyHostToDevice));
+  PFSP_HIP(c, hipMemset(S->am, 0, kParams * 4));
+  PFSP_HIP(c, hipMemset(S->av, 0, kParams * 4));
+  S->step = 0;
+  hipLaunchKernelGGL(k_round_weights, dim3((kParams + 255) / 256), dim3(256), 0, c->stream,
+                     S->master, S->wq);
+  PFSP_HIP(c, hipGetLastError());
+  PFSP_HIP(c, hipStreamSynchronize(c->stream));
+  S->loaded = 1;
+  return PFSP_OK;
+}
+
+int pfsp_selector_get(pfsp_ctx *h, float *params, int64_t count) {
+  if (!h || !params) return PFSP_EINVAL;
+  Ctx *c = &h->impl;
+  if (!c->sel || !c->sel->loaded) return set_err(c, PFSP_EINVAL, "no selector parameters set");
+  if (count != kParams) return set_err(c, PFSP_EINVAL, "selector has 20670 parameters");
+  PFSP_HIP(c, hipSetDevice(c->device));
+  PFSP_HIP(c, hipStreamSynchronize(c->stream));
+  PFSP_HIP(c, hipMemcpy(params, c->sel->master, kParams * 4, hipMemcpyDeviceToHost));
+  return PFSP_OK;
+}
+
+int pfsp_selector_features(pfsp_ctx *h, const pfsp_pool *pool, float *feat_out) {
+  if (!h || !pool || !feat_out) return PFSP_EINVAL;
+  Ctx *c = &h->impl;
+  if (c->n == 0) return set_err(c, PFSP_ENOINST, "no instance loaded");
+  if (pool->count < 0 || pool->n != c->n) return set_err(c, PFSP_EINVAL, "bad pool");
+  if (pool->count == 0) return PFSP_OK;
+  PFSP_HIP(c, hipSetDevice(c->device));
+  DevPool dp{};
+  dp.count = pool->count;
+  dp.n = pool->n;
+  dp.perm = pool->perm;
+  dp.d1 = pool->d1;
+  dp.d2 = pool->d2;
+  int rc = ensure_costs(c, pool->count);
+  if (rc) return rc;
+  rc = launch_costs(c, dp, c->stream);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_features, dim3((pool->count + 255) / 256), dim3(256), 0, c->stream,
+                     c->inst(), dp, c->d_costs, instance_norm(c), feat_out);
+  PFSP_HIP(c, hipGetLastError());
+  return PFSP_OK;
+}
+
+int pfsp_selector_forward(pfsp_ctx *h, const float *x, int32_t rows, float *scores_out) {
+  if (!h || (rows > 0 && (!x || !scores_out)) || rows < 0) return PFSP_EINVAL;
+  Ctx *c = &h->impl;
+  if (c->n == 0) return set_err(c, PFSP_ENOINST, "no instance loaded");
+  int rc = learned_prepare(c, rows);
+  if (rc) return rc;
+  if (rows == 0) return PFSP_OK;
+  hipLaunchKernelGGL(k_mlp_forward, dim3((rows + 255) / 256), dim3(256), 0, c->stream,
+                     c->sel->wq, x, rows, (const int *)nullptr, scores_out, c->sel->to_inst);
+  PFSP_HIP(c, hipGetLastError());
+  return PFSP_OK;
+}
+
+int pfsp_selector_select(pfsp_ctx *h, const float *scores, int32_t rows, int32_t k,
+                         uint32_t *mask_out) {
+  if (!h || rows < 0 || (rows > 0 && (!scores || !mask_out))) return PFSP_EINVAL;
+  Ctx *c = &h->impl;
+  if (c->n == 0) return set_err(c, PFSP_ENOINST, "no instance loaded");
+  if (k < 1 || k > kTopKMax) return set_err(c, PFSP_ERANGE, "k must be in [1, 32]");
+  if (c->m > kMMax || c->m < 2) return set_err(c, PFSP_ERANGE, "selection needs 2 <= m <= 20");
+  Selector *S;
+  int rc = sel_get(c, &S);
+  if (rc) return rc;
+  rc = sel_tables(c, S);
+  if (rc) return rc;
+  if (rows == 0) return PFSP_OK;
+  hipLaunchKernelGGL(k_select, dim3((rows + 255) / 256), dim3(256), 0, c->stream, scores, rows,
+                     (const int *)nullptr, (int)k, S->to_inst, (c->P + 31) / 32, mask_out);
+  PFSP_HIP(c, hipGetLastError());
+  return PFSP_OK;
+}
+
+int pfsp_selector_targets(pfsp_ctx *h, const pfsp_pool *pool, const int16_t *argpair,
+                          float *target_out) {
+  if (!h || !pool || !argpair || !target_out) return PFSP_EINVAL;
+  Ctx *c = &h->impl;
+  if (c->n == 0) return set_err(c, PFSP_ENOINST, "no instance loaded");
+  if (c->m > kMMax || c->m < 2) return set_err(c, PFSP_ERANGE, "targets need 2 <= m <= 20");
+  if (pool->count < 0 || pool->n != c->n) return set_err(c, PFSP_EINVAL, "bad pool");
+  if (pool->count == 0) return PFSP_OK;
+  Selector *S;
+  int rc = sel_get(c, &S);
+  if (rc) return rc;
+  // instance pair -> layout pair
+  int inst_to20[kOut];
+  const int m = c->m;
+  for (int u = 0; u < m; ++u)
+    for (int v = u + 1; v < m; ++v)
+      inst_to20[u * (2 * m - u - 1) / 2 + (v - u - 1)] = u * (2 * kMMax - u - 1) / 2 + (v - u - 1);
+  int *d_map = nullptr;
+  PFSP_HIP(c, hipMalloc(&d_map, sizeof(inst_to20)));
+  PFSP_HIP(c, hipMemcpyAsync(d_map, inst_to20, sizeof(inst_to20), hipMemcpyHostToDevice,
+                             c->stream));
+  DevPool dp{};
+  dp.count = pool->count;
+  dp.n = pool->n;
+  dp.perm = pool->perm;
+  dp.d1 = pool->d1;
+  dp.d2 = pool->d2;
+  hipLaunchKernelGGL(k_targets, dim3((pool->count + 255) / 256), dim3(256), 0, c->stream,
+                     c->inst(), dp, argpair, d_map, target_out);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(d_map);
+  if (e != hipSuccess) return hip_err(c, e, "k_targets");
+  return PFSP_OK;
+}
+
+int pfsp_selector_train_step(pfsp_ctx *h, const float *x, const float *target, int32_t rows,
+                             float lr, float *loss_out, float *grad_out) {
+  if (!h || !x || !target || rows <= 0) return PFSP_EINVAL;
+  Ctx *c = &h->impl;
+  if (c->n == 0) return set_err(c, PFSP_ENOINST, "no instance loaded");
+  int rc = learned_prepare(c, 1);
+  if (rc) return rc;
+  Selector *S = c->sel;
+  PFSP_HIP(c, hipSetDevice(c->device));
+  if ((size_t)rows > S->train_cap) {
+    PFSP_HIP(c, hipStreamSynchronize(c->stream));
+    for (float **p : {&S->h1, &S->h2, &S->ds, &S->dh1, &S->dh2, &S->rowloss}) {
+      (void)hipFree(*p);
+      *p = nullptr;
+    }
+    bool ok = hipMalloc(&S->h1, (size_t)rows * kHid * 4) == hipSuccess &&
+              hipMalloc(&S->h2, (size_t)rows * kHid * 4) == hipSuccess &&
+              hipMalloc(&S->dh1, (size_t)rows * kHid * 4) == hipSuccess &&
+              hipMalloc(&S->dh2, (size_t)rows * kHid * 4) == hipSuccess &&
+              hipMalloc(&S->ds, (size_t)rows * kOut * 4) == hipSuccess &&
+              hipMalloc(&S->rowloss, (size_t)rows * 4) == hipSuccess;
+    if (!ok) return set_err(c, PFSP_ENOMEM, "training workspace allocation failed");
+    S->train_cap = rows;
+  }
+  // number of rows with a non-empty target (the mean runs over those)
+  std::vector<float> th((size_t)rows * kOut);
+  PFSP_HIP(c, hipStreamSynchronize(c->stream));
+  PFSP_HIP(c, hipMemcpy(th.data(), target, th.size() * 4, hipMemcpyDeviceToHost));
+  int nvalid = 0;
+  for (int i = 0; i < rows; ++i) {
+    float s = 0.f;
+    for (int o = 0; o < kOut; ++o) s += th[(size_t)i * kOut + o];
+    nvalid += s > 0.f;
+  }
+  if (nvalid == 0) nvalid = 1;
+  hipStream_t s = c->stream;
+  hipLaunchKernelGGL(k_train_rows, dim3((rows + 255) / 256), dim3(256), 0, s, S->wq, x, target,
+                     (int)rows, nvalid, S->to_inst, S->h1, S->h2, S->ds, S->dh1, S->dh2,
+                     S->rowloss);
+  hipLaunchKernelGGL(k_train_wgrad, dim3((kParams + 255) / 256), dim3(256), 0, s, x, S->h1, S->h2,
+                     S->ds, S->dh1, S->dh2, (int)rows, S->grad);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, S->rowloss, (int)rows, S->loss);
+  PFSP_HIP(c, hipGetLastError());
+  if (grad_out)
+    PFSP_HIP(c, hipMemcpyAsync(grad_out, S->grad, kParams * 4, hipMemcpyDeviceToDevice, s));
+  if (lr > 0.f) {
+    S->step += 1;
+    const float bc1 = 1.f - powf(0.9f, (float)S->step);
+    const float bc2 = 1.f - powf(0.999f, (float)S->step);
+    hipLaunchKernelGGL(k_adam, dim3((kParams + 255) / 256), dim3(256), 0, s, S->master, S->grad,
+                       S->am, S->av, lr, bc1, bc2);
+    hipLaunchKernelGGL(k_round_weights, dim3((kParams + 255) / 256), dim3(256), 0, s, S->master,
+                       S->wq);
+    PFSP_HIP(c, hipGetLastError());
+  }
+  float l = 0.f;
+  PFSP_HIP(c, hipMemcpyAsync(&l, S->loss, 4, hipMemcpyDeviceToHost, s));
+  PFSP_HIP(c, hipStreamSynchronize(s));
+  if (loss_out) *loss_out = l / (float)nvalid;
+  return PFSP_OK;
+}
+
+}  // extern "C"

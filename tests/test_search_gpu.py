@@ -1,0 +1,121 @@
+"""GPU parity of pfsp_search against the CPU oracle.
+
+Optimal makespans must match brute force and the oracle's depth-first search.
+With the incumbent set to the optimum nothing better exists, the incumbent
+never changes, and the set of decomposed nodes (the critical tree under MinMin
+branching) does not depend on the exploration order, so the node counts must
+match the oracle's exactly.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2012_09511_amd import binding, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = binding.Context(0)
+    yield c
+    c.close()
+
+
+def _valid(p, perm, cmax):
+    n = p.shape[0]
+    assert sorted(perm.tolist()) == list(range(n))
+    assert oracle.makespan(p, perm) == cmax
+
+
+@pytest.mark.parametrize("seed", range(1, 9))
+def test_optimum_10x5(ctx, seed):
+    """n=10 jobs x m=5 machines, p ~ U[1,99], incumbent from NEH."""
+    p = inputs.instance(10, 5, seed)
+    opt, _ = oracle.bruteforce(p)
+    ctx.load_instance(p)
+    ub0, perm0 = ctx.neh()
+    oub, operm = oracle.neh(p)
+    assert (ub0, perm0.tolist()) == (oub, operm.tolist())   # host heuristic parity
+    for kind in (binding.LB1, binding.LB2_FULL):
+        r = ctx.search(ub0 + 1, 0, kind)
+        assert r["proven"] and r["found"] and r["best"] == opt
+        _valid(p, r["perm"], opt)
+
+
+@pytest.mark.parametrize("n,m,seed", [(10, 5, 3), (11, 4, 5), (12, 6, 7), (9, 9, 11)])
+@pytest.mark.parametrize("kind", [binding.LB1, binding.LB2_FULL])
+def test_critical_tree_node_count(ctx, n, m, seed, kind):
+    p = inputs.instance(n, m, seed)
+    opt = oracle.search(p, 10**9, kind)["best"]
+    ref = oracle.search(p, opt, kind)
+    assert ref["proven"] and not ref["found"]
+    ctx.load_instance(p)
+    for batch in (65536, 7):
+        ctx.set_option("pool_batch", batch)
+        r = ctx.search(opt, 0, kind)
+        assert r["proven"] and not r["found"] and r["best"] == opt
+        assert r["nodes"] == ref["nodes"]
+        assert r["children"] == ref["children"]
+    ctx.set_option("pool_batch", 65536)
+
+
+def test_small_batches_and_graph_off(ctx):
+    p = inputs.instance(11, 5, 21)
+    opt, _ = oracle.bruteforce(p)
+    ctx.load_instance(p)
+    for batch, graph in ((1, 1), (3, 0), (64, 1), (1000, 0)):
+        ctx.set_option("pool_batch", batch)
+        ctx.set_option("use_graph", graph)
+        r = ctx.search(10**6, 0, binding.LB1)
+        assert r["proven"] and r["found"] and r["best"] == opt
+        _valid(p, r["perm"], opt)
+    ctx.set_option("pool_batch", 65536)
+    ctx.set_option("use_graph", 1)
+
+
+def test_budget_stops_without_proof(ctx):
+    p = inputs.instance(12, 6, 31)
+    ctx.load_instance(p)
+    ctx.set_option("pool_batch", 4)
+    ctx.set_option("poll_every", 1)
+    r = ctx.search(10**6, 20, binding.LB1)
+    assert r["budget_hit"] and not r["proven"] and r["nodes"] >= 20
+    ctx.set_option("pool_batch", 65536)
+    ctx.set_option("poll_every", 8)
+
+
+@pytest.mark.parametrize("n,m", [(2, 1), (2, 3), (3, 2), (4, 1)])
+def test_tiny_instances(ctx, n, m):
+    p = inputs.instance(n, m, 40 + n + m)
+    opt, _ = oracle.bruteforce(p)
+    ctx.load_instance(p)
+    kinds = (binding.LB1, binding.LB2_FULL) if m >= 2 else (binding.LB1,)
+    for kind in kinds:
+        r = ctx.search(10**6, 0, kind)
+        assert r["proven"] and r["found"] and r["best"] == opt
+        _valid(p, r["perm"], opt)
+
+
+def test_two_machines_root_proves_johnson(ctx):
+    p = inputs.instance(30, 2, 55)
+    ctx.load_instance(p)
+    r = ctx.search(10**6, 0, binding.LB2_FULL)
+    ref = oracle.search(p, 10**6, oracle.LB2_FULL)
+    assert r["best"] == ref["best"] and r["proven"]
+    r2 = ctx.search(ref["best"], 0, binding.LB2_FULL)
+    assert r2["nodes"] == 1 and not r2["found"]
+
+
+def test_search_20x10_matches_oracle(ctx):
+    """A 20 x 10 instance (the search workload's shape) against the oracle, LB1."""
+    p = inputs.instance(20, 10, 1)
+    ctx.load_instance(p)
+    ub0, _ = ctx.neh()
+    r = ctx.search(ub0 + 1, 0, binding.LB1)
+    ref = oracle.search(p, ub0 + 1, oracle.LB1, budget=3_000_000)
+    assert r["proven"]
+    if ref["proven"]:
+        assert r["best"] == ref["best"]
+    if r["found"]:
+        _valid(p, r["perm"], r["best"])

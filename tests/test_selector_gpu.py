@@ -1,0 +1,164 @@
+"""GPU checks of the learned pair selector against oracle/selector.py.
+
+Floating-point results (features, scores, loss, gradients, Adam updates) are
+compared within a tolerance derived from fp32 accumulation over at most 190
+terms of magnitude <= ~10 (relative 1e-4 of the largest magnitude); integer
+decisions are compared exactly where they are unique, and by validity where
+fp32 rounding could reorder near-ties.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import selector as S
+from paper_2012_09511_amd import binding, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = binding.Context(0)
+    yield c
+    c.close()
+
+
+def _t(ctx, a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    return t.to(ctx.device) if dtype is None else t.to(ctx.device, dtype)
+
+
+def _params(seed):
+    ps = inputs.selector_params(seed, scale=2.0)
+    rng = np.random.default_rng(seed)
+    ps[1] = (rng.normal(size=64) * 0.1).astype(np.float32)
+    ps[3] = (rng.normal(size=64) * 0.1).astype(np.float32)
+    ps[5] = (rng.normal(size=190) * 0.1).astype(np.float32)
+    return ps
+
+
+def _close(got, ref, rel=1e-4):
+    scale = max(1.0, float(np.abs(ref).max()))
+    np.testing.assert_allclose(got, ref, rtol=0, atol=rel * scale)
+
+
+@pytest.mark.parametrize("n,m", [(20, 20), (12, 7), (50, 20)])
+def test_features(ctx, n, m):
+    p = inputs.instance(n, m, 70 + m)
+    perm, d1, d2 = inputs.random_pool(n, 300, 71)
+    ctx.load_instance(p)
+    f = ctx.selector_features(*[_t(ctx, a) for a in (perm, d1, d2)]).cpu().numpy()
+    _close(f, S.features(p, perm, d1, d2), rel=1e-6)
+
+
+def test_forward_and_select(ctx):
+    n, m = 20, 13
+    p = inputs.instance(n, m, 80)
+    ctx.load_instance(p)
+    params = _params(81)
+    ctx.selector_set(params)
+    np.testing.assert_array_equal(ctx.selector_get(),
+                                  np.concatenate([q.reshape(-1) for q in params]))
+    rng = np.random.default_rng(82)
+    x = rng.random((500, 64)).astype(np.float32)
+    sc = ctx.selector_forward(_t(ctx, x)).cpu().numpy()
+    ref, _ = S.forward([q.astype(np.float64) for q in params], x.astype(np.float64))
+    valid = S.valid_pairs(m)
+    assert np.isneginf(sc[:, ~valid]).all()
+    _close(sc[:, valid], ref[:, valid])
+    for k in (1, 16, 32):
+        mk = ctx.selector_select(_t(ctx, sc), k).cpu().numpy().view(np.uint32)
+        P = m * (m - 1) // 2
+        bits = np.array([[(mk[i, b >> 5] >> (b & 31)) & 1 for b in range(P)]
+                         for i in range(len(x))], dtype=bool)
+        # exact against the oracle's top-k of the same (GPU) scores
+        ref_mask = S.topk_mask(sc, valid, k)
+        inst = np.zeros((len(x), P), dtype=bool)
+        for u in range(m):
+            for v in range(u + 1, m):
+                inst[:, oracle.pair_index(m, u, v)] = ref_mask[:, S.pair20(u, v)]
+        np.testing.assert_array_equal(bits, inst)
+
+
+def test_targets_from_logged_argmax(ctx):
+    n, m = 15, 9
+    p = inputs.instance(n, m, 90)
+    perm, d1, d2 = inputs.random_pool(n, 200, 91)
+    ctx.load_instance(p)
+    dev = [_t(ctx, a) for a in (perm, d1, d2)]
+    _, _, _, ap = ctx.bound_children(*dev, kind=binding.LB2_FULL, want_argpair=True)
+    tg = ctx.selector_targets(*dev, ap).cpu().numpy()
+    _, _, _, oap = oracle.bound_children(p, perm, d1, d2, oracle.LB2_FULL, with_argpair=True)
+    _close(tg, S.pair_histogram(oap, d1, d2, m), rel=1e-6)
+
+
+def test_train_step_gradients_and_adam(ctx):
+    n, m = 20, 20
+    p = inputs.instance(n, m, 100)
+    ctx.load_instance(p)
+    params = _params(101)
+    rng = np.random.default_rng(102)
+    B = 257
+    x = rng.random((B, 64)).astype(np.float32)
+    valid = S.valid_pairs(m)
+    t = (rng.random((B, 190)) * valid).astype(np.float32)
+    t[::7] = 0
+    t /= np.maximum(t.sum(axis=1, keepdims=True), 1e-30)
+    t = t.astype(np.float32)
+    ctx.selector_set(params)
+    loss, g = ctx.selector_train_step(_t(ctx, x), _t(ctx, t), 0.0, want_grad=True)
+    p64 = [q.astype(np.float64) for q in params]
+    rl, rg = S.loss_and_grads(p64, x.astype(np.float64), t.astype(np.float64), valid)
+    assert abs(loss - rl) <= 1e-4 * max(1.0, abs(rl))
+    flat = np.concatenate([q.reshape(-1) for q in rg])
+    _close(g.cpu().numpy(), flat, rel=1e-4)
+    # one Adam step of size 1e-3 against the reference update
+    ctx.selector_set(params)
+    ctx.selector_train_step(_t(ctx, x), _t(ctx, t), 1e-3)
+    new = ctx.selector_get()
+    ref = S.adam_step(p64, rg, {}, lr=1e-3)
+    _close(new, np.concatenate([q.reshape(-1) for q in ref]), rel=1e-5)
+
+
+def test_training_lowers_the_loss(ctx):
+    n, m = 20, 20
+    p = inputs.instance(n, m, 110)
+    perm, d1, d2 = inputs.random_pool(n, 4096, 111)
+    ctx.load_instance(p)
+    dev = [_t(ctx, a) for a in (perm, d1, d2)]
+    _, _, _, ap = ctx.bound_children(*dev, kind=binding.LB2_FULL, want_argpair=True)
+    tg = ctx.selector_targets(*dev, ap)
+    x = ctx.selector_features(*dev)
+    ctx.selector_set(inputs.selector_params(112))
+    first, _ = ctx.selector_train_step(x, tg, 3e-3)
+    for _ in range(60):
+        last, _ = ctx.selector_train_step(x, tg, 3e-3)
+    assert last < 0.8 * first
+
+
+@pytest.mark.parametrize("topk", [1, 16, 190])
+def test_learned_bound_equals_subset_bound(ctx, topk):
+    """LB2_LEARNED = subset LB2 over the pairs the selector picks (checked
+    against the oracle with the same mask) and never above full LB2."""
+    import torch
+    n, m = 20, 20
+    p = inputs.instance(n, m, 120)
+    perm, d1, d2 = inputs.random_pool(n, 300, 121)
+    ctx.load_instance(p)
+    ctx.selector_set(_params(122))
+    dev = [_t(ctx, a) for a in (perm, d1, d2)]
+    k = min(topk, 32)
+    ctx.set_option("learned_topk", k)
+    lb, pr, dr, _ = ctx.bound_children(*dev, kind=binding.LB2_LEARNED, ub=1900)
+    torch.cuda.synchronize()
+    mask = ctx.selector_select(ctx.selector_forward(ctx.selector_features(*dev)), k)
+    mask = mask.cpu().numpy().view(np.uint32)
+    olb, opr, odr = oracle.bound_children(p, perm, d1, d2, oracle.LB2_SUBSET, 1900,
+                                          pair_mask=mask, threads=8)
+    np.testing.assert_array_equal(lb.cpu().numpy(), olb)
+    np.testing.assert_array_equal(pr.cpu().numpy(), opr)
+    np.testing.assert_array_equal(dr.cpu().numpy(), odr)
+    full, _, _ = oracle.bound_children(p, perm, d1, d2, oracle.LB2_FULL, 1900, threads=8)
+    assert (olb <= full).all()
+    ctx.set_option("learned_topk", 16)

@@ -459,6 +459,18 @@ k_lb2f(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
       umask = ((MT)hi << 32) | lo;
     }
     wave_sync();
+    // number of selected pairs of this parent (subset bounds)
+    int nsel = 0;
+    if constexpr (SUBSET) {
+      const int words = (P + 31) >> 5;
+      const uint32_t *mw = pool.mask + (size_t)par * pool.mask_words;
+      for (int w = lane; w < words; w += 64) nsel += __popc(mw[w] & (w == words - 1 && (P & 31)
+                                                                ? (1u << (P & 31)) - 1u
+                                                                : 0xffffffffu));
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) nsel += __shfl_xor(nsel, o, kWave);
+      nsel = __builtin_amdgcn_readfirstlane(nsel);
+    }
     MinMin mm;
     mm.init();
     for (int cb = 0; cb < r; cb += 32) {
@@ -493,11 +505,32 @@ k_lb2f(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
 #pragma unroll
         for (int q = 0; q < 64; ++q) arg[q] = 0x7fffffff;
       }
-      for (int pc = 0; pc < Ppad; pc += 64) {
-        const int pi = pc + lane;
+      // subset bounds: lane l of pass pc takes the (pc + l)-th selected pair, so
+      // k selected pairs need ceil(k / 64) passes instead of ceil(P / 64)
+      const int npass = SUBSET ? nsel : Ppad;
+      for (int pc = 0; pc < npass; pc += 64) {
+        int pi = pc + lane;
         bool act = pi < P;
-        if (SUBSET && act)
-          act = (pool.mask[(size_t)par * pool.mask_words + (pi >> 5)] >> (pi & 31)) & 1u;
+        if constexpr (SUBSET) {
+          act = pi < nsel;
+          int sidx = pi;
+          pi = Ppad - 1;  // a padded pair for idle lanes
+          if (act) {
+            const int words = (P + 31) >> 5;
+            const uint32_t *mw = pool.mask + (size_t)par * pool.mask_words;
+            for (int w = 0; w < words; ++w) {
+              uint32_t bits = mw[w];
+              if (w == words - 1 && (P & 31)) bits &= (1u << (P & 31)) - 1u;  // pairs >= P
+              const int cnt = __popc(bits);
+              if (sidx < cnt) {
+                for (int t = 0; t < sidx; ++t) bits &= bits - 1u;
+                pi = w * 32 + __ffs(bits) - 1;
+                break;
+              }
+              sidx -= cnt;
+            }
+          }
+        }
         const int uvp = uv[pi];
         const int u = uvp & 0xff, v = uvp >> 8;
         const int RU = rr[u], RV = rr[v], C1u = c1[u], C1v = c1[v], C2u = c2[u], C2v = c2[v];

@@ -137,6 +137,13 @@ int pfsp_check(pfsp_ctx *c);
 int pfsp_search(pfsp_ctx *c, int32_t ub0, int64_t budget_nodes, int lb_kind,
                 pfsp_result *res);
 
+/* Copies up to max_records nodes decomposed by the last pfsp_search (every
+ * log_stride-th node of each batch, at most log_capacity; option names above)
+ * to HOST perm_out[max_records][n], d1_out, d2_out; *count receives the number
+ * copied.  Synchronous. */
+int pfsp_search_log(pfsp_ctx *c, uint8_t *perm_out, uint8_t *d1_out, uint8_t *d2_out,
+                    int64_t max_records, int64_t *count);
+
 /* Nawaz-Enscore-Ham constructive heuristic on the loaded instance, used for
  * the initial incumbent: jobs by decreasing total time (ties: lower id), each
  * inserted at the first position minimising the partial makespan.  HOST
@@ -150,9 +157,21 @@ int pfsp_neh(pfsp_ctx *c, int32_t *perm_out, int32_t *cmax_out);
  * "learned_topk" (pairs kept by the selector, default 16),
  * "learned_exact" (1 = re-bound subset survivors with all pairs, default 0),
  * "timing" (1 = bracket every kernel launch with HIP events on the ctx
- * stream, default 0). */
+ * stream, default 0), "lb2_waves" (waves per block of the LB2 kernel, 0 =
+ * automatic), "lb2_blocks_per_cu" (cap on resident LB2 blocks per CU, 0 = 16),
+ * "force_generic" (1 = always use the generic LB2 kernel),
+ * "log_capacity" (records kept by pfsp_search's node log, 0 = off) and
+ * "log_stride" (log every log_stride-th decomposed node of a batch). */
 int pfsp_set_option(pfsp_ctx *c, const char *key, int64_t value);
 int pfsp_get_option(pfsp_ctx *c, const char *key, int64_t *value);
+
+/* Autotuner for the single-instance LB2 kernels: times pfsp_bound_children on
+ * this pool (DEVICE buffers as there) for every candidate of options
+ * "lb2_waves" (0,1,2,3,4,6,8) and "lb2_blocks_per_cu" (0,2,4,8,16,32), median
+ * of reps runs each, sets the fastest pair on the context and writes a JSON
+ * summary to report (HOST, report_len bytes).  Synchronous. */
+int pfsp_autotune(pfsp_ctx *c, const pfsp_pool *pool, int lb_kind, int32_t ub, int32_t *out_lb,
+                  uint8_t *out_prune, int32_t reps, char *report, int32_t report_len);
 
 /* Instrumentation (option "timing" = 1): total milliseconds and number of
  * launches of the kernel named `kernel` ("k_lb1", "k_lb2", ...) since the last
@@ -161,6 +180,45 @@ int pfsp_get_option(pfsp_ctx *c, const char *key, int64_t *value);
  * reading. */
 int pfsp_kernel_time(pfsp_ctx *c, const char *kernel, double *total_ms, int64_t *launches,
                      int reset);
+
+/* ------------------------------------------------------------------------
+ * Several instances of different (n, m) bounded together.  Parents of all
+ * instances share one DEVICE pool whose rows have a common stride (>= every
+ * n used); the parents of instance k are rows [seg_begin[k], seg_begin[k+1]).
+ * Outputs use the same stride: out_lb/out_prune [N][2][stride], slots
+ * q >= n - d1 - d2 hold INT32_MAX / prune 1.  The launch sequence (one costs
+ * kernel, one persistent LB2 kernel per instance class draining a queue of
+ * instance tiles, generic kernels for n > 64 or p >= 2^16) is captured as a
+ * HIP graph on first use and replayed while buffers and grouping are
+ * unchanged.
+ * ------------------------------------------------------------------------ */
+typedef struct pfsp_multi pfsp_multi;
+
+/* Stages `count` instances (HOST p[k][n[k]*m[k]]) for batched bounding. */
+int pfsp_multi_create(pfsp_ctx *c, int32_t count, const int32_t *n, const int32_t *m,
+                      const int32_t *const *p, pfsp_multi **out);
+
+void pfsp_multi_destroy(pfsp_multi *mt);
+
+/* Decomposition of every parent (as pfsp_bound_children, lb_kind PFSP_LB1 or
+ * PFSP_LB2_FULL) with incumbent ub[k] (HOST [count]) for instance k;
+ * seg_begin is HOST [count + 1] with seg_begin[0] = 0.  Synchronous. */
+int pfsp_multi_bound(pfsp_multi *mt, int lb_kind, const uint8_t *perm, const uint8_t *d1,
+                     const uint8_t *d2, int32_t stride, const int64_t *seg_begin,
+                     const int32_t *ub, int32_t *out_lb, uint8_t *out_prune, uint8_t *dir_out);
+
+/* Launch shape: parents per tile, waves per block of the n <= 20 and n <= 64
+ * classes (0 = most resident waves), blocks per CU (0 = as many as fit). */
+int pfsp_multi_set_shape(pfsp_multi *mt, int32_t tile, int32_t waves_small, int32_t waves_large,
+                         int32_t blocks_per_cu);
+
+/* Autotuner: runs pfsp_multi_bound's launch for every candidate shape (tile
+ * 64..1024, waves 0/2/4/8, blocks per CU 0/2/4/8) on this batch, keeps the
+ * fastest (median of reps replays) and writes a JSON summary to report. */
+int pfsp_multi_autotune(pfsp_multi *mt, int lb_kind, const uint8_t *perm, const uint8_t *d1,
+                        const uint8_t *d2, int32_t stride, const int64_t *seg_begin,
+                        const int32_t *ub, int32_t *out_lb, uint8_t *out_prune, uint8_t *dir_out,
+                        int32_t reps, char *report, int32_t report_len);
 
 /* ------------------------------------------------------------------------
  * Learned machine-pair selector (PFSP_LB2_LEARNED).  Section 2.4 allows LB2

@@ -24,7 +24,9 @@ EXPORTS = ["pfsp_create", "pfsp_destroy", "pfsp_last_error", "pfsp_load_instance
            "pfsp_pair_count", "pfsp_bound_children", "pfsp_check", "pfsp_search", "pfsp_neh",
            "pfsp_set_option", "pfsp_get_option", "pfsp_kernel_time", "pfsp_selector_set",
            "pfsp_selector_get", "pfsp_selector_features", "pfsp_selector_forward",
-           "pfsp_selector_select", "pfsp_selector_targets", "pfsp_selector_train_step"]
+           "pfsp_selector_select", "pfsp_selector_targets", "pfsp_selector_train_step",
+           "pfsp_search_log", "pfsp_multi_create", "pfsp_multi_destroy", "pfsp_multi_bound",
+           "pfsp_multi_set_shape", "pfsp_multi_autotune", "pfsp_autotune"]
 SELECTOR_PARAMS = 20670
 
 
@@ -77,6 +79,16 @@ def lib():
         L.pfsp_get_option.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(i64)]
         L.pfsp_kernel_time.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(i64), ctypes.c_int]
+        L.pfsp_search_log.argtypes = [vp, vp, vp, vp, i64, ctypes.POINTER(i64)]
+        L.pfsp_autotune.argtypes = [vp, ctypes.POINTER(Pool), ctypes.c_int, i32, vp, vp, i32,
+                                    ctypes.c_char_p, i32]
+        L.pfsp_multi_create.argtypes = [vp, i32, vp, vp, vp, ctypes.POINTER(vp)]
+        L.pfsp_multi_destroy.argtypes = [vp]
+        L.pfsp_multi_destroy.restype = None
+        L.pfsp_multi_bound.argtypes = [vp, ctypes.c_int, vp, vp, vp, i32, vp, vp, vp, vp, vp]
+        L.pfsp_multi_set_shape.argtypes = [vp, i32, i32, i32, i32]
+        L.pfsp_multi_autotune.argtypes = [vp, ctypes.c_int, vp, vp, vp, i32, vp, vp, vp, vp, vp,
+                                          i32, ctypes.c_char_p, i32]
         L.pfsp_selector_set.argtypes = [vp, vp, i64]
         L.pfsp_selector_get.argtypes = [vp, vp, i64]
         L.pfsp_selector_features.argtypes = [vp, ctypes.POINTER(Pool), vp]
@@ -86,7 +98,7 @@ def lib():
         L.pfsp_selector_train_step.argtypes = [vp, vp, vp, i32, ctypes.c_float,
                                                ctypes.POINTER(ctypes.c_float), vp]
         for name in EXPORTS:
-            if name not in ("pfsp_destroy", "pfsp_last_error"):
+            if name not in ("pfsp_destroy", "pfsp_last_error", "pfsp_multi_destroy"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -163,6 +175,20 @@ class Context:
                                               _ptr(out_lb), _ptr(out_prune)))
         return out_lb, out_prune, dir_out, argpair_out
 
+    def autotune(self, perm, d1, d2, kind=LB2_FULL, ub=INT32_MAX, reps=3, pair_mask=None):
+        """Times LB2 block shapes on this pool and keeps the fastest; returns the report."""
+        import json
+        torch = self.torch
+        N = perm.shape[0]
+        lb = torch.empty((N, 2, self.n), dtype=torch.int32, device=self.device)
+        pr = torch.empty((N, 2, self.n), dtype=torch.uint8, device=self.device)
+        pool = Pool(N, self.n, _ptr(perm), _ptr(d1), _ptr(d2), _ptr(pair_mask),
+                    0 if pair_mask is None else pair_mask.shape[-1], None, None)
+        buf = ctypes.create_string_buffer(4096)
+        self._check(lib().pfsp_autotune(self.h, ctypes.byref(pool), kind, int(ub), _ptr(lb),
+                                        _ptr(pr), reps, buf, 4096))
+        return json.loads(buf.value.decode())
+
     def check(self):
         return self._check(lib().pfsp_check(self.h))
 
@@ -176,6 +202,18 @@ class Context:
                     steps=res.steps, nodes=res.nodes_decomposed,
                     children=res.children_bounded, max_pool=res.max_pool,
                     seconds=res.seconds, perm=perm.astype(np.uint8), budget_hit=rc == 1)
+
+    def search_log(self, max_records):
+        """Nodes logged by the last search: (perm [k, n] u8, d1 [k], d2 [k]) on the host."""
+        perm = np.zeros((max_records, self.n), dtype=np.uint8)
+        d1 = np.zeros(max_records, dtype=np.uint8)
+        d2 = np.zeros(max_records, dtype=np.uint8)
+        k = ctypes.c_int64()
+        self._check(lib().pfsp_search_log(self.h, perm.ctypes.data_as(ctypes.c_void_p),
+                                          d1.ctypes.data_as(ctypes.c_void_p),
+                                          d2.ctypes.data_as(ctypes.c_void_p), max_records,
+                                          ctypes.byref(k)))
+        return perm[:k.value], d1[:k.value], d2[:k.value]
 
     def neh(self):
         perm = np.zeros(self.n, dtype=np.int32)
@@ -255,3 +293,67 @@ class Context:
         self._check(lib().pfsp_selector_train_step(self.h, _ptr(x), _ptr(target), x.shape[0],
                                                    float(lr), ctypes.byref(loss), _ptr(g)))
         return loss.value, g
+
+
+class Multi:
+    """Several instances bounded together (pfsp_multi_*); owned by a Context."""
+
+    def __init__(self, ctx: Context, instances):
+        """instances: list of int32 arrays p[n, m]."""
+        self.ctx = ctx
+        ps = [np.ascontiguousarray(p, dtype=np.int32) for p in instances]
+        self.shapes = [p.shape for p in ps]
+        ns = np.array([s[0] for s in self.shapes], dtype=np.int32)
+        ms = np.array([s[1] for s in self.shapes], dtype=np.int32)
+        ptrs = (ctypes.c_void_p * len(ps))(*[p.ctypes.data for p in ps])
+        h = ctypes.c_void_p()
+        ctx._check(lib().pfsp_multi_create(ctx.h, len(ps), ns.ctypes.data_as(ctypes.c_void_p),
+                                           ms.ctypes.data_as(ctypes.c_void_p), ptrs,
+                                           ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib().pfsp_multi_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _args(self, perm, d1, d2, seg, ub, out):
+        seg = np.ascontiguousarray(seg, dtype=np.int64)
+        ub = np.ascontiguousarray(ub, dtype=np.int32)
+        lb, pr, dr = out
+        return (_ptr(perm), _ptr(d1), _ptr(d2), perm.shape[1],
+                seg.ctypes.data_as(ctypes.c_void_p), ub.ctypes.data_as(ctypes.c_void_p),
+                _ptr(lb), _ptr(pr), _ptr(dr)), (seg, ub)
+
+    def outputs(self, N, stride):
+        torch = self.ctx.torch
+        dev = self.ctx.device
+        return (torch.empty((N, 2, stride), dtype=torch.int32, device=dev),
+                torch.empty((N, 2, stride), dtype=torch.uint8, device=dev),
+                torch.empty(N, dtype=torch.uint8, device=dev))
+
+    def bound(self, perm, d1, d2, seg, ub, kind=LB2_FULL, out=None):
+        if out is None:
+            out = self.outputs(perm.shape[0], perm.shape[1])
+        args, keep = self._args(perm, d1, d2, seg, ub, out)
+        self.ctx._check(lib().pfsp_multi_bound(self.h, kind, *args))
+        return out
+
+    def set_shape(self, tile=256, waves_small=0, waves_large=0, blocks_per_cu=0):
+        self.ctx._check(lib().pfsp_multi_set_shape(self.h, tile, waves_small, waves_large,
+                                                   blocks_per_cu))
+
+    def autotune(self, perm, d1, d2, seg, ub, kind=LB2_FULL, out=None, reps=3):
+        import json
+        if out is None:
+            out = self.outputs(perm.shape[0], perm.shape[1])
+        args, keep = self._args(perm, d1, d2, seg, ub, out)
+        buf = ctypes.create_string_buffer(4096)
+        self.ctx._check(lib().pfsp_multi_autotune(self.h, kind, *args, reps, buf, 4096))
+        return json.loads(buf.value.decode())

@@ -5,7 +5,9 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
+#include <vector>
 
 #include "internal.h"
 
@@ -226,6 +228,9 @@ static int64_t *opt_slot(Ctx *c, const char *key) {
   if (!strcmp(key, "timing")) return &c->timing;
   if (!strcmp(key, "force_generic")) return &c->force_generic;
   if (!strcmp(key, "lb2_waves")) return &c->lb2_waves;
+  if (!strcmp(key, "lb2_blocks_per_cu")) return &c->lb2_blocks_per_cu;
+  if (!strcmp(key, "log_capacity")) return &c->log_capacity;
+  if (!strcmp(key, "log_stride")) return &c->log_stride;
   return nullptr;
 }
 
@@ -240,6 +245,12 @@ int pfsp_set_option(pfsp_ctx *h, const char *key, int64_t value) {
     return set_err(c, PFSP_ERANGE, "poll_every must be in [1, 4096]");
   if (!strcmp(key, "pool_capacity") && value < 0)
     return set_err(c, PFSP_ERANGE, "pool_capacity must be >= 0");
+  if (!strcmp(key, "log_capacity") && (value < 0 || value > (int64_t(1) << 31)))
+    return set_err(c, PFSP_ERANGE, "log_capacity must be in [0, 2^31]");
+  if (!strcmp(key, "log_stride") && (value < 1 || value > (1 << 24)))
+    return set_err(c, PFSP_ERANGE, "log_stride must be in [1, 2^24]");
+  if (!strcmp(key, "lb2_blocks_per_cu") && (value < 0 || value > 64))
+    return set_err(c, PFSP_ERANGE, "lb2_blocks_per_cu must be in [0, 64]");
   if (!strcmp(key, "lb2_waves") && (value < 0 || value > 8))
     return set_err(c, PFSP_ERANGE, "lb2_waves must be in [0, 8]");
   if (!strcmp(key, "learned_topk") && (value < 1 || value > 2016))
@@ -248,7 +259,9 @@ int pfsp_set_option(pfsp_ctx *h, const char *key, int64_t value) {
        !strcmp(key, "force_generic")) &&
       value != 0 && value != 1)
     return set_err(c, PFSP_EINVAL, "flag options take 0 or 1");
-  if (!strcmp(key, "pool_batch") || !strcmp(key, "pool_capacity")) search_free(c);
+  if (!strcmp(key, "pool_batch") || !strcmp(key, "pool_capacity") ||
+      !strcmp(key, "log_capacity"))
+    search_free(c);
   *s = value;
   return PFSP_OK;
 }
@@ -259,6 +272,73 @@ int pfsp_get_option(pfsp_ctx *h, const char *key, int64_t *value) {
   int64_t *s = opt_slot(c, key);
   if (!s) return set_err(c, PFSP_EINVAL, std::string("unknown option ") + key);
   *value = *s;
+  return PFSP_OK;
+}
+
+int pfsp_autotune(pfsp_ctx *h, const pfsp_pool *pool, int lb_kind, int32_t ub, int32_t *out_lb,
+                  uint8_t *out_prune, int32_t reps, char *report, int32_t report_len) {
+  if (!h || !pool) return PFSP_EINVAL;
+  Ctx *c = &h->impl;
+  if (lb_kind != PFSP_LB2_FULL && lb_kind != PFSP_LB2_SUBSET && lb_kind != PFSP_LB2_LEARNED)
+    return set_err(c, PFSP_EINVAL, "the autotuner shapes the LB2 kernels");
+  if (reps < 1) reps = 3;
+  PFSP_HIP(c, hipSetDevice(c->device));
+  const int64_t save_w = c->lb2_waves, save_g = c->lb2_blocks_per_cu, save_t = c->timing;
+  c->timing = 0;
+  hipEvent_t e0, e1;
+  PFSP_HIP(c, hipEventCreate(&e0));
+  PFSP_HIP(c, hipEventCreate(&e1));
+  struct Cand {
+    int w, g;
+    double ms;
+  };
+  std::vector<Cand> res;
+  int rc = PFSP_OK;
+  for (int w : {0, 1, 2, 3, 4, 6, 8})
+    for (int g : {0, 2, 4, 8, 16, 32}) {
+      c->lb2_waves = w;
+      c->lb2_blocks_per_cu = g;
+      rc = pfsp_bound_children(h, pool, lb_kind, ub, out_lb, out_prune);  // warm-up
+      if (rc) break;
+      std::vector<double> ts;
+      for (int r = 0; r < reps && rc == PFSP_OK; ++r) {
+        if (hipEventRecord(e0, c->stream) != hipSuccess) rc = PFSP_EDEVICE;
+        if (!rc) rc = pfsp_bound_children(h, pool, lb_kind, ub, out_lb, out_prune);
+        if (!rc && hipEventRecord(e1, c->stream) != hipSuccess) rc = PFSP_EDEVICE;
+        float ms = 0.f;
+        if (!rc && (hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+          rc = PFSP_EDEVICE;
+        ts.push_back(ms);
+      }
+      if (rc) break;
+      std::sort(ts.begin(), ts.end());
+      res.push_back({w, g, ts[ts.size() / 2]});
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->timing = save_t;
+  if (rc || res.empty()) {
+    c->lb2_waves = save_w;
+    c->lb2_blocks_per_cu = save_g;
+    return rc ? rc : set_err(c, PFSP_EINVAL, "no candidate ran");
+  }
+  Cand best = res[0];
+  double dflt = -1;
+  for (const Cand &x : res) {
+    if (x.ms < best.ms) best = x;
+    if (x.w == 0 && x.g == 0) dflt = x.ms;
+  }
+  c->lb2_waves = best.w;
+  c->lb2_blocks_per_cu = best.g;
+  if (report && report_len > 0) {
+    std::string js = "{\"best\": {\"lb2_waves\": " + std::to_string(best.w) +
+                     ", \"lb2_blocks_per_cu\": " + std::to_string(best.g) +
+                     ", \"ms\": " + std::to_string(best.ms) + "}, \"default_ms\": " +
+                     std::to_string(dflt) + ", \"candidates\": " + std::to_string(res.size()) +
+                     "}";
+    snprintf(report, (size_t)report_len, "%s", js.c_str());
+  }
   return PFSP_OK;
 }
 

@@ -59,6 +59,8 @@ struct Wide {
   }
 };
 
+// Slots q >= from of both directions of a row of 2 * n entries: INT32_MAX,
+// pruned, no argmax pair.
 __device__ __forceinline__ void fill_invalid(int *lbrow, uint8_t *prow, int16_t *arow, int n,
                                              int from, int lane, int step) {
   for (int x = lane; x < 2 * n; x += step) {
@@ -74,6 +76,101 @@ __device__ __forceinline__ void fill_invalid(int *lbrow, uint8_t *prow, int16_t 
 }  // namespace
 
 // ---------------------------------------------------------------- LB1 / costs
+// One parent (one lane): validity check, front/back/remaining, and in LB1 mode
+// every child's LB1 plus MinMin and prune flags.  pmat: p[n][m] (LDS or
+// global); C1/C2/R: per-lane scratch with stride B; rows of the pool and the
+// outputs have stride ns >= n.
+__device__ __forceinline__ void lb1_row(const DevInst &I, const int *__restrict__ pmat, int *C1,
+                                        int *C2, int *R, int B, const uint8_t *__restrict__ row,
+                                        int a, int b, int ns, int ub, int *__restrict__ lbrow,
+                                        uint8_t *__restrict__ prow, int16_t *__restrict__ arow,
+                                        uint8_t *__restrict__ dirp, int *__restrict__ cs,
+                                        int write_out, int *__restrict__ flag) {
+  const int n = I.n, m = I.m;
+  const int r = n - a - b;
+  // a row must be a permutation of 0..n-1 with d1 + d2 < n
+  bool bad = r < 1;
+  uint32_t seen[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int x = 0; x < n && !bad; ++x) {
+    const int j = row[x];
+    const uint32_t bit = 1u << (j & 31);
+    if (j >= n || (seen[j >> 5] & bit)) bad = true;
+    seen[j >> 5] |= bit;
+  }
+  if (bad) {
+    flag[0] = 1;
+    if (write_out) {  // in costs mode the LB2 kernel fills the outputs of this row
+      fill_invalid(lbrow, prow, arow, ns, 0, 0, 1);
+      if (dirp) *dirp = 0;
+    }
+    if (cs) {
+      for (int k = 0; k < 3 * m; ++k) cs[k] = 0;
+      cs[0] = -1;  // marks the row invalid for the LB2 kernels
+    }
+    return;
+  }
+  for (int k = 0; k < m; ++k) {
+    C1[k * B] = 0;
+    C2[k * B] = 0;
+    R[k * B] = I.T[k];
+  }
+  for (int x = 0; x < a; ++x) {  // front of sigma1, Eq. (1)
+    const int *pj = pmat + row[x] * m;
+    int c = 0;
+    for (int k = 0; k < m; ++k) {
+      c = max(c, C1[k * B]) + pj[k];
+      C1[k * B] = c;
+      R[k * B] -= pj[k];
+    }
+  }
+  for (int x = n - 1; x >= n - b; --x) {  // back of sigma2: reverse jobs, reverse machines
+    const int *pj = pmat + row[x] * m;
+    int c = 0;
+    for (int k = m - 1; k >= 0; --k) {
+      c = max(c, C2[k * B]) + pj[k];
+      C2[k * B] = c;
+      R[k * B] -= pj[k];
+    }
+  }
+  if (cs) {
+    for (int k = 0; k < m; ++k) {
+      cs[k] = C1[k * B];
+      cs[m + k] = C2[k * B];
+      cs[2 * m + k] = R[k * B];
+    }
+  }
+  if (!write_out) return;
+  MinMin mm;
+  mm.init();
+  for (int q = 0; q < r; ++q) {
+    const int *pj = pmat + row[a + q] * m;
+    int c = 0, lbf = 0;
+    for (int k = 0; k < m; ++k) {
+      c = max(c, C1[k * B]) + pj[k];
+      lbf = max(lbf, c + R[k * B] - pj[k] + C2[k * B]);
+    }
+    c = 0;
+    int lbb = 0;
+    for (int k = m - 1; k >= 0; --k) {
+      c = max(c, C2[k * B]) + pj[k];
+      lbb = max(lbb, C1[k * B] + R[k * B] - pj[k] + c);
+    }
+    lbrow[q] = lbf;
+    lbrow[ns + q] = lbb;
+    prow[q] = lbf >= ub;
+    prow[ns + q] = lbb >= ub;
+    mm.add(lbf, false);
+    mm.add(lbb, true);
+  }
+  for (int q = r; q < ns; ++q) {
+    lbrow[q] = kInt32Max;
+    lbrow[ns + q] = kInt32Max;
+    prow[q] = 1;
+    prow[ns + q] = 1;
+  }
+  if (dirp) *dirp = (uint8_t)mm.dir();
+}
+
 __global__ void __launch_bounds__(128)
 k_lb1(DevInst I, DevPool pool, int ub, int *__restrict__ out_lb, uint8_t *__restrict__ out_prune,
       int *__restrict__ costs, int write_out, int *__restrict__ flag) {
@@ -87,95 +184,40 @@ k_lb1(DevInst I, DevPool pool, int ub, int *__restrict__ out_lb, uint8_t *__rest
   if (i >= count) return;
   if (pool.ub_dev) ub = *pool.ub_dev;
   int *C1 = sh + n * m + t;  // per-lane arrays, stride B (bank-conflict free)
-  int *C2 = C1 + m * B;
-  int *R = C2 + m * B;
-  const uint8_t *row = pool.perm + (size_t)i * n;
-  const int a = pool.d1[i], b = pool.d2[i], r = n - a - b;
-  int *lbrow = out_lb + (size_t)i * 2 * n;
-  uint8_t *prow = out_prune + (size_t)i * 2 * n;
-  int16_t *arow = pool.argpair ? pool.argpair + (size_t)i * 2 * n : nullptr;
-  // a row must be a permutation of 0..n-1 with d1 + d2 < n
-  bool bad = r < 1;
-  uint32_t seen[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int x = 0; x < n && !bad; ++x) {
-    const int j = row[x];
-    const uint32_t bit = 1u << (j & 31);
-    if (j >= n || (seen[j >> 5] & bit)) bad = true;
-    seen[j >> 5] |= bit;
+  const int ns = pool.n;     // row stride of the pool and the outputs (>= n)
+  lb1_row(I, sp, C1, C1 + m * B, C1 + 2 * m * B, B, pool.perm + (size_t)i * ns, pool.d1[i],
+          pool.d2[i], ns, ub, write_out ? out_lb + (size_t)i * 2 * ns : nullptr,
+          write_out ? out_prune + (size_t)i * 2 * ns : nullptr,
+          write_out && pool.argpair ? pool.argpair + (size_t)i * 2 * ns : nullptr,
+          write_out && pool.dir ? pool.dir + i : nullptr,
+          costs ? costs + (size_t)i * 3 * m : nullptr, write_out, flag);
+}
+
+// Several instances: parent i belongs to the instance k with
+// seg[k] <= i < seg[k + 1]; p is read from global memory (cached); costs rows
+// have stride 3 * mmax.
+__global__ void __launch_bounds__(128)
+k_lb1m(const DevInst *__restrict__ insts, const long long *__restrict__ seg, int ninst,
+       const uint8_t *__restrict__ perm, const uint8_t *__restrict__ d1,
+       const uint8_t *__restrict__ d2, int stride, int mmax, const int *__restrict__ ubs,
+       int *__restrict__ out_lb, uint8_t *__restrict__ out_prune, uint8_t *__restrict__ dir,
+       int *__restrict__ costs, int write_out, int *__restrict__ flag) {
+  extern __shared__ int sh[];
+  const int B = blockDim.x, t = threadIdx.x;
+  const long long i = (long long)blockIdx.x * B + t;
+  if (i >= seg[ninst]) return;
+  int lo = 0, hi = ninst;  // seg[lo] <= i < seg[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (seg[mid] <= i) lo = mid; else hi = mid;
   }
-  if (bad) {
-    flag[0] = 1;
-    if (write_out) {  // in costs mode the LB2 kernel fills the outputs of this row
-      fill_invalid(lbrow, prow, arow, n, 0, 0, 1);
-      if (pool.dir) pool.dir[i] = 0;
-    }
-    if (costs) {
-      for (int k = 0; k < 3 * m; ++k) costs[(size_t)i * 3 * m + k] = 0;
-      costs[(size_t)i * 3 * m] = -1;  // marks the row invalid for the LB2 kernels
-    }
-    return;
-  }
-  for (int k = 0; k < m; ++k) {
-    C1[k * B] = 0;
-    C2[k * B] = 0;
-    R[k * B] = I.T[k];
-  }
-  for (int x = 0; x < a; ++x) {  // front of sigma1, Eq. (1)
-    const int *pj = sp + row[x] * m;
-    int c = 0;
-    for (int k = 0; k < m; ++k) {
-      c = max(c, C1[k * B]) + pj[k];
-      C1[k * B] = c;
-      R[k * B] -= pj[k];
-    }
-  }
-  for (int x = n - 1; x >= n - b; --x) {  // back of sigma2: reverse jobs, reverse machines
-    const int *pj = sp + row[x] * m;
-    int c = 0;
-    for (int k = m - 1; k >= 0; --k) {
-      c = max(c, C2[k * B]) + pj[k];
-      C2[k * B] = c;
-      R[k * B] -= pj[k];
-    }
-  }
-  if (costs) {
-    int *o = costs + (size_t)i * 3 * m;
-    for (int k = 0; k < m; ++k) {
-      o[k] = C1[k * B];
-      o[m + k] = C2[k * B];
-      o[2 * m + k] = R[k * B];
-    }
-  }
-  if (!write_out) return;
-  MinMin mm;
-  mm.init();
-  for (int q = 0; q < r; ++q) {
-    const int *pj = sp + row[a + q] * m;
-    int c = 0, lbf = 0;
-    for (int k = 0; k < m; ++k) {
-      c = max(c, C1[k * B]) + pj[k];
-      lbf = max(lbf, c + R[k * B] - pj[k] + C2[k * B]);
-    }
-    c = 0;
-    int lbb = 0;
-    for (int k = m - 1; k >= 0; --k) {
-      c = max(c, C2[k * B]) + pj[k];
-      lbb = max(lbb, C1[k * B] + R[k * B] - pj[k] + c);
-    }
-    lbrow[q] = lbf;
-    lbrow[n + q] = lbb;
-    prow[q] = lbf >= ub;
-    prow[n + q] = lbb >= ub;
-    mm.add(lbf, false);
-    mm.add(lbb, true);
-  }
-  for (int q = r; q < n; ++q) {
-    lbrow[q] = kInt32Max;
-    lbrow[n + q] = kInt32Max;
-    prow[q] = 1;
-    prow[n + q] = 1;
-  }
-  if (pool.dir) pool.dir[i] = (uint8_t)mm.dir();
+  const DevInst I = insts[lo];
+  int *C1 = sh + t;
+  lb1_row(I, I.p, C1, C1 + mmax * B, C1 + 2 * mmax * B, B, perm + (size_t)i * stride, d1[i],
+          d2[i], stride, ubs[lo], write_out ? out_lb + (size_t)i * 2 * stride : nullptr,
+          write_out ? out_prune + (size_t)i * 2 * stride : nullptr, nullptr,
+          write_out ? dir + i : nullptr, costs ? costs + (size_t)i * 3 * mmax : nullptr,
+          write_out, flag);
 }
 
 // ------------------------------------------------------------------------ LB2
@@ -212,20 +254,21 @@ k_lb2(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__res
   const int count = pool.count_dev ? *pool.count_dev : pool.count;
   if (pool.ub_dev) ub = *pool.ub_dev;
 
+  const int ns = pool.n;  // row stride of the pool and the outputs (>= n)
   for (int par = blockIdx.x * nw + w; par < count; par += gridDim.x * nw) {
     const int a = pool.d1[par], b = pool.d2[par], r = n - a - b;
-    int *lbrow = out_lb + (size_t)par * 2 * n;
-    uint8_t *prow = out_prune + (size_t)par * 2 * n;
-    int16_t *arow = LOG ? pool.argpair + (size_t)par * 2 * n : nullptr;
+    int *lbrow = out_lb + (size_t)par * 2 * ns;
+    uint8_t *prow = out_prune + (size_t)par * 2 * ns;
+    int16_t *arow = LOG ? pool.argpair + (size_t)par * 2 * ns : nullptr;
     // rows that are not valid nodes were flagged by k_lb1 (a front value is
     // never negative otherwise): every slot gets INT32_MAX / prune 1
     if (r < 1 || costs[(size_t)par * 3 * m] < 0) {
-      fill_invalid(lbrow, prow, arow, n, 0, lane, 64);
+      fill_invalid(lbrow, prow, arow, ns, 0, lane, 64);
       if (pool.dir && lane == 0) pool.dir[par] = 0;
       continue;
     }
     for (int x = lane; x < n; x += 64) {
-      jobs[x] = pool.perm[(size_t)par * n + x];
+      jobs[x] = pool.perm[(size_t)par * ns + x];
       slot[x] = -1;
     }
     for (int x = lane; x < m; x += 64) {
@@ -344,7 +387,7 @@ k_lb2(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__res
       const bool bwd = lane >= 32;
       const int val = mine ? max(lb1, acc[0]) : kInt32Max;
       if (mine) {
-        const int o = (bwd ? n : 0) + cb + ql;
+        const int o = (bwd ? ns : 0) + cb + ql;
         lbrow[o] = val;
         prow[o] = val >= ub;
         if (LOG) arow[o] = (int16_t)(acc[0] > kNeg ? arg[0] : -1);
@@ -358,7 +401,7 @@ k_lb2(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__res
       mm.merge(cmn, ccf, ccb, csf, csb);
       wave_sync();
     }
-    fill_invalid(lbrow, prow, arow, n, r, lane, 64);
+    fill_invalid(lbrow, prow, arow, ns, r, lane, 64);
     if (pool.dir && lane == 0) pool.dir[par] = (uint8_t)mm.dir();
   }
 }
@@ -382,257 +425,350 @@ struct MaskT {
   }
 };
 
+// LDS layout of the fast LB2 kernels for a class of instances with at most
+// NMAX jobs, mmax machines and ppad padded pairs.
+struct FastLayout {
+  int ppad, nmax_jobs, mmax;
+  __host__ __device__ size_t block_bytes(int nmax) const {
+    return align16((size_t)nmax * ppad * 8) + align16((size_t)ppad * 4) +
+           align16((size_t)nmax_jobs * mmax * 4);
+  }
+  __host__ __device__ size_t wave_bytes(int nmax) const {
+    const int xr = nmax < 32 ? nmax : 32;
+    return align16((size_t)nmax * 64 * 8) + align16((size_t)xr * mmax * 8) +
+           align16((size_t)3 * mmax * 4) + align16((size_t)nmax * 4);
+  }
+};
+
+template <int NMAX>
+struct FastLds {
+  uint2 *ent;  // [NMAX][Ppad] padded pair entries
+  int *uv;     // [Ppad] u | v << 8
+  int *sp;     // p[n][m]
+  int2 *X;     // per wave [NMAX][64]: per job, per lane
+  int2 *FB;    // per wave [32][m]: (forward child front - p, backward child back - p)
+  int *c1, *c2, *rr, *jobs;
+  __device__ FastLds(unsigned char *sm, const FastLayout &L, int w) {
+    ent = (uint2 *)sm;
+    size_t off = align16((size_t)NMAX * L.ppad * 8);
+    uv = (int *)(sm + off);
+    off += align16((size_t)L.ppad * 4);
+    sp = (int *)(sm + off);
+    off += align16((size_t)L.nmax_jobs * L.mmax * 4);
+    unsigned char *wb = sm + off + (size_t)w * L.wave_bytes(NMAX);
+    const int xr = NMAX < 32 ? NMAX : 32;
+    X = (int2 *)wb;
+    wb += align16((size_t)NMAX * 64 * 8);
+    FB = (int2 *)wb;
+    wb += align16((size_t)xr * L.mmax * 8);
+    c1 = (int *)wb;
+    c2 = c1 + L.mmax;
+    rr = c2 + L.mmax;
+    wb += align16((size_t)3 * L.mmax * 4);
+    jobs = (int *)wb;
+  }
+};
+
+// Block-cooperative staging of one instance: rows >= n and pairs >= P of the
+// padded table hold a job id that is never a member (NMAX - 1 >= n whenever
+// such rows exist) and zero times.  No barrier inside.
+template <int NMAX>
+__device__ void lb2f_stage(const DevInst &I, int Ppad, const FastLds<NMAX> &S) {
+  const int n = I.n, m = I.m, P = I.P;
+  const unsigned kpad = (unsigned)(NMAX - 1) << 24;
+  for (int x = threadIdx.x; x < NMAX * Ppad; x += blockDim.x) {
+    const int i = x / Ppad, pi = x - i * Ppad;
+    S.ent[x] = (i < n && pi < P) ? I.ent[(size_t)i * P + pi] : make_uint2(0u, kpad);
+  }
+  for (int x = threadIdx.x; x < Ppad; x += blockDim.x)
+    S.uv[x] = x < P ? ((int)I.pu[x] | ((int)I.pv[x] << 8)) : 0;
+  for (int x = threadIdx.x; x < n * m; x += blockDim.x) S.sp[x] = I.p[x];
+}
+
+// One wave decomposes one parent (see k_lb2 for the method).  row: the
+// parent's perm; cs: its (C1, C2, R); outputs lbrow/prow/arow hold 2 * stride
+// slots (stride >= n; slots q >= n - d1 - d2 get INT32_MAX / prune 1).
 template <int NMAX, bool SUBSET, bool LOG>
-__global__ void __launch_bounds__(512)
-k_lb2f(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__restrict__ out_lb,
-       uint8_t *__restrict__ out_prune, int Ppad) {
-  extern __shared__ __align__(16) unsigned char sm[];
+__device__ void lb2f_parent(const DevInst &I, int Ppad, const FastLds<NMAX> &S,
+                            const uint8_t *__restrict__ row, int a, int b,
+                            const int *__restrict__ cs, const uint32_t *__restrict__ mw,
+                            int stride, int ub, int *__restrict__ lbrow,
+                            uint8_t *__restrict__ prow, int16_t *__restrict__ arow,
+                            uint8_t *__restrict__ dirp, int lane) {
   using M = MaskT<NMAX>;
   using MT = typename M::T;
   // pair entries stay in registers between the two scans when they fit
   constexpr bool KEEP = NMAX <= 20 && !LOG && !SUBSET;
   constexpr bool PMB_REG = NMAX <= 24 && !LOG;
   const int n = I.n, m = I.m, P = I.P;
-  const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int xr = NMAX < 32 ? NMAX : 32;
-  uint2 *ent = (uint2 *)sm;  // [NMAX][Ppad]
-  size_t off = align16((size_t)NMAX * Ppad * 8);
-  int *uv = (int *)(sm + off);  // [Ppad]: u | v << 8
-  off += align16((size_t)Ppad * 4);
-  int *sp = (int *)(sm + off);  // p[n][m]
-  off += align16((size_t)n * m * 4);
-  const size_t per_wave = align16((size_t)NMAX * 64 * 8) + align16((size_t)xr * m * 8) +
-                          align16((size_t)3 * m * 4) + align16((size_t)NMAX * 4);
-  unsigned char *wb = sm + off + w * per_wave;
-  int2 *X = (int2 *)wb;  // [NMAX][64]: per job, per lane
-  wb += align16((size_t)NMAX * 64 * 8);
-  int2 *FB = (int2 *)wb;  // [xr][m]
-  wb += align16((size_t)xr * m * 8);
-  int *c1 = (int *)wb, *c2 = c1 + m, *rr = c2 + m;
-  wb += align16((size_t)3 * m * 4);
-  int *jobs = (int *)wb;  // [NMAX]
-
-  // stage the padded pair table: rows >= n and pairs >= P hold a job id that
-  // is never a member (NMAX - 1 >= n whenever such rows exist) and zero times
-  const unsigned kpad = (unsigned)(NMAX - 1) << 24;
-  for (int x = threadIdx.x; x < NMAX * Ppad; x += blockDim.x) {
-    const int i = x / Ppad, pi = x - i * Ppad;
-    ent[x] = (i < n && pi < P) ? I.ent[(size_t)i * P + pi] : make_uint2(0u, kpad);
+  const int r = n - a - b;
+  if (r < 1 || cs[0] < 0) {  // flagged by k_lb1: not a valid node
+    fill_invalid(lbrow, prow, arow, stride, 0, lane, 64);
+    if (dirp && lane == 0) *dirp = 0;
+    return;
   }
-  for (int x = threadIdx.x; x < Ppad; x += blockDim.x)
-    uv[x] = x < P ? ((int)I.pu[x] | ((int)I.pv[x] << 8)) : 0;
-  for (int x = threadIdx.x; x < n * m; x += blockDim.x) sp[x] = I.p[x];
+  const uint2 *ent = S.ent;
+  int2 *X = S.X, *FB = S.FB;
+  int *c1 = S.c1, *c2 = S.c2, *rr = S.rr, *jobs = S.jobs;
+  const int *sp = S.sp;
+  const int *uv = S.uv;
+  MT bits = 0;
+  for (int x = lane; x < n; x += 64) {
+    const int j = row[x];
+    jobs[x] = j;
+    if (x >= a && x < a + r) bits |= (MT)1 << j;
+  }
+  for (int x = lane; x < m; x += 64) {
+    c1[x] = cs[x];
+    c2[x] = cs[m + x];
+    rr[x] = cs[2 * m + x];
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) bits |= __shfl_xor(bits, o, kWave);
+  MT umask;
+  if constexpr (NMAX <= 32) {
+    umask = (MT)__builtin_amdgcn_readfirstlane((int)bits);
+  } else {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)bits);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((int)(uint32_t)(bits >> 32));
+    umask = ((MT)hi << 32) | lo;
+  }
+  wave_sync();
+  // number of selected pairs of this parent (subset bounds)
+  int nsel = 0;
+  if constexpr (SUBSET) {
+    const int words = (P + 31) >> 5;
+    for (int w = lane; w < words; w += 64)
+      nsel += __popc(mw[w] & (w == words - 1 && (P & 31) ? (1u << (P & 31)) - 1u : 0xffffffffu));
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) nsel += __shfl_xor(nsel, o, kWave);
+    nsel = __builtin_amdgcn_readfirstlane(nsel);
+  }
+  MinMin mm;
+  mm.init();
+  for (int cb = 0; cb < r; cb += 32) {
+    const int nq = min(32, r - cb);
+    int lb1 = kNeg;
+    const int ql = lane & 31;
+    const int myjob = ql < nq ? jobs[a + cb + ql] : 0;
+    if (ql < nq) {
+      const int *pj = sp + myjob * m;
+      int c = 0, l = 0;
+      if (lane < 32) {
+        for (int k = 0; k < m; ++k) {
+          c = max(c, c1[k]) + pj[k];
+          FB[ql * m + k].x = c - pj[k];
+          l = max(l, c + rr[k] - pj[k] + c2[k]);
+        }
+      } else {
+        for (int k = m - 1; k >= 0; --k) {
+          c = max(c, c2[k]) + pj[k];
+          FB[ql * m + k].y = c - pj[k];
+          l = max(l, c1[k] + rr[k] - pj[k] + c);
+        }
+      }
+      lb1 = l;
+    }
+    wave_sync();
+    int acc[64];
+    int arg[LOG ? 64 : 1];
+#pragma unroll
+    for (int q = 0; q < 64; ++q) acc[q] = kNeg;
+    if constexpr (LOG) {
+#pragma unroll
+      for (int q = 0; q < 64; ++q) arg[q] = 0x7fffffff;
+    }
+    // subset bounds: lane l of pass pc takes the (pc + l)-th selected pair, so
+    // k selected pairs need ceil(k / 64) passes instead of ceil(P / 64)
+    const int npass = SUBSET ? nsel : Ppad;
+    for (int pc = 0; pc < npass; pc += 64) {
+      int pi = pc + lane;
+      bool act = pi < P;
+      if constexpr (SUBSET) {
+        act = pi < nsel;
+        int sidx = pi;
+        pi = Ppad - 1;  // a padded pair for idle lanes
+        if (act) {
+          const int words = (P + 31) >> 5;
+          for (int w = 0; w < words; ++w) {
+            uint32_t wbits = mw[w];
+            if (w == words - 1 && (P & 31)) wbits &= (1u << (P & 31)) - 1u;  // pairs >= P
+            const int cnt = __popc(wbits);
+            if (sidx < cnt) {
+              for (int t = 0; t < sidx; ++t) wbits &= wbits - 1u;
+              pi = w * 32 + __ffs(wbits) - 1;
+              break;
+            }
+            sidx -= cnt;
+          }
+        }
+      }
+      const int uvp = uv[pi];
+      const int u = uvp & 0xff, v = uvp >> 8;
+      const int RU = rr[u], RV = rr[v], C1u = c1[u], C1v = c1[v], C2u = c2[u], C2v = c2[v];
+      uint2 e[KEEP ? NMAX : 1];
+      if constexpr (KEEP) {
+#pragma unroll
+        for (int i = 0; i < NMAX; ++i) e[i] = ent[i * Ppad + pi];
+      }
+      // forward scan: exclusive prefix maxima of term - B(U), minus b (kept in
+      // registers when they fit, else in the lane's X column)
+      int pmb[PMB_REG ? NMAX : 1];
+      int Y = 0, Pm = kNeg;
+#pragma unroll
+      for (int i = 0; i < NMAX; ++i) {
+        const uint2 ei = KEEP ? e[KEEP ? i : 0] : ent[i * Ppad + pi];
+        const int ea = (int)(ei.x & 0xffffu), eb = (int)(ei.x >> 16);
+        const int el = (int)(ei.y & 0xffffffu), ek = (int)(ei.y >> 24);
+        const int ng = M::neg(umask, ek);
+        Y += ea & ng;
+        const int tt = Y + el;
+        if constexpr (PMB_REG)
+          pmb[PMB_REG ? i : 0] = Pm - eb;
+        else
+          X[ek * 64 + lane].x = Pm - eb;
+        Pm = max(Pm, ng ? tt : kNeg);
+        Y -= eb & ng;
+      }
+      // backward scan: exclusive suffix maxima; X(j) = max(PM - b, SM - a)
+      const int c0 = RU - RV;
+      int Wb = 0, Sm = kNeg;
+#pragma unroll
+      for (int i = NMAX - 1; i >= 0; --i) {
+        const uint2 ei = KEEP ? e[KEEP ? i : 0] : ent[i * Ppad + pi];
+        const int ea = (int)(ei.x & 0xffffu), eb = (int)(ei.x >> 16);
+        const int el = (int)(ei.y & 0xffffffu), ek = (int)(ei.y >> 24);
+        const int ng = M::neg(umask, ek);
+        Wb += eb & ng;
+        const int tp = Wb + el + c0;
+        const int pm = PMB_REG ? pmb[PMB_REG ? i : 0] : X[ek * 64 + lane].x;
+        const int x = max(pm, Sm - ea);
+        X[ek * 64 + lane] = make_int2(x + ea, x + eb);
+        Sm = max(Sm, ng ? tp : kNeg);
+        Wb -= ea & ng;
+      }
+      const int K1 = RU + C2u, K2 = C1u + RU, K3 = C1v + RV;
+#pragma unroll
+      for (int q = 0; q < 32; ++q) {
+        if (q < nq) {
+          const int kq = __builtin_amdgcn_readlane(myjob, q);
+          const int2 xab = X[kq * 64 + lane];
+          const int2 fu = FB[q * m + u], fv = FB[q * m + v];
+          const int xa = xab.x + RV, xb = xab.y + RV;
+          int lbf = max(fu.x + K1, max(fv.x + RV, fu.x + xa) + C2v);
+          int lbb = max(fu.y + K2, max(K3, C1u + xb) + fv.y);
+          lbf = act ? lbf : kNeg;
+          lbb = act ? lbb : kNeg;
+          if constexpr (LOG) {
+            if (lbf > acc[q]) { acc[q] = lbf; arg[q] = pi; }
+            if (lbb > acc[32 + q]) { acc[32 + q] = lbb; arg[32 + q] = pi; }
+          } else {
+            acc[q] = max(acc[q], lbf);
+            acc[32 + q] = max(acc[32 + q], lbb);
+          }
+        }
+      }
+    }
+    if constexpr (LOG) {
+      transpose_argmax64(acc, arg, lane);
+    } else {
+      transpose_max64(acc, lane);
+    }
+    const bool mine = ql < nq;
+    const bool bwd = lane >= 32;
+    const int val = mine ? max(lb1, acc[0]) : kInt32Max;
+    if (mine) {
+      const int o = (bwd ? stride : 0) + cb + ql;
+      lbrow[o] = val;
+      prow[o] = val >= ub;
+      if constexpr (LOG) arow[o] = (int16_t)(acc[0] > kNeg ? arg[0] : -1);
+    }
+    const int cmn = wave_min(val);
+    const int ccf = wave_popc(mine && !bwd && val == cmn);
+    const int ccb = wave_popc(mine && bwd && val == cmn);
+    const long long csf = wave_sum64(mine && !bwd ? (long long)val : 0);
+    const long long csb = wave_sum64(mine && bwd ? (long long)val : 0);
+    mm.merge(cmn, ccf, ccb, csf, csb);
+    wave_sync();
+  }
+  fill_invalid(lbrow, prow, arow, stride, r, lane, 64);
+  if (dirp && lane == 0) *dirp = (uint8_t)mm.dir();
+}
+
+// Single instance: the block stages the tables once, then each wave takes
+// parents in a grid-stride loop.
+template <int NMAX, bool SUBSET, bool LOG>
+__global__ void __launch_bounds__(512)
+k_lb2f(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__restrict__ out_lb,
+       uint8_t *__restrict__ out_prune, int Ppad) {
+  extern __shared__ __align__(16) unsigned char sm[];
+  const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const FastLayout L{Ppad, I.n, I.m};
+  const FastLds<NMAX> S(sm, L, w);
+  lb2f_stage<NMAX>(I, Ppad, S);
   __syncthreads();
   const int count = pool.count_dev ? *pool.count_dev : pool.count;
   if (pool.ub_dev) ub = *pool.ub_dev;
-
+  const int m = I.m;
   for (int par = blockIdx.x * nw + w; par < count; par += gridDim.x * nw) {
-    const int a = pool.d1[par], b = pool.d2[par], r = n - a - b;
-    int *lbrow = out_lb + (size_t)par * 2 * n;
-    uint8_t *prow = out_prune + (size_t)par * 2 * n;
-    int16_t *arow = LOG ? pool.argpair + (size_t)par * 2 * n : nullptr;
-    if (r < 1 || costs[(size_t)par * 3 * m] < 0) {  // flagged by k_lb1: not a valid node
-      fill_invalid(lbrow, prow, arow, n, 0, lane, 64);
-      if (pool.dir && lane == 0) pool.dir[par] = 0;
-      continue;
+    const int ns = pool.n;  // row stride (>= n)
+    lb2f_parent<NMAX, SUBSET, LOG>(
+        I, Ppad, S, pool.perm + (size_t)par * ns, pool.d1[par], pool.d2[par],
+        costs + (size_t)par * 3 * m,
+        SUBSET ? pool.mask + (size_t)par * pool.mask_words : nullptr, ns, ub,
+        out_lb + (size_t)par * 2 * ns, out_prune + (size_t)par * 2 * ns,
+        LOG ? pool.argpair + (size_t)par * 2 * ns : nullptr, pool.dir ? pool.dir + par : nullptr,
+        lane);
+  }
+}
+
+// Several instances in one persistent launch.  Work is a list of tiles (an
+// instance and a range of its parents, tiles grouped by instance); each block
+// takes tiles from a device counter, restages the LDS tables when the
+// instance changes, and its waves decompose the tile's parents.  Pool rows
+// and outputs use a common stride (the largest n); costs use stride 3 * mmax.
+template <int NMAX>
+__global__ void __launch_bounds__(512)
+k_lb2m(const DevInst *__restrict__ insts, const MultiTile *__restrict__ tiles, int ntiles,
+       int *__restrict__ queue, FastLayout L, const uint8_t *__restrict__ perm,
+       const uint8_t *__restrict__ d1, const uint8_t *__restrict__ d2, int stride,
+       const int *__restrict__ ubs, const int *__restrict__ costs, int *__restrict__ out_lb,
+       uint8_t *__restrict__ out_prune, uint8_t *__restrict__ dir) {
+  extern __shared__ __align__(16) unsigned char sm[];
+  __shared__ int s_tile;
+  const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const FastLds<NMAX> S(sm, L, w);
+  int cur = -1, Ppad = 0;
+  DevInst I{};
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = atomicAdd(queue, 1);
+    __syncthreads();
+    const int t = s_tile;
+    __syncthreads();  // every thread has read s_tile before it is overwritten
+    if (t >= ntiles) break;
+    const MultiTile T = tiles[t];
+    if (T.inst != cur) {
+      cur = T.inst;
+      I = insts[cur];
+      Ppad = (I.P + 63) / 64 * 64;
+      lb2f_stage<NMAX>(I, Ppad, S);
+      __syncthreads();
     }
-    MT bits = 0;
-    for (int x = lane; x < n; x += 64) {
-      const int j = pool.perm[(size_t)par * n + x];
-      jobs[x] = j;
-      if (x >= a && x < a + r) bits |= (MT)1 << j;
+    const int ub = ubs[cur];
+    for (int par = T.begin + w; par < T.end; par += nw) {
+      lb2f_parent<NMAX, false, false>(
+          I, Ppad, S, perm + (size_t)par * stride, d1[par], d2[par],
+          costs + (size_t)par * 3 * L.mmax, nullptr, stride, ub,
+          out_lb + (size_t)par * 2 * stride, out_prune + (size_t)par * 2 * stride, nullptr,
+          dir + par, lane);
     }
-    for (int x = lane; x < m; x += 64) {
-      const int *cs = costs + (size_t)par * 3 * m;
-      c1[x] = cs[x];
-      c2[x] = cs[m + x];
-      rr[x] = cs[2 * m + x];
-    }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) bits |= __shfl_xor(bits, o, kWave);
-    MT umask;
-    if constexpr (NMAX <= 32) {
-      umask = (MT)__builtin_amdgcn_readfirstlane((int)bits);
-    } else {
-      const uint32_t lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)bits);
-      const uint32_t hi = __builtin_amdgcn_readfirstlane((int)(uint32_t)(bits >> 32));
-      umask = ((MT)hi << 32) | lo;
-    }
-    wave_sync();
-    // number of selected pairs of this parent (subset bounds)
-    int nsel = 0;
-    if constexpr (SUBSET) {
-      const int words = (P + 31) >> 5;
-      const uint32_t *mw = pool.mask + (size_t)par * pool.mask_words;
-      for (int w = lane; w < words; w += 64) nsel += __popc(mw[w] & (w == words - 1 && (P & 31)
-                                                                ? (1u << (P & 31)) - 1u
-                                                                : 0xffffffffu));
-#pragma unroll
-      for (int o = 32; o >= 1; o >>= 1) nsel += __shfl_xor(nsel, o, kWave);
-      nsel = __builtin_amdgcn_readfirstlane(nsel);
-    }
-    MinMin mm;
-    mm.init();
-    for (int cb = 0; cb < r; cb += 32) {
-      const int nq = min(32, r - cb);
-      int lb1 = kNeg;
-      const int ql = lane & 31;
-      const int myjob = ql < nq ? jobs[a + cb + ql] : 0;
-      if (ql < nq) {
-        const int *pj = sp + myjob * m;
-        int c = 0, l = 0;
-        if (lane < 32) {
-          for (int k = 0; k < m; ++k) {
-            c = max(c, c1[k]) + pj[k];
-            FB[ql * m + k].x = c - pj[k];
-            l = max(l, c + rr[k] - pj[k] + c2[k]);
-          }
-        } else {
-          for (int k = m - 1; k >= 0; --k) {
-            c = max(c, c2[k]) + pj[k];
-            FB[ql * m + k].y = c - pj[k];
-            l = max(l, c1[k] + rr[k] - pj[k] + c);
-          }
-        }
-        lb1 = l;
-      }
-      wave_sync();
-      int acc[64];
-      int arg[LOG ? 64 : 1];
-#pragma unroll
-      for (int q = 0; q < 64; ++q) acc[q] = kNeg;
-      if constexpr (LOG) {
-#pragma unroll
-        for (int q = 0; q < 64; ++q) arg[q] = 0x7fffffff;
-      }
-      // subset bounds: lane l of pass pc takes the (pc + l)-th selected pair, so
-      // k selected pairs need ceil(k / 64) passes instead of ceil(P / 64)
-      const int npass = SUBSET ? nsel : Ppad;
-      for (int pc = 0; pc < npass; pc += 64) {
-        int pi = pc + lane;
-        bool act = pi < P;
-        if constexpr (SUBSET) {
-          act = pi < nsel;
-          int sidx = pi;
-          pi = Ppad - 1;  // a padded pair for idle lanes
-          if (act) {
-            const int words = (P + 31) >> 5;
-            const uint32_t *mw = pool.mask + (size_t)par * pool.mask_words;
-            for (int w = 0; w < words; ++w) {
-              uint32_t bits = mw[w];
-              if (w == words - 1 && (P & 31)) bits &= (1u << (P & 31)) - 1u;  // pairs >= P
-              const int cnt = __popc(bits);
-              if (sidx < cnt) {
-                for (int t = 0; t < sidx; ++t) bits &= bits - 1u;
-                pi = w * 32 + __ffs(bits) - 1;
-                break;
-              }
-              sidx -= cnt;
-            }
-          }
-        }
-        const int uvp = uv[pi];
-        const int u = uvp & 0xff, v = uvp >> 8;
-        const int RU = rr[u], RV = rr[v], C1u = c1[u], C1v = c1[v], C2u = c2[u], C2v = c2[v];
-        uint2 e[KEEP ? NMAX : 1];
-        if constexpr (KEEP) {
-#pragma unroll
-          for (int i = 0; i < NMAX; ++i) e[i] = ent[i * Ppad + pi];
-        }
-        // forward scan: exclusive prefix maxima of term - B(U), minus b (kept in
-        // registers when they fit, else in the lane's X column)
-        int pmb[PMB_REG ? NMAX : 1];
-        int Y = 0, Pm = kNeg;
-#pragma unroll
-        for (int i = 0; i < NMAX; ++i) {
-          const uint2 ei = KEEP ? e[KEEP ? i : 0] : ent[i * Ppad + pi];
-          const int ea = (int)(ei.x & 0xffffu), eb = (int)(ei.x >> 16);
-          const int el = (int)(ei.y & 0xffffffu), ek = (int)(ei.y >> 24);
-          const int ng = M::neg(umask, ek);
-          Y += ea & ng;
-          const int tt = Y + el;
-          if constexpr (PMB_REG)
-            pmb[PMB_REG ? i : 0] = Pm - eb;
-          else
-            X[ek * 64 + lane].x = Pm - eb;
-          Pm = max(Pm, ng ? tt : kNeg);
-          Y -= eb & ng;
-        }
-        // backward scan: exclusive suffix maxima; X(j) = max(PM - b, SM - a)
-        const int c0 = RU - RV;
-        int Wb = 0, Sm = kNeg;
-#pragma unroll
-        for (int i = NMAX - 1; i >= 0; --i) {
-          const uint2 ei = KEEP ? e[KEEP ? i : 0] : ent[i * Ppad + pi];
-          const int ea = (int)(ei.x & 0xffffu), eb = (int)(ei.x >> 16);
-          const int el = (int)(ei.y & 0xffffffu), ek = (int)(ei.y >> 24);
-          const int ng = M::neg(umask, ek);
-          Wb += eb & ng;
-          const int tp = Wb + el + c0;
-          const int pm = PMB_REG ? pmb[PMB_REG ? i : 0] : X[ek * 64 + lane].x;
-          const int x = max(pm, Sm - ea);
-          X[ek * 64 + lane] = make_int2(x + ea, x + eb);
-          Sm = max(Sm, ng ? tp : kNeg);
-          Wb -= ea & ng;
-        }
-        const int K1 = RU + C2u, K2 = C1u + RU, K3 = C1v + RV;
-#pragma unroll
-        for (int q = 0; q < 32; ++q) {
-          if (q < nq) {
-            const int kq = __builtin_amdgcn_readlane(myjob, q);
-            const int2 xab = X[kq * 64 + lane];
-            const int2 fu = FB[q * m + u], fv = FB[q * m + v];
-            const int xa = xab.x + RV, xb = xab.y + RV;
-            int lbf = max(fu.x + K1, max(fv.x + RV, fu.x + xa) + C2v);
-            int lbb = max(fu.y + K2, max(K3, C1u + xb) + fv.y);
-            lbf = act ? lbf : kNeg;
-            lbb = act ? lbb : kNeg;
-            if constexpr (LOG) {
-              if (lbf > acc[q]) { acc[q] = lbf; arg[q] = pi; }
-              if (lbb > acc[32 + q]) { acc[32 + q] = lbb; arg[32 + q] = pi; }
-            } else {
-              acc[q] = max(acc[q], lbf);
-              acc[32 + q] = max(acc[32 + q], lbb);
-            }
-          }
-        }
-      }
-      if constexpr (LOG) {
-        transpose_argmax64(acc, arg, lane);
-      } else {
-        transpose_max64(acc, lane);
-      }
-      const bool mine = ql < nq;
-      const bool bwd = lane >= 32;
-      const int val = mine ? max(lb1, acc[0]) : kInt32Max;
-      if (mine) {
-        const int o = (bwd ? n : 0) + cb + ql;
-        lbrow[o] = val;
-        prow[o] = val >= ub;
-        if constexpr (LOG) arow[o] = (int16_t)(acc[0] > kNeg ? arg[0] : -1);
-      }
-      const int cmn = wave_min(val);
-      const int ccf = wave_popc(mine && !bwd && val == cmn);
-      const int ccb = wave_popc(mine && bwd && val == cmn);
-      const long long csf = wave_sum64(mine && !bwd ? (long long)val : 0);
-      const long long csb = wave_sum64(mine && bwd ? (long long)val : 0);
-      mm.merge(cmn, ccf, ccb, csf, csb);
-      wave_sync();
-    }
-    fill_invalid(lbrow, prow, arow, n, r, lane, 64);
-    if (pool.dir && lane == 0) pool.dir[par] = (uint8_t)mm.dir();
+    __syncthreads();  // the tables may be restaged for the next tile
   }
 }
 
 static size_t lb2f_lds(const Ctx *c, int nmax, int waves) {
-  const int m = c->m, n = c->n;
-  const int Ppad = (c->P + 63) / 64 * 64;
-  const int xr = nmax < 32 ? nmax : 32;
-  size_t s = align16((size_t)nmax * Ppad * 8) + align16((size_t)Ppad * 4) +
-             align16((size_t)n * m * 4);
-  const size_t pw = align16((size_t)nmax * 64 * 8) + align16((size_t)xr * m * 8) +
-                    align16((size_t)3 * m * 4) + align16((size_t)nmax * 4);
-  return s + waves * pw;
+  const FastLayout L{(c->P + 63) / 64 * 64, c->n, c->m};
+  return L.block_bytes(nmax) + (size_t)waves * L.wave_bytes(nmax);
 }
 
 template <int NMAX>
@@ -664,6 +800,8 @@ static int fast_nmax(int n) {
   return 0;
 }
 
+__global__ void k_zero(int *p) { *p = 0; }
+
 // -------------------------------------------------------------------- host
 int ensure_costs(Ctx *c, int count) {
   const size_t need = (size_t)(count > 0 ? count : 1) * 3 * c->m;
@@ -684,14 +822,18 @@ int ensure_costs(Ctx *c, int count) {
   return PFSP_OK;
 }
 
-static size_t lb2_lds(const Ctx *c, int waves, bool ent_lds, int xrows) {
-  const int n = c->n, m = c->m, P = c->P;
-  const size_t esz = c->narrow ? 8 : 16;
+static size_t lb2_lds_inst(int n, int m, int P, int narrow, int waves, bool ent_lds,
+                           int xrows) {
+  const size_t esz = narrow ? 8 : 16;
   size_t s = ent_lds ? align16((size_t)n * P * esz) : 0;
   s += align16((size_t)n * m * 4);
   const size_t pw = align16((size_t)xrows * 64 * 8) + align16((size_t)xrows * m * 8) +
                     align16((size_t)3 * m * 4) + align16((size_t)2 * n * 4);
   return s + waves * pw;
+}
+
+static size_t lb2_lds(const Ctx *c, int waves, bool ent_lds, int xrows) {
+  return lb2_lds_inst(c->n, c->m, c->P, c->narrow, waves, ent_lds, xrows);
 }
 
 size_t lb2_lds_bytes(const Ctx *c, int waves) {
@@ -748,7 +890,56 @@ static void attr_lb2f() {
                             hipFuncAttributeMaxDynamicSharedMemorySize, mx);
 }
 
+size_t lb2m_lds_bytes(int nmax, int ppad, int nmax_jobs, int mmax, int waves) {
+  const FastLayout L{ppad, nmax_jobs, mmax};
+  return L.block_bytes(nmax) + (size_t)waves * L.wave_bytes(nmax);
+}
+
+int launch_lb1m(Ctx *c, const DevInst *insts, const long long *seg, int ninst, long long total,
+                const uint8_t *perm, const uint8_t *d1, const uint8_t *d2, int stride, int mmax,
+                const int *ubs, int *out_lb, uint8_t *out_prune, uint8_t *dir, int *costs,
+                int write_out, hipStream_t s) {
+  if (total <= 0) return PFSP_OK;
+  const int B = 128;
+  const size_t lds = (size_t)3 * mmax * B * 4;
+  KTimer kt(c, s, "k_lb1m");
+  hipLaunchKernelGGL(k_lb1m, dim3((unsigned)((total + B - 1) / B)), dim3(B), lds, s, insts, seg,
+                     ninst, perm, d1, d2, stride, mmax, ubs, out_lb, out_prune, dir, costs,
+                     write_out, c->d_flag);
+  PFSP_HIP(c, hipGetLastError());
+  return PFSP_OK;
+}
+
+int launch_lb2m(Ctx *c, const FastClassLaunch &L, const DevInst *insts, const uint8_t *perm,
+                const uint8_t *d1, const uint8_t *d2, int stride, const int *ubs,
+                const int *costs, int *out_lb, uint8_t *out_prune, uint8_t *dir, hipStream_t s) {
+  if (L.ntiles <= 0) return PFSP_OK;
+  const FastLayout FL{L.ppad, L.nmax_jobs, L.mmax};
+  const size_t lds = FL.block_bytes(L.nmax) + (size_t)L.waves * FL.wave_bytes(L.nmax);
+  if (lds > 160 * 1024) return set_err(c, PFSP_ERANGE, "multi-instance class exceeds LDS");
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(1), 0, s, L.queue);
+  KTimer kt(c, s, "k_lb2m");
+  if (L.nmax == 20)
+    hipLaunchKernelGGL(k_lb2m<20>, dim3(L.grid), dim3(64 * L.waves), lds, s, insts, L.tiles,
+                       L.ntiles, L.queue, FL, perm, d1, d2, stride, ubs, costs, out_lb, out_prune,
+                       dir);
+  else if (L.nmax == 64)
+    hipLaunchKernelGGL(k_lb2m<64>, dim3(L.grid), dim3(64 * L.waves), lds, s, insts, L.tiles,
+                       L.ntiles, L.queue, FL, perm, d1, d2, stride, ubs, costs, out_lb, out_prune,
+                       dir);
+  else
+    return set_err(c, PFSP_EINVAL, "no multi-instance kernel for this class");
+  PFSP_HIP(c, hipGetLastError());
+  return PFSP_OK;
+}
+
 void init_bound_attributes() {
+  (void)hipFuncSetAttribute((const void *)k_lb1m, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+  (void)hipFuncSetAttribute((const void *)k_lb2m<20>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+  (void)hipFuncSetAttribute((const void *)k_lb2m<64>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
   (void)hipFuncSetAttribute((const void *)k_lb1, hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024);
   attr_lb2<Narrow, true>();
@@ -834,7 +1025,7 @@ int launch_bound_costs_ready(Ctx *c, const DevPool &pool, int kind, int ub, int 
     if (waves) {
       const int Ppad = (c->P + 63) / 64 * 64;
       int grid = (pool.count + waves - 1) / waves;
-      const int cap = c->cu_count * 16;
+      const int cap = c->cu_count * (int)(c->lb2_blocks_per_cu > 0 ? c->lb2_blocks_per_cu : 16);
       if (grid > cap) grid = cap;
       const dim3 g(grid), bl(64 * waves);
       KTimer kt(c, s, "k_lb2");
@@ -879,6 +1070,54 @@ int launch_bound_costs_ready(Ctx *c, const DevPool &pool, int kind, int ub, int 
                                out_prune, xrows);
     else
       launch_lb2_e<Wide, false>(subset, log, g, bl, lds, s, I, pool, ub, c->d_costs, out_lb,
+                                out_prune, xrows);
+  }
+  PFSP_HIP(c, hipGetLastError());
+  return PFSP_OK;
+}
+
+// Generic kernels (any n, wide entries) on one staged instance that need not
+// be the context's: costs into `costs` (stride 3 * I.m), then k_lb2.
+int launch_generic_instance(Ctx *c, const DevInst &I, const DevPool &pool, int ub, int *costs,
+                            int *out_lb, uint8_t *out_prune, hipStream_t s) {
+  if (pool.count <= 0) return PFSP_OK;
+  const int n = I.n, m = I.m;
+  int b1 = 128;
+  size_t lds1 = ((size_t)n * m + 3 * (size_t)m * b1) * 4;
+  if (lds1 > 64 * 1024) {
+    b1 = 64;
+    lds1 = ((size_t)n * m + 3 * (size_t)m * b1) * 4;
+  }
+  {
+    KTimer kt(c, s, "k_lb1");
+    hipLaunchKernelGGL(k_lb1, dim3((pool.count + b1 - 1) / b1), dim3(b1), lds1, s, I, pool, ub,
+                       out_lb, out_prune, costs, 0, c->d_flag);
+  }
+  const int xrows = n < 32 ? n : 32;
+  int waves = 8;
+  const bool ent_lds = lb2_lds_inst(n, m, I.P, I.narrow, 1, true, xrows) <= 64 * 1024;
+  size_t lds = lb2_lds_inst(n, m, I.P, I.narrow, waves, ent_lds, xrows);
+  while (lds > 160 * 1024 && waves > 1) {
+    waves >>= 1;
+    lds = lb2_lds_inst(n, m, I.P, I.narrow, waves, ent_lds, xrows);
+  }
+  int grid = (pool.count + waves - 1) / waves;
+  if (grid > c->cu_count * 8) grid = c->cu_count * 8;
+  const dim3 g(grid), bl(64 * waves);
+  KTimer kt(c, s, "k_lb2");
+  if (I.narrow) {
+    if (ent_lds)
+      launch_lb2_e<Narrow, true>(false, false, g, bl, lds, s, I, pool, ub, costs, out_lb,
+                                 out_prune, xrows);
+    else
+      launch_lb2_e<Narrow, false>(false, false, g, bl, lds, s, I, pool, ub, costs, out_lb,
+                                  out_prune, xrows);
+  } else {
+    if (ent_lds)
+      launch_lb2_e<Wide, true>(false, false, g, bl, lds, s, I, pool, ub, costs, out_lb, out_prune,
+                               xrows);
+    else
+      launch_lb2_e<Wide, false>(false, false, g, bl, lds, s, I, pool, ub, costs, out_lb,
                                 out_prune, xrows);
   }
   PFSP_HIP(c, hipGetLastError());

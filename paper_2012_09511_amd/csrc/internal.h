@@ -74,7 +74,10 @@ struct Ctx {
   int64_t learned_exact = 0;
   int64_t timing = 0;
   int64_t force_generic = 0;
-  int64_t lb2_waves = 0;      // waves per block of the LB2 kernel (0 = automatic)  // 1: always use the generic LB2 kernel
+  int64_t lb2_waves = 0;      // waves per block of the LB2 kernel (0 = automatic)
+  int64_t lb2_blocks_per_cu = 0;  // persistent LB2 blocks per CU (0 = 16)
+  int64_t log_capacity = 0;   // search node log size in records (0 = off)
+  int64_t log_stride = 1;     // log every log_stride-th decomposed node of a batch  // 1: always use the generic LB2 kernel
   struct Pending {
     const char *name;
     hipEvent_t a, b;
@@ -126,6 +129,8 @@ void collect_timings(Ctx *c);
 
 // stage.hip
 int stage_instance(Ctx *c);
+int stage_tables(Ctx *c, hipStream_t s, int n, int m, const int *d_p, int *d_T, uint2 *d_ent,
+                 uint4 *d_entw, uint8_t *d_pu, uint8_t *d_pv, int narrow);
 // bound.hip
 int ensure_costs(Ctx *c, int count);
 int launch_bound(Ctx *c, const DevPool &pool, int kind, int ub, int *out_lb,
@@ -135,6 +140,28 @@ int launch_bound_costs_ready(Ctx *c, const DevPool &pool, int kind, int ub, int 
                              uint8_t *out_prune, hipStream_t s);
 size_t lb2_lds_bytes(const Ctx *c, int waves);
 void init_bound_attributes();
+// multi-instance launches (bound.hip)
+struct MultiTile {
+  int inst, begin, end, pad;
+};
+struct FastClassLaunch {
+  int nmax;                 // compiled job bound of the class (20 or 64)
+  int ppad, nmax_jobs, mmax;  // LDS layout of the class
+  const MultiTile *tiles;   // device, grouped by instance
+  int ntiles;
+  int *queue;               // device tile counter (zeroed by the launcher)
+  int waves, grid;
+};
+size_t lb2m_lds_bytes(int nmax, int ppad, int nmax_jobs, int mmax, int waves);
+int launch_generic_instance(Ctx *c, const DevInst &I, const DevPool &pool, int ub, int *costs,
+                            int *out_lb, uint8_t *out_prune, hipStream_t s);
+int launch_lb1m(Ctx *c, const DevInst *insts, const long long *seg, int ninst, long long total,
+                const uint8_t *perm, const uint8_t *d1, const uint8_t *d2, int stride, int mmax,
+                const int *ubs, int *out_lb, uint8_t *out_prune, uint8_t *dir, int *costs,
+                int write_out, hipStream_t s);
+int launch_lb2m(Ctx *c, const FastClassLaunch &L, const DevInst *insts, const uint8_t *perm,
+                const uint8_t *d1, const uint8_t *d2, int stride, const int *ubs,
+                const int *costs, int *out_lb, uint8_t *out_prune, uint8_t *dir, hipStream_t s);
 // selector.hip
 int launch_learned(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8_t *out_prune,
                    hipStream_t s);

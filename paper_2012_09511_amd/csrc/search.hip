@@ -39,6 +39,7 @@ struct SearchCtl {
   long long nodes;               // decomposed nodes
   long long children;            // bounded children
   long long steps;               // steps that popped at least one record
+  long long log_count;           // decomposed nodes offered to the node log
 };
 
 struct SearchState {
@@ -60,6 +61,10 @@ struct SearchState {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   int graph_kind = 0;
+  long long graph_log = -1;
+  // node log (option log_capacity > 0): every log_stride-th decomposed node
+  uint8_t *l_perm = nullptr, *l_d1 = nullptr, *l_d2 = nullptr;
+  long long log_cap = 0;
 };
 
 constexpr int kScanBlock = 1024;  // parents per k_scan_local block (256 threads x 4)
@@ -93,6 +98,22 @@ __global__ void k_gather(const SearchCtl *__restrict__ c, int n, const uint8_t *
     b_lb[i] = lb;
     b_alive[i] = lb < ub;  // lazy re-check against the current incumbent
   }
+}
+
+// Appends every stride-th decomposed node of the batch to the node log.
+__global__ void k_log(SearchCtl *__restrict__ c, int n, const uint8_t *__restrict__ b_perm,
+                      const uint8_t *__restrict__ b_d1, const uint8_t *__restrict__ b_d2,
+                      const uint8_t *__restrict__ b_alive, int stride, long long cap,
+                      uint8_t *__restrict__ l_perm, uint8_t *__restrict__ l_d1,
+                      uint8_t *__restrict__ l_d2) {
+  const int count = c->count;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count || !b_alive[i] || i % stride) return;
+  const long long slot = (long long)atomicAdd((unsigned long long *)&c->log_count, 1ull);
+  if (slot >= cap) return;
+  for (int x = 0; x < n; ++x) l_perm[slot * n + x] = b_perm[(size_t)i * n + x];
+  l_d1[slot] = b_d1[i];
+  l_d2[slot] = b_d2[i];
 }
 
 // Per parent: node statistics, leaf incumbent updates, and the number of
@@ -289,6 +310,7 @@ __global__ void k_init_root(SearchCtl *c, int n, int ub0, uint8_t *s_perm, uint8
     c->nodes = 0;
     c->children = 0;
     c->steps = 0;
+    c->log_count = 0;
   }
 }
 
@@ -300,7 +322,7 @@ void search_free(Ctx *c) {
   if (S->graph) (void)hipGraphDestroy(S->graph);
   void *bufs[] = {S->s_perm, S->s_d1, S->s_d2, S->s_lb, S->b_perm, S->b_d1, S->b_d2, S->b_dir,
                   S->b_lb, S->b_alive, S->out_lb, S->out_prune, S->cnt, S->offs, S->bsum,
-                  S->best_perm, S->ctl};
+                  S->best_perm, S->ctl, S->l_perm, S->l_d1, S->l_d2};
   for (void *p : bufs) (void)hipFree(p);
   if (S->ctl_host) (void)hipHostFree(S->ctl_host);
   if (S->stream) (void)hipStreamDestroy(S->stream);
@@ -315,7 +337,8 @@ static int search_alloc(Ctx *c) {
   if (cap <= 0) cap = (long long)N * (n * (n + 1) / 2 + 1);
   if (cap > 0x7fffffffLL) cap = 0x7fffffffLL;
   SearchState *S = c->search;
-  if (S && S->n == n && S->N == N && S->cap == cap) return PFSP_OK;
+  if (S && S->n == n && S->N == N && S->cap == cap && S->log_cap == c->log_capacity)
+    return PFSP_OK;
   search_free(c);
   S = new (std::nothrow) SearchState();
   if (!S) return set_err(c, PFSP_ENOMEM, "host allocation failed");
@@ -345,6 +368,12 @@ static int search_alloc(Ctx *c) {
   alloc((void **)&S->bsum, (size_t)nb * 4);
   alloc((void **)&S->best_perm, (size_t)n);
   alloc((void **)&S->ctl, sizeof(SearchCtl));
+  S->log_cap = c->log_capacity;
+  if (S->log_cap > 0) {
+    alloc((void **)&S->l_perm, (size_t)S->log_cap * n);
+    alloc((void **)&S->l_d1, (size_t)S->log_cap);
+    alloc((void **)&S->l_d2, (size_t)S->log_cap);
+  }
   if (ok && hipHostMalloc((void **)&S->ctl_host, sizeof(SearchCtl), hipHostMallocDefault) !=
                 hipSuccess)
     ok = false;
@@ -366,6 +395,10 @@ static int enqueue_step(Ctx *c, int kind) {
   const int gg = (int)(((long long)N * n + 255) / 256 < 4096 ? ((long long)N * n + 255) / 256 : 4096);
   hipLaunchKernelGGL(k_gather, dim3(gg), dim3(256), 0, s, S->ctl, n, S->s_perm, S->s_d1, S->s_d2,
                      S->s_lb, S->b_perm, S->b_d1, S->b_d2, S->b_lb, S->b_alive);
+  if (S->log_cap > 0)
+    hipLaunchKernelGGL(k_log, dim3((N + 255) / 256), dim3(256), 0, s, S->ctl, n, S->b_perm,
+                       S->b_d1, S->b_d2, S->b_alive, (int)c->log_stride, S->log_cap, S->l_perm,
+                       S->l_d1, S->l_d2);
   DevPool pool;
   pool.count = N;
   pool.n = n;
@@ -398,7 +431,8 @@ static int enqueue_step(Ctx *c, int kind) {
 
 static int build_graph(Ctx *c, int kind) {
   SearchState *S = c->search;
-  if (S->gexec && S->graph_kind == kind) return PFSP_OK;
+  const long long logkey = S->log_cap > 0 ? c->log_stride : 0;
+  if (S->gexec && S->graph_kind == kind && S->graph_log == logkey) return PFSP_OK;
   if (S->gexec) (void)hipGraphExecDestroy(S->gexec);
   if (S->graph) (void)hipGraphDestroy(S->graph);
   S->gexec = nullptr;
@@ -417,6 +451,7 @@ static int build_graph(Ctx *c, int kind) {
   S->graph = g;
   PFSP_HIP(c, hipGraphInstantiate(&S->gexec, g, nullptr, nullptr, 0));
   S->graph_kind = kind;
+  S->graph_log = logkey;
   return PFSP_OK;
 }
 
@@ -496,4 +531,29 @@ extern "C" int pfsp_search(pfsp_ctx *h, int32_t ub0, int64_t budget_nodes, int l
     for (int j = 0; j < n; ++j) res->best_perm[j] = tmp[j];
   }
   return status;
+}
+
+extern "C" int pfsp_search_log(pfsp_ctx *h, uint8_t *perm_out, uint8_t *d1_out, uint8_t *d2_out,
+                               int64_t max_records, int64_t *count) {
+  if (!h || !count || max_records < 0) return PFSP_EINVAL;
+  Ctx *c = &h->impl;
+  SearchState *S = c->search;
+  *count = 0;
+  if (!S || S->log_cap <= 0) return PFSP_OK;
+  if (max_records > 0 && (!perm_out || !d1_out || !d2_out))
+    return set_err(c, PFSP_EINVAL, "null output");
+  PFSP_HIP(c, hipSetDevice(c->device));
+  PFSP_HIP(c, hipMemcpyAsync(S->ctl_host, S->ctl, sizeof(SearchCtl), hipMemcpyDeviceToHost,
+                             S->stream));
+  PFSP_HIP(c, hipStreamSynchronize(S->stream));
+  long long k = S->ctl_host->log_count;
+  if (k > S->log_cap) k = S->log_cap;
+  if (k > max_records) k = max_records;
+  if (k > 0) {
+    PFSP_HIP(c, hipMemcpy(perm_out, S->l_perm, (size_t)k * S->n, hipMemcpyDeviceToHost));
+    PFSP_HIP(c, hipMemcpy(d1_out, S->l_d1, (size_t)k, hipMemcpyDeviceToHost));
+    PFSP_HIP(c, hipMemcpy(d2_out, S->l_d2, (size_t)k, hipMemcpyDeviceToHost));
+  }
+  *count = k;
+  return PFSP_OK;
 }

@@ -75,20 +75,25 @@ __global__ void k_stage(int n, int m, int P, const int *__restrict__ p, int *__r
   }
 }
 
-int stage_instance(Ctx *c) {
-  const int n = c->n, m = c->m, P = c->P;
+int stage_tables(Ctx *c, hipStream_t s, int n, int m, const int *d_p, int *d_T, uint2 *d_ent,
+                 uint4 *d_entw, uint8_t *d_pu, uint8_t *d_pv, int narrow) {
+  const int P = m * (m - 1) / 2;
   uint8_t *d_ord = nullptr;
   const int threads = 64;
   const int work = P > m ? P : m;
   PFSP_HIP(c, hipMalloc(&d_ord, (size_t)(P > 0 ? P : 1) * n));
-  hipLaunchKernelGGL(k_stage, dim3((work + threads - 1) / threads), dim3(threads), 0,
-                     c->stream, n, m, P, c->d_p, c->d_T, d_ord, c->d_ent, c->d_entw, c->d_pu,
-                     c->d_pv, c->narrow);
+  hipLaunchKernelGGL(k_stage, dim3((work + threads - 1) / threads), dim3(threads), 0, s, n, m, P,
+                     d_p, d_T, d_ord, d_ent, d_entw, d_pu, d_pv, narrow);
   hipError_t e = hipGetLastError();
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(d_ord);
   if (e != hipSuccess) return hip_err(c, e, "k_stage");
   return PFSP_OK;
+}
+
+int stage_instance(Ctx *c) {
+  return stage_tables(c, c->stream, c->n, c->m, c->d_p, c->d_T, c->d_ent, c->d_entw, c->d_pu,
+                      c->d_pv, c->narrow);
 }
 
 }  // namespace pfsp

@@ -180,3 +180,25 @@ def test_generic_kernel_parity(ctx, n, m):
         _check(ctx, p, perm, d1, d2, binding.LB2_FULL, INT32_MAX, argpair=True)
     finally:
         ctx.set_option("force_generic", 0)
+
+
+def test_autotune_keeps_results(ctx):
+    """The autotuner only changes launch shapes: results stay bit-exact."""
+    import torch
+    n, m = 20, 20
+    p = inputs.instance(n, m, 2012)
+    perm, d1, d2 = inputs.random_pool(n, 4096, 31)
+    ctx.load_instance(p)
+    dev = _dev(ctx, perm, d1, d2)
+    rep = ctx.autotune(*dev, kind=binding.LB2_FULL, ub=2000, reps=1)
+    assert rep["best"]["ms"] > 0 and rep["candidates"] >= 10
+    try:
+        lb, pr, dr, _ = ctx.bound_children(*dev, binding.LB2_FULL, 2000)
+        torch.cuda.synchronize()
+        olb, opr, odr = oracle.bound_children(p, perm[:300], d1[:300], d2[:300],
+                                              oracle.LB2_FULL, 2000, threads=8)
+        np.testing.assert_array_equal(lb.cpu().numpy()[:300], olb)
+        np.testing.assert_array_equal(dr.cpu().numpy()[:300], odr)
+    finally:
+        ctx.set_option("lb2_waves", 0)
+        ctx.set_option("lb2_blocks_per_cu", 0)

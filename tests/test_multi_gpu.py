@@ -1,0 +1,88 @@
+"""GPU parity of the multi-instance batched launch (pfsp_multi_*): every
+instance's rows must equal the oracle on that instance, bit for bit, across
+graph replays, launch shapes and the autotuner's choice."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2012_09511_amd import binding, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = binding.Context(0)
+    yield c
+    c.close()
+
+
+def _batch(insts, per, seed, stride):
+    perms, d1s, d2s, seg = [], [], [], [0]
+    for k, (n, m, p) in enumerate(insts):
+        cnt = per[k]
+        perm, d1, d2 = inputs.random_pool(n, cnt, seed + k)
+        pad = np.zeros((cnt, stride), dtype=np.uint8)
+        pad[:, :n] = perm
+        perms.append(pad)
+        d1s.append(d1)
+        d2s.append(d2)
+        seg.append(seg[-1] + cnt)
+    return np.concatenate(perms), np.concatenate(d1s), np.concatenate(d2s), np.array(seg)
+
+
+def _check(insts, perm, d1, d2, seg, ub, lb, pr, dr, kind):
+    lb, pr, dr = lb.cpu().numpy(), pr.cpu().numpy(), dr.cpu().numpy()
+    stride = perm.shape[1]
+    for k, (n, m, p) in enumerate(insts):
+        a, b = seg[k], seg[k + 1]
+        if a == b:
+            continue
+        olb, opr, odr = oracle.bound_children(p, perm[a:b, :n], d1[a:b], d2[a:b], kind, ub[k],
+                                              threads=8)
+        np.testing.assert_array_equal(lb[a:b, :, :n], olb)
+        np.testing.assert_array_equal(pr[a:b, :, :n], opr)
+        np.testing.assert_array_equal(dr[a:b], odr)
+        assert (lb[a:b, :, n:] == binding.INT32_MAX).all() and (pr[a:b, :, n:] == 1).all()
+
+
+def _dev(ctx, *a):
+    import torch
+    return [torch.from_numpy(np.ascontiguousarray(x)).to(ctx.device) for x in a]
+
+
+@pytest.mark.parametrize("kind", [binding.LB1, binding.LB2_FULL])
+def test_mixed_instances(ctx, kind):
+    """(n, m) round-robin over {20, 50, 100} x {5, 10, 20}, every fourth instance
+    job-correlated; includes an empty segment."""
+    insts = inputs.mixed_instances(9, 1234)
+    per = [40, 7, 0, 25, 3, 30, 2, 12, 5]
+    per = [x if insts[i][0] < 100 else min(x, 3) for i, x in enumerate(per)]
+    stride = max(n for n, _, _ in insts)
+    perm, d1, d2, seg = _batch(insts, per, 55, stride)
+    ub = np.array([1400 + 300 * i for i in range(len(insts))], dtype=np.int32)
+    mt = binding.Multi(ctx, [p for _, _, p in insts])
+    dev = _dev(ctx, perm, d1, d2)
+    out = mt.outputs(len(perm), stride)
+    for rep in range(2):     # capture, then a replay
+        lb, pr, dr = mt.bound(*dev, seg, ub, kind, out=out)
+        _check(insts, perm, d1, d2, seg, ub, lb, pr, dr, kind)
+    mt.set_shape(tile=16, waves_small=2, waves_large=1, blocks_per_cu=1)
+    lb, pr, dr = mt.bound(*dev, seg, ub, kind, out=out)
+    _check(insts, perm, d1, d2, seg, ub, lb, pr, dr, kind)
+    mt.close()
+
+
+def test_autotune_keeps_results(ctx):
+    insts = [(20, 20, inputs.instance(20, 20, 7)), (20, 5, inputs.instance(20, 5, 8)),
+             (50, 10, inputs.instance(50, 10, 9))]
+    per = [300, 200, 20]
+    perm, d1, d2, seg = _batch(insts, per, 77, 50)
+    ub = np.array([2400, 1500, 3200], dtype=np.int32)
+    mt = binding.Multi(ctx, [p for _, _, p in insts])
+    dev = _dev(ctx, perm, d1, d2)
+    rep = mt.autotune(*dev, seg, ub, binding.LB2_FULL, reps=1)
+    assert rep["best"]["ms"] > 0 and rep["candidates"] > 10
+    lb, pr, dr = mt.bound(*dev, seg, ub, binding.LB2_FULL)
+    _check(insts, perm, d1, d2, seg, ub, lb, pr, dr, binding.LB2_FULL)
+    mt.close()

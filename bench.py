@@ -7,8 +7,13 @@ p ~ U[1,99], including the MinMin branching decision and the prune flags.
 The metric is children bounded per second.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+    python bench.py --workload search|multi|learned [...]
 
-Prints one JSON line.  The dominant kernel's roofline entry divides the
+Prints one JSON line.  Other workloads (not the headline): `search` = the
+device depth-first B&B on n=20 x m=10 instances (seeds 1..8, NEH incumbent)
+to proven optimality; `multi` = 64 instances of mixed (n, m) bounded in one
+persistent graph launch, autotuned shape vs default; `learned` = full LB2
+vs learned-pair LB2 searches to the same proven optimum.  The dominant kernel's roofline entry divides the
 kernel's algorithmic integer operations (formula in alg_ops_lb2) by its mean
 duration measured with HIP events on the library stream over the timed
 steps.  The CPU baseline is the plain oracle on a bounded sample of the same
@@ -83,6 +88,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--workload", default="bound", choices=["bound", "search", "multi", "learned"])
+    ap.add_argument("--selector", default=os.path.join(ROOT, "profiles", "selector_n50m20.npy"))
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the bounding path has no multi-GPU mode in this "
@@ -92,6 +99,12 @@ def main():
     import torch
     from paper_2012_09511_amd import binding, inputs
 
+    if args.workload == "search":
+        return bench_search(args)
+    if args.workload == "multi":
+        return bench_multi(args)
+    if args.workload == "learned":
+        return bench_learned(args)
     n, m, N = 20, 20, args.parents
     p = inputs.instance(n, m, 2012)
     perm, d1, d2 = inputs.random_pool(n, N, 9511)
@@ -106,11 +119,7 @@ def main():
     children = int((2 * (n - d1.astype(np.int64) - d2.astype(np.int64))).sum())
 
     if args.copy_probe:
-        src = torch.ones(64 << 20, dtype=torch.int32, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        _copy_probe(torch)
     for _ in range(args.warmup):
         ctx.bound_children(*dev, kind=kind, ub=ub, out_lb=out_lb, out_prune=out_pr,
                            dir_out=out_dir)
@@ -158,6 +167,157 @@ def main():
                                                              else {})))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, perm, d1, d2, kind)
+    ctx.close()
+    print(json.dumps(out))
+
+
+def _copy_probe(torch):
+    src = torch.ones(64 << 20, dtype=torch.int32, device="cuda")
+    junk = torch.empty(1 << 29, dtype=torch.int32, device="cuda")
+    junk.fill_(1)                      # evicts src from the caches
+    del junk
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+
+
+def bench_search(args):
+    """Device B&B to proven optimality: n=20 x m=10, p~U[1,99], seeds 1..8, NEH + 1."""
+    import torch
+    import oracle
+    from paper_2012_09511_amd import binding, inputs
+    ctx = binding.Context(0)
+    rows = []
+    for kind_name in ("LB1", "LB2_FULL"):
+        kind = getattr(binding, kind_name)
+        for seed in range(1, 9):
+            p = inputs.instance(20, 10, seed)
+            ctx.load_instance(p)
+            ub0, _ = ctx.neh()
+            ctx.search(ub0 + 1, 0, kind)          # warm-up: graph build, allocation
+            t = time.perf_counter()
+            r = ctx.search(ub0 + 1, 0, kind)
+            dt = time.perf_counter() - t
+            rows.append(dict(kind=kind_name, seed=seed, best=r["best"], proven=r["proven"],
+                             nodes=r["nodes"], children=r["children"], steps=r["steps"],
+                             seconds=dt))
+    tot = {k: (sum(x["seconds"] for x in rows if x["kind"] == k),
+               sum(x["nodes"] for x in rows if x["kind"] == k),
+               sum(x["children"] for x in rows if x["kind"] == k)) for k in ("LB1", "LB2_FULL")}
+    out = dict(metric="time to proven optimum, 8 instances (device B&B)",
+               value=tot["LB2_FULL"][0], unit="s", n_gpus=1, steps=1, warmup=1,
+               ms_per_step=tot["LB2_FULL"][0] * 1e3, higher_is_better=False, scaling="weak",
+               vs_baseline=None, dtype="int32", data="synthetic",
+               config=dict(workload="depth-first B&B, n=20 x m=10, p~U[1,99], seeds 1..8, "
+                                    "incumbent NEH+1, pool_batch 65536", lb_kind="LB2_FULL"),
+               lb1=dict(seconds=tot["LB1"][0], nodes_per_s=tot["LB1"][1] / tot["LB1"][0],
+                        children_per_s=tot["LB1"][2] / tot["LB1"][0]),
+               lb2=dict(seconds=tot["LB2_FULL"][0],
+                        nodes_per_s=tot["LB2_FULL"][1] / tot["LB2_FULL"][0],
+                        children_per_s=tot["LB2_FULL"][2] / tot["LB2_FULL"][0]),
+               instances=rows)
+    if not args.no_cpu:
+        cores = 1
+        t = time.perf_counter()
+        cpu_rows = []
+        for seed in range(1, 9):
+            p = inputs.instance(20, 10, seed)
+            ub0, _ = oracle.neh(p)
+            r = oracle.search(p, ub0 + 1, oracle.LB1)
+            cpu_rows.append((r["best"], r["nodes"]))
+        dt = time.perf_counter() - t
+        assert [b for b, _ in cpu_rows] == [x["best"] for x in rows if x["kind"] == "LB1"]
+        out["cpu_baseline"] = dict(value=dt, unit="s", cores=cores, kind="oracle",
+                                   sample="the same 8 instances with LB1, single-thread "
+                                          "recursive DFS; same optima")
+    ctx.close()
+    print(json.dumps(out))
+
+
+def bench_multi(args):
+    """64 instances, (n, m) round-robin over {20,50,100} x {5,10,20}, 25% job-correlated,
+    16,384 random parents each, LB2 in one persistent graph launch."""
+    import torch
+    from paper_2012_09511_amd import binding, inputs
+    ctx = binding.Context(0)
+    insts = inputs.mixed_instances(64, 4000)
+    stride = max(n for n, _, _ in insts)
+    per = 16384
+    perms, d1s, d2s, seg = [], [], [], [0]
+    children = 0
+    for k, (n, m, p) in enumerate(insts):
+        perm, d1, d2 = inputs.random_pool(n, per, 5000 + k)
+        pad = np.zeros((per, stride), dtype=np.uint8)
+        pad[:, :n] = perm
+        perms.append(pad)
+        d1s.append(d1)
+        d2s.append(d2)
+        seg.append(seg[-1] + per)
+        children += int((2 * (n - d1.astype(np.int64) - d2.astype(np.int64))).sum())
+    perm = torch.from_numpy(np.concatenate(perms)).cuda()
+    d1 = torch.from_numpy(np.concatenate(d1s)).cuda()
+    d2 = torch.from_numpy(np.concatenate(d2s)).cuda()
+    seg = np.array(seg)
+    ub = np.full(64, binding.INT32_MAX, dtype=np.int32)
+    mt = binding.Multi(ctx, [p for _, _, p in insts])
+    out_bufs = mt.outputs(perm.shape[0], stride)
+
+    def run(k):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(k):
+            mt.bound(perm, d1, d2, seg, ub, binding.LB2_FULL, out=out_bufs)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / k
+
+    run(args.warmup)
+    default_s = run(args.steps)
+    rep = mt.autotune(perm, d1, d2, seg, ub, binding.LB2_FULL, out=out_bufs, reps=2)
+    run(args.warmup)
+    tuned_s = run(args.steps)
+    out = dict(metric="children bounded/sec (LB2), 64 mixed instances, one graph launch",
+               value=children / tuned_s, unit="children/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=tuned_s * 1e3, higher_is_better=True,
+               scaling="weak", vs_baseline=None, dtype="int32", data="synthetic",
+               config=dict(workload="64 instances (n,m) in {20,50,100}x{5,10,20}, 25% "
+                                    "job-correlated, 16384 random parents each, LB2_FULL",
+                           parents=int(perm.shape[0]), children=children),
+               default_shape=dict(ms=default_s * 1e3, children_per_s=children / default_s),
+               autotuned=rep)
+    mt.close()
+    ctx.close()
+    print(json.dumps(out))
+
+
+def bench_learned(args):
+    """Full LB2 vs learned-pair LB2 (top-16) searches to the same proven optimum."""
+    import torch
+    from paper_2012_09511_amd import binding, inputs
+    ctx = binding.Context(0)
+    params = np.load(args.selector)
+    ctx.selector_set(params)
+    rows = []
+    for seed in range(600, 608):
+        p = inputs.instance(20, 20, seed)
+        ctx.load_instance(p)
+        ub0, _ = ctx.neh()
+        res = {}
+        for name, kind in (("full", binding.LB2_FULL), ("learned", binding.LB2_LEARNED)):
+            t = time.perf_counter()
+            r = ctx.search(ub0 + 1, 0, kind)
+            res[name] = dict(best=r["best"], proven=r["proven"], nodes=r["nodes"],
+                             seconds=time.perf_counter() - t)
+        assert res["full"]["best"] == res["learned"]["best"]
+        rows.append(dict(seed=seed, **res))
+    tf = sum(x["full"]["seconds"] for x in rows)
+    tl = sum(x["learned"]["seconds"] for x in rows)
+    out = dict(metric="time to the same proven optimum, learned-pair vs full LB2",
+               value=tf / tl, unit="speedup", n_gpus=1, steps=1, warmup=0,
+               ms_per_step=tl * 1e3, higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="int32", data="synthetic",
+               config=dict(workload="depth-first B&B, n=20 x m=20, seeds 600..607, NEH+1, "
+                                    "learned top-16 of 190 pairs"),
+               full_seconds=tf, learned_seconds=tl, instances=rows)
     ctx.close()
     print(json.dumps(out))
 

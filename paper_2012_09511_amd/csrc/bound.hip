@@ -475,10 +475,20 @@ struct FastLds {
 template <int NMAX>
 __device__ void lb2f_stage(const DevInst &I, int Ppad, const FastLds<NMAX> &S) {
   const int n = I.n, m = I.m, P = I.P;
-  const unsigned kpad = (unsigned)(NMAX - 1) << 24;
+  // NMAX <= 32: entries are restaged as (a | b << 16, job | lag << 16) (the
+  // launcher only takes this path when every lag is below 2^16), so that the
+  // job id is the low field used by the membership bit test and the lag a
+  // 16-bit field; NMAX = 64 keeps (a | b << 16, lag | job << 24).
+  constexpr bool L16 = NMAX <= 32;
+  const unsigned kpad = L16 ? (unsigned)(NMAX - 1) : (unsigned)(NMAX - 1) << 24;
   for (int x = threadIdx.x; x < NMAX * Ppad; x += blockDim.x) {
     const int i = x / Ppad, pi = x - i * Ppad;
-    S.ent[x] = (i < n && pi < P) ? I.ent[(size_t)i * P + pi] : make_uint2(0u, kpad);
+    uint2 e = make_uint2(0u, kpad);
+    if (i < n && pi < P) {
+      e = I.ent[(size_t)i * P + pi];
+      if (L16) e.y = (e.y >> 24) | ((e.y & 0xffffu) << 16);
+    }
+    S.ent[x] = e;
   }
   for (int x = threadIdx.x; x < Ppad; x += blockDim.x)
     S.uv[x] = x < P ? ((int)I.pu[x] | ((int)I.pv[x] << 8)) : 0;
@@ -499,7 +509,8 @@ __device__ void lb2f_parent(const DevInst &I, int Ppad, const FastLds<NMAX> &S,
   using MT = typename M::T;
   // pair entries stay in registers between the two scans when they fit
   constexpr bool KEEP = NMAX <= 20 && !LOG && !SUBSET;
-  constexpr bool PMB_REG = NMAX <= 24 && !LOG;
+  constexpr bool PMB_REG = NMAX <= 20 && !LOG;
+  constexpr bool L16 = NMAX <= 32;  // staged entry layout, see lb2f_stage
   const int n = I.n, m = I.m, P = I.P;
   const int r = n - a - b;
   if (r < 1 || cs[0] < 0) {  // flagged by k_lb1: not a valid node
@@ -611,41 +622,89 @@ __device__ void lb2f_parent(const DevInst &I, int Ppad, const FastLds<NMAX> &S,
 #pragma unroll
         for (int i = 0; i < NMAX; ++i) e[i] = ent[i * Ppad + pi];
       }
-      // forward scan: exclusive prefix maxima of term - B(U), minus b (kept in
-      // registers when they fit, else in the lane's X column)
-      int pmb[PMB_REG ? NMAX : 1];
-      int Y = 0, Pm = kNeg;
+      if constexpr (L16) {
+        // forward scan: running A - B over members and, per entry, the exclusive
+        // prefix maximum minus b and the member's term (-inf for non-members),
+        // all relative to B(U); the backward scan then only combines the stored
+        // terms into suffix maxima.
+        int pmb[PMB_REG ? NMAX : 1], tmv[PMB_REG ? NMAX : 1];
+        int Y = 0, Pm = kNeg;
 #pragma unroll
-      for (int i = 0; i < NMAX; ++i) {
-        const uint2 ei = KEEP ? e[KEEP ? i : 0] : ent[i * Ppad + pi];
-        const int ea = (int)(ei.x & 0xffffu), eb = (int)(ei.x >> 16);
-        const int el = (int)(ei.y & 0xffffffu), ek = (int)(ei.y >> 24);
-        const int ng = M::neg(umask, ek);
-        Y += ea & ng;
-        const int tt = Y + el;
-        if constexpr (PMB_REG)
-          pmb[PMB_REG ? i : 0] = Pm - eb;
-        else
-          X[ek * 64 + lane].x = Pm - eb;
-        Pm = max(Pm, ng ? tt : kNeg);
-        Y -= eb & ng;
-      }
-      // backward scan: exclusive suffix maxima; X(j) = max(PM - b, SM - a)
-      const int c0 = RU - RV;
-      int Wb = 0, Sm = kNeg;
+        for (int i = 0; i < NMAX; ++i) {
+          const uint2 ei = KEEP ? e[KEEP ? i : 0] : ent[i * Ppad + pi];
+          const int ng = M::neg(umask, (int)(ei.y & 31u));
+          const int ea = (int)(ei.x & 0xffffu), eb = (int)(ei.x >> 16);
+          const int t0 = Y + (ea & ng);
+          const int tt = t0 + (int)(ei.y >> 16);
+          const int tm = (tt & ng) | (kNeg & ~ng);
+          if constexpr (PMB_REG) {
+            pmb[PMB_REG ? i : 0] = Pm - eb;
+            tmv[PMB_REG ? i : 0] = tm;
+          } else {
+            X[(int)(ei.y & 0xffu) * 64 + lane] = make_int2(Pm - eb, tm);
+          }
+          Pm = max(Pm, tm);
+          Y = t0 - (eb & ng);
+        }
+        // backward scan: X(j) = max(PM - b, SM - a), stored as (X + a, X + b)
+        int Sm = kNeg;
 #pragma unroll
-      for (int i = NMAX - 1; i >= 0; --i) {
-        const uint2 ei = KEEP ? e[KEEP ? i : 0] : ent[i * Ppad + pi];
-        const int ea = (int)(ei.x & 0xffffu), eb = (int)(ei.x >> 16);
-        const int el = (int)(ei.y & 0xffffffu), ek = (int)(ei.y >> 24);
-        const int ng = M::neg(umask, ek);
-        Wb += eb & ng;
-        const int tp = Wb + el + c0;
-        const int pm = PMB_REG ? pmb[PMB_REG ? i : 0] : X[ek * 64 + lane].x;
-        const int x = max(pm, Sm - ea);
-        X[ek * 64 + lane] = make_int2(x + ea, x + eb);
-        Sm = max(Sm, ng ? tp : kNeg);
-        Wb -= ea & ng;
+        for (int i = NMAX - 1; i >= 0; --i) {
+          const uint2 ei = KEEP ? e[KEEP ? i : 0] : ent[i * Ppad + pi];
+          const int ea = (int)(ei.x & 0xffffu), eb = (int)(ei.x >> 16);
+          const int ek = (int)(ei.y & 0xffu);
+          int pm, tm;
+          if constexpr (PMB_REG) {
+            pm = pmb[PMB_REG ? i : 0];
+            tm = tmv[PMB_REG ? i : 0];
+          } else {
+            // padding rows share one job id, so their stored values may have
+            // been overwritten: only members may feed the suffix maximum
+            const int2 st = X[ek * 64 + lane];
+            pm = st.x;
+            tm = M::neg(umask, (int)(ei.y & 31u)) ? st.y : kNeg;
+          }
+          const int x = max(pm, Sm - ea);
+          X[ek * 64 + lane] = make_int2(x + ea, x + eb);
+          Sm = max(Sm, tm);
+        }
+      } else {
+        // forward scan: exclusive prefix maxima of term - B(U), minus b (kept in
+        // registers when they fit, else in the lane's X column)
+        int pmb[PMB_REG ? NMAX : 1];
+        int Y = 0, Pm = kNeg;
+  #pragma unroll
+        for (int i = 0; i < NMAX; ++i) {
+          const uint2 ei = KEEP ? e[KEEP ? i : 0] : ent[i * Ppad + pi];
+          const int ea = (int)(ei.x & 0xffffu), eb = (int)(ei.x >> 16);
+          const int el = (int)(ei.y & 0xffffffu), ek = (int)(ei.y >> 24);
+          const int ng = M::neg(umask, ek);
+          Y += ea & ng;
+          const int tt = Y + el;
+          if constexpr (PMB_REG)
+            pmb[PMB_REG ? i : 0] = Pm - eb;
+          else
+            X[ek * 64 + lane].x = Pm - eb;
+          Pm = max(Pm, ng ? tt : kNeg);
+          Y -= eb & ng;
+        }
+        // backward scan: exclusive suffix maxima; X(j) = max(PM - b, SM - a)
+        const int c0 = RU - RV;
+        int Wb = 0, Sm = kNeg;
+  #pragma unroll
+        for (int i = NMAX - 1; i >= 0; --i) {
+          const uint2 ei = KEEP ? e[KEEP ? i : 0] : ent[i * Ppad + pi];
+          const int ea = (int)(ei.x & 0xffffu), eb = (int)(ei.x >> 16);
+          const int el = (int)(ei.y & 0xffffffu), ek = (int)(ei.y >> 24);
+          const int ng = M::neg(umask, ek);
+          Wb += eb & ng;
+          const int tp = Wb + el + c0;
+          const int pm = PMB_REG ? pmb[PMB_REG ? i : 0] : X[ek * 64 + lane].x;
+          const int x = max(pm, Sm - ea);
+          X[ek * 64 + lane] = make_int2(x + ea, x + eb);
+          Sm = max(Sm, ng ? tp : kNeg);
+          Wb -= ea & ng;
+        }
       }
       const int K1 = RU + C2u, K2 = C1u + RU, K3 = C1v + RV;
 #pragma unroll
@@ -672,7 +731,7 @@ __device__ void lb2f_parent(const DevInst &I, int Ppad, const FastLds<NMAX> &S,
     if constexpr (LOG) {
       transpose_argmax64(acc, arg, lane);
     } else {
-      transpose_max64(acc, lane);
+      transpose_max64_xl(acc, lane);
     }
     const bool mine = ql < nq;
     const bool bwd = lane >= 32;
@@ -732,8 +791,8 @@ __global__ void __launch_bounds__(512)
 k_lb2m(const DevInst *__restrict__ insts, const MultiTile *__restrict__ tiles, int ntiles,
        int *__restrict__ queue, FastLayout L, const uint8_t *__restrict__ perm,
        const uint8_t *__restrict__ d1, const uint8_t *__restrict__ d2, int stride,
-       const int *__restrict__ ubs, const int *__restrict__ costs, int *__restrict__ out_lb,
-       uint8_t *__restrict__ out_prune, uint8_t *__restrict__ dir) {
+       const int *__restrict__ ubs, const int *__restrict__ costs, int cstride,
+       int *__restrict__ out_lb, uint8_t *__restrict__ out_prune, uint8_t *__restrict__ dir) {
   extern __shared__ __align__(16) unsigned char sm[];
   __shared__ int s_tile;
   const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -758,7 +817,7 @@ k_lb2m(const DevInst *__restrict__ insts, const MultiTile *__restrict__ tiles, i
     for (int par = T.begin + w; par < T.end; par += nw) {
       lb2f_parent<NMAX, false, false>(
           I, Ppad, S, perm + (size_t)par * stride, d1[par], d2[par],
-          costs + (size_t)par * 3 * L.mmax, nullptr, stride, ub,
+          costs + (size_t)par * cstride, nullptr, stride, ub,
           out_lb + (size_t)par * 2 * stride, out_prune + (size_t)par * 2 * stride, nullptr,
           dir + par, lane);
     }
@@ -792,11 +851,12 @@ static void launch_lb2f_n(bool subset, bool log, dim3 g, dim3 b, size_t lds, hip
   }
 }
 
-// Smallest compiled NMAX >= n (0 if none).
-static int fast_nmax(int n) {
+// Smallest compiled NMAX >= n (0 if none); the variants up to 32 jobs need
+// every lag below 2^16.
+static int fast_nmax(int n, int l16) {
   static const int sizes[] = {8, 12, 16, 20, 24, 32, 64};
   for (int s : sizes)
-    if (n <= s) return s;
+    if (n <= s && (l16 || s == 64)) return s;
   return 0;
 }
 
@@ -864,30 +924,29 @@ static void launch_lb2_e(bool subset, bool log, dim3 g, dim3 b, size_t lds, hipS
 
 // Allows every bound kernel to use up to 160 KiB of dynamic LDS (the gfx950
 // per-CU size); called once per process, before any launch or graph capture.
+// Lets a kernel use the whole 160 KiB of gfx950 LDS minus its static LDS.
+static void lds_limit(const void *f) {
+  hipFuncAttributes at;
+  size_t stat = 0;
+  if (hipFuncGetAttributes(&at, f) == hipSuccess) stat = at.sharedSizeBytes;
+  (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(160 * 1024 - stat));
+}
+
 template <class E, bool ENT_LDS>
 static void attr_lb2() {
-  const int mx = 160 * 1024;
-  (void)hipFuncSetAttribute((const void *)k_lb2<E, ENT_LDS, true, true>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-  (void)hipFuncSetAttribute((const void *)k_lb2<E, ENT_LDS, true, false>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-  (void)hipFuncSetAttribute((const void *)k_lb2<E, ENT_LDS, false, true>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-  (void)hipFuncSetAttribute((const void *)k_lb2<E, ENT_LDS, false, false>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+  lds_limit((const void *)k_lb2<E, ENT_LDS, true, true>);
+  lds_limit((const void *)k_lb2<E, ENT_LDS, true, false>);
+  lds_limit((const void *)k_lb2<E, ENT_LDS, false, true>);
+  lds_limit((const void *)k_lb2<E, ENT_LDS, false, false>);
 }
 
 template <int NMAX>
 static void attr_lb2f() {
-  const int mx = 160 * 1024;
-  (void)hipFuncSetAttribute((const void *)k_lb2f<NMAX, true, true>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-  (void)hipFuncSetAttribute((const void *)k_lb2f<NMAX, true, false>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-  (void)hipFuncSetAttribute((const void *)k_lb2f<NMAX, false, true>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-  (void)hipFuncSetAttribute((const void *)k_lb2f<NMAX, false, false>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+  lds_limit((const void *)k_lb2f<NMAX, true, true>);
+  lds_limit((const void *)k_lb2f<NMAX, true, false>);
+  lds_limit((const void *)k_lb2f<NMAX, false, true>);
+  lds_limit((const void *)k_lb2f<NMAX, false, false>);
 }
 
 size_t lb2m_lds_bytes(int nmax, int ppad, int nmax_jobs, int mmax, int waves) {
@@ -916,17 +975,17 @@ int launch_lb2m(Ctx *c, const FastClassLaunch &L, const DevInst *insts, const ui
   if (L.ntiles <= 0) return PFSP_OK;
   const FastLayout FL{L.ppad, L.nmax_jobs, L.mmax};
   const size_t lds = FL.block_bytes(L.nmax) + (size_t)L.waves * FL.wave_bytes(L.nmax);
-  if (lds > 160 * 1024) return set_err(c, PFSP_ERANGE, "multi-instance class exceeds LDS");
+  if (lds > 160 * 1024 - 64) return set_err(c, PFSP_ERANGE, "multi-instance class exceeds LDS");
   hipLaunchKernelGGL(k_zero, dim3(1), dim3(1), 0, s, L.queue);
   KTimer kt(c, s, "k_lb2m");
   if (L.nmax == 20)
     hipLaunchKernelGGL(k_lb2m<20>, dim3(L.grid), dim3(64 * L.waves), lds, s, insts, L.tiles,
-                       L.ntiles, L.queue, FL, perm, d1, d2, stride, ubs, costs, out_lb, out_prune,
-                       dir);
+                       L.ntiles, L.queue, FL, perm, d1, d2, stride, ubs, costs, L.cstride, out_lb,
+                       out_prune, dir);
   else if (L.nmax == 64)
     hipLaunchKernelGGL(k_lb2m<64>, dim3(L.grid), dim3(64 * L.waves), lds, s, insts, L.tiles,
-                       L.ntiles, L.queue, FL, perm, d1, d2, stride, ubs, costs, out_lb, out_prune,
-                       dir);
+                       L.ntiles, L.queue, FL, perm, d1, d2, stride, ubs, costs, L.cstride, out_lb,
+                       out_prune, dir);
   else
     return set_err(c, PFSP_EINVAL, "no multi-instance kernel for this class");
   PFSP_HIP(c, hipGetLastError());
@@ -934,14 +993,10 @@ int launch_lb2m(Ctx *c, const FastClassLaunch &L, const DevInst *insts, const ui
 }
 
 void init_bound_attributes() {
-  (void)hipFuncSetAttribute((const void *)k_lb1m, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            160 * 1024);
-  (void)hipFuncSetAttribute((const void *)k_lb2m<20>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            160 * 1024);
-  (void)hipFuncSetAttribute((const void *)k_lb2m<64>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            160 * 1024);
-  (void)hipFuncSetAttribute((const void *)k_lb1, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            160 * 1024);
+  lds_limit((const void *)k_lb1m);
+  lds_limit((const void *)k_lb2m<20>);
+  lds_limit((const void *)k_lb2m<64>);
+  lds_limit((const void *)k_lb1);
   attr_lb2<Narrow, true>();
   attr_lb2<Narrow, false>();
   attr_lb2<Wide, true>();
@@ -953,6 +1008,7 @@ void init_bound_attributes() {
   attr_lb2f<24>();
   attr_lb2f<32>();
   attr_lb2f<64>();
+  (void)hipGetLastError();  // a refused attribute must not surface as a later launch error
 }
 
 static void lb1_shape(const Ctx *c, int count, int &b1, size_t &lds1, int &g1) {
@@ -1007,7 +1063,7 @@ int launch_bound_costs_ready(Ctx *c, const DevPool &pool, int kind, int ub, int 
   const int n = c->n;
   const bool subset = kind == PFSP_LB2_SUBSET;
   const bool log = pool.argpair != nullptr;
-  const int nmax = c->narrow && !c->force_generic ? fast_nmax(n) : 0;
+  const int nmax = c->narrow && !c->force_generic ? fast_nmax(n, c->l16) : 0;
   if (nmax) {
     // waves per block: the most resident waves per CU within 160 KiB of LDS
     int waves = 0, best = 0;

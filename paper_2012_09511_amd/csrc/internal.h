@@ -25,6 +25,7 @@ constexpr int kInt32Max = 0x7fffffff;
 struct DevInst {
   int n, m, P;
   int narrow;              // 1: ent holds packed 8-byte entries, else entw
+  int l16;                 // 1: every lag is below 2^16 (fast kernels with NMAX <= 32)
   const int *p;            // [n][m] processing times
   const int *T;            // [m] per-machine totals
   const uint2 *ent;        // [n][P] narrow entries: x = a | b << 16, y = lag | k << 24
@@ -61,6 +62,7 @@ struct Ctx {
   uint4 *d_entw = nullptr;
   uint8_t *d_pu = nullptr, *d_pv = nullptr;
   int narrow = 1;
+  int l16 = 1;
   // workspace: parent front/back/remaining [count][3][m]
   int *d_costs = nullptr;
   size_t costs_cap = 0;
@@ -90,7 +92,7 @@ struct Ctx {
   int cu_count = 256;
   DevInst inst() const {
     DevInst I;
-    I.n = n; I.m = m; I.P = P; I.narrow = narrow;
+    I.n = n; I.m = m; I.P = P; I.narrow = narrow; I.l16 = l16;
     I.p = d_p; I.T = d_T; I.ent = d_ent; I.entw = d_entw; I.pu = d_pu; I.pv = d_pv;
     return I;
   }
@@ -151,6 +153,7 @@ struct FastClassLaunch {
   int ntiles;
   int *queue;               // device tile counter (zeroed by the launcher)
   int waves, grid;
+  int cstride;              // ints per parent row of the costs workspace (3 * largest m)
 };
 size_t lb2m_lds_bytes(int nmax, int ppad, int nmax_jobs, int mmax, int waves);
 int launch_generic_instance(Ctx *c, const DevInst &I, const DevPool &pool, int ub, int *costs,

@@ -21,15 +21,20 @@
 
 namespace pfsp {
 
+// LDS budget of the persistent multi-instance kernels (160 KiB minus their
+// few bytes of static LDS)
+constexpr size_t kLdsM = 160 * 1024 - 64;
+
 struct MultiInst {
-  int n = 0, m = 0, P = 0, narrow = 1, cls = -1;  // cls: 0 -> NMAX 20, 1 -> NMAX 64, -1 generic
+  int n = 0, m = 0, P = 0, narrow = 1, l16 = 1;
+  int cls = -1;  // 0 -> NMAX 20, 1 -> NMAX 64, -1 generic
   int *d_p = nullptr, *d_T = nullptr;
   uint2 *d_ent = nullptr;
   uint4 *d_entw = nullptr;
   uint8_t *d_pu = nullptr, *d_pv = nullptr;
   DevInst view() const {
     DevInst I;
-    I.n = n; I.m = m; I.P = P; I.narrow = narrow;
+    I.n = n; I.m = m; I.P = P; I.narrow = narrow; I.l16 = l16;
     I.p = d_p; I.T = d_T; I.ent = d_ent; I.entw = d_entw; I.pu = d_pu; I.pv = d_pv;
     return I;
   }
@@ -86,7 +91,7 @@ static void multi_drop_graph(pfsp_multi *mt) {
 
 static int class_of(const MultiInst &x, const Ctx *c) {
   if (!x.narrow || c->force_generic) return -1;
-  if (x.n <= 20) return 0;
+  if (x.n <= 20 && x.l16) return 0;
   if (x.n <= 64) return 1;
   return -1;
 }
@@ -111,7 +116,7 @@ static int auto_waves(int nmax, int ppad, int nj, int mm) {
   int waves = 1, best = 0;
   for (int w = 8; w >= 1; --w) {
     const size_t l = lb2m_lds_bytes(nmax, ppad, nj, mm, w);
-    const int per_cu = l <= 160 * 1024 ? (int)((160 * 1024) / l) * w : 0;
+    const int per_cu = l <= kLdsM ? (int)((kLdsM) / l) * w : 0;
     if (per_cu > best) {
       best = per_cu;
       waves = w;
@@ -174,11 +179,12 @@ static int multi_enqueue(pfsp_multi *mt, int kind, const uint8_t *perm, const ui
     L.tiles = mt->d_tiles + mt->first[cls];
     L.ntiles = mt->first[cls + 1] - mt->first[cls];
     L.queue = mt->d_queue + cls;
+    L.cstride = 3 * mt->mmax;  // k_lb1m's row stride, not the class's
     L.waves = mt->waves[cls] > 0 ? mt->waves[cls] : auto_waves(L.nmax, L.ppad, L.nmax_jobs, L.mmax);
-    while (L.waves > 1 && lb2m_lds_bytes(L.nmax, L.ppad, L.nmax_jobs, L.mmax, L.waves) > 160 * 1024)
+    while (L.waves > 1 && lb2m_lds_bytes(L.nmax, L.ppad, L.nmax_jobs, L.mmax, L.waves) > kLdsM)
       --L.waves;
     const size_t lds = lb2m_lds_bytes(L.nmax, L.ppad, L.nmax_jobs, L.mmax, L.waves);
-    const int per_cu = std::max(1, (int)((160 * 1024) / std::max<size_t>(lds, 1)));
+    const int per_cu = std::max(1, (int)((kLdsM) / std::max<size_t>(lds, 1)));
     const int gpc = mt->grid_per_cu > 0 ? mt->grid_per_cu : per_cu;
     L.grid = std::max(1, std::min(L.ntiles, c->cu_count * gpc));
     rc = launch_lb2m(c, L, mt->d_insts, perm, d1, d2, stride, mt->d_ubs, mt->d_costs, out_lb,
@@ -336,6 +342,7 @@ int pfsp_multi_create(pfsp_ctx *h, int32_t count, const int32_t *n, const int32_
     x.m = m[k];
     x.P = x.m * (x.m - 1) / 2;
     x.narrow = maxp < 65536 && (int64_t)(x.m > 2 ? x.m - 2 : 0) * maxp < (1 << 24);
+    x.l16 = x.narrow && (int64_t)(x.m > 2 ? x.m - 2 : 0) * maxp < (1 << 16);
     const size_t P = x.P > 0 ? x.P : 1;
     if (hipMalloc(&x.d_p, (size_t)x.n * x.m * 4) != hipSuccess ||
         hipMalloc(&x.d_T, (size_t)x.m * 4) != hipSuccess || hipMalloc(&x.d_pu, P) != hipSuccess ||

@@ -58,6 +58,46 @@ __device__ __forceinline__ void transpose_max64(int (&acc)[64], int lane) {
   transpose_max_step<32>(acc, lane);
 }
 
+// The same reduction without the LDS crossbar (gfx950): the 32- and 16-lane
+// exchanges use v_permlane32_swap / v_permlane16_swap, which swap the upper
+// half-wave (odd 16-lane rows) of one register with the lower half-wave (even
+// rows) of another, so max() of the two results is already the folded pair;
+// the 8-, 4-, 2- and 1-lane steps use DPP (row rotation by 8, half-row mirror,
+// quad permutations), each pairing lanes that differ in the step's bit.
+template <int O>
+__device__ __forceinline__ int dpp_partner(int x) {
+  if constexpr (O == 8) return __builtin_amdgcn_mov_dpp(x, 0x128, 0xf, 0xf, false);  // row_ror:8
+  if constexpr (O == 4) return __builtin_amdgcn_mov_dpp(x, 0x141, 0xf, 0xf, false);  // half mirror
+  if constexpr (O == 2) return __builtin_amdgcn_mov_dpp(x, 0x4E, 0xf, 0xf, false);   // [2,3,0,1]
+  return __builtin_amdgcn_mov_dpp(x, 0xB1, 0xf, 0xf, false);                         // [1,0,3,2]
+}
+
+template <int O>
+__device__ __forceinline__ void transpose_max_dpp(int (&acc)[64], int lane) {
+  const bool hi = (lane & O) != 0;
+#pragma unroll
+  for (int j = 0; j < O; ++j) {
+    const int send = hi ? acc[j] : acc[O + j];
+    const int keep = hi ? acc[O + j] : acc[j];
+    acc[j] = max(keep, dpp_partner<O>(send));
+  }
+  if constexpr (O > 1) transpose_max_dpp<O / 2>(acc, lane);
+}
+
+__device__ __forceinline__ void transpose_max64_xl(int (&acc)[64], int lane) {
+#pragma unroll
+  for (int j = 0; j < 32; ++j) {
+    const auto r = __builtin_amdgcn_permlane32_swap(acc[j], acc[32 + j], false, false);
+    acc[j] = max((int)r[0], (int)r[1]);
+  }
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const auto r = __builtin_amdgcn_permlane16_swap(acc[j], acc[16 + j], false, false);
+    acc[j] = max((int)r[0], (int)r[1]);
+  }
+  transpose_max_dpp<8>(acc, lane);
+}
+
 // Same reduction carrying an argument: the larger value wins, equal values
 // keep the smaller argument.
 template <int O>

@@ -86,3 +86,15 @@ def test_autotune_keeps_results(ctx):
     lb, pr, dr = mt.bound(*dev, seg, ub, binding.LB2_FULL)
     _check(insts, perm, d1, d2, seg, ub, lb, pr, dr, binding.LB2_FULL)
     mt.close()
+
+
+def test_class_with_fewer_machines_than_batch(ctx):
+    """The n <= 64 class holds only an m = 10 instance while the batch's largest
+    m is 20: the costs rows must be read with the batch's stride."""
+    insts = [(20, 20, inputs.instance(20, 20, 17)), (50, 10, inputs.instance(50, 10, 19))]
+    perm, d1, d2, seg = _batch(insts, [64, 30], 91, 50)
+    ub = np.array([2400, 3200], dtype=np.int32)
+    mt = binding.Multi(ctx, [p for _, _, p in insts])
+    lb, pr, dr = mt.bound(*_dev(ctx, perm, d1, d2), seg, ub, binding.LB2_FULL)
+    _check(insts, perm, d1, d2, seg, ub, lb, pr, dr, binding.LB2_FULL)
+    mt.close()

@@ -132,7 +132,7 @@ int pfsp_load_instance(pfsp_ctx *h, int32_t n, int32_t m, const int32_t *p) {
   c->maxp = (int)maxp;
   // packed 8-byte pair entries need a, b < 2^16 and lag < 2^24
   c->narrow = maxp < 65536 && (int64_t)(m > 2 ? m - 2 : 0) * maxp < (1 << 24);
-  c->l16 = c->narrow && (int64_t)(m > 2 ? m - 2 : 0) * maxp < (1 << 16);
+  c->l16 = c->narrow && (int64_t)(m > 1 ? m - 1 : 0) * maxp < (1 << 16);
   c->p_host = (int *)malloc((size_t)n * m * 4);
   if (!c->p_host) return set_err(c, PFSP_ENOMEM, "host allocation failed");
   memcpy(c->p_host, p, (size_t)n * m * 4);

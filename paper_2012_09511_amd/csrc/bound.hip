@@ -754,6 +754,286 @@ __device__ void lb2f_parent(const DevInst &I, int Ppad, const FastLds<NMAX> &S,
   if (dirp && lane == 0) *dirp = (uint8_t)mm.dir();
 }
 
+// ---------------------------------------------------------------- quick LB2
+// LB2 for instances with n <= NMAX <= 32 and every a_j + l_j below 2^16.
+//
+// For a pair (u, v) and a child whose unscheduled set is U' (the parent's U
+// without the child's job j), the two-machine value is the maximum of three
+// terms: h_u + A(U') + t_u, h_v + B(U') + t_v, and h_u + T(U') + t_v, where
+// h and t are the child's heads and tails and T(U') is the longest
+// first-to-second machine path of the Johnson schedule of U' (Section 2.4).
+// The first two are one-machine bounds of machines u and v, never above LB1,
+// so LB2 = max(LB1, max over pairs of h_u + T(U') + t_v) and only the third
+// term is evaluated per child and pair.  With terms relative to B(U),
+// term_i = Y(<i) + a_i + l_i, Y(<i) = sum over members before i of a - b,
+// and the exclusive prefix/suffix maxima PM(i), SM(i) over the members of U
+// in Johnson order, removing member j gives
+//   T(U') - B(U) + a_j = max(PM(j) + a_j - b_j, SM(j))  =: Xa(j)
+//   T(U') - B(U) + b_j = Xa(j) + b_j - a_j               =: Xb(j)
+// so that, with f_u the start of j on machine u in the forward child and g_v
+// its start on machine v in the backward child,
+//   forward child:  f_u + Xa(j) + R_v + C2_v
+//   backward child: g_v + Xb(j) + C1_u + R_v.
+// One wave decomposes one parent; lane L takes pair 64 * pass + L, and the
+// per-child maxima over pairs are folded across lanes at the end.
+//
+// Block-shared LDS: ent [npass][NMAX][64] entries {b - a, k | (a + l) << 16}
+// in Johnson order (pairs >= P repeat pair 0, rows >= n hold job NMAX - 1
+// with zero times), uv [Ppad] (u | v << 8), and p transposed [m][32] plus a
+// copy with the machines reversed.  Per wave: X [NMAX][64] (Xa, Xb) by job,
+// child starts FBf [m][ROW] (forward, by machine) and FBb [m][ROW] (backward,
+// machines reversed), HTf/HTb [m] (head, tail + remaining work per machine
+// in scan order), C1, C2, R [m], and the inverse permutation inv [32].
+struct QuickLayout {
+  int ppad, mmax;
+  __host__ __device__ static constexpr int row(int nmax) { return nmax | 1; }
+  __host__ __device__ size_t block_bytes(int nmax) const {
+    return align16((size_t)nmax * ppad * 8) + align16((size_t)ppad * 4) +
+           align16((size_t)2 * mmax * 32 * 4);
+  }
+  __host__ __device__ size_t wave_bytes(int nmax) const {
+    return align16((size_t)nmax * 64 * 8) + align16((size_t)2 * mmax * row(nmax) * 4) +
+           align16((size_t)2 * mmax * 8) + align16((size_t)3 * mmax * 4) + 32 * 4;
+  }
+};
+
+template <int NMAX>
+struct QuickLds {
+  uint2 *ent;
+  int *uv, *pt, *pr;
+  int2 *X;
+  int *FBf, *FBb;
+  int2 *HTf, *HTb;
+  int *c1, *c2, *rr, *inv;
+  __device__ QuickLds(unsigned char *sm, const QuickLayout &L, int w) {
+    constexpr int ROW = QuickLayout::row(NMAX);
+    ent = (uint2 *)sm;
+    size_t off = align16((size_t)NMAX * L.ppad * 8);
+    uv = (int *)(sm + off);
+    off += align16((size_t)L.ppad * 4);
+    pt = (int *)(sm + off);
+    pr = pt + L.mmax * 32;
+    off += align16((size_t)2 * L.mmax * 32 * 4);
+    unsigned char *wb = sm + off + (size_t)w * L.wave_bytes(NMAX);
+    X = (int2 *)wb;
+    wb += align16((size_t)NMAX * 64 * 8);
+    FBf = (int *)wb;
+    FBb = FBf + L.mmax * ROW;
+    wb += align16((size_t)2 * L.mmax * ROW * 4);
+    HTf = (int2 *)wb;
+    HTb = HTf + L.mmax;
+    wb += align16((size_t)2 * L.mmax * 8);
+    c1 = (int *)wb;
+    c2 = c1 + L.mmax;
+    rr = c2 + L.mmax;
+    wb += align16((size_t)3 * L.mmax * 4);
+    inv = (int *)wb;
+  }
+};
+
+// Block-cooperative staging of one instance for the quick kernels (no
+// barrier inside).  The staged narrow entries hold x = a | b << 16 and
+// y = l | k << 24.
+template <int NMAX>
+__device__ void lb2q_stage(const DevInst &I, int Ppad, const QuickLds<NMAX> &S) {
+  const int n = I.n, m = I.m, P = I.P;
+  for (int x = threadIdx.x; x < NMAX * Ppad; x += blockDim.x) {
+    const int pass = x / (NMAX * 64), rem = x - pass * NMAX * 64;
+    const int i = rem >> 6, pi = pass * 64 + (rem & 63);
+    uint2 e = make_uint2(0u, (unsigned)(NMAX - 1));
+    if (i < n && P > 0) {
+      const uint2 s = I.ent[(size_t)i * P + (pi < P ? pi : 0)];
+      const unsigned a = s.x & 0xffffu, b = s.x >> 16, l = s.y & 0xffffffu, k = s.y >> 24;
+      e = make_uint2(b - a, k | ((a + l) << 16));
+    }
+    S.ent[x] = e;
+  }
+  for (int x = threadIdx.x; x < Ppad; x += blockDim.x) {
+    const int q = x < P ? x : 0;
+    S.uv[x] = P > 0 ? ((int)I.pu[q] | ((int)I.pv[q] << 8)) : 0;
+  }
+  for (int x = threadIdx.x; x < m * 32; x += blockDim.x) {
+    const int s = x >> 5, k = x & 31;
+    S.pt[x] = k < n ? I.p[k * m + s] : 0;
+    S.pr[x] = k < n ? I.p[k * m + (m - 1 - s)] : 0;
+  }
+}
+
+// Index of the sidx-th set bit among the first P bits of a pair mask (the
+// caller guarantees that it exists).
+__device__ __forceinline__ int nth_pair(const uint32_t *__restrict__ mw, int P, int sidx) {
+  const int words = (P + 31) >> 5;
+  for (int w = 0; w < words; ++w) {
+    uint32_t wbits = mw[w];
+    if (w == words - 1 && (P & 31)) wbits &= (1u << (P & 31)) - 1u;
+    const int cnt = __popc(wbits);
+    if (sidx < cnt) {
+      for (int t = 0; t < sidx; ++t) wbits &= wbits - 1u;
+      return w * 32 + __ffs(wbits) - 1;
+    }
+    sidx -= cnt;
+  }
+  return 0;
+}
+
+template <int NMAX, bool SUBSET>
+__device__ void lb2q_parent(const DevInst &I, int Ppad, const QuickLds<NMAX> &S,
+                            const uint8_t *__restrict__ row, int a, int b,
+                            const int *__restrict__ cs, const uint32_t *__restrict__ mw,
+                            int stride, int ub, int *__restrict__ lbrow,
+                            uint8_t *__restrict__ prow, uint8_t *__restrict__ dirp, int lane) {
+  constexpr int ROW = QuickLayout::row(NMAX);
+  const int n = I.n, m = I.m, P = I.P;
+  const int r = n - a - b;
+  if (r < 1 || cs[0] < 0) {  // flagged by k_lb1: not a valid node
+    fill_invalid(lbrow, prow, nullptr, stride, 0, lane, 64);
+    if (dirp && lane == 0) *dirp = 0;
+    return;
+  }
+  // inverse permutation, parent costs, per-direction head/tail tables
+  if (lane < n) S.inv[row[lane]] = lane;
+  for (int x = lane; x < m; x += 64) {
+    const int C1 = cs[x], C2 = cs[m + x], R = cs[2 * m + x];
+    S.c1[x] = C1;
+    S.c2[x] = C2;
+    S.rr[x] = R;
+    S.HTf[x] = make_int2(C1, R + C2);
+    S.HTb[m - 1 - x] = make_int2(C2, C1 + R);
+  }
+  wave_sync();
+  const int k = lane & 31;  // job of this lane; lanes >= 32 take its backward child
+  const bool bwd = lane >= 32;
+  const int slot = k < n ? S.inv[k] - a : -1;
+  const bool member = slot >= 0 && slot < r;
+  const uint32_t umask =
+      (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)__ballot(member && !bwd));
+  // LB1 of both children of job k, and the start times f (forward child,
+  // machines in order) or g (backward child, machines reversed)
+  int lb1 = 0;
+  if (k < NMAX) {
+    const int2 *HT = bwd ? S.HTb : S.HTf;
+    const int *PT = (bwd ? S.pr : S.pt) + k;
+    int *FB = (bwd ? S.FBb : S.FBf) + k;
+    int c = 0;
+#pragma unroll 4
+    for (int s = 0; s < m; ++s) {
+      const int2 ht = HT[s];
+      const int f = max(c, ht.x);
+      c = f + PT[s * 32];
+      FB[s * ROW] = f;
+      lb1 = max(lb1, f + ht.y);
+    }
+  }
+  wave_sync();
+  int nsel = 0;
+  if constexpr (SUBSET) {
+    const int words = (P + 31) >> 5;
+    for (int w = lane; w < words; w += 64)
+      nsel += __popc(mw[w] & (w == words - 1 && (P & 31) ? (1u << (P & 31)) - 1u : 0xffffffffu));
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) nsel += __shfl_xor(nsel, o, kWave);
+    nsel = __builtin_amdgcn_readfirstlane(nsel);
+  }
+  int accf[NMAX], accb[NMAX];
+#pragma unroll
+  for (int q = 0; q < NMAX; ++q) accf[q] = accb[q] = kNeg;
+  const int npass = SUBSET ? nsel : (P > 0 ? Ppad : 0);
+  int2 *Xl = S.X + lane;
+  for (int pc = 0; pc < npass; pc += 64) {
+    int pi = pc + lane;
+    // subset bounds: lanes past the selection repeat the first selected pair
+    if constexpr (SUBSET) pi = nth_pair(mw, P, pi < nsel ? pi : 0);
+    const int uvp = S.uv[pi];
+    const int u = uvp & 0xff, v = uvp >> 8;
+    const int K4 = S.rr[v] + S.c2[v], K5 = S.c1[u] + S.rr[v];
+    const int *Fu = S.FBf + u * ROW;
+    const int *Gv = S.FBb + (m - 1 - v) * ROW;
+    const uint2 *eb = S.ent + (pi >> 6) * (NMAX * 64) + (pi & 63);
+    uint2 e[NMAX];
+#pragma unroll
+    for (int i = 0; i < NMAX; ++i) e[i] = eb[i * 64];
+    // forward scan: terms of members (NEG for the others) and exclusive prefix maxima
+    int pm[NMAX], tm[NMAX];
+    int Y = 0, Pm = kNeg;
+#pragma unroll
+    for (int i = 0; i < NMAX; ++i) {
+      const int ng = __builtin_amdgcn_sbfe((int)umask, (int)e[i].y, 1);  // -1 if member
+      const int tt = Y + (int)(e[i].y >> 16);
+      tm[i] = (tt & ng) | (kNeg & ~ng);
+      pm[i] = Pm;
+      Pm = max(Pm, tm[i]);
+      Y = __mul24(ng, (int)e[i].x) + Y;  // Y += a - b for members
+    }
+    // backward scan: Xa, Xb by job
+    int Sm = kNeg;
+#pragma unroll
+    for (int i = NMAX - 1; i >= 0; --i) {
+      const int E = (int)e[i].x;
+      const int xa = max(pm[i] - E, Sm);
+      Xl[(e[i].y & 31u) * 64] = make_int2(xa, xa + E);
+      Sm = max(Sm, tm[i]);
+    }
+    // children of the members (each lane reads back only its own column of X)
+#pragma unroll
+    for (int q = 0; q < NMAX; ++q) {
+      if (umask & (1u << q)) {
+        const int2 x = Xl[q * 64];
+        accf[q] = max(accf[q], Fu[q] + x.x + K4);
+        accb[q] = max(accb[q], Gv[q] + x.y + K5);
+      }
+    }
+  }
+  const int t = transpose_max_fb<NMAX>(accf, accb, lane, kNeg);
+  const int val = member ? max(lb1, t) : kInt32Max;
+  if (member) {
+    const int o = (bwd ? stride : 0) + slot;
+    lbrow[o] = val;
+    prow[o] = val >= ub;
+  }
+  fill_invalid(lbrow, prow, nullptr, stride, r, lane, 64);
+  if (dirp) {
+    // MinMin over both children sets
+    const int cmn = wave_min_xl(val);
+    const uint64_t at = __ballot(member && val == cmn);
+    const int cf = __popc((uint32_t)at), cb = __popc((uint32_t)(at >> 32));
+    const int sv = member ? val : 0;
+    const int slo = half_sum(sv & 0xffff), shi = half_sum(sv >> 16);
+    const long long sf = ((long long)__builtin_amdgcn_readlane(shi, 0) << 16) +
+                         __builtin_amdgcn_readlane(slo, 0);
+    const long long sb = ((long long)__builtin_amdgcn_readlane(shi, 32) << 16) +
+                         __builtin_amdgcn_readlane(slo, 32);
+    MinMin mm;
+    mm.init();
+    mm.merge(cmn, cf, cb, sf, sb);
+    if (lane == 0) *dirp = (uint8_t)mm.dir();
+  }
+  wave_sync();  // the next parent rewrites this wave's tables
+}
+
+template <int NMAX, bool SUBSET>
+__global__ void __launch_bounds__(512)
+k_lb2q(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__restrict__ out_lb,
+       uint8_t *__restrict__ out_prune, int Ppad) {
+  extern __shared__ __align__(16) unsigned char sm[];
+  const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const QuickLayout L{Ppad, I.m};
+  const QuickLds<NMAX> S(sm, L, w);
+  lb2q_stage<NMAX>(I, Ppad, S);
+  __syncthreads();
+  const int count = pool.count_dev ? *pool.count_dev : pool.count;
+  if (pool.ub_dev) ub = *pool.ub_dev;
+  const int m = I.m;
+  for (int par = blockIdx.x * nw + w; par < count; par += gridDim.x * nw) {
+    const int ns = pool.n;  // row stride (>= n)
+    lb2q_parent<NMAX, SUBSET>(
+        I, Ppad, S, pool.perm + (size_t)par * ns, pool.d1[par], pool.d2[par],
+        costs + (size_t)par * 3 * m,
+        SUBSET ? pool.mask + (size_t)par * pool.mask_words : nullptr, ns, ub,
+        out_lb + (size_t)par * 2 * ns, out_prune + (size_t)par * 2 * ns,
+        pool.dir ? pool.dir + par : nullptr, lane);
+  }
+}
+
 // Single instance: the block stages the tables once, then each wave takes
 // parents in a grid-stride loop.
 template <int NMAX, bool SUBSET, bool LOG>
@@ -781,11 +1061,20 @@ k_lb2f(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
   }
 }
 
+template <int NMAX>
+__device__ __forceinline__ auto make_lds(unsigned char *sm, const FastLayout &L, int w) {
+  if constexpr (NMAX <= 32)
+    return QuickLds<NMAX>(sm, QuickLayout{L.ppad, L.mmax}, w);
+  else
+    return FastLds<NMAX>(sm, L, w);
+}
+
 // Several instances in one persistent launch.  Work is a list of tiles (an
 // instance and a range of its parents, tiles grouped by instance); each block
 // takes tiles from a device counter, restages the LDS tables when the
 // instance changes, and its waves decompose the tile's parents.  Pool rows
-// and outputs use a common stride (the largest n); costs use stride 3 * mmax.
+// and outputs use a common stride (the largest n); costs rows hold cstride
+// ints.
 template <int NMAX>
 __global__ void __launch_bounds__(512)
 k_lb2m(const DevInst *__restrict__ insts, const MultiTile *__restrict__ tiles, int ntiles,
@@ -795,8 +1084,10 @@ k_lb2m(const DevInst *__restrict__ insts, const MultiTile *__restrict__ tiles, i
        int *__restrict__ out_lb, uint8_t *__restrict__ out_prune, uint8_t *__restrict__ dir) {
   extern __shared__ __align__(16) unsigned char sm[];
   __shared__ int s_tile;
+  constexpr bool QUICK = NMAX <= 32;
+  using Lds = typename std::conditional<QUICK, QuickLds<NMAX>, FastLds<NMAX>>::type;
   const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const FastLds<NMAX> S(sm, L, w);
+  const Lds S = make_lds<NMAX>(sm, L, w);
   int cur = -1, Ppad = 0;
   DevInst I{};
   for (;;) {
@@ -810,23 +1101,39 @@ k_lb2m(const DevInst *__restrict__ insts, const MultiTile *__restrict__ tiles, i
       cur = T.inst;
       I = insts[cur];
       Ppad = (I.P + 63) / 64 * 64;
-      lb2f_stage<NMAX>(I, Ppad, S);
+      if constexpr (QUICK)
+        lb2q_stage<NMAX>(I, Ppad, S);
+      else
+        lb2f_stage<NMAX>(I, Ppad, S);
       __syncthreads();
     }
     const int ub = ubs[cur];
     for (int par = T.begin + w; par < T.end; par += nw) {
-      lb2f_parent<NMAX, false, false>(
-          I, Ppad, S, perm + (size_t)par * stride, d1[par], d2[par],
-          costs + (size_t)par * cstride, nullptr, stride, ub,
-          out_lb + (size_t)par * 2 * stride, out_prune + (size_t)par * 2 * stride, nullptr,
-          dir + par, lane);
+      if constexpr (QUICK)
+        lb2q_parent<NMAX, false>(I, Ppad, S, perm + (size_t)par * stride, d1[par], d2[par],
+                                 costs + (size_t)par * cstride, nullptr, stride, ub,
+                                 out_lb + (size_t)par * 2 * stride,
+                                 out_prune + (size_t)par * 2 * stride, dir + par, lane);
+      else
+        lb2f_parent<NMAX, false, false>(
+            I, Ppad, S, perm + (size_t)par * stride, d1[par], d2[par],
+            costs + (size_t)par * cstride, nullptr, stride, ub,
+            out_lb + (size_t)par * 2 * stride, out_prune + (size_t)par * 2 * stride, nullptr,
+            dir + par, lane);
     }
     __syncthreads();  // the tables may be restaged for the next tile
   }
 }
 
-static size_t lb2f_lds(const Ctx *c, int nmax, int waves) {
-  const FastLayout L{(c->P + 63) / 64 * 64, c->n, c->m};
+// LDS of the single-instance fast kernels: the quick layout for n <= 32
+// without argmax logging, the scan layout otherwise.
+static size_t lb2f_lds(const Ctx *c, int nmax, int waves, bool log) {
+  const int ppad = (c->P + 63) / 64 * 64;
+  if (nmax <= 32 && !log) {
+    const QuickLayout L{ppad, c->m};
+    return L.block_bytes(nmax) + (size_t)waves * L.wave_bytes(nmax);
+  }
+  const FastLayout L{ppad, c->n, c->m};
   return L.block_bytes(nmax) + (size_t)waves * L.wave_bytes(nmax);
 }
 
@@ -834,6 +1141,17 @@ template <int NMAX>
 static void launch_lb2f_n(bool subset, bool log, dim3 g, dim3 b, size_t lds, hipStream_t s,
                           const DevInst &I, const DevPool &pool, int ub, const int *costs,
                           int *out_lb, uint8_t *out_prune, int Ppad) {
+  if constexpr (NMAX <= 32) {
+    if (!log) {
+      if (subset)
+        hipLaunchKernelGGL((k_lb2q<NMAX, true>), g, b, lds, s, I, pool, ub, costs, out_lb,
+                           out_prune, Ppad);
+      else
+        hipLaunchKernelGGL((k_lb2q<NMAX, false>), g, b, lds, s, I, pool, ub, costs, out_lb,
+                           out_prune, Ppad);
+      return;
+    }
+  }
   if (subset) {
     if (log)
       hipLaunchKernelGGL((k_lb2f<NMAX, true, true>), g, b, lds, s, I, pool, ub, costs, out_lb,
@@ -852,7 +1170,7 @@ static void launch_lb2f_n(bool subset, bool log, dim3 g, dim3 b, size_t lds, hip
 }
 
 // Smallest compiled NMAX >= n (0 if none); the variants up to 32 jobs need
-// every lag below 2^16.
+// (m - 1) * max p below 2^16.
 static int fast_nmax(int n, int l16) {
   static const int sizes[] = {8, 12, 16, 20, 24, 32, 64};
   for (int s : sizes)
@@ -943,6 +1261,10 @@ static void attr_lb2() {
 
 template <int NMAX>
 static void attr_lb2f() {
+  if constexpr (NMAX <= 32) {
+    lds_limit((const void *)k_lb2q<NMAX, true>);
+    lds_limit((const void *)k_lb2q<NMAX, false>);
+  }
   lds_limit((const void *)k_lb2f<NMAX, true, true>);
   lds_limit((const void *)k_lb2f<NMAX, true, false>);
   lds_limit((const void *)k_lb2f<NMAX, false, true>);
@@ -950,6 +1272,10 @@ static void attr_lb2f() {
 }
 
 size_t lb2m_lds_bytes(int nmax, int ppad, int nmax_jobs, int mmax, int waves) {
+  if (nmax <= 32) {
+    const QuickLayout L{ppad, mmax};
+    return L.block_bytes(nmax) + (size_t)waves * L.wave_bytes(nmax);
+  }
   const FastLayout L{ppad, nmax_jobs, mmax};
   return L.block_bytes(nmax) + (size_t)waves * L.wave_bytes(nmax);
 }
@@ -974,7 +1300,7 @@ int launch_lb2m(Ctx *c, const FastClassLaunch &L, const DevInst *insts, const ui
                 const int *costs, int *out_lb, uint8_t *out_prune, uint8_t *dir, hipStream_t s) {
   if (L.ntiles <= 0) return PFSP_OK;
   const FastLayout FL{L.ppad, L.nmax_jobs, L.mmax};
-  const size_t lds = FL.block_bytes(L.nmax) + (size_t)L.waves * FL.wave_bytes(L.nmax);
+  const size_t lds = lb2m_lds_bytes(L.nmax, L.ppad, L.nmax_jobs, L.mmax, L.waves);
   if (lds > 160 * 1024 - 64) return set_err(c, PFSP_ERANGE, "multi-instance class exceeds LDS");
   hipLaunchKernelGGL(k_zero, dim3(1), dim3(1), 0, s, L.queue);
   KTimer kt(c, s, "k_lb2m");
@@ -1068,16 +1394,16 @@ int launch_bound_costs_ready(Ctx *c, const DevPool &pool, int kind, int ub, int 
     // waves per block: the most resident waves per CU within 160 KiB of LDS
     int waves = 0, best = 0;
     for (int w = 8; w >= 1; --w) {
-      const size_t l = lb2f_lds(c, nmax, w);
+      const size_t l = lb2f_lds(c, nmax, w, log);
       const int per_cu = l <= 160 * 1024 ? (int)((160 * 1024) / l) * w : 0;
       if (per_cu > best) {
         best = per_cu;
         waves = w;
       }
     }
-    if (c->lb2_waves > 0 && lb2f_lds(c, nmax, (int)c->lb2_waves) <= 160 * 1024)
+    if (c->lb2_waves > 0 && lb2f_lds(c, nmax, (int)c->lb2_waves, log) <= 160 * 1024)
       waves = (int)c->lb2_waves;
-    const size_t lds = waves ? lb2f_lds(c, nmax, waves) : 0;
+    const size_t lds = waves ? lb2f_lds(c, nmax, waves, log) : 0;
     if (waves) {
       const int Ppad = (c->P + 63) / 64 * 64;
       int grid = (pool.count + waves - 1) / waves;

@@ -25,7 +25,7 @@ constexpr int kInt32Max = 0x7fffffff;
 struct DevInst {
   int n, m, P;
   int narrow;              // 1: ent holds packed 8-byte entries, else entw
-  int l16;                 // 1: every lag is below 2^16 (fast kernels with NMAX <= 32)
+  int l16;                 // 1: (m - 1) * max p < 2^16, so every a + lag fits 16 bits (NMAX <= 32)
   const int *p;            // [n][m] processing times
   const int *T;            // [m] per-machine totals
   const uint2 *ent;        // [n][P] narrow entries: x = a | b << 16, y = lag | k << 24

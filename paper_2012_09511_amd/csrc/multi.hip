@@ -342,7 +342,7 @@ int pfsp_multi_create(pfsp_ctx *h, int32_t count, const int32_t *n, const int32_
     x.m = m[k];
     x.P = x.m * (x.m - 1) / 2;
     x.narrow = maxp < 65536 && (int64_t)(x.m > 2 ? x.m - 2 : 0) * maxp < (1 << 24);
-    x.l16 = x.narrow && (int64_t)(x.m > 2 ? x.m - 2 : 0) * maxp < (1 << 16);
+    x.l16 = x.narrow && (int64_t)(x.m > 1 ? x.m - 1 : 0) * maxp < (1 << 16);
     const size_t P = x.P > 0 ? x.P : 1;
     if (hipMalloc(&x.d_p, (size_t)x.n * x.m * 4) != hipSuccess ||
         hipMalloc(&x.d_T, (size_t)x.m * 4) != hipSuccess || hipMalloc(&x.d_pu, P) != hipSuccess ||

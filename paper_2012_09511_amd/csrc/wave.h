@@ -72,8 +72,8 @@ __device__ __forceinline__ int dpp_partner(int x) {
   return __builtin_amdgcn_mov_dpp(x, 0xB1, 0xf, 0xf, false);                         // [1,0,3,2]
 }
 
-template <int O>
-__device__ __forceinline__ void transpose_max_dpp(int (&acc)[64], int lane) {
+template <int O, int N>
+__device__ __forceinline__ void transpose_max_dpp(int (&acc)[N], int lane) {
   const bool hi = (lane & O) != 0;
 #pragma unroll
   for (int j = 0; j < O; ++j) {
@@ -96,6 +96,59 @@ __device__ __forceinline__ void transpose_max64_xl(int (&acc)[64], int lane) {
     acc[j] = max((int)r[0], (int)r[1]);
   }
   transpose_max_dpp<8>(acc, lane);
+}
+
+// Transposing max-reduction of per-job values held as two arrays, f (the
+// forward children) and b (the backward children), NJ <= 32 entries each: on
+// return lane q < 32 holds the maximum over all lanes of f[q] and lane 32 + q
+// that of b[q] (lanes whose index is >= NJ hold NEG).  Entries that are
+// known to be absent are never exchanged.
+template <int NJ>
+__device__ __forceinline__ int transpose_max_fb(const int (&f)[NJ], const int (&b)[NJ],
+                                                int lane, int neg) {
+  static_assert(NJ >= 1 && NJ <= 32, "one job per lane of a half-wave");
+  int t[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const auto r = __builtin_amdgcn_permlane32_swap(f[j], b[j], false, false);
+    t[j] = max((int)r[0], (int)r[1]);
+  }
+  int acc[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    if (j < NJ) {
+      const int hi = j + 16 < NJ ? t[j + 16 < NJ ? j + 16 : 0] : neg;
+      const auto r = __builtin_amdgcn_permlane16_swap(t[j], hi, false, false);
+      acc[j] = max((int)r[0], (int)r[1]);
+    } else {
+      acc[j] = neg;
+    }
+  }
+  transpose_max_dpp<8>(acc, lane);
+  return acc[0];
+}
+
+// Minimum over the wave through permlane swaps and DPP (no LDS crossbar).
+__device__ __forceinline__ int wave_min_xl(int x) {
+  auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+  x = min((int)r[0], (int)r[1]);
+  r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+  x = min((int)r[0], (int)r[1]);
+  x = min(x, dpp_partner<8>(x));
+  x = min(x, dpp_partner<4>(x));
+  x = min(x, dpp_partner<2>(x));
+  return min(x, dpp_partner<1>(x));
+}
+
+// Sum over each half-wave separately (lanes 0-31 and lanes 32-63); every
+// lane of a half receives its half's sum.
+__device__ __forceinline__ int half_sum(int x) {
+  const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+  x = (int)r[0] + (int)r[1];
+  x += dpp_partner<8>(x);
+  x += dpp_partner<4>(x);
+  x += dpp_partner<2>(x);
+  return x + dpp_partner<1>(x);
 }
 
 // Same reduction carrying an argument: the larger value wins, equal values

@@ -133,6 +133,7 @@ int pfsp_load_instance(pfsp_ctx *h, int32_t n, int32_t m, const int32_t *p) {
   // packed 8-byte pair entries need a, b < 2^16 and lag < 2^24
   c->narrow = maxp < 65536 && (int64_t)(m > 2 ? m - 2 : 0) * maxp < (1 << 24);
   c->l16 = c->narrow && (int64_t)(m > 1 ? m - 1 : 0) * maxp < (1 << 16);
+  c->x16 = c->l16 && (int64_t)(2 * n + 2 * m + 2) * maxp < (1 << 14);
   c->p_host = (int *)malloc((size_t)n * m * 4);
   if (!c->p_host) return set_err(c, PFSP_ENOMEM, "host allocation failed");
   memcpy(c->p_host, p, (size_t)n * m * 4);
@@ -252,8 +253,8 @@ int pfsp_set_option(pfsp_ctx *h, const char *key, int64_t value) {
     return set_err(c, PFSP_ERANGE, "log_stride must be in [1, 2^24]");
   if (!strcmp(key, "lb2_blocks_per_cu") && (value < 0 || value > 64))
     return set_err(c, PFSP_ERANGE, "lb2_blocks_per_cu must be in [0, 64]");
-  if (!strcmp(key, "lb2_waves") && (value < 0 || value > 8))
-    return set_err(c, PFSP_ERANGE, "lb2_waves must be in [0, 8]");
+  if (!strcmp(key, "lb2_waves") && (value < 0 || value > 12))
+    return set_err(c, PFSP_ERANGE, "lb2_waves must be in [0, 12]");
   if (!strcmp(key, "learned_topk") && (value < 1 || value > 2016))
     return set_err(c, PFSP_ERANGE, "learned_topk must be in [1, 2016]");
   if ((!strcmp(key, "use_graph") || !strcmp(key, "learned_exact") || !strcmp(key, "timing") ||
@@ -295,7 +296,7 @@ int pfsp_autotune(pfsp_ctx *h, const pfsp_pool *pool, int lb_kind, int32_t ub, i
   };
   std::vector<Cand> res;
   int rc = PFSP_OK;
-  for (int w : {0, 1, 2, 3, 4, 6, 8})
+  for (int w : {0, 1, 2, 3, 4, 6, 8, 12})
     for (int g : {0, 2, 4, 8, 16, 32}) {
       c->lb2_waves = w;
       c->lb2_blocks_per_cu = g;

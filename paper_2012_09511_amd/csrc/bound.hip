@@ -780,19 +780,20 @@ __device__ void lb2f_parent(const DevInst &I, int Ppad, const FastLds<NMAX> &S,
 // Block-shared LDS: ent [npass][NMAX][64] entries {b - a, k | (a + l) << 16}
 // in Johnson order (pairs >= P repeat pair 0, rows >= n hold job NMAX - 1
 // with zero times), uv [Ppad] (u | v << 8), and p transposed [m][32] plus a
-// copy with the machines reversed.  Per wave: X [NMAX][64] (Xa, Xb) by job,
+// copy with the machines reversed.  Per wave: X [NMAX][64] (Xa, Xb) by job
+// (two 16-bit halves when X16, see below),
 // child starts FBf [m][ROW] (forward, by machine) and FBb [m][ROW] (backward,
 // machines reversed), HTf/HTb [m] (head, tail + remaining work per machine
 // in scan order), C1, C2, R [m], and the inverse permutation inv [32].
 struct QuickLayout {
-  int ppad, mmax;
+  int ppad, mmax, x16;
   __host__ __device__ static constexpr int row(int nmax) { return nmax | 1; }
   __host__ __device__ size_t block_bytes(int nmax) const {
     return align16((size_t)nmax * ppad * 8) + align16((size_t)ppad * 4) +
            align16((size_t)2 * mmax * 32 * 4);
   }
   __host__ __device__ size_t wave_bytes(int nmax) const {
-    return align16((size_t)nmax * 64 * 8) + align16((size_t)2 * mmax * row(nmax) * 4) +
+    return align16((size_t)nmax * 64 * (x16 ? 4 : 8)) + align16((size_t)2 * mmax * row(nmax) * 4) +
            align16((size_t)2 * mmax * 8) + align16((size_t)3 * mmax * 4) + 32 * 4;
   }
 };
@@ -801,7 +802,7 @@ template <int NMAX>
 struct QuickLds {
   uint2 *ent;
   int *uv, *pt, *pr;
-  int2 *X;
+  void *X;
   int *FBf, *FBb;
   int2 *HTf, *HTb;
   int *c1, *c2, *rr, *inv;
@@ -815,8 +816,8 @@ struct QuickLds {
     pr = pt + L.mmax * 32;
     off += align16((size_t)2 * L.mmax * 32 * 4);
     unsigned char *wb = sm + off + (size_t)w * L.wave_bytes(NMAX);
-    X = (int2 *)wb;
-    wb += align16((size_t)NMAX * 64 * 8);
+    X = wb;
+    wb += align16((size_t)NMAX * 64 * (L.x16 ? 4 : 8));
     FBf = (int *)wb;
     FBb = FBf + L.mmax * ROW;
     wb += align16((size_t)2 * L.mmax * ROW * 4);
@@ -876,7 +877,13 @@ __device__ __forceinline__ int nth_pair(const uint32_t *__restrict__ mw, int P, 
   return 0;
 }
 
-template <int NMAX, bool SUBSET>
+// X16: the scan starts from Y = R_v + C2_v instead of 0, so the stored
+// Xa(j) + R_v + C2_v equals T(U') + a_j + C2_v, a sum of processing times
+// over disjoint cells of at most n + m jobs and machines, and the stored
+// values lie in [-max p, (n + m + 1) max p] (NEG16 - max p for a job that is
+// the only member).  With (2n + 2m + 2) max p < 2^14 both fit int16 and a
+// NEG16-derived term stays below zero, hence below LB1.
+template <int NMAX, bool SUBSET, bool X16>
 __device__ void lb2q_parent(const DevInst &I, int Ppad, const QuickLds<NMAX> &S,
                             const uint8_t *__restrict__ row, int a, int b,
                             const int *__restrict__ cs, const uint32_t *__restrict__ mw,
@@ -938,7 +945,9 @@ __device__ void lb2q_parent(const DevInst &I, int Ppad, const QuickLds<NMAX> &S,
 #pragma unroll
   for (int q = 0; q < NMAX; ++q) accf[q] = accb[q] = kNeg;
   const int npass = SUBSET ? nsel : (P > 0 ? Ppad : 0);
-  int2 *Xl = S.X + lane;
+  constexpr int NEGX = X16 ? -(1 << 14) : kNeg;
+  int2 *Xl = (int2 *)S.X + lane;
+  int *Xh = (int *)S.X + lane;
   for (int pc = 0; pc < npass; pc += 64) {
     int pi = pc + lane;
     // subset bounds: lanes past the selection repeat the first selected pair
@@ -949,37 +958,65 @@ __device__ void lb2q_parent(const DevInst &I, int Ppad, const QuickLds<NMAX> &S,
     const int *Fu = S.FBf + u * ROW;
     const int *Gv = S.FBb + (m - 1 - v) * ROW;
     const uint2 *eb = S.ent + (pi >> 6) * (NMAX * 64) + (pi & 63);
-    uint2 e[NMAX];
-#pragma unroll
-    for (int i = 0; i < NMAX; ++i) e[i] = eb[i * 64];
     // forward scan: terms of members (NEG for the others) and exclusive prefix maxima
     int pm[NMAX], tm[NMAX];
-    int Y = 0, Pm = kNeg;
+    int Y = X16 ? K4 : 0, Pm = NEGX;
 #pragma unroll
     for (int i = 0; i < NMAX; ++i) {
-      const int ng = __builtin_amdgcn_sbfe((int)umask, (int)e[i].y, 1);  // -1 if member
-      const int tt = Y + (int)(e[i].y >> 16);
-      tm[i] = (tt & ng) | (kNeg & ~ng);
+      const uint2 e = eb[i * 64];
+      const int ng = __builtin_amdgcn_sbfe((int)umask, (int)e.y, 1);  // -1 if member
+      const int tt = Y + (int)(e.y >> 16);
+      tm[i] = (tt & ng) | (NEGX & ~ng);
       pm[i] = Pm;
       Pm = max(Pm, tm[i]);
-      Y = __mul24(ng, (int)e[i].x) + Y;  // Y += a - b for members
+      Y = __mul24(ng, (int)e.x) + Y;  // Y += a - b for members
     }
-    // backward scan: Xa, Xb by job
-    int Sm = kNeg;
+    // backward scan: Xa, Xb by job (the entries are read again rather than
+    // held in registers)
+    int Sm = NEGX;
 #pragma unroll
     for (int i = NMAX - 1; i >= 0; --i) {
-      const int E = (int)e[i].x;
+      const uint2 e = eb[i * 64];
+      const int E = (int)e.x;
       const int xa = max(pm[i] - E, Sm);
-      Xl[(e[i].y & 31u) * 64] = make_int2(xa, xa + E);
+      if constexpr (X16)
+        Xh[(e.y & 31u) * 64] = (int)__builtin_amdgcn_perm((unsigned)(xa + E), (unsigned)xa,
+                                                          0x05040100u);
+      else
+        Xl[(e.y & 31u) * 64] = make_int2(xa, xa + E);
       Sm = max(Sm, tm[i]);
     }
-    // children of the members (each lane reads back only its own column of X)
+    const int K5x = X16 ? K5 - K4 : K5;  // X16: K4 is already inside X
+    // children, four jobs at a time so that their loads are issued together
+    // (each lane reads back only its own column of X; jobs that are not
+    // members accumulate values that are never used)
 #pragma unroll
-    for (int q = 0; q < NMAX; ++q) {
-      if (umask & (1u << q)) {
-        const int2 x = Xl[q * 64];
-        accf[q] = max(accf[q], Fu[q] + x.x + K4);
-        accb[q] = max(accb[q], Gv[q] + x.y + K5);
+    for (int g = 0; g < NMAX; g += 4) {
+      if (umask & (0xfu << g)) {
+        int xa[4], xb[4], fu[4], gv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (g + j < NMAX) {
+            if constexpr (X16) {
+              const int h = Xh[(g + j) * 64];
+              xa[j] = (int)(short)(h & 0xffff);
+              xb[j] = h >> 16;
+            } else {
+              const int2 x = Xl[(g + j) * 64];
+              xa[j] = x.x + K4;
+              xb[j] = x.y;
+            }
+            fu[j] = Fu[g + j];
+            gv[j] = Gv[g + j];
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (g + j < NMAX) {
+            accf[g + j] = max(accf[g + j], fu[j] + xa[j]);
+            accb[g + j] = max(accb[g + j], gv[j] + xb[j] + K5x);
+          }
+        }
       }
     }
   }
@@ -1010,13 +1047,14 @@ __device__ void lb2q_parent(const DevInst &I, int Ppad, const QuickLds<NMAX> &S,
   wave_sync();  // the next parent rewrites this wave's tables
 }
 
-template <int NMAX, bool SUBSET>
-__global__ void __launch_bounds__(512)
+// Up to 12 waves per block: three per SIMD, which the register use allows.
+template <int NMAX, bool SUBSET, bool X16>
+__global__ void __launch_bounds__(768)
 k_lb2q(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__restrict__ out_lb,
        uint8_t *__restrict__ out_prune, int Ppad) {
   extern __shared__ __align__(16) unsigned char sm[];
   const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const QuickLayout L{Ppad, I.m};
+  const QuickLayout L{Ppad, I.m, X16};
   const QuickLds<NMAX> S(sm, L, w);
   lb2q_stage<NMAX>(I, Ppad, S);
   __syncthreads();
@@ -1025,7 +1063,7 @@ k_lb2q(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
   const int m = I.m;
   for (int par = blockIdx.x * nw + w; par < count; par += gridDim.x * nw) {
     const int ns = pool.n;  // row stride (>= n)
-    lb2q_parent<NMAX, SUBSET>(
+    lb2q_parent<NMAX, SUBSET, X16>(
         I, Ppad, S, pool.perm + (size_t)par * ns, pool.d1[par], pool.d2[par],
         costs + (size_t)par * 3 * m,
         SUBSET ? pool.mask + (size_t)par * pool.mask_words : nullptr, ns, ub,
@@ -1061,10 +1099,10 @@ k_lb2f(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
   }
 }
 
-template <int NMAX>
+template <int NMAX, bool X16>
 __device__ __forceinline__ auto make_lds(unsigned char *sm, const FastLayout &L, int w) {
   if constexpr (NMAX <= 32)
-    return QuickLds<NMAX>(sm, QuickLayout{L.ppad, L.mmax}, w);
+    return QuickLds<NMAX>(sm, QuickLayout{L.ppad, L.mmax, X16}, w);
   else
     return FastLds<NMAX>(sm, L, w);
 }
@@ -1075,8 +1113,8 @@ __device__ __forceinline__ auto make_lds(unsigned char *sm, const FastLayout &L,
 // instance changes, and its waves decompose the tile's parents.  Pool rows
 // and outputs use a common stride (the largest n); costs rows hold cstride
 // ints.
-template <int NMAX>
-__global__ void __launch_bounds__(512)
+template <int NMAX, bool X16>
+__global__ void __launch_bounds__(NMAX <= 32 ? 768 : 512)
 k_lb2m(const DevInst *__restrict__ insts, const MultiTile *__restrict__ tiles, int ntiles,
        int *__restrict__ queue, FastLayout L, const uint8_t *__restrict__ perm,
        const uint8_t *__restrict__ d1, const uint8_t *__restrict__ d2, int stride,
@@ -1087,7 +1125,7 @@ k_lb2m(const DevInst *__restrict__ insts, const MultiTile *__restrict__ tiles, i
   constexpr bool QUICK = NMAX <= 32;
   using Lds = typename std::conditional<QUICK, QuickLds<NMAX>, FastLds<NMAX>>::type;
   const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const Lds S = make_lds<NMAX>(sm, L, w);
+  const Lds S = make_lds<NMAX, X16>(sm, L, w);
   int cur = -1, Ppad = 0;
   DevInst I{};
   for (;;) {
@@ -1110,7 +1148,7 @@ k_lb2m(const DevInst *__restrict__ insts, const MultiTile *__restrict__ tiles, i
     const int ub = ubs[cur];
     for (int par = T.begin + w; par < T.end; par += nw) {
       if constexpr (QUICK)
-        lb2q_parent<NMAX, false>(I, Ppad, S, perm + (size_t)par * stride, d1[par], d2[par],
+        lb2q_parent<NMAX, false, X16>(I, Ppad, S, perm + (size_t)par * stride, d1[par], d2[par],
                                  costs + (size_t)par * cstride, nullptr, stride, ub,
                                  out_lb + (size_t)par * 2 * stride,
                                  out_prune + (size_t)par * 2 * stride, dir + par, lane);
@@ -1130,7 +1168,7 @@ k_lb2m(const DevInst *__restrict__ insts, const MultiTile *__restrict__ tiles, i
 static size_t lb2f_lds(const Ctx *c, int nmax, int waves, bool log) {
   const int ppad = (c->P + 63) / 64 * 64;
   if (nmax <= 32 && !log) {
-    const QuickLayout L{ppad, c->m};
+    const QuickLayout L{ppad, c->m, c->x16};
     return L.block_bytes(nmax) + (size_t)waves * L.wave_bytes(nmax);
   }
   const FastLayout L{ppad, c->n, c->m};
@@ -1143,12 +1181,15 @@ static void launch_lb2f_n(bool subset, bool log, dim3 g, dim3 b, size_t lds, hip
                           int *out_lb, uint8_t *out_prune, int Ppad) {
   if constexpr (NMAX <= 32) {
     if (!log) {
-      if (subset)
-        hipLaunchKernelGGL((k_lb2q<NMAX, true>), g, b, lds, s, I, pool, ub, costs, out_lb,
-                           out_prune, Ppad);
-      else
-        hipLaunchKernelGGL((k_lb2q<NMAX, false>), g, b, lds, s, I, pool, ub, costs, out_lb,
-                           out_prune, Ppad);
+#define PFSP_Q(SUB, X)                                                                      \
+  hipLaunchKernelGGL((k_lb2q<NMAX, SUB, X>), g, b, lds, s, I, pool, ub, costs, out_lb, out_prune, \
+                     Ppad)
+      if (subset) {
+        if (I.x16) PFSP_Q(true, true); else PFSP_Q(true, false);
+      } else {
+        if (I.x16) PFSP_Q(false, true); else PFSP_Q(false, false);
+      }
+#undef PFSP_Q
       return;
     }
   }
@@ -1262,8 +1303,10 @@ static void attr_lb2() {
 template <int NMAX>
 static void attr_lb2f() {
   if constexpr (NMAX <= 32) {
-    lds_limit((const void *)k_lb2q<NMAX, true>);
-    lds_limit((const void *)k_lb2q<NMAX, false>);
+    lds_limit((const void *)k_lb2q<NMAX, true, true>);
+    lds_limit((const void *)k_lb2q<NMAX, false, true>);
+    lds_limit((const void *)k_lb2q<NMAX, true, false>);
+    lds_limit((const void *)k_lb2q<NMAX, false, false>);
   }
   lds_limit((const void *)k_lb2f<NMAX, true, true>);
   lds_limit((const void *)k_lb2f<NMAX, true, false>);
@@ -1271,9 +1314,9 @@ static void attr_lb2f() {
   lds_limit((const void *)k_lb2f<NMAX, false, false>);
 }
 
-size_t lb2m_lds_bytes(int nmax, int ppad, int nmax_jobs, int mmax, int waves) {
+size_t lb2m_lds_bytes(int nmax, int ppad, int nmax_jobs, int mmax, int waves, int x16) {
   if (nmax <= 32) {
-    const QuickLayout L{ppad, mmax};
+    const QuickLayout L{ppad, mmax, x16};
     return L.block_bytes(nmax) + (size_t)waves * L.wave_bytes(nmax);
   }
   const FastLayout L{ppad, nmax_jobs, mmax};
@@ -1300,18 +1343,21 @@ int launch_lb2m(Ctx *c, const FastClassLaunch &L, const DevInst *insts, const ui
                 const int *costs, int *out_lb, uint8_t *out_prune, uint8_t *dir, hipStream_t s) {
   if (L.ntiles <= 0) return PFSP_OK;
   const FastLayout FL{L.ppad, L.nmax_jobs, L.mmax};
-  const size_t lds = lb2m_lds_bytes(L.nmax, L.ppad, L.nmax_jobs, L.mmax, L.waves);
+  const size_t lds = lb2m_lds_bytes(L.nmax, L.ppad, L.nmax_jobs, L.mmax, L.waves, L.x16);
   if (lds > 160 * 1024 - 64) return set_err(c, PFSP_ERANGE, "multi-instance class exceeds LDS");
   hipLaunchKernelGGL(k_zero, dim3(1), dim3(1), 0, s, L.queue);
   KTimer kt(c, s, "k_lb2m");
-  if (L.nmax == 20)
-    hipLaunchKernelGGL(k_lb2m<20>, dim3(L.grid), dim3(64 * L.waves), lds, s, insts, L.tiles,
-                       L.ntiles, L.queue, FL, perm, d1, d2, stride, ubs, costs, L.cstride, out_lb,
-                       out_prune, dir);
+#define PFSP_M(N, X)                                                                        \
+  hipLaunchKernelGGL((k_lb2m<N, X>), dim3(L.grid), dim3(64 * L.waves), lds, s, insts, L.tiles,  \
+                     L.ntiles, L.queue, FL, perm, d1, d2, stride, ubs, costs, L.cstride, out_lb, \
+                     out_prune, dir)
+  if (L.nmax == 20 && L.x16)
+    PFSP_M(20, true);
+  else if (L.nmax == 20)
+    PFSP_M(20, false);
   else if (L.nmax == 64)
-    hipLaunchKernelGGL(k_lb2m<64>, dim3(L.grid), dim3(64 * L.waves), lds, s, insts, L.tiles,
-                       L.ntiles, L.queue, FL, perm, d1, d2, stride, ubs, costs, L.cstride, out_lb,
-                       out_prune, dir);
+    PFSP_M(64, false);
+#undef PFSP_M
   else
     return set_err(c, PFSP_EINVAL, "no multi-instance kernel for this class");
   PFSP_HIP(c, hipGetLastError());
@@ -1320,8 +1366,9 @@ int launch_lb2m(Ctx *c, const FastClassLaunch &L, const DevInst *insts, const ui
 
 void init_bound_attributes() {
   lds_limit((const void *)k_lb1m);
-  lds_limit((const void *)k_lb2m<20>);
-  lds_limit((const void *)k_lb2m<64>);
+  lds_limit((const void *)k_lb2m<20, true>);
+  lds_limit((const void *)k_lb2m<20, false>);
+  lds_limit((const void *)k_lb2m<64, false>);
   lds_limit((const void *)k_lb1);
   attr_lb2<Narrow, true>();
   attr_lb2<Narrow, false>();
@@ -1393,7 +1440,8 @@ int launch_bound_costs_ready(Ctx *c, const DevPool &pool, int kind, int ub, int 
   if (nmax) {
     // waves per block: the most resident waves per CU within 160 KiB of LDS
     int waves = 0, best = 0;
-    for (int w = 8; w >= 1; --w) {
+    const int wmax = nmax <= 32 && !log ? 12 : 8;
+    for (int w = wmax; w >= 1; --w) {
       const size_t l = lb2f_lds(c, nmax, w, log);
       const int per_cu = l <= 160 * 1024 ? (int)((160 * 1024) / l) * w : 0;
       if (per_cu > best) {
@@ -1401,7 +1449,8 @@ int launch_bound_costs_ready(Ctx *c, const DevPool &pool, int kind, int ub, int 
         waves = w;
       }
     }
-    if (c->lb2_waves > 0 && lb2f_lds(c, nmax, (int)c->lb2_waves, log) <= 160 * 1024)
+    if (c->lb2_waves > 0 && c->lb2_waves <= wmax &&
+        lb2f_lds(c, nmax, (int)c->lb2_waves, log) <= 160 * 1024)
       waves = (int)c->lb2_waves;
     const size_t lds = waves ? lb2f_lds(c, nmax, waves, log) : 0;
     if (waves) {

@@ -26,6 +26,7 @@ struct DevInst {
   int n, m, P;
   int narrow;              // 1: ent holds packed 8-byte entries, else entw
   int l16;                 // 1: (m - 1) * max p < 2^16, so every a + lag fits 16 bits (NMAX <= 32)
+  int x16;                 // 1: (2n + 2m + 2) * max p < 2^14 (quick kernels store X in 16 bits)
   const int *p;            // [n][m] processing times
   const int *T;            // [m] per-machine totals
   const uint2 *ent;        // [n][P] narrow entries: x = a | b << 16, y = lag | k << 24
@@ -63,6 +64,7 @@ struct Ctx {
   uint8_t *d_pu = nullptr, *d_pv = nullptr;
   int narrow = 1;
   int l16 = 1;
+  int x16 = 1;
   // workspace: parent front/back/remaining [count][3][m]
   int *d_costs = nullptr;
   size_t costs_cap = 0;
@@ -92,7 +94,7 @@ struct Ctx {
   int cu_count = 256;
   DevInst inst() const {
     DevInst I;
-    I.n = n; I.m = m; I.P = P; I.narrow = narrow; I.l16 = l16;
+    I.n = n; I.m = m; I.P = P; I.narrow = narrow; I.l16 = l16; I.x16 = x16;
     I.p = d_p; I.T = d_T; I.ent = d_ent; I.entw = d_entw; I.pu = d_pu; I.pv = d_pv;
     return I;
   }
@@ -154,8 +156,9 @@ struct FastClassLaunch {
   int *queue;               // device tile counter (zeroed by the launcher)
   int waves, grid;
   int cstride;              // ints per parent row of the costs workspace (3 * largest m)
+  int x16;                  // every instance of the class allows 16-bit X
 };
-size_t lb2m_lds_bytes(int nmax, int ppad, int nmax_jobs, int mmax, int waves);
+size_t lb2m_lds_bytes(int nmax, int ppad, int nmax_jobs, int mmax, int waves, int x16);
 int launch_generic_instance(Ctx *c, const DevInst &I, const DevPool &pool, int ub, int *costs,
                             int *out_lb, uint8_t *out_prune, hipStream_t s);
 int launch_lb1m(Ctx *c, const DevInst *insts, const long long *seg, int ninst, long long total,

@@ -26,7 +26,7 @@ namespace pfsp {
 constexpr size_t kLdsM = 160 * 1024 - 64;
 
 struct MultiInst {
-  int n = 0, m = 0, P = 0, narrow = 1, l16 = 1;
+  int n = 0, m = 0, P = 0, narrow = 1, l16 = 1, x16 = 1;
   int cls = -1;  // 0 -> NMAX 20, 1 -> NMAX 64, -1 generic
   int *d_p = nullptr, *d_T = nullptr;
   uint2 *d_ent = nullptr;
@@ -34,7 +34,7 @@ struct MultiInst {
   uint8_t *d_pu = nullptr, *d_pv = nullptr;
   DevInst view() const {
     DevInst I;
-    I.n = n; I.m = m; I.P = P; I.narrow = narrow; I.l16 = l16;
+    I.n = n; I.m = m; I.P = P; I.narrow = narrow; I.l16 = l16; I.x16 = x16;
     I.p = d_p; I.T = d_T; I.ent = d_ent; I.entw = d_entw; I.pu = d_pu; I.pv = d_pv;
     return I;
   }
@@ -98,24 +98,29 @@ static int class_of(const MultiInst &x, const Ctx *c) {
 
 static const int kClassNmax[2] = {20, 64};
 
+// waves per block that the class kernel's launch bounds allow
+static int max_waves(int nmax) { return nmax <= 32 ? 12 : 8; }
+
 // Class layout: the largest padded pair count, job count and machine count
-// of the instances of the class.
-static void class_layout(const pfsp_multi *mt, int cls, int &ppad, int &nj, int &mm) {
+// of the instances of the class, and whether all of them allow 16-bit X.
+static void class_layout(const pfsp_multi *mt, int cls, int &ppad, int &nj, int &mm, int &x16) {
   ppad = 64;
   nj = 1;
   mm = 1;
+  x16 = 1;
   for (const MultiInst &x : mt->in)
     if (x.cls == cls) {
       ppad = std::max(ppad, (x.P + 63) / 64 * 64);
       nj = std::max(nj, x.n);
       mm = std::max(mm, x.m);
+      x16 = x16 && x.x16;
     }
 }
 
-static int auto_waves(int nmax, int ppad, int nj, int mm) {
+static int auto_waves(int nmax, int ppad, int nj, int mm, int x16) {
   int waves = 1, best = 0;
-  for (int w = 8; w >= 1; --w) {
-    const size_t l = lb2m_lds_bytes(nmax, ppad, nj, mm, w);
+  for (int w = max_waves(nmax); w >= 1; --w) {
+    const size_t l = lb2m_lds_bytes(nmax, ppad, nj, mm, w, x16);
     const int per_cu = l <= kLdsM ? (int)((kLdsM) / l) * w : 0;
     if (per_cu > best) {
       best = per_cu;
@@ -175,15 +180,17 @@ static int multi_enqueue(pfsp_multi *mt, int kind, const uint8_t *perm, const ui
   for (int cls = 0; cls < 2; ++cls) {
     FastClassLaunch L;
     L.nmax = kClassNmax[cls];
-    class_layout(mt, cls, L.ppad, L.nmax_jobs, L.mmax);
+    class_layout(mt, cls, L.ppad, L.nmax_jobs, L.mmax, L.x16);
     L.tiles = mt->d_tiles + mt->first[cls];
     L.ntiles = mt->first[cls + 1] - mt->first[cls];
     L.queue = mt->d_queue + cls;
     L.cstride = 3 * mt->mmax;  // k_lb1m's row stride, not the class's
-    L.waves = mt->waves[cls] > 0 ? mt->waves[cls] : auto_waves(L.nmax, L.ppad, L.nmax_jobs, L.mmax);
-    while (L.waves > 1 && lb2m_lds_bytes(L.nmax, L.ppad, L.nmax_jobs, L.mmax, L.waves) > kLdsM)
+    L.waves = mt->waves[cls] > 0 ? std::min(mt->waves[cls], max_waves(L.nmax))
+                                 : auto_waves(L.nmax, L.ppad, L.nmax_jobs, L.mmax, L.x16);
+    while (L.waves > 1 &&
+           lb2m_lds_bytes(L.nmax, L.ppad, L.nmax_jobs, L.mmax, L.waves, L.x16) > kLdsM)
       --L.waves;
-    const size_t lds = lb2m_lds_bytes(L.nmax, L.ppad, L.nmax_jobs, L.mmax, L.waves);
+    const size_t lds = lb2m_lds_bytes(L.nmax, L.ppad, L.nmax_jobs, L.mmax, L.waves, L.x16);
     const int per_cu = std::max(1, (int)((kLdsM) / std::max<size_t>(lds, 1)));
     const int gpc = mt->grid_per_cu > 0 ? mt->grid_per_cu : per_cu;
     L.grid = std::max(1, std::min(L.ntiles, c->cu_count * gpc));
@@ -343,6 +350,7 @@ int pfsp_multi_create(pfsp_ctx *h, int32_t count, const int32_t *n, const int32_
     x.P = x.m * (x.m - 1) / 2;
     x.narrow = maxp < 65536 && (int64_t)(x.m > 2 ? x.m - 2 : 0) * maxp < (1 << 24);
     x.l16 = x.narrow && (int64_t)(x.m > 1 ? x.m - 1 : 0) * maxp < (1 << 16);
+    x.x16 = x.l16 && (int64_t)(2 * x.n + 2 * x.m + 2) * maxp < (1 << 14);
     const size_t P = x.P > 0 ? x.P : 1;
     if (hipMalloc(&x.d_p, (size_t)x.n * x.m * 4) != hipSuccess ||
         hipMalloc(&x.d_T, (size_t)x.m * 4) != hipSuccess || hipMalloc(&x.d_pu, P) != hipSuccess ||
@@ -416,7 +424,7 @@ int pfsp_multi_set_shape(pfsp_multi *mt, int32_t tile, int32_t waves_small, int3
                          int32_t blocks_per_cu) {
   if (!mt) return PFSP_EINVAL;
   Ctx *c = mt->c;
-  if (tile < 1 || tile > (1 << 20) || waves_small < 0 || waves_small > 8 || waves_large < 0 ||
+  if (tile < 1 || tile > (1 << 20) || waves_small < 0 || waves_small > 12 || waves_large < 0 ||
       waves_large > 8 || blocks_per_cu < 0 || blocks_per_cu > 64)
     return set_err(c, PFSP_ERANGE, "shape out of range");
   mt->tile = tile;
@@ -441,7 +449,7 @@ int pfsp_multi_autotune(pfsp_multi *mt, int lb_kind, const uint8_t *perm, const 
   if (reps < 1) reps = 3;
   PFSP_HIP(c, hipSetDevice(c->device));
   const int tiles[] = {64, 128, 256, 512, 1024};
-  const int wv[] = {0, 2, 4, 8};
+  const int wv[] = {0, 2, 4, 8, 12};
   const int gpc[] = {0, 2, 4, 8};
   struct Cand {
     int tile, w, g;

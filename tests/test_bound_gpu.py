@@ -107,6 +107,29 @@ def test_edge_depths(ctx, kind):
     _check(ctx, p, perm, d1, d2, kind, int(olb[olb < INT32_MAX].min()))
 
 
+@pytest.mark.parametrize("n,m,lo,hi", [
+    (20, 20, 150, 199),   # largest times that keep 16-bit X at n = m = 20
+    (32, 20, 100, 154),   # the same bound at n = 32
+    (20, 20, 1, 1500),    # 32-bit X
+    (12, 7, 2000, 3000),  # 32-bit X, short rows
+    (32, 5, 1, 16000),    # (m - 1) * max p just below 2^16
+])
+def test_quick_kernel_value_ranges(ctx, n, m, lo, hi):
+    """LB2 of the n <= 32 kernels at the edges of their value ranges, on
+    random pools plus the root and one-job-left nodes."""
+    rng = np.random.default_rng(n * 1000 + hi)
+    p = rng.integers(lo, hi + 1, size=(n, m)).astype(np.int32)
+    parts = [inputs.random_pool(n, 150, 31 + n), inputs.random_pool(n, 20, 32 + n, depth=0),
+             inputs.random_pool(n, 40, 33 + n, depth=n - 1)]
+    perm, d1, d2 = (np.concatenate([q[i] for q in parts]) for i in range(3))
+    olb = _check(ctx, p, perm, d1, d2, binding.LB2_FULL, INT32_MAX)
+    _check(ctx, p, perm, d1, d2, binding.LB2_FULL, int(np.median(olb[olb < INT32_MAX])))
+    P = m * (m - 1) // 2
+    mask = rng.integers(0, 1 << 32, size=(len(perm), (P + 31) // 32), dtype=np.uint64)
+    mask = (mask & rng.integers(0, 1 << 32, size=mask.shape, dtype=np.uint64)).astype(np.uint32)
+    _check(ctx, p, perm, d1, d2, binding.LB2_SUBSET, INT32_MAX, mask=mask)
+
+
 def test_wide_processing_times(ctx):
     """Processing times above 2^16 use the wide pair-table format."""
     n, m = 9, 6

@@ -193,6 +193,101 @@ k_lb1(DevInst I, DevPool pool, int ub, int *__restrict__ out_lb, uint8_t *__rest
           costs ? costs + (size_t)i * 3 * m : nullptr, write_out, flag);
 }
 
+// Parent costs for n <= 32 and m <= MMAX (the same values as k_lb1 in costs
+// mode): one lane per parent with the row and the per-machine front, back
+// and remaining work held in registers; p is staged in LDS with an odd row
+// stride, so that lanes reading different jobs hit different banks, and
+// zero-padded to MMAX machines, so that the machine loops need no bounds.
+template <int MMAX>
+__global__ void __launch_bounds__(256)
+k_costs(DevInst I, DevPool pool, int *__restrict__ costs, int *__restrict__ flag) {
+  extern __shared__ int sh[];
+  constexpr int MS = MMAX | 1;
+  const int n = I.n, m = I.m;
+  int *sp = sh;           // [n][MS]
+  int *sT = sh + n * MS;  // [MMAX] per-machine totals
+  for (int x = threadIdx.x; x < n * MS; x += blockDim.x) {
+    const int j = x / MS, k = x - j * MS;
+    sp[x] = k < m ? I.p[j * m + k] : 0;
+  }
+  for (int x = threadIdx.x; x < MMAX; x += blockDim.x) sT[x] = x < m ? I.T[x] : 0;
+  __syncthreads();
+  const int count = pool.count_dev ? *pool.count_dev : pool.count;
+  const int ns = pool.n;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+    const uint8_t *row = pool.perm + (size_t)i * ns;
+    const int a = pool.d1[i], b = pool.d2[i];
+    int *cs = costs + (size_t)i * 3 * m;
+    uint32_t rw[8];
+#pragma unroll
+    for (int w = 0; w < 8; ++w) {
+      uint32_t v = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (4 * w + q < n) v |= (uint32_t)row[4 * w + q] << (8 * q);
+      rw[w] = v;
+    }
+    // a row must be a permutation of 0..n-1 with d1 + d2 < n
+    uint32_t seen = 0;
+#pragma unroll
+    for (int x = 0; x < 32; ++x)
+      if (x < n) seen |= 1u << ((rw[x >> 2] >> (8 * (x & 3))) & 31u);
+    bool bad = a + b >= n || seen != (n == 32 ? 0xffffffffu : (1u << n) - 1u);
+#pragma unroll
+    for (int x = 0; x < 32; ++x)
+      if (x < n) bad |= ((rw[x >> 2] >> (8 * (x & 3))) & 0xffu) >= (uint32_t)n;
+    if (bad) {
+      flag[0] = 1;
+      for (int k = 0; k < 3 * m; ++k) cs[k] = 0;
+      cs[0] = -1;  // marks the row invalid for the LB2 kernels
+      continue;
+    }
+    int C1[MMAX], C2[MMAX], R[MMAX];
+#pragma unroll
+    for (int k = 0; k < MMAX; ++k) {
+      C1[k] = 0;
+      C2[k] = 0;
+      R[k] = sT[k];
+    }
+#pragma unroll
+    for (int x = 0; x < 32; ++x) {  // front of sigma1, Eq. (1)
+      if (x < a) {
+        const int *pj = sp + (int)((rw[x >> 2] >> (8 * (x & 3))) & 0xffu) * MS;
+        int c = 0;
+#pragma unroll
+        for (int k = 0; k < MMAX; ++k) {
+          const int q = pj[k];
+          c = max(c, C1[k]) + q;
+          C1[k] = c;
+          R[k] -= q;
+        }
+      }
+    }
+#pragma unroll
+    for (int x = 31; x >= 0; --x) {  // back of sigma2: jobs and machines reversed
+      if (x < n && x >= n - b) {
+        const int *pj = sp + (int)((rw[x >> 2] >> (8 * (x & 3))) & 0xffu) * MS;
+        int c = 0;
+#pragma unroll
+        for (int k = MMAX - 1; k >= 0; --k) {
+          const int q = pj[k];
+          c = max(c, C2[k]) + q;
+          C2[k] = c;
+          R[k] -= q;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < MMAX; ++k) {
+      if (k < m) {
+        cs[k] = C1[k];
+        cs[m + k] = C2[k];
+        cs[2 * m + k] = R[k];
+      }
+    }
+  }
+}
+
 // Several instances: parent i belongs to the instance k with
 // seg[k] <= i < seg[k + 1]; p is read from global memory (cached); costs rows
 // have stride 3 * mmax.
@@ -1400,6 +1495,26 @@ int launch_costs(Ctx *c, const DevPool &pool, hipStream_t s) {
   if (pool.count <= 0) return PFSP_OK;
   int rc = ensure_costs(c, pool.count);
   if (rc) return rc;
+  if (c->n <= 32 && c->m <= 32) {
+    const int mm = c->m <= 8 ? 8 : c->m <= 12 ? 12 : c->m <= 16 ? 16 : c->m <= 20 ? 20 : c->m <= 24 ? 24 : 32;
+    const size_t lds = ((size_t)c->n * (mm | 1) + mm) * 4;
+    int grid = (pool.count + 255) / 256;
+    if (grid > c->cu_count * 8) grid = c->cu_count * 8;
+    if (grid < 1) grid = 1;
+    KTimer kt(c, s, "k_costs");
+    switch (mm) {
+#define PFSP_C(M)                                                                          \
+  case M:                                                                                  \
+    hipLaunchKernelGGL(k_costs<M>, dim3(grid), dim3(256), lds, s, c->inst(), pool, c->d_costs, \
+                       c->d_flag);                                                         \
+    break;
+      PFSP_C(8) PFSP_C(12) PFSP_C(16) PFSP_C(20) PFSP_C(24) PFSP_C(32)
+#undef PFSP_C
+      default: break;
+    }
+    PFSP_HIP(c, hipGetLastError());
+    return PFSP_OK;
+  }
   int b1, g1;
   size_t lds1;
   lb1_shape(c, pool.count, b1, lds1, g1);

@@ -929,8 +929,10 @@ struct QuickLds {
 
 // Block-cooperative staging of one instance for the quick kernels (no
 // barrier inside).  The staged narrow entries hold x = a | b << 16 and
-// y = l | k << 24.
-template <int NMAX>
+// y = l | k << 24; the quick entries are {b - a, k | (a + l) << 16}, or
+// {(b - a) & 0xffff | (a + l) << 16, k} when X16 (then |b - a| and a + l are
+// below 2^14).
+template <int NMAX, bool X16>
 __device__ void lb2q_stage(const DevInst &I, int Ppad, const QuickLds<NMAX> &S) {
   const int n = I.n, m = I.m, P = I.P;
   for (int x = threadIdx.x; x < NMAX * Ppad; x += blockDim.x) {
@@ -940,7 +942,8 @@ __device__ void lb2q_stage(const DevInst &I, int Ppad, const QuickLds<NMAX> &S) 
     if (i < n && P > 0) {
       const uint2 s = I.ent[(size_t)i * P + (pi < P ? pi : 0)];
       const unsigned a = s.x & 0xffffu, b = s.x >> 16, l = s.y & 0xffffffu, k = s.y >> 24;
-      e = make_uint2(b - a, k | ((a + l) << 16));
+      e = X16 ? make_uint2(((b - a) & 0xffffu) | ((a + l) << 16), k)
+              : make_uint2(b - a, k | ((a + l) << 16));
     }
     S.ent[x] = e;
   }
@@ -976,8 +979,9 @@ __device__ __forceinline__ int nth_pair(const uint32_t *__restrict__ mw, int P, 
 // Xa(j) + R_v + C2_v equals T(U') + a_j + C2_v, a sum of processing times
 // over disjoint cells of at most n + m jobs and machines, and the stored
 // values lie in [-max p, (n + m + 1) max p] (NEG16 - max p for a job that is
-// the only member).  With (2n + 2m + 2) max p < 2^14 both fit int16 and a
-// NEG16-derived term stays below zero, hence below LB1.
+// the only member); the high half holds Xb + C1_u + R_v, likewise bounded.
+// With (2n + 2m + 2) max p < 2^14 both fit int16 and a NEG16-derived term
+// stays below zero, hence below LB1.
 template <int NMAX, bool SUBSET, bool X16>
 __device__ void lb2q_parent(const DevInst &I, int Ppad, const QuickLds<NMAX> &S,
                             const uint8_t *__restrict__ row, int a, int b,
@@ -1041,8 +1045,8 @@ __device__ void lb2q_parent(const DevInst &I, int Ppad, const QuickLds<NMAX> &S,
   for (int q = 0; q < NMAX; ++q) accf[q] = accb[q] = kNeg;
   const int npass = SUBSET ? nsel : (P > 0 ? Ppad : 0);
   constexpr int NEGX = X16 ? -(1 << 14) : kNeg;
-  int2 *Xl = (int2 *)S.X + lane;
-  int *Xh = (int *)S.X + lane;
+  int2 *__restrict__ Xl = (int2 *)S.X + lane;
+  int *__restrict__ Xh = (int *)S.X + lane;
   for (int pc = 0; pc < npass; pc += 64) {
     int pi = pc + lane;
     // subset bounds: lanes past the selection repeat the first selected pair
@@ -1052,36 +1056,42 @@ __device__ void lb2q_parent(const DevInst &I, int Ppad, const QuickLds<NMAX> &S,
     const int K4 = S.rr[v] + S.c2[v], K5 = S.c1[u] + S.rr[v];
     const int *Fu = S.FBf + u * ROW;
     const int *Gv = S.FBb + (m - 1 - v) * ROW;
-    const uint2 *eb = S.ent + (pi >> 6) * (NMAX * 64) + (pi & 63);
+    const uint2 *__restrict__ eb = S.ent + (pi >> 6) * (NMAX * 64) + (pi & 63);
     // forward scan: terms of members (NEG for the others) and exclusive prefix maxima
     int pm[NMAX], tm[NMAX];
+    unsigned ke[X16 ? NMAX : 1];  // X16: E in bits 0-15, job << 24 (bits 16-23 zero)
     int Y = X16 ? K4 : 0, Pm = NEGX;
 #pragma unroll
     for (int i = 0; i < NMAX; ++i) {
       const uint2 e = eb[i * 64];
       const int ng = __builtin_amdgcn_sbfe((int)umask, (int)e.y, 1);  // -1 if member
-      const int tt = Y + (int)(e.y >> 16);
+      const int tt = Y + (int)((X16 ? e.x : e.y) >> 16);
       tm[i] = (tt & ng) | (NEGX & ~ng);
       pm[i] = Pm;
       Pm = max(Pm, tm[i]);
-      Y = __mul24(ng, (int)e.x) + Y;  // Y += a - b for members
+      const int E = X16 ? (int)(short)(e.x & 0xffffu) : (int)e.x;
+      Y = __mul24(ng, E) + Y;  // Y += a - b for members
+      if constexpr (X16) ke[i] = __builtin_amdgcn_perm(e.y, e.x, 0x040c0100u);
     }
-    // backward scan: Xa, Xb by job (the entries are read again rather than
-    // held in registers)
+    // backward scan: Xa, Xb by job (the 32-bit entries are read again rather
+    // than held in registers; X16 keeps a packed copy from the forward scan)
     int Sm = NEGX;
+    const int K5x = K5 - K4;  // X16: the high half is Xb + K5 (K4 is already inside)
 #pragma unroll
     for (int i = NMAX - 1; i >= 0; --i) {
-      const uint2 e = eb[i * 64];
-      const int E = (int)e.x;
-      const int xa = max(pm[i] - E, Sm);
-      if constexpr (X16)
-        Xh[(e.y & 31u) * 64] = (int)__builtin_amdgcn_perm((unsigned)(xa + E), (unsigned)xa,
-                                                          0x05040100u);
-      else
+      if constexpr (X16) {
+        const int E = (int)(short)(ke[i] & 0xffffu);
+        const int xa = max(pm[i] - E, Sm);
+        *(int *)((char *)Xh + (ke[i] >> 16)) =
+            (int)__builtin_amdgcn_perm((unsigned)(xa + E + K5x), (unsigned)xa, 0x05040100u);
+      } else {
+        const uint2 e = eb[i * 64];
+        const int E = (int)e.x;
+        const int xa = max(pm[i] - E, Sm);
         Xl[(e.y & 31u) * 64] = make_int2(xa, xa + E);
+      }
       Sm = max(Sm, tm[i]);
     }
-    const int K5x = X16 ? K5 - K4 : K5;  // X16: K4 is already inside X
     // children, four jobs at a time so that their loads are issued together
     // (each lane reads back only its own column of X; jobs that are not
     // members accumulate values that are never used)
@@ -1099,7 +1109,7 @@ __device__ void lb2q_parent(const DevInst &I, int Ppad, const QuickLds<NMAX> &S,
             } else {
               const int2 x = Xl[(g + j) * 64];
               xa[j] = x.x + K4;
-              xb[j] = x.y;
+              xb[j] = x.y + K5;
             }
             fu[j] = Fu[g + j];
             gv[j] = Gv[g + j];
@@ -1109,7 +1119,7 @@ __device__ void lb2q_parent(const DevInst &I, int Ppad, const QuickLds<NMAX> &S,
         for (int j = 0; j < 4; ++j) {
           if (g + j < NMAX) {
             accf[g + j] = max(accf[g + j], fu[j] + xa[j]);
-            accb[g + j] = max(accb[g + j], gv[j] + xb[j] + K5x);
+            accb[g + j] = max(accb[g + j], gv[j] + xb[j]);
           }
         }
       }
@@ -1151,7 +1161,7 @@ k_lb2q(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
   const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const QuickLayout L{Ppad, I.m, X16};
   const QuickLds<NMAX> S(sm, L, w);
-  lb2q_stage<NMAX>(I, Ppad, S);
+  lb2q_stage<NMAX, X16>(I, Ppad, S);
   __syncthreads();
   const int count = pool.count_dev ? *pool.count_dev : pool.count;
   if (pool.ub_dev) ub = *pool.ub_dev;
@@ -1235,7 +1245,7 @@ k_lb2m(const DevInst *__restrict__ insts, const MultiTile *__restrict__ tiles, i
       I = insts[cur];
       Ppad = (I.P + 63) / 64 * 64;
       if constexpr (QUICK)
-        lb2q_stage<NMAX>(I, Ppad, S);
+        lb2q_stage<NMAX, X16>(I, Ppad, S);
       else
         lb2f_stage<NMAX>(I, Ppad, S);
       __syncthreads();

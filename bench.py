@@ -90,7 +90,11 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--workload", default="bound", choices=["bound", "search", "multi", "learned"])
-    ap.add_argument("--selector", default=os.path.join(ROOT, "profiles", "selector_n50m20.npy"))
+    ap.add_argument("--selector", default=os.path.join(ROOT, "paper_2012_09511_amd", "data",
+                                                       "selector_n50m20.npy"))
+    ap.add_argument("--topk", type=int, default=16, help="pairs kept by the learned selector")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="search steps as plain launches (profilers see graph replays as one)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the bounding path has no multi-GPU mode in this "
@@ -299,19 +303,28 @@ def bench_learned(args):
     ctx = binding.Context(0)
     params = np.load(args.selector)
     ctx.selector_set(params)
+    ctx.set_option("learned_topk", args.topk)
+    if args.no_graph:
+        ctx.set_option("use_graph", 0)
     rows = []
+    modes = (("full", binding.LB2_FULL), ("learned", binding.LB2_LEARNED))
     for seed in range(600, 608):
         p = inputs.instance(20, 20, seed)
         ctx.load_instance(p)
         ub0, _ = ctx.neh()
+        for _, kind in modes:   # untimed: workspaces and graph capture for this instance
+            ctx.search(ub0 + 1, 1, kind)
         res = {}
-        for name, kind in (("full", binding.LB2_FULL), ("learned", binding.LB2_LEARNED)):
+        for name, kind in modes:
+            torch.cuda.synchronize()
             t = time.perf_counter()
             r = ctx.search(ub0 + 1, 0, kind)
             res[name] = dict(best=r["best"], proven=r["proven"], nodes=r["nodes"],
-                             seconds=time.perf_counter() - t)
+                             children=r["children"], seconds=time.perf_counter() - t)
         assert res["full"]["best"] == res["learned"]["best"]
+        assert res["full"]["proven"] and res["learned"]["proven"]
         rows.append(dict(seed=seed, **res))
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
     tf = sum(x["full"]["seconds"] for x in rows)
     tl = sum(x["learned"]["seconds"] for x in rows)
     out = dict(metric="time to the same proven optimum, learned-pair vs full LB2",
@@ -319,7 +332,7 @@ def bench_learned(args):
                ms_per_step=tl * 1e3, higher_is_better=True, scaling="weak", vs_baseline=None,
                dtype="int32", data="synthetic",
                config=dict(workload="depth-first B&B, n=20 x m=20, seeds 600..607, NEH+1, "
-                                    "learned top-16 of 190 pairs"),
+                                    f"learned top-{args.topk} of 190 pairs"),
                full_seconds=tf, learned_seconds=tl, instances=rows)
     ctx.close()
     print(json.dumps(out))

@@ -162,8 +162,10 @@ static int pair_index(int m, int u, int v) { return u * (2 * m - u - 1) / 2 + (v
  *  - LB2 (Section 2.4): max over the machine pairs u < v (all of them, or the
  *    pairs whose bit is set in pair_mask) of the two-machine bound with heads
  *    C1[u], C1[v] and tails C2[u], C2[v]; the returned value is max(LB1, LB2).
- * If argpair is given it receives the lowest pair index attaining the pair
- * maximum (-1 when no pair is evaluated). */
+ * If argpair is given it receives the lowest index of a pair whose
+ * two-machine bound exceeds LB1 and attains the returned value, or -1 when
+ * the value equals LB1 (no pair is needed to reach it) or no pair is
+ * evaluated. */
 int64_t or_node_bound(int n, int m, const int32_t *p, const uint8_t *perm, int d1, int d2,
                       int kind, const uint32_t *pair_mask, int32_t *argpair) {
   int64_t C1[MAXM], C2[MAXM], R[MAXM];
@@ -189,6 +191,7 @@ int64_t or_node_bound(int n, int m, const int32_t *p, const uint8_t *perm, int d
         if (argpair) *argpair = pi;
       }
     }
+  if (argpair && best <= lb) *argpair = -1;
   return max64(lb, best);
 }
 

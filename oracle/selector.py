@@ -154,9 +154,10 @@ def topk_mask(scores, valid, k):
 
 
 def pair_histogram(argpair, d1, d2, m):
-    """Soft targets [B, 190]: the share of a node's 2(n-d) children whose full
-    LB2 is attained first (lowest index) by each pair; argpair holds instance
-    pair indices [B, 2, n] (-1: none)."""
+    """Soft targets [B, 190]: among a node's children whose full LB2 exceeds
+    LB1, the share whose LB2 is attained first (lowest index) by each pair;
+    argpair holds instance pair indices [B, 2, n] (-1: LB1 suffices, or no
+    child).  A node none of whose children needs a pair gets a zero row."""
     B, _, n = argpair.shape
     to20 = np.zeros(m * (m - 1) // 2, dtype=np.int64)
     for u in range(m):

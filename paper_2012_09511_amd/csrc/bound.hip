@@ -193,19 +193,104 @@ k_lb1(DevInst I, DevPool pool, int ub, int *__restrict__ out_lb, uint8_t *__rest
           costs ? costs + (size_t)i * 3 * m : nullptr, write_out, flag);
 }
 
-// Parent costs for n <= 32 and m <= MMAX (the same values as k_lb1 in costs
-// mode): one lane per parent with the row and the per-machine front, back
-// and remaining work held in registers; p is staged in LDS with an odd row
-// stride, so that lanes reading different jobs hit different banks, and
-// zero-padded to MMAX machines, so that the machine loops need no bounds.
+// One parent's costs (front C1, back C2, remaining R; Eq. (1)) for n <= 32
+// and m <= MMAX, written to cs[0 .. 3m); an invalid row (not a permutation of
+// 0..n-1, or d1 + d2 >= n) sets *flag and gets cs = {-1, 0, ...}.  The row and
+// the per-machine state stay in registers; sp holds p zero-padded to MMAX
+// machines (row stride MS) so that the machine loops need no bounds.
+template <int MMAX, int MS>
+__device__ __forceinline__ void costs_row(int n, int m, const int *__restrict__ sp,
+                                          const int *__restrict__ sT,
+                                          const uint8_t *__restrict__ row, int a, int b,
+                                          int *__restrict__ cs, int *__restrict__ flag) {
+  uint32_t rw[8];
+#pragma unroll
+  for (int w = 0; w < 8; ++w) {
+    uint32_t v = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (4 * w + q < n) v |= (uint32_t)row[4 * w + q] << (8 * q);
+    rw[w] = v;
+  }
+  uint32_t seen = 0;
+  bool bad = a + b >= n;
+#pragma unroll
+  for (int x = 0; x < 32; ++x) {
+    if (x < n) {
+      const uint32_t j = (rw[x >> 2] >> (8 * (x & 3))) & 0xffu;
+      seen |= 1u << (j & 31u);
+      bad |= j >= (uint32_t)n;
+    }
+  }
+  bad |= seen != (n == 32 ? 0xffffffffu : (1u << n) - 1u);
+  if (bad) {
+    flag[0] = 1;
+    for (int k = 0; k < 3 * m; ++k) cs[k] = 0;
+    cs[0] = -1;  // marks the row invalid for the LB2 kernels
+    return;
+  }
+  int C1[MMAX], C2[MMAX], R[MMAX];
+#pragma unroll
+  for (int k = 0; k < MMAX; ++k) {
+    C1[k] = 0;
+    C2[k] = 0;
+    R[k] = sT[k];
+  }
+#pragma unroll
+  for (int x = 0; x < 32; ++x) {  // front of sigma1
+    if (x < a) {
+      const int *pj = sp + (int)((rw[x >> 2] >> (8 * (x & 3))) & 0xffu) * MS;
+      int c = 0;
+#pragma unroll
+      for (int k = 0; k < MMAX; ++k) {
+        const int q = pj[k];
+        c = max(c, C1[k]) + q;
+        C1[k] = c;
+        R[k] -= q;
+      }
+    }
+  }
+#pragma unroll
+  for (int x = 31; x >= 0; --x) {  // back of sigma2: jobs and machines reversed
+    if (x < n && x >= n - b) {
+      const int *pj = sp + (int)((rw[x >> 2] >> (8 * (x & 3))) & 0xffu) * MS;
+      int c = 0;
+#pragma unroll
+      for (int k = MMAX - 1; k >= 0; --k) {
+        const int q = pj[k];
+        c = max(c, C2[k]) + q;
+        C2[k] = c;
+        R[k] -= q;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < MMAX; ++k) {
+    if (k < m) {
+      cs[k] = C1[k];
+      cs[m + k] = C2[k];
+      cs[2 * m + k] = R[k];
+    }
+  }
+}
+
+// Parent costs for n <= 32 and m <= MMAX (the values of k_lb1 in costs mode),
+// one lane per parent.  p is staged in LDS with an odd row stride, so that
+// lanes reading different jobs hit different banks.  The 64 rows of a wave
+// are contiguous in the workspace: each lane writes its row into the wave's
+// LDS tile and the wave then stores the tile with consecutive lanes on
+// consecutive words (whole cache lines rather than scattered words).
 template <int MMAX>
 __global__ void __launch_bounds__(256)
 k_costs(DevInst I, DevPool pool, int *__restrict__ costs, int *__restrict__ flag) {
   extern __shared__ int sh[];
   constexpr int MS = MMAX | 1;
-  const int n = I.n, m = I.m;
-  int *sp = sh;           // [n][MS]
-  int *sT = sh + n * MS;  // [MMAX] per-machine totals
+  const int n = I.n, m = I.m, cm = 3 * m;
+  const int RS = cm + 1;   // tile row stride (odd: the lanes' row writes spread over banks)
+  int *sp = sh;            // [n][MS]
+  int *sT = sh + n * MS;   // [MMAX] per-machine totals
+  const int lane = threadIdx.x & 63;
+  int *tile = sT + MMAX + (threadIdx.x >> 6) * 64 * RS;  // this wave's [64][RS]
   for (int x = threadIdx.x; x < n * MS; x += blockDim.x) {
     const int j = x / MS, k = x - j * MS;
     sp[x] = k < m ? I.p[j * m + k] : 0;
@@ -214,77 +299,21 @@ k_costs(DevInst I, DevPool pool, int *__restrict__ costs, int *__restrict__ flag
   __syncthreads();
   const int count = pool.count_dev ? *pool.count_dev : pool.count;
   const int ns = pool.n;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
-    const uint8_t *row = pool.perm + (size_t)i * ns;
-    const int a = pool.d1[i], b = pool.d2[i];
-    int *cs = costs + (size_t)i * 3 * m;
-    uint32_t rw[8];
-#pragma unroll
-    for (int w = 0; w < 8; ++w) {
-      uint32_t v = 0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (4 * w + q < n) v |= (uint32_t)row[4 * w + q] << (8 * q);
-      rw[w] = v;
+  // whole waves step together: the tile store is a wave-wide operation
+  for (int i0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63); i0 < count;
+       i0 += gridDim.x * blockDim.x) {
+    const int i = i0 + lane;
+    if (i < count)
+      costs_row<MMAX, MS>(n, m, sp, sT, pool.perm + (size_t)i * ns, pool.d1[i], pool.d2[i],
+                          tile + lane * RS, flag);
+    wave_sync();
+    const int rows = min(64, count - i0);
+    int *dst = costs + (size_t)i0 * cm;
+    for (int x = lane; x < rows * cm; x += 64) {
+      const int r = x / cm;
+      dst[x] = tile[r * RS + (x - r * cm)];
     }
-    // a row must be a permutation of 0..n-1 with d1 + d2 < n
-    uint32_t seen = 0;
-#pragma unroll
-    for (int x = 0; x < 32; ++x)
-      if (x < n) seen |= 1u << ((rw[x >> 2] >> (8 * (x & 3))) & 31u);
-    bool bad = a + b >= n || seen != (n == 32 ? 0xffffffffu : (1u << n) - 1u);
-#pragma unroll
-    for (int x = 0; x < 32; ++x)
-      if (x < n) bad |= ((rw[x >> 2] >> (8 * (x & 3))) & 0xffu) >= (uint32_t)n;
-    if (bad) {
-      flag[0] = 1;
-      for (int k = 0; k < 3 * m; ++k) cs[k] = 0;
-      cs[0] = -1;  // marks the row invalid for the LB2 kernels
-      continue;
-    }
-    int C1[MMAX], C2[MMAX], R[MMAX];
-#pragma unroll
-    for (int k = 0; k < MMAX; ++k) {
-      C1[k] = 0;
-      C2[k] = 0;
-      R[k] = sT[k];
-    }
-#pragma unroll
-    for (int x = 0; x < 32; ++x) {  // front of sigma1, Eq. (1)
-      if (x < a) {
-        const int *pj = sp + (int)((rw[x >> 2] >> (8 * (x & 3))) & 0xffu) * MS;
-        int c = 0;
-#pragma unroll
-        for (int k = 0; k < MMAX; ++k) {
-          const int q = pj[k];
-          c = max(c, C1[k]) + q;
-          C1[k] = c;
-          R[k] -= q;
-        }
-      }
-    }
-#pragma unroll
-    for (int x = 31; x >= 0; --x) {  // back of sigma2: jobs and machines reversed
-      if (x < n && x >= n - b) {
-        const int *pj = sp + (int)((rw[x >> 2] >> (8 * (x & 3))) & 0xffu) * MS;
-        int c = 0;
-#pragma unroll
-        for (int k = MMAX - 1; k >= 0; --k) {
-          const int q = pj[k];
-          c = max(c, C2[k]) + q;
-          C2[k] = c;
-          R[k] -= q;
-        }
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < MMAX; ++k) {
-      if (k < m) {
-        cs[k] = C1[k];
-        cs[m + k] = C2[k];
-        cs[2 * m + k] = R[k];
-      }
-    }
+    wave_sync();
   }
 }
 
@@ -485,7 +514,7 @@ k_lb2(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__res
         const int o = (bwd ? ns : 0) + cb + ql;
         lbrow[o] = val;
         prow[o] = val >= ub;
-        if (LOG) arow[o] = (int16_t)(acc[0] > kNeg ? arg[0] : -1);
+        if (LOG) arow[o] = (int16_t)(acc[0] > lb1 ? arg[0] : -1);  // -1: LB1 suffices
       }
       // MinMin over this chunk
       const int cmn = wave_min(val);
@@ -835,7 +864,7 @@ __device__ void lb2f_parent(const DevInst &I, int Ppad, const FastLds<NMAX> &S,
       const int o = (bwd ? stride : 0) + cb + ql;
       lbrow[o] = val;
       prow[o] = val >= ub;
-      if constexpr (LOG) arow[o] = (int16_t)(acc[0] > kNeg ? arg[0] : -1);
+      if constexpr (LOG) arow[o] = (int16_t)(acc[0] > lb1 ? arg[0] : -1);  // -1: LB1 suffices
     }
     const int cmn = wave_min(val);
     const int ccf = wave_popc(mine && !bwd && val == cmn);
@@ -1507,7 +1536,7 @@ int launch_costs(Ctx *c, const DevPool &pool, hipStream_t s) {
   if (rc) return rc;
   if (c->n <= 32 && c->m <= 32) {
     const int mm = c->m <= 8 ? 8 : c->m <= 12 ? 12 : c->m <= 16 ? 16 : c->m <= 20 ? 20 : c->m <= 24 ? 24 : 32;
-    const size_t lds = ((size_t)c->n * (mm | 1) + mm) * 4;
+    const size_t lds = ((size_t)c->n * (mm | 1) + mm + 4 * 64 * (3 * (size_t)c->m + 1)) * 4;
     int grid = (pool.count + 255) / 256;
     if (grid > c->cu_count * 8) grid = c->cu_count * 8;
     if (grid < 1) grid = 1;

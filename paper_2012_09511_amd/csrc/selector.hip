@@ -45,6 +45,10 @@ struct Selector {
   size_t train_cap = 0;
   int *to_inst = nullptr;  // [190]: instance pair index of each layout pair, -1 if absent
   int to_inst_m = -1;
+  int *order = nullptr;    // [190]: output visiting order of k_infer
+  float order_norm = -1.f;  // instance (norm) and weights the order was computed for;
+  int order_m = -1;         // the order is only a speed heuristic of k_infer
+  int order_ok = 0;
 };
 
 // round to nearest even bfloat16, kept as float
@@ -84,6 +88,170 @@ __global__ void k_features(DevInst I, DevPool pool, const int *__restrict__ cost
   f[61] = (float)b / (float)n;
   f[62] = (float)(n - a - b) / (float)n;
   f[63] = bad ? 0.f : (float)lb1 / norm;
+}
+
+// Features of one parent from its costs row (the formula of k_features).
+__device__ __forceinline__ void parent_features(int n, int m, const int *__restrict__ cs, int a,
+                                                int b, float norm, float (&f)[kIn]) {
+  const bool bad = cs[0] < 0;  // invalid row flagged by the costs kernel
+  int lb1 = 0;
+  for (int k = 0; k < m; ++k) lb1 = max(lb1, cs[k] + cs[2 * m + k] + cs[m + k]);
+#pragma unroll
+  for (int k = 0; k < kMMax; ++k) {
+    const bool on = k < m && !bad;
+    f[k] = on ? (float)cs[k] / norm : 0.f;
+    f[20 + k] = on ? (float)cs[m + k] / norm : 0.f;
+    f[40 + k] = on ? (float)cs[2 * m + k] / norm : 0.f;
+  }
+  f[60] = (float)a / (float)n;
+  f[61] = (float)b / (float)n;
+  f[62] = (float)(n - a - b) / (float)n;
+  f[63] = bad ? 0.f : (float)lb1 / norm;
+}
+
+// (v, id) ranks before (w, jd): larger score first, then lower layout index
+// (the order of k_select); an empty slot (jd < 0) ranks last.
+__device__ __forceinline__ bool ranks_before(float v, int id, float w, int jd) {
+  return jd < 0 || v > w || (v == w && id < jd);
+}
+
+// Selector inference for the bound kernels, fused: features from the costs
+// workspace, the MLP and the top-k, writing only the pair masks.  One thread
+// per row; each hidden layer goes through LDS ([unit][thread], each thread
+// touching only its own column) so that the next layer reads it from
+// statically indexed registers, and the weights are read at wave-uniform
+// addresses.  Every score is accumulated in the order of k_mlp_forward and
+// the top-k follows k_select's ranking, so the masks equal
+// select(forward(features)).  The output layer is visited in `order`, a
+// permutation that puts likely winners first so that the running k-th score
+// rises early and later scores rarely enter the list (the result does not
+// depend on the order).
+template <int KMAX>
+__global__ void __launch_bounds__(128)
+k_infer(DevInst I, DevPool pool, const int *__restrict__ costs, float norm,
+        const float *__restrict__ wq, const int *__restrict__ to_inst,
+        const int *__restrict__ order, int k, int words, uint32_t *__restrict__ mask) {
+  __shared__ float hs[kHid][128];
+  const int count = pool.count_dev ? *pool.count_dev : pool.count;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int t = threadIdx.x;
+  float x[kIn];
+  parent_features(I.n, I.m, costs + (size_t)i * 3 * I.m, pool.d1[i], pool.d2[i], norm, x);
+  for (int o = 0; o < kHid; ++o) {
+    float s = wq[kOffB1 + o];
+#pragma unroll
+    for (int j = 0; j < kIn; ++j) s = fmaf(wq[kOffW1 + o * kIn + j], x[j], s);
+    hs[o][t] = fmaxf(s, 0.f);
+  }
+#pragma unroll
+  for (int j = 0; j < kHid; ++j) x[j] = hs[j][t];
+  for (int o = 0; o < kHid; ++o) {
+    float s = wq[kOffB2 + o];
+#pragma unroll
+    for (int j = 0; j < kHid; ++j) s = fmaf(wq[kOffW2 + o * kHid + j], x[j], s);
+    hs[o][t] = fmaxf(s, 0.f);
+  }
+#pragma unroll
+  for (int j = 0; j < kHid; ++j) x[j] = hs[j][t];
+  float best[KMAX];
+  int idx[KMAX];
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) {
+    best[q] = -INFINITY;
+    idx[q] = -1;
+  }
+  float thr = -INFINITY;  // the k-th entry of the list
+  int thr_id = -1;
+  for (int r = 0; r < kOut; ++r) {
+    const int o = order[r];
+    if (to_inst[o] < 0) continue;
+    float v = wq[kOffB3 + o];
+#pragma unroll
+    for (int j = 0; j < kHid; ++j) v = fmaf(wq[kOffW3 + o * kHid + j], x[j], v);
+    if (ranks_before(v, o, thr, thr_id)) {
+      int id = o;
+#pragma unroll
+      for (int q = 0; q < KMAX; ++q) {
+        if (q < k && ranks_before(v, id, best[q], idx[q])) {
+          const float tv = best[q];
+          const int ti = idx[q];
+          best[q] = v;
+          idx[q] = id;
+          v = tv;
+          id = ti;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < KMAX; ++q)
+        if (q == k - 1) {
+          thr = best[q];
+          thr_id = idx[q];
+        }
+    }
+  }
+  uint32_t *mi = mask + (size_t)i * words;
+  uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0, w5 = 0;  // 190 pairs fit 6 words
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) {
+    if (q < k && idx[q] >= 0) {
+      const int pi = to_inst[idx[q]];
+      const uint32_t bit = 1u << (pi & 31);
+      const int wd = pi >> 5;
+      w0 |= wd == 0 ? bit : 0u;
+      w1 |= wd == 1 ? bit : 0u;
+      w2 |= wd == 2 ? bit : 0u;
+      w3 |= wd == 3 ? bit : 0u;
+      w4 |= wd == 4 ? bit : 0u;
+      w5 |= wd == 5 ? bit : 0u;
+    }
+  }
+  const uint32_t ws[6] = {w0, w1, w2, w3, w4, w5};
+#pragma unroll
+  for (int wd = 0; wd < 6; ++wd)
+    if (wd < words) mi[wd] = ws[wd];
+}
+
+// Visiting order of the output layer for k_infer: the layout pairs sorted by
+// their score at the root node of the loaded instance (C1 = C2 = 0, R = the
+// machine totals), highest first.  One thread; run when the weights or the
+// instance change.
+__global__ void k_order(DevInst I, float norm, const float *__restrict__ wq,
+                        int *__restrict__ order) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  float x[kIn], h1[kHid], h2[kHid], sc[kOut];
+  const int m = I.m;
+  int lb1 = 0;
+  for (int k = 0; k < kIn; ++k) x[k] = 0.f;
+  for (int k = 0; k < m && k < kMMax; ++k) x[40 + k] = (float)I.T[k] / norm;
+  for (int k = 0; k < m; ++k) lb1 = max(lb1, I.T[k]);
+  x[62] = 1.f;
+  x[63] = (float)lb1 / norm;
+  for (int o = 0; o < kHid; ++o) {
+    float s = wq[kOffB1 + o];
+    for (int j = 0; j < kIn; ++j) s = fmaf(wq[kOffW1 + o * kIn + j], x[j], s);
+    h1[o] = fmaxf(s, 0.f);
+  }
+  for (int o = 0; o < kHid; ++o) {
+    float s = wq[kOffB2 + o];
+    for (int j = 0; j < kHid; ++j) s = fmaf(wq[kOffW2 + o * kHid + j], h1[j], s);
+    h2[o] = fmaxf(s, 0.f);
+  }
+  for (int o = 0; o < kOut; ++o) {
+    float s = wq[kOffB3 + o];
+    for (int j = 0; j < kHid; ++j) s = fmaf(wq[kOffW3 + o * kHid + j], h2[j], s);
+    sc[o] = s;
+    order[o] = o;
+  }
+  for (int a = 1; a < kOut; ++a) {  // insertion sort, descending score
+    const int o = order[a];
+    int b = a - 1;
+    while (b >= 0 && sc[order[b]] < sc[o]) {
+      order[b + 1] = order[b];
+      --b;
+    }
+    order[b + 1] = o;
+  }
 }
 
 // Forward pass, one thread per row; the weights are read at wave-uniform
@@ -361,7 +529,7 @@ void selector_free(Ctx *c) {
   Selector *S = c->sel;
   if (!S) return;
   void *bufs[] = {S->master, S->wq, S->grad, S->am, S->av, S->feat, S->scores, S->mask, S->h1,
-                  S->h2, S->ds, S->dh1, S->dh2, S->rowloss, S->loss, S->to_inst};
+                  S->h2, S->ds, S->dh1, S->dh2, S->rowloss, S->loss, S->to_inst, S->order};
   for (void *p : bufs) (void)hipFree(p);
   delete S;
   c->sel = nullptr;
@@ -417,9 +585,20 @@ int learned_prepare(Ctx *c, int rows) {
   if (c->m > kMMax) return set_err(c, PFSP_ERANGE, "the learned selector covers m <= 20");
   if (c->learned_topk > kTopKMax)
     return set_err(c, PFSP_ERANGE, "learned_topk must be <= 32 for the learned bound");
-  int rc = sel_tables(c, c->sel);
+  Selector *S = c->sel;
+  int rc = sel_tables(c, S);
   if (rc) return rc;
-  return sel_rows(c, c->sel, rows > 0 ? rows : 1);
+  const float norm = instance_norm(c);
+  if (!S->order_ok || S->order_m != c->m || S->order_norm != norm) {
+    if (!S->order) PFSP_HIP(c, hipMalloc(&S->order, kOut * sizeof(int)));
+    hipLaunchKernelGGL(k_order, dim3(1), dim3(64), 0, c->stream, c->inst(), norm, S->wq,
+                       S->order);
+    PFSP_HIP(c, hipGetLastError());
+    S->order_ok = 1;
+    S->order_m = c->m;
+    S->order_norm = norm;
+  }
+  return sel_rows(c, S, rows > 0 ? rows : 1);
 }
 
 int launch_learned(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8_t *out_prune,
@@ -434,22 +613,17 @@ int launch_learned(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8_t *ou
   // parent costs (front, back, remaining) for the features
   rc = launch_costs(c, pool, s);
   if (rc) return rc;
-  const int g = (pool.count + 255) / 256;
-  {
-    KTimer kt(c, s, "k_features");
-    hipLaunchKernelGGL(k_features, dim3(g), dim3(256), 0, s, I, pool, c->d_costs,
-                       instance_norm(c), S->feat);
-  }
-  {
-    KTimer kt(c, s, "k_mlp_forward");
-    hipLaunchKernelGGL(k_mlp_forward, dim3(g), dim3(256), 0, s, S->wq, S->feat, pool.count,
-                       pool.count_dev, S->scores, S->to_inst);
-  }
   const int words = (c->P + 31) / 32;
+  const int k = (int)c->learned_topk;
   {
-    KTimer kt(c, s, "k_select");
-    hipLaunchKernelGGL(k_select, dim3(g), dim3(256), 0, s, S->scores, pool.count,
-                       pool.count_dev, (int)c->learned_topk, S->to_inst, words, S->mask);
+    KTimer kt(c, s, "k_infer");
+    const dim3 g((pool.count + 127) / 128), b(128);
+    if (k <= 16)
+      hipLaunchKernelGGL(k_infer<16>, g, b, 0, s, I, pool, c->d_costs, instance_norm(c), S->wq,
+                         S->to_inst, S->order, k, words, S->mask);
+    else
+      hipLaunchKernelGGL(k_infer<32>, g, b, 0, s, I, pool, c->d_costs, instance_norm(c), S->wq,
+                         S->to_inst, S->order, k, words, S->mask);
   }
   PFSP_HIP(c, hipGetLastError());
   DevPool sp = pool;
@@ -476,6 +650,7 @@ int pfsp_selector_set(pfsp_ctx *h, const float *params, int64_t count) {
   PFSP_HIP(c, hipMemset(S->am, 0, kParams * 4));
   PFSP_HIP(c, hipMemset(S->av, 0, kParams * 4));
   S->step = 0;
+  S->order_ok = 0;
   hipLaunchKernelGGL(k_round_weights, dim3((kParams + 255) / 256), dim3(256), 0, c->stream,
                      S->master, S->wq);
   PFSP_HIP(c, hipGetLastError());
@@ -640,6 +815,7 @@ int pfsp_selector_train_step(pfsp_ctx *h, const float *x, const float *target, i
     hipLaunchKernelGGL(k_round_weights, dim3((kParams + 255) / 256), dim3(256), 0, s, S->master,
                        S->wq);
     PFSP_HIP(c, hipGetLastError());
+    S->order_ok = 0;
   }
   float l = 0.f;
   PFSP_HIP(c, hipMemcpyAsync(&l, S->loss, 4, hipMemcpyDeviceToHost, s));

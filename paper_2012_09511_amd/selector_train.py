@@ -22,7 +22,7 @@ from . import binding, inputs
 
 
 def collect(ctx, instances, budget_nodes=2_000_000, log_capacity=200_000, log_stride=8,
-            max_per_instance=50_000, chunk=65536, seed=0):
+            max_per_instance=50_000, chunk=65536, seed=0, log=None):
     """Logs nodes of full-LB2 searches and returns (features [N,64], targets [N,190])
     as device tensors, plus per-instance statistics."""
     import torch
@@ -48,6 +48,8 @@ def collect(ctx, instances, budget_nodes=2_000_000, log_capacity=200_000, log_st
             feats.append(ctx.selector_features(*dev))
         stats.append(dict(n=n, m=m, nodes=r["nodes"], logged=len(perm), best=r["best"],
                           proven=r["proven"], seconds=round(time.time() - t0, 3)))
+        if log:
+            log(json.dumps(stats[-1]))
     X = torch.cat(feats) if feats else None
     T = torch.cat(targs) if targs else None
     return X, T, stats
@@ -88,7 +90,8 @@ def main():
     a, b = (int(x) for x in args.seeds.split("-"))
     ctx = binding.Context(0)
     insts = [(args.n, args.m, inputs.instance(args.n, args.m, s)) for s in range(a, b + 1)]
-    X, T, stats = collect(ctx, insts, budget_nodes=args.budget)
+    X, T, stats = collect(ctx, insts, budget_nodes=args.budget,
+                          log=lambda s: print(s, flush=True))
     print(json.dumps(dict(records=int(X.shape[0]), instances=stats)), flush=True)
     params, hist = train(ctx, X, T, epochs=args.epochs, lr=args.lr,
                          log=lambda s: print(s, flush=True))

@@ -229,11 +229,21 @@ def test_subset_between_lb1_and_full():
         lf, ap = oracle.node_bound(p, perm[i], int(d1[i]), int(d2[i]), oracle.LB2_FULL,
                                    with_argpair=True)
         assert l1 <= ls <= lf
-        # a subset holding the full bound's argmax pair reaches the full bound
+        # the logged pair alone reaches the full bound; none is logged when
+        # LB1 already does
         one = np.zeros(1, dtype=np.uint32)
-        one[0] = np.uint32(1 << ap)
+        if ap >= 0:
+            assert lf > l1
+            one[0] = np.uint32(1 << ap)
+        else:
+            assert lf == l1
         assert oracle.node_bound(p, perm[i], int(d1[i]), int(d2[i]), oracle.LB2_SUBSET,
                                  one) == lf
+        # ... and it is the lowest such pair
+        for q in range(ap if ap >= 0 else 0):
+            one[0] = np.uint32(1 << q)
+            assert oracle.node_bound(p, perm[i], int(d1[i]), int(d2[i]), oracle.LB2_SUBSET,
+                                     one) < lf
 
 
 # ----------------------------------------------------------- MinMin / prune

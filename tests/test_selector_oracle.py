@@ -96,13 +96,18 @@ def test_topk_and_histogram():
         chosen = sc[i][mk[i]]
         rest = sc[i][valid & ~mk[i]]
         assert chosen.min() >= rest.max()
-    # histogram of logged argmax pairs sums to one per node
+    # histogram of logged argmax pairs: one per node that has a child needing a
+    # pair (LB2 > LB1), zero otherwise
     n, m = 9, 6
     p = inputs.instance(n, m, 3)
     perm, d1, d2 = inputs.random_pool(n, 20, 4)
-    _, _, _, ap = oracle.bound_children(p, perm, d1, d2, oracle.LB2_FULL, with_argpair=True)
+    l1, _, _ = oracle.bound_children(p, perm, d1, d2, oracle.LB1)
+    l2, _, _, ap = oracle.bound_children(p, perm, d1, d2, oracle.LB2_FULL, with_argpair=True)
     h = S.pair_histogram(ap, d1, d2, m)
-    np.testing.assert_allclose(h.sum(axis=1), 1.0)
+    needs = ((l2 > l1) & (l1 < 2**31 - 1)).reshape(len(perm), -1).any(axis=1)
+    assert needs.any() and not needs.all()
+    np.testing.assert_allclose(h.sum(axis=1), needs.astype(float))
+    assert ((ap >= 0) == ((l2 > l1) & (l1 < 2**31 - 1))).all()
     assert not (h[:, ~S.valid_pairs(m)] > 0).any()
 
 

@@ -59,6 +59,26 @@ def bytes_lb2(n, m, count):
     return per * count
 
 
+def profiled_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a probe copy of known size), or None
+    when the kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_lb2q_20x20_1M.md")
+    try:
+        text = open(path).read()
+        rec = json.loads(text.split("```json")[1].split("```")[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in ("bound.hip", "wave.h", "internal.h"):
+        with open(os.path.join(ROOT, "paper_2012_09511_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if rec.get("source_sha256") != h.hexdigest() or not rec["kernel"].startswith(kernel):
+        return None
+    return rec
+
+
 def cpu_baseline(p, perm, d1, d2, kind, target_s=12.0):
     import oracle
     threads = len(os.sched_getaffinity(0))
@@ -151,10 +171,13 @@ def main():
     if kind != binding.LB1:
         ops = alg_ops_lb2(n, m, d1, d2)
         achieved = ops / (dom_ms * 1e-3)
+        prof = profiled_traffic("pfsp::k_lb2q<20, false, true>")
         roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_INT32_OPS / 1e12,
-                    unit="TOP/s", frac=achieved / PEAK_INT32_OPS, traffic=None,
+                    unit="TOP/s", frac=achieved / PEAK_INT32_OPS,
+                    traffic=prof["traffic_bytes"] if prof else None,
                     kernel=dom, kernel_ms=dom_ms, alg_ops_per_launch=ops,
-                    op_count="P*(n+32(n-d)) per parent: O(1)-per-child pair bound")
+                    op_count="P*(n+32(n-d)) per parent: O(1)-per-child pair bound",
+                    valu_issue_frac=prof["valu_issue_frac"] if prof else None)
     else:
         b = bytes_lb2(n, m, N)
         achieved = b / (dom_ms * 1e-3)

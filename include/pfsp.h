@@ -160,6 +160,13 @@ int pfsp_neh(pfsp_ctx *c, int32_t *perm_out, int32_t *cmax_out);
  * stream, default 0), "lb2_waves" (waves per block of the LB2 kernel, 0..12, 0 =
  * automatic), "lb2_blocks_per_cu" (cap on resident LB2 blocks per CU, 0 = 16),
  * "force_generic" (1 = always use the generic LB2 kernel),
+ * "search_filter" (1 = LB2 search steps close every parent whose children
+ * all have LB1 >= incumbent in the costs kernel and bound only the others
+ * with LB2; the tree is unchanged since LB2 >= LB1; default 1),
+ * "subset_group" (parents per wave of subset LB2 for n <= 32 when every
+ * stored value fits 16 bits: 2 or 4, each parent then gets 32 or 16 lanes
+ * and a selection of up to that many pairs costs one scan pass; 0 = one
+ * parent per wave for PFSP_LB2_SUBSET and by top-k for PFSP_LB2_LEARNED),
  * "log_capacity" (records kept by pfsp_search's node log, 0 = off) and
  * "log_stride" (log every log_stride-th decomposed node of a batch). */
 int pfsp_set_option(pfsp_ctx *c, const char *key, int64_t value);

@@ -82,6 +82,7 @@ int pfsp_create(pfsp_ctx **out, int device, void *hip_stream) {
   static bool attrs = false;
   if (!attrs) {
     init_bound_attributes();
+    init_selector_attributes();
     attrs = true;
   }
   hipDeviceProp_t prop;
@@ -230,6 +231,8 @@ static int64_t *opt_slot(Ctx *c, const char *key) {
   if (!strcmp(key, "timing")) return &c->timing;
   if (!strcmp(key, "force_generic")) return &c->force_generic;
   if (!strcmp(key, "lb2_waves")) return &c->lb2_waves;
+  if (!strcmp(key, "subset_group")) return &c->subset_group;
+  if (!strcmp(key, "search_filter")) return &c->search_filter;
   if (!strcmp(key, "lb2_blocks_per_cu")) return &c->lb2_blocks_per_cu;
   if (!strcmp(key, "log_capacity")) return &c->log_capacity;
   if (!strcmp(key, "log_stride")) return &c->log_stride;
@@ -253,11 +256,14 @@ int pfsp_set_option(pfsp_ctx *h, const char *key, int64_t value) {
     return set_err(c, PFSP_ERANGE, "log_stride must be in [1, 2^24]");
   if (!strcmp(key, "lb2_blocks_per_cu") && (value < 0 || value > 64))
     return set_err(c, PFSP_ERANGE, "lb2_blocks_per_cu must be in [0, 64]");
+  if (!strcmp(key, "subset_group") && value != 0 && value != 1 && value != 2 && value != 4)
+    return set_err(c, PFSP_ERANGE, "subset_group must be 0, 1, 2 or 4");
   if (!strcmp(key, "lb2_waves") && (value < 0 || value > 12))
     return set_err(c, PFSP_ERANGE, "lb2_waves must be in [0, 12]");
   if (!strcmp(key, "learned_topk") && (value < 1 || value > 2016))
     return set_err(c, PFSP_ERANGE, "learned_topk must be in [1, 2016]");
   if ((!strcmp(key, "use_graph") || !strcmp(key, "learned_exact") || !strcmp(key, "timing") ||
+       !strcmp(key, "search_filter") ||
        !strcmp(key, "force_generic")) &&
       value != 0 && value != 1)
     return set_err(c, PFSP_EINVAL, "flag options take 0 or 1");

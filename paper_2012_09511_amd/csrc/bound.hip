@@ -171,9 +171,32 @@ __device__ __forceinline__ void lb1_row(const DevInst &I, const int *__restrict_
   if (dirp) *dirp = (uint8_t)mm.dir();
 }
 
+// Filter outcome of pool row i (see CostFilter): closed rows get their prune
+// row and direction here, open rows are appended to the list (one atomic per
+// wave).  Whole waves call it.
+__device__ __forceinline__ void filter_row(const CostFilter &f, int i, bool live, bool open,
+                                           int ns, int lane) {
+  const bool app = live && open;
+  const uint64_t bal = __ballot(app);
+  int base = 0;
+  if (bal) {
+    if (lane == 0) base = atomicAdd(f.open, __popcll(bal));
+    base = __shfl(base, 0, kWave);
+  }
+  if (app) {
+    const int pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                              __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
+    f.rows[base + pos] = i;
+  } else if (live) {
+    uint8_t *pr = f.out_prune + (size_t)i * 2 * ns;
+    for (int x = 0; x < 2 * ns; ++x) pr[x] = 1;
+    if (f.dir) f.dir[i] = 0;
+  }
+}
+
 __global__ void __launch_bounds__(128)
 k_lb1(DevInst I, DevPool pool, int ub, int *__restrict__ out_lb, uint8_t *__restrict__ out_prune,
-      int *__restrict__ costs, int write_out, int *__restrict__ flag) {
+      int *__restrict__ costs, int write_out, int *__restrict__ flag, CostFilter f) {
   extern __shared__ int sh[];
   const int n = I.n, m = I.m, B = blockDim.x, t = threadIdx.x;
   int *sp = sh;  // p[n][m]
@@ -181,16 +204,43 @@ k_lb1(DevInst I, DevPool pool, int ub, int *__restrict__ out_lb, uint8_t *__rest
   __syncthreads();
   const int i = blockIdx.x * B + t;
   const int count = pool.count_dev ? *pool.count_dev : pool.count;
-  if (i >= count) return;
+  const bool filt = f.rows != nullptr;  // costs mode only
+  if (i >= count && !filt) return;
   if (pool.ub_dev) ub = *pool.ub_dev;
   int *C1 = sh + n * m + t;  // per-lane arrays, stride B (bank-conflict free)
   const int ns = pool.n;     // row stride of the pool and the outputs (>= n)
-  lb1_row(I, sp, C1, C1 + m * B, C1 + 2 * m * B, B, pool.perm + (size_t)i * ns, pool.d1[i],
-          pool.d2[i], ns, ub, write_out ? out_lb + (size_t)i * 2 * ns : nullptr,
-          write_out ? out_prune + (size_t)i * 2 * ns : nullptr,
-          write_out && pool.argpair ? pool.argpair + (size_t)i * 2 * ns : nullptr,
-          write_out && pool.dir ? pool.dir + i : nullptr,
-          costs ? costs + (size_t)i * 3 * m : nullptr, write_out, flag);
+  bool live = false, open = false;
+  if (i < count) {
+    live = !filt || !f.alive || f.alive[i];
+    const uint8_t *row = pool.perm + (size_t)i * ns;
+    const int a = pool.d1[i], b = pool.d2[i];
+    int *cs = costs ? costs + (size_t)i * 3 * m : nullptr;
+    lb1_row(I, sp, C1, C1 + m * B, C1 + 2 * m * B, B, row, a, b, ns, ub,
+            write_out ? out_lb + (size_t)i * 2 * ns : nullptr,
+            write_out ? out_prune + (size_t)i * 2 * ns : nullptr,
+            write_out && pool.argpair ? pool.argpair + (size_t)i * 2 * ns : nullptr,
+            write_out && pool.dir ? pool.dir + i : nullptr, cs, write_out, flag);
+    if (filt && live && cs[0] >= 0) {
+      // children's LB1 from the state lb1_row left in the lane's arrays
+      const int fub = *f.ub_dev;
+      const int *C2 = C1 + m * B, *R = C1 + 2 * m * B;
+      for (int x = a; x < n - b && !open; ++x) {
+        const int *pj = sp + row[x] * m;
+        int c = 0, lf = 0;
+        for (int k = 0; k < m; ++k) {
+          c = max(c, C1[k * B]) + pj[k];
+          lf = max(lf, c + R[k * B] - pj[k] + C2[k * B]);
+        }
+        int d = 0, lb = 0;
+        for (int k = m - 1; k >= 0; --k) {
+          d = max(d, C2[k * B]) + pj[k];
+          lb = max(lb, C1[k * B] + R[k * B] - pj[k] + d);
+        }
+        open = lf < fub || lb < fub;
+      }
+    }
+  }
+  if (filt) filter_row(f, i, live, open, ns, t & 63);
 }
 
 // One parent's costs (front C1, back C2, remaining R; Eq. (1)) for n <= 32
@@ -198,11 +248,16 @@ k_lb1(DevInst I, DevPool pool, int ub, int *__restrict__ out_lb, uint8_t *__rest
 // 0..n-1, or d1 + d2 >= n) sets *flag and gets cs = {-1, 0, ...}.  The row and
 // the per-machine state stay in registers; sp holds p zero-padded to MMAX
 // machines (row stride MS) so that the machine loops need no bounds.
+// *valid reports whether the row is a valid node.  With check, returns
+// whether some child (either direction) has LB1 < ub (the children's LB1 of
+// Section 2.4 from the same state; padded machines add nothing); without
+// check, returns whether the row is valid.
 template <int MMAX, int MS>
-__device__ __forceinline__ void costs_row(int n, int m, const int *__restrict__ sp,
+__device__ __forceinline__ bool costs_row(int n, int m, const int *__restrict__ sp,
                                           const int *__restrict__ sT,
                                           const uint8_t *__restrict__ row, int a, int b,
-                                          int *__restrict__ cs, int *__restrict__ flag) {
+                                          int *__restrict__ cs, int *__restrict__ flag,
+                                          bool check, int ub, bool *valid) {
   uint32_t rw[8];
 #pragma unroll
   for (int w = 0; w < 8; ++w) {
@@ -223,11 +278,12 @@ __device__ __forceinline__ void costs_row(int n, int m, const int *__restrict__ 
     }
   }
   bad |= seen != (n == 32 ? 0xffffffffu : (1u << n) - 1u);
+  *valid = !bad;
   if (bad) {
     flag[0] = 1;
     for (int k = 0; k < 3 * m; ++k) cs[k] = 0;
     cs[0] = -1;  // marks the row invalid for the LB2 kernels
-    return;
+    return false;
   }
   int C1[MMAX], C2[MMAX], R[MMAX];
 #pragma unroll
@@ -272,6 +328,28 @@ __device__ __forceinline__ void costs_row(int n, int m, const int *__restrict__ 
       cs[2 * m + k] = R[k];
     }
   }
+  if (!check) return true;
+  bool open = false;
+#pragma unroll
+  for (int x = 0; x < 32; ++x) {
+    if (x >= a && x < n - b && !open) {
+      const int *pj = sp + (int)((rw[x >> 2] >> (8 * (x & 3))) & 0xffu) * MS;
+      int c = 0, lf = 0;
+#pragma unroll
+      for (int k = 0; k < MMAX; ++k) {  // child with the job appended to sigma1
+        c = max(c, C1[k]) + pj[k];
+        lf = max(lf, c + R[k] - pj[k] + C2[k]);
+      }
+      int d = 0, lb = 0;
+#pragma unroll
+      for (int k = MMAX - 1; k >= 0; --k) {  // child with the job prepended to sigma2
+        d = max(d, C2[k]) + pj[k];
+        lb = max(lb, C1[k] + R[k] - pj[k] + d);
+      }
+      open = lf < ub || lb < ub;
+    }
+  }
+  return open;
 }
 
 // Parent costs for n <= 32 and m <= MMAX (the values of k_lb1 in costs mode),
@@ -282,7 +360,7 @@ __device__ __forceinline__ void costs_row(int n, int m, const int *__restrict__ 
 // consecutive words (whole cache lines rather than scattered words).
 template <int MMAX>
 __global__ void __launch_bounds__(256)
-k_costs(DevInst I, DevPool pool, int *__restrict__ costs, int *__restrict__ flag) {
+k_costs(DevInst I, DevPool pool, int *__restrict__ costs, int *__restrict__ flag, CostFilter f) {
   extern __shared__ int sh[];
   constexpr int MS = MMAX | 1;
   const int n = I.n, m = I.m, cm = 3 * m;
@@ -299,13 +377,20 @@ k_costs(DevInst I, DevPool pool, int *__restrict__ costs, int *__restrict__ flag
   __syncthreads();
   const int count = pool.count_dev ? *pool.count_dev : pool.count;
   const int ns = pool.n;
+  const bool filt = f.rows != nullptr;
+  const int ub = filt ? *f.ub_dev : 0;
   // whole waves step together: the tile store is a wave-wide operation
   for (int i0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63); i0 < count;
        i0 += gridDim.x * blockDim.x) {
     const int i = i0 + lane;
-    if (i < count)
-      costs_row<MMAX, MS>(n, m, sp, sT, pool.perm + (size_t)i * ns, pool.d1[i], pool.d2[i],
-                          tile + lane * RS, flag);
+    bool live = false, open = false, valid = false;
+    if (i < count) {
+      live = !filt || !f.alive || f.alive[i];
+      open = costs_row<MMAX, MS>(n, m, sp, sT, pool.perm + (size_t)i * ns, pool.d1[i],
+                                 pool.d2[i], tile + lane * RS, flag, filt && live, ub, &valid);
+      open = open && valid;
+    }
+    if (filt) filter_row(f, i, live, open, ns, lane);
     wave_sync();
     const int rows = min(64, count - i0);
     int *dst = costs + (size_t)i0 * cm;
@@ -353,6 +438,7 @@ k_lb2(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__res
   using ET = typename E::T;
   const int n = I.n, m = I.m, P = I.P;
   const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if ((int)blockIdx.x * nw >= (pool.count_dev ? *pool.count_dev : pool.count)) return;
   const ET *ent_g = (const ET *)(I.narrow ? (const void *)I.ent : (const void *)I.entw);
   size_t off = 0;
   ET *ent_s = (ET *)sm;
@@ -379,7 +465,8 @@ k_lb2(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__res
   if (pool.ub_dev) ub = *pool.ub_dev;
 
   const int ns = pool.n;  // row stride of the pool and the outputs (>= n)
-  for (int par = blockIdx.x * nw + w; par < count; par += gridDim.x * nw) {
+  for (int it = blockIdx.x * nw + w; it < count; it += gridDim.x * nw) {
+    const int par = pool.index ? pool.index[it] : it;
     const int a = pool.d1[par], b = pool.d2[par], r = n - a - b;
     int *lbrow = out_lb + (size_t)par * 2 * ns;
     uint8_t *prow = out_prune + (size_t)par * 2 * ns;
@@ -961,8 +1048,8 @@ struct QuickLds {
 // y = l | k << 24; the quick entries are {b - a, k | (a + l) << 16}, or
 // {(b - a) & 0xffff | (a + l) << 16, k} when X16 (then |b - a| and a + l are
 // below 2^14).
-template <int NMAX, bool X16>
-__device__ void lb2q_stage(const DevInst &I, int Ppad, const QuickLds<NMAX> &S) {
+template <int NMAX, bool X16, class Lds>
+__device__ void lb2q_stage(const DevInst &I, int Ppad, const Lds &S) {
   const int n = I.n, m = I.m, P = I.P;
   for (int x = threadIdx.x; x < NMAX * Ppad; x += blockDim.x) {
     const int pass = x / (NMAX * 64), rem = x - pass * NMAX * 64;
@@ -1188,14 +1275,16 @@ k_lb2q(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
        uint8_t *__restrict__ out_prune, int Ppad) {
   extern __shared__ __align__(16) unsigned char sm[];
   const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int count = pool.count_dev ? *pool.count_dev : pool.count;
+  if ((int)blockIdx.x * nw >= count) return;  // no parent for this block: skip the staging
   const QuickLayout L{Ppad, I.m, X16};
   const QuickLds<NMAX> S(sm, L, w);
   lb2q_stage<NMAX, X16>(I, Ppad, S);
   __syncthreads();
-  const int count = pool.count_dev ? *pool.count_dev : pool.count;
   if (pool.ub_dev) ub = *pool.ub_dev;
   const int m = I.m;
-  for (int par = blockIdx.x * nw + w; par < count; par += gridDim.x * nw) {
+  for (int it = blockIdx.x * nw + w; it < count; it += gridDim.x * nw) {
+    const int par = pool.index ? pool.index[it] : it;
     const int ns = pool.n;  // row stride (>= n)
     lb2q_parent<NMAX, SUBSET, X16>(
         I, Ppad, S, pool.perm + (size_t)par * ns, pool.d1[par], pool.d2[par],
@@ -1203,6 +1292,457 @@ k_lb2q(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
         SUBSET ? pool.mask + (size_t)par * pool.mask_words : nullptr, ns, ub,
         out_lb + (size_t)par * 2 * ns, out_prune + (size_t)par * 2 * ns,
         pool.dir ? pool.dir + par : nullptr, lane);
+  }
+}
+
+// ------------------------------------------------------- packed subset LB2
+// Subset LB2 with G parents per wave for n <= NMAX <= 32 and 16-bit X (the
+// method of k_lb2q): group g of L = 64 / G consecutive lanes takes parent g,
+// lane l the l-th pair of the parent's selection (lanes past it repeat the
+// first), so a selection of at most L pairs costs one scan pass for G
+// parents.  Per-child maxima are folded within each group; MinMin reduces
+// within each group.  Per parent and wave: start times FB [m][ROW] with f
+// (forward child, by machine) in the low and g (backward child, by machine)
+// in the high 16 bits (both below 2^14 when 16-bit X applies), C1, C2, R,
+// the inverse permutation, the children's LB1 and the compacted selection.
+struct PackLayout {
+  int ppad, mmax;
+  __host__ __device__ static constexpr int row(int nmax) { return nmax | 1; }
+  __host__ __device__ size_t block_bytes(int nmax) const {
+    return align16((size_t)nmax * ppad * 8) + align16((size_t)ppad * 4) +
+           align16((size_t)2 * mmax * 32 * 4);
+  }
+  __host__ __device__ size_t parent_bytes(int nmax) const {
+    return align16((size_t)mmax * row(nmax) * 4) + align16((size_t)3 * mmax * 4) + 32 * 4 +
+           64 * 4 + align16((size_t)ppad * 2) + align16((size_t)2 * mmax * 8);
+  }
+  __host__ __device__ size_t wave_bytes(int nmax, int g) const {
+    return align16((size_t)nmax * 64 * 4) + (size_t)g * parent_bytes(nmax);
+  }
+};
+
+template <int NMAX>
+struct PackParent {
+  uint32_t *fb;  // [m][ROW]: f | g << 16
+  int *c1, *c2, *rr, *inv, *lb1;
+  int16_t *sel;
+  int2 *htf, *htb;  // per scan step: (head, tail + remaining) forward, backward
+};
+
+template <int NMAX, int G>
+struct PackLds {
+  uint2 *ent;
+  int *uv, *pt, *pr;
+  int *X;
+  unsigned char *pb;  // parent 0's block; parent g's starts g * pstride later
+  int pstride, mmax, o_c, o_inv, o_lb1, o_sel, o_ht;
+  __device__ PackLds(unsigned char *sm, const PackLayout &L, int w) {
+    constexpr int ROW = PackLayout::row(NMAX);
+    ent = (uint2 *)sm;
+    size_t off = align16((size_t)NMAX * L.ppad * 8);
+    uv = (int *)(sm + off);
+    off += align16((size_t)L.ppad * 4);
+    pt = (int *)(sm + off);
+    pr = pt + L.mmax * 32;
+    off += align16((size_t)2 * L.mmax * 32 * 4);
+    unsigned char *wb = sm + off + (size_t)w * L.wave_bytes(NMAX, G);
+    X = (int *)wb;
+    pb = wb + align16((size_t)NMAX * 64 * 4);
+    pstride = (int)L.parent_bytes(NMAX);
+    mmax = L.mmax;
+    o_c = (int)align16((size_t)L.mmax * ROW * 4);
+    o_inv = o_c + (int)align16((size_t)3 * L.mmax * 4);
+    o_lb1 = o_inv + 32 * 4;
+    o_sel = o_lb1 + 64 * 4;
+    o_ht = o_sel + (int)align16((size_t)L.ppad * 2);
+  }
+  // tables of parent g of this wave (g may differ between lanes)
+  __device__ PackParent<NMAX> parent(int g) const {
+    unsigned char *b = pb + (size_t)g * pstride;
+    PackParent<NMAX> P;
+    P.fb = (uint32_t *)b;
+    P.c1 = (int *)(b + o_c);
+    P.c2 = P.c1 + mmax;
+    P.rr = P.c2 + mmax;
+    P.inv = (int *)(b + o_inv);
+    P.lb1 = (int *)(b + o_lb1);
+    P.sel = (int16_t *)(b + o_sel);
+    P.htf = (int2 *)(b + o_ht);
+    P.htb = P.htf + mmax;
+    return P;
+  }
+};
+
+// Reductions within groups of L consecutive lanes (L = 16 or 32).
+template <int L>
+__device__ __forceinline__ int group_min(int x) {
+  if constexpr (L == 32) {
+    const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    x = min((int)r[0], (int)r[1]);
+  }
+  x = min(x, dpp_partner<8>(x));
+  x = min(x, dpp_partner<4>(x));
+  x = min(x, dpp_partner<2>(x));
+  return min(x, dpp_partner<1>(x));
+}
+
+template <int L>
+__device__ __forceinline__ int group_sum(int x) {
+  if constexpr (L == 32) {
+    const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    x = (int)r[0] + (int)r[1];
+  }
+  x += dpp_partner<8>(x);
+  x += dpp_partner<4>(x);
+  x += dpp_partner<2>(x);
+  return x + dpp_partner<1>(x);
+}
+
+// acc[0..L) per lane -> lane p of each group holds the group maximum of acc[p].
+template <int L>
+__device__ __forceinline__ int group_transpose_max(int (&acc)[L], int lane) {
+  if constexpr (L == 32) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const auto r = __builtin_amdgcn_permlane16_swap(acc[j], acc[16 + j], false, false);
+      acc[j] = max((int)r[0], (int)r[1]);
+    }
+  }
+  transpose_max_dpp<8>(acc, lane);
+  return acc[0];
+}
+
+// Global inputs of one parent as the lanes hold them: row byte `lane` (lane
+// < n), costs C1, C2, R of machine `lane` (lane < m), mask word `lane`
+// (lane < words), and d1, d2.  Loaded one batch ahead so that their latency
+// overlaps the previous batch's work.
+struct PackFetch {
+  int rb, c1, c2, rr, d1, d2;
+  uint32_t mw;
+};
+
+__device__ __forceinline__ PackFetch pack_fetch(const DevPool &pool, int par, int n, int m,
+                                                const int *__restrict__ costs, int lane) {
+  PackFetch F{0, -1, 0, 0, 0, 0, 0u};
+  if (par >= 0) {
+    const int *cs = costs + (size_t)par * 3 * m;
+    F.d1 = pool.d1[par];
+    F.d2 = pool.d2[par];
+    if (lane < n) F.rb = pool.perm[(size_t)par * pool.n + lane];
+    if (lane < m) {
+      F.c1 = cs[lane];
+      F.c2 = cs[m + lane];
+      F.rr = cs[2 * m + lane];
+    }
+    if (lane < pool.mask_words) F.mw = pool.mask[(size_t)par * pool.mask_words + lane];
+  }
+  return F;
+}
+
+// One wave bounds the pool rows rows[0 .. G) (-1: none) from their prefetched
+// inputs F.
+template <int NMAX, int G>
+__device__ void lb2s_wave(const DevInst &I, int Ppad, const PackLds<NMAX, G> &S,
+                          const DevPool &pool, const int (&rows)[G], const PackFetch (&F)[G],
+                          int ub, int *__restrict__ out_lb, uint8_t *__restrict__ out_prune,
+                          int lane) {
+  constexpr int L = 64 / G;
+  constexpr int ROW = PackLayout::row(NMAX);
+  constexpr int NB = (2 * NMAX + L - 1) / L;  // blocks of L (direction, job) elements
+  constexpr int NEGX = -(1 << 14);
+  const int n = I.n, m = I.m, P = I.P, ns = pool.n;
+  const int gl = lane / L, l = lane % L;  // this lane's group and position in it
+  // per parent: validity, tables in LDS
+  int a_[G], r_[G];
+  bool ok_[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const int a = __builtin_amdgcn_readfirstlane(F[g].d1);
+    const int b = __builtin_amdgcn_readfirstlane(F[g].d2);
+    a_[g] = a;
+    r_[g] = n - a - b;
+    // cs[0] < 0 flags a row that the costs kernel found invalid
+    ok_[g] = rows[g] >= 0 && r_[g] >= 1 && __builtin_amdgcn_readfirstlane(F[g].c1) >= 0;
+    if (ok_[g]) {
+      const PackParent<NMAX> Q = S.parent(g);
+      if (lane < n) Q.inv[F[g].rb] = lane;
+      if (lane < m) {
+        Q.c1[lane] = F[g].c1;
+        Q.c2[lane] = F[g].c2;
+        Q.rr[lane] = F[g].rr;
+        Q.htf[lane] = make_int2(F[g].c1, F[g].rr + F[g].c2);
+        Q.htb[m - 1 - lane] = make_int2(F[g].c2, F[g].c1 + F[g].rr);
+      }
+    }
+  }
+  wave_sync();
+  // membership masks (uniform per parent), the children's LB1 and start times
+  uint32_t um[G];
+  uint32_t uany = 0;
+  const int k = lane & 31;
+  const bool bwd = lane >= 32;
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    um[g] = 0;
+    if (!ok_[g]) continue;
+    const PackParent<NMAX> Q = S.parent(g);
+    const int slot = k < n ? Q.inv[k] - a_[g] : -1;
+    um[g] = (uint32_t)__builtin_amdgcn_readfirstlane(
+        (int)(uint32_t)__ballot(!bwd && slot >= 0 && slot < r_[g]));
+    uany |= um[g];
+    int lb1 = 0;
+    if (k < NMAX) {
+      const int2 *HT = bwd ? Q.htb : Q.htf;
+      const int *PT = (bwd ? S.pr : S.pt) + k;
+      // f into the low half of [s][k] (forward, machine s), g into the high
+      // half of [m-1-s][k] (backward steps run over reversed machines)
+      unsigned short *fb = (unsigned short *)Q.fb + 2 * k + (bwd ? 1 + 2 * (m - 1) * ROW : 0);
+      const int fstep = bwd ? -2 * ROW : 2 * ROW;
+      int c = 0;
+#pragma unroll 4
+      for (int s = 0; s < m; ++s) {
+        const int2 ht = HT[s];
+        const int f = max(c, ht.x);
+        c = f + PT[s * 32];
+        fb[s * fstep] = (unsigned short)f;
+        lb1 = max(lb1, f + ht.y);
+      }
+    }
+    Q.lb1[lane] = lb1;
+  }
+  // compacted selections: pair indices whose bit is set, in index order
+  int nsel[G];
+  int nmax_sel = 0;
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    nsel[g] = 0;
+    if (!ok_[g]) continue;
+    for (int base = 0; base < P; base += 64) {
+      const int pi = base + lane;
+      const uint32_t w = (uint32_t)__shfl((int)F[g].mw, (pi >> 5) & 63, kWave);
+      const bool on = pi < P && ((w >> (pi & 31)) & 1u);
+      const uint64_t bal = __ballot(on);
+      const int pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
+      if (on) S.parent(g).sel[nsel[g] + pos] = (int16_t)pi;
+      nsel[g] += __popcll(bal);
+    }
+    nmax_sel = max(nmax_sel, nsel[g]);
+  }
+  wave_sync();
+  // this lane's parent
+  uint32_t umask = 0;
+  int nsg = 0;
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+    if (gl == g) {
+      umask = um[g];
+      nsg = nsel[g];
+    }
+  const PackParent<NMAX> Q = S.parent(gl);  // this lane's parent
+  int accf[NMAX], accb[NMAX];
+#pragma unroll
+  for (int q = 0; q < NMAX; ++q) accf[q] = accb[q] = kNeg;
+  int *__restrict__ Xh = S.X + lane;
+  for (int pc = 0; pc < nmax_sel; pc += L) {
+    const int idx = pc + l;
+    const int pi = nsg > 0 ? Q.sel[idx < nsg ? idx : 0] : 0;
+    const int uvp = S.uv[pi];
+    const int u = uvp & 0xff, v = uvp >> 8;
+    const int K4 = Q.rr[v] + Q.c2[v], K5 = Q.c1[u] + Q.rr[v];
+    const unsigned short *Fu = (const unsigned short *)(Q.fb + u * ROW);
+    const unsigned short *Gv = (const unsigned short *)(Q.fb + v * ROW) + 1;
+    const uint2 *__restrict__ eb = S.ent + (pi >> 6) * (NMAX * 64) + (pi & 63);
+    int pm[NMAX], tm[NMAX];
+    unsigned ke[NMAX];
+    int Y = K4, Pm = NEGX;
+#pragma unroll
+    for (int i = 0; i < NMAX; ++i) {
+      const uint2 e = eb[i * 64];
+      const int ng = __builtin_amdgcn_sbfe((int)umask, (int)e.y, 1);
+      const int tt = Y + (int)(e.x >> 16);
+      tm[i] = (tt & ng) | (NEGX & ~ng);
+      pm[i] = Pm;
+      Pm = max(Pm, tm[i]);
+      Y = __mul24(ng, (int)(short)(e.x & 0xffffu)) + Y;
+      ke[i] = __builtin_amdgcn_perm(e.y, e.x, 0x040c0100u);
+    }
+    int Sm = NEGX;
+    const int K5x = K5 - K4;
+#pragma unroll
+    for (int i = NMAX - 1; i >= 0; --i) {
+      const int E = (int)(short)(ke[i] & 0xffffu);
+      const int xa = max(pm[i] - E, Sm);
+      *(int *)((char *)Xh + (ke[i] >> 16)) =
+          (int)__builtin_amdgcn_perm((unsigned)(xa + E + K5x), (unsigned)xa, 0x05040100u);
+      Sm = max(Sm, tm[i]);
+    }
+#pragma unroll
+    for (int g0 = 0; g0 < NMAX; g0 += 4) {
+      if (uany & (0xfu << g0)) {
+        int xa[4], xb[4], fu[4], gv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (g0 + j < NMAX) {
+            const int h = Xh[(g0 + j) * 64];
+            xa[j] = (int)(short)(h & 0xffff);
+            xb[j] = h >> 16;
+            fu[j] = Fu[2 * (g0 + j)];
+            gv[j] = Gv[2 * (g0 + j)];
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (g0 + j < NMAX) {
+            accf[g0 + j] = max(accf[g0 + j], fu[j] + xa[j]);
+            accb[g0 + j] = max(accb[g0 + j], gv[j] + xb[j]);
+          }
+        }
+      }
+    }
+  }
+  // fold over each group's lanes: element e = dir * NMAX + job, block e / L
+  int t[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    int blk[L];
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+      const int e = b * L + j;
+      blk[j] = e < NMAX ? accf[e < NMAX ? e : 0]
+                        : (e < 2 * NMAX ? accb[e < 2 * NMAX && e >= NMAX ? e - NMAX : 0] : kNeg);
+    }
+    t[b] = group_transpose_max<L>(blk, lane);
+  }
+  // outputs and MinMin, per group
+  int vmin = kInt32Max;
+  int val[NB];
+  int slot[NB];
+  bool mem[NB], dirb[NB];
+  const bool okg = [&] {
+    bool o = false;
+#pragma unroll
+    for (int g = 0; g < G; ++g) o = gl == g ? ok_[g] : o;
+    return o;
+  }();
+  int ag = 0, rg = 0;
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+    if (gl == g) {
+      ag = a_[g];
+      rg = r_[g];
+    }
+  int par = -1;
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+    if (gl == g) par = rows[g];
+  int *lbrow = out_lb + (size_t)(par >= 0 ? par : 0) * 2 * ns;
+  uint8_t *prow = out_prune + (size_t)(par >= 0 ? par : 0) * 2 * ns;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int e = b * L + l;
+    const bool live = okg && e < 2 * NMAX;
+    const int dr = e >= NMAX, q = e - (dr ? NMAX : 0);
+    const bool member = live && q < n && ((umask >> q) & 1u);
+    const int sl = member ? Q.inv[q] - ag : 0;
+    const int pairmax = nsg > 0 ? t[b] : kNeg;
+    const int v = member ? max(Q.lb1[(dr ? 32 : 0) + q], pairmax) : kInt32Max;
+    if (member) {
+      lbrow[(dr ? ns : 0) + sl] = v;
+      prow[(dr ? ns : 0) + sl] = v >= ub;
+    }
+    val[b] = v;
+    mem[b] = member;
+    dirb[b] = dr;
+    slot[b] = sl;
+    vmin = min(vmin, v);
+  }
+  const int cmn = group_min<L>(vmin);
+  int cf = 0, cb = 0, flo = 0, fhi = 0, blo = 0, bhi = 0;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    if (mem[b]) {
+      const int v = val[b];
+      if (dirb[b]) {
+        cb += v == cmn;
+        blo += v & 0xffff;
+        bhi += v >> 16;
+      } else {
+        cf += v == cmn;
+        flo += v & 0xffff;
+        fhi += v >> 16;
+      }
+    }
+  }
+  cf = group_sum<L>(cf);
+  cb = group_sum<L>(cb);
+  flo = group_sum<L>(flo);
+  fhi = group_sum<L>(fhi);
+  blo = group_sum<L>(blo);
+  bhi = group_sum<L>(bhi);
+  if (par >= 0) {
+    if (okg) {
+      for (int x = l; x < 2 * ns; x += L) {  // slots >= r of both directions
+        const int q = x < ns ? x : x - ns;
+        if (q >= rg) {
+          lbrow[x] = kInt32Max;
+          prow[x] = 1;
+        }
+      }
+      if (l == 0 && pool.dir) {
+        MinMin mm;
+        mm.init();
+        mm.merge(cmn, cf, cb, ((long long)fhi << 16) + flo, ((long long)bhi << 16) + blo);
+        pool.dir[par] = (uint8_t)mm.dir();
+      }
+    } else {
+      for (int x = l; x < 2 * ns; x += L) {
+        lbrow[x] = kInt32Max;
+        prow[x] = 1;
+      }
+      if (l == 0 && pool.dir) pool.dir[par] = 0;
+    }
+  }
+  wave_sync();  // the next parents rewrite this wave's tables
+}
+
+// At most 8 waves per block: the per-parent tables limit a CU to about eight
+// resident waves anyway, and the register budget of two waves per SIMD keeps
+// the G parents' state out of scratch.
+template <int NMAX, int G>
+__global__ void __launch_bounds__(512)
+k_lb2s(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__restrict__ out_lb,
+       uint8_t *__restrict__ out_prune, int Ppad) {
+  extern __shared__ __align__(16) unsigned char sm[];
+  const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int count = pool.count_dev ? *pool.count_dev : pool.count;
+  if ((int)blockIdx.x * nw * G >= count) return;  // no parent for this block
+  const PackLayout L{Ppad, I.m};
+  const PackLds<NMAX, G> S(sm, L, w);
+  lb2q_stage<NMAX, true>(I, Ppad, S);
+  __syncthreads();
+  if (pool.ub_dev) ub = *pool.ub_dev;
+  const int step = gridDim.x * nw * G;
+  int it0 = (blockIdx.x * nw + w) * G;
+  auto row_of = [&](int it) { return it < count ? (pool.index ? pool.index[it] : it) : -1; };
+  int rows[G];
+  PackFetch F[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    rows[g] = row_of(it0 + g);
+    F[g] = pack_fetch(pool, rows[g], I.n, I.m, costs, lane);
+  }
+  for (; it0 < count; it0 += step) {
+    PackFetch C[G];
+    int cur[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      C[g] = F[g];
+      cur[g] = rows[g];
+      rows[g] = row_of(it0 + step + g);
+      F[g] = pack_fetch(pool, rows[g], I.n, I.m, costs, lane);
+    }
+    lb2s_wave<NMAX, G>(I, Ppad, S, pool, cur, C, ub, out_lb, out_prune, lane);
   }
 }
 
@@ -1214,14 +1754,16 @@ k_lb2f(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
        uint8_t *__restrict__ out_prune, int Ppad) {
   extern __shared__ __align__(16) unsigned char sm[];
   const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int count = pool.count_dev ? *pool.count_dev : pool.count;
+  if ((int)blockIdx.x * nw >= count) return;  // no parent for this block
   const FastLayout L{Ppad, I.n, I.m};
   const FastLds<NMAX> S(sm, L, w);
   lb2f_stage<NMAX>(I, Ppad, S);
   __syncthreads();
-  const int count = pool.count_dev ? *pool.count_dev : pool.count;
   if (pool.ub_dev) ub = *pool.ub_dev;
   const int m = I.m;
-  for (int par = blockIdx.x * nw + w; par < count; par += gridDim.x * nw) {
+  for (int it = blockIdx.x * nw + w; it < count; it += gridDim.x * nw) {
+    const int par = pool.index ? pool.index[it] : it;
     const int ns = pool.n;  // row stride (>= n)
     lb2f_parent<NMAX, SUBSET, LOG>(
         I, Ppad, S, pool.perm + (size_t)par * ns, pool.d1[par], pool.d2[par],
@@ -1434,6 +1976,11 @@ static void attr_lb2() {
   lds_limit((const void *)k_lb2<E, ENT_LDS, false, false>);
 }
 
+template <int NMAX, int G>
+static void attr_lb2s() {
+  lds_limit((const void *)k_lb2s<NMAX, G>);
+}
+
 template <int NMAX>
 static void attr_lb2f() {
   if constexpr (NMAX <= 32) {
@@ -1508,6 +2055,11 @@ void init_bound_attributes() {
   attr_lb2<Narrow, false>();
   attr_lb2<Wide, true>();
   attr_lb2<Wide, false>();
+  attr_lb2s<16, 2>();
+  attr_lb2s<20, 2>();
+  attr_lb2s<32, 2>();
+  attr_lb2s<16, 4>();
+  attr_lb2s<20, 4>();
   attr_lb2f<8>();
   attr_lb2f<12>();
   attr_lb2f<16>();
@@ -1529,8 +2081,10 @@ static void lb1_shape(const Ctx *c, int count, int &b1, size_t &lds1, int &g1) {
   g1 = (count + b1 - 1) / b1;
 }
 
-// Parent front/back/remaining into the workspace (k_lb1 without outputs).
-int launch_costs(Ctx *c, const DevPool &pool, hipStream_t s) {
+// Parent front/back/remaining into the workspace (k_lb1 without outputs);
+// with f, also the search-step filter (CostFilter).
+int launch_costs(Ctx *c, const DevPool &pool, hipStream_t s, const CostFilter *f) {
+  const CostFilter fv = f ? *f : CostFilter{};
   if (pool.count <= 0) return PFSP_OK;
   int rc = ensure_costs(c, pool.count);
   if (rc) return rc;
@@ -1545,7 +2099,7 @@ int launch_costs(Ctx *c, const DevPool &pool, hipStream_t s) {
 #define PFSP_C(M)                                                                          \
   case M:                                                                                  \
     hipLaunchKernelGGL(k_costs<M>, dim3(grid), dim3(256), lds, s, c->inst(), pool, c->d_costs, \
-                       c->d_flag);                                                         \
+                       c->d_flag, fv);                                                     \
     break;
       PFSP_C(8) PFSP_C(12) PFSP_C(16) PFSP_C(20) PFSP_C(24) PFSP_C(32)
 #undef PFSP_C
@@ -1559,7 +2113,7 @@ int launch_costs(Ctx *c, const DevPool &pool, hipStream_t s) {
   lb1_shape(c, pool.count, b1, lds1, g1);
   KTimer kt(c, s, "k_lb1");
   hipLaunchKernelGGL(k_lb1, dim3(g1), dim3(b1), lds1, s, c->inst(), pool, 0, (int *)nullptr,
-                     (uint8_t *)nullptr, c->d_costs, 0, c->d_flag);
+                     (uint8_t *)nullptr, c->d_costs, 0, c->d_flag, fv);
   PFSP_HIP(c, hipGetLastError());
   return PFSP_OK;
 }
@@ -1573,24 +2127,68 @@ int launch_bound(Ctx *c, const DevPool &pool, int kind, int ub, int *out_lb, uin
     lb1_shape(c, pool.count, b1, lds1, g1);
     KTimer kt(c, s, "k_lb1");
     hipLaunchKernelGGL(k_lb1, dim3(g1), dim3(b1), lds1, s, c->inst(), pool, ub, out_lb,
-                       out_prune, (int *)nullptr, 1, c->d_flag);
+                       out_prune, (int *)nullptr, 1, c->d_flag, CostFilter{});
     PFSP_HIP(c, hipGetLastError());
     return PFSP_OK;
   }
   int rc = launch_costs(c, pool, s);
   if (rc) return rc;
-  return launch_bound_costs_ready(c, pool, kind, ub, out_lb, out_prune, s);
+  return launch_bound_costs_ready(c, pool, kind, ub, out_lb, out_prune, s, 0);
 }
 
-// LB2 kinds once launch_costs has run for the same pool.
+static size_t lb2s_lds(const Ctx *c, int nmax, int G, int waves) {
+  const PackLayout L{(c->P + 63) / 64 * 64, c->m};
+  return L.block_bytes(nmax) + (size_t)waves * L.wave_bytes(nmax, G);
+}
+
+// Packed subset kernel: G parents per wave.
+static int launch_lb2s(Ctx *c, const DevPool &pool, int G, int ub, int *out_lb,
+                       uint8_t *out_prune, hipStream_t s) {
+  const int nmax = c->n <= 16 ? 16 : c->n <= 20 ? 20 : 32;
+  if (nmax == 32) G = 2;  // four parents' state of 32 jobs does not fit the registers
+  int waves = 0, best = 0;
+  for (int w = 8; w >= 1; --w) {
+    const size_t l = lb2s_lds(c, nmax, G, w);
+    const int per_cu = l <= 160 * 1024 ? (int)((160 * 1024) / l) * w : 0;
+    if (per_cu > best) {
+      best = per_cu;
+      waves = w;
+    }
+  }
+  if (!waves) return set_err(c, PFSP_ERANGE, "packed subset kernel exceeds LDS");
+  const size_t lds = lb2s_lds(c, nmax, G, waves);
+  const int Ppad = (c->P + 63) / 64 * 64;
+  const int per_block = waves * G;
+  int grid = (pool.count + per_block - 1) / per_block;
+  const int cap = c->cu_count * 16;
+  if (grid > cap) grid = cap;
+  KTimer kt(c, s, "k_lb2");
+#define PFSP_S(N, GG)                                                                       \
+  hipLaunchKernelGGL((k_lb2s<N, GG>), dim3(grid), dim3(64 * waves), lds, s, c->inst(), pool, ub, \
+                     c->d_costs, out_lb, out_prune, Ppad)
+  if (G == 4) {
+    if (nmax == 16) PFSP_S(16, 4); else PFSP_S(20, 4);
+  } else {
+    if (nmax == 16) PFSP_S(16, 2); else if (nmax == 20) PFSP_S(20, 2); else PFSP_S(32, 2);
+  }
+#undef PFSP_S
+  PFSP_HIP(c, hipGetLastError());
+  return PFSP_OK;
+}
+
+// LB2 kinds once launch_costs has run for the same pool.  group: parents per
+// wave for subset bounds (1, 2 or 4; 0 = the context's "subset_group").
 int launch_bound_costs_ready(Ctx *c, const DevPool &pool, int kind, int ub, int *out_lb,
-                             uint8_t *out_prune, hipStream_t s) {
+                             uint8_t *out_prune, hipStream_t s, int group) {
   if (pool.count <= 0) return PFSP_OK;
   const DevInst I = c->inst();
   const int n = c->n;
   const bool subset = kind == PFSP_LB2_SUBSET;
   const bool log = pool.argpair != nullptr;
   const int nmax = c->narrow && !c->force_generic ? fast_nmax(n, c->l16) : 0;
+  if (group <= 0) group = (int)c->subset_group;
+  if (subset && !log && nmax && nmax <= 32 && c->x16 && (group == 2 || group == 4))
+    return launch_lb2s(c, pool, group, ub, out_lb, out_prune, s);
   if (nmax) {
     // waves per block: the most resident waves per CU within 160 KiB of LDS
     int waves = 0, best = 0;
@@ -1676,7 +2274,7 @@ int launch_generic_instance(Ctx *c, const DevInst &I, const DevPool &pool, int u
   {
     KTimer kt(c, s, "k_lb1");
     hipLaunchKernelGGL(k_lb1, dim3((pool.count + b1 - 1) / b1), dim3(b1), lds1, s, I, pool, ub,
-                       out_lb, out_prune, costs, 0, c->d_flag);
+                       out_lb, out_prune, costs, 0, c->d_flag, CostFilter{});
   }
   const int xrows = n < 32 ? n : 32;
   int waves = 8;

@@ -45,6 +45,23 @@ struct DevPool {
   int mask_words;
   uint8_t *dir;
   int16_t *argpair;
+  const int *index = nullptr;  // if set, launch row i bounds pool row index[i]
+};
+
+// Search-step filter of the costs kernels (row i of the pool):
+//  - a dead record (alive[i] == 0, lazy re-check) is skipped;
+//  - a parent all of whose children (both directions) have LB1 >= *ub_dev
+//    cannot keep a child under any LB2 kind (LB2 >= LB1): its prune row is
+//    written here (all pruned, direction 0) and it is left out of the bound
+//    kernels;
+//  - every other parent is appended to rows[0 .. *open) (any order).
+struct CostFilter {
+  const uint8_t *alive;
+  const int *ub_dev;
+  uint8_t *out_prune;
+  uint8_t *dir;
+  int *rows;
+  int *open;
 };
 
 struct Selector;   // learned pair selector state (selector.hip)
@@ -80,6 +97,8 @@ struct Ctx {
   int64_t force_generic = 0;
   int64_t lb2_waves = 0;      // waves per block of the LB2 kernel (0 = automatic)
   int64_t lb2_blocks_per_cu = 0;  // persistent LB2 blocks per CU (0 = 16)
+  int64_t subset_group = 0;   // parents per wave of subset LB2 (0/1 = one, 2, 4)
+  int64_t search_filter = 1;  // LB2 search steps bound only parents with a child LB1 < ub
   int64_t log_capacity = 0;   // search node log size in records (0 = off)
   int64_t log_stride = 1;     // log every log_stride-th decomposed node of a batch  // 1: always use the generic LB2 kernel
   struct Pending {
@@ -139,11 +158,13 @@ int stage_tables(Ctx *c, hipStream_t s, int n, int m, const int *d_p, int *d_T, 
 int ensure_costs(Ctx *c, int count);
 int launch_bound(Ctx *c, const DevPool &pool, int kind, int ub, int *out_lb,
                  uint8_t *out_prune, hipStream_t s);
-int launch_costs(Ctx *c, const DevPool &pool, hipStream_t s);
+int launch_costs(Ctx *c, const DevPool &pool, hipStream_t s, const CostFilter *f = nullptr);
+// group: parents per wave for subset bounds (1, 2 or 4; 0 = option "subset_group")
 int launch_bound_costs_ready(Ctx *c, const DevPool &pool, int kind, int ub, int *out_lb,
-                             uint8_t *out_prune, hipStream_t s);
+                             uint8_t *out_prune, hipStream_t s, int group = 0);
 size_t lb2_lds_bytes(const Ctx *c, int waves);
 void init_bound_attributes();
+void init_selector_attributes();
 // multi-instance launches (bound.hip)
 struct MultiTile {
   int inst, begin, end, pad;
@@ -170,6 +191,8 @@ int launch_lb2m(Ctx *c, const FastClassLaunch &L, const DevInst *insts, const ui
                 const int *costs, int *out_lb, uint8_t *out_prune, uint8_t *dir, hipStream_t s);
 // selector.hip
 int launch_learned(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8_t *out_prune,
+                   hipStream_t s);
+int launch_learned_ready(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8_t *out_prune,
                    hipStream_t s);
 int learned_prepare(Ctx *c, int rows);
 void selector_free(Ctx *c);

@@ -62,12 +62,17 @@ struct SearchState {
   hipGraphExec_t gexec = nullptr;
   int graph_kind = 0;
   long long graph_log = -1;
+  int graph_filter = -1;
+  // LB2 steps: parents that survive the costs kernels' LB1 filter
+  int *rows = nullptr, *open = nullptr;
   // node log (option log_capacity > 0): every log_stride-th decomposed node
   uint8_t *l_perm = nullptr, *l_d1 = nullptr, *l_d2 = nullptr;
   long long log_cap = 0;
 };
 
 constexpr int kScanBlock = 1024;  // parents per k_scan_local block (256 threads x 4)
+
+__global__ void k_clear(int *p) { *p = 0; }
 
 __global__ void k_pop(SearchCtl *c, int N) {
   const int top = c->top;
@@ -136,9 +141,9 @@ k_count(SearchCtl *__restrict__ c, int n, const uint8_t *__restrict__ b_d1,
       children = 2 * r;
       const int *lb = out_lb + ((size_t)i * 2 + dir) * n;
       const uint8_t *pr = out_prune + ((size_t)i * 2 + dir) * n;
-      if (r == 1) {
+      if (r == 1) {  // leaf children: the bound is the makespan (pruned: not below ub)
         const int v = lb[0];
-        if (v < ub) {
+        if (!pr[0] && v < ub) {
           atomicMin(&c->ub, v);
           atomicMin(&c->step_best, ((unsigned long long)(unsigned)v << 32) | (unsigned)i);
         }
@@ -322,7 +327,7 @@ void search_free(Ctx *c) {
   if (S->graph) (void)hipGraphDestroy(S->graph);
   void *bufs[] = {S->s_perm, S->s_d1, S->s_d2, S->s_lb, S->b_perm, S->b_d1, S->b_d2, S->b_dir,
                   S->b_lb, S->b_alive, S->out_lb, S->out_prune, S->cnt, S->offs, S->bsum,
-                  S->best_perm, S->ctl, S->l_perm, S->l_d1, S->l_d2};
+                  S->best_perm, S->ctl, S->l_perm, S->l_d1, S->l_d2, S->rows, S->open};
   for (void *p : bufs) (void)hipFree(p);
   if (S->ctl_host) (void)hipHostFree(S->ctl_host);
   if (S->stream) (void)hipStreamDestroy(S->stream);
@@ -368,6 +373,8 @@ static int search_alloc(Ctx *c) {
   alloc((void **)&S->bsum, (size_t)nb * 4);
   alloc((void **)&S->best_perm, (size_t)n);
   alloc((void **)&S->ctl, sizeof(SearchCtl));
+  alloc((void **)&S->rows, (size_t)N * 4);
+  alloc((void **)&S->open, 4);
   S->log_cap = c->log_capacity;
   if (S->log_cap > 0) {
     alloc((void **)&S->l_perm, (size_t)S->log_cap * n);
@@ -412,10 +419,25 @@ static int enqueue_step(Ctx *c, int kind) {
   pool.dir = S->b_dir;
   pool.argpair = nullptr;
   int rc;
-  if (kind == PFSP_LB2_LEARNED)
+  if (kind != PFSP_LB1 && c->search_filter) {
+    // parents whose children all have LB1 >= ub are closed by the costs
+    // kernel (LB2 >= LB1 cannot keep a child); only the others are bounded
+    hipLaunchKernelGGL(k_clear, dim3(1), dim3(1), 0, s, S->open);
+    const CostFilter f{S->b_alive, &S->ctl->ub_step, S->out_prune, S->b_dir, S->rows, S->open};
+    rc = launch_costs(c, pool, s, &f);
+    if (rc) return rc;
+    DevPool op = pool;
+    op.index = S->rows;
+    op.count_dev = S->open;
+    if (kind == PFSP_LB2_LEARNED)
+      rc = launch_learned_ready(c, op, 0, S->out_lb, S->out_prune, s);
+    else
+      rc = launch_bound_costs_ready(c, op, kind, 0, S->out_lb, S->out_prune, s);
+  } else if (kind == PFSP_LB2_LEARNED) {
     rc = launch_learned(c, pool, 0, S->out_lb, S->out_prune, s);
-  else
+  } else {
     rc = launch_bound(c, pool, kind, 0, S->out_lb, S->out_prune, s);
+  }
   if (rc) return rc;
   hipLaunchKernelGGL(k_count, dim3((N + 255) / 256), dim3(256), 0, s, S->ctl, n, S->b_d1, S->b_d2,
                      S->b_alive, S->b_dir, S->out_lb, S->out_prune, S->cnt);
@@ -432,7 +454,9 @@ static int enqueue_step(Ctx *c, int kind) {
 static int build_graph(Ctx *c, int kind) {
   SearchState *S = c->search;
   const long long logkey = S->log_cap > 0 ? c->log_stride : 0;
-  if (S->gexec && S->graph_kind == kind && S->graph_log == logkey) return PFSP_OK;
+  if (S->gexec && S->graph_kind == kind && S->graph_log == logkey &&
+      S->graph_filter == (int)c->search_filter)
+    return PFSP_OK;
   if (S->gexec) (void)hipGraphExecDestroy(S->gexec);
   if (S->graph) (void)hipGraphDestroy(S->graph);
   S->gexec = nullptr;
@@ -451,6 +475,7 @@ static int build_graph(Ctx *c, int kind) {
   S->graph = g;
   PFSP_HIP(c, hipGraphInstantiate(&S->gexec, g, nullptr, nullptr, 0));
   S->graph_kind = kind;
+  S->graph_filter = (int)c->search_filter;
   S->graph_log = logkey;
   return PFSP_OK;
 }

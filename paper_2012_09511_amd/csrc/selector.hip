@@ -45,10 +45,6 @@ struct Selector {
   size_t train_cap = 0;
   int *to_inst = nullptr;  // [190]: instance pair index of each layout pair, -1 if absent
   int to_inst_m = -1;
-  int *order = nullptr;    // [190]: output visiting order of k_infer
-  float order_norm = -1.f;  // instance (norm) and weights the order was computed for;
-  int order_m = -1;         // the order is only a speed heuristic of k_infer
-  int order_ok = 0;
 };
 
 // round to nearest even bfloat16, kept as float
@@ -109,51 +105,59 @@ __device__ __forceinline__ void parent_features(int n, int m, const int *__restr
   f[63] = bad ? 0.f : (float)lb1 / norm;
 }
 
-// (v, id) ranks before (w, jd): larger score first, then lower layout index
-// (the order of k_select); an empty slot (jd < 0) ranks last.
-__device__ __forceinline__ bool ranks_before(float v, int id, float w, int jd) {
-  return jd < 0 || v > w || (v == w && id < jd);
-}
-
 // Selector inference for the bound kernels, fused: features from the costs
 // workspace, the MLP and the top-k, writing only the pair masks.  One thread
-// per row; each hidden layer goes through LDS ([unit][thread], each thread
-// touching only its own column) so that the next layer reads it from
-// statically indexed registers, and the weights are read at wave-uniform
-// addresses.  Every score is accumulated in the order of k_mlp_forward and
-// the top-k follows k_select's ranking, so the masks equal
-// select(forward(features)).  The output layer is visited in `order`, a
-// permutation that puts likely winners first so that the running k-th score
-// rises early and later scores rarely enter the list (the result does not
-// depend on the order).
+// per row, 256 rows per block.  The block stages the bf16-rounded weights in
+// LDS once; each layer's outputs go through LDS ([unit][thread], each thread
+// touching only its own column) so that the next layer reads its inputs from
+// statically indexed registers, and four output units are accumulated at a
+// time (independent chains, weights read as LDS broadcasts).  Every score is
+// accumulated in the order of k_mlp_forward (bias, then inputs 0..63) and
+// the list keeps the KMAX best (score, then lower layout index: the ranking
+// of k_select) in visiting order 0..189, so its first k entries are the
+// masks of select(forward(features)).
+constexpr int kInferRows = 256;
 template <int KMAX>
-__global__ void __launch_bounds__(128)
+__global__ void __launch_bounds__(kInferRows)
 k_infer(DevInst I, DevPool pool, const int *__restrict__ costs, float norm,
-        const float *__restrict__ wq, const int *__restrict__ to_inst,
-        const int *__restrict__ order, int k, int words, uint32_t *__restrict__ mask) {
-  __shared__ float hs[kHid][128];
+        const float *__restrict__ wq, const int *__restrict__ to_inst, int k, int words,
+        uint32_t *__restrict__ mask) {
+  extern __shared__ __align__(16) float wsh[];  // [kParams] weights, then [kHid][kInferRows]
+  float(*hs)[kInferRows] = reinterpret_cast<float(*)[kInferRows]>(wsh + ((kParams + 3) & ~3));
   const int count = pool.count_dev ? *pool.count_dev : pool.count;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= count) return;
+  if ((int)(blockIdx.x * kInferRows) >= count) return;
+  for (int x = threadIdx.x; x < kParams; x += kInferRows) wsh[x] = wq[x];
+  __syncthreads();
+  const int it = blockIdx.x * kInferRows + threadIdx.x;
+  if (it >= count) return;
+  const int i = pool.index ? pool.index[it] : it;
   const int t = threadIdx.x;
   float x[kIn];
   parent_features(I.n, I.m, costs + (size_t)i * 3 * I.m, pool.d1[i], pool.d2[i], norm, x);
-  for (int o = 0; o < kHid; ++o) {
-    float s = wq[kOffB1 + o];
+  // hidden layers: units o .. o + 3 at a time
+#pragma unroll 1
+  for (int layer = 0; layer < 2; ++layer) {
+    const float *W = wsh + (layer == 0 ? kOffW1 : kOffW2);
+    const float *Bv = wsh + (layer == 0 ? kOffB1 : kOffB2);
+#pragma unroll 1
+    for (int o = 0; o < kHid; o += 4) {
+      float s0 = Bv[o], s1 = Bv[o + 1], s2 = Bv[o + 2], s3 = Bv[o + 3];
 #pragma unroll
-    for (int j = 0; j < kIn; ++j) s = fmaf(wq[kOffW1 + o * kIn + j], x[j], s);
-    hs[o][t] = fmaxf(s, 0.f);
+      for (int j = 0; j < kIn; ++j) {
+        s0 = fmaf(W[(o + 0) * kIn + j], x[j], s0);
+        s1 = fmaf(W[(o + 1) * kIn + j], x[j], s1);
+        s2 = fmaf(W[(o + 2) * kIn + j], x[j], s2);
+        s3 = fmaf(W[(o + 3) * kIn + j], x[j], s3);
+      }
+      hs[o][t] = fmaxf(s0, 0.f);
+      hs[o + 1][t] = fmaxf(s1, 0.f);
+      hs[o + 2][t] = fmaxf(s2, 0.f);
+      hs[o + 3][t] = fmaxf(s3, 0.f);
+    }
+#pragma unroll
+    for (int j = 0; j < kHid; ++j) x[j] = hs[j][t];
   }
-#pragma unroll
-  for (int j = 0; j < kHid; ++j) x[j] = hs[j][t];
-  for (int o = 0; o < kHid; ++o) {
-    float s = wq[kOffB2 + o];
-#pragma unroll
-    for (int j = 0; j < kHid; ++j) s = fmaf(wq[kOffW2 + o * kHid + j], x[j], s);
-    hs[o][t] = fmaxf(s, 0.f);
-  }
-#pragma unroll
-  for (int j = 0; j < kHid; ++j) x[j] = hs[j][t];
+  // output layer, pairs in index order, into the top-KMAX list
   float best[KMAX];
   int idx[KMAX];
 #pragma unroll
@@ -161,36 +165,35 @@ k_infer(DevInst I, DevPool pool, const int *__restrict__ costs, float norm,
     best[q] = -INFINITY;
     idx[q] = -1;
   }
-  float thr = -INFINITY;  // the k-th entry of the list
-  int thr_id = -1;
-  for (int r = 0; r < kOut; ++r) {
-    const int o = order[r];
-    if (to_inst[o] < 0) continue;
-    float v = wq[kOffB3 + o];
+  const float *W3 = wsh + kOffW3;
+#pragma unroll 1
+  for (int o = 0; o < kOut; o += 2) {  // kOut is even
+    float v[2] = {wsh[kOffB3 + o], wsh[kOffB3 + o + 1]};
 #pragma unroll
-    for (int j = 0; j < kHid; ++j) v = fmaf(wq[kOffW3 + o * kHid + j], x[j], v);
-    if (ranks_before(v, o, thr, thr_id)) {
-      int id = o;
+    for (int j = 0; j < kHid; ++j) {
+      v[0] = fmaf(W3[o * kHid + j], x[j], v[0]);
+      v[1] = fmaf(W3[(o + 1) * kHid + j], x[j], v[1]);
+    }
 #pragma unroll
-      for (int q = 0; q < KMAX; ++q) {
-        if (q < k && ranks_before(v, id, best[q], idx[q])) {
+    for (int e = 0; e < 2; ++e) {
+      float val = v[e];
+      int id = o + e;
+      // absent pairs never enter; a later pair displaces only strictly smaller
+      // scores, so equal scores keep the lower index first
+      if (to_inst[id] >= 0 && val > best[KMAX - 1]) {
+#pragma unroll
+        for (int q = 0; q < KMAX; ++q) {
+          const bool c = val > best[q];
           const float tv = best[q];
           const int ti = idx[q];
-          best[q] = v;
-          idx[q] = id;
-          v = tv;
-          id = ti;
+          best[q] = c ? val : tv;
+          idx[q] = c ? id : ti;
+          val = c ? tv : val;
+          id = c ? ti : id;
         }
       }
-#pragma unroll
-      for (int q = 0; q < KMAX; ++q)
-        if (q == k - 1) {
-          thr = best[q];
-          thr_id = idx[q];
-        }
     }
   }
-  uint32_t *mi = mask + (size_t)i * words;
   uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0, w5 = 0;  // 190 pairs fit 6 words
 #pragma unroll
   for (int q = 0; q < KMAX; ++q) {
@@ -206,52 +209,11 @@ k_infer(DevInst I, DevPool pool, const int *__restrict__ costs, float norm,
       w5 |= wd == 5 ? bit : 0u;
     }
   }
+  uint32_t *mi = mask + (size_t)i * words;
   const uint32_t ws[6] = {w0, w1, w2, w3, w4, w5};
 #pragma unroll
   for (int wd = 0; wd < 6; ++wd)
     if (wd < words) mi[wd] = ws[wd];
-}
-
-// Visiting order of the output layer for k_infer: the layout pairs sorted by
-// their score at the root node of the loaded instance (C1 = C2 = 0, R = the
-// machine totals), highest first.  One thread; run when the weights or the
-// instance change.
-__global__ void k_order(DevInst I, float norm, const float *__restrict__ wq,
-                        int *__restrict__ order) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  float x[kIn], h1[kHid], h2[kHid], sc[kOut];
-  const int m = I.m;
-  int lb1 = 0;
-  for (int k = 0; k < kIn; ++k) x[k] = 0.f;
-  for (int k = 0; k < m && k < kMMax; ++k) x[40 + k] = (float)I.T[k] / norm;
-  for (int k = 0; k < m; ++k) lb1 = max(lb1, I.T[k]);
-  x[62] = 1.f;
-  x[63] = (float)lb1 / norm;
-  for (int o = 0; o < kHid; ++o) {
-    float s = wq[kOffB1 + o];
-    for (int j = 0; j < kIn; ++j) s = fmaf(wq[kOffW1 + o * kIn + j], x[j], s);
-    h1[o] = fmaxf(s, 0.f);
-  }
-  for (int o = 0; o < kHid; ++o) {
-    float s = wq[kOffB2 + o];
-    for (int j = 0; j < kHid; ++j) s = fmaf(wq[kOffW2 + o * kHid + j], h1[j], s);
-    h2[o] = fmaxf(s, 0.f);
-  }
-  for (int o = 0; o < kOut; ++o) {
-    float s = wq[kOffB3 + o];
-    for (int j = 0; j < kHid; ++j) s = fmaf(wq[kOffW3 + o * kHid + j], h2[j], s);
-    sc[o] = s;
-    order[o] = o;
-  }
-  for (int a = 1; a < kOut; ++a) {  // insertion sort, descending score
-    const int o = order[a];
-    int b = a - 1;
-    while (b >= 0 && sc[order[b]] < sc[o]) {
-      order[b + 1] = order[b];
-      --b;
-    }
-    order[b + 1] = o;
-  }
 }
 
 // Forward pass, one thread per row; the weights are read at wave-uniform
@@ -529,7 +491,7 @@ void selector_free(Ctx *c) {
   Selector *S = c->sel;
   if (!S) return;
   void *bufs[] = {S->master, S->wq, S->grad, S->am, S->av, S->feat, S->scores, S->mask, S->h1,
-                  S->h2, S->ds, S->dh1, S->dh2, S->rowloss, S->loss, S->to_inst, S->order};
+                  S->h2, S->ds, S->dh1, S->dh2, S->rowloss, S->loss, S->to_inst};
   for (void *p : bufs) (void)hipFree(p);
   delete S;
   c->sel = nullptr;
@@ -588,16 +550,6 @@ int learned_prepare(Ctx *c, int rows) {
   Selector *S = c->sel;
   int rc = sel_tables(c, S);
   if (rc) return rc;
-  const float norm = instance_norm(c);
-  if (!S->order_ok || S->order_m != c->m || S->order_norm != norm) {
-    if (!S->order) PFSP_HIP(c, hipMalloc(&S->order, kOut * sizeof(int)));
-    hipLaunchKernelGGL(k_order, dim3(1), dim3(64), 0, c->stream, c->inst(), norm, S->wq,
-                       S->order);
-    PFSP_HIP(c, hipGetLastError());
-    S->order_ok = 1;
-    S->order_m = c->m;
-    S->order_norm = norm;
-  }
   return sel_rows(c, S, rows > 0 ? rows : 1);
 }
 
@@ -605,31 +557,54 @@ int launch_learned(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8_t *ou
                    hipStream_t s) {
   int rc = learned_prepare(c, pool.count);
   if (rc) return rc;
-  Selector *S = c->sel;
   if (pool.count <= 0) return PFSP_OK;
   rc = ensure_costs(c, pool.count);
   if (rc) return rc;
-  const DevInst I = c->inst();
   // parent costs (front, back, remaining) for the features
   rc = launch_costs(c, pool, s);
   if (rc) return rc;
+  return launch_learned_ready(c, pool, ub, out_lb, out_prune, s);
+}
+
+// The learned bound once the costs of the pool are in the workspace.
+int launch_learned_ready(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8_t *out_prune,
+                         hipStream_t s) {
+  int rc = learned_prepare(c, pool.count);
+  if (rc) return rc;
+  Selector *S = c->sel;
+  if (pool.count <= 0) return PFSP_OK;
+  const DevInst I = c->inst();
   const int words = (c->P + 31) / 32;
   const int k = (int)c->learned_topk;
   {
     KTimer kt(c, s, "k_infer");
-    const dim3 g((pool.count + 127) / 128), b(128);
+    const dim3 g((pool.count + kInferRows - 1) / kInferRows), b(kInferRows);
+    const size_t lds = (((size_t)kParams + 3) / 4 * 4 + (size_t)kHid * kInferRows) * 4;
     if (k <= 16)
-      hipLaunchKernelGGL(k_infer<16>, g, b, 0, s, I, pool, c->d_costs, instance_norm(c), S->wq,
-                         S->to_inst, S->order, k, words, S->mask);
+      hipLaunchKernelGGL(k_infer<16>, g, b, lds, s, I, pool, c->d_costs, instance_norm(c), S->wq,
+                         S->to_inst, k, words, S->mask);
     else
-      hipLaunchKernelGGL(k_infer<32>, g, b, 0, s, I, pool, c->d_costs, instance_norm(c), S->wq,
-                         S->to_inst, S->order, k, words, S->mask);
+      hipLaunchKernelGGL(k_infer<32>, g, b, lds, s, I, pool, c->d_costs, instance_norm(c), S->wq,
+                         S->to_inst, k, words, S->mask);
   }
   PFSP_HIP(c, hipGetLastError());
   DevPool sp = pool;
   sp.mask = S->mask;
   sp.mask_words = words;
-  return launch_bound_costs_ready(c, sp, PFSP_LB2_SUBSET, ub, out_lb, out_prune, s);
+  // a top-k of at most 16 (32) pairs fills a quarter (half) of a wave: pack
+  // four (two) parents per wave
+  const int group = c->subset_group > 0 ? (int)c->subset_group : k <= 16 ? 4 : k <= 32 ? 2 : 1;
+  return launch_bound_costs_ready(c, sp, PFSP_LB2_SUBSET, ub, out_lb, out_prune, s, group);
+}
+
+// k_infer stages all weights and a layer of activations in LDS (about 148
+// KiB); called once per process with the bound kernels' attributes.
+void init_selector_attributes() {
+  (void)hipFuncSetAttribute((const void *)k_infer<16>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  (void)hipFuncSetAttribute((const void *)k_infer<32>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  (void)hipGetLastError();
 }
 
 }  // namespace pfsp
@@ -650,7 +625,6 @@ int pfsp_selector_set(pfsp_ctx *h, const float *params, int64_t count) {
   PFSP_HIP(c, hipMemset(S->am, 0, kParams * 4));
   PFSP_HIP(c, hipMemset(S->av, 0, kParams * 4));
   S->step = 0;
-  S->order_ok = 0;
   hipLaunchKernelGGL(k_round_weights, dim3((kParams + 255) / 256), dim3(256), 0, c->stream,
                      S->master, S->wq);
   PFSP_HIP(c, hipGetLastError());
@@ -815,7 +789,6 @@ int pfsp_selector_train_step(pfsp_ctx *h, const float *x, const float *target, i
     hipLaunchKernelGGL(k_round_weights, dim3((kParams + 255) / 256), dim3(256), 0, s, S->master,
                        S->wq);
     PFSP_HIP(c, hipGetLastError());
-    S->order_ok = 0;
   }
   float l = 0.f;
   PFSP_HIP(c, hipMemcpyAsync(&l, S->loss, 4, hipMemcpyDeviceToHost, s));

@@ -130,6 +130,68 @@ def test_quick_kernel_value_ranges(ctx, n, m, lo, hi):
     _check(ctx, p, perm, d1, d2, binding.LB2_SUBSET, INT32_MAX, mask=mask)
 
 
+def _random_masks(rng, count, m, kmax):
+    """Per row a uniform number of distinct pairs in [0, kmax], as bit masks."""
+    P = m * (m - 1) // 2
+    words = (P + 31) // 32
+    mask = np.zeros((count, words), dtype=np.uint32)
+    for i in range(count):
+        for q in rng.choice(P, size=int(rng.integers(0, min(kmax, P) + 1)), replace=False):
+            mask[i, q >> 5] |= np.uint32(1 << (int(q) & 31))
+    return mask
+
+
+@pytest.mark.parametrize("group", [2, 4])
+@pytest.mark.parametrize("n,m,kmax", [(20, 20, 16), (20, 20, 40), (12, 7, 21), (32, 10, 45),
+                                      (16, 20, 190), (5, 3, 3), (2, 2, 1)])
+def test_packed_subset_parity(ctx, group, n, m, kmax):
+    """Subset LB2 with 2 or 4 parents per wave: selections up to the group's
+    lanes (one pass), beyond them (several passes) and empty; root and
+    one-job-left nodes; pool sizes that leave a wave partly empty."""
+    p = inputs.instance(n, m, 3000 + 64 * n + m)
+    rng = np.random.default_rng(n * 100 + m + group)
+    parts = [inputs.random_pool(n, 97, 41 + n), inputs.random_pool(n, 9, 42 + n, depth=0),
+             inputs.random_pool(n, 13, 43 + n, depth=n - 1)]
+    perm, d1, d2 = (np.concatenate([q[i] for q in parts]) for i in range(3))
+    mask = _random_masks(rng, len(perm), m, kmax)
+    ctx.set_option("subset_group", group)
+    try:
+        olb = _check(ctx, p, perm, d1, d2, binding.LB2_SUBSET, INT32_MAX, mask=mask)
+        _check(ctx, p, perm, d1, d2, binding.LB2_SUBSET, int(np.median(olb[olb < INT32_MAX])),
+               mask=mask)
+    finally:
+        ctx.set_option("subset_group", 0)
+
+
+def test_packed_subset_invalid_rows(ctx):
+    n, m = 8, 4
+    p = inputs.instance(n, m, 9)
+    perm, d1, d2 = inputs.random_pool(n, 11, 10)
+    d1[1], d2[1] = 5, 3          # d1 + d2 = n
+    perm[2, 3] = perm[2, 4]      # not a permutation
+    perm[7, 0] = 200             # job id out of range
+    mask = np.full((len(perm), 1), 0x3f, dtype=np.uint32)
+    ctx.set_option("subset_group", 4)
+    try:
+        ctx.load_instance(p)
+        tp, t1, t2, tm = _dev(ctx, perm, d1, d2, mask)
+        lb, pr, dr, _ = ctx.bound_children(tp, t1, t2, binding.LB2_SUBSET, 1000, pair_mask=tm)
+        with pytest.raises(binding.PfspError):
+            ctx.check()
+        lb, pr, dr = lb.cpu().numpy(), pr.cpu().numpy(), dr.cpu().numpy()
+        bad = [1, 2, 7]
+        assert (lb[bad] == INT32_MAX).all() and (pr[bad] == 1).all() and (dr[bad] == 0).all()
+        good = [i for i in range(len(perm)) if i not in bad]
+        olb, opr, odr = oracle.bound_children(p, perm[good], d1[good], d2[good],
+                                              binding.LB2_SUBSET, 1000, pair_mask=mask[good])
+        np.testing.assert_array_equal(lb[good], olb)
+        np.testing.assert_array_equal(pr[good], opr)
+        np.testing.assert_array_equal(dr[good], odr)
+    finally:
+        ctx.set_option("subset_group", 0)
+        ctx.check()
+
+
 def test_wide_processing_times(ctx):
     """Processing times above 2^16 use the wide pair-table format."""
     n, m = 9, 6

@@ -167,8 +167,11 @@ int pfsp_neh(pfsp_ctx *c, int32_t *perm_out, int32_t *cmax_out);
  * stored value fits 16 bits: 2 or 4, each parent then gets 32 or 16 lanes
  * and a selection of up to that many pairs costs one scan pass; 0 = one
  * parent per wave for PFSP_LB2_SUBSET and by top-k for PFSP_LB2_LEARNED),
- * "log_capacity" (records kept by pfsp_search's node log, 0 = off) and
- * "log_stride" (log every log_stride-th decomposed node of a batch). */
+ * "wide_lb2" (1 = PFSP_LB2_FULL for 32 < n <= 128 with (n + m) max p < 2^15
+ * runs the wide kernel, whose entries are staged at pfsp_load_instance;
+ * default 1), "log_capacity" (records kept by pfsp_search's node log,
+ * 0 = off) and "log_stride" (log every log_stride-th decomposed node of a
+ * batch). */
 int pfsp_set_option(pfsp_ctx *c, const char *key, int64_t value);
 int pfsp_get_option(pfsp_ctx *c, const char *key, int64_t *value);
 
@@ -195,7 +198,9 @@ int pfsp_kernel_time(pfsp_ctx *c, const char *kernel, double *total_ms, int64_t 
  * Outputs use the same stride: out_lb/out_prune [N][2][stride], slots
  * q >= n - d1 - d2 hold INT32_MAX / prune 1.  The launch sequence (one costs
  * kernel, one persistent LB2 kernel per instance class draining a queue of
- * instance tiles, generic kernels for n > 64 or p >= 2^16) is captured as a
+ * instance tiles: n <= 20; 20 < n <= 128 with (n + m) max p < 2^15 (the wide
+ * kernel, unless "wide_lb2" was 0 at pfsp_multi_create); other n <= 64;
+ * generic kernels for the rest) is captured as a
  * HIP graph on first use and replayed while buffers and grouping are
  * unchanged.
  * ------------------------------------------------------------------------ */
@@ -214,8 +219,9 @@ int pfsp_multi_bound(pfsp_multi *mt, int lb_kind, const uint8_t *perm, const uin
                      const uint8_t *d2, int32_t stride, const int64_t *seg_begin,
                      const int32_t *ub, int32_t *out_lb, uint8_t *out_prune, uint8_t *dir_out);
 
-/* Launch shape: parents per tile, waves per block of the n <= 20 (0..12) and n <= 64 (0..8)
- * classes (0 = most resident waves), blocks per CU (0 = as many as fit). */
+/* Launch shape: parents per tile, waves per block of the n <= 20 class (0..12) and of the
+ * larger classes (0..8, at most 4 for the n > 64 wide class; 0 = most resident waves),
+ * blocks per CU (0 = as many as fit). */
 int pfsp_multi_set_shape(pfsp_multi *mt, int32_t tile, int32_t waves_small, int32_t waves_large,
                          int32_t blocks_per_cu);
 

@@ -27,11 +27,13 @@ static void free_instance(Ctx *c) {
   (void)hipFree(c->d_p);
   (void)hipFree(c->d_T);
   (void)hipFree(c->d_ent);
+  (void)hipFree(c->d_entq);
   (void)hipFree(c->d_entw);
   (void)hipFree(c->d_pu);
   (void)hipFree(c->d_pv);
   c->d_p = c->d_T = nullptr;
   c->d_ent = nullptr;
+  c->d_entq = nullptr;
   c->d_entw = nullptr;
   c->d_pu = c->d_pv = nullptr;
   free(c->p_host);
@@ -134,7 +136,7 @@ int pfsp_load_instance(pfsp_ctx *h, int32_t n, int32_t m, const int32_t *p) {
   // packed 8-byte pair entries need a, b < 2^16 and lag < 2^24
   c->narrow = maxp < 65536 && (int64_t)(m > 2 ? m - 2 : 0) * maxp < (1 << 24);
   c->l16 = c->narrow && (int64_t)(m > 1 ? m - 1 : 0) * maxp < (1 << 16);
-  c->x16 = c->l16 && (int64_t)(2 * n + 2 * m + 2) * maxp < (1 << 14);
+  c->x16 = c->l16 && (int64_t)(n + m) * maxp < (1 << 15);
   c->p_host = (int *)malloc((size_t)n * m * 4);
   if (!c->p_host) return set_err(c, PFSP_ENOMEM, "host allocation failed");
   memcpy(c->p_host, p, (size_t)n * m * 4);
@@ -149,6 +151,8 @@ int pfsp_load_instance(pfsp_ctx *h, int32_t n, int32_t m, const int32_t *p) {
   }
   PFSP_HIP(c, hipMemcpyAsync(c->d_p, p, (size_t)n * m * 4, hipMemcpyHostToDevice, c->stream));
   int rc = stage_instance(c);
+  if (rc == PFSP_OK && c->narrow && c->x16 && n > 32 && n <= 128)
+    rc = stage_quick(c, c->stream, n, m, c->d_ent, &c->d_entq);
   if (rc) {
     free_instance(c);
     return rc;
@@ -233,6 +237,7 @@ static int64_t *opt_slot(Ctx *c, const char *key) {
   if (!strcmp(key, "lb2_waves")) return &c->lb2_waves;
   if (!strcmp(key, "subset_group")) return &c->subset_group;
   if (!strcmp(key, "search_filter")) return &c->search_filter;
+  if (!strcmp(key, "wide_lb2")) return &c->wide_lb2;
   if (!strcmp(key, "lb2_blocks_per_cu")) return &c->lb2_blocks_per_cu;
   if (!strcmp(key, "log_capacity")) return &c->log_capacity;
   if (!strcmp(key, "log_stride")) return &c->log_stride;
@@ -263,7 +268,7 @@ int pfsp_set_option(pfsp_ctx *h, const char *key, int64_t value) {
   if (!strcmp(key, "learned_topk") && (value < 1 || value > 2016))
     return set_err(c, PFSP_ERANGE, "learned_topk must be in [1, 2016]");
   if ((!strcmp(key, "use_graph") || !strcmp(key, "learned_exact") || !strcmp(key, "timing") ||
-       !strcmp(key, "search_filter") ||
+       !strcmp(key, "search_filter") || !strcmp(key, "wide_lb2") ||
        !strcmp(key, "force_generic")) &&
       value != 0 && value != 1)
     return set_err(c, PFSP_EINVAL, "flag options take 0 or 1");

@@ -1046,8 +1046,8 @@ struct QuickLds {
 // Block-cooperative staging of one instance for the quick kernels (no
 // barrier inside).  The staged narrow entries hold x = a | b << 16 and
 // y = l | k << 24; the quick entries are {b - a, k | (a + l) << 16}, or
-// {(b - a) & 0xffff | (a + l) << 16, k} when X16 (then |b - a| and a + l are
-// below 2^14).
+// {(b - a) & 0xffff | (a + l) << 16, k} when X16 (then |b - a| < 2^14 and
+// a + l < 2^16).
 template <int NMAX, bool X16, class Lds>
 __device__ void lb2q_stage(const DevInst &I, int Ppad, const Lds &S) {
   const int n = I.n, m = I.m, P = I.P;
@@ -1091,13 +1091,14 @@ __device__ __forceinline__ int nth_pair(const uint32_t *__restrict__ mw, int P, 
   return 0;
 }
 
-// X16: the scan starts from Y = R_v + C2_v instead of 0, so the stored
-// Xa(j) + R_v + C2_v equals T(U') + a_j + C2_v, a sum of processing times
-// over disjoint cells of at most n + m jobs and machines, and the stored
-// values lie in [-max p, (n + m + 1) max p] (NEG16 - max p for a job that is
-// the only member); the high half holds Xb + C1_u + R_v, likewise bounded.
-// With (2n + 2m + 2) max p < 2^14 both fit int16 and a NEG16-derived term
-// stays below zero, hence below LB1.
+// X16: the scan starts from Y = R_v + C2_v instead of 0.  For a member j
+// with at least one other member (U' not empty) the stored Xa(j) + R_v +
+// C2_v equals T(U') + a_j + C2_v and the high half Xb(j) + C1_u + R_v equals
+// T(U') + b_j + C1_u: sums of processing times over disjoint cells, in
+// [0, (n + m) max p], so with (n + m) max p < 2^15 both fit int16.  A parent
+// with one job left needs no pair (its children are leaves and LB1 is their
+// makespan), so the only NEG-derived value, that of a sole member, never
+// reaches a bound.
 template <int NMAX, bool SUBSET, bool X16>
 __device__ void lb2q_parent(const DevInst &I, int Ppad, const QuickLds<NMAX> &S,
                             const uint8_t *__restrict__ row, int a, int b,
@@ -1159,7 +1160,7 @@ __device__ void lb2q_parent(const DevInst &I, int Ppad, const QuickLds<NMAX> &S,
   int accf[NMAX], accb[NMAX];
 #pragma unroll
   for (int q = 0; q < NMAX; ++q) accf[q] = accb[q] = kNeg;
-  const int npass = SUBSET ? nsel : (P > 0 ? Ppad : 0);
+  const int npass = r < 2 ? 0 : SUBSET ? nsel : (P > 0 ? Ppad : 0);  // leaves: LB2 = LB1
   constexpr int NEGX = X16 ? -(1 << 14) : kNeg;
   int2 *__restrict__ Xl = (int2 *)S.X + lane;
   int *__restrict__ Xh = (int *)S.X + lane;
@@ -1295,6 +1296,346 @@ k_lb2q(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
   }
 }
 
+// ------------------------------------------------------------ wide LB2
+// Full LB2 for 32 < n <= NMAX (64 or 128) with 16-bit X, one wave per
+// parent and lanes = pairs as in k_lb2q.  The per-pair scan runs over the n
+// Johnson positions in chunks of CH: a first sweep keeps only the running Y
+// and prefix maximum at each chunk start; the second sweep takes the chunks
+// from last to first, repeats each chunk's forward steps in registers and
+// then its backward steps, so the suffix maximum carries across chunks.  The
+// quick-format entries stream from the instance's global table
+// [pass][position][64 lanes] (L2-resident, coalesced).  The children's
+// pair maxima of both directions live in one register per job as two int16
+// halves (forward low, backward high): every pair term of a child is a
+// lower bound of one of its completions, hence at most (n + m - 1) max p,
+// below 2^15 when 16-bit X applies.
+struct WideLayout {
+  int ppad, nj, mmax;  // padded pairs, rows of X (largest n), machines
+  __host__ __device__ static constexpr int row(int nmax) { return nmax | 1; }
+  // scan chunk length: the 128-job variant keeps fewer positions in registers
+  __host__ __device__ static constexpr int chunk_len(int nmax) { return nmax >= 128 ? 8 : 16; }
+  __host__ __device__ static constexpr int chunks(int nmax) { return nmax / chunk_len(nmax); }
+  __host__ __device__ size_t block_bytes(int nmax) const {
+    return align16((size_t)ppad * 4) + align16((size_t)mmax * nmax * 4);
+  }
+  __host__ __device__ size_t wave_bytes(int nmax) const {
+    return align16((size_t)(nj + 3) * 64 * 4) + align16((size_t)mmax * row(nmax) * 4) +
+           align16((size_t)chunks(nmax) * 64 * 4) + align16((size_t)2 * mmax * 8) +
+           align16((size_t)3 * mmax * 4) + (size_t)nmax * 4;
+  }
+};
+
+template <int NMAX>
+struct WideLds {
+  int *uv, *pt;    // block: pair -> u | v << 8; p by [machine][job]
+  int *X;          // [nj + 3][64]: xa | xb << 16 by job (row n: padding sink; rows
+                   // n + 1, n + 2: read, never used, by the last group of four jobs)
+  int *FB;         // [m][ROW]: f (forward, low half) | g (backward, high half) by machine
+  int *ST;         // [chunks][64]: Y | prefix max << 16 at each chunk start (both int16)
+  int2 *HTf, *HTb;
+  int *c1, *c2, *rr, *inv;
+  __device__ WideLds(unsigned char *sm, const WideLayout &L, int w) {
+    constexpr int ROW = WideLayout::row(NMAX);
+    uv = (int *)sm;
+    size_t off = align16((size_t)L.ppad * 4);
+    pt = (int *)(sm + off);
+    off += align16((size_t)L.mmax * NMAX * 4);
+    unsigned char *wb = sm + off + (size_t)w * L.wave_bytes(NMAX);
+    X = (int *)wb;
+    wb += align16((size_t)(L.nj + 3) * 64 * 4);
+    FB = (int *)wb;
+    wb += align16((size_t)L.mmax * ROW * 4);
+    ST = (int *)wb;
+    wb += align16((size_t)WideLayout::chunks(NMAX) * 64 * 4);
+    HTf = (int2 *)wb;
+    HTb = HTf + L.mmax;
+    wb += align16((size_t)2 * L.mmax * 8);
+    c1 = (int *)wb;
+    c2 = c1 + L.mmax;
+    rr = c2 + L.mmax;
+    wb += align16((size_t)3 * L.mmax * 4);
+    inv = (int *)wb;
+  }
+};
+
+// Block-cooperative staging of one instance for the wide kernels (no
+// barrier inside): pair machines and the processing times by machine.
+template <int NMAX>
+__device__ void lb2w_stage(const DevInst &I, int Ppad, const WideLds<NMAX> &S) {
+  const int n = I.n, m = I.m, P = I.P;
+  for (int x = threadIdx.x; x < Ppad; x += blockDim.x) {
+    const int q = x < P ? x : 0;
+    S.uv[x] = P > 0 ? ((int)I.pu[q] | ((int)I.pv[q] << 8)) : 0;
+  }
+  for (int x = threadIdx.x; x < m * NMAX; x += blockDim.x) {
+    const int s = x / NMAX, k = x - s * NMAX;
+    S.pt[x] = k < n ? I.p[k * m + s] : 0;
+  }
+}
+
+// -1 if job k is a member (bit k of the mask words), else 0.
+template <int NW>
+__device__ __forceinline__ int member_ng(const uint64_t (&um)[NW], unsigned k) {
+  if constexpr (NW == 1) {
+    return __builtin_amdgcn_sbfe((int)(uint32_t)(um[0] >> (k & 63u)), 0, 1);
+  } else {  // both words shifted, then a bitwise select (no indexed register array)
+    const uint32_t b0 = (uint32_t)(um[0] >> (k & 63u)), b1 = (uint32_t)(um[1] >> (k & 63u));
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_sbfe((int)k, 6, 1);
+    return __builtin_amdgcn_sbfe((int)((b1 & hi) | (b0 & ~hi)), 0, 1);
+  }
+}
+
+// One chunk of the second sweep: the forward steps from the chunk-start
+// state (Y, Pm), then the backward steps with the suffix maximum Sm, storing
+// xa | xb << 16 in the job's row of X.  RAGGED: positions from rem on lie
+// past n (they count as non-members and write the padding sink, row n).
+template <int NW, int CH, bool RAGGED>
+__device__ __forceinline__ void lb2w_chunk(const uint2 *__restrict__ ec, int rem,
+                                           const uint64_t (&um)[NW], int n, int K5x, int Y,
+                                           int Pm, int &Sm, int *__restrict__ Xh) {
+  constexpr int NEGX = -(1 << 14);
+  int pm[CH], tm[CH];
+  unsigned ke[CH];  // E in bits 0-15, job << 24: (ke >> 16) is the byte offset of its row of X
+  uint2 ev[CH];
+#pragma unroll
+  for (int i = 0; i < CH; ++i) ev[i] = ec[(!RAGGED || i < rem ? i : rem - 1) * 64];
+  __builtin_amdgcn_sched_barrier(0);  // all CH loads in flight before the first use
+#pragma unroll
+  for (int i = 0; i < CH; ++i) {
+    const bool in = !RAGGED || i < rem;
+    const uint2 e = ev[i];
+    int ng = member_ng<NW>(um, e.y);
+    if (RAGGED) ng &= in ? -1 : 0;
+    const int tt = Y + (int)(e.x >> 16);
+    tm[i] = (tt & ng) | (NEGX & ~ng);
+    pm[i] = Pm;
+    Pm = max(Pm, tm[i]);
+    Y = __mul24(ng, (int)(short)(e.x & 0xffffu)) + Y;
+    ke[i] = __builtin_amdgcn_perm(in ? e.y : (unsigned)n, e.x, 0x040c0100u);
+  }
+#pragma unroll
+  for (int i = CH - 1; i >= 0; --i) {
+    const int E = (int)(short)(ke[i] & 0xffffu);
+    const int xa = max(pm[i] - E, Sm);
+    *(int *)((char *)Xh + (ke[i] >> 16)) =
+        (int)__builtin_amdgcn_perm((unsigned)(xa + E + K5x), (unsigned)xa, 0x05040100u);
+    Sm = max(Sm, tm[i]);
+  }
+}
+
+template <int NMAX>
+__device__ void lb2w_parent(const DevInst &I, int Ppad, const WideLds<NMAX> &S,
+                            const uint8_t *__restrict__ row, int a, int b,
+                            const int *__restrict__ cs, int stride, int ub,
+                            int *__restrict__ lbrow, uint8_t *__restrict__ prow,
+                            uint8_t *__restrict__ dirp, int lane) {
+  constexpr int ROW = WideLayout::row(NMAX);
+  constexpr int CH = WideLayout::chunk_len(NMAX);
+  constexpr int NC = NMAX / 32;  // 32-job chunks of the lane-per-job steps
+  constexpr int NW = NMAX / 64;  // 64-bit membership words
+  constexpr int NEGX = -(1 << 14);
+  const int n = I.n, m = I.m, P = I.P;
+  const int r = n - a - b;
+  if (r < 1 || cs[0] < 0) {  // flagged by the costs kernel: not a valid node
+    fill_invalid(lbrow, prow, nullptr, stride, 0, lane, 64);
+    if (dirp && lane == 0) *dirp = 0;
+    return;
+  }
+  for (int x = lane; x < n; x += 64) S.inv[row[x]] = x;
+  for (int x = lane; x < m; x += 64) {
+    const int C1 = cs[x], C2 = cs[m + x], R = cs[2 * m + x];
+    S.c1[x] = C1;
+    S.c2[x] = C2;
+    S.rr[x] = R;
+    S.HTf[x] = make_int2(C1, R + C2);
+    S.HTb[m - 1 - x] = make_int2(C2, C1 + R);
+  }
+  wave_sync();
+  uint64_t um[NW];
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const int k = 64 * w + lane;
+    const int slot = k < n ? S.inv[k] - a : -1;
+    um[w] = __ballot(slot >= 0 && slot < r);
+  }
+  // LB1 of both children of each member job and their start times: lane
+  // q < 32 takes the forward child of job 32c + q, lane 32 + q its backward
+  // child (machines reversed; g is stored under the machine's own index)
+  const bool bwd = lane >= 32;
+  int lb1[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    lb1[c] = 0;
+    if (!((um[c >> 1] >> (32 * (c & 1))) & 0xffffffffull)) continue;
+    const int k = 32 * c + (lane & 31);
+    if (!((um[c >> 1] >> (k & 63)) & 1ull)) continue;
+    const int2 *HT = bwd ? S.HTb : S.HTf;
+    unsigned short *fb = (unsigned short *)S.FB + 2 * k + (bwd ? 1 + 2 * (m - 1) * ROW : 0);
+    const int fstep = bwd ? -2 * ROW : 2 * ROW;
+    const int *PT = S.pt + k + (bwd ? (m - 1) * NMAX : 0);
+    const int pstep = bwd ? -NMAX : NMAX;
+    int cc = 0, l = 0;
+#pragma unroll 4
+    for (int s = 0; s < m; ++s) {
+      const int2 ht = HT[s];
+      const int f = max(cc, ht.x);
+      cc = f + PT[s * pstep];
+      fb[s * fstep] = (unsigned short)f;
+      l = max(l, f + ht.y);
+    }
+    lb1[c] = l;
+  }
+  wave_sync();
+  int acc[NMAX];  // two int16 maxima per job: forward | backward << 16
+#pragma unroll
+  for (int q = 0; q < NMAX; ++q) acc[q] = (int)0x80008000u;
+  const int npass = r < 2 ? 0 : (P > 0 ? Ppad : 0);  // leaves: LB2 = LB1
+  const int nch = (n + CH - 1) / CH;
+  int *__restrict__ Xh = S.X + lane;
+  int *__restrict__ st = S.ST + lane;
+  for (int pc = 0; pc < npass; pc += 64) {
+    // the masks are opaque per pass, so that the per-group branch conditions
+    // below are recomputed (two scalar ops) rather than held in registers
+#pragma unroll
+    for (int w = 0; w < NW; ++w) asm volatile("" : "+s"(um[w]));
+    const int pi = pc + lane;
+    const int uvp = S.uv[pi];
+    const int u = uvp & 0xff, v = uvp >> 8;
+    const int K4 = S.rr[v] + S.c2[v], K5 = S.c1[u] + S.rr[v];
+    const int K5x = K5 - K4;  // the high half is Xb + K5 (K4 is already inside)
+    const uint2 *__restrict__ eb = I.entq + (size_t)(pc >> 6) * n * 64 + lane;
+    // first sweep: Y and the prefix maximum at each chunk start
+    int Y = K4, Pm = NEGX;
+    for (int ch = 0; ch < nch - 1; ++ch) {
+      // Y lies in [0, (n + m) max p) and Pm in it or NEGX: both fit int16
+      st[ch * 64] = (int)__builtin_amdgcn_perm((unsigned)Pm, (unsigned)Y, 0x05040100u);
+      const uint2 *ec = eb + ch * CH * 64;
+      uint2 ev[CH];
+#pragma unroll
+      for (int i = 0; i < CH; ++i) ev[i] = ec[i * 64];
+      __builtin_amdgcn_sched_barrier(0);  // all CH loads in flight before the first use
+#pragma unroll
+      for (int i = 0; i < CH; ++i) {
+        const uint2 e = ev[i];
+        const int ng = member_ng<NW>(um, e.y);
+        const int tt = Y + (int)(e.x >> 16);
+        Pm = max(Pm, (tt & ng) | (NEGX & ~ng));
+        Y = __mul24(ng, (int)(short)(e.x & 0xffffu)) + Y;
+      }
+    }
+    // second sweep, chunks from last to first (only the last can be ragged)
+    int Sm = NEGX;
+    {
+      const int ch = nch - 1, rem = n - ch * CH;
+      if (rem < CH)
+        lb2w_chunk<NW, CH, true>(eb + ch * CH * 64, rem, um, n, K5x, Y, Pm, Sm, Xh);
+      else
+        lb2w_chunk<NW, CH, false>(eb + ch * CH * 64, rem, um, n, K5x, Y, Pm, Sm, Xh);
+    }
+    for (int ch = nch - 2; ch >= 0; --ch) {
+      const int s2 = st[ch * 64];
+      lb2w_chunk<NW, CH, false>(eb + ch * CH * 64, CH, um, n, K5x, s2 & 0xffff, s2 >> 16, Sm,
+                                Xh);
+    }
+    // children of the member jobs, four at a time: f_u + xa | g_v + xb
+    const int *Fu = S.FB + u * ROW;
+    const int *Gv = S.FB + v * ROW;
+#pragma unroll
+    for (int g = 0; g < NMAX; g += 4) {
+      if ((um[g >> 6] >> (g & 63)) & 0xfull) {
+        int h[4], fw[4], gw[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {  // a group holding a member ends before row n + 3
+          h[j] = Xh[(g + j) * 64];
+          fw[j] = Fu[g + j];
+          gw[j] = Gv[g + j];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int fg = (int)__builtin_amdgcn_perm((unsigned)gw[j], (unsigned)fw[j], 0x07060100u);
+          acc[g + j] = pk_max(acc[g + j], pk_add(fg, h[j]));
+        }
+      }
+    }
+  }
+  // per-job maxima over the pairs, 32 jobs at a time; outputs; MinMin
+  int vmin = kInt32Max, slo = 0, shi = 0;
+  int val[NC];
+  bool mem[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int k = 32 * c + (lane & 31);
+    const bool member = (um[c >> 1] >> (k & 63)) & 1ull;
+    mem[c] = member;
+    val[c] = kInt32Max;
+    if (!((um[c >> 1] >> (32 * (c & 1))) & 0xffffffffull)) continue;
+    int t;
+    if (c == 0) t = transpose_pkmax32<0>(acc, lane);
+    else if (c == 1) t = transpose_pkmax32<(NC > 1 ? 32 : 0)>(acc, lane);
+    else if (c == 2) t = transpose_pkmax32<(NC > 2 ? 64 : 0)>(acc, lane);
+    else t = transpose_pkmax32<(NC > 3 ? 96 : 0)>(acc, lane);
+    const int v = member ? max(lb1[c], t) : kInt32Max;
+    if (member) {
+      const int o = (bwd ? stride : 0) + S.inv[k] - a;
+      lbrow[o] = v;
+      prow[o] = v >= ub;
+      slo += v & 0xffff;
+      shi += v >> 16;
+    }
+    val[c] = v;
+    vmin = min(vmin, v);
+  }
+  fill_invalid(lbrow, prow, nullptr, stride, r, lane, 64);
+  if (dirp) {
+    const int cmn = wave_min_xl(vmin);
+    int cf = 0, cb = 0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const uint64_t at = __ballot(mem[c] && val[c] == cmn);
+      cf += __popc((uint32_t)at);
+      cb += __popc((uint32_t)(at >> 32));
+    }
+    const int hlo = half_sum(slo), hhi = half_sum(shi);
+    const long long sf = ((long long)__builtin_amdgcn_readlane(hhi, 0) << 16) +
+                         __builtin_amdgcn_readlane(hlo, 0);
+    const long long sb = ((long long)__builtin_amdgcn_readlane(hhi, 32) << 16) +
+                         __builtin_amdgcn_readlane(hlo, 32);
+    MinMin mm;
+    mm.init();
+    mm.merge(cmn, cf, cb, sf, sb);
+    if (lane == 0) *dirp = (uint8_t)mm.dir();
+  }
+  wave_sync();  // the next parent rewrites this wave's tables
+}
+
+// Single instance: each block stages the pair machines and processing
+// times, then its waves take parents in a grid-stride loop.  The 128-job
+// variant runs one wave per SIMD (its LDS tables allow about three waves per
+// CU anyway), which leaves it the accumulation registers beyond 256.
+template <int NMAX>
+__global__ void __launch_bounds__(NMAX >= 128 ? 256 : 512)
+k_lb2w(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__restrict__ out_lb,
+       uint8_t *__restrict__ out_prune, int Ppad) {
+  extern __shared__ __align__(16) unsigned char sm[];
+  const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int count = pool.count_dev ? *pool.count_dev : pool.count;
+  if ((int)blockIdx.x * nw >= count) return;  // no parent for this block: skip the staging
+  const WideLayout L{Ppad, I.n, I.m};
+  const WideLds<NMAX> S(sm, L, w);
+  lb2w_stage<NMAX>(I, Ppad, S);
+  __syncthreads();
+  if (pool.ub_dev) ub = *pool.ub_dev;
+  const int m = I.m;
+  for (int it = blockIdx.x * nw + w; it < count; it += gridDim.x * nw) {
+    const int par = pool.index ? pool.index[it] : it;
+    const int ns = pool.n;  // row stride (>= n)
+    lb2w_parent<NMAX>(I, Ppad, S, pool.perm + (size_t)par * ns, pool.d1[par], pool.d2[par],
+                      costs + (size_t)par * 3 * m, ns, ub, out_lb + (size_t)par * 2 * ns,
+                      out_prune + (size_t)par * 2 * ns, pool.dir ? pool.dir + par : nullptr,
+                      lane);
+  }
+}
+
 // ------------------------------------------------------- packed subset LB2
 // Subset LB2 with G parents per wave for n <= NMAX <= 32 and 16-bit X (the
 // method of k_lb2q): group g of L = 64 / G consecutive lanes takes parent g,
@@ -1303,7 +1644,7 @@ k_lb2q(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
 // parents.  Per-child maxima are folded within each group; MinMin reduces
 // within each group.  Per parent and wave: start times FB [m][ROW] with f
 // (forward child, by machine) in the low and g (backward child, by machine)
-// in the high 16 bits (both below 2^14 when 16-bit X applies), C1, C2, R,
+// in the high 16 bits (both below 2^15 when 16-bit X applies), C1, C2, R,
 // the inverse permutation, the children's LB1 and the compacted selection.
 struct PackLayout {
   int ppad, mmax;
@@ -1516,7 +1857,7 @@ __device__ void lb2s_wave(const DevInst &I, int Ppad, const PackLds<NMAX, G> &S,
 #pragma unroll
   for (int g = 0; g < G; ++g) {
     nsel[g] = 0;
-    if (!ok_[g]) continue;
+    if (!ok_[g] || r_[g] < 2) continue;  // leaves: LB2 = LB1, no pair needed
     for (int base = 0; base < P; base += 64) {
       const int pi = base + lane;
       const uint32_t w = (uint32_t)__shfl((int)F[g].mw, (pi >> 5) & 63, kWave);
@@ -1839,6 +2180,45 @@ k_lb2m(const DevInst *__restrict__ insts, const MultiTile *__restrict__ tiles, i
   }
 }
 
+// The wide kernel in the persistent multi-instance form of k_lb2m: L is the
+// class layout (largest padded pair count, n and m of its instances).
+template <int NMAX>
+__global__ void __launch_bounds__(NMAX >= 128 ? 256 : 512)
+k_lb2mw(const DevInst *__restrict__ insts, const MultiTile *__restrict__ tiles, int ntiles,
+        int *__restrict__ queue, WideLayout L, const uint8_t *__restrict__ perm,
+        const uint8_t *__restrict__ d1, const uint8_t *__restrict__ d2, int stride,
+        const int *__restrict__ ubs, const int *__restrict__ costs, int cstride,
+        int *__restrict__ out_lb, uint8_t *__restrict__ out_prune, uint8_t *__restrict__ dir) {
+  extern __shared__ __align__(16) unsigned char sm[];
+  __shared__ int s_tile;
+  const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const WideLds<NMAX> S(sm, L, w);
+  int cur = -1, Ppad = 0;
+  DevInst I{};
+  for (;;) {
+    if (threadIdx.x == 0) s_tile = atomicAdd(queue, 1);
+    __syncthreads();
+    const int t = s_tile;
+    __syncthreads();  // every thread has read s_tile before it is overwritten
+    if (t >= ntiles) break;
+    const MultiTile T = tiles[t];
+    if (T.inst != cur) {
+      cur = T.inst;
+      I = insts[cur];
+      Ppad = (I.P + 63) / 64 * 64;
+      lb2w_stage<NMAX>(I, Ppad, S);
+      __syncthreads();
+    }
+    const int ub = ubs[cur];
+    for (int par = T.begin + w; par < T.end; par += nw)
+      lb2w_parent<NMAX>(I, Ppad, S, perm + (size_t)par * stride, d1[par], d2[par],
+                        costs + (size_t)par * cstride, stride, ub,
+                        out_lb + (size_t)par * 2 * stride, out_prune + (size_t)par * 2 * stride,
+                        dir + par, lane);
+    __syncthreads();  // the tables may be restaged for the next tile
+  }
+}
+
 // LDS of the single-instance fast kernels: the quick layout for n <= 32
 // without argmax logging, the scan layout otherwise.
 static size_t lb2f_lds(const Ctx *c, int nmax, int waves, bool log) {
@@ -1995,7 +2375,12 @@ static void attr_lb2f() {
   lds_limit((const void *)k_lb2f<NMAX, false, false>);
 }
 
-size_t lb2m_lds_bytes(int nmax, int ppad, int nmax_jobs, int mmax, int waves, int x16) {
+size_t lb2m_lds_bytes(int nmax, int ppad, int nmax_jobs, int mmax, int waves, int x16,
+                      int wide) {
+  if (wide) {
+    const WideLayout L{ppad, nmax_jobs, mmax};
+    return L.block_bytes(nmax) + (size_t)waves * L.wave_bytes(nmax);
+  }
   if (nmax <= 32) {
     const QuickLayout L{ppad, mmax, x16};
     return L.block_bytes(nmax) + (size_t)waves * L.wave_bytes(nmax);
@@ -2024,10 +2409,27 @@ int launch_lb2m(Ctx *c, const FastClassLaunch &L, const DevInst *insts, const ui
                 const int *costs, int *out_lb, uint8_t *out_prune, uint8_t *dir, hipStream_t s) {
   if (L.ntiles <= 0) return PFSP_OK;
   const FastLayout FL{L.ppad, L.nmax_jobs, L.mmax};
-  const size_t lds = lb2m_lds_bytes(L.nmax, L.ppad, L.nmax_jobs, L.mmax, L.waves, L.x16);
+  const size_t lds =
+      lb2m_lds_bytes(L.nmax, L.ppad, L.nmax_jobs, L.mmax, L.waves, L.x16, L.wide);
   if (lds > 160 * 1024 - 64) return set_err(c, PFSP_ERANGE, "multi-instance class exceeds LDS");
   hipLaunchKernelGGL(k_zero, dim3(1), dim3(1), 0, s, L.queue);
   KTimer kt(c, s, "k_lb2m");
+  if (L.wide) {
+    const WideLayout WL{L.ppad, L.nmax_jobs, L.mmax};
+#define PFSP_W(N)                                                                            \
+  hipLaunchKernelGGL((k_lb2mw<N>), dim3(L.grid), dim3(64 * L.waves), lds, s, insts, L.tiles,    \
+                     L.ntiles, L.queue, WL, perm, d1, d2, stride, ubs, costs, L.cstride, out_lb, \
+                     out_prune, dir)
+    if (L.nmax == 64)
+      PFSP_W(64);
+    else if (L.nmax == 128)
+      PFSP_W(128);
+    else
+      return set_err(c, PFSP_EINVAL, "no wide multi-instance kernel for this class");
+#undef PFSP_W
+    PFSP_HIP(c, hipGetLastError());
+    return PFSP_OK;
+  }
 #define PFSP_M(N, X)                                                                        \
   hipLaunchKernelGGL((k_lb2m<N, X>), dim3(L.grid), dim3(64 * L.waves), lds, s, insts, L.tiles,  \
                      L.ntiles, L.queue, FL, perm, d1, d2, stride, ubs, costs, L.cstride, out_lb, \
@@ -2046,6 +2448,10 @@ int launch_lb2m(Ctx *c, const FastClassLaunch &L, const DevInst *insts, const ui
 }
 
 void init_bound_attributes() {
+  lds_limit((const void *)k_lb2w<64>);
+  lds_limit((const void *)k_lb2w<128>);
+  lds_limit((const void *)k_lb2mw<64>);
+  lds_limit((const void *)k_lb2mw<128>);
   lds_limit((const void *)k_lb1m);
   lds_limit((const void *)k_lb2m<20, true>);
   lds_limit((const void *)k_lb2m<20, false>);
@@ -2178,6 +2584,47 @@ static int launch_lb2s(Ctx *c, const DevPool &pool, int G, int ub, int *out_lb,
 
 // LB2 kinds once launch_costs has run for the same pool.  group: parents per
 // wave for subset bounds (1, 2 or 4; 0 = the context's "subset_group").
+// Wide-kernel LDS of one block: the most resident waves per CU within 160 KiB.
+static int wide_waves(const WideLayout &L, int nmax, int pref) {
+  int waves = 0, best = 0;
+  const int wmax = nmax >= 128 ? 4 : 8;  // the kernels' launch bounds
+  if (pref > wmax) pref = 0;
+  for (int w = wmax; w >= 1; --w) {
+    const size_t l = L.block_bytes(nmax) + (size_t)w * L.wave_bytes(nmax);
+    const int per_cu = l <= 160 * 1024 ? (int)((160 * 1024) / l) * w : 0;
+    if (per_cu > best) {
+      best = per_cu;
+      waves = w;
+    }
+  }
+  if (pref > 0 && pref <= 8 && L.block_bytes(nmax) + (size_t)pref * L.wave_bytes(nmax) <= 160 * 1024)
+    waves = pref;
+  return waves;
+}
+
+static int launch_lb2w(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8_t *out_prune,
+                       hipStream_t s) {
+  const int Ppad = (c->P + 63) / 64 * 64;
+  const int nmax = c->n <= 64 ? 64 : 128;
+  const WideLayout L{Ppad, c->n, c->m};
+  const int waves = wide_waves(L, nmax, (int)c->lb2_waves);
+  if (!waves) return set_err(c, PFSP_ERANGE, "wide LB2 tables exceed LDS");
+  const size_t lds = L.block_bytes(nmax) + (size_t)waves * L.wave_bytes(nmax);
+  int grid = (pool.count + waves - 1) / waves;
+  const int cap = c->cu_count * (int)(c->lb2_blocks_per_cu > 0 ? c->lb2_blocks_per_cu : 16);
+  if (grid > cap) grid = cap;
+  const DevInst I = c->inst();
+  KTimer kt(c, s, "k_lb2w");
+  if (nmax == 64)
+    hipLaunchKernelGGL(k_lb2w<64>, dim3(grid), dim3(64 * waves), lds, s, I, pool, ub, c->d_costs,
+                       out_lb, out_prune, Ppad);
+  else
+    hipLaunchKernelGGL(k_lb2w<128>, dim3(grid), dim3(64 * waves), lds, s, I, pool, ub,
+                       c->d_costs, out_lb, out_prune, Ppad);
+  PFSP_HIP(c, hipGetLastError());
+  return PFSP_OK;
+}
+
 int launch_bound_costs_ready(Ctx *c, const DevPool &pool, int kind, int ub, int *out_lb,
                              uint8_t *out_prune, hipStream_t s, int group) {
   if (pool.count <= 0) return PFSP_OK;
@@ -2185,6 +2632,8 @@ int launch_bound_costs_ready(Ctx *c, const DevPool &pool, int kind, int ub, int 
   const int n = c->n;
   const bool subset = kind == PFSP_LB2_SUBSET;
   const bool log = pool.argpair != nullptr;
+  if (!subset && !log && c->d_entq && c->wide_lb2 && !c->force_generic && n > 32 && n <= 128)
+    return launch_lb2w(c, pool, ub, out_lb, out_prune, s);
   const int nmax = c->narrow && !c->force_generic ? fast_nmax(n, c->l16) : 0;
   if (group <= 0) group = (int)c->subset_group;
   if (subset && !log && nmax && nmax <= 32 && c->x16 && (group == 2 || group == 4))

@@ -26,11 +26,12 @@ struct DevInst {
   int n, m, P;
   int narrow;              // 1: ent holds packed 8-byte entries, else entw
   int l16;                 // 1: (m - 1) * max p < 2^16, so every a + lag fits 16 bits (NMAX <= 32)
-  int x16;                 // 1: (2n + 2m + 2) * max p < 2^14 (quick kernels store X in 16 bits)
+  int x16;                 // 1: l16 and (n + m) * max p < 2^15 (quick kernels store X in 16 bits)
   const int *p;            // [n][m] processing times
   const int *T;            // [m] per-machine totals
   const uint2 *ent;        // [n][P] narrow entries: x = a | b << 16, y = lag | k << 24
   const uint4 *entw;       // [n][P] wide entries: {a, b, lag, k}
+  const uint2 *entq;       // [P/64 passes][n][64] 16-bit-X entries (n > 32, x16), else null
   const uint8_t *pu;       // [P] first machine of pair
   const uint8_t *pv;       // [P] second machine of pair
 };
@@ -77,6 +78,7 @@ struct Ctx {
   int *p_host = nullptr;
   int *d_p = nullptr, *d_T = nullptr;
   uint2 *d_ent = nullptr;
+  uint2 *d_entq = nullptr;  // staged for the wide kernels when n > 32 and x16
   uint4 *d_entw = nullptr;
   uint8_t *d_pu = nullptr, *d_pv = nullptr;
   int narrow = 1;
@@ -100,7 +102,8 @@ struct Ctx {
   int64_t subset_group = 0;   // parents per wave of subset LB2 (0/1 = one, 2, 4)
   int64_t search_filter = 1;  // LB2 search steps bound only parents with a child LB1 < ub
   int64_t log_capacity = 0;   // search node log size in records (0 = off)
-  int64_t log_stride = 1;     // log every log_stride-th decomposed node of a batch  // 1: always use the generic LB2 kernel
+  int64_t log_stride = 1;     // log every log_stride-th decomposed node of a batch
+  int64_t wide_lb2 = 1;       // full LB2 for 32 < n <= 128 with 16-bit X takes k_lb2w
   struct Pending {
     const char *name;
     hipEvent_t a, b;
@@ -115,6 +118,7 @@ struct Ctx {
     DevInst I;
     I.n = n; I.m = m; I.P = P; I.narrow = narrow; I.l16 = l16; I.x16 = x16;
     I.p = d_p; I.T = d_T; I.ent = d_ent; I.entw = d_entw; I.pu = d_pu; I.pv = d_pv;
+    I.entq = d_entq;
     return I;
   }
 };
@@ -154,6 +158,10 @@ void collect_timings(Ctx *c);
 int stage_instance(Ctx *c);
 int stage_tables(Ctx *c, hipStream_t s, int n, int m, const int *d_p, int *d_T, uint2 *d_ent,
                  uint4 *d_entw, uint8_t *d_pu, uint8_t *d_pv, int narrow);
+// Quick-format copy of the narrow pair table for the wide kernels: entries
+// {(b - a) & 0xffff | (a + lag) << 16, job} in [pass][position][64 lanes]
+// order, pairs >= P repeating pair 0; allocates *d_entq.  Synchronous.
+int stage_quick(Ctx *c, hipStream_t s, int n, int m, const uint2 *d_ent, uint2 **d_entq);
 // bound.hip
 int ensure_costs(Ctx *c, int count);
 int launch_bound(Ctx *c, const DevPool &pool, int kind, int ub, int *out_lb,
@@ -170,7 +178,8 @@ struct MultiTile {
   int inst, begin, end, pad;
 };
 struct FastClassLaunch {
-  int nmax;                 // compiled job bound of the class (20 or 64)
+  int nmax;                 // compiled job bound of the class (20, 64 or 128)
+  int wide = 0;             // 1: the wide kernel (16-bit X, entries from entq)
   int ppad, nmax_jobs, mmax;  // LDS layout of the class
   const MultiTile *tiles;   // device, grouped by instance
   int ntiles;
@@ -179,7 +188,8 @@ struct FastClassLaunch {
   int cstride;              // ints per parent row of the costs workspace (3 * largest m)
   int x16;                  // every instance of the class allows 16-bit X
 };
-size_t lb2m_lds_bytes(int nmax, int ppad, int nmax_jobs, int mmax, int waves, int x16);
+size_t lb2m_lds_bytes(int nmax, int ppad, int nmax_jobs, int mmax, int waves, int x16,
+                      int wide);
 int launch_generic_instance(Ctx *c, const DevInst &I, const DevPool &pool, int ub, int *costs,
                             int *out_lb, uint8_t *out_prune, hipStream_t s);
 int launch_lb1m(Ctx *c, const DevInst *insts, const long long *seg, int ninst, long long total,

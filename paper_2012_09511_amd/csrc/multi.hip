@@ -27,15 +27,16 @@ constexpr size_t kLdsM = 160 * 1024 - 64;
 
 struct MultiInst {
   int n = 0, m = 0, P = 0, narrow = 1, l16 = 1, x16 = 1;
-  int cls = -1;  // 0 -> NMAX 20, 1 -> NMAX 64, -1 generic
+  int cls = -1;  // 0 quick (n <= 20), 1 scan (n <= 64), 2, 3 wide (n <= 64, 128), -1 generic
   int *d_p = nullptr, *d_T = nullptr;
-  uint2 *d_ent = nullptr;
+  uint2 *d_ent = nullptr, *d_entq = nullptr;
   uint4 *d_entw = nullptr;
   uint8_t *d_pu = nullptr, *d_pv = nullptr;
   DevInst view() const {
     DevInst I;
     I.n = n; I.m = m; I.P = P; I.narrow = narrow; I.l16 = l16; I.x16 = x16;
     I.p = d_p; I.T = d_T; I.ent = d_ent; I.entw = d_entw; I.pu = d_pu; I.pv = d_pv;
+    I.entq = d_entq;
     return I;
   }
 };
@@ -71,8 +72,8 @@ struct pfsp_multi {
   size_t costs_cap = 0;
   pfsp::MultiTile *d_tiles = nullptr;
   size_t tiles_cap = 0;
-  int first[3] = {0, 0, 0};  // tile ranges of the two fast classes
-  int *d_queue = nullptr;  // [2]
+  int first[5] = {0, 0, 0, 0, 0};  // tile ranges of the four fast classes
+  int *d_queue = nullptr;  // [4] tile counters
   // graph cache
   pfsp::MultiKey key;
   hipGraph_t graph = nullptr;
@@ -92,14 +93,21 @@ static void multi_drop_graph(pfsp_multi *mt) {
 static int class_of(const MultiInst &x, const Ctx *c) {
   if (!x.narrow || c->force_generic) return -1;
   if (x.n <= 20 && x.l16) return 0;
+  if (x.d_entq && x.n <= 64) return 2;
+  if (x.d_entq && x.n <= 128) return 3;
   if (x.n <= 64) return 1;
   return -1;
 }
 
-static const int kClassNmax[2] = {20, 64};
+constexpr int kNumCls = 4;
+static const int kClassNmax[kNumCls] = {20, 64, 64, 128};
+static const int kClassWide[kNumCls] = {0, 0, 1, 1};
 
 // waves per block that the class kernel's launch bounds allow
-static int max_waves(int nmax) { return nmax <= 32 ? 12 : 8; }
+static int max_waves(int cls) {
+  static const int w[kNumCls] = {12, 8, 8, 4};
+  return w[cls];
+}
 
 // Class layout: the largest padded pair count, job count and machine count
 // of the instances of the class, and whether all of them allow 16-bit X.
@@ -117,10 +125,10 @@ static void class_layout(const pfsp_multi *mt, int cls, int &ppad, int &nj, int 
     }
 }
 
-static int auto_waves(int nmax, int ppad, int nj, int mm, int x16) {
+static int auto_waves(int cls, int ppad, int nj, int mm, int x16) {
   int waves = 1, best = 0;
-  for (int w = max_waves(nmax); w >= 1; --w) {
-    const size_t l = lb2m_lds_bytes(nmax, ppad, nj, mm, w, x16);
+  for (int w = max_waves(cls); w >= 1; --w) {
+    const size_t l = lb2m_lds_bytes(kClassNmax[cls], ppad, nj, mm, w, x16, kClassWide[cls]);
     const int per_cu = l <= kLdsM ? (int)((kLdsM) / l) * w : 0;
     if (per_cu > best) {
       best = per_cu;
@@ -130,13 +138,13 @@ static int auto_waves(int nmax, int ppad, int nj, int mm, int x16) {
   return waves;
 }
 
-// Tiles of the two fast classes, grouped by instance, uploaded synchronously
+// Tiles of the fast classes, grouped by instance, uploaded synchronously
 // (never inside a graph capture).
 static int multi_tiles(pfsp_multi *mt, const std::vector<long long> &seg) {
   Ctx *c = mt->c;
   const int K = (int)mt->in.size();
   std::vector<MultiTile> tiles;
-  for (int cls = 0; cls < 2; ++cls) {
+  for (int cls = 0; cls < kNumCls; ++cls) {
     mt->first[cls] = (int)tiles.size();
     for (int k = 0; k < K; ++k) {
       if (mt->in[k].cls != cls) continue;
@@ -150,7 +158,7 @@ static int multi_tiles(pfsp_multi *mt, const std::vector<long long> &seg) {
       }
     }
   }
-  mt->first[2] = (int)tiles.size();
+  mt->first[kNumCls] = (int)tiles.size();
   PFSP_HIP(c, hipStreamSynchronize(mt->stream));
   if (tiles.size() > mt->tiles_cap) {
     multi_drop_graph(mt);
@@ -177,20 +185,24 @@ static int multi_enqueue(pfsp_multi *mt, int kind, const uint8_t *perm, const ui
   int rc = launch_lb1m(c, mt->d_insts, mt->d_seg, K, total, perm, d1, d2, stride, mt->mmax,
                        mt->d_ubs, out_lb, out_prune, dir, mt->d_costs, kind == PFSP_LB1, s);
   if (rc || kind == PFSP_LB1) return rc;
-  for (int cls = 0; cls < 2; ++cls) {
+  for (int cls = 0; cls < kNumCls; ++cls) {
+    if (mt->first[cls + 1] == mt->first[cls]) continue;
     FastClassLaunch L;
     L.nmax = kClassNmax[cls];
+    L.wide = kClassWide[cls];
     class_layout(mt, cls, L.ppad, L.nmax_jobs, L.mmax, L.x16);
     L.tiles = mt->d_tiles + mt->first[cls];
     L.ntiles = mt->first[cls + 1] - mt->first[cls];
     L.queue = mt->d_queue + cls;
     L.cstride = 3 * mt->mmax;  // k_lb1m's row stride, not the class's
-    L.waves = mt->waves[cls] > 0 ? std::min(mt->waves[cls], max_waves(L.nmax))
-                                 : auto_waves(L.nmax, L.ppad, L.nmax_jobs, L.mmax, L.x16);
-    while (L.waves > 1 &&
-           lb2m_lds_bytes(L.nmax, L.ppad, L.nmax_jobs, L.mmax, L.waves, L.x16) > kLdsM)
+    const int pref = mt->waves[cls == 0 ? 0 : 1];  // small: the quick class; large: the rest
+    L.waves = pref > 0 ? std::min(pref, max_waves(cls))
+                       : auto_waves(cls, L.ppad, L.nmax_jobs, L.mmax, L.x16);
+    while (L.waves > 1 && lb2m_lds_bytes(L.nmax, L.ppad, L.nmax_jobs, L.mmax, L.waves, L.x16,
+                                         L.wide) > kLdsM)
       --L.waves;
-    const size_t lds = lb2m_lds_bytes(L.nmax, L.ppad, L.nmax_jobs, L.mmax, L.waves, L.x16);
+    const size_t lds =
+        lb2m_lds_bytes(L.nmax, L.ppad, L.nmax_jobs, L.mmax, L.waves, L.x16, L.wide);
     const int per_cu = std::max(1, (int)((kLdsM) / std::max<size_t>(lds, 1)));
     const int gpc = mt->grid_per_cu > 0 ? mt->grid_per_cu : per_cu;
     L.grid = std::max(1, std::min(L.ntiles, c->cu_count * gpc));
@@ -350,7 +362,7 @@ int pfsp_multi_create(pfsp_ctx *h, int32_t count, const int32_t *n, const int32_
     x.P = x.m * (x.m - 1) / 2;
     x.narrow = maxp < 65536 && (int64_t)(x.m > 2 ? x.m - 2 : 0) * maxp < (1 << 24);
     x.l16 = x.narrow && (int64_t)(x.m > 1 ? x.m - 1 : 0) * maxp < (1 << 16);
-    x.x16 = x.l16 && (int64_t)(2 * x.n + 2 * x.m + 2) * maxp < (1 << 14);
+    x.x16 = x.l16 && (int64_t)(x.n + x.m) * maxp < (1 << 15);
     const size_t P = x.P > 0 ? x.P : 1;
     if (hipMalloc(&x.d_p, (size_t)x.n * x.m * 4) != hipSuccess ||
         hipMalloc(&x.d_T, (size_t)x.m * 4) != hipSuccess || hipMalloc(&x.d_pu, P) != hipSuccess ||
@@ -366,6 +378,9 @@ int pfsp_multi_create(pfsp_ctx *h, int32_t count, const int32_t *n, const int32_
     }
     rc = stage_tables(c, mt->stream, x.n, x.m, x.d_p, x.d_T, x.d_ent, x.d_entw, x.d_pu, x.d_pv,
                       x.narrow);
+    if (rc == PFSP_OK && x.narrow && x.x16 && x.n > 20 && x.n <= 128 && x.P > 0 &&
+        c->wide_lb2 && !c->force_generic)
+      rc = stage_quick(c, mt->stream, x.n, x.m, x.d_ent, &x.d_entq);
     x.cls = class_of(x, c);
     mt->nmax = std::max(mt->nmax, x.n);
     mt->mmax = std::max(mt->mmax, x.m);
@@ -376,7 +391,7 @@ int pfsp_multi_create(pfsp_ctx *h, int32_t count, const int32_t *n, const int32_
     if (hipMalloc(&mt->d_insts, count * sizeof(DevInst)) != hipSuccess ||
         hipMalloc(&mt->d_seg, (count + 1) * sizeof(long long)) != hipSuccess ||
         hipMalloc(&mt->d_ubs, count * sizeof(int)) != hipSuccess ||
-        hipMalloc(&mt->d_queue, 2 * sizeof(int)) != hipSuccess)
+        hipMalloc(&mt->d_queue, kNumCls * sizeof(int)) != hipSuccess)
       rc = set_err(c, PFSP_ENOMEM, "device allocation failed");
     else if (hipMemcpy(mt->d_insts, views.data(), count * sizeof(DevInst),
                        hipMemcpyHostToDevice) != hipSuccess)
@@ -395,7 +410,7 @@ void pfsp_multi_destroy(pfsp_multi *mt) {
   if (mt->stream) (void)hipStreamSynchronize(mt->stream);
   multi_drop_graph(mt);
   for (MultiInst &x : mt->in) {
-    void *bufs[] = {x.d_p, x.d_T, x.d_ent, x.d_entw, x.d_pu, x.d_pv};
+    void *bufs[] = {x.d_p, x.d_T, x.d_ent, x.d_entq, x.d_entw, x.d_pu, x.d_pv};
     for (void *b : bufs) (void)hipFree(b);
   }
   void *bufs[] = {mt->d_insts, mt->d_seg, mt->d_ubs, mt->d_costs, mt->d_tiles, mt->d_queue};

@@ -91,6 +91,33 @@ int stage_tables(Ctx *c, hipStream_t s, int n, int m, const int *d_p, int *d_T, 
   return PFSP_OK;
 }
 
+__global__ void k_stage_q(int n, int P, int Ppad, const uint2 *__restrict__ ent,
+                          uint2 *__restrict__ entq) {
+  const long long x = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (x >= (long long)Ppad * n) return;
+  const int pass = (int)(x / (64LL * n));
+  const int rem = (int)(x - (long long)pass * 64 * n);
+  const int i = rem >> 6, pi = pass * 64 + (rem & 63);
+  const uint2 s = ent[(size_t)i * P + (pi < P ? pi : 0)];
+  const unsigned a = s.x & 0xffffu, b = s.x >> 16, l = s.y & 0xffffffu, k = s.y >> 24;
+  entq[x] = make_uint2(((b - a) & 0xffffu) | ((a + l) << 16), k);
+}
+
+int stage_quick(Ctx *c, hipStream_t s, int n, int m, const uint2 *d_ent, uint2 **d_entq) {
+  const int P = m * (m - 1) / 2;
+  *d_entq = nullptr;
+  if (P == 0) return PFSP_OK;
+  const int Ppad = (P + 63) / 64 * 64;
+  PFSP_HIP(c, hipMalloc(d_entq, (size_t)Ppad * n * 8));
+  const long long tot = (long long)Ppad * n;
+  hipLaunchKernelGGL(k_stage_q, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, P, Ppad,
+                     d_ent, *d_entq);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_err(c, e, "k_stage_q");
+  return PFSP_OK;
+}
+
 int stage_instance(Ctx *c) {
   return stage_tables(c, c->stream, c->n, c->m, c->d_p, c->d_T, c->d_ent, c->d_entw, c->d_pu,
                       c->d_pv, c->narrow);

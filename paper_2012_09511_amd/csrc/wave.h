@@ -128,6 +128,67 @@ __device__ __forceinline__ int transpose_max_fb(const int (&f)[NJ], const int (&
   return acc[0];
 }
 
+// Two int16 halves per register: wrapping add, signed max (v_pk_add_u16,
+// v_pk_max_i16).
+typedef short pk16 __attribute__((ext_vector_type(2)));
+typedef unsigned short pku16 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ int pk_add(int x, int y) {
+  return __builtin_bit_cast(int, __builtin_bit_cast(pku16, x) + __builtin_bit_cast(pku16, y));
+}
+__device__ __forceinline__ int pk_max(int x, int y) {
+  return __builtin_bit_cast(
+      int, __builtin_elementwise_max(__builtin_bit_cast(pk16, x), __builtin_bit_cast(pk16, y)));
+}
+
+// Transposing max-reduction of 32 per-job values held as int16 pairs
+// (forward child low, backward child high), acc[OFF .. OFF + 32): on return
+// lane q < 32 holds the maximum over all lanes of the low half of job q and
+// lane 32 + q that of the high half (sign-extended).  Each step pairs two
+// lanes that differ in one lane bit and keeps the jobs whose matching job bit
+// equals the lane's: lane bit 5 <-> job bit 4 (permlane32 swap), 4 <-> 3
+// (permlane16 swap), 3, 2, 1 <-> 2, 1, 0 (DPP); lane bit 0 folds last, so
+// lane l ends with job l >> 1, and one lane gather puts job q in lanes q and
+// 32 + q.
+template <int O>
+__device__ __forceinline__ void pk_split_dpp(int (&a)[2 * O], int lane, int lb_mask) {
+  const bool hi = (lane & lb_mask) != 0;
+#pragma unroll
+  for (int j = 0; j < O; ++j) {
+    const int send = hi ? a[j] : a[O + j];
+    const int keep = hi ? a[O + j] : a[j];
+    int got;
+    if (lb_mask == 8) got = dpp_partner<8>(send);
+    else if (lb_mask == 4) got = dpp_partner<4>(send);
+    else got = dpp_partner<2>(send);
+    a[j] = pk_max(keep, got);
+  }
+}
+
+template <int OFF, int N>
+__device__ __forceinline__ int transpose_pkmax32(const int (&acc)[N], int lane) {
+  static_assert(OFF + 32 <= N, "32 jobs from OFF");
+  int t[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const auto r = __builtin_amdgcn_permlane32_swap(acc[OFF + j], acc[OFF + 16 + j], false, false);
+    t[j] = pk_max((int)r[0], (int)r[1]);
+  }
+  int u[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const auto r = __builtin_amdgcn_permlane16_swap(t[j], t[8 + j], false, false);
+    u[j] = pk_max((int)r[0], (int)r[1]);
+  }
+  pk_split_dpp<4>(u, lane, 8);
+  int (&u4)[4] = *reinterpret_cast<int (*)[4]>(&u[0]);
+  pk_split_dpp<2>(u4, lane, 4);
+  int (&u2)[2] = *reinterpret_cast<int (*)[2]>(&u[0]);
+  pk_split_dpp<1>(u2, lane, 2);
+  const int w = pk_max(u[0], dpp_partner<1>(u[0]));
+  const int g = __shfl(w, 2 * (lane & 31), kWave);
+  return lane < 32 ? (int)(short)(g & 0xffff) : g >> 16;
+}
+
 // Minimum over the wave through permlane swaps and DPP (no LDS crossbar).
 __device__ __forceinline__ int wave_min_xl(int x) {
   auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);

@@ -108,8 +108,9 @@ def test_edge_depths(ctx, kind):
 
 
 @pytest.mark.parametrize("n,m,lo,hi", [
-    (20, 20, 150, 199),   # largest times that keep 16-bit X at n = m = 20
-    (32, 20, 100, 154),   # the same bound at n = 32
+    (20, 20, 700, 819),   # largest times that keep 16-bit X at n = m = 20: (n + m) max p < 2^15
+    (32, 20, 500, 630),   # the same bound at n = 32
+    (20, 20, 700, 820),   # one above it: 32-bit X
     (20, 20, 1, 1500),    # 32-bit X
     (12, 7, 2000, 3000),  # 32-bit X, short rows
     (32, 5, 1, 16000),    # (m - 1) * max p just below 2^16
@@ -142,13 +143,18 @@ def _random_masks(rng, count, m, kmax):
 
 
 @pytest.mark.parametrize("group", [2, 4])
-@pytest.mark.parametrize("n,m,kmax", [(20, 20, 16), (20, 20, 40), (12, 7, 21), (32, 10, 45),
-                                      (16, 20, 190), (5, 3, 3), (2, 2, 1)])
-def test_packed_subset_parity(ctx, group, n, m, kmax):
+@pytest.mark.parametrize("n,m,kmax,hi", [(20, 20, 16, 99), (20, 20, 40, 99), (12, 7, 21, 99),
+                                         (32, 10, 45, 99), (16, 20, 190, 99), (5, 3, 3, 99),
+                                         (2, 2, 1, 99), (20, 20, 16, 819), (32, 10, 45, 780)])
+def test_packed_subset_parity(ctx, group, n, m, kmax, hi):
     """Subset LB2 with 2 or 4 parents per wave: selections up to the group's
     lanes (one pass), beyond them (several passes) and empty; root and
-    one-job-left nodes; pool sizes that leave a wave partly empty."""
-    p = inputs.instance(n, m, 3000 + 64 * n + m)
+    one-job-left nodes; pool sizes that leave a wave partly empty; times up to
+    the 16-bit limit (n + m) max p < 2^15."""
+    if hi == 99:
+        p = inputs.instance(n, m, 3000 + 64 * n + m)
+    else:
+        p = np.random.default_rng(hi).integers(hi - 120, hi + 1, size=(n, m)).astype(np.int32)
     rng = np.random.default_rng(n * 100 + m + group)
     parts = [inputs.random_pool(n, 97, 41 + n), inputs.random_pool(n, 9, 42 + n, depth=0),
              inputs.random_pool(n, 13, 43 + n, depth=n - 1)]
@@ -161,6 +167,71 @@ def test_packed_subset_parity(ctx, group, n, m, kmax):
                mask=mask)
     finally:
         ctx.set_option("subset_group", 0)
+
+
+WIDE_CASES = [
+    (33, 2, 1, 99),      # one pass, last chunk of one position
+    (48, 16, 1, 99),     # n a multiple of the chunk length
+    (64, 20, 1, 99),     # a full 64-job table, three passes
+    (65, 9, 1, 99),      # smallest 128-job case
+    (100, 20, 200, 273),  # (n + m) max p = 32760, just below 2^15
+    (128, 7, 1, 240),    # a full 128-job table
+    (57, 20, 0, 425),    # zero times allowed, (n + m) max p = 32725
+]
+
+
+@pytest.mark.parametrize("n,m,lo,hi", WIDE_CASES)
+def test_wide_kernel_parity(ctx, n, m, lo, hi):
+    """Full LB2 for 32 < n <= 128 with 16-bit X (the wide kernel): random
+    pools plus root, one-job-left and two-jobs-left nodes, at an open and at a
+    mid-range incumbent; the kernel must be the one that ran, and the earlier
+    kernels give the same bytes."""
+    import torch
+    rng = np.random.default_rng(n * 7919 + m + hi)
+    p = rng.integers(lo, hi + 1, size=(n, m)).astype(np.int32)
+    count = 60 if n * m <= 1000 else 24
+    parts = [inputs.random_pool(n, count, 61 + n), inputs.random_pool(n, 5, 62 + n, depth=0),
+             inputs.random_pool(n, 9, 63 + n, depth=n - 1),
+             inputs.random_pool(n, 9, 64 + n, depth=n - 2)]
+    perm, d1, d2 = (np.concatenate([q[i] for q in parts]) for i in range(3))
+    ctx.set_option("timing", 1)
+    try:
+        ctx.kernel_time("k_lb2w", reset=True)
+        olb = _check(ctx, p, perm, d1, d2, binding.LB2_FULL, INT32_MAX)
+        assert ctx.kernel_time("k_lb2w")[1] == 1, "the wide kernel did not run"
+    finally:
+        ctx.set_option("timing", 0)
+    ub = int(np.median(olb[olb < INT32_MAX]))
+    _check(ctx, p, perm, d1, d2, binding.LB2_FULL, ub)
+    tp, t1, t2 = _dev(ctx, perm, d1, d2)
+    r = ctx.bound_children(tp, t1, t2, binding.LB2_FULL, ub)
+    torch.cuda.synchronize()
+    a = [x.cpu().numpy() for x in r[:3]]
+    ctx.set_option("wide_lb2", 0)
+    try:
+        r = ctx.bound_children(tp, t1, t2, binding.LB2_FULL, ub)
+        torch.cuda.synchronize()
+        b = [x.cpu().numpy() for x in r[:3]]
+    finally:
+        ctx.set_option("wide_lb2", 1)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_wide_kernel_not_taken_past_limit(ctx):
+    """(n + m) max p = 2^15 exactly: 16-bit X does not apply, the earlier
+    kernel runs and results stay exact."""
+    n, m = 44, 20
+    p = np.full((n, m), 512, dtype=np.int32)
+    p[::3, ::2] = 1
+    perm, d1, d2 = inputs.random_pool(n, 30, 71)
+    ctx.set_option("timing", 1)
+    try:
+        ctx.kernel_time("k_lb2w", reset=True)
+        _check(ctx, p, perm, d1, d2, binding.LB2_FULL, INT32_MAX)
+        assert ctx.kernel_time("k_lb2w")[1] == 0
+    finally:
+        ctx.set_option("timing", 0)
 
 
 def test_packed_subset_invalid_rows(ctx):

@@ -98,3 +98,30 @@ def test_class_with_fewer_machines_than_batch(ctx):
     lb, pr, dr = mt.bound(*_dev(ctx, perm, d1, d2), seg, ub, binding.LB2_FULL)
     _check(insts, perm, d1, d2, seg, ub, lb, pr, dr, binding.LB2_FULL)
     mt.close()
+
+
+def test_wide_classes(ctx):
+    """Instances of every class in one batch: n <= 20 (quick), 20 < n <= 64 and
+    64 < n <= 128 with 16-bit X (wide), n <= 64 with times past the 16-bit
+    limit (scan kernel) and n > 128 (generic); root and leaf-parent rows."""
+    rng = np.random.default_rng(4242)
+    shapes = [(12, 6, 99), (25, 5, 99), (50, 20, 99), (64, 3, 99), (65, 11, 99),
+              (100, 20, 273), (128, 4, 99), (40, 10, 900), (130, 3, 99)]
+    insts = [(n, m, rng.integers(1, hi + 1, size=(n, m)).astype(np.int32)) for n, m, hi in shapes]
+    per = [50, 40, 12, 30, 10, 4, 6, 20, 3]
+    stride = max(n for n, _, _ in insts)
+    perm, d1, d2, seg = _batch(insts, per, 303, stride)
+    for k, (n, m, p) in enumerate(insts):   # first row: the root; second: one job left
+        a = seg[k]
+        d1[a], d2[a] = 0, 0
+        d1[a + 1], d2[a + 1] = n - 1, 0
+    ub = np.array([3000 + 500 * k for k in range(len(insts))], dtype=np.int32)
+    mt = binding.Multi(ctx, [p for _, _, p in insts])
+    dev = _dev(ctx, perm, d1, d2)
+    for rep in range(2):
+        lb, pr, dr = mt.bound(*dev, seg, ub, binding.LB2_FULL)
+        _check(insts, perm, d1, d2, seg, ub, lb, pr, dr, binding.LB2_FULL)
+    mt.set_shape(tile=8, waves_small=3, waves_large=2, blocks_per_cu=1)
+    lb, pr, dr = mt.bound(*dev, seg, ub, binding.LB2_FULL)
+    _check(insts, perm, d1, d2, seg, ub, lb, pr, dr, binding.LB2_FULL)
+    mt.close()

@@ -1131,19 +1131,27 @@ __device__ void lb2q_parent(const DevInst &I, int Ppad, const QuickLds<NMAX> &S,
   const uint32_t umask =
       (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)__ballot(member && !bwd));
   // LB1 of both children of job k, and the start times f (forward child,
-  // machines in order) or g (backward child, machines reversed)
+  // machines in order) or g (backward child, machines reversed).  X16: one
+  // table of int16 pairs, f in the low half of [s][k] and g in the high half
+  // of [m - 1 - s][k] (by the machine's own index; both below 2^15)
   int lb1 = 0;
   if (k < NMAX) {
     const int2 *HT = bwd ? S.HTb : S.HTf;
     const int *PT = (bwd ? S.pr : S.pt) + k;
     int *FB = (bwd ? S.FBb : S.FBf) + k;
+    unsigned short *fb16 =
+        (unsigned short *)S.FBf + 2 * k + (bwd ? 1 + 2 * (m - 1) * ROW : 0);
+    const int fstep = bwd ? -2 * ROW : 2 * ROW;
     int c = 0;
 #pragma unroll 4
     for (int s = 0; s < m; ++s) {
       const int2 ht = HT[s];
       const int f = max(c, ht.x);
       c = f + PT[s * 32];
-      FB[s * ROW] = f;
+      if constexpr (X16)
+        fb16[s * fstep] = (unsigned short)f;
+      else
+        FB[s * ROW] = f;
       lb1 = max(lb1, f + ht.y);
     }
   }
@@ -1157,9 +1165,14 @@ __device__ void lb2q_parent(const DevInst &I, int Ppad, const QuickLds<NMAX> &S,
     for (int o = 32; o >= 1; o >>= 1) nsel += __shfl_xor(nsel, o, kWave);
     nsel = __builtin_amdgcn_readfirstlane(nsel);
   }
-  int accf[NMAX], accb[NMAX];
+  // pair maxima per job: X16 keeps both directions in one register as int16
+  // halves (every pair term of a child is at most (n + m - 1) max p < 2^15)
+  constexpr int NA = X16 ? 1 : NMAX;
+  int accf[NA], accb[NA], acc[X16 ? NMAX : 1];
 #pragma unroll
-  for (int q = 0; q < NMAX; ++q) accf[q] = accb[q] = kNeg;
+  for (int q = 0; q < NA; ++q) accf[q] = accb[q] = kNeg;
+#pragma unroll
+  for (int q = 0; q < (X16 ? NMAX : 1); ++q) acc[q] = (int)0x80008000u;
   const int npass = r < 2 ? 0 : SUBSET ? nsel : (P > 0 ? Ppad : 0);  // leaves: LB2 = LB1
   constexpr int NEGX = X16 ? -(1 << 14) : kNeg;
   int2 *__restrict__ Xl = (int2 *)S.X + lane;
@@ -1172,7 +1185,7 @@ __device__ void lb2q_parent(const DevInst &I, int Ppad, const QuickLds<NMAX> &S,
     const int u = uvp & 0xff, v = uvp >> 8;
     const int K4 = S.rr[v] + S.c2[v], K5 = S.c1[u] + S.rr[v];
     const int *Fu = S.FBf + u * ROW;
-    const int *Gv = S.FBb + (m - 1 - v) * ROW;
+    const int *Gv = X16 ? S.FBf + v * ROW : S.FBb + (m - 1 - v) * ROW;
     const uint2 *__restrict__ eb = S.ent + (pi >> 6) * (NMAX * 64) + (pi & 63);
     // forward scan: terms of members (NEG for the others) and exclusive prefix maxima
     int pm[NMAX], tm[NMAX];
@@ -1215,34 +1228,56 @@ __device__ void lb2q_parent(const DevInst &I, int Ppad, const QuickLds<NMAX> &S,
 #pragma unroll
     for (int g = 0; g < NMAX; g += 4) {
       if (umask & (0xfu << g)) {
-        int xa[4], xb[4], fu[4], gv[4];
+        if constexpr (X16) {  // f_u + xa | g_v + xb in int16 halves
+          int h[4], fw[4], gw[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          if (g + j < NMAX) {
-            if constexpr (X16) {
-              const int h = Xh[(g + j) * 64];
-              xa[j] = (int)(short)(h & 0xffff);
-              xb[j] = h >> 16;
-            } else {
+          for (int j = 0; j < 4; ++j) {
+            if (g + j < NMAX) {
+              h[j] = Xh[(g + j) * 64];
+              fw[j] = Fu[g + j];
+              gw[j] = Gv[g + j];
+            }
+          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (g + j < NMAX) {
+              const int fg =
+                  (int)__builtin_amdgcn_perm((unsigned)gw[j], (unsigned)fw[j], 0x07060100u);
+              acc[g + j] = pk_max(acc[g + j], pk_add(fg, h[j]));
+            }
+          }
+        } else {
+          int xa[4], xb[4], fu[4], gv[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (g + j < NMAX) {
               const int2 x = Xl[(g + j) * 64];
               xa[j] = x.x + K4;
               xb[j] = x.y + K5;
+              fu[j] = Fu[g + j];
+              gv[j] = Gv[g + j];
             }
-            fu[j] = Fu[g + j];
-            gv[j] = Gv[g + j];
           }
-        }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          if (g + j < NMAX) {
-            accf[g + j] = max(accf[g + j], fu[j] + xa[j]);
-            accb[g + j] = max(accb[g + j], gv[j] + xb[j]);
+          for (int j = 0; j < 4; ++j) {
+            if (g + j < NMAX) {
+              accf[g + j] = max(accf[g + j], fu[j] + xa[j]);
+              accb[g + j] = max(accb[g + j], gv[j] + xb[j]);
+            }
           }
         }
       }
     }
   }
-  const int t = transpose_max_fb<NMAX>(accf, accb, lane, kNeg);
+  int t;
+  if constexpr (X16) {
+    int a32[32];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) a32[q] = q < NMAX ? acc[q < NMAX ? q : 0] : (int)0x80008000u;
+    t = transpose_pkmax32<0>(a32, lane);
+  } else {
+    t = transpose_max_fb<NMAX>(accf, accb, lane, kNeg);
+  }
   const int val = member ? max(lb1, t) : kInt32Max;
   if (member) {
     const int o = (bwd ? stride : 0) + slot;

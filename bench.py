@@ -113,6 +113,9 @@ def main():
     ap.add_argument("--selector", default=os.path.join(ROOT, "paper_2012_09511_amd", "data",
                                                        "selector_n50m20.npy"))
     ap.add_argument("--topk", type=int, default=16, help="pairs kept by the learned selector")
+    ap.add_argument("--float-selector", action="store_true",
+                    help="learned workload: rank pairs with the float model instead of its "
+                         "int8 form")
     ap.add_argument("--no-graph", action="store_true",
                     help="search steps as plain launches (profilers see graph replays as one)")
     args = ap.parse_args()
@@ -320,11 +323,11 @@ def bench_multi(args):
 
 
 def bench_learned(args):
-    """Full LB2 vs learned-pair LB2 (top-16) searches to the same proven optimum."""
+    """Full LB2 vs learned-pair LB2 (top-k) searches to the same proven optimum."""
     import torch
-    from paper_2012_09511_amd import binding, inputs
+    from paper_2012_09511_amd import binding, inputs, selector_quant
     ctx = binding.Context(0)
-    params = np.load(args.selector)
+    params = np.load(args.selector, allow_pickle=False)
     ctx.selector_set(params)
     ctx.set_option("learned_topk", args.topk)
     if args.no_graph:
@@ -334,6 +337,9 @@ def bench_learned(args):
     for seed in range(600, 608):
         p = inputs.instance(20, 20, seed)
         ctx.load_instance(p)
+        if not args.float_selector:   # int8 form, calibrated on random nodes of this instance
+            ctx.selector_set_quant(selector_quant.quantize(
+                params, selector_quant.calibration_features(ctx, 20, 4096, seed)))
         ub0, _ = ctx.neh()
         for _, kind in modes:   # untimed: workspaces and graph capture for this instance
             ctx.search(ub0 + 1, 1, kind)
@@ -355,7 +361,8 @@ def bench_learned(args):
                ms_per_step=tl * 1e3, higher_is_better=True, scaling="weak", vs_baseline=None,
                dtype="int32", data="synthetic",
                config=dict(workload="depth-first B&B, n=20 x m=20, seeds 600..607, NEH+1, "
-                                    f"learned top-{args.topk} of 190 pairs"),
+                                    f"learned top-{args.topk} of 190 pairs, "
+                                    + ("float" if args.float_selector else "int8") + " selector"),
                full_seconds=tf, learned_seconds=tl, instances=rows)
     ctx.close()
     print(json.dumps(out))

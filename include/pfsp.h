@@ -267,6 +267,28 @@ int pfsp_selector_forward(pfsp_ctx *c, const float *x, int32_t rows, float *scor
 int pfsp_selector_select(pfsp_ctx *c, const float *scores, int32_t rows, int32_t k,
                          uint32_t *mask_out);
 
+/* Integer-only deployment of the selector.  With these parameters set,
+ * PFSP_LB2_LEARNED ranks pairs with an int8 form of the MLP whose sums are
+ * exact integers (int8 weights and activations, int32 accumulation):
+ *   features  xq[j] = clamp(rint(float(c) * q), 0, 127), c the numerator of
+ *             feature j above (C1, C2, R, LB1 with q = sx / norm; d1, d2,
+ *             n - d1 - d2 with q = sx / n; float32 products; zero for absent
+ *             machines and invalid rows);
+ *   hidden    a = b + W xq (int32), h = min(127, (max(a, 0) * M + 2^(S-1)) >> S),
+ *             M in [1, 1023], S in [1, 30], per hidden layer;
+ *   scores    s = b3 + W3 h2 (int32); the k largest among present pairs, ties
+ *             to the lower layout index.
+ * blob (HOST int32, 20675 values): sx (float32 bits), M1, S1, M2, S2,
+ * W1[64][64], b1[64], W2[64][64], b2[64], W3[190][64], b3[190]; weights in
+ * [-127, 127], biases in (-2^19, 2^19) (else PFSP_ERANGE).  blob = NULL
+ * returns to the float model.  Synchronous. */
+int pfsp_selector_set_quant(pfsp_ctx *c, const int32_t *blob, int64_t count);
+
+/* Pair masks that PFSP_LB2_LEARNED would bound for every parent of the pool
+ * (the integer model if set, else the float model), k in [1, 32]: DEVICE
+ * mask_out[N][ceil(P/32)] over the instance's pair indices. */
+int pfsp_selector_infer(pfsp_ctx *c, const pfsp_pool *pool, int32_t k, uint32_t *mask_out);
+
 /* Training targets from argpair_out of an LB2_FULL pfsp_bound_children call on
  * the same pool: DEVICE target_out[N][190] = share of the parent's 2(n-d)
  * children whose LB2 is attained first by each layout pair (all zero if none).

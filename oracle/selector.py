@@ -11,7 +11,9 @@ of logged nodes.
 Everything here is float64 numpy, with the weights rounded to bfloat16 (round
 to nearest even) before use, as the kernels do.  Pinned in
 tests/test_selector_oracle.py against torch (bf16 conversion, autograd, Adam),
-finite differences and closed forms of the features.
+finite differences and closed forms of the features.  The integer model at the
+end (int8 codes, exact int64 sums) is pinned there by hand-computed codes and
+layers, invariances (hidden-unit permutation, score scaling) and brute force.
 """
 from __future__ import annotations
 
@@ -172,3 +174,84 @@ def pair_histogram(argpair, d1, d2, m):
             np.add.at(out[i], to20[vals], 1.0)
             out[i] /= len(vals)
     return out
+
+
+# ---------------------------------------------------------------- integer model
+# The deployed form of the selector: int8 weights and activations, int32
+# sums, so that every score is an exact integer.  A blob of int32 holds
+#   [0] the feature scale sx (float32 bits), [1..4] M1, S1, M2, S2,
+#   W1[64][64], b1[64], W2[64][64], b2[64], W3[190][64], b3[190].
+Q_HEAD = 5
+Q_LEN = Q_HEAD + N_HID * N_IN + N_HID + N_HID * N_HID + N_HID + N_OUT * N_HID + N_OUT
+
+
+def quant_unpack(blob):
+    """(sx float32, M1, S1, M2, S2, W1, b1, W2, b2, W3, b3) with int64 arrays."""
+    b = np.asarray(blob, dtype=np.int64).reshape(-1)
+    assert b.size == Q_LEN
+    sx = np.array([b[0]], dtype=np.int64).astype(np.uint32).view(np.float32)[0]
+    o = Q_HEAD
+    out = []
+    for shape in ((N_HID, N_IN), (N_HID,), (N_HID, N_HID), (N_HID,), (N_OUT, N_HID), (N_OUT,)):
+        size = int(np.prod(shape))
+        out.append(b[o:o + size].reshape(shape))
+        o += size
+    return (sx, int(b[1]), int(b[2]), int(b[3]), int(b[4]), *out)
+
+
+def quant_code(c, q) -> int:
+    """clamp(rint(float32(c) * q), 0, 127), the product in float32 (ties to even)."""
+    v = np.float32(c) * np.float32(q)
+    return int(min(max(np.rint(v), np.float32(0)), np.float32(127)))
+
+
+def quant_features(p, perm, d1, d2, sx):
+    """int64 [B, 64] feature codes of the integer model: each feature of
+    features() has an integer numerator c (C1, C2, R, LB1 over the largest
+    machine load norm; d1, d2 and the unscheduled count over n) and its code is
+    quant_code(c, sx / norm) or quant_code(c, sx / n), both quotients in
+    float32."""
+    import oracle
+    p = np.asarray(p)
+    n, m = p.shape
+    norm = np.float32(int(p.sum(axis=0).max()))
+    qs = np.float32(np.float32(sx) / norm)
+    qd = np.float32(np.float32(sx) / np.float32(n))
+    out = np.zeros((len(perm), N_IN), dtype=np.int64)
+    for i in range(len(perm)):
+        a, b = int(d1[i]), int(d2[i])
+        C1 = oracle.front(p, perm[i][:a])
+        C2 = oracle.back(p, perm[i][n - b:])
+        R = p[perm[i][a:n - b]].sum(axis=0).astype(np.int64)
+        for k in range(min(m, M_MAX)):
+            out[i, k] = quant_code(int(C1[k]), qs)
+            out[i, 20 + k] = quant_code(int(C2[k]), qs)
+            out[i, 40 + k] = quant_code(int(R[k]), qs)
+        out[i, 60] = quant_code(a, qd)
+        out[i, 61] = quant_code(b, qd)
+        out[i, 62] = quant_code(n - a - b, qd)
+        out[i, 63] = quant_code(int(oracle.lb1_parts(C1, R, C2)), qs)
+    return out
+
+
+def requant(a, M, S):
+    """min(127, (max(a, 0) * M + 2^(S-1)) >> S): ReLU, then the fixed-point
+    multiply by M / 2^S rounded half up, saturated to int8."""
+    a = np.maximum(np.asarray(a, dtype=np.int64), 0)
+    return np.minimum((a * M + (1 << (S - 1))) >> S, 127)
+
+
+def quant_forward(blob, xq):
+    """int64 scores [B, 190] of the integer model on feature codes xq [B, 64]."""
+    _, M1, S1, M2, S2, W1, b1, W2, b2, W3, b3 = quant_unpack(blob)
+    x = np.asarray(xq, dtype=np.int64)
+    h1 = requant(x @ W1.T + b1, M1, S1)
+    h2 = requant(h1 @ W2.T + b2, M2, S2)
+    return h2 @ W3.T + b3
+
+
+def quant_masks(blob, p, perm, d1, d2, k):
+    """bool [B, 190]: the learned bound's pairs under the integer model."""
+    sx = quant_unpack(blob)[0]
+    s = quant_forward(blob, quant_features(p, perm, d1, d2, sx))
+    return topk_mask(s, valid_pairs(np.asarray(p).shape[1]), k)

@@ -26,8 +26,10 @@ EXPORTS = ["pfsp_create", "pfsp_destroy", "pfsp_last_error", "pfsp_load_instance
            "pfsp_selector_get", "pfsp_selector_features", "pfsp_selector_forward",
            "pfsp_selector_select", "pfsp_selector_targets", "pfsp_selector_train_step",
            "pfsp_search_log", "pfsp_multi_create", "pfsp_multi_destroy", "pfsp_multi_bound",
-           "pfsp_multi_set_shape", "pfsp_multi_autotune", "pfsp_autotune"]
+           "pfsp_multi_set_shape", "pfsp_multi_autotune", "pfsp_autotune",
+           "pfsp_selector_set_quant", "pfsp_selector_infer"]
 SELECTOR_PARAMS = 20670
+SELECTOR_QPARAMS = 20675
 
 
 class PfspError(RuntimeError):
@@ -97,6 +99,8 @@ def lib():
         L.pfsp_selector_targets.argtypes = [vp, ctypes.POINTER(Pool), vp, vp]
         L.pfsp_selector_train_step.argtypes = [vp, vp, vp, i32, ctypes.c_float,
                                                ctypes.POINTER(ctypes.c_float), vp]
+        L.pfsp_selector_set_quant.argtypes = [vp, vp, i64]
+        L.pfsp_selector_infer.argtypes = [vp, ctypes.POINTER(Pool), i32, vp]
         for name in EXPORTS:
             if name not in ("pfsp_destroy", "pfsp_last_error", "pfsp_multi_destroy"):
                 getattr(L, name).restype = ctypes.c_int
@@ -254,6 +258,24 @@ class Context:
         out = np.empty(SELECTOR_PARAMS, dtype=np.float32)
         self._check(lib().pfsp_selector_get(self.h, out.ctypes.data_as(ctypes.c_void_p),
                                             out.size))
+        return out
+
+    def selector_set_quant(self, blob):
+        """blob: int32 array of 20675 (the integer model), or None for the float model."""
+        if blob is None:
+            self._check(lib().pfsp_selector_set_quant(self.h, None, 0))
+            return
+        flat = np.ascontiguousarray(np.asarray(blob, dtype=np.int32).reshape(-1))
+        self._check(lib().pfsp_selector_set_quant(self.h, flat.ctypes.data_as(ctypes.c_void_p),
+                                                  flat.size))
+
+    def selector_infer(self, perm, d1, d2, k):
+        """Pair masks [N][ceil(P/32)] (int32 view of the uint32 words) of the learned bound."""
+        torch = self.torch
+        out = torch.empty((perm.shape[0], self.mask_words), dtype=torch.int32,
+                          device=self.device)
+        pool = self._pool(perm, d1, d2)
+        self._check(lib().pfsp_selector_infer(self.h, ctypes.byref(pool), int(k), _ptr(out)))
         return out
 
     def selector_features(self, perm, d1, d2):

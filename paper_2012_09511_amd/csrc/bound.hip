@@ -1788,6 +1788,32 @@ __device__ __forceinline__ int group_transpose_max(int (&acc)[L], int lane) {
   return acc[0];
 }
 
+// The same network on int16 pairs (both halves reduced independently).
+template <int O, int N>
+__device__ __forceinline__ void transpose_pkmax_dpp(int (&acc)[N], int lane) {
+  const bool hi = (lane & O) != 0;
+#pragma unroll
+  for (int j = 0; j < O; ++j) {
+    const int send = hi ? acc[j] : acc[O + j];
+    const int keep = hi ? acc[O + j] : acc[j];
+    acc[j] = pk_max(keep, dpp_partner<O>(send));
+  }
+  if constexpr (O > 1) transpose_pkmax_dpp<O / 2>(acc, lane);
+}
+
+template <int L>
+__device__ __forceinline__ int group_transpose_pkmax(int (&acc)[L], int lane) {
+  if constexpr (L == 32) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const auto r = __builtin_amdgcn_permlane16_swap(acc[j], acc[16 + j], false, false);
+      acc[j] = pk_max((int)r[0], (int)r[1]);
+    }
+  }
+  transpose_pkmax_dpp<8>(acc, lane);
+  return acc[0];
+}
+
 // Global inputs of one parent as the lanes hold them: row byte `lane` (lane
 // < n), costs C1, C2, R of machine `lane` (lane < m), mask word `lane`
 // (lane < words), and d1, d2.  Loaded one batch ahead so that their latency
@@ -1824,7 +1850,7 @@ __device__ void lb2s_wave(const DevInst &I, int Ppad, const PackLds<NMAX, G> &S,
                           int lane) {
   constexpr int L = 64 / G;
   constexpr int ROW = PackLayout::row(NMAX);
-  constexpr int NB = (2 * NMAX + L - 1) / L;  // blocks of L (direction, job) elements
+  constexpr int NB = (NMAX + L - 1) / L;  // blocks of L jobs (both directions per job)
   constexpr int NEGX = -(1 << 14);
   const int n = I.n, m = I.m, P = I.P, ns = pool.n;
   const int gl = lane / L, l = lane % L;  // this lane's group and position in it
@@ -1916,9 +1942,9 @@ __device__ void lb2s_wave(const DevInst &I, int Ppad, const PackLds<NMAX, G> &S,
       nsg = nsel[g];
     }
   const PackParent<NMAX> Q = S.parent(gl);  // this lane's parent
-  int accf[NMAX], accb[NMAX];
+  int acc[NMAX];  // pair maxima per job: forward | backward << 16 (int16 halves)
 #pragma unroll
-  for (int q = 0; q < NMAX; ++q) accf[q] = accb[q] = kNeg;
+  for (int q = 0; q < NMAX; ++q) acc[q] = (int)0x80008000u;
   int *__restrict__ Xh = S.X + lane;
   for (int pc = 0; pc < nmax_sel; pc += L) {
     const int idx = pc + l;
@@ -1926,8 +1952,8 @@ __device__ void lb2s_wave(const DevInst &I, int Ppad, const PackLds<NMAX, G> &S,
     const int uvp = S.uv[pi];
     const int u = uvp & 0xff, v = uvp >> 8;
     const int K4 = Q.rr[v] + Q.c2[v], K5 = Q.c1[u] + Q.rr[v];
-    const unsigned short *Fu = (const unsigned short *)(Q.fb + u * ROW);
-    const unsigned short *Gv = (const unsigned short *)(Q.fb + v * ROW) + 1;
+    const int *Fu = (const int *)Q.fb + u * ROW;  // f_u in the low halves
+    const int *Gv = (const int *)Q.fb + v * ROW;  // g_v in the high halves
     const uint2 *__restrict__ eb = S.ent + (pi >> 6) * (NMAX * 64) + (pi & 63);
     int pm[NMAX], tm[NMAX];
     unsigned ke[NMAX];
@@ -1956,28 +1982,27 @@ __device__ void lb2s_wave(const DevInst &I, int Ppad, const PackLds<NMAX, G> &S,
 #pragma unroll
     for (int g0 = 0; g0 < NMAX; g0 += 4) {
       if (uany & (0xfu << g0)) {
-        int xa[4], xb[4], fu[4], gv[4];
+        int h[4], fw[4], gw[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           if (g0 + j < NMAX) {
-            const int h = Xh[(g0 + j) * 64];
-            xa[j] = (int)(short)(h & 0xffff);
-            xb[j] = h >> 16;
-            fu[j] = Fu[2 * (g0 + j)];
-            gv[j] = Gv[2 * (g0 + j)];
+            h[j] = Xh[(g0 + j) * 64];
+            fw[j] = Fu[g0 + j];
+            gw[j] = Gv[g0 + j];
           }
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           if (g0 + j < NMAX) {
-            accf[g0 + j] = max(accf[g0 + j], fu[j] + xa[j]);
-            accb[g0 + j] = max(accb[g0 + j], gv[j] + xb[j]);
+            const int fg =
+                (int)__builtin_amdgcn_perm((unsigned)gw[j], (unsigned)fw[j], 0x07060100u);
+            acc[g0 + j] = pk_max(acc[g0 + j], pk_add(fg, h[j]));
           }
         }
       }
     }
   }
-  // fold over each group's lanes: element e = dir * NMAX + job, block e / L
+  // fold over each group's lanes: job b * L + j of block b
   int t[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
@@ -1985,16 +2010,15 @@ __device__ void lb2s_wave(const DevInst &I, int Ppad, const PackLds<NMAX, G> &S,
 #pragma unroll
     for (int j = 0; j < L; ++j) {
       const int e = b * L + j;
-      blk[j] = e < NMAX ? accf[e < NMAX ? e : 0]
-                        : (e < 2 * NMAX ? accb[e < 2 * NMAX && e >= NMAX ? e - NMAX : 0] : kNeg);
+      blk[j] = e < NMAX ? acc[e < NMAX ? e : 0] : (int)0x80008000u;
     }
-    t[b] = group_transpose_max<L>(blk, lane);
+    t[b] = group_transpose_pkmax<L>(blk, lane);
   }
-  // outputs and MinMin, per group
+  // outputs and MinMin, per group: lane l of block b takes job b * L + l in
+  // both directions
   int vmin = kInt32Max;
-  int val[NB];
-  int slot[NB];
-  bool mem[NB], dirb[NB];
+  int valf[NB], valb[NB];
+  bool mem[NB];
   const bool okg = [&] {
     bool o = false;
 #pragma unroll
@@ -2016,38 +2040,35 @@ __device__ void lb2s_wave(const DevInst &I, int Ppad, const PackLds<NMAX, G> &S,
   uint8_t *prow = out_prune + (size_t)(par >= 0 ? par : 0) * 2 * ns;
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    const int e = b * L + l;
-    const bool live = okg && e < 2 * NMAX;
-    const int dr = e >= NMAX, q = e - (dr ? NMAX : 0);
-    const bool member = live && q < n && ((umask >> q) & 1u);
+    const int q = b * L + l;
+    const bool member = okg && q < NMAX && q < n && ((umask >> (q & 31)) & 1u);
     const int sl = member ? Q.inv[q] - ag : 0;
-    const int pairmax = nsg > 0 ? t[b] : kNeg;
-    const int v = member ? max(Q.lb1[(dr ? 32 : 0) + q], pairmax) : kInt32Max;
+    const int pf = nsg > 0 ? (int)(short)(t[b] & 0xffff) : kNeg;
+    const int pb = nsg > 0 ? t[b] >> 16 : kNeg;
+    const int vf = member ? max(Q.lb1[q & 31], pf) : kInt32Max;
+    const int vb = member ? max(Q.lb1[32 + (q & 31)], pb) : kInt32Max;
     if (member) {
-      lbrow[(dr ? ns : 0) + sl] = v;
-      prow[(dr ? ns : 0) + sl] = v >= ub;
+      lbrow[sl] = vf;
+      prow[sl] = vf >= ub;
+      lbrow[ns + sl] = vb;
+      prow[ns + sl] = vb >= ub;
     }
-    val[b] = v;
+    valf[b] = vf;
+    valb[b] = vb;
     mem[b] = member;
-    dirb[b] = dr;
-    slot[b] = sl;
-    vmin = min(vmin, v);
+    vmin = min(vmin, min(vf, vb));
   }
   const int cmn = group_min<L>(vmin);
   int cf = 0, cb = 0, flo = 0, fhi = 0, blo = 0, bhi = 0;
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     if (mem[b]) {
-      const int v = val[b];
-      if (dirb[b]) {
-        cb += v == cmn;
-        blo += v & 0xffff;
-        bhi += v >> 16;
-      } else {
-        cf += v == cmn;
-        flo += v & 0xffff;
-        fhi += v >> 16;
-      }
+      cf += valf[b] == cmn;
+      flo += valf[b] & 0xffff;
+      fhi += valf[b] >> 16;
+      cb += valb[b] == cmn;
+      blo += valb[b] & 0xffff;
+      bhi += valb[b] >> 16;
     }
   }
   cf = group_sum<L>(cf);
@@ -2082,11 +2103,12 @@ __device__ void lb2s_wave(const DevInst &I, int Ppad, const PackLds<NMAX, G> &S,
   wave_sync();  // the next parents rewrite this wave's tables
 }
 
-// At most 8 waves per block: the per-parent tables limit a CU to about eight
-// resident waves anyway, and the register budget of two waves per SIMD keeps
-// the G parents' state out of scratch.
+// Blocks of up to 8 waves (two per SIMD, the register budget that keeps the
+// G parents' state out of scratch); two parents of at most 20 jobs fit three
+// waves per SIMD, and their blocks take up to 12 waves.
 template <int NMAX, int G>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(G == 2 && NMAX <= 20 ? 768 : 512)
+    __attribute__((amdgpu_waves_per_eu(G == 2 && NMAX <= 20 ? 3 : 1)))
 k_lb2s(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__restrict__ out_lb,
        uint8_t *__restrict__ out_prune, int Ppad) {
   extern __shared__ __align__(16) unsigned char sm[];
@@ -2588,7 +2610,8 @@ static int launch_lb2s(Ctx *c, const DevPool &pool, int G, int ub, int *out_lb,
   const int nmax = c->n <= 16 ? 16 : c->n <= 20 ? 20 : 32;
   if (nmax == 32) G = 2;  // four parents' state of 32 jobs does not fit the registers
   int waves = 0, best = 0;
-  for (int w = 8; w >= 1; --w) {
+  const int wmax = G == 2 && nmax <= 20 ? 12 : 8;  // the kernels' launch bounds
+  for (int w = wmax; w >= 1; --w) {
     const size_t l = lb2s_lds(c, nmax, G, w);
     const int per_cu = l <= 160 * 1024 ? (int)((160 * 1024) / l) * w : 0;
     if (per_cu > best) {
@@ -2617,8 +2640,6 @@ static int launch_lb2s(Ctx *c, const DevPool &pool, int G, int ub, int *out_lb,
   return PFSP_OK;
 }
 
-// LB2 kinds once launch_costs has run for the same pool.  group: parents per
-// wave for subset bounds (1, 2 or 4; 0 = the context's "subset_group").
 // Wide-kernel LDS of one block: the most resident waves per CU within 160 KiB.
 static int wide_waves(const WideLayout &L, int nmax, int pref) {
   int waves = 0, best = 0;
@@ -2660,6 +2681,8 @@ static int launch_lb2w(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8_t
   return PFSP_OK;
 }
 
+// LB2 kinds once launch_costs has run for the same pool.  group: parents per
+// wave for subset bounds (1, 2 or 4; 0 = the context's "subset_group").
 int launch_bound_costs_ready(Ctx *c, const DevPool &pool, int kind, int ub, int *out_lb,
                              uint8_t *out_prune, hipStream_t s, int group) {
   if (pool.count <= 0) return PFSP_OK;

@@ -14,11 +14,14 @@
 //   [0,20) front C1[k]/norm, [20,40) back C2[k]/norm, [40,60) remaining
 //   R[k]/norm for machines k < min(m, 20) (zero beyond), 60: d1/n, 61: d2/n,
 //   62: (n - d1 - d2)/n, 63: LB1(parent)/norm.
+#include <limits.h>
 #include <math.h>
+#include <string.h>
 
 #include <vector>
 
 #include "internal.h"
+#include "wave.h"
 
 namespace pfsp {
 
@@ -45,6 +48,12 @@ struct Selector {
   size_t train_cap = 0;
   int *to_inst = nullptr;  // [190]: instance pair index of each layout pair, -1 if absent
   int to_inst_m = -1;
+  // integer-only model (used by the learned bound when set)
+  uint2 *qops = nullptr;  // int8 MFMA B operands
+  int *qbias = nullptr;   // per-lane biases
+  float sx = 0.f;
+  int M1 = 0, S1 = 0, M2 = 0, S2 = 0;
+  int qloaded = 0;
 };
 
 // round to nearest even bfloat16, kept as float
@@ -199,6 +208,247 @@ k_infer(DevInst I, DevPool pool, const int *__restrict__ costs, float norm,
   for (int q = 0; q < KMAX; ++q) {
     if (q < k && idx[q] >= 0) {
       const int pi = to_inst[idx[q]];
+      const uint32_t bit = 1u << (pi & 31);
+      const int wd = pi >> 5;
+      w0 |= wd == 0 ? bit : 0u;
+      w1 |= wd == 1 ? bit : 0u;
+      w2 |= wd == 2 ? bit : 0u;
+      w3 |= wd == 3 ? bit : 0u;
+      w4 |= wd == 4 ? bit : 0u;
+      w5 |= wd == 5 ? bit : 0u;
+    }
+  }
+  uint32_t *mi = mask + (size_t)i * words;
+  const uint32_t ws[6] = {w0, w1, w2, w3, w4, w5};
+#pragma unroll
+  for (int wd = 0; wd < 6; ++wd)
+    if (wd < words) mi[wd] = ws[wd];
+}
+
+// ------------------------------------------------- integer-only inference
+// The deployed selector is the MLP above quantized to int8 weights and
+// activations with int32 accumulation, so every score is an exact integer
+// and the ranking does not depend on the order of the sums:
+//   features   xq[j] = clamp(rint(float(c) * q), 0, 127), c the integer
+//              feature numerator (C1, C2, R, LB1 with q = sx / norm; d1, d2,
+//              n - d1 - d2 with q = sx / n; zero for absent machines and
+//              invalid rows), sx the feature scale (float32);
+//   hidden     a = b + W.in (int32), h = min(127, (max(a, 0) * M + 2^(S-1)) >> S)
+//              per layer (M in [1, 1023], S in [1, 30]);
+//   scores     s = b3 + W3.h2 (int32); top-k pairs by s, ties to the lower
+//              layout index (key s * 256 + 255 - index, unique).
+// Blob (int32): sx bits, M1, S1, M2, S2, W1[64][64], b1[64], W2[64][64],
+// b2[64], W3[190][64], b3[190]; weights in [-127, 127], |b| < 2^19.
+constexpr int kQHead = 5;
+constexpr int kQOffW1 = kQHead, kQOffB1 = kQOffW1 + kHid * kIn, kQOffW2 = kQOffB1 + kHid,
+              kQOffB2 = kQOffW2 + kHid * kHid, kQOffW3 = kQOffB2 + kHid,
+              kQOffB3 = kQOffW3 + kOut * kHid, kQParams = kQOffB3 + kOut;
+// Device form: int8 MFMA B operands per (layer, column tile t, k step, lane)
+// and per-lane biases.  v_mfma_i32_16x16x32_i8: lane l holds A row l % 16
+// and B column l % 16 over k = 8 (l / 16) .. + 7; D register j is row
+// 4 (l / 16) + j, column l % 16.  Hidden layers: tile t, column c computes
+// unit 4c + t, so each lane's four tiles give four consecutive units (one
+// 32-bit LDS store per row); the output layer: tile t, column c is pair
+// 16t + c (t < 12).
+constexpr int kQT1 = 4, kQT3 = 12;
+constexpr int kQOpB1 = 0, kQOpB2 = kQOpB1 + kQT1 * 2 * 64, kQOpB3 = kQOpB2 + kQT1 * 2 * 64,
+              kQOps = kQOpB3 + kQT3 * 2 * 64;  // uint2 entries
+constexpr int kQBias1 = 0, kQBias2 = kQT1 * 64, kQBias3 = 2 * kQT1 * 64,
+              kQBiases = kQBias3 + kQT3 * 64;  // int entries
+constexpr int kQWaves = 4, kQRowStride = 72;   // bytes per LDS activation row (8-aligned)
+constexpr int kQKeyStride = 20;                // ints per LDS key row (16-aligned)
+constexpr size_t kQWaveLds = 2 * 64 * kQRowStride + 64 * kQKeyStride * 4;
+
+typedef int qv4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int q8(float v) {  // rint, clamp to [0, 127]
+  return (int)fminf(fmaxf(rintf(v), 0.f), 127.f);
+}
+
+// Bitonic networks over unique keys (max/min exchanges).
+template <int N>
+__device__ __forceinline__ void bitonic_sort_desc(int (&a)[N]) {
+#pragma unroll
+  for (int k = 2; k <= N; k <<= 1)
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const int l = i ^ j;
+        if (l > i) {
+          const int hi = max(a[i], a[l]), lo = min(a[i], a[l]);
+          const bool desc = (i & k) == 0;
+          a[i] = desc ? hi : lo;
+          a[l] = desc ? lo : hi;
+        }
+      }
+}
+
+template <int N>
+__device__ __forceinline__ void bitonic_merge_desc(int (&a)[N]) {
+#pragma unroll
+  for (int j = N >> 1; j > 0; j >>= 1)
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const int l = i ^ j;
+      if (l > i) {
+        const int hi = max(a[i], a[l]), lo = min(a[i], a[l]);
+        a[i] = hi;
+        a[l] = lo;
+      }
+    }
+}
+
+// One hidden layer for the wave's 64 rows: A from `in` (row-major bytes),
+// int8 codes of the 64 units to `out`.
+__device__ __forceinline__ void q_hidden(const unsigned char *in, unsigned char *out,
+                                         const uint2 *__restrict__ ops, const int *__restrict__ bias,
+                                         int M, int S, int lane) {
+  const int c = lane & 15, g = lane >> 4;
+  long bq[kQT1][2];
+  int bb[kQT1];
+#pragma unroll
+  for (int t = 0; t < kQT1; ++t) {
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      const uint2 e = ops[(t * 2 + ks) * 64 + lane];
+      bq[t][ks] = (long)(((unsigned long)e.y << 32) | e.x);
+    }
+    bb[t] = bias[t * 64 + lane];
+  }
+  const unsigned rnd = 1u << (S - 1);
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const unsigned char *row = in + (16 * s + c) * kQRowStride + 8 * g;
+    const long a0 = *(const long *)row, a1 = *(const long *)(row + 32);
+    unsigned code[4] = {0u, 0u, 0u, 0u};  // rows 4g + j: units 4c .. 4c + 3
+#pragma unroll
+    for (int t = 0; t < kQT1; ++t) {
+      qv4 d = {0, 0, 0, 0};
+      d = __builtin_amdgcn_mfma_i32_16x16x32_i8(a0, bq[t][0], d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_i32_16x16x32_i8(a1, bq[t][1], d, 0, 0, 0);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const unsigned h = (unsigned)max(d[j] + bb[t], 0);
+        code[j] |= min((h * (unsigned)M + rnd) >> S, 127u) << (8 * t);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      *(unsigned *)(out + (16 * s + 4 * g + j) * kQRowStride + 4 * c) = code[j];
+  }
+}
+
+// Fused integer inference: features from the costs workspace, the three
+// layers on int8 MFMA, the top-KMAX keys per row, the pair masks.  Each wave
+// takes 64 consecutive pool rows (row = lane for features and selection).
+template <int KMAX>
+__global__ void __launch_bounds__(64 * kQWaves)
+k_infer_q(DevInst I, DevPool pool, const int *__restrict__ costs, float qs, float qd,
+          const uint2 *__restrict__ ops, const int *__restrict__ bias, int M1, int S1, int M2,
+          int S2, const int *__restrict__ to_inst, int k, int words,
+          uint32_t *__restrict__ mask) {
+  extern __shared__ __align__(16) unsigned char qsm[];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int count = pool.count_dev ? *pool.count_dev : pool.count;
+  const int base = (blockIdx.x * kQWaves + w) * 64;
+  if (base >= count) return;  // waves never synchronize across the block
+  unsigned char *xa = qsm + (size_t)w * kQWaveLds;
+  unsigned char *xb = xa + 64 * kQRowStride;
+  int *keys = (int *)(xb + 64 * kQRowStride);
+  const int n = I.n, m = I.m;
+  // features of row `lane`
+  const int it = base + lane;
+  const bool live = it < count;
+  const int i = live ? (pool.index ? pool.index[it] : it) : 0;
+  {
+    unsigned f[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) f[q] = 0u;
+    if (live) {
+      const int *cs = costs + (size_t)i * 3 * m;
+      const int a = pool.d1[i], b = pool.d2[i];
+      const bool bad = cs[0] < 0;  // invalid row flagged by the costs kernel
+      int lb1 = 0;
+      for (int x = 0; x < m; ++x) lb1 = max(lb1, cs[x] + cs[2 * m + x] + cs[m + x]);
+#pragma unroll
+      for (int x = 0; x < kMMax; ++x) {
+        const bool on = x < m && !bad;
+        const unsigned c1 = on ? (unsigned)q8((float)cs[on ? x : 0] * qs) : 0u;
+        const unsigned c2 = on ? (unsigned)q8((float)cs[on ? m + x : 0] * qs) : 0u;
+        const unsigned rr = on ? (unsigned)q8((float)cs[on ? 2 * m + x : 0] * qs) : 0u;
+        f[x >> 2] |= c1 << (8 * (x & 3));
+        f[(20 + x) >> 2] |= c2 << (8 * ((20 + x) & 3));
+        f[(40 + x) >> 2] |= rr << (8 * ((40 + x) & 3));
+      }
+      f[15] = (unsigned)q8((float)a * qd) | ((unsigned)q8((float)b * qd) << 8) |
+              ((unsigned)q8((float)(n - a - b) * qd) << 16) |
+              ((bad ? 0u : (unsigned)q8((float)lb1 * qs)) << 24);
+    }
+#pragma unroll
+    for (int q = 0; q < 16; q += 2)
+      *(uint2 *)(xa + lane * kQRowStride + 4 * q) = make_uint2(f[q], f[q + 1]);
+  }
+  wave_sync();
+  q_hidden(xa, xb, ops + kQOpB1, bias + kQBias1, M1, S1, lane);
+  wave_sync();
+  q_hidden(xb, xa, ops + kQOpB2, bias + kQBias2, M2, S2, lane);
+  wave_sync();
+  // output layer, 16 pairs at a time, into the running top-KMAX keys
+  const int c = lane & 15, g = lane >> 4;
+  long a3[4][2];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const unsigned char *row = xa + (16 * s + c) * kQRowStride + 8 * g;
+    a3[s][0] = *(const long *)row;
+    a3[s][1] = *(const long *)(row + 32);
+  }
+  int best[KMAX];
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) best[q] = INT_MIN;
+#pragma unroll 1
+  for (int t = 0; t < kQT3; ++t) {
+    const uint2 e0 = ops[kQOpB3 + (t * 2) * 64 + lane], e1 = ops[kQOpB3 + (t * 2 + 1) * 64 + lane];
+    const long b0 = (long)(((unsigned long)e0.y << 32) | e0.x);
+    const long b1 = (long)(((unsigned long)e1.y << 32) | e1.x);
+    const int o = 16 * t + c;
+    const bool valid = o < kOut && to_inst[o < kOut ? o : 0] >= 0;
+    const int kb = bias[kQBias3 + t * 64 + lane];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      qv4 d = {0, 0, 0, 0};
+      d = __builtin_amdgcn_mfma_i32_16x16x32_i8(a3[s][0], b0, d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_i32_16x16x32_i8(a3[s][1], b1, d, 0, 0, 0);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        keys[(16 * s + 4 * g + j) * kQKeyStride + c] =
+            valid ? (d[j] + kb) * 256 + (255 - o) : INT_MIN;
+    }
+    wave_sync();
+    int ch[16];
+#pragma unroll
+    for (int q = 0; q < 16; q += 4) {
+      const int4 v = *(const int4 *)(keys + lane * kQKeyStride + q);
+      ch[q] = v.x;
+      ch[q + 1] = v.y;
+      ch[q + 2] = v.z;
+      ch[q + 3] = v.w;
+    }
+    wave_sync();  // the next tile rewrites the keys
+    bitonic_sort_desc<16>(ch);
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) {
+      const int r = KMAX - 1 - q;
+      best[q] = max(best[q], r < 16 ? ch[r < 16 ? r : 0] : INT_MIN);
+    }
+    bitonic_merge_desc<KMAX>(best);
+  }
+  if (!live) return;
+  uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0, w5 = 0;  // 190 pairs fit 6 words
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) {
+    if (q < k && best[q] != INT_MIN) {
+      const int pi = to_inst[255 - (best[q] & 255)];
       const uint32_t bit = 1u << (pi & 31);
       const int wd = pi >> 5;
       w0 |= wd == 0 ? bit : 0u;
@@ -491,7 +741,8 @@ void selector_free(Ctx *c) {
   Selector *S = c->sel;
   if (!S) return;
   void *bufs[] = {S->master, S->wq, S->grad, S->am, S->av, S->feat, S->scores, S->mask, S->h1,
-                  S->h2, S->ds, S->dh1, S->dh2, S->rowloss, S->loss, S->to_inst};
+                  S->h2, S->ds, S->dh1, S->dh2, S->rowloss, S->loss, S->to_inst, S->qops,
+                  S->qbias};
   for (void *p : bufs) (void)hipFree(p);
   delete S;
   c->sel = nullptr;
@@ -543,7 +794,8 @@ static float instance_norm(const Ctx *c) {
 }
 
 int learned_prepare(Ctx *c, int rows) {
-  if (!c->sel || !c->sel->loaded) return set_err(c, PFSP_EINVAL, "no selector parameters set");
+  if (!c->sel || !(c->sel->loaded || c->sel->qloaded))
+    return set_err(c, PFSP_EINVAL, "no selector parameters set");
   if (c->m > kMMax) return set_err(c, PFSP_ERANGE, "the learned selector covers m <= 20");
   if (c->learned_topk > kTopKMax)
     return set_err(c, PFSP_ERANGE, "learned_topk must be <= 32 for the learned bound");
@@ -576,7 +828,19 @@ int launch_learned_ready(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8
   const DevInst I = c->inst();
   const int words = (c->P + 31) / 32;
   const int k = (int)c->learned_topk;
-  {
+  if (S->qloaded) {
+    KTimer kt(c, s, "k_infer");
+    const float norm = instance_norm(c);
+    const float qs = S->sx / norm, qd = S->sx / (float)c->n;
+    const dim3 g((pool.count + 64 * kQWaves - 1) / (64 * kQWaves)), b(64 * kQWaves);
+    const size_t lds = kQWaves * kQWaveLds;
+    if (k <= 16)
+      hipLaunchKernelGGL(k_infer_q<16>, g, b, lds, s, I, pool, c->d_costs, qs, qd, S->qops,
+                         S->qbias, S->M1, S->S1, S->M2, S->S2, S->to_inst, k, words, S->mask);
+    else
+      hipLaunchKernelGGL(k_infer_q<32>, g, b, lds, s, I, pool, c->d_costs, qs, qd, S->qops,
+                         S->qbias, S->M1, S->S1, S->M2, S->S2, S->to_inst, k, words, S->mask);
+  } else {
     KTimer kt(c, s, "k_infer");
     const dim3 g((pool.count + kInferRows - 1) / kInferRows), b(kInferRows);
     const size_t lds = (((size_t)kParams + 3) / 4 * 4 + (size_t)kHid * kInferRows) * 4;
@@ -607,11 +871,142 @@ void init_selector_attributes() {
   (void)hipGetLastError();
 }
 
+// Device form of an integer-model blob (layout above).
+static void q_pack(const int32_t *blob, std::vector<uint2> &ops, std::vector<int> &bias) {
+  ops.assign(kQOps, make_uint2(0u, 0u));
+  bias.assign(kQBiases, 0);
+  auto pack8 = [](const int32_t *w) {  // eight int8 codes, little-endian
+    uint32_t lo = 0, hi = 0;
+    for (int i = 0; i < 4; ++i) lo |= (uint32_t)(uint8_t)(int8_t)w[i] << (8 * i);
+    for (int i = 0; i < 4; ++i) hi |= (uint32_t)(uint8_t)(int8_t)w[4 + i] << (8 * i);
+    return make_uint2(lo, hi);
+  };
+  for (int L = 0; L < 2; ++L) {
+    const int32_t *W = blob + (L == 0 ? kQOffW1 : kQOffW2);
+    const int32_t *B = blob + (L == 0 ? kQOffB1 : kQOffB2);
+    for (int t = 0; t < kQT1; ++t)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int c = lane & 15, g = lane >> 4, u = 4 * c + t;
+        for (int ks = 0; ks < 2; ++ks)
+          ops[(L == 0 ? kQOpB1 : kQOpB2) + (t * 2 + ks) * 64 + lane] =
+              pack8(W + u * kIn + 32 * ks + 8 * g);
+        bias[(L == 0 ? kQBias1 : kQBias2) + t * 64 + lane] = B[u];
+      }
+  }
+  const int32_t *W3 = blob + kQOffW3, *B3 = blob + kQOffB3;
+  for (int t = 0; t < kQT3; ++t)
+    for (int lane = 0; lane < 64; ++lane) {
+      const int c = lane & 15, g = lane >> 4, o = 16 * t + c;
+      if (o >= kOut) continue;
+      for (int ks = 0; ks < 2; ++ks)
+        ops[kQOpB3 + (t * 2 + ks) * 64 + lane] = pack8(W3 + o * kHid + 32 * ks + 8 * g);
+      bias[kQBias3 + t * 64 + lane] = B3[o];
+    }
+}
+
 }  // namespace pfsp
 
 using namespace pfsp;
 
 extern "C" {
+
+int pfsp_selector_set_quant(pfsp_ctx *h, const int32_t *blob, int64_t count) {
+  if (!h) return PFSP_EINVAL;
+  Ctx *c = &h->impl;
+  PFSP_HIP(c, hipSetDevice(c->device));
+  Selector *S;
+  int rc = sel_get(c, &S);
+  if (rc) return rc;
+  if (!blob) {  // back to the float model
+    S->qloaded = 0;
+    return PFSP_OK;
+  }
+  if (count != kQParams) return set_err(c, PFSP_EINVAL, "integer selector expects 20675 values");
+  float sx;
+  memcpy(&sx, blob, 4);
+  if (!(sx > 0.f) || !isfinite(sx)) return set_err(c, PFSP_ERANGE, "feature scale must be > 0");
+  for (int L = 0; L < 2; ++L) {
+    const int M = blob[1 + 2 * L], Sh = blob[2 + 2 * L];
+    if (M < 1 || M > 1023 || Sh < 1 || Sh > 30)
+      return set_err(c, PFSP_ERANGE, "requantization needs M in [1, 1023] and S in [1, 30]");
+  }
+  for (int x = kQOffW1; x < kQParams; ++x) {
+    const bool isb = (x >= kQOffB1 && x < kQOffW2) || (x >= kQOffB2 && x < kQOffW3) ||
+                     x >= kQOffB3;
+    const int v = blob[x];
+    if (isb ? (v <= -(1 << 19) || v >= (1 << 19)) : (v < -127 || v > 127))
+      return set_err(c, PFSP_ERANGE, "weights must lie in [-127, 127] and biases in (-2^19, 2^19)");
+  }
+  std::vector<uint2> ops;
+  std::vector<int> bias;
+  q_pack(blob, ops, bias);
+  PFSP_HIP(c, hipStreamSynchronize(c->stream));
+  if (!S->qops && hipMalloc(&S->qops, kQOps * sizeof(uint2)) != hipSuccess)
+    return set_err(c, PFSP_ENOMEM, "selector allocation failed");
+  if (!S->qbias && hipMalloc(&S->qbias, kQBiases * sizeof(int)) != hipSuccess)
+    return set_err(c, PFSP_ENOMEM, "selector allocation failed");
+  PFSP_HIP(c, hipMemcpy(S->qops, ops.data(), kQOps * sizeof(uint2), hipMemcpyHostToDevice));
+  PFSP_HIP(c, hipMemcpy(S->qbias, bias.data(), kQBiases * sizeof(int), hipMemcpyHostToDevice));
+  S->sx = sx;
+  S->M1 = blob[1];
+  S->S1 = blob[2];
+  S->M2 = blob[3];
+  S->S2 = blob[4];
+  S->qloaded = 1;
+  return PFSP_OK;
+}
+
+int pfsp_selector_infer(pfsp_ctx *h, const pfsp_pool *pool, int32_t k, uint32_t *mask_out) {
+  if (!h || !pool || (pool->count > 0 && !mask_out)) return PFSP_EINVAL;
+  Ctx *c = &h->impl;
+  if (c->n == 0) return set_err(c, PFSP_ENOINST, "no instance loaded");
+  if (pool->count < 0 || pool->n != c->n) return set_err(c, PFSP_EINVAL, "bad pool");
+  if (k < 1 || k > kTopKMax) return set_err(c, PFSP_ERANGE, "k must be in [1, 32]");
+  if (c->m > kMMax || c->m < 2) return set_err(c, PFSP_ERANGE, "selection needs 2 <= m <= 20");
+  PFSP_HIP(c, hipSetDevice(c->device));
+  const int64_t saved = c->learned_topk;
+  c->learned_topk = k;
+  int rc = learned_prepare(c, pool->count);
+  c->learned_topk = saved;
+  if (rc) return rc;
+  if (pool->count == 0) return PFSP_OK;
+  DevPool dp{};
+  dp.count = pool->count;
+  dp.n = pool->n;
+  dp.perm = pool->perm;
+  dp.d1 = pool->d1;
+  dp.d2 = pool->d2;
+  rc = ensure_costs(c, pool->count);
+  if (rc) return rc;
+  rc = launch_costs(c, dp, c->stream);
+  if (rc) return rc;
+  Selector *S = c->sel;
+  const DevInst I = c->inst();
+  const int words = (c->P + 31) / 32;
+  if (S->qloaded) {
+    const float qs = S->sx / instance_norm(c), qd = S->sx / (float)c->n;
+    const dim3 g((pool->count + 64 * kQWaves - 1) / (64 * kQWaves)), b(64 * kQWaves);
+    if (k <= 16)
+      hipLaunchKernelGGL(k_infer_q<16>, g, b, kQWaves * kQWaveLds, c->stream, I, dp, c->d_costs,
+                         qs, qd, S->qops, S->qbias, S->M1, S->S1, S->M2, S->S2, S->to_inst, k,
+                         words, mask_out);
+    else
+      hipLaunchKernelGGL(k_infer_q<32>, g, b, kQWaves * kQWaveLds, c->stream, I, dp, c->d_costs,
+                         qs, qd, S->qops, S->qbias, S->M1, S->S1, S->M2, S->S2, S->to_inst, k,
+                         words, mask_out);
+  } else {
+    const dim3 g((pool->count + kInferRows - 1) / kInferRows), b(kInferRows);
+    const size_t lds = (((size_t)kParams + 3) / 4 * 4 + (size_t)kHid * kInferRows) * 4;
+    if (k <= 16)
+      hipLaunchKernelGGL(k_infer<16>, g, b, lds, c->stream, I, dp, c->d_costs, instance_norm(c),
+                         S->wq, S->to_inst, k, words, mask_out);
+    else
+      hipLaunchKernelGGL(k_infer<32>, g, b, lds, c->stream, I, dp, c->d_costs, instance_norm(c),
+                         S->wq, S->to_inst, k, words, mask_out);
+  }
+  PFSP_HIP(c, hipGetLastError());
+  return PFSP_OK;
+}
 
 int pfsp_selector_set(pfsp_ctx *h, const float *params, int64_t count) {
   if (!h || !params) return PFSP_EINVAL;
@@ -673,6 +1068,7 @@ int pfsp_selector_forward(pfsp_ctx *h, const float *x, int32_t rows, float *scor
   if (c->n == 0) return set_err(c, PFSP_ENOINST, "no instance loaded");
   int rc = learned_prepare(c, rows);
   if (rc) return rc;
+  if (!c->sel->loaded) return set_err(c, PFSP_EINVAL, "no float selector parameters set");
   if (rows == 0) return PFSP_OK;
   hipLaunchKernelGGL(k_mlp_forward, dim3((rows + 255) / 256), dim3(256), 0, c->stream,
                      c->sel->wq, x, rows, (const int *)nullptr, scores_out, c->sel->to_inst);
@@ -743,6 +1139,7 @@ int pfsp_selector_train_step(pfsp_ctx *h, const float *x, const float *target, i
   int rc = learned_prepare(c, 1);
   if (rc) return rc;
   Selector *S = c->sel;
+  if (!S->loaded) return set_err(c, PFSP_EINVAL, "no float selector parameters set");
   PFSP_HIP(c, hipSetDevice(c->device));
   if ((size_t)rows > S->train_cap) {
     PFSP_HIP(c, hipStreamSynchronize(c->stream));

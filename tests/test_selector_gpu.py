@@ -162,3 +162,105 @@ def test_learned_bound_equals_subset_bound(ctx, topk):
     full, _, _ = oracle.bound_children(p, perm, d1, d2, oracle.LB2_FULL, 1900, threads=8)
     assert (olb <= full).all()
     ctx.set_option("learned_topk", 16)
+
+
+# ---------------------------------------------------------------- integer model
+def _qblob(seed, ties=False):
+    """A random integer-model blob (layout of pfsp_selector_set_quant); with
+    ties, the output layer gives many pairs the same score."""
+    rng = np.random.default_rng(seed)
+    W3 = rng.integers(-127, 128, (190, 64))
+    b3 = rng.integers(-5000, 5000, 190)
+    if ties:
+        W3[:, 8:] = 0
+        W3[:, :8] = rng.integers(-1, 2, (1, 8))     # one row for every pair
+        b3 = rng.integers(0, 3, 190) * 1000
+    head = [int(np.array([20.0 + seed], dtype=np.float32).view(np.int32)[0]),
+            int(rng.integers(300, 1024)), int(rng.integers(10, 16)),
+            int(rng.integers(300, 1024)), int(rng.integers(10, 16))]
+    parts = [rng.integers(-127, 128, (64, 64)), rng.integers(-5000, 5000, 64),
+             rng.integers(-127, 128, (64, 64)), rng.integers(-5000, 5000, 64), W3, b3]
+    return np.concatenate([np.array(head)] + [a.reshape(-1) for a in parts]).astype(np.int32)
+
+
+def _words(layout_mask, m):
+    """bool [B, 190] over layout pairs -> uint32 words over instance pair indices."""
+    P = m * (m - 1) // 2
+    out = np.zeros((layout_mask.shape[0], (P + 31) // 32), dtype=np.uint32)
+    for u in range(m):
+        for v in range(u + 1, m):
+            pi = u * (2 * m - u - 1) // 2 + (v - u - 1)
+            out[:, pi >> 5] |= layout_mask[:, S.pair20(u, v)].astype(np.uint32) << (pi & 31)
+    return out
+
+
+def _quant_pool(n, seed):
+    parts = [inputs.random_pool(n, 250, seed), inputs.random_pool(n, 6, seed + 1, depth=0),
+             inputs.random_pool(n, 9, seed + 2, depth=n - 1)]
+    return tuple(np.concatenate([q[i] for q in parts]) for i in range(3))
+
+
+@pytest.mark.parametrize("m", [20, 13, 2])
+@pytest.mark.parametrize("k", [1, 16, 17, 32])
+@pytest.mark.parametrize("ties", [False, True])
+def test_integer_selector_masks(ctx, m, k, ties):
+    """The fused int8-MFMA inference selects exactly the oracle's pairs: random
+    blobs (with and without tied scores), every k, fewer pairs than k (m = 2),
+    pools of 265 rows (a partial last wave), root and leaf-parent rows."""
+    n = 20
+    p = inputs.instance(n, m, 400 + m)
+    perm, d1, d2 = _quant_pool(n, 410 + m)
+    ctx.load_instance(p)
+    blob = _qblob(420 + m + k, ties)
+    ctx.selector_set_quant(blob)
+    try:
+        got = ctx.selector_infer(*[_t(ctx, a) for a in (perm, d1, d2)], k)
+        got = got.cpu().numpy().view(np.uint32)
+        exp = _words(S.quant_masks(blob, p, perm, d1, d2, k), m)
+        np.testing.assert_array_equal(got, exp)
+    finally:
+        ctx.selector_set_quant(None)
+
+
+@pytest.mark.parametrize("k", [16, 32])
+def test_learned_bound_integer_model(ctx, k):
+    """LB2_LEARNED with the quantized trained selector (calibrated by the
+    library's own quantizer) equals subset LB2 over the oracle's pairs."""
+    import torch
+    from paper_2012_09511_amd import selector_quant
+    n, m = 20, 20
+    p = inputs.instance(n, m, 430)
+    perm, d1, d2 = _quant_pool(n, 431)
+    ctx.load_instance(p)
+    import os
+    flat = np.load(os.path.join(os.path.dirname(inputs.__file__), "data", "selector_n20m20.npy"),
+                   allow_pickle=False)
+    ctx.selector_set(flat)
+    blob = selector_quant.quantize(flat, selector_quant.calibration_features(ctx, n, 2048))
+    ctx.selector_set_quant(blob)
+    ctx.set_option("learned_topk", k)
+    try:
+        dev = [_t(ctx, a) for a in (perm, d1, d2)]
+        lb, pr, dr, _ = ctx.bound_children(*dev, kind=binding.LB2_LEARNED, ub=1900)
+        torch.cuda.synchronize()
+        mask = _words(S.quant_masks(blob, p, perm, d1, d2, k), m)
+        olb, opr, odr = oracle.bound_children(p, perm, d1, d2, oracle.LB2_SUBSET, 1900,
+                                              pair_mask=mask, threads=8)
+        np.testing.assert_array_equal(lb.cpu().numpy(), olb)
+        np.testing.assert_array_equal(pr.cpu().numpy(), opr)
+        np.testing.assert_array_equal(dr.cpu().numpy(), odr)
+    finally:
+        ctx.set_option("learned_topk", 16)
+        ctx.selector_set_quant(None)
+
+
+def test_integer_selector_rejects_bad_blobs(ctx):
+    ctx.load_instance(inputs.instance(10, 5, 3))
+    good = _qblob(3)
+    for idx, val in ((1, 0), (1, 1024), (2, 0), (2, 31), (10, 128), (5 + 4096, 1 << 19)):
+        bad = good.copy()
+        bad[idx] = val
+        with pytest.raises(binding.PfspError):
+            ctx.selector_set_quant(bad)
+    with pytest.raises(binding.PfspError):
+        ctx.selector_set_quant(good[:-1])

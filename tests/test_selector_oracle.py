@@ -118,3 +118,116 @@ def test_root_features_closed_form():
     T = p.sum(axis=0)
     np.testing.assert_allclose(f[40:48], T / T.max())
     assert f[63] == 1.0 and f[62] == 1.0 and f[60] == 0 and f[:8].sum() == 0
+
+
+# ---------------------------------------------------------------- integer model
+def _blob(sx, M1, S1, M2, S2, W1, b1, W2, b2, W3, b3):
+    head = [int(np.array([sx], dtype=np.float32).view(np.int32)[0]), M1, S1, M2, S2]
+    parts = [np.asarray(a, dtype=np.int64).reshape(-1) for a in (W1, b1, W2, b2, W3, b3)]
+    blob = np.concatenate([np.array(head, dtype=np.int64)] + parts)
+    assert blob.size == S.Q_LEN
+    return blob
+
+
+def _random_blob(seed, wmax=127, bmax=5000):
+    rng = np.random.default_rng(seed)
+    return _blob(np.float32(20 + seed), int(rng.integers(300, 1024)), int(rng.integers(10, 16)),
+                 int(rng.integers(300, 1024)), int(rng.integers(10, 16)),
+                 rng.integers(-wmax, wmax + 1, (64, 64)), rng.integers(-bmax, bmax, 64),
+                 rng.integers(-wmax, wmax + 1, (64, 64)), rng.integers(-bmax, bmax, 64),
+                 rng.integers(-wmax, wmax + 1, (190, 64)), rng.integers(-bmax, bmax, 190))
+
+
+def test_quant_codes_by_hand():
+    # float32 product, ties to even, saturation at both ends
+    assert S.quant_code(3, 0.5) == 2 and S.quant_code(5, 0.5) == 2 and S.quant_code(7, 0.5) == 4
+    assert S.quant_code(1000, 1.0) == 127 and S.quant_code(0, 3.0) == 0
+    assert S.quant_code(1, 0.49) == 0 and S.quant_code(1, 0.51) == 1
+    # 4 x 3 instance of unit times at its root: C1 = C2 = 0, R = (4, 4, 4),
+    # LB1 = 4, norm = 4; sx = 31.75 gives q = 7.9375 per unit of work or job
+    p = np.ones((4, 3), dtype=np.int32)
+    perm = np.array([[0, 1, 2, 3], [2, 0, 1, 3]], dtype=np.uint8)
+    d1 = np.array([0, 1], dtype=np.uint8)
+    d2 = np.array([0, 1], dtype=np.uint8)
+    x = S.quant_features(p, perm, d1, d2, np.float32(31.75))
+    root = np.zeros(64, dtype=np.int64)
+    root[40:43] = 32                      # rint(4 * 7.9375) = rint(31.75)
+    root[62] = 32                         # four unscheduled jobs
+    root[63] = 32                         # LB1 = 4
+    np.testing.assert_array_equal(x[0], root)
+    # second node: job 2 in front, job 3 at the back: C1 = (1, 2, 3),
+    # C2 = (3, 2, 1), R = (2, 2, 2), LB1 = max(1+2+3, 2+2+2, 3+2+1) = 6
+    row = np.zeros(64, dtype=np.int64)
+    row[0:3] = [8, 16, 24]                # rint(7.9375 k): 7.94, 15.88, 23.81
+    row[20:23] = [24, 16, 8]
+    row[40:43] = 16                       # rint(15.875)
+    row[60] = row[61] = 8                 # one job each side
+    row[62] = 16
+    row[63] = 48                          # rint(47.625)
+    np.testing.assert_array_equal(x[1], row)
+
+
+def test_quant_layers_by_hand():
+    # identity first layer with M / 2^S = 1/2 (half up), a second layer summing
+    # units 0 and 1 into unit 0, an output layer reading unit 0 with weight 3
+    W1 = np.eye(64, dtype=np.int64)
+    W2 = np.zeros((64, 64), dtype=np.int64)
+    W2[0, 0] = W2[0, 1] = 1
+    W3 = np.zeros((190, 64), dtype=np.int64)
+    W3[:, 0] = 3
+    b3 = np.arange(190)
+    blob = _blob(1.0, 1, 1, 1, 0 + 1, W1, np.zeros(64), W2, np.zeros(64), W3, b3)
+    x = np.zeros((3, 64), dtype=np.int64)
+    x[0, :2] = [3, 4]      # h1 = (2, 2)  -> h2[0] = (4 + 1) >> 1 = 2
+    x[1, :2] = [5, 127]    # h1 = (3, 64) -> h2[0] = (67 + 1) >> 1 = 34
+    x[2, :2] = [1, 0]      # h1 = (1, 0)  -> h2[0] = 1
+    s = S.quant_forward(blob, x)
+    np.testing.assert_array_equal(s, np.array([6, 102, 3])[:, None] + b3[None, :])
+    # negative pre-activations are cut by the ReLU, large ones saturate at 127
+    W1b = -np.eye(64, dtype=np.int64)
+    blob2 = _blob(1.0, 1, 1, 1023, 1, W1b, np.zeros(64), W2, np.zeros(64), W3, b3)
+    np.testing.assert_array_equal(S.quant_forward(blob2, x)[:, 0], [0, 0, 0])
+    # M1 = 1023: every positive unit saturates at 127; row 2 keeps h1 = (127, 0),
+    # so h2[0] = (127 + 1) >> 1 = 64
+    blob3 = _blob(1.0, 1023, 1, 1, 1, W1, np.zeros(64), W2, np.zeros(64), W3, b3)
+    np.testing.assert_array_equal(S.quant_forward(blob3, x)[:, 0], [3 * 127, 3 * 127, 3 * 64])
+
+
+def test_quant_forward_brute_force():
+    """Each score against scalar loops over the blob's own order."""
+    blob = _random_blob(4)
+    sx, M1, S1, M2, S2, W1, b1, W2, b2, W3, b3 = S.quant_unpack(blob)
+    rng = np.random.default_rng(5)
+    x = rng.integers(0, 128, (3, 64))
+    s = S.quant_forward(blob, x)
+    for r in range(3):
+        h1 = []
+        for o in range(64):
+            a = int(b1[o]) + sum(int(W1[o, j]) * int(x[r, j]) for j in range(64))
+            h1.append(min(127, (max(a, 0) * M1 + 2 ** (S1 - 1)) // 2 ** S1))
+        h2 = []
+        for o in range(64):
+            a = int(b2[o]) + sum(int(W2[o, j]) * h1[j] for j in range(64))
+            h2.append(min(127, (max(a, 0) * M2 + 2 ** (S2 - 1)) // 2 ** S2))
+        for o in range(0, 190, 17):
+            assert s[r, o] == int(b3[o]) + sum(int(W3[o, j]) * h2[j] for j in range(64))
+
+
+def test_quant_invariances():
+    """Permuting hidden units (rows of W1 and b1 with the columns of W2) leaves
+    every score unchanged; doubling W3 and b3 leaves the selection unchanged."""
+    blob = _random_blob(6)
+    sx, M1, S1, M2, S2, W1, b1, W2, b2, W3, b3 = S.quant_unpack(blob)
+    perm = np.random.default_rng(7).permutation(64)
+    blobp = _blob(sx, M1, S1, M2, S2, W1[perm], b1[perm], W2[:, perm], b2, W3, b3)
+    x = np.random.default_rng(8).integers(0, 128, (5, 64))
+    np.testing.assert_array_equal(S.quant_forward(blob, x), S.quant_forward(blobp, x))
+    blob2 = _blob(sx, M1, S1, M2, S2, W1, b1, W2, b2, 2 * W3, 2 * b3)
+    valid = S.valid_pairs(15)
+    for k in (1, 9, 32):
+        np.testing.assert_array_equal(S.topk_mask(S.quant_forward(blob, x), valid, k),
+                                      S.topk_mask(S.quant_forward(blob2, x), valid, k))
+    # equal scores: the lower layout index is kept
+    s = np.zeros((1, 190), dtype=np.int64)
+    m = S.topk_mask(s, S.valid_pairs(20), 3)
+    assert list(np.nonzero(m[0])[0]) == [0, 1, 2]

@@ -13,11 +13,14 @@ Prints one JSON line.  Other workloads (not the headline): `search` = the
 device depth-first B&B on n=20 x m=10 instances (seeds 1..8, NEH incumbent)
 to proven optimality; `multi` = 64 instances of mixed (n, m) bounded in one
 persistent graph launch, autotuned shape vs default; `learned` = full LB2
-vs learned-pair LB2 searches to the same proven optimum.  The dominant kernel's roofline entry divides the
+vs learned-pair LB2 searches to the same proven optimum (by default the
+20 x 20-trained selector in its int8 form, top-32 pairs; --float-selector,
+--topk and --selector select the other variants).  The dominant kernel's
+roofline entry divides the
 kernel's algorithmic integer operations (formula in alg_ops_lb2) by its mean
 duration measured with HIP events on the library stream over the timed
 steps.  The CPU baseline is the plain oracle on a bounded sample of the same
-pool, on all host cores available to this process.
+pool, on the host cores available to this process (at most 16).
 """
 from __future__ import annotations
 
@@ -83,11 +86,16 @@ def cpu_baseline(p, perm, d1, d2, kind, target_s=12.0):
     import oracle
     threads = len(os.sched_getaffinity(0))
     threads = max(1, min(threads, 16))
-    # calibrate on a small sample, then run ~target_s of work
+    # calibrate on samples growing until one takes 0.5 s (thread start-up
+    # dominates tiny ones), then run ~target_s of work
     k = 64
-    t = time.perf_counter()
-    oracle.bound_children(p, perm[:k], d1[:k], d2[:k], kind, threads=threads)
-    dt = max(time.perf_counter() - t, 1e-3)
+    while True:
+        t = time.perf_counter()
+        oracle.bound_children(p, perm[:k], d1[:k], d2[:k], kind, threads=threads)
+        dt = max(time.perf_counter() - t, 1e-3)
+        if dt >= 0.5 or k >= len(perm):
+            break
+        k = min(len(perm), k * 4)
     k2 = int(min(len(perm), max(k, k * target_s / dt)))
     t = time.perf_counter()
     oracle.bound_children(p, perm[:k2], d1[:k2], d2[:k2], kind, threads=threads)
@@ -111,8 +119,10 @@ def main():
                     help="also run one 256 MiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--workload", default="bound", choices=["bound", "search", "multi", "learned"])
     ap.add_argument("--selector", default=os.path.join(ROOT, "paper_2012_09511_amd", "data",
-                                                       "selector_n50m20.npy"))
-    ap.add_argument("--topk", type=int, default=16, help="pairs kept by the learned selector")
+                                                       "selector_n20m20.npy"),
+                    help="learned workload: trained weights (selector_n50m20.npy: the 50 x 20 "
+                         "training set)")
+    ap.add_argument("--topk", type=int, default=32, help="pairs kept by the learned selector")
     ap.add_argument("--float-selector", action="store_true",
                     help="learned workload: rank pairs with the float model instead of its "
                          "int8 form")
@@ -362,7 +372,8 @@ def bench_learned(args):
                dtype="int32", data="synthetic",
                config=dict(workload="depth-first B&B, n=20 x m=20, seeds 600..607, NEH+1, "
                                     f"learned top-{args.topk} of 190 pairs, "
-                                    + ("float" if args.float_selector else "int8") + " selector"),
+                                    + ("float" if args.float_selector else "int8") + " selector "
+                                    + os.path.basename(args.selector)),
                full_seconds=tf, learned_seconds=tl, instances=rows)
     ctx.close()
     print(json.dumps(out))

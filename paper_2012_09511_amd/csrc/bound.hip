@@ -1304,9 +1304,10 @@ __device__ void lb2q_parent(const DevInst &I, int Ppad, const QuickLds<NMAX> &S,
   wave_sync();  // the next parent rewrites this wave's tables
 }
 
-// Up to 12 waves per block: three per SIMD, which the register use allows.
+// Up to 12 waves per block (three per SIMD, which the register use of up to
+// 24 jobs allows); 8 for 32 jobs, whose registers need two per SIMD.
 template <int NMAX, bool SUBSET, bool X16>
-__global__ void __launch_bounds__(768)
+__global__ void __launch_bounds__(NMAX <= 24 ? 768 : 512)
 k_lb2q(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__restrict__ out_lb,
        uint8_t *__restrict__ out_prune, int Ppad) {
   extern __shared__ __align__(16) unsigned char sm[];
@@ -1344,25 +1345,32 @@ k_lb2q(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
 // halves (forward low, backward high): every pair term of a child is a
 // lower bound of one of its completions, hence at most (n + m - 1) max p,
 // below 2^15 when 16-bit X applies.
+// Tables are sized by the largest n and m they serve (nj, mmax), so that a
+// 100-job, 20-machine class fits four waves per CU.
 struct WideLayout {
   int ppad, nj, mmax;  // padded pairs, rows of X (largest n), machines
-  __host__ __device__ static constexpr int row(int nmax) { return nmax | 1; }
+  // start-time rows: odd, and long enough for reads up to job n + 2
+  __host__ __device__ int row() const { return (nj + 3) | 1; }
   // scan chunk length: the 128-job variant keeps fewer positions in registers
   __host__ __device__ static constexpr int chunk_len(int nmax) { return nmax >= 128 ? 8 : 16; }
-  __host__ __device__ static constexpr int chunks(int nmax) { return nmax / chunk_len(nmax); }
+  __host__ __device__ int chunks(int nmax) const {
+    return (nj + chunk_len(nmax) - 1) / chunk_len(nmax);
+  }
   __host__ __device__ size_t block_bytes(int nmax) const {
-    return align16((size_t)ppad * 4) + align16((size_t)mmax * nmax * 4);
+    return align16((size_t)ppad * 4) + align16((size_t)mmax * nmax * 2);
   }
   __host__ __device__ size_t wave_bytes(int nmax) const {
-    return align16((size_t)(nj + 3) * 64 * 4) + align16((size_t)mmax * row(nmax) * 4) +
+    return align16((size_t)(nj + 3) * 64 * 4) + align16((size_t)mmax * row() * 4) +
            align16((size_t)chunks(nmax) * 64 * 4) + align16((size_t)2 * mmax * 8) +
-           align16((size_t)3 * mmax * 4) + (size_t)nmax * 4;
+           align16((size_t)3 * mmax * 4) + align16((size_t)nj * 4);
   }
 };
 
 template <int NMAX>
 struct WideLds {
-  int *uv, *pt;    // block: pair -> u | v << 8; p by [machine][job]
+  int *uv;         // block: pair -> u | v << 8
+  unsigned short *pt;  // block: p by [machine][job] (below 2^15 with 16-bit X)
+  int ROW;         // row length of FB
   int *X;          // [nj + 3][64]: xa | xb << 16 by job (row n: padding sink; rows
                    // n + 1, n + 2: read, never used, by the last group of four jobs)
   int *FB;         // [m][ROW]: f (forward, low half) | g (backward, high half) by machine
@@ -1370,18 +1378,18 @@ struct WideLds {
   int2 *HTf, *HTb;
   int *c1, *c2, *rr, *inv;
   __device__ WideLds(unsigned char *sm, const WideLayout &L, int w) {
-    constexpr int ROW = WideLayout::row(NMAX);
+    ROW = L.row();
     uv = (int *)sm;
     size_t off = align16((size_t)L.ppad * 4);
-    pt = (int *)(sm + off);
-    off += align16((size_t)L.mmax * NMAX * 4);
+    pt = (unsigned short *)(sm + off);
+    off += align16((size_t)L.mmax * NMAX * 2);
     unsigned char *wb = sm + off + (size_t)w * L.wave_bytes(NMAX);
     X = (int *)wb;
     wb += align16((size_t)(L.nj + 3) * 64 * 4);
     FB = (int *)wb;
     wb += align16((size_t)L.mmax * ROW * 4);
     ST = (int *)wb;
-    wb += align16((size_t)WideLayout::chunks(NMAX) * 64 * 4);
+    wb += align16((size_t)L.chunks(NMAX) * 64 * 4);
     HTf = (int2 *)wb;
     HTb = HTf + L.mmax;
     wb += align16((size_t)2 * L.mmax * 8);
@@ -1404,7 +1412,7 @@ __device__ void lb2w_stage(const DevInst &I, int Ppad, const WideLds<NMAX> &S) {
   }
   for (int x = threadIdx.x; x < m * NMAX; x += blockDim.x) {
     const int s = x / NMAX, k = x - s * NMAX;
-    S.pt[x] = k < n ? I.p[k * m + s] : 0;
+    S.pt[x] = (unsigned short)(k < n ? I.p[k * m + s] : 0);
   }
 }
 
@@ -1464,7 +1472,7 @@ __device__ void lb2w_parent(const DevInst &I, int Ppad, const WideLds<NMAX> &S,
                             const int *__restrict__ cs, int stride, int ub,
                             int *__restrict__ lbrow, uint8_t *__restrict__ prow,
                             uint8_t *__restrict__ dirp, int lane) {
-  constexpr int ROW = WideLayout::row(NMAX);
+  const int ROW = S.ROW;
   constexpr int CH = WideLayout::chunk_len(NMAX);
   constexpr int NC = NMAX / 32;  // 32-job chunks of the lane-per-job steps
   constexpr int NW = NMAX / 64;  // 64-bit membership words
@@ -1507,7 +1515,7 @@ __device__ void lb2w_parent(const DevInst &I, int Ppad, const WideLds<NMAX> &S,
     const int2 *HT = bwd ? S.HTb : S.HTf;
     unsigned short *fb = (unsigned short *)S.FB + 2 * k + (bwd ? 1 + 2 * (m - 1) * ROW : 0);
     const int fstep = bwd ? -2 * ROW : 2 * ROW;
-    const int *PT = S.pt + k + (bwd ? (m - 1) * NMAX : 0);
+    const unsigned short *PT = S.pt + k + (bwd ? (m - 1) * NMAX : 0);
     const int pstep = bwd ? -NMAX : NMAX;
     int cc = 0, l = 0;
 #pragma unroll 4
@@ -2699,7 +2707,7 @@ int launch_bound_costs_ready(Ctx *c, const DevPool &pool, int kind, int ub, int 
   if (nmax) {
     // waves per block: the most resident waves per CU within 160 KiB of LDS
     int waves = 0, best = 0;
-    const int wmax = nmax <= 32 && !log ? 12 : 8;
+    const int wmax = nmax <= 24 && !log ? 12 : 8;  // the kernels' launch bounds
     for (int w = wmax; w >= 1; --w) {
       const size_t l = lb2f_lds(c, nmax, w, log);
       const int per_cu = l <= 160 * 1024 ? (int)((160 * 1024) / l) * w : 0;

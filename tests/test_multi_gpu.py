@@ -125,3 +125,44 @@ def test_wide_classes(ctx):
     lb, pr, dr = mt.bound(*dev, seg, ub, binding.LB2_FULL)
     _check(insts, perm, d1, d2, seg, ub, lb, pr, dr, binding.LB2_FULL)
     mt.close()
+
+
+def test_full_size_batch_sampled(ctx):
+    """The multi-instance benchmark batch at full size (64 instances, 16,384
+    parents each, incumbent open) in the default and an autotuned launch
+    shape; 4 sampled rows per instance against the oracle, and at every row
+    exactly 2(n - d) finite children."""
+    import torch
+    insts = inputs.mixed_instances(64, 4000)
+    stride = max(n for n, _, _ in insts)
+    per = 16384
+    perm, d1, d2, seg = [], [], [], [0]
+    for k, (n, m, p) in enumerate(insts):
+        pk, a, b = inputs.random_pool(n, per, 5000 + k)
+        pad = np.zeros((per, stride), dtype=np.uint8)
+        pad[:, :n] = pk
+        perm.append(pad)
+        d1.append(a)
+        d2.append(b)
+        seg.append(seg[-1] + per)
+    perm, d1, d2, seg = np.concatenate(perm), np.concatenate(d1), np.concatenate(d2), np.array(seg)
+    ub = np.full(64, binding.INT32_MAX, dtype=np.int32)
+    mt = binding.Multi(ctx, [p for _, _, p in insts])
+    dev = _dev(ctx, perm, d1, d2)
+    rng = np.random.default_rng(64)
+    for shape in (None, dict(tile=64, waves_small=12, waves_large=0, blocks_per_cu=2)):
+        if shape:
+            mt.set_shape(**shape)
+        lb, pr, dr = mt.bound(*dev, seg, ub, binding.LB2_FULL)
+        torch.cuda.synchronize()
+        lb, pr, dr = lb.cpu().numpy(), pr.cpu().numpy(), dr.cpu().numpy()
+        for k, (n, m, p) in enumerate(insts):
+            rows = seg[k] + np.sort(rng.choice(per, 4, replace=False))
+            olb, opr, odr = oracle.bound_children(p, perm[rows, :n], d1[rows], d2[rows],
+                                                  binding.LB2_FULL, binding.INT32_MAX, threads=8)
+            np.testing.assert_array_equal(lb[rows, :, :n], olb)
+            np.testing.assert_array_equal(pr[rows, :, :n], opr)
+            np.testing.assert_array_equal(dr[rows], odr)
+        r = np.repeat(np.array([n for n, _, _ in insts]), per) - d1.astype(np.int64) - d2
+        np.testing.assert_array_equal((lb < binding.INT32_MAX).sum(axis=(1, 2)), 2 * r)
+    mt.close()

@@ -154,7 +154,8 @@ int pfsp_neh(pfsp_ctx *c, int32_t *perm_out, int32_t *cmax_out);
  * 65536), "poll_every" (search steps between host polls, default 8),
  * "pool_capacity" (max stacked nodes, default derived from n and pool_batch),
  * "use_graph" (1 = replay the search step as a HIP graph, default 1),
- * "learned_topk" (pairs kept by the selector, default 16),
+ * "learned_topk" (pairs kept by the selector, default 16; at most 32 with
+ * the float selector, 64 with the integer one),
  * "learned_exact" (1 = re-bound subset survivors with all pairs, default 0),
  * "timing" (1 = bracket every kernel launch with HIP events on the ctx
  * stream, default 0), "lb2_waves" (waves per block of the LB2 kernel, 0..12, 0 =
@@ -285,7 +286,8 @@ int pfsp_selector_select(pfsp_ctx *c, const float *scores, int32_t rows, int32_t
 int pfsp_selector_set_quant(pfsp_ctx *c, const int32_t *blob, int64_t count);
 
 /* Pair masks that PFSP_LB2_LEARNED would bound for every parent of the pool
- * (the integer model if set, else the float model), k in [1, 32]: DEVICE
+ * (the integer model if set, k in [1, 64], else the float model, k in
+ * [1, 32]): DEVICE
  * mask_out[N][ceil(P/32)] over the instance's pair indices. */
 int pfsp_selector_infer(pfsp_ctx *c, const pfsp_pool *pool, int32_t k, uint32_t *mask_out);
 

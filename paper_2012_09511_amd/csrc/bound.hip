@@ -1005,7 +1005,8 @@ struct QuickLayout {
   }
   __host__ __device__ size_t wave_bytes(int nmax) const {
     return align16((size_t)nmax * 64 * (x16 ? 4 : 8)) + align16((size_t)2 * mmax * row(nmax) * 4) +
-           align16((size_t)2 * mmax * 8) + align16((size_t)3 * mmax * 4) + 32 * 4;
+           align16((size_t)2 * mmax * 8) + align16((size_t)3 * mmax * 4) + align16(32 * 4) +
+           align16((size_t)ppad * 2);
   }
 };
 
@@ -1017,6 +1018,7 @@ struct QuickLds {
   int *FBf, *FBb;
   int2 *HTf, *HTb;
   int *c1, *c2, *rr, *inv;
+  short *sel;  // subset bounds: the selected pair indices in order
   __device__ QuickLds(unsigned char *sm, const QuickLayout &L, int w) {
     constexpr int ROW = QuickLayout::row(NMAX);
     ent = (uint2 *)sm;
@@ -1040,6 +1042,8 @@ struct QuickLds {
     rr = c2 + L.mmax;
     wb += align16((size_t)3 * L.mmax * 4);
     inv = (int *)wb;
+    wb += align16(32 * 4);
+    sel = (short *)wb;
   }
 };
 
@@ -1074,21 +1078,45 @@ __device__ void lb2q_stage(const DevInst &I, int Ppad, const Lds &S) {
   }
 }
 
-// Index of the sidx-th set bit among the first P bits of a pair mask (the
-// caller guarantees that it exists).
-__device__ __forceinline__ int nth_pair(const uint32_t *__restrict__ mw, int P, int sidx) {
-  const int words = (P + 31) >> 5;
-  for (int w = 0; w < words; ++w) {
-    uint32_t wbits = mw[w];
-    if (w == words - 1 && (P & 31)) wbits &= (1u << (P & 31)) - 1u;
-    const int cnt = __popc(wbits);
-    if (sidx < cnt) {
-      for (int t = 0; t < sidx; ++t) wbits &= wbits - 1u;
-      return w * 32 + __ffs(wbits) - 1;
-    }
-    sidx -= cnt;
+// Global inputs of one parent as the lanes hold them: row byte `lane` (lane
+// < n), costs C1, C2, R of machine `lane` (lane < m), mask word `lane`
+// (lane < words), and d1, d2 (c1 = -1 on every lane: no parent).  The
+// kernels load them one parent (or batch) ahead so that their latency
+// overlaps the previous one's work.
+struct PackFetch {
+  int rb, c1, c2, rr, d1, d2;
+  uint32_t mw;
+};
+
+__device__ __forceinline__ PackFetch row_fetch(const uint8_t *__restrict__ row,
+                                               const int *__restrict__ cs, int d1, int d2, int n,
+                                               int m, int lane) {
+  PackFetch F{0, -1, 0, 0, d1, d2, 0u};
+  if (lane < n) F.rb = row[lane];
+  if (lane < m) {
+    F.c1 = cs[lane];
+    F.c2 = cs[m + lane];
+    F.rr = cs[2 * m + lane];
   }
-  return 0;
+  return F;
+}
+
+__device__ __forceinline__ PackFetch pack_fetch(const DevPool &pool, int par, int n, int m,
+                                                const int *__restrict__ costs, int lane) {
+  PackFetch F{0, -1, 0, 0, 0, 0, 0u};
+  if (par >= 0) {
+    const int *cs = costs + (size_t)par * 3 * m;
+    F.d1 = pool.d1[par];
+    F.d2 = pool.d2[par];
+    if (lane < n) F.rb = pool.perm[(size_t)par * pool.n + lane];
+    if (lane < m) {
+      F.c1 = cs[lane];
+      F.c2 = cs[m + lane];
+      F.rr = cs[2 * m + lane];
+    }
+    if (lane < pool.mask_words) F.mw = pool.mask[(size_t)par * pool.mask_words + lane];
+  }
+  return F;
 }
 
 // X16: the scan starts from Y = R_v + C2_v instead of 0.  For a member j
@@ -1101,27 +1129,25 @@ __device__ __forceinline__ int nth_pair(const uint32_t *__restrict__ mw, int P, 
 // reaches a bound.
 template <int NMAX, bool SUBSET, bool X16>
 __device__ void lb2q_parent(const DevInst &I, int Ppad, const QuickLds<NMAX> &S,
-                            const uint8_t *__restrict__ row, int a, int b,
-                            const int *__restrict__ cs, const uint32_t *__restrict__ mw,
-                            int stride, int ub, int *__restrict__ lbrow,
+                            const PackFetch &F, int stride, int ub, int *__restrict__ lbrow,
                             uint8_t *__restrict__ prow, uint8_t *__restrict__ dirp, int lane) {
   constexpr int ROW = QuickLayout::row(NMAX);
   const int n = I.n, m = I.m, P = I.P;
+  const int a = __builtin_amdgcn_readfirstlane(F.d1), b = __builtin_amdgcn_readfirstlane(F.d2);
   const int r = n - a - b;
-  if (r < 1 || cs[0] < 0) {  // flagged by k_lb1: not a valid node
+  if (r < 1 || __builtin_amdgcn_readfirstlane(F.c1) < 0) {  // flagged by the costs kernel
     fill_invalid(lbrow, prow, nullptr, stride, 0, lane, 64);
     if (dirp && lane == 0) *dirp = 0;
     return;
   }
   // inverse permutation, parent costs, per-direction head/tail tables
-  if (lane < n) S.inv[row[lane]] = lane;
-  for (int x = lane; x < m; x += 64) {
-    const int C1 = cs[x], C2 = cs[m + x], R = cs[2 * m + x];
-    S.c1[x] = C1;
-    S.c2[x] = C2;
-    S.rr[x] = R;
-    S.HTf[x] = make_int2(C1, R + C2);
-    S.HTb[m - 1 - x] = make_int2(C2, C1 + R);
+  if (lane < n) S.inv[F.rb] = lane;
+  if (lane < m) {
+    S.c1[lane] = F.c1;
+    S.c2[lane] = F.c2;
+    S.rr[lane] = F.rr;
+    S.HTf[lane] = make_int2(F.c1, F.rr + F.c2);
+    S.HTb[m - 1 - lane] = make_int2(F.c2, F.c1 + F.rr);
   }
   wave_sync();
   const int k = lane & 31;  // job of this lane; lanes >= 32 take its backward child
@@ -1157,13 +1183,18 @@ __device__ void lb2q_parent(const DevInst &I, int Ppad, const QuickLds<NMAX> &S,
   }
   wave_sync();
   int nsel = 0;
-  if constexpr (SUBSET) {
-    const int words = (P + 31) >> 5;
-    for (int w = lane; w < words; w += 64)
-      nsel += __popc(mw[w] & (w == words - 1 && (P & 31) ? (1u << (P & 31)) - 1u : 0xffffffffu));
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) nsel += __shfl_xor(nsel, o, kWave);
-    nsel = __builtin_amdgcn_readfirstlane(nsel);
+  if constexpr (SUBSET) {  // selected pairs in index order, compacted by ballot
+    for (int base = 0; base < P; base += 64) {
+      const int q = base + lane;
+      const uint32_t wq = (uint32_t)__shfl((int)F.mw, (q >> 5) & 63, kWave);
+      const bool on = q < P && ((wq >> (q & 31)) & 1u);
+      const uint64_t bal = __ballot(on);
+      const int pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
+      if (on) S.sel[nsel + pos] = (short)q;
+      nsel += __popcll(bal);
+    }
+    wave_sync();
   }
   // pair maxima per job: X16 keeps both directions in one register as int16
   // halves (every pair term of a child is at most (n + m - 1) max p < 2^15)
@@ -1180,7 +1211,7 @@ __device__ void lb2q_parent(const DevInst &I, int Ppad, const QuickLds<NMAX> &S,
   for (int pc = 0; pc < npass; pc += 64) {
     int pi = pc + lane;
     // subset bounds: lanes past the selection repeat the first selected pair
-    if constexpr (SUBSET) pi = nth_pair(mw, P, pi < nsel ? pi : 0);
+    if constexpr (SUBSET) pi = S.sel[pi < nsel ? pi : 0];
     const int uvp = S.uv[pi];
     const int u = uvp & 0xff, v = uvp >> 8;
     const int K4 = S.rr[v] + S.c2[v], K5 = S.c1[u] + S.rr[v];
@@ -1319,16 +1350,20 @@ k_lb2q(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
   lb2q_stage<NMAX, X16>(I, Ppad, S);
   __syncthreads();
   if (pool.ub_dev) ub = *pool.ub_dev;
-  const int m = I.m;
-  for (int it = blockIdx.x * nw + w; it < count; it += gridDim.x * nw) {
-    const int par = pool.index ? pool.index[it] : it;
-    const int ns = pool.n;  // row stride (>= n)
-    lb2q_parent<NMAX, SUBSET, X16>(
-        I, Ppad, S, pool.perm + (size_t)par * ns, pool.d1[par], pool.d2[par],
-        costs + (size_t)par * 3 * m,
-        SUBSET ? pool.mask + (size_t)par * pool.mask_words : nullptr, ns, ub,
-        out_lb + (size_t)par * 2 * ns, out_prune + (size_t)par * 2 * ns,
-        pool.dir ? pool.dir + par : nullptr, lane);
+  const int n = I.n, m = I.m, ns = pool.n;  // ns: row stride (>= n)
+  const int step = gridDim.x * nw;
+  auto row_of = [&](int x) { return x < count ? (pool.index ? pool.index[x] : x) : -1; };
+  int it = blockIdx.x * nw + w;
+  int par = row_of(it);
+  PackFetch F = pack_fetch(pool, par, n, m, costs, lane);
+  for (; it < count; it += step) {
+    const int nxt = row_of(it + step);  // the next parent's inputs are loaded meanwhile
+    const PackFetch Fn = pack_fetch(pool, nxt, n, m, costs, lane);
+    lb2q_parent<NMAX, SUBSET, X16>(I, Ppad, S, F, ns, ub, out_lb + (size_t)par * 2 * ns,
+                                   out_prune + (size_t)par * 2 * ns,
+                                   pool.dir ? pool.dir + par : nullptr, lane);
+    par = nxt;
+    F = Fn;
   }
 }
 
@@ -1822,33 +1857,6 @@ __device__ __forceinline__ int group_transpose_pkmax(int (&acc)[L], int lane) {
   return acc[0];
 }
 
-// Global inputs of one parent as the lanes hold them: row byte `lane` (lane
-// < n), costs C1, C2, R of machine `lane` (lane < m), mask word `lane`
-// (lane < words), and d1, d2.  Loaded one batch ahead so that their latency
-// overlaps the previous batch's work.
-struct PackFetch {
-  int rb, c1, c2, rr, d1, d2;
-  uint32_t mw;
-};
-
-__device__ __forceinline__ PackFetch pack_fetch(const DevPool &pool, int par, int n, int m,
-                                                const int *__restrict__ costs, int lane) {
-  PackFetch F{0, -1, 0, 0, 0, 0, 0u};
-  if (par >= 0) {
-    const int *cs = costs + (size_t)par * 3 * m;
-    F.d1 = pool.d1[par];
-    F.d2 = pool.d2[par];
-    if (lane < n) F.rb = pool.perm[(size_t)par * pool.n + lane];
-    if (lane < m) {
-      F.c1 = cs[lane];
-      F.c2 = cs[m + lane];
-      F.rr = cs[2 * m + lane];
-    }
-    if (lane < pool.mask_words) F.mw = pool.mask[(size_t)par * pool.mask_words + lane];
-  }
-  return F;
-}
-
 // One wave bounds the pool rows rows[0 .. G) (-1: none) from their prefetched
 // inputs F.
 template <int NMAX, int G>
@@ -2230,10 +2238,12 @@ k_lb2m(const DevInst *__restrict__ insts, const MultiTile *__restrict__ tiles, i
     const int ub = ubs[cur];
     for (int par = T.begin + w; par < T.end; par += nw) {
       if constexpr (QUICK)
-        lb2q_parent<NMAX, false, X16>(I, Ppad, S, perm + (size_t)par * stride, d1[par], d2[par],
-                                 costs + (size_t)par * cstride, nullptr, stride, ub,
-                                 out_lb + (size_t)par * 2 * stride,
-                                 out_prune + (size_t)par * 2 * stride, dir + par, lane);
+        lb2q_parent<NMAX, false, X16>(
+            I, Ppad, S,
+            row_fetch(perm + (size_t)par * stride, costs + (size_t)par * cstride, d1[par],
+                      d2[par], I.n, I.m, lane),
+            stride, ub, out_lb + (size_t)par * 2 * stride, out_prune + (size_t)par * 2 * stride,
+            dir + par, lane);
       else
         lb2f_parent<NMAX, false, false>(
             I, Ppad, S, perm + (size_t)par * stride, d1[par], d2[par],

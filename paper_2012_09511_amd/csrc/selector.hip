@@ -29,7 +29,8 @@ constexpr int kIn = 64, kHid = 64, kOut = 190, kMMax = 20;
 constexpr int kOffW1 = 0, kOffB1 = kOffW1 + kHid * kIn, kOffW2 = kOffB1 + kHid,
               kOffB2 = kOffW2 + kHid * kHid, kOffW3 = kOffB2 + kHid, kOffB3 = kOffW3 + kOut * kHid,
               kParams = kOffB3 + kOut;
-constexpr int kTopKMax = 32;
+constexpr int kTopKMax = 32;   // float model and pfsp_selector_select
+constexpr int kTopKMaxQ = 64;  // integer model
 
 struct Selector {
   float *master = nullptr;  // fp32 parameters, layout W1[64][64] b1 W2[64][64] b2 W3[190][64] b3
@@ -797,12 +798,45 @@ int learned_prepare(Ctx *c, int rows) {
   if (!c->sel || !(c->sel->loaded || c->sel->qloaded))
     return set_err(c, PFSP_EINVAL, "no selector parameters set");
   if (c->m > kMMax) return set_err(c, PFSP_ERANGE, "the learned selector covers m <= 20");
-  if (c->learned_topk > kTopKMax)
-    return set_err(c, PFSP_ERANGE, "learned_topk must be <= 32 for the learned bound");
+  if (c->learned_topk > (c->sel->qloaded ? kTopKMaxQ : kTopKMax))
+    return set_err(c, PFSP_ERANGE,
+                   "learned_topk must be <= 32 (float selector) or <= 64 (integer selector)");
   Selector *S = c->sel;
   int rc = sel_tables(c, S);
   if (rc) return rc;
   return sel_rows(c, S, rows > 0 ? rows : 1);
+}
+
+// Pair masks of the pool's rows (costs already in the workspace) into
+// `mask`: the integer model when set (k <= 64), else the float one (k <= 32).
+static void launch_infer(Ctx *c, const DevPool &pool, int k, uint32_t *mask, hipStream_t s) {
+  Selector *S = c->sel;
+  const DevInst I = c->inst();
+  const int words = (c->P + 31) / 32;
+  if (S->qloaded) {
+    const float qs = S->sx / instance_norm(c), qd = S->sx / (float)c->n;
+    const dim3 g((pool.count + 64 * kQWaves - 1) / (64 * kQWaves)), b(64 * kQWaves);
+    const size_t lds = kQWaves * kQWaveLds;
+#define PFSP_IQ(K)                                                                         \
+  hipLaunchKernelGGL(k_infer_q<K>, g, b, lds, s, I, pool, c->d_costs, qs, qd, S->qops,       \
+                     S->qbias, S->M1, S->S1, S->M2, S->S2, S->to_inst, k, words, mask)
+    if (k <= 16)
+      PFSP_IQ(16);
+    else if (k <= 32)
+      PFSP_IQ(32);
+    else
+      PFSP_IQ(64);
+#undef PFSP_IQ
+  } else {
+    const dim3 g((pool.count + kInferRows - 1) / kInferRows), b(kInferRows);
+    const size_t lds = (((size_t)kParams + 3) / 4 * 4 + (size_t)kHid * kInferRows) * 4;
+    if (k <= 16)
+      hipLaunchKernelGGL(k_infer<16>, g, b, lds, s, I, pool, c->d_costs, instance_norm(c), S->wq,
+                         S->to_inst, k, words, mask);
+    else
+      hipLaunchKernelGGL(k_infer<32>, g, b, lds, s, I, pool, c->d_costs, instance_norm(c), S->wq,
+                         S->to_inst, k, words, mask);
+  }
 }
 
 int launch_learned(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8_t *out_prune,
@@ -825,39 +859,20 @@ int launch_learned_ready(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8
   if (rc) return rc;
   Selector *S = c->sel;
   if (pool.count <= 0) return PFSP_OK;
-  const DevInst I = c->inst();
   const int words = (c->P + 31) / 32;
   const int k = (int)c->learned_topk;
-  if (S->qloaded) {
+  {
     KTimer kt(c, s, "k_infer");
-    const float norm = instance_norm(c);
-    const float qs = S->sx / norm, qd = S->sx / (float)c->n;
-    const dim3 g((pool.count + 64 * kQWaves - 1) / (64 * kQWaves)), b(64 * kQWaves);
-    const size_t lds = kQWaves * kQWaveLds;
-    if (k <= 16)
-      hipLaunchKernelGGL(k_infer_q<16>, g, b, lds, s, I, pool, c->d_costs, qs, qd, S->qops,
-                         S->qbias, S->M1, S->S1, S->M2, S->S2, S->to_inst, k, words, S->mask);
-    else
-      hipLaunchKernelGGL(k_infer_q<32>, g, b, lds, s, I, pool, c->d_costs, qs, qd, S->qops,
-                         S->qbias, S->M1, S->S1, S->M2, S->S2, S->to_inst, k, words, S->mask);
-  } else {
-    KTimer kt(c, s, "k_infer");
-    const dim3 g((pool.count + kInferRows - 1) / kInferRows), b(kInferRows);
-    const size_t lds = (((size_t)kParams + 3) / 4 * 4 + (size_t)kHid * kInferRows) * 4;
-    if (k <= 16)
-      hipLaunchKernelGGL(k_infer<16>, g, b, lds, s, I, pool, c->d_costs, instance_norm(c), S->wq,
-                         S->to_inst, k, words, S->mask);
-    else
-      hipLaunchKernelGGL(k_infer<32>, g, b, lds, s, I, pool, c->d_costs, instance_norm(c), S->wq,
-                         S->to_inst, k, words, S->mask);
+    launch_infer(c, pool, k, S->mask, s);
   }
   PFSP_HIP(c, hipGetLastError());
   DevPool sp = pool;
   sp.mask = S->mask;
   sp.mask_words = words;
-  // a top-k of at most 16 (32) pairs fills a quarter (half) of a wave: pack
-  // four (two) parents per wave
-  const int group = c->subset_group > 0 ? (int)c->subset_group : k <= 16 ? 4 : k <= 32 ? 2 : 1;
+  // a top-k of at most 32 pairs fills half a wave: two parents per wave (four
+  // for k <= 16 cost about as much per parent at n <= 20, whose two-parent
+  // kernel runs three waves per SIMD; so four only where asked)
+  const int group = c->subset_group > 0 ? (int)c->subset_group : k <= 32 ? 2 : 1;
   return launch_bound_costs_ready(c, sp, PFSP_LB2_SUBSET, ub, out_lb, out_prune, s, group);
 }
 
@@ -961,7 +976,7 @@ int pfsp_selector_infer(pfsp_ctx *h, const pfsp_pool *pool, int32_t k, uint32_t 
   Ctx *c = &h->impl;
   if (c->n == 0) return set_err(c, PFSP_ENOINST, "no instance loaded");
   if (pool->count < 0 || pool->n != c->n) return set_err(c, PFSP_EINVAL, "bad pool");
-  if (k < 1 || k > kTopKMax) return set_err(c, PFSP_ERANGE, "k must be in [1, 32]");
+  if (k < 1 || k > kTopKMaxQ) return set_err(c, PFSP_ERANGE, "k must be in [1, 64]");
   if (c->m > kMMax || c->m < 2) return set_err(c, PFSP_ERANGE, "selection needs 2 <= m <= 20");
   PFSP_HIP(c, hipSetDevice(c->device));
   const int64_t saved = c->learned_topk;
@@ -980,30 +995,7 @@ int pfsp_selector_infer(pfsp_ctx *h, const pfsp_pool *pool, int32_t k, uint32_t 
   if (rc) return rc;
   rc = launch_costs(c, dp, c->stream);
   if (rc) return rc;
-  Selector *S = c->sel;
-  const DevInst I = c->inst();
-  const int words = (c->P + 31) / 32;
-  if (S->qloaded) {
-    const float qs = S->sx / instance_norm(c), qd = S->sx / (float)c->n;
-    const dim3 g((pool->count + 64 * kQWaves - 1) / (64 * kQWaves)), b(64 * kQWaves);
-    if (k <= 16)
-      hipLaunchKernelGGL(k_infer_q<16>, g, b, kQWaves * kQWaveLds, c->stream, I, dp, c->d_costs,
-                         qs, qd, S->qops, S->qbias, S->M1, S->S1, S->M2, S->S2, S->to_inst, k,
-                         words, mask_out);
-    else
-      hipLaunchKernelGGL(k_infer_q<32>, g, b, kQWaves * kQWaveLds, c->stream, I, dp, c->d_costs,
-                         qs, qd, S->qops, S->qbias, S->M1, S->S1, S->M2, S->S2, S->to_inst, k,
-                         words, mask_out);
-  } else {
-    const dim3 g((pool->count + kInferRows - 1) / kInferRows), b(kInferRows);
-    const size_t lds = (((size_t)kParams + 3) / 4 * 4 + (size_t)kHid * kInferRows) * 4;
-    if (k <= 16)
-      hipLaunchKernelGGL(k_infer<16>, g, b, lds, c->stream, I, dp, c->d_costs, instance_norm(c),
-                         S->wq, S->to_inst, k, words, mask_out);
-    else
-      hipLaunchKernelGGL(k_infer<32>, g, b, lds, c->stream, I, dp, c->d_costs, instance_norm(c),
-                         S->wq, S->to_inst, k, words, mask_out);
-  }
+  launch_infer(c, dp, k, mask_out, c->stream);
   PFSP_HIP(c, hipGetLastError());
   return PFSP_OK;
 }

@@ -201,7 +201,7 @@ def _quant_pool(n, seed):
 
 
 @pytest.mark.parametrize("m", [20, 13, 2])
-@pytest.mark.parametrize("k", [1, 16, 17, 32])
+@pytest.mark.parametrize("k", [1, 16, 17, 32, 33, 64])
 @pytest.mark.parametrize("ties", [False, True])
 def test_integer_selector_masks(ctx, m, k, ties):
     """The fused int8-MFMA inference selects exactly the oracle's pairs: random
@@ -222,7 +222,7 @@ def test_integer_selector_masks(ctx, m, k, ties):
         ctx.selector_set_quant(None)
 
 
-@pytest.mark.parametrize("k", [16, 32])
+@pytest.mark.parametrize("k", [16, 32, 64])
 def test_learned_bound_integer_model(ctx, k):
     """LB2_LEARNED with the quantized trained selector (calibrated by the
     library's own quantizer) equals subset LB2 over the oracle's pairs."""
@@ -264,3 +264,15 @@ def test_integer_selector_rejects_bad_blobs(ctx):
             ctx.selector_set_quant(bad)
     with pytest.raises(binding.PfspError):
         ctx.selector_set_quant(good[:-1])
+    # more than 32 pairs needs the integer model
+    import torch
+    perm, d1, d2 = inputs.random_pool(10, 4, 5)
+    dev = [_t(ctx, a) for a in (perm, d1, d2)]
+    ctx.selector_set(_params(9))
+    ctx.selector_set_quant(None)
+    with pytest.raises(binding.PfspError):
+        ctx.selector_infer(*dev, 33)
+    ctx.selector_set_quant(good)
+    ctx.selector_infer(*dev, 64)
+    torch.cuda.synchronize()
+    ctx.selector_set_quant(None)

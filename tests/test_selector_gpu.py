@@ -276,3 +276,83 @@ def test_integer_selector_rejects_bad_blobs(ctx):
     ctx.selector_infer(*dev, 64)
     torch.cuda.synchronize()
     ctx.selector_set_quant(None)
+
+
+def _trained_blob(ctx, n):
+    import os
+    from paper_2012_09511_amd import selector_quant
+    flat = np.load(os.path.join(os.path.dirname(inputs.__file__), "data", "selector_n20m20.npy"),
+                   allow_pickle=False)
+    ctx.selector_set(flat)
+    return selector_quant.quantize(flat, selector_quant.calibration_features(ctx, n, 2048))
+
+
+def test_trained_selector_gains(ctx):
+    """What training gains, with 16 of the 190 pairs per parent on 4,096 random
+    nodes of a 20 x 20 instance: the trained selector's bound equals full LB2
+    on more children, and prunes more at an incumbent in the middle of the
+    bounds, than 16 pairs drawn at random or picked by an untrained network
+    (LB1 alone is the floor).  Values go to stdout."""
+    import torch
+    n, m, k = 20, 20, 16
+    p = inputs.instance(n, m, 650)
+    perm, d1, d2 = inputs.random_pool(n, 4096, 651)
+    ctx.load_instance(p)
+    dev = [_t(ctx, a) for a in (perm, d1, d2)]
+
+    def bound(kind, mask=None):
+        tm = None if mask is None else _t(ctx, mask)
+        lb, _, _, _ = ctx.bound_children(*dev, kind=kind, ub=binding.INT32_MAX, pair_mask=tm)
+        torch.cuda.synchronize()
+        return lb.cpu().numpy()
+
+    full = bound(binding.LB2_FULL)
+    lb1 = bound(binding.LB1)
+    fin = full < binding.INT32_MAX
+    ub = int(np.percentile(full[fin], 40))
+    ctx.set_option("learned_topk", k)
+    try:
+        ctx.selector_set_quant(_trained_blob(ctx, n))
+        trained = bound(binding.LB2_LEARNED)
+        ctx.selector_set_quant(None)
+        ctx.selector_set(_params(652))            # an untrained network
+        untrained = bound(binding.LB2_LEARNED)
+    finally:
+        ctx.set_option("learned_topk", 16)
+    rng = np.random.default_rng(653)
+    P = m * (m - 1) // 2
+    sel = np.argsort(rng.random((len(perm), P)), axis=1)[:, :k]
+    mask = np.zeros((len(perm), (P + 31) // 32), dtype=np.uint32)
+    for w in range(mask.shape[1]):
+        bits = np.where((sel >> 5) == w, np.left_shift(np.uint64(1), (sel & 31).astype(np.uint64)), 0)
+        mask[:, w] = np.bitwise_or.reduce(bits, axis=1).astype(np.uint32)
+    rand = bound(binding.LB2_SUBSET, mask)
+    stats = {}
+    for name, x in (("trained", trained), ("untrained", untrained), ("random", rand),
+                    ("lb1", lb1)):
+        assert (x[fin] <= full[fin]).all() and (x[fin] >= lb1[fin]).all()
+        stats[name] = (float((x[fin] == full[fin]).mean()), int((x[fin] >= ub).sum()))
+    stats["full"] = (1.0, int((full[fin] >= ub).sum()))
+    print("recall of full LB2, prunes at ub =", ub, stats)
+    for other in ("untrained", "random", "lb1"):
+        assert stats["trained"][0] > stats[other][0] + 0.05
+        assert stats["trained"][1] > stats[other][1]
+
+
+def test_learned_search_same_optimum(ctx):
+    """Learned-pair LB2 (the trained selector's int8 form, 32 pairs) proves the
+    same optimum as full LB2 on a 20 x 20 instance from NEH + 1."""
+    p = inputs.instance(20, 20, 601)
+    ctx.load_instance(p)
+    ctx.selector_set_quant(_trained_blob(ctx, 20))
+    ctx.set_option("learned_topk", 32)
+    try:
+        ub0, _ = ctx.neh()
+        full = ctx.search(ub0 + 1, 0, binding.LB2_FULL)
+        learned = ctx.search(ub0 + 1, 0, binding.LB2_LEARNED)
+    finally:
+        ctx.set_option("learned_topk", 16)
+        ctx.selector_set_quant(None)
+    assert full["proven"] and learned["proven"]
+    assert full["best"] == learned["best"] <= ub0
+    assert learned["nodes"] >= full["nodes"]       # a subset never prunes more

@@ -241,8 +241,11 @@ k_scan_top(SearchCtl *__restrict__ c, int *__restrict__ bsum, long long cap) {
   }
 }
 
-// One wave per parent: writes the surviving children of the chosen direction
-// as new stack records (leftmost child on top), and the step's best leaf.
+// One wave per parent: the prune flags and bounds of 64 children are read at
+// once, the survivors of the chosen direction ranked by a ballot (leftmost
+// child on top of the stack), their indices put in LDS; then each survivor's
+// record is written with consecutive lanes on consecutive bytes.  The step's
+// best leaf is stored too.
 __global__ void __launch_bounds__(256)
 k_push(SearchCtl *__restrict__ c, int n, const uint8_t *__restrict__ b_perm,
        const uint8_t *__restrict__ b_d1, const uint8_t *__restrict__ b_d2,
@@ -251,9 +254,11 @@ k_push(SearchCtl *__restrict__ c, int n, const uint8_t *__restrict__ b_perm,
        const int *__restrict__ offs, const int *__restrict__ bsum, uint8_t *__restrict__ s_perm,
        uint8_t *__restrict__ s_d1, uint8_t *__restrict__ s_d2, int *__restrict__ s_lb,
        uint8_t *__restrict__ best_perm) {
+  __shared__ int sq[4][64];  // per wave: child index of each survivor rank
   const int count = c->count;
   if (c->overflow) return;
   const int lane = threadIdx.x & 63;
+  int *const rank_q = sq[threadIdx.x >> 6];
   const int waves = (gridDim.x * blockDim.x) >> 6;
   const unsigned long long sb = c->step_best;
   for (int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < count; i += waves) {
@@ -269,29 +274,46 @@ k_push(SearchCtl *__restrict__ c, int n, const uint8_t *__restrict__ b_perm,
     const int *lb = out_lb + ((size_t)i * 2 + dir) * n;
     const uint8_t *pr = out_prune + ((size_t)i * 2 + dir) * n;
     const long long dst = (long long)c->base + bsum[i / kScanBlock] + offs[i];
-    int t = 0;
-    for (int q = 0; q < r; ++q) {
-      if (pr[q]) continue;
-      const long long pos = dst + (s - 1 - t);
-      ++t;
-      uint8_t *out = s_perm + pos * n;
-      const int j = row[a + q];
-      for (int x = lane; x < n; x += 64) {
-        int v;
-        if (x < a || x >= a + r) {
-          v = row[x];
-        } else if (dir == 0) {  // sigma1 j | U \ j | sigma2
-          v = x == a ? j : (x <= a + q ? row[x - 1] : row[x]);
-        } else {  // sigma1 | U \ j | j sigma2
-          v = x == a + r - 1 ? j : (x < a + q ? row[x] : row[x + 1]);
+    int done = 0;  // survivors among earlier chunks of 64 children
+    for (int q0 = 0; q0 < r; q0 += 64) {
+      const int ql = q0 + lane;
+      const bool live = ql < r && pr[ql] == 0;
+      const int lbv = live ? lb[ql] : 0;
+      const uint64_t bal = __ballot(live);
+      if (live)
+        rank_q[__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                         __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0))] = ql;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const int nl = __popcll(bal);
+      for (int tt = 0; tt < nl; ++tt) {
+        const int q = rank_q[tt];
+        const int lq = __shfl(lbv, q - q0, 64);
+        const long long pos = dst + (s - 1 - (done + tt));
+        uint8_t *out = s_perm + pos * n;
+        const int j = row[a + q];
+        for (int x = lane; x < n; x += 64) {
+          int v;
+          if (x < a || x >= a + r) {
+            v = row[x];
+          } else if (dir == 0) {  // sigma1 j | U \ j | sigma2
+            v = x == a ? j : (x <= a + q ? row[x - 1] : row[x]);
+          } else {  // sigma1 | U \ j | j sigma2
+            v = x == a + r - 1 ? j : (x < a + q ? row[x] : row[x + 1]);
+          }
+          out[x] = (uint8_t)v;
         }
-        out[x] = (uint8_t)v;
+        if (lane == 0) {
+          s_d1[pos] = (uint8_t)(a + (dir == 0));
+          s_d2[pos] = (uint8_t)(b + (dir == 1));
+          s_lb[pos] = lq;
+        }
       }
-      if (lane == 0) {
-        s_d1[pos] = (uint8_t)(a + (dir == 0));
-        s_d2[pos] = (uint8_t)(b + (dir == 1));
-        s_lb[pos] = lb[q];
-      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();  // rank_q is rewritten by the next chunk
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      done += nl;
     }
   }
 }

@@ -256,9 +256,11 @@ constexpr int kQOpB1 = 0, kQOpB2 = kQOpB1 + kQT1 * 2 * 64, kQOpB3 = kQOpB2 + kQT
               kQOps = kQOpB3 + kQT3 * 2 * 64;  // uint2 entries
 constexpr int kQBias1 = 0, kQBias2 = kQT1 * 64, kQBias3 = 2 * kQT1 * 64,
               kQBiases = kQBias3 + kQT3 * 64;  // int entries
-constexpr int kQWaves = 4, kQRowStride = 72;   // bytes per LDS activation row (8-aligned)
-constexpr int kQKeyStride = 20;                // ints per LDS key row (16-aligned)
-constexpr size_t kQWaveLds = 2 * 64 * kQRowStride + 64 * kQKeyStride * 4;
+// A wave takes 16 rows (one MFMA row tile); four lanes share a row's top-k.
+constexpr int kQRows = 16, kQWaves = 4;
+constexpr int kQRowStride = 72;                // bytes per LDS activation row (8-aligned)
+constexpr int kQKeyStride = 196;               // ints per LDS key row: 192 pairs, 16-aligned
+constexpr size_t kQWaveLds = 2 * kQRows * kQRowStride + kQRows * kQKeyStride * 4;
 
 typedef int qv4 __attribute__((ext_vector_type(4)));
 
@@ -300,8 +302,8 @@ __device__ __forceinline__ void bitonic_merge_desc(int (&a)[N]) {
     }
 }
 
-// One hidden layer for the wave's 64 rows: A from `in` (row-major bytes),
-// int8 codes of the 64 units to `out`.
+// One hidden layer for the wave's rows: A from `in` (row-major bytes), int8
+// codes of the 64 units to `out`.
 __device__ __forceinline__ void q_hidden(const unsigned char *in, unsigned char *out,
                                          const uint2 *__restrict__ ops, const int *__restrict__ bias,
                                          int M, int S, int lane) {
@@ -319,7 +321,7 @@ __device__ __forceinline__ void q_hidden(const unsigned char *in, unsigned char 
   }
   const unsigned rnd = 1u << (S - 1);
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
+  for (int s = 0; s < kQRows / 16; ++s) {
     const unsigned char *row = in + (16 * s + c) * kQRowStride + 8 * g;
     const long a0 = *(const long *)row, a1 = *(const long *)(row + 32);
     unsigned code[4] = {0u, 0u, 0u, 0u};  // rows 4g + j: units 4c .. 4c + 3
@@ -342,7 +344,11 @@ __device__ __forceinline__ void q_hidden(const unsigned char *in, unsigned char 
 
 // Fused integer inference: features from the costs workspace, the three
 // layers on int8 MFMA, the top-KMAX keys per row, the pair masks.  Each wave
-// takes 64 consecutive pool rows (row = lane for features and selection).
+// takes 16 consecutive pool rows.  Features: lane l computes features
+// 16 (l / 16) .. + 15 of row l % 16.  Selection: lanes 4q .. 4q + 3 share row
+// q, lane part p keeping the top-KMAX of output tiles p, p + 4, p + 8; two
+// exchange-and-merge rounds (lanes l ^ 1, then l ^ 2) give all four the
+// row's top-KMAX.
 template <int KMAX>
 __global__ void __launch_bounds__(64 * kQWaves)
 k_infer_q(DevInst I, DevPool pool, const int *__restrict__ costs, float qs, float qd,
@@ -352,90 +358,91 @@ k_infer_q(DevInst I, DevPool pool, const int *__restrict__ costs, float qs, floa
   extern __shared__ __align__(16) unsigned char qsm[];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int count = pool.count_dev ? *pool.count_dev : pool.count;
-  const int base = (blockIdx.x * kQWaves + w) * 64;
+  const int base = (blockIdx.x * kQWaves + w) * kQRows;
   if (base >= count) return;  // waves never synchronize across the block
   unsigned char *xa = qsm + (size_t)w * kQWaveLds;
-  unsigned char *xb = xa + 64 * kQRowStride;
-  int *keys = (int *)(xb + 64 * kQRowStride);
+  unsigned char *xb = xa + kQRows * kQRowStride;
+  int *keys = (int *)(xb + kQRows * kQRowStride);
   const int n = I.n, m = I.m;
-  // features of row `lane`
-  const int it = base + lane;
-  const bool live = it < count;
-  const int i = live ? (pool.index ? pool.index[it] : it) : 0;
+  // features: 16 of row lane % 16
   {
-    unsigned f[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) f[q] = 0u;
-    if (live) {
+    const int fr = lane & 15, fg = lane >> 4;
+    const int it = base + fr;
+    unsigned f[4] = {0u, 0u, 0u, 0u};
+    if (it < count) {
+      const int i = pool.index ? pool.index[it] : it;
       const int *cs = costs + (size_t)i * 3 * m;
-      const int a = pool.d1[i], b = pool.d2[i];
       const bool bad = cs[0] < 0;  // invalid row flagged by the costs kernel
-      int lb1 = 0;
-      for (int x = 0; x < m; ++x) lb1 = max(lb1, cs[x] + cs[2 * m + x] + cs[m + x]);
 #pragma unroll
-      for (int x = 0; x < kMMax; ++x) {
-        const bool on = x < m && !bad;
-        const unsigned c1 = on ? (unsigned)q8((float)cs[on ? x : 0] * qs) : 0u;
-        const unsigned c2 = on ? (unsigned)q8((float)cs[on ? m + x : 0] * qs) : 0u;
-        const unsigned rr = on ? (unsigned)q8((float)cs[on ? 2 * m + x : 0] * qs) : 0u;
-        f[x >> 2] |= c1 << (8 * (x & 3));
-        f[(20 + x) >> 2] |= c2 << (8 * ((20 + x) & 3));
-        f[(40 + x) >> 2] |= rr << (8 * ((40 + x) & 3));
+      for (int e = 0; e < 16; ++e) {
+        const int x = 16 * fg + e;  // feature index
+        unsigned code = 0u;
+        if (x < 60) {
+          const int part = x / 20, kk = x - 20 * part;  // C1, C2, R of machine kk
+          if (kk < m && !bad) code = (unsigned)q8((float)cs[part * m + kk] * qs);
+        } else {
+          const int a = pool.d1[i], b = pool.d2[i];
+          if (x == 60) code = (unsigned)q8((float)a * qd);
+          if (x == 61) code = (unsigned)q8((float)b * qd);
+          if (x == 62) code = (unsigned)q8((float)(n - a - b) * qd);
+          if (x == 63 && !bad) {
+            int lb1 = 0;
+            for (int y = 0; y < m; ++y) lb1 = max(lb1, cs[y] + cs[2 * m + y] + cs[m + y]);
+            code = (unsigned)q8((float)lb1 * qs);
+          }
+        }
+        f[e >> 2] |= code << (8 * (e & 3));
       }
-      f[15] = (unsigned)q8((float)a * qd) | ((unsigned)q8((float)b * qd) << 8) |
-              ((unsigned)q8((float)(n - a - b) * qd) << 16) |
-              ((bad ? 0u : (unsigned)q8((float)lb1 * qs)) << 24);
     }
-#pragma unroll
-    for (int q = 0; q < 16; q += 2)
-      *(uint2 *)(xa + lane * kQRowStride + 4 * q) = make_uint2(f[q], f[q + 1]);
+    unsigned char *dst = xa + fr * kQRowStride + 16 * fg;
+    *(uint2 *)dst = make_uint2(f[0], f[1]);
+    *(uint2 *)(dst + 8) = make_uint2(f[2], f[3]);
   }
   wave_sync();
   q_hidden(xa, xb, ops + kQOpB1, bias + kQBias1, M1, S1, lane);
   wave_sync();
   q_hidden(xb, xa, ops + kQOpB2, bias + kQBias2, M2, S2, lane);
   wave_sync();
-  // output layer, 16 pairs at a time, into the running top-KMAX keys
-  const int c = lane & 15, g = lane >> 4;
-  long a3[4][2];
+  // output layer: keys of all 16 x 192 (row, pair) cells into LDS
+  {
+    const int c = lane & 15, g = lane >> 4;
+    const unsigned char *row = xa + c * kQRowStride + 8 * g;
+    const long a0 = *(const long *)row, a1 = *(const long *)(row + 32);
+#pragma unroll 4
+    for (int t = 0; t < kQT3; ++t) {
+      const uint2 e0 = ops[kQOpB3 + (t * 2) * 64 + lane];
+      const uint2 e1 = ops[kQOpB3 + (t * 2 + 1) * 64 + lane];
+      const long b0 = (long)(((unsigned long)e0.y << 32) | e0.x);
+      const long b1 = (long)(((unsigned long)e1.y << 32) | e1.x);
+      const int o = 16 * t + c;
+      const bool valid = o < kOut && to_inst[o < kOut ? o : 0] >= 0;
+      const int kb = bias[kQBias3 + t * 64 + lane];
+      qv4 d = {0, 0, 0, 0};
+      d = __builtin_amdgcn_mfma_i32_16x16x32_i8(a0, b0, d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_i32_16x16x32_i8(a1, b1, d, 0, 0, 0);
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const unsigned char *row = xa + (16 * s + c) * kQRowStride + 8 * g;
-    a3[s][0] = *(const long *)row;
-    a3[s][1] = *(const long *)(row + 32);
+      for (int j = 0; j < 4; ++j)
+        keys[(4 * g + j) * kQKeyStride + o] = valid ? (d[j] + kb) * 256 + (255 - o) : INT_MIN;
+    }
   }
+  wave_sync();
+  // selection: row lane / 4, tiles p, p + 4, p + 8
+  const int srow = lane >> 2, p = lane & 3;
   int best[KMAX];
 #pragma unroll
   for (int q = 0; q < KMAX; ++q) best[q] = INT_MIN;
-#pragma unroll 1
-  for (int t = 0; t < kQT3; ++t) {
-    const uint2 e0 = ops[kQOpB3 + (t * 2) * 64 + lane], e1 = ops[kQOpB3 + (t * 2 + 1) * 64 + lane];
-    const long b0 = (long)(((unsigned long)e0.y << 32) | e0.x);
-    const long b1 = (long)(((unsigned long)e1.y << 32) | e1.x);
-    const int o = 16 * t + c;
-    const bool valid = o < kOut && to_inst[o < kOut ? o : 0] >= 0;
-    const int kb = bias[kQBias3 + t * 64 + lane];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      qv4 d = {0, 0, 0, 0};
-      d = __builtin_amdgcn_mfma_i32_16x16x32_i8(a3[s][0], b0, d, 0, 0, 0);
-      d = __builtin_amdgcn_mfma_i32_16x16x32_i8(a3[s][1], b1, d, 0, 0, 0);
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        keys[(16 * s + 4 * g + j) * kQKeyStride + c] =
-            valid ? (d[j] + kb) * 256 + (255 - o) : INT_MIN;
-    }
-    wave_sync();
+  for (int u = 0; u < kQT3 / 4; ++u) {
+    const int *kr = keys + srow * kQKeyStride + 16 * (p + 4 * u);
     int ch[16];
 #pragma unroll
     for (int q = 0; q < 16; q += 4) {
-      const int4 v = *(const int4 *)(keys + lane * kQKeyStride + q);
+      const int4 v = *(const int4 *)(kr + q);
       ch[q] = v.x;
       ch[q + 1] = v.y;
       ch[q + 2] = v.z;
       ch[q + 3] = v.w;
     }
-    wave_sync();  // the next tile rewrites the keys
     bitonic_sort_desc<16>(ch);
 #pragma unroll
     for (int q = 0; q < KMAX; ++q) {
@@ -444,7 +451,18 @@ k_infer_q(DevInst I, DevPool pool, const int *__restrict__ costs, float qs, floa
     }
     bitonic_merge_desc<KMAX>(best);
   }
-  if (!live) return;
+#pragma unroll
+  for (int d = 1; d <= 2; d <<= 1) {  // merge with the partner's list
+    int other[KMAX];
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) other[q] = __shfl_xor(best[q], d, kWave);
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) best[q] = max(best[q], other[KMAX - 1 - q]);
+    bitonic_merge_desc<KMAX>(best);
+  }
+  const int it = base + srow;
+  if (p != 0 || it >= count) return;
+  const int i = pool.index ? pool.index[it] : it;
   uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0, w5 = 0;  // 190 pairs fit 6 words
 #pragma unroll
   for (int q = 0; q < KMAX; ++q) {
@@ -815,7 +833,7 @@ static void launch_infer(Ctx *c, const DevPool &pool, int k, uint32_t *mask, hip
   const int words = (c->P + 31) / 32;
   if (S->qloaded) {
     const float qs = S->sx / instance_norm(c), qd = S->sx / (float)c->n;
-    const dim3 g((pool.count + 64 * kQWaves - 1) / (64 * kQWaves)), b(64 * kQWaves);
+    const dim3 g((pool.count + kQRows * kQWaves - 1) / (kQRows * kQWaves)), b(64 * kQWaves);
     const size_t lds = kQWaves * kQWaveLds;
 #define PFSP_IQ(K)                                                                         \
   hipLaunchKernelGGL(k_infer_q<K>, g, b, lds, s, I, pool, c->d_costs, qs, qd, S->qops,       \

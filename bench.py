@@ -82,10 +82,10 @@ def profiled_traffic(kernel):
     return rec
 
 
-def cpu_baseline(p, perm, d1, d2, kind, target_s=12.0):
+def cpu_baseline(p, perm, d1, d2, kind, target_s=12.0, threads=None):
     import oracle
-    threads = len(os.sched_getaffinity(0))
-    threads = max(1, min(threads, 16))
+    if threads is None:
+        threads = max(1, min(len(os.sched_getaffinity(0)), 16))
     # calibrate on samples growing until one takes 0.5 s (thread start-up
     # dominates tiny ones), then run ~target_s of work
     k = 64
@@ -104,7 +104,7 @@ def cpu_baseline(p, perm, d1, d2, kind, target_s=12.0):
     children = int((2 * (n - d1[:k2].astype(np.int64) - d2[:k2].astype(np.int64))).sum())
     return dict(value=children / dt, unit="children/s", cores=threads, kind="oracle",
                 sample=f"first {k2} parents of the same pool ({children} children), "
-                       f"{dt:.1f} s, OpenMP over parents")
+                       f"{dt:.1f} s" + (", OpenMP over parents" if threads > 1 else ""))
 
 
 def main():
@@ -208,10 +208,35 @@ def main():
                kernels_ms={k: v for k, v in (("k_costs", ms_costs / max(lc, 1)),
                                              ("k_lb1", ms_lb1 / max(l1, 1)), (dom, dom_ms))
                            if v > 0})
+    if kind != binding.LB1:
+        out["depth_sweep"] = depth_sweep(ctx, torch, binding, inputs, n, m, ub)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, perm, d1, d2, kind)
+        out["cpu_baseline_1core"] = cpu_baseline(p, perm, d1, d2, kind, target_s=8.0, threads=1)
     ctx.close()
     print(json.dumps(out))
+
+
+def depth_sweep(ctx, torch, binding, inputs, n, m, ub, depths=(0, 5, 10, 15, 18), N=1 << 18):
+    """LB2 kernel time and roofline fraction on pools of one fixed depth d (d1 ~ U{0..d})."""
+    res = {}
+    for d in depths:
+        perm, d1, d2 = inputs.random_pool(n, N, 9600 + d, depth=d)
+        dev = [torch.from_numpy(a).cuda() for a in (perm, d1, d2)]
+        ctx.bound_children(*dev, kind=binding.LB2_FULL, ub=ub)
+        torch.cuda.synchronize()
+        ctx.set_option("timing", 1)
+        ctx.kernel_time("k_lb2", reset=True)
+        for _ in range(5):
+            ctx.bound_children(*dev, kind=binding.LB2_FULL, ub=ub)
+        torch.cuda.synchronize()
+        ms = ctx.kernel_time("k_lb2")[0] / 5
+        ctx.set_option("timing", 0)
+        children = 2 * (n - d) * N
+        res[str(d)] = dict(parents=N, k_lb2_ms=round(ms, 4),
+                           children_per_s=children / (ms * 1e-3),
+                           frac=alg_ops_lb2(n, m, d1, d2) / (ms * 1e-3) / PEAK_INT32_OPS)
+    return res
 
 
 def _copy_probe(torch):
@@ -318,6 +343,13 @@ def bench_multi(args):
     rep = mt.autotune(perm, d1, d2, seg, ub, binding.LB2_FULL, out=out_bufs, reps=2)
     run(args.warmup)
     tuned_s = run(args.steps)
+    d1h, d2h = d1.cpu().numpy(), d2.cpu().numpy()
+    ops = sum(alg_ops_lb2(n, m, d1h[seg[k]:seg[k + 1]], d2h[seg[k]:seg[k + 1]])
+              for k, (n, m, _) in enumerate(insts))
+    roof = dict(bound="alu", achieved=ops / tuned_s / 1e12, peak=PEAK_INT32_OPS / 1e12,
+                unit="TOP/s", frac=ops / tuned_s / PEAK_INT32_OPS, traffic=None,
+                kernel="whole graph launch (costs + every class kernel)",
+                alg_ops_per_launch=ops, op_count="P*(n+32(n-d)) per parent, summed")
     out = dict(metric="children bounded/sec (LB2), 64 mixed instances, one graph launch",
                value=children / tuned_s, unit="children/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=tuned_s * 1e3, higher_is_better=True,
@@ -325,6 +357,7 @@ def bench_multi(args):
                config=dict(workload="64 instances (n,m) in {20,50,100}x{5,10,20}, 25% "
                                     "job-correlated, 16384 random parents each, LB2_FULL",
                            parents=int(perm.shape[0]), children=children),
+               roofline=roof,
                default_shape=dict(ms=default_s * 1e3, children_per_s=children / default_s),
                autotuned=rep)
     mt.close()
@@ -362,10 +395,14 @@ def bench_learned(args):
                              children=r["children"], seconds=time.perf_counter() - t)
         assert res["full"]["best"] == res["learned"]["best"]
         assert res["full"]["proven"] and res["learned"]["proven"]
+        res["prune_rate_loss"] = prune_rate_loss(ctx, torch, binding, inputs, res["full"]["best"],
+                                                 seed)
         rows.append(dict(seed=seed, **res))
         print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
     tf = sum(x["full"]["seconds"] for x in rows)
     tl = sum(x["learned"]["seconds"] for x in rows)
+    nf = sum(x["full"]["nodes"] for x in rows)
+    nl = sum(x["learned"]["nodes"] for x in rows)
     out = dict(metric="time to the same proven optimum, learned-pair vs full LB2",
                value=tf / tl, unit="speedup", n_gpus=1, steps=1, warmup=0,
                ms_per_step=tl * 1e3, higher_is_better=True, scaling="weak", vs_baseline=None,
@@ -374,9 +411,27 @@ def bench_learned(args):
                                     f"learned top-{args.topk} of 190 pairs, "
                                     + ("float" if args.float_selector else "int8") + " selector "
                                     + os.path.basename(args.selector)),
-               full_seconds=tf, learned_seconds=tl, instances=rows)
+               full_seconds=tf, learned_seconds=tl, node_ratio=nl / nf,
+               prune_rate_loss=float(np.mean([x["prune_rate_loss"] for x in rows])),
+               instances=rows)
     ctx.close()
     print(json.dumps(out))
+
+
+def prune_rate_loss(ctx, torch, binding, inputs, opt, seed, N=1 << 16):
+    """Share of the children that full LB2 prunes at the optimum (LB >= opt)
+    and the learned bound does not, over those full LB2 prunes, on N random
+    nodes of the loaded instance (same children for both bounds)."""
+    n = 20
+    perm, d1, d2 = inputs.random_pool(n, N, 9900 + seed)
+    dev = [torch.from_numpy(a).cuda() for a in (perm, d1, d2)]
+    lf, pf, _, _ = ctx.bound_children(*dev, kind=binding.LB2_FULL, ub=opt)
+    pl = ctx.bound_children(*dev, kind=binding.LB2_LEARNED, ub=opt)[1]
+    torch.cuda.synchronize()
+    live = lf < binding.INT32_MAX
+    full_pr = (pf.bool() & live).sum().item()
+    lost = (pf.bool() & ~pl.bool() & live).sum().item()
+    return lost / max(full_pr, 1)
 
 
 if __name__ == "__main__":

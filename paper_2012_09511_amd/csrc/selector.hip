@@ -259,7 +259,7 @@ constexpr int kQBias1 = 0, kQBias2 = kQT1 * 64, kQBias3 = 2 * kQT1 * 64,
 // A wave takes 16 rows (one MFMA row tile); four lanes share a row's top-k.
 constexpr int kQRows = 16, kQWaves = 4;
 constexpr int kQRowStride = 72;                // bytes per LDS activation row (8-aligned)
-constexpr int kQKeyStride = 196;               // ints per LDS key row: 192 pairs, 16-aligned
+constexpr int kQKeyStride = 68;                // ints per LDS key row: 4 tiles, 16-aligned
 constexpr size_t kQWaveLds = 2 * kQRows * kQRowStride + kQRows * kQKeyStride * 4;
 
 typedef int qv4 __attribute__((ext_vector_type(4)));
@@ -346,9 +346,9 @@ __device__ __forceinline__ void q_hidden(const unsigned char *in, unsigned char 
 // layers on int8 MFMA, the top-KMAX keys per row, the pair masks.  Each wave
 // takes 16 consecutive pool rows.  Features: lane l computes features
 // 16 (l / 16) .. + 15 of row l % 16.  Selection: lanes 4q .. 4q + 3 share row
-// q, lane part p keeping the top-KMAX of output tiles p, p + 4, p + 8; two
-// exchange-and-merge rounds (lanes l ^ 1, then l ^ 2) give all four the
-// row's top-KMAX.
+// q; the output layer runs four 16-pair tiles at a time through LDS and lane
+// part p keeps the top-KMAX of tiles p, p + 4, p + 8; two exchange-and-merge
+// rounds (lanes l ^ 1, then l ^ 2) give all four the row's top-KMAX.
 template <int KMAX>
 __global__ void __launch_bounds__(64 * kQWaves)
 k_infer_q(DevInst I, DevPool pool, const int *__restrict__ costs, float qs, float qd,
@@ -403,13 +403,20 @@ k_infer_q(DevInst I, DevPool pool, const int *__restrict__ costs, float qs, floa
   wave_sync();
   q_hidden(xb, xa, ops + kQOpB2, bias + kQBias2, M2, S2, lane);
   wave_sync();
-  // output layer: keys of all 16 x 192 (row, pair) cells into LDS
-  {
-    const int c = lane & 15, g = lane >> 4;
-    const unsigned char *row = xa + c * kQRowStride + 8 * g;
-    const long a0 = *(const long *)row, a1 = *(const long *)(row + 32);
-#pragma unroll 4
-    for (int t = 0; t < kQT3; ++t) {
+  // output layer, four 16-pair tiles per round: keys into LDS, then each lane
+  // part sorts one tile of its row and merges it into its running top-KMAX
+  const int c = lane & 15, g = lane >> 4;
+  const unsigned char *arow = xa + c * kQRowStride + 8 * g;
+  const long a0 = *(const long *)arow, a1 = *(const long *)(arow + 32);
+  const int srow = lane >> 2, p = lane & 3;
+  int best[KMAX];
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) best[q] = INT_MIN;
+#pragma unroll 1
+  for (int u = 0; u < kQT3 / 4; ++u) {
+#pragma unroll
+    for (int tq = 0; tq < 4; ++tq) {
+      const int t = 4 * u + tq;
       const uint2 e0 = ops[kQOpB3 + (t * 2) * 64 + lane];
       const uint2 e1 = ops[kQOpB3 + (t * 2 + 1) * 64 + lane];
       const long b0 = (long)(((unsigned long)e0.y << 32) | e0.x);
@@ -422,18 +429,11 @@ k_infer_q(DevInst I, DevPool pool, const int *__restrict__ costs, float qs, floa
       d = __builtin_amdgcn_mfma_i32_16x16x32_i8(a1, b1, d, 0, 0, 0);
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        keys[(4 * g + j) * kQKeyStride + o] = valid ? (d[j] + kb) * 256 + (255 - o) : INT_MIN;
+        keys[(4 * g + j) * kQKeyStride + 16 * tq + c] =
+            valid ? (d[j] + kb) * 256 + (255 - o) : INT_MIN;
     }
-  }
-  wave_sync();
-  // selection: row lane / 4, tiles p, p + 4, p + 8
-  const int srow = lane >> 2, p = lane & 3;
-  int best[KMAX];
-#pragma unroll
-  for (int q = 0; q < KMAX; ++q) best[q] = INT_MIN;
-#pragma unroll
-  for (int u = 0; u < kQT3 / 4; ++u) {
-    const int *kr = keys + srow * kQKeyStride + 16 * (p + 4 * u);
+    wave_sync();
+    const int *kr = keys + srow * kQKeyStride + 16 * p;
     int ch[16];
 #pragma unroll
     for (int q = 0; q < 16; q += 4) {
@@ -443,6 +443,7 @@ k_infer_q(DevInst I, DevPool pool, const int *__restrict__ costs, float qs, floa
       ch[q + 2] = v.z;
       ch[q + 3] = v.w;
     }
+    wave_sync();  // the next round rewrites the keys
     bitonic_sort_desc<16>(ch);
 #pragma unroll
     for (int q = 0; q < KMAX; ++q) {

@@ -1049,10 +1049,11 @@ struct QuickLds {
 
 // Block-cooperative staging of one instance for the quick kernels (no
 // barrier inside).  The staged narrow entries hold x = a | b << 16 and
-// y = l | k << 24; the quick entries are {b - a, k | (a + l) << 16}, or
-// {(b - a) & 0xffff | (a + l) << 16, k} when X16 (then |b - a| < 2^14 and
-// a + l < 2^16).
-template <int NMAX, bool X16, class Lds>
+// y = l | k << 24; the quick entries are {b - a, k | (a + l) << 16}: the
+// scans add b - a straight from x (no sign extension) and a + l from the
+// high half of y, and k < 32 sits in the low bits that a bit-field extract
+// takes as its offset.
+template <int NMAX, class Lds>
 __device__ void lb2q_stage(const DevInst &I, int Ppad, const Lds &S) {
   const int n = I.n, m = I.m, P = I.P;
   for (int x = threadIdx.x; x < NMAX * Ppad; x += blockDim.x) {
@@ -1062,8 +1063,7 @@ __device__ void lb2q_stage(const DevInst &I, int Ppad, const Lds &S) {
     if (i < n && P > 0) {
       const uint2 s = I.ent[(size_t)i * P + (pi < P ? pi : 0)];
       const unsigned a = s.x & 0xffffu, b = s.x >> 16, l = s.y & 0xffffffu, k = s.y >> 24;
-      e = X16 ? make_uint2(((b - a) & 0xffffu) | ((a + l) << 16), k)
-              : make_uint2(b - a, k | ((a + l) << 16));
+      e = make_uint2(b - a, k | ((a + l) << 16));
     }
     S.ent[x] = e;
   }
@@ -1130,7 +1130,8 @@ __device__ __forceinline__ PackFetch pack_fetch(const DevPool &pool, int par, in
 template <int NMAX, bool SUBSET, bool X16>
 __device__ void lb2q_parent(const DevInst &I, int Ppad, const QuickLds<NMAX> &S,
                             const PackFetch &F, int stride, int ub, int *__restrict__ lbrow,
-                            uint8_t *__restrict__ prow, uint8_t *__restrict__ dirp, int lane) {
+                            uint8_t *__restrict__ prow, uint8_t *__restrict__ dirp, int lane,
+                            int tsrc) {
   constexpr int ROW = QuickLayout::row(NMAX);
   const int n = I.n, m = I.m, P = I.P;
   const int a = __builtin_amdgcn_readfirstlane(F.d1), b = __builtin_amdgcn_readfirstlane(F.d2);
@@ -1215,8 +1216,8 @@ __device__ void lb2q_parent(const DevInst &I, int Ppad, const QuickLds<NMAX> &S,
     const int uvp = S.uv[pi];
     const int u = uvp & 0xff, v = uvp >> 8;
     const int K4 = S.rr[v] + S.c2[v], K5 = S.c1[u] + S.rr[v];
-    const int *Fu = S.FBf + u * ROW;
-    const int *Gv = X16 ? S.FBf + v * ROW : S.FBb + (m - 1 - v) * ROW;
+    const int *Fu = lds_opaque(S.FBf + u * ROW);
+    const int *Gv = lds_opaque(X16 ? S.FBf + v * ROW : S.FBb + (m - 1 - v) * ROW);
     const uint2 *__restrict__ eb = S.ent + (pi >> 6) * (NMAX * 64) + (pi & 63);
     // forward scan: terms of members (NEG for the others) and exclusive prefix maxima
     int pm[NMAX], tm[NMAX];
@@ -1226,12 +1227,11 @@ __device__ void lb2q_parent(const DevInst &I, int Ppad, const QuickLds<NMAX> &S,
     for (int i = 0; i < NMAX; ++i) {
       const uint2 e = eb[i * 64];
       const int ng = __builtin_amdgcn_sbfe((int)umask, (int)e.y, 1);  // -1 if member
-      const int tt = Y + (int)((X16 ? e.x : e.y) >> 16);
+      const int tt = Y + (int)(e.y >> 16);
       tm[i] = (tt & ng) | (NEGX & ~ng);
       pm[i] = Pm;
       Pm = max(Pm, tm[i]);
-      const int E = X16 ? (int)(short)(e.x & 0xffffu) : (int)e.x;
-      Y = __mul24(ng, E) + Y;  // Y += a - b for members
+      Y = __mul24(ng, (int)e.x) + Y;  // Y += a - b for members
       if constexpr (X16) ke[i] = __builtin_amdgcn_perm(e.y, e.x, 0x040c0100u);
     }
     // backward scan: Xa, Xb by job (the 32-bit entries are read again rather
@@ -1269,13 +1269,18 @@ __device__ void lb2q_parent(const DevInst &I, int Ppad, const QuickLds<NMAX> &S,
               gw[j] = Gv[g + j];
             }
           }
+          // all four sums before the maxima: a packed result read by the
+          // next instruction costs a wait state
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            if (g + j < NMAX) {
-              const int fg =
-                  (int)__builtin_amdgcn_perm((unsigned)gw[j], (unsigned)fw[j], 0x07060100u);
-              acc[g + j] = pk_max(acc[g + j], pk_add(fg, h[j]));
-            }
+            if (g + j < NMAX)
+              h[j] = pk_add((int)__builtin_amdgcn_perm((unsigned)gw[j], (unsigned)fw[j],
+                                                       0x07060100u),
+                            h[j]);
+          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (g + j < NMAX) acc[g + j] = pk_max(acc[g + j], h[j]);
           }
         } else {
           int xa[4], xb[4], fu[4], gv[4];
@@ -1302,10 +1307,7 @@ __device__ void lb2q_parent(const DevInst &I, int Ppad, const QuickLds<NMAX> &S,
   }
   int t;
   if constexpr (X16) {
-    int a32[32];
-#pragma unroll
-    for (int q = 0; q < 32; ++q) a32[q] = q < NMAX ? acc[q < NMAX ? q : 0] : (int)0x80008000u;
-    t = transpose_pkmax32<0>(a32, lane);
+    t = transpose_pkmax<NMAX>(acc, lane, tsrc);
   } else {
     t = transpose_max_fb<NMAX>(accf, accb, lane, kNeg);
   }
@@ -1347,7 +1349,7 @@ k_lb2q(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
   if ((int)blockIdx.x * nw >= count) return;  // no parent for this block: skip the staging
   const QuickLayout L{Ppad, I.m, X16};
   const QuickLds<NMAX> S(sm, L, w);
-  lb2q_stage<NMAX, X16>(I, Ppad, S);
+  lb2q_stage<NMAX>(I, Ppad, S);
   __syncthreads();
   if (pool.ub_dev) ub = *pool.ub_dev;
   const int n = I.n, m = I.m, ns = pool.n;  // ns: row stride (>= n)
@@ -1356,12 +1358,13 @@ k_lb2q(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
   int it = blockIdx.x * nw + w;
   int par = row_of(it);
   PackFetch F = pack_fetch(pool, par, n, m, costs, lane);
+  const int tsrc = tp_source<NMAX>(lane);
   for (; it < count; it += step) {
     const int nxt = row_of(it + step);  // the next parent's inputs are loaded meanwhile
     const PackFetch Fn = pack_fetch(pool, nxt, n, m, costs, lane);
     lb2q_parent<NMAX, SUBSET, X16>(I, Ppad, S, F, ns, ub, out_lb + (size_t)par * 2 * ns,
                                    out_prune + (size_t)par * 2 * ns,
-                                   pool.dir ? pool.dir + par : nullptr, lane);
+                                   pool.dir ? pool.dir + par : nullptr, lane, tsrc);
     par = nxt;
     F = Fn;
   }
@@ -1484,11 +1487,11 @@ __device__ __forceinline__ void lb2w_chunk(const uint2 *__restrict__ ec, int rem
     const uint2 e = ev[i];
     int ng = member_ng<NW>(um, e.y);
     if (RAGGED) ng &= in ? -1 : 0;
-    const int tt = Y + (int)(e.x >> 16);
+    const int tt = Y + (int)(e.y >> 16);
     tm[i] = (tt & ng) | (NEGX & ~ng);
     pm[i] = Pm;
     Pm = max(Pm, tm[i]);
-    Y = __mul24(ng, (int)(short)(e.x & 0xffffu)) + Y;
+    Y = __mul24(ng, (int)e.x) + Y;
     ke[i] = __builtin_amdgcn_perm(in ? e.y : (unsigned)n, e.x, 0x040c0100u);
   }
 #pragma unroll
@@ -1596,9 +1599,9 @@ __device__ void lb2w_parent(const DevInst &I, int Ppad, const WideLds<NMAX> &S,
       for (int i = 0; i < CH; ++i) {
         const uint2 e = ev[i];
         const int ng = member_ng<NW>(um, e.y);
-        const int tt = Y + (int)(e.x >> 16);
+        const int tt = Y + (int)(e.y >> 16);
         Pm = max(Pm, (tt & ng) | (NEGX & ~ng));
-        Y = __mul24(ng, (int)(short)(e.x & 0xffffu)) + Y;
+        Y = __mul24(ng, (int)e.x) + Y;
       }
     }
     // second sweep, chunks from last to first (only the last can be ragged)
@@ -1978,11 +1981,11 @@ __device__ void lb2s_wave(const DevInst &I, int Ppad, const PackLds<NMAX, G> &S,
     for (int i = 0; i < NMAX; ++i) {
       const uint2 e = eb[i * 64];
       const int ng = __builtin_amdgcn_sbfe((int)umask, (int)e.y, 1);
-      const int tt = Y + (int)(e.x >> 16);
+      const int tt = Y + (int)(e.y >> 16);
       tm[i] = (tt & ng) | (NEGX & ~ng);
       pm[i] = Pm;
       Pm = max(Pm, tm[i]);
-      Y = __mul24(ng, (int)(short)(e.x & 0xffffu)) + Y;
+      Y = __mul24(ng, (int)e.x) + Y;
       ke[i] = __builtin_amdgcn_perm(e.y, e.x, 0x040c0100u);
     }
     int Sm = NEGX;
@@ -2133,7 +2136,7 @@ k_lb2s(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
   if ((int)blockIdx.x * nw * G >= count) return;  // no parent for this block
   const PackLayout L{Ppad, I.m};
   const PackLds<NMAX, G> S(sm, L, w);
-  lb2q_stage<NMAX, true>(I, Ppad, S);
+  lb2q_stage<NMAX>(I, Ppad, S);
   __syncthreads();
   if (pool.ub_dev) ub = *pool.ub_dev;
   const int step = gridDim.x * nw * G;
@@ -2216,6 +2219,7 @@ k_lb2m(const DevInst *__restrict__ insts, const MultiTile *__restrict__ tiles, i
   using Lds = typename std::conditional<QUICK, QuickLds<NMAX>, FastLds<NMAX>>::type;
   const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const Lds S = make_lds<NMAX, X16>(sm, L, w);
+  const int tsrc = tp_source<QUICK ? NMAX : 32>(lane);
   int cur = -1, Ppad = 0;
   DevInst I{};
   for (;;) {
@@ -2230,7 +2234,7 @@ k_lb2m(const DevInst *__restrict__ insts, const MultiTile *__restrict__ tiles, i
       I = insts[cur];
       Ppad = (I.P + 63) / 64 * 64;
       if constexpr (QUICK)
-        lb2q_stage<NMAX, X16>(I, Ppad, S);
+        lb2q_stage<NMAX>(I, Ppad, S);
       else
         lb2f_stage<NMAX>(I, Ppad, S);
       __syncthreads();
@@ -2243,7 +2247,7 @@ k_lb2m(const DevInst *__restrict__ insts, const MultiTile *__restrict__ tiles, i
             row_fetch(perm + (size_t)par * stride, costs + (size_t)par * cstride, d1[par],
                       d2[par], I.n, I.m, lane),
             stride, ub, out_lb + (size_t)par * 2 * stride, out_prune + (size_t)par * 2 * stride,
-            dir + par, lane);
+            dir + par, lane, tsrc);
       else
         lb2f_parent<NMAX, false, false>(
             I, Ppad, S, perm + (size_t)par * stride, d1[par], d2[par],

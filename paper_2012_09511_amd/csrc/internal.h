@@ -31,7 +31,7 @@ struct DevInst {
   const int *T;            // [m] per-machine totals
   const uint2 *ent;        // [n][P] narrow entries: x = a | b << 16, y = lag | k << 24
   const uint4 *entw;       // [n][P] wide entries: {a, b, lag, k}
-  const uint2 *entq;       // [P/64 passes][n][64] 16-bit-X entries (n > 32, x16), else null
+  const uint2 *entq;       // [P/64 passes][n][64] quick entries (n > 32, x16), else null
   const uint8_t *pu;       // [P] first machine of pair
   const uint8_t *pv;       // [P] second machine of pair
 };
@@ -159,7 +159,7 @@ int stage_instance(Ctx *c);
 int stage_tables(Ctx *c, hipStream_t s, int n, int m, const int *d_p, int *d_T, uint2 *d_ent,
                  uint4 *d_entw, uint8_t *d_pu, uint8_t *d_pv, int narrow);
 // Quick-format copy of the narrow pair table for the wide kernels: entries
-// {(b - a) & 0xffff | (a + lag) << 16, job} in [pass][position][64 lanes]
+// {b - a, job | (a + lag) << 16} (job < 128) in [pass][position][64 lanes]
 // order, pairs >= P repeating pair 0; allocates *d_entq.  Synchronous.
 int stage_quick(Ctx *c, hipStream_t s, int n, int m, const uint2 *d_ent, uint2 **d_entq);
 // bound.hip

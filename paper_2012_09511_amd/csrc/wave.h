@@ -15,6 +15,19 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// p (an LDS address) with its value hidden from the compiler: it then keeps
+// the whole address in one register and puts the small constant offsets of
+// the accesses through it into the instructions, instead of splitting off a
+// large constant part that paired loads cannot encode and re-adding it
+// before each pair.
+template <class T>
+__device__ __forceinline__ const T *lds_opaque(const T *p) {
+  using LT = __attribute__((address_space(3))) const T;
+  uint32_t a = (uint32_t)(uintptr_t)(LT *)p;
+  asm("" : "+v"(a));
+  return (const T *)(LT *)(uintptr_t)a;
+}
+
 __device__ __forceinline__ int wave_min(int x) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) x = min(x, __shfl_xor(x, o, kWave));
@@ -162,6 +175,91 @@ __device__ __forceinline__ void pk_split_dpp(int (&a)[2 * O], int lane, int lb_m
     else got = dpp_partner<2>(send);
     a[j] = pk_max(keep, got);
   }
+}
+
+// Transposing max-reduction of NJ <= 32 such pairs without padding to 32
+// jobs.  The lane bits are taken from 5 down to 0; while N > 1 registers are
+// left, registers j and j + H (H = ceil(N / 2)) combine (lanes with the bit
+// set keep the second's job, the others the first's, each taking the
+// maximum with its partner lane across the bit), an odd N leaving register
+// H - 1 to be folded with its partner unchanged; from one register on the
+// remaining bits are folded.  Which lane ends with which job depends only on
+// the lane's bits (tp_job); tp_source gives, for lane q or 32 + q, the first
+// lane that ends with job q.
+template <int LB>
+__device__ __forceinline__ int tp_pair(int lo, int hi_job, bool hi) {
+  if constexpr (LB == 5) {
+    const auto r = __builtin_amdgcn_permlane32_swap(lo, hi_job, false, false);
+    return pk_max((int)r[0], (int)r[1]);
+  } else if constexpr (LB == 4) {
+    const auto r = __builtin_amdgcn_permlane16_swap(lo, hi_job, false, false);
+    return pk_max((int)r[0], (int)r[1]);
+  } else {
+    const int send = hi ? lo : hi_job, keep = hi ? hi_job : lo;
+    return pk_max(keep, dpp_partner<(1 << LB)>(send));
+  }
+}
+
+template <int LB>
+__device__ __forceinline__ int tp_fold(int x) {
+  if constexpr (LB == 5) {
+    const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    return pk_max((int)r[0], (int)r[1]);
+  } else if constexpr (LB == 4) {
+    const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    return pk_max((int)r[0], (int)r[1]);
+  } else {
+    return pk_max(x, dpp_partner<(1 << LB)>(x));
+  }
+}
+
+template <int N, int LB, int NA>
+__device__ __forceinline__ void tp_steps(int (&a)[NA], int lane) {
+  if constexpr (LB >= 0) {
+    constexpr int H = (N + 1) / 2;
+    const bool hi = ((lane >> LB) & 1) != 0;
+#pragma unroll
+    for (int j = 0; j < N - H; ++j) a[j] = tp_pair<LB>(a[j], a[j + H], hi);
+    if constexpr (N & 1) a[H - 1] = tp_fold<LB>(a[H - 1]);
+    tp_steps<H, LB - 1>(a, lane);
+  }
+}
+
+// The job that lane l holds after tp_steps over NJ registers.
+template <int NJ>
+__host__ __device__ constexpr int tp_job(int l) {
+  int ns[6] = {};
+  int n = NJ;
+  for (int s = 0; s < 6; ++s) {
+    ns[s] = n;
+    n = (n + 1) / 2;
+  }
+  int j = 0;
+  for (int s = 5; s >= 0; --s) {  // step s takes lane bit 5 - s
+    const int h = (ns[s] + 1) / 2;
+    if (j < ns[s] - h && ((l >> (5 - s)) & 1)) j += h;
+  }
+  return j;
+}
+
+template <int NJ>
+__device__ __forceinline__ int tp_source(int lane) {
+  const int q = lane & 31;
+  int src = 0;
+#pragma unroll
+  for (int l = 63; l >= 0; --l)
+    if (tp_job<NJ>(l) == q) src = l;
+  return src;
+}
+
+// acc[0 .. NJ) is consumed; src = tp_source<NJ>(lane).  Lane q < 32 returns
+// job q's low-half maximum, lane 32 + q its high-half one (sign-extended).
+template <int NJ>
+__device__ __forceinline__ int transpose_pkmax(int (&acc)[NJ], int lane, int src) {
+  static_assert(NJ >= 1 && NJ <= 32, "one job per lane of a half-wave");
+  tp_steps<NJ, 5>(acc, lane);
+  const int g = __shfl(acc[0], src, kWave);
+  return lane < 32 ? (int)(short)(g & 0xffff) : g >> 16;
 }
 
 template <int OFF, int N>

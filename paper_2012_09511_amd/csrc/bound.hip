@@ -1203,8 +1203,13 @@ __device__ void lb2q_parent(const DevInst &I, int Ppad, const QuickLds<NMAX> &S,
   int accf[NA], accb[NA], acc[X16 ? NMAX : 1];
 #pragma unroll
   for (int q = 0; q < NA; ++q) accf[q] = accb[q] = kNeg;
+  // (set once here: left to itself the compiler repeats these moves on the
+  // path into the pair loop)
 #pragma unroll
-  for (int q = 0; q < (X16 ? NMAX : 1); ++q) acc[q] = (int)0x80008000u;
+  for (int q = 0; q < (X16 ? NMAX : 1); ++q) {
+    acc[q] = (int)0x80008000u;
+    asm volatile("" : "+v"(acc[q]));
+  }
   const int npass = r < 2 ? 0 : SUBSET ? nsel : (P > 0 ? Ppad : 0);  // leaves: LB2 = LB1
   constexpr int NEGX = X16 ? -(1 << 14) : kNeg;
   int2 *__restrict__ Xl = (int2 *)S.X + lane;
@@ -1569,7 +1574,10 @@ __device__ void lb2w_parent(const DevInst &I, int Ppad, const WideLds<NMAX> &S,
   wave_sync();
   int acc[NMAX];  // two int16 maxima per job: forward | backward << 16
 #pragma unroll
-  for (int q = 0; q < NMAX; ++q) acc[q] = (int)0x80008000u;
+  for (int q = 0; q < NMAX; ++q) {  // set once (not repeated on the path into the loop)
+    acc[q] = (int)0x80008000u;
+    asm volatile("" : "+v"(acc[q]));
+  }
   const int npass = r < 2 ? 0 : (P > 0 ? Ppad : 0);  // leaves: LB2 = LB1
   const int nch = (n + CH - 1) / CH;
   int *__restrict__ Xh = S.X + lane;
@@ -1632,10 +1640,11 @@ __device__ void lb2w_parent(const DevInst &I, int Ppad, const WideLds<NMAX> &S,
           gw[j] = Gv[g + j];
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int fg = (int)__builtin_amdgcn_perm((unsigned)gw[j], (unsigned)fw[j], 0x07060100u);
-          acc[g + j] = pk_max(acc[g + j], pk_add(fg, h[j]));
-        }
+        for (int j = 0; j < 4; ++j)  // sums first: no wait state before each maximum
+          h[j] = pk_add((int)__builtin_amdgcn_perm((unsigned)gw[j], (unsigned)fw[j], 0x07060100u),
+                        h[j]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[g + j] = pk_max(acc[g + j], h[j]);
       }
     }
   }
@@ -1834,30 +1843,46 @@ __device__ __forceinline__ int group_transpose_max(int (&acc)[L], int lane) {
   return acc[0];
 }
 
-// The same network on int16 pairs (both halves reduced independently).
-template <int O, int N>
-__device__ __forceinline__ void transpose_pkmax_dpp(int (&acc)[N], int lane) {
-  const bool hi = (lane & O) != 0;
-#pragma unroll
-  for (int j = 0; j < O; ++j) {
-    const int send = hi ? acc[j] : acc[O + j];
-    const int keep = hi ? acc[O + j] : acc[j];
-    acc[j] = pk_max(keep, dpp_partner<O>(send));
-  }
-  if constexpr (O > 1) transpose_pkmax_dpp<O / 2>(acc, lane);
+// Per group of L lanes (32 or 16): lane l ends with the group maximum of
+// blk[l], the NJ <= L jobs combined without padding and gathered back to
+// their own lanes from src = tp_group_source<L, NJ>(lane) (a full block
+// already ends in place).
+template <int L, int NJ>
+__device__ __forceinline__ int group_transpose_pkmax(int (&blk)[L], int lane, int src) {
+  constexpr int TOP = L == 32 ? 4 : 3;
+  static_assert(L == 32 || L == 16, "two or four parents per wave");
+  tp_steps<NJ, TOP>(blk, lane);
+  if constexpr (NJ == L) return blk[0];
+  return __shfl(blk[0], src, kWave);
 }
 
-template <int L>
-__device__ __forceinline__ int group_transpose_pkmax(int (&acc)[L], int lane) {
-  if constexpr (L == 32) {
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const auto r = __builtin_amdgcn_permlane16_swap(acc[j], acc[16 + j], false, false);
-      acc[j] = pk_max((int)r[0], (int)r[1]);
+// The gather lanes of the blocks of L jobs that cover NMAX jobs.
+template <int NMAX, int L>
+struct GroupSrc {
+  static constexpr int NB = (NMAX + L - 1) / L;
+  int s[NB];
+  __device__ explicit GroupSrc(int lane) { fill<0>(lane); }
+  template <int B>
+  __device__ void fill(int lane) {
+    if constexpr (B < NB) {
+      s[B] = tp_group_source<L, (NMAX - B * L < L ? NMAX - B * L : L)>(lane);
+      fill<B + 1>(lane);
     }
   }
-  transpose_pkmax_dpp<8>(acc, lane);
-  return acc[0];
+};
+
+// Block B of L jobs: job B * L + l ends in lane l of each group.
+template <int B, int L, int NMAX, int NB>
+__device__ __forceinline__ void group_blocks(const int (&acc)[NMAX], int (&t)[NB],
+                                             const GroupSrc<NMAX, L> &src, int lane) {
+  if constexpr (B < NB) {
+    constexpr int NJ = NMAX - B * L < L ? NMAX - B * L : L;
+    int blk[L];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) blk[j] = acc[B * L + j];
+    t[B] = group_transpose_pkmax<L, NJ>(blk, lane, src.s[B]);
+    group_blocks<B + 1, L, NMAX, NB>(acc, t, src, lane);
+  }
 }
 
 // One wave bounds the pool rows rows[0 .. G) (-1: none) from their prefetched
@@ -1866,7 +1891,7 @@ template <int NMAX, int G>
 __device__ void lb2s_wave(const DevInst &I, int Ppad, const PackLds<NMAX, G> &S,
                           const DevPool &pool, const int (&rows)[G], const PackFetch (&F)[G],
                           int ub, int *__restrict__ out_lb, uint8_t *__restrict__ out_prune,
-                          int lane) {
+                          int lane, const GroupSrc<NMAX, 64 / G> &tsrc) {
   constexpr int L = 64 / G;
   constexpr int ROW = PackLayout::row(NMAX);
   constexpr int NB = (NMAX + L - 1) / L;  // blocks of L jobs (both directions per job)
@@ -1963,7 +1988,10 @@ __device__ void lb2s_wave(const DevInst &I, int Ppad, const PackLds<NMAX, G> &S,
   const PackParent<NMAX> Q = S.parent(gl);  // this lane's parent
   int acc[NMAX];  // pair maxima per job: forward | backward << 16 (int16 halves)
 #pragma unroll
-  for (int q = 0; q < NMAX; ++q) acc[q] = (int)0x80008000u;
+  for (int q = 0; q < NMAX; ++q) {  // set once (not repeated on the path into the loop)
+    acc[q] = (int)0x80008000u;
+    asm volatile("" : "+v"(acc[q]));
+  }
   int *__restrict__ Xh = S.X + lane;
   for (int pc = 0; pc < nmax_sel; pc += L) {
     const int idx = pc + l;
@@ -1971,8 +1999,8 @@ __device__ void lb2s_wave(const DevInst &I, int Ppad, const PackLds<NMAX, G> &S,
     const int uvp = S.uv[pi];
     const int u = uvp & 0xff, v = uvp >> 8;
     const int K4 = Q.rr[v] + Q.c2[v], K5 = Q.c1[u] + Q.rr[v];
-    const int *Fu = (const int *)Q.fb + u * ROW;  // f_u in the low halves
-    const int *Gv = (const int *)Q.fb + v * ROW;  // g_v in the high halves
+    const int *Fu = lds_opaque((const int *)Q.fb + u * ROW);  // f_u in the low halves
+    const int *Gv = lds_opaque((const int *)Q.fb + v * ROW);  // g_v in the high halves
     const uint2 *__restrict__ eb = S.ent + (pi >> 6) * (NMAX * 64) + (pi & 63);
     int pm[NMAX], tm[NMAX];
     unsigned ke[NMAX];
@@ -2012,27 +2040,20 @@ __device__ void lb2s_wave(const DevInst &I, int Ppad, const PackLds<NMAX, G> &S,
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          if (g0 + j < NMAX) {
-            const int fg =
-                (int)__builtin_amdgcn_perm((unsigned)gw[j], (unsigned)fw[j], 0x07060100u);
-            acc[g0 + j] = pk_max(acc[g0 + j], pk_add(fg, h[j]));
-          }
+          if (g0 + j < NMAX)
+            h[j] = pk_add(
+                (int)__builtin_amdgcn_perm((unsigned)gw[j], (unsigned)fw[j], 0x07060100u), h[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (g0 + j < NMAX) acc[g0 + j] = pk_max(acc[g0 + j], h[j]);
         }
       }
     }
   }
   // fold over each group's lanes: job b * L + j of block b
   int t[NB];
-#pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    int blk[L];
-#pragma unroll
-    for (int j = 0; j < L; ++j) {
-      const int e = b * L + j;
-      blk[j] = e < NMAX ? acc[e < NMAX ? e : 0] : (int)0x80008000u;
-    }
-    t[b] = group_transpose_pkmax<L>(blk, lane);
-  }
+  group_blocks<0, L, NMAX, NB>(acc, t, tsrc, lane);
   // outputs and MinMin, per group: lane l of block b takes job b * L + l in
   // both directions
   int vmin = kInt32Max;
@@ -2142,6 +2163,7 @@ k_lb2s(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
   const int step = gridDim.x * nw * G;
   int it0 = (blockIdx.x * nw + w) * G;
   auto row_of = [&](int it) { return it < count ? (pool.index ? pool.index[it] : it) : -1; };
+  const GroupSrc<NMAX, 64 / G> tsrc(lane);
   int rows[G];
   PackFetch F[G];
 #pragma unroll
@@ -2159,7 +2181,7 @@ k_lb2s(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
       rows[g] = row_of(it0 + step + g);
       F[g] = pack_fetch(pool, rows[g], I.n, I.m, costs, lane);
     }
-    lb2s_wave<NMAX, G>(I, Ppad, S, pool, cur, C, ub, out_lb, out_prune, lane);
+    lb2s_wave<NMAX, G>(I, Ppad, S, pool, cur, C, ub, out_lb, out_prune, lane, tsrc);
   }
 }
 

@@ -225,21 +225,35 @@ __device__ __forceinline__ void tp_steps(int (&a)[NA], int lane) {
   }
 }
 
-// The job that lane l holds after tp_steps over NJ registers.
-template <int NJ>
+// The job that lane l holds after tp_steps<NJ, TOP> over NJ registers.
+template <int NJ, int TOP = 5>
 __host__ __device__ constexpr int tp_job(int l) {
-  int ns[6] = {};
+  int ns[TOP + 1] = {};
   int n = NJ;
-  for (int s = 0; s < 6; ++s) {
+  for (int s = 0; s <= TOP; ++s) {
     ns[s] = n;
     n = (n + 1) / 2;
   }
   int j = 0;
-  for (int s = 5; s >= 0; --s) {  // step s takes lane bit 5 - s
+  for (int s = TOP; s >= 0; --s) {  // step s takes lane bit TOP - s
     const int h = (ns[s] + 1) / 2;
-    if (j < ns[s] - h && ((l >> (5 - s)) & 1)) j += h;
+    if (j < ns[s] - h && ((l >> (TOP - s)) & 1)) j += h;
   }
   return j;
+}
+
+// For groups of L lanes (lane bits below log2 L only): the lane of this
+// lane's group that ends with job lane % L.
+template <int L, int NJ>
+__device__ __forceinline__ int tp_group_source(int lane) {
+  constexpr int TOP = L == 64 ? 5 : L == 32 ? 4 : L == 16 ? 3 : L == 8 ? 2 : L == 4 ? 1 : 0;
+  static_assert((1 << (TOP + 1)) == L && NJ <= L, "a power-of-two group of at most 64 lanes");
+  const int q = lane & (L - 1);
+  int src = 0;
+#pragma unroll
+  for (int l = L - 1; l >= 0; --l)
+    if (tp_job<NJ, TOP>(l) == q) src = l;
+  return (lane & ~(L - 1)) | src;
 }
 
 template <int NJ>

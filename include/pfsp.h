@@ -158,8 +158,8 @@ int pfsp_neh(pfsp_ctx *c, int32_t *perm_out, int32_t *cmax_out);
  * the float selector, 64 with the integer one),
  * "learned_exact" (1 = re-bound subset survivors with all pairs, default 0),
  * "timing" (1 = bracket every kernel launch with HIP events on the ctx
- * stream, default 0), "lb2_waves" (waves per block of the LB2 kernel, 0..12, 0 =
- * automatic), "lb2_blocks_per_cu" (cap on resident LB2 blocks per CU, 0 = 16),
+ * stream, default 0), "lb2_waves" (waves per block of the LB2 kernel, 0..16, 0 =
+ * automatic; larger values than a kernel's launch bounds allow are ignored), "lb2_blocks_per_cu" (cap on resident LB2 blocks per CU, 0 = 16),
  * "force_generic" (1 = always use the generic LB2 kernel),
  * "search_filter" (1 = LB2 search steps close every parent whose children
  * all have LB1 >= incumbent in the costs kernel and bound only the others
@@ -178,7 +178,7 @@ int pfsp_get_option(pfsp_ctx *c, const char *key, int64_t *value);
 
 /* Autotuner for the single-instance LB2 kernels: times pfsp_bound_children on
  * this pool (DEVICE buffers as there) for every candidate of options
- * "lb2_waves" (0,1,2,3,4,6,8,12) and "lb2_blocks_per_cu" (0,2,4,8,16,32), median
+ * "lb2_waves" (0,1,2,3,4,6,8,12,16) and "lb2_blocks_per_cu" (0,2,4,8,16,32), median
  * of reps runs each, sets the fastest pair on the context and writes a JSON
  * summary to report (HOST, report_len bytes).  Synchronous. */
 int pfsp_autotune(pfsp_ctx *c, const pfsp_pool *pool, int lb_kind, int32_t ub, int32_t *out_lb,
@@ -220,14 +220,15 @@ int pfsp_multi_bound(pfsp_multi *mt, int lb_kind, const uint8_t *perm, const uin
                      const uint8_t *d2, int32_t stride, const int64_t *seg_begin,
                      const int32_t *ub, int32_t *out_lb, uint8_t *out_prune, uint8_t *dir_out);
 
-/* Launch shape: parents per tile, waves per block of the n <= 20 class (0..12) and of the
+/* Launch shape: parents per tile, waves per block of the n <= 20 class (0..16; 16 only
+ * when all its instances allow 16-bit X, else at most 12) and of the
  * larger classes (0..8, at most 4 for the n > 64 wide class; 0 = most resident waves),
  * blocks per CU (0 = as many as fit). */
 int pfsp_multi_set_shape(pfsp_multi *mt, int32_t tile, int32_t waves_small, int32_t waves_large,
                          int32_t blocks_per_cu);
 
 /* Autotuner: runs pfsp_multi_bound's launch for every candidate shape (tile
- * 64..1024, waves 0/2/4/8/12, blocks per CU 0/2/4/8) on this batch, keeps the
+ * 64..1024, waves 0/2/4/8/12/16, blocks per CU 0/2/4/8) on this batch, keeps the
  * fastest (median of reps replays) and writes a JSON summary to report. */
 int pfsp_multi_autotune(pfsp_multi *mt, int lb_kind, const uint8_t *perm, const uint8_t *d1,
                         const uint8_t *d2, int32_t stride, const int64_t *seg_begin,

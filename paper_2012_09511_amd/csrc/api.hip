@@ -263,8 +263,8 @@ int pfsp_set_option(pfsp_ctx *h, const char *key, int64_t value) {
     return set_err(c, PFSP_ERANGE, "lb2_blocks_per_cu must be in [0, 64]");
   if (!strcmp(key, "subset_group") && value != 0 && value != 1 && value != 2 && value != 4)
     return set_err(c, PFSP_ERANGE, "subset_group must be 0, 1, 2 or 4");
-  if (!strcmp(key, "lb2_waves") && (value < 0 || value > 12))
-    return set_err(c, PFSP_ERANGE, "lb2_waves must be in [0, 12]");
+  if (!strcmp(key, "lb2_waves") && (value < 0 || value > 16))
+    return set_err(c, PFSP_ERANGE, "lb2_waves must be in [0, 16]");
   if (!strcmp(key, "learned_topk") && (value < 1 || value > 2016))
     return set_err(c, PFSP_ERANGE, "learned_topk must be in [1, 2016]");
   if ((!strcmp(key, "use_graph") || !strcmp(key, "learned_exact") || !strcmp(key, "timing") ||
@@ -307,7 +307,7 @@ int pfsp_autotune(pfsp_ctx *h, const pfsp_pool *pool, int lb_kind, int32_t ub, i
   };
   std::vector<Cand> res;
   int rc = PFSP_OK;
-  for (int w : {0, 1, 2, 3, 4, 6, 8, 12})
+  for (int w : {0, 1, 2, 3, 4, 6, 8, 12, 16})
     for (int g : {0, 2, 4, 8, 16, 32}) {
       c->lb2_waves = w;
       c->lb2_blocks_per_cu = g;

@@ -437,7 +437,8 @@ k_lb2(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__res
   extern __shared__ __align__(16) unsigned char sm[];
   using ET = typename E::T;
   const int n = I.n, m = I.m, P = I.P;
-  const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nw = blockDim.x >> 6, lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // uniform
   if ((int)blockIdx.x * nw >= (pool.count_dev ? *pool.count_dev : pool.count)) return;
   const ET *ent_g = (const ET *)(I.narrow ? (const void *)I.ent : (const void *)I.entw);
   size_t off = 0;
@@ -997,16 +998,16 @@ __device__ void lb2f_parent(const DevInst &I, int Ppad, const FastLds<NMAX> &S,
 // machines reversed), HTf/HTb [m] (head, tail + remaining work per machine
 // in scan order), C1, C2, R [m], and the inverse permutation inv [32].
 struct QuickLayout {
-  int ppad, mmax, x16;
+  int ppad, mmax, x16, subset;  // X16 needs one start-time table, subset bounds the sel list
   __host__ __device__ static constexpr int row(int nmax) { return nmax | 1; }
   __host__ __device__ size_t block_bytes(int nmax) const {
     return align16((size_t)nmax * ppad * 8) + align16((size_t)ppad * 4) +
            align16((size_t)2 * mmax * 32 * 4);
   }
   __host__ __device__ size_t wave_bytes(int nmax) const {
-    return align16((size_t)nmax * 64 * (x16 ? 4 : 8)) + align16((size_t)2 * mmax * row(nmax) * 4) +
-           align16((size_t)2 * mmax * 8) + align16((size_t)3 * mmax * 4) + align16(32 * 4) +
-           align16((size_t)ppad * 2);
+    return align16((size_t)nmax * 64 * (x16 ? 4 : 8)) +
+           align16((size_t)(x16 ? 1 : 2) * mmax * row(nmax) * 4) + align16((size_t)2 * mmax * 8) +
+           align16((size_t)3 * mmax * 4) + align16(32 * 4) + (subset ? align16((size_t)ppad * 2) : 0);
   }
 };
 
@@ -1032,8 +1033,8 @@ struct QuickLds {
     X = wb;
     wb += align16((size_t)NMAX * 64 * (L.x16 ? 4 : 8));
     FBf = (int *)wb;
-    FBb = FBf + L.mmax * ROW;
-    wb += align16((size_t)2 * L.mmax * ROW * 4);
+    FBb = FBf + (L.x16 ? 0 : L.mmax * ROW);  // X16: one table of int16 pairs
+    wb += align16((size_t)(L.x16 ? 1 : 2) * L.mmax * ROW * 4);
     HTf = (int2 *)wb;
     HTb = HTf + L.mmax;
     wb += align16((size_t)2 * L.mmax * 8);
@@ -1159,16 +1160,15 @@ __device__ void lb2q_parent(const DevInst &I, int Ppad, const QuickLds<NMAX> &S,
       (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)__ballot(member && !bwd));
   // LB1 of both children of job k, and the start times f (forward child,
   // machines in order) or g (backward child, machines reversed).  X16: one
-  // table of int16 pairs, f in the low half of [s][k] and g in the high half
-  // of [m - 1 - s][k] (by the machine's own index; both below 2^15)
+  // table of int16 pairs in scan order, f of machine s in the low half of
+  // [s][k] and g of machine m - 1 - s in the high half (both below 2^15), so
+  // that both directions write with one constant stride
   int lb1 = 0;
   if (k < NMAX) {
     const int2 *HT = bwd ? S.HTb : S.HTf;
     const int *PT = (bwd ? S.pr : S.pt) + k;
     int *FB = (bwd ? S.FBb : S.FBf) + k;
-    unsigned short *fb16 =
-        (unsigned short *)S.FBf + 2 * k + (bwd ? 1 + 2 * (m - 1) * ROW : 0);
-    const int fstep = bwd ? -2 * ROW : 2 * ROW;
+    unsigned short *fb16 = (unsigned short *)S.FBf + 2 * k + (bwd ? 1 : 0);
     int c = 0;
 #pragma unroll 4
     for (int s = 0; s < m; ++s) {
@@ -1176,7 +1176,7 @@ __device__ void lb2q_parent(const DevInst &I, int Ppad, const QuickLds<NMAX> &S,
       const int f = max(c, ht.x);
       c = f + PT[s * 32];
       if constexpr (X16)
-        fb16[s * fstep] = (unsigned short)f;
+        fb16[s * 2 * ROW] = (unsigned short)f;
       else
         FB[s * ROW] = f;
       lb1 = max(lb1, f + ht.y);
@@ -1222,41 +1222,58 @@ __device__ void lb2q_parent(const DevInst &I, int Ppad, const QuickLds<NMAX> &S,
     const int u = uvp & 0xff, v = uvp >> 8;
     const int K4 = S.rr[v] + S.c2[v], K5 = S.c1[u] + S.rr[v];
     const int *Fu = lds_opaque(S.FBf + u * ROW);
-    const int *Gv = lds_opaque(X16 ? S.FBf + v * ROW : S.FBb + (m - 1 - v) * ROW);
+    const int *Gv = lds_opaque((X16 ? S.FBf : S.FBb) + (m - 1 - v) * ROW);
     const uint2 *__restrict__ eb = S.ent + (pi >> 6) * (NMAX * 64) + (pi & 63);
-    // forward scan: terms of members (NEG for the others) and exclusive prefix maxima
-    int pm[NMAX], tm[NMAX];
-    unsigned ke[X16 ? NMAX : 1];  // X16: E in bits 0-15, job << 24 (bits 16-23 zero)
+    // forward scan: terms of members (NEG for the others) and exclusive prefix
+    // maxima.  X16 keeps per position one int16 pair, the prefix maximum less
+    // b - a (low) and the term (high), and E | job << 24
+    constexpr int NS = X16 ? 1 : NMAX, NP = X16 ? NMAX : 1;
+    int pm[NS], tm[NS], pt[NP];
+    unsigned ke[NP];
     int Y = X16 ? K4 : 0, Pm = NEGX;
 #pragma unroll
     for (int i = 0; i < NMAX; ++i) {
       const uint2 e = eb[i * 64];
       const int ng = __builtin_amdgcn_sbfe((int)umask, (int)e.y, 1);  // -1 if member
       const int tt = Y + (int)(e.y >> 16);
-      tm[i] = (tt & ng) | (NEGX & ~ng);
-      pm[i] = Pm;
-      Pm = max(Pm, tm[i]);
+      const int term = (tt & ng) | (NEGX & ~ng);
+      if constexpr (X16) {
+        pt[i] = (int)__builtin_amdgcn_perm((unsigned)term, (unsigned)(Pm - (int)e.x), 0x05040100u);
+        ke[i] = __builtin_amdgcn_perm(e.y, e.x, 0x040c0100u);
+      } else {
+        tm[i] = term;
+        pm[i] = Pm;
+      }
+      Pm = max(Pm, term);
       Y = __mul24(ng, (int)e.x) + Y;  // Y += a - b for members
-      if constexpr (X16) ke[i] = __builtin_amdgcn_perm(e.y, e.x, 0x040c0100u);
     }
     // backward scan: Xa, Xb by job (the 32-bit entries are read again rather
     // than held in registers; X16 keeps a packed copy from the forward scan)
-    int Sm = NEGX;
     const int K5x = K5 - K4;  // X16: the high half is Xb + K5 (K4 is already inside)
+    if constexpr (X16) {
+      // one packed maximum per position: against the suffix maximum Sm of the
+      // terms after it (held in both halves) the low half becomes Xa and the
+      // high half the suffix maximum that includes this term.  Xa - b + a
+      // fits int16 wherever the value is used (a member with another member
+      // left), and Xb + K5 = Xa + E + K5x in the high half of the stored word
+      // needs only the low 16 bits of each addend
+      int R = (int)0xC000C000u;  // NEGX in both halves
 #pragma unroll
-    for (int i = NMAX - 1; i >= 0; --i) {
-      if constexpr (X16) {
-        const int E = (int)(short)(ke[i] & 0xffffu);
-        const int xa = max(pm[i] - E, Sm);
-        *(int *)((char *)Xh + (ke[i] >> 16)) =
-            (int)__builtin_amdgcn_perm((unsigned)(xa + E + K5x), (unsigned)xa, 0x05040100u);
-      } else {
+      for (int i = NMAX - 1; i >= 0; --i) {
+        R = pk_max_hi(pt[i], R);
+        *(int *)((char *)Xh + (ke[i] >> 16)) = (int)__builtin_amdgcn_perm(
+            (unsigned)(R + (int)ke[i] + K5x), (unsigned)R, 0x05040100u);
+      }
+    } else {
+      int Sm = NEGX;
+#pragma unroll
+      for (int i = NMAX - 1; i >= 0; --i) {
         const uint2 e = eb[i * 64];
         const int E = (int)e.x;
         const int xa = max(pm[i] - E, Sm);
         Xl[(e.y & 31u) * 64] = make_int2(xa, xa + E);
+        Sm = max(Sm, tm[i]);
       }
-      Sm = max(Sm, tm[i]);
     }
     // children, four jobs at a time so that their loads are issued together
     // (each lane reads back only its own column of X; jobs that are not
@@ -1329,11 +1346,17 @@ __device__ void lb2q_parent(const DevInst &I, int Ppad, const QuickLds<NMAX> &S,
     const uint64_t at = __ballot(member && val == cmn);
     const int cf = __popc((uint32_t)at), cb = __popc((uint32_t)(at >> 32));
     const int sv = member ? val : 0;
-    const int slo = half_sum(sv & 0xffff), shi = half_sum(sv >> 16);
-    const long long sf = ((long long)__builtin_amdgcn_readlane(shi, 0) << 16) +
-                         __builtin_amdgcn_readlane(slo, 0);
-    const long long sb = ((long long)__builtin_amdgcn_readlane(shi, 32) << 16) +
-                         __builtin_amdgcn_readlane(slo, 32);
+    long long sf, sb;
+    if constexpr (X16) {  // bounds below 2^15: the 32 of a half sum below 2^20
+      const int s = half_sum(sv);
+      sf = __builtin_amdgcn_readlane(s, 0);
+      sb = __builtin_amdgcn_readlane(s, 32);
+    } else {
+      const int slo = half_sum(sv & 0xffff), shi = half_sum(sv >> 16);
+      sf = ((long long)__builtin_amdgcn_readlane(shi, 0) << 16) + __builtin_amdgcn_readlane(slo, 0);
+      sb = ((long long)__builtin_amdgcn_readlane(shi, 32) << 16) +
+           __builtin_amdgcn_readlane(slo, 32);
+    }
     MinMin mm;
     mm.init();
     mm.merge(cmn, cf, cb, sf, sb);
@@ -1342,17 +1365,21 @@ __device__ void lb2q_parent(const DevInst &I, int Ppad, const QuickLds<NMAX> &S,
   wave_sync();  // the next parent rewrites this wave's tables
 }
 
-// Up to 12 waves per block (three per SIMD, which the register use of up to
-// 24 jobs allows); 8 for 32 jobs, whose registers need two per SIMD.
+// Up to 16 waves per block (four per SIMD, which the registers of up to 20
+// jobs with 16-bit X allow), else 12 (three per SIMD, up to 24 jobs); 8 for
+// 32 jobs, whose registers need two per SIMD.
 template <int NMAX, bool SUBSET, bool X16>
-__global__ void __launch_bounds__(NMAX <= 24 ? 768 : 512)
+__global__ void __launch_bounds__(X16 && NMAX <= 20 ? 1024 : NMAX <= 24 ? 768 : 512)
 k_lb2q(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__restrict__ out_lb,
        uint8_t *__restrict__ out_prune, int Ppad) {
   extern __shared__ __align__(16) unsigned char sm[];
-  const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nw = blockDim.x >> 6, lane = threadIdx.x & 63;
+  // the wave index as a uniform value: parent indices, and the loads of their
+  // depths and pool rows, stay scalar
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int count = pool.count_dev ? *pool.count_dev : pool.count;
   if ((int)blockIdx.x * nw >= count) return;  // no parent for this block: skip the staging
-  const QuickLayout L{Ppad, I.m, X16};
+  const QuickLayout L{Ppad, I.m, X16, SUBSET};
   const QuickLds<NMAX> S(sm, L, w);
   lb2q_stage<NMAX>(I, Ppad, S);
   __syncthreads();
@@ -1480,7 +1507,7 @@ __device__ __forceinline__ void lb2w_chunk(const uint2 *__restrict__ ec, int rem
                                            const uint64_t (&um)[NW], int n, int K5x, int Y,
                                            int Pm, int &Sm, int *__restrict__ Xh) {
   constexpr int NEGX = -(1 << 14);
-  int pm[CH], tm[CH];
+  int pt[CH];       // (prefix maximum - E) | term << 16, int16 halves (as in the quick kernel)
   unsigned ke[CH];  // E in bits 0-15, job << 24: (ke >> 16) is the byte offset of its row of X
   uint2 ev[CH];
 #pragma unroll
@@ -1493,20 +1520,22 @@ __device__ __forceinline__ void lb2w_chunk(const uint2 *__restrict__ ec, int rem
     int ng = member_ng<NW>(um, e.y);
     if (RAGGED) ng &= in ? -1 : 0;
     const int tt = Y + (int)(e.y >> 16);
-    tm[i] = (tt & ng) | (NEGX & ~ng);
-    pm[i] = Pm;
-    Pm = max(Pm, tm[i]);
+    const int term = (tt & ng) | (NEGX & ~ng);
+    pt[i] = (int)__builtin_amdgcn_perm((unsigned)term, (unsigned)(Pm - (int)e.x), 0x05040100u);
+    Pm = max(Pm, term);
     Y = __mul24(ng, (int)e.x) + Y;
     ke[i] = __builtin_amdgcn_perm(in ? e.y : (unsigned)n, e.x, 0x040c0100u);
   }
+  // the suffix maximum in both halves; each step leaves Xa low and the
+  // suffix maximum with this term high
+  int R = (int)__builtin_amdgcn_perm((unsigned)Sm, (unsigned)Sm, 0x05040100u);
 #pragma unroll
   for (int i = CH - 1; i >= 0; --i) {
-    const int E = (int)(short)(ke[i] & 0xffffu);
-    const int xa = max(pm[i] - E, Sm);
+    R = pk_max_hi(pt[i], R);
     *(int *)((char *)Xh + (ke[i] >> 16)) =
-        (int)__builtin_amdgcn_perm((unsigned)(xa + E + K5x), (unsigned)xa, 0x05040100u);
-    Sm = max(Sm, tm[i]);
+        (int)__builtin_amdgcn_perm((unsigned)(R + (int)ke[i] + K5x), (unsigned)R, 0x05040100u);
   }
+  Sm = R >> 16;
 }
 
 template <int NMAX>
@@ -1707,7 +1736,8 @@ __global__ void __launch_bounds__(NMAX >= 128 ? 256 : 512)
 k_lb2w(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__restrict__ out_lb,
        uint8_t *__restrict__ out_prune, int Ppad) {
   extern __shared__ __align__(16) unsigned char sm[];
-  const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nw = blockDim.x >> 6, lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // uniform
   const int count = pool.count_dev ? *pool.count_dev : pool.count;
   if ((int)blockIdx.x * nw >= count) return;  // no parent for this block: skip the staging
   const WideLayout L{Ppad, I.n, I.m};
@@ -1940,17 +1970,16 @@ __device__ void lb2s_wave(const DevInst &I, int Ppad, const PackLds<NMAX, G> &S,
     if (k < NMAX) {
       const int2 *HT = bwd ? Q.htb : Q.htf;
       const int *PT = (bwd ? S.pr : S.pt) + k;
-      // f into the low half of [s][k] (forward, machine s), g into the high
-      // half of [m-1-s][k] (backward steps run over reversed machines)
-      unsigned short *fb = (unsigned short *)Q.fb + 2 * k + (bwd ? 1 + 2 * (m - 1) * ROW : 0);
-      const int fstep = bwd ? -2 * ROW : 2 * ROW;
+      // in scan order: f of machine s into the low half of [s][k], g of
+      // machine m - 1 - s into the high half (one constant stride)
+      unsigned short *fb = (unsigned short *)Q.fb + 2 * k + (bwd ? 1 : 0);
       int c = 0;
 #pragma unroll 4
       for (int s = 0; s < m; ++s) {
         const int2 ht = HT[s];
         const int f = max(c, ht.x);
         c = f + PT[s * 32];
-        fb[s * fstep] = (unsigned short)f;
+        fb[s * 2 * ROW] = (unsigned short)f;
         lb1 = max(lb1, f + ht.y);
       }
     }
@@ -2000,9 +2029,12 @@ __device__ void lb2s_wave(const DevInst &I, int Ppad, const PackLds<NMAX, G> &S,
     const int u = uvp & 0xff, v = uvp >> 8;
     const int K4 = Q.rr[v] + Q.c2[v], K5 = Q.c1[u] + Q.rr[v];
     const int *Fu = lds_opaque((const int *)Q.fb + u * ROW);  // f_u in the low halves
-    const int *Gv = lds_opaque((const int *)Q.fb + v * ROW);  // g_v in the high halves
+    const int *Gv = lds_opaque((const int *)Q.fb + (m - 1 - v) * ROW);  // g_v, high halves
     const uint2 *__restrict__ eb = S.ent + (pi >> 6) * (NMAX * 64) + (pi & 63);
-    int pm[NMAX], tm[NMAX];
+    // the scans of the quick kernel with 16-bit X: per position the pair
+    // (prefix maximum - E, term) and E | job << 24, then one packed maximum
+    // per position against the suffix maximum
+    int pt[NMAX];
     unsigned ke[NMAX];
     int Y = K4, Pm = NEGX;
 #pragma unroll
@@ -2010,21 +2042,19 @@ __device__ void lb2s_wave(const DevInst &I, int Ppad, const PackLds<NMAX, G> &S,
       const uint2 e = eb[i * 64];
       const int ng = __builtin_amdgcn_sbfe((int)umask, (int)e.y, 1);
       const int tt = Y + (int)(e.y >> 16);
-      tm[i] = (tt & ng) | (NEGX & ~ng);
-      pm[i] = Pm;
-      Pm = max(Pm, tm[i]);
+      const int term = (tt & ng) | (NEGX & ~ng);
+      pt[i] = (int)__builtin_amdgcn_perm((unsigned)term, (unsigned)(Pm - (int)e.x), 0x05040100u);
+      Pm = max(Pm, term);
       Y = __mul24(ng, (int)e.x) + Y;
       ke[i] = __builtin_amdgcn_perm(e.y, e.x, 0x040c0100u);
     }
-    int Sm = NEGX;
     const int K5x = K5 - K4;
+    int R = (int)0xC000C000u;  // NEGX in both halves
 #pragma unroll
     for (int i = NMAX - 1; i >= 0; --i) {
-      const int E = (int)(short)(ke[i] & 0xffffu);
-      const int xa = max(pm[i] - E, Sm);
+      R = pk_max_hi(pt[i], R);
       *(int *)((char *)Xh + (ke[i] >> 16)) =
-          (int)__builtin_amdgcn_perm((unsigned)(xa + E + K5x), (unsigned)xa, 0x05040100u);
-      Sm = max(Sm, tm[i]);
+          (int)__builtin_amdgcn_perm((unsigned)(R + (int)ke[i] + K5x), (unsigned)R, 0x05040100u);
     }
 #pragma unroll
     for (int g0 = 0; g0 < NMAX; g0 += 4) {
@@ -2152,7 +2182,10 @@ __global__ void __launch_bounds__(G == 2 && NMAX <= 20 ? 768 : 512)
 k_lb2s(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__restrict__ out_lb,
        uint8_t *__restrict__ out_prune, int Ppad) {
   extern __shared__ __align__(16) unsigned char sm[];
-  const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nw = blockDim.x >> 6, lane = threadIdx.x & 63;
+  // the wave index as a uniform value: parent indices, and the loads of their
+  // depths and pool rows, stay scalar
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int count = pool.count_dev ? *pool.count_dev : pool.count;
   if ((int)blockIdx.x * nw * G >= count) return;  // no parent for this block
   const PackLayout L{Ppad, I.m};
@@ -2192,7 +2225,8 @@ __global__ void __launch_bounds__(512)
 k_lb2f(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__restrict__ out_lb,
        uint8_t *__restrict__ out_prune, int Ppad) {
   extern __shared__ __align__(16) unsigned char sm[];
-  const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nw = blockDim.x >> 6, lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // uniform
   const int count = pool.count_dev ? *pool.count_dev : pool.count;
   if ((int)blockIdx.x * nw >= count) return;  // no parent for this block
   const FastLayout L{Ppad, I.n, I.m};
@@ -2217,7 +2251,7 @@ k_lb2f(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
 template <int NMAX, bool X16>
 __device__ __forceinline__ auto make_lds(unsigned char *sm, const FastLayout &L, int w) {
   if constexpr (NMAX <= 32)
-    return QuickLds<NMAX>(sm, QuickLayout{L.ppad, L.mmax, X16}, w);
+    return QuickLds<NMAX>(sm, QuickLayout{L.ppad, L.mmax, X16, 0}, w);
   else
     return FastLds<NMAX>(sm, L, w);
 }
@@ -2229,7 +2263,7 @@ __device__ __forceinline__ auto make_lds(unsigned char *sm, const FastLayout &L,
 // and outputs use a common stride (the largest n); costs rows hold cstride
 // ints.
 template <int NMAX, bool X16>
-__global__ void __launch_bounds__(NMAX <= 32 ? 768 : 512)
+__global__ void __launch_bounds__(X16 && NMAX <= 20 ? 1024 : NMAX <= 32 ? 768 : 512)
 k_lb2m(const DevInst *__restrict__ insts, const MultiTile *__restrict__ tiles, int ntiles,
        int *__restrict__ queue, FastLayout L, const uint8_t *__restrict__ perm,
        const uint8_t *__restrict__ d1, const uint8_t *__restrict__ d2, int stride,
@@ -2239,7 +2273,8 @@ k_lb2m(const DevInst *__restrict__ insts, const MultiTile *__restrict__ tiles, i
   __shared__ int s_tile;
   constexpr bool QUICK = NMAX <= 32;
   using Lds = typename std::conditional<QUICK, QuickLds<NMAX>, FastLds<NMAX>>::type;
-  const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nw = blockDim.x >> 6, lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // uniform
   const Lds S = make_lds<NMAX, X16>(sm, L, w);
   const int tsrc = tp_source<QUICK ? NMAX : 32>(lane);
   int cur = -1, Ppad = 0;
@@ -2292,7 +2327,8 @@ k_lb2mw(const DevInst *__restrict__ insts, const MultiTile *__restrict__ tiles, 
         int *__restrict__ out_lb, uint8_t *__restrict__ out_prune, uint8_t *__restrict__ dir) {
   extern __shared__ __align__(16) unsigned char sm[];
   __shared__ int s_tile;
-  const int nw = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nw = blockDim.x >> 6, lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // uniform
   const WideLds<NMAX> S(sm, L, w);
   int cur = -1, Ppad = 0;
   DevInst I{};
@@ -2320,12 +2356,20 @@ k_lb2mw(const DevInst *__restrict__ insts, const MultiTile *__restrict__ tiles, 
   }
 }
 
+// Waves per block that the single-instance kernels' launch bounds allow:
+// with 16-bit X, up to 20 jobs fit 128 registers, four waves per SIMD.
+static int quick_wmax(int nmax, int x16, bool log) {
+  if (log) return 8;
+  if (x16 && nmax <= 20) return 16;
+  return nmax <= 24 ? 12 : 8;
+}
+
 // LDS of the single-instance fast kernels: the quick layout for n <= 32
 // without argmax logging, the scan layout otherwise.
-static size_t lb2f_lds(const Ctx *c, int nmax, int waves, bool log) {
+static size_t lb2f_lds(const Ctx *c, int nmax, int waves, bool log, bool subset) {
   const int ppad = (c->P + 63) / 64 * 64;
   if (nmax <= 32 && !log) {
-    const QuickLayout L{ppad, c->m, c->x16};
+    const QuickLayout L{ppad, c->m, c->x16, subset ? 1 : 0};
     return L.block_bytes(nmax) + (size_t)waves * L.wave_bytes(nmax);
   }
   const FastLayout L{ppad, c->n, c->m};
@@ -2483,7 +2527,7 @@ size_t lb2m_lds_bytes(int nmax, int ppad, int nmax_jobs, int mmax, int waves, in
     return L.block_bytes(nmax) + (size_t)waves * L.wave_bytes(nmax);
   }
   if (nmax <= 32) {
-    const QuickLayout L{ppad, mmax, x16};
+    const QuickLayout L{ppad, mmax, x16, 0};
     return L.block_bytes(nmax) + (size_t)waves * L.wave_bytes(nmax);
   }
   const FastLayout L{ppad, nmax_jobs, mmax};
@@ -2743,9 +2787,9 @@ int launch_bound_costs_ready(Ctx *c, const DevPool &pool, int kind, int ub, int 
   if (nmax) {
     // waves per block: the most resident waves per CU within 160 KiB of LDS
     int waves = 0, best = 0;
-    const int wmax = nmax <= 24 && !log ? 12 : 8;  // the kernels' launch bounds
+    const int wmax = quick_wmax(nmax, c->x16, log);  // the kernels' launch bounds
     for (int w = wmax; w >= 1; --w) {
-      const size_t l = lb2f_lds(c, nmax, w, log);
+      const size_t l = lb2f_lds(c, nmax, w, log, subset);
       const int per_cu = l <= 160 * 1024 ? (int)((160 * 1024) / l) * w : 0;
       if (per_cu > best) {
         best = per_cu;
@@ -2753,9 +2797,9 @@ int launch_bound_costs_ready(Ctx *c, const DevPool &pool, int kind, int ub, int 
       }
     }
     if (c->lb2_waves > 0 && c->lb2_waves <= wmax &&
-        lb2f_lds(c, nmax, (int)c->lb2_waves, log) <= 160 * 1024)
+        lb2f_lds(c, nmax, (int)c->lb2_waves, log, subset) <= 160 * 1024)
       waves = (int)c->lb2_waves;
-    const size_t lds = waves ? lb2f_lds(c, nmax, waves, log) : 0;
+    const size_t lds = waves ? lb2f_lds(c, nmax, waves, log, subset) : 0;
     if (waves) {
       const int Ppad = (c->P + 63) / 64 * 64;
       int grid = (pool.count + waves - 1) / waves;

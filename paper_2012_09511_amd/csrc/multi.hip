@@ -103,10 +103,11 @@ constexpr int kNumCls = 4;
 static const int kClassNmax[kNumCls] = {20, 64, 64, 128};
 static const int kClassWide[kNumCls] = {0, 0, 1, 1};
 
-// waves per block that the class kernel's launch bounds allow
-static int max_waves(int cls) {
+// waves per block that the class kernel's launch bounds allow (the quick
+// class with 16-bit X: four per SIMD)
+static int max_waves(int cls, int x16) {
   static const int w[kNumCls] = {12, 8, 8, 4};
-  return w[cls];
+  return cls == 0 && x16 ? 16 : w[cls];
 }
 
 // Class layout: the largest padded pair count, job count and machine count
@@ -127,7 +128,7 @@ static void class_layout(const pfsp_multi *mt, int cls, int &ppad, int &nj, int 
 
 static int auto_waves(int cls, int ppad, int nj, int mm, int x16) {
   int waves = 1, best = 0;
-  for (int w = max_waves(cls); w >= 1; --w) {
+  for (int w = max_waves(cls, x16); w >= 1; --w) {
     const size_t l = lb2m_lds_bytes(kClassNmax[cls], ppad, nj, mm, w, x16, kClassWide[cls]);
     const int per_cu = l <= kLdsM ? (int)((kLdsM) / l) * w : 0;
     if (per_cu > best) {
@@ -196,7 +197,7 @@ static int multi_enqueue(pfsp_multi *mt, int kind, const uint8_t *perm, const ui
     L.queue = mt->d_queue + cls;
     L.cstride = 3 * mt->mmax;  // k_lb1m's row stride, not the class's
     const int pref = mt->waves[cls == 0 ? 0 : 1];  // small: the quick class; large: the rest
-    L.waves = pref > 0 ? std::min(pref, max_waves(cls))
+    L.waves = pref > 0 ? std::min(pref, max_waves(cls, L.x16))
                        : auto_waves(cls, L.ppad, L.nmax_jobs, L.mmax, L.x16);
     while (L.waves > 1 && lb2m_lds_bytes(L.nmax, L.ppad, L.nmax_jobs, L.mmax, L.waves, L.x16,
                                          L.wide) > kLdsM)
@@ -439,7 +440,7 @@ int pfsp_multi_set_shape(pfsp_multi *mt, int32_t tile, int32_t waves_small, int3
                          int32_t blocks_per_cu) {
   if (!mt) return PFSP_EINVAL;
   Ctx *c = mt->c;
-  if (tile < 1 || tile > (1 << 20) || waves_small < 0 || waves_small > 12 || waves_large < 0 ||
+  if (tile < 1 || tile > (1 << 20) || waves_small < 0 || waves_small > 16 || waves_large < 0 ||
       waves_large > 8 || blocks_per_cu < 0 || blocks_per_cu > 64)
     return set_err(c, PFSP_ERANGE, "shape out of range");
   mt->tile = tile;
@@ -464,7 +465,7 @@ int pfsp_multi_autotune(pfsp_multi *mt, int lb_kind, const uint8_t *perm, const 
   if (reps < 1) reps = 3;
   PFSP_HIP(c, hipSetDevice(c->device));
   const int tiles[] = {64, 128, 256, 512, 1024};
-  const int wv[] = {0, 2, 4, 8, 12};
+  const int wv[] = {0, 2, 4, 8, 12, 16};
   const int gpc[] = {0, 2, 4, 8};
   struct Cand {
     int tile, w, g;

@@ -153,6 +153,13 @@ __device__ __forceinline__ int pk_max(int x, int y) {
       int, __builtin_elementwise_max(__builtin_bit_cast(pk16, x), __builtin_bit_cast(pk16, y)));
 }
 
+// pk_max with both halves of y replaced by its high half (an operand
+// selection of the instruction, not a separate move).
+__device__ __forceinline__ int pk_max_hi(int x, int y) {
+  const pk16 b = __builtin_bit_cast(pk16, y);
+  return __builtin_bit_cast(int, __builtin_elementwise_max(__builtin_bit_cast(pk16, x), b.yy));
+}
+
 // Transposing max-reduction of 32 per-job values held as int16 pairs
 // (forward child low, backward child high), acc[OFF .. OFF + 32): on return
 // lane q < 32 holds the maximum over all lanes of the low half of job q and

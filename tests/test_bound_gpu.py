@@ -338,6 +338,31 @@ def test_generic_kernel_parity(ctx, n, m):
         ctx.set_option("force_generic", 0)
 
 
+@pytest.mark.parametrize("n,m,hi", [(20, 20, 99), (20, 20, 1500), (16, 10, 99), (8, 3, 99)])
+def test_quick_kernel_block_shapes(ctx, n, m, hi):
+    """Waves per block of the n <= 32 kernel from one to sixteen (four per
+    SIMD with 16-bit X, a request above a kernel's launch bounds falls back to
+    the automatic shape), full and subset bounds, on a pool whose size is not
+    a multiple of any block."""
+    rng = np.random.default_rng(n * 100 + m + hi)
+    p = rng.integers(1, hi + 1, size=(n, m)).astype(np.int32)
+    perm, d1, d2 = inputs.random_pool(n, 397, 41 + n)
+    P = m * (m - 1) // 2
+    mask = rng.integers(0, 1 << 32, size=(len(perm), (P + 31) // 32), dtype=np.uint64)
+    mask = mask.astype(np.uint32)
+    ctx.set_option("subset_group", 1)  # subset bounds through the same kernel
+    try:
+        for waves in (1, 4, 12, 16):
+            ctx.set_option("lb2_waves", waves)
+            olb = _check(ctx, p, perm, d1, d2, binding.LB2_FULL, INT32_MAX)
+            _check(ctx, p, perm, d1, d2, binding.LB2_FULL,
+                   int(np.median(olb[olb < INT32_MAX])))
+            _check(ctx, p, perm, d1, d2, binding.LB2_SUBSET, INT32_MAX, mask=mask)
+    finally:
+        ctx.set_option("lb2_waves", 0)
+        ctx.set_option("subset_group", 0)
+
+
 def test_autotune_keeps_results(ctx):
     """The autotuner only changes launch shapes: results stay bit-exact."""
     import torch

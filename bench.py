@@ -115,6 +115,8 @@ def main():
     ap.add_argument("--parents", type=int, default=1 << 20)
     ap.add_argument("--kind", default="LB2_FULL", choices=["LB1", "LB2_FULL"])
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the fixed-depth sweep (profiles of the headline launch alone)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--workload", default="bound", choices=["bound", "search", "multi", "learned"])
@@ -208,7 +210,7 @@ def main():
                kernels_ms={k: v for k, v in (("k_costs", ms_costs / max(lc, 1)),
                                              ("k_lb1", ms_lb1 / max(l1, 1)), (dom, dom_ms))
                            if v > 0})
-    if kind != binding.LB1:
+    if kind != binding.LB1 and not args.no_sweep:
         out["depth_sweep"] = depth_sweep(ctx, torch, binding, inputs, n, m, ub)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, perm, d1, d2, kind)

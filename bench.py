@@ -128,6 +128,9 @@ def main():
     ap.add_argument("--float-selector", action="store_true",
                     help="learned workload: rank pairs with the float model instead of its "
                          "int8 form")
+    ap.add_argument("--pool-batch", type=int, default=0,
+                    help="learned workload: nodes popped per search step (0 = 262144, the "
+                         "fastest of 2^16 .. 2^20 for both the full and the learned search)")
     ap.add_argument("--no-graph", action="store_true",
                     help="search steps as plain launches (profilers see graph replays as one)")
     args = ap.parse_args()
@@ -375,6 +378,7 @@ def bench_learned(args):
     params = np.load(args.selector, allow_pickle=False)
     ctx.selector_set(params)
     ctx.set_option("learned_topk", args.topk)
+    ctx.set_option("pool_batch", args.pool_batch or 1 << 18)
     if args.no_graph:
         ctx.set_option("use_graph", 0)
     rows = []
@@ -410,6 +414,7 @@ def bench_learned(args):
                ms_per_step=tl * 1e3, higher_is_better=True, scaling="weak", vs_baseline=None,
                dtype="int32", data="synthetic",
                config=dict(workload="depth-first B&B, n=20 x m=20, seeds 600..607, NEH+1, "
+                                    f"{ctx.get_option('pool_batch')} nodes per step, "
                                     f"learned top-{args.topk} of 190 pairs, "
                                     + ("float" if args.float_selector else "int8") + " selector "
                                     + os.path.basename(args.selector)),

@@ -338,7 +338,8 @@ def test_generic_kernel_parity(ctx, n, m):
         ctx.set_option("force_generic", 0)
 
 
-@pytest.mark.parametrize("n,m,hi", [(20, 20, 99), (20, 20, 1500), (16, 10, 99), (8, 3, 99)])
+@pytest.mark.parametrize("n,m,hi", [(20, 20, 99), (20, 20, 1500), (16, 10, 99), (8, 3, 99),
+                                    (24, 9, 99), (22, 15, 99), (27, 6, 99)])
 def test_quick_kernel_block_shapes(ctx, n, m, hi):
     """Waves per block of the n <= 32 kernel from one to sixteen (four per
     SIMD with 16-bit X, a request above a kernel's launch bounds falls back to

@@ -243,9 +243,9 @@ k_scan_top(SearchCtl *__restrict__ c, int *__restrict__ bsum, long long cap) {
 
 // One wave per parent: the prune flags and bounds of 64 children are read at
 // once, the survivors of the chosen direction ranked by a ballot (leftmost
-// child on top of the stack), their indices put in LDS; then each survivor's
-// record is written with consecutive lanes on consecutive bytes.  The step's
-// best leaf is stored too.
+// child on top of the stack), their indices put in LDS; then the survivors'
+// records are written floor(64 / n) at a time, each by n consecutive lanes on
+// consecutive bytes.  The step's best leaf is stored too.
 __global__ void __launch_bounds__(256)
 k_push(SearchCtl *__restrict__ c, int n, const uint8_t *__restrict__ b_perm,
        const uint8_t *__restrict__ b_d1, const uint8_t *__restrict__ b_d2,
@@ -261,6 +261,10 @@ k_push(SearchCtl *__restrict__ c, int n, const uint8_t *__restrict__ b_perm,
   int *const rank_q = sq[threadIdx.x >> 6];
   const int waves = (gridDim.x * blockDim.x) >> 6;
   const unsigned long long sb = c->step_best;
+  // record writers: G groups of n lanes (n <= 64), else the whole wave
+  const int G = n <= 64 ? 64 / n : 1;
+  const int gi = n <= 64 ? lane / n : 0, xl = n <= 64 ? lane - gi * n : lane;
+  const int xstep = n <= 64 ? n : 64;
   for (int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < count; i += waves) {
     const uint8_t *row = b_perm + (size_t)i * n;
     if (sb != ~0ull && (int)(sb & 0xffffffffu) == i) {
@@ -287,27 +291,31 @@ k_push(SearchCtl *__restrict__ c, int n, const uint8_t *__restrict__ b_perm,
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       const int nl = __popcll(bal);
-      for (int tt = 0; tt < nl; ++tt) {
-        const int q = rank_q[tt];
+      for (int t0 = 0; t0 < nl; t0 += G) {
+        const int tt = t0 + gi;
+        const bool act = gi < G && tt < nl;
+        const int q = rank_q[act ? tt : t0];
         const int lq = __shfl(lbv, q - q0, 64);
-        const long long pos = dst + (s - 1 - (done + tt));
-        uint8_t *out = s_perm + pos * n;
-        const int j = row[a + q];
-        for (int x = lane; x < n; x += 64) {
-          int v;
-          if (x < a || x >= a + r) {
-            v = row[x];
-          } else if (dir == 0) {  // sigma1 j | U \ j | sigma2
-            v = x == a ? j : (x <= a + q ? row[x - 1] : row[x]);
-          } else {  // sigma1 | U \ j | j sigma2
-            v = x == a + r - 1 ? j : (x < a + q ? row[x] : row[x + 1]);
+        if (act) {
+          const long long pos = dst + (s - 1 - (done + tt));
+          uint8_t *out = s_perm + pos * n;
+          const int j = row[a + q];
+          for (int x = xl; x < n; x += xstep) {
+            int v;
+            if (x < a || x >= a + r) {
+              v = row[x];
+            } else if (dir == 0) {  // sigma1 j | U \ j | sigma2
+              v = x == a ? j : (x <= a + q ? row[x - 1] : row[x]);
+            } else {  // sigma1 | U \ j | j sigma2
+              v = x == a + r - 1 ? j : (x < a + q ? row[x] : row[x + 1]);
+            }
+            out[x] = (uint8_t)v;
           }
-          out[x] = (uint8_t)v;
-        }
-        if (lane == 0) {
-          s_d1[pos] = (uint8_t)(a + (dir == 0));
-          s_d2[pos] = (uint8_t)(b + (dir == 1));
-          s_lb[pos] = lq;
+          if (xl == 0) {
+            s_d1[pos] = (uint8_t)(a + (dir == 0));
+            s_d2[pos] = (uint8_t)(b + (dir == 1));
+            s_lb[pos] = lq;
+          }
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

@@ -445,12 +445,17 @@ k_infer_q(DevInst I, DevPool pool, const int *__restrict__ costs, float qs, floa
     }
     wave_sync();  // the next round rewrites the keys
     bitonic_sort_desc<16>(ch);
+    if (u == 0) {  // the first sorted tile is the running list as it stands
 #pragma unroll
-    for (int q = 0; q < KMAX; ++q) {
-      const int r = KMAX - 1 - q;
-      best[q] = max(best[q], r < 16 ? ch[r < 16 ? r : 0] : INT_MIN);
+      for (int q = 0; q < KMAX; ++q) best[q] = q < 16 ? ch[q < 16 ? q : 0] : INT_MIN;
+    } else {
+#pragma unroll
+      for (int q = 0; q < KMAX; ++q) {
+        const int r = KMAX - 1 - q;
+        best[q] = max(best[q], r < 16 ? ch[r < 16 ? r : 0] : INT_MIN);
+      }
+      bitonic_merge_desc<KMAX>(best);
     }
-    bitonic_merge_desc<KMAX>(best);
   }
 #pragma unroll
   for (int d = 1; d <= 2; d <<= 1) {  // merge with the partner's list

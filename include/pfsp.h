@@ -159,7 +159,9 @@ int pfsp_neh(pfsp_ctx *c, int32_t *perm_out, int32_t *cmax_out);
  * "learned_exact" (1 = re-bound subset survivors with all pairs, default 0),
  * "timing" (1 = bracket every kernel launch with HIP events on the ctx
  * stream, default 0), "lb2_waves" (waves per block of the LB2 kernel, 0..16, 0 =
- * automatic; larger values than a kernel's launch bounds allow are ignored), "lb2_blocks_per_cu" (cap on resident LB2 blocks per CU, 0 = 16),
+ * automatic; larger values than a kernel's launch bounds allow are ignored), "lb2_blocks_per_cu" (cap on LB2 blocks per CU, 0 = twice
+ * the blocks that fit a CU's LDS for the n <= 32 and subset kernels, 16 for
+ * the others),
  * "force_generic" (1 = always use the generic LB2 kernel),
  * "search_filter" (1 = LB2 search steps close every parent whose children
  * all have LB1 >= incumbent in the costs kernel and bound only the others

@@ -2712,7 +2712,10 @@ static int launch_lb2s(Ctx *c, const DevPool &pool, int G, int ub, int *out_lb,
   const int Ppad = (c->P + 63) / 64 * 64;
   const int per_block = waves * G;
   int grid = (pool.count + per_block - 1) / per_block;
-  const int cap = c->cu_count * 16;
+  // twice the blocks that LDS lets a CU hold (each block stages its tables once)
+  const int resident = std::max(1, (int)((160 * 1024) / std::max<size_t>(lds, 1)));
+  const int cap = c->cu_count * (c->lb2_blocks_per_cu > 0 ? (int)c->lb2_blocks_per_cu
+                                                          : 2 * resident);
   if (grid > cap) grid = cap;
   KTimer kt(c, s, "k_lb2");
 #define PFSP_S(N, GG)                                                                       \
@@ -2803,7 +2806,11 @@ int launch_bound_costs_ready(Ctx *c, const DevPool &pool, int kind, int ub, int 
     if (waves) {
       const int Ppad = (c->P + 63) / 64 * 64;
       int grid = (pool.count + waves - 1) / waves;
-      const int cap = c->cu_count * (int)(c->lb2_blocks_per_cu > 0 ? c->lb2_blocks_per_cu : 16);
+      // default: twice the blocks that LDS lets a CU hold, so that each block
+      // stages its tables once and then loops over many parents
+      const int resident = std::max(1, (int)((160 * 1024) / std::max<size_t>(lds, 1)));
+      const int cap = c->cu_count * (int)(c->lb2_blocks_per_cu > 0 ? c->lb2_blocks_per_cu
+                                                                   : 2 * resident);
       if (grid > cap) grid = cap;
       const dim3 g(grid), bl(64 * waves);
       KTimer kt(c, s, "k_lb2");

@@ -147,6 +147,13 @@ k_count(SearchCtl *__restrict__ c, int n, const uint8_t *__restrict__ b_d1,
           atomicMin(&c->ub, v);
           atomicMin(&c->step_best, ((unsigned long long)(unsigned)v << 32) | (unsigned)i);
         }
+      } else if ((n & 3) == 0) {  // rows start on 4-byte boundaries: a word per 4 flags
+        const uint32_t *pw = (const uint32_t *)pr;
+        for (int w = 0; 4 * w < r; ++w) {
+          const int valid = min(4, r - 4 * w);  // flags are 0 or 1
+          const uint32_t keep = 0x01010101u >> (8 * (4 - valid));
+          s += valid - __popc(pw[w] & keep);
+        }
       } else {
         for (int q = 0; q < r; ++q) s += pr[q] == 0;
       }

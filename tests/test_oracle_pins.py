@@ -184,6 +184,54 @@ def test_pair_johnson_with_lags_is_optimal():
         assert a == b
 
 
+def test_lb2_one_job_left_equals_makespan():
+    """A node with exactly one unscheduled job j has a unique completion.  Its
+    makespan is the longest grid path, which enters j's row at some machine k
+    and leaves it at some k2 >= k.  For k = k2 that path is LB1's machine-k
+    term; for k < k2 it is the value of pair (k, k2): head on k, a_j, the lag of
+    the machines strictly between them, b_j, tail on k2.  So full LB2 equals
+    that makespan exactly, and a lag that is dropped, shortened or shifted
+    makes it fall short on paths that cross machines between k and k2."""
+    rng = np.random.default_rng(71)
+    checked = 0
+    for t in range(60):
+        n, m = int(rng.integers(2, 9)), int(rng.integers(3, 9))
+        kind = "correlated" if t % 4 == 3 else "uniform"
+        p = inputs.instance(n, m, 7100 + t, kind)
+        for _ in range(8):
+            perm = rng.permutation(n).astype(np.uint8)
+            d1 = int(rng.integers(0, n))
+            d2 = n - 1 - d1
+            assert oracle.node_bound(p, perm, d1, d2, oracle.LB2_FULL) == \
+                oracle.makespan(p, perm)
+            checked += 1
+    assert checked == 480
+
+
+def test_lb2_lag_decides_hand_example():
+    """Two jobs on three machines, root node (no heads, no tails), worked by hand.
+    p = J0 (5, 1, 1), J1 (1, 1, 5).
+      LB1 = max(5+1, 1+1, 1+5) = 6.
+      pair (0,1): a = (5, 1), b = (1, 1), no lag.  Johnson: J1 (a <= b), then J0.
+                  t_u = 1, t_v = 1 + 1 = 2; t_u = 6, t_v = max(2, 6) + 1 = 7.   -> 7
+      pair (1,2): a = (1, 1), b = (1, 5), no lag.  Both a <= b, ascending a, ties
+                  by id: J0, J1.  t_u = 1, t_v = 2; t_u = 2, t_v = max(2, 2) + 5 = 7.   -> 7
+      pair (0,2): a = (5, 1), b = (1, 5), lag = p[j][1] = 1.  Johnson: J1, then J0.
+                  t_u = 1, t_v = max(0, 1 + 1) + 5 = 7; t_u = 6, t_v = max(7, 6 + 1) + 1 = 8.
+                  -> 8 (7 without the lag)
+    LB2 = 8, reached only through the lag; it equals the optimum (J1 J0: 8)."""
+    p = np.array([[5, 1, 1], [1, 1, 5]], dtype=np.int32)
+    jobs = np.array([0, 1], dtype=np.uint8)
+    assert oracle.node_bound(p, jobs, 0, 0, oracle.LB1) == 6
+    assert oracle.pair_value(p, jobs, 0, 1, 0, 0, 0, 0) == 7
+    assert oracle.pair_value(p, jobs, 1, 2, 0, 0, 0, 0) == 7
+    assert oracle.pair_value(p, jobs, 0, 2, 0, 0, 0, 0) == 8
+    lb2, ap = oracle.node_bound(p, jobs, 0, 0, oracle.LB2_FULL, with_argpair=True)
+    assert lb2 == 8 and ap == oracle.pair_index(3, 0, 2)
+    assert oracle.bruteforce(p)[0] == 8
+    assert list(oracle.johnson_lag_order(p, jobs, 0, 2)) == [1, 0]
+
+
 def test_pair_value_tie_invariance():
     """Equal Johnson keys in any order give the same value (ties on purpose)."""
     rng = np.random.default_rng(9)
@@ -344,6 +392,24 @@ def test_search_critical_tree_and_budget():
     # (reversed machines) has the same optimum
     rm = oracle.search(p[:, ::-1], opt + 1, oracle.LB1)
     assert rm["best"] == opt
+
+
+def test_neh_hand_examples():
+    """Nawaz-Enscore-Ham worked by hand.
+    (a) p = J0 (3,2), J1 (1,4), J2 (2,3), J3 (4,1): every total is 5, so the
+        order is by id.  [0]; J1: [1,0] = 7 < [0,1] = 9.  J2: [2,1,0] = 11,
+        [1,2,0] = 10, [1,0,2] = 10 -> first of the ties, [1,2,0].  J3:
+        [3,1,2,0] = 14, [1,3,2,0] = 12, [1,2,3,0] = 12, [1,2,0,3] = 11 -> [1,2,0,3], 11.
+        (Taking the last of equal insertions, or higher ids first, gives [1,0,2,3].)
+    (b) p = J0 (1,1), J1 (5,2), J2 (2,6): totals 2, 7, 8, so the order is J2, J1,
+        J0.  [2]; J1: [1,2] = 13, [2,1] = 10 -> [2,1].  J0: all three insertions
+        give 11 -> the first, [0,2,1].  (Ascending totals would give [2,1,0].)"""
+    p = np.array([[3, 2], [1, 4], [2, 3], [4, 1]], dtype=np.int32)
+    c, perm = oracle.neh(p)
+    assert (c, perm.tolist()) == (11, [1, 2, 0, 3])
+    p = np.array([[1, 1], [5, 2], [2, 6]], dtype=np.int32)
+    c, perm = oracle.neh(p)
+    assert (c, perm.tolist()) == (11, [0, 2, 1])
 
 
 def test_neh_is_a_feasible_upper_bound():

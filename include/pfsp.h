@@ -133,7 +133,9 @@ int pfsp_check(pfsp_ctx *c);
  * and their surviving children pushed back (leftmost on top).  Looks for a
  * schedule with C_max < ub0 (INT32_MAX: none known).  budget_nodes > 0 stops
  * after about that many decomposed nodes (returns PFSP_BUDGET).  lb_kind as
- * above except PFSP_LB2_SUBSET.  Synchronous; res must not be NULL. */
+ * above except PFSP_LB2_SUBSET.  Waits for the ctx stream first (the search
+ * runs on a stream of its own and shares the bound workspace).  Synchronous;
+ * res must not be NULL. */
 int pfsp_search(pfsp_ctx *c, int32_t ub0, int64_t budget_nodes, int lb_kind,
                 pfsp_result *res);
 
@@ -156,7 +158,11 @@ int pfsp_neh(pfsp_ctx *c, int32_t *perm_out, int32_t *cmax_out);
  * "use_graph" (1 = replay the search step as a HIP graph, default 1),
  * "learned_topk" (pairs kept by the selector, default 16; at most 32 with
  * the float selector, 64 with the integer one),
- * "learned_exact" (1 = re-bound subset survivors with all pairs, default 0),
+ * "learned_exact" (1 = PFSP_LB2_LEARNED bounds every parent that keeps a
+ * child under the selected pairs again with all pairs: the prune flags, and a
+ * search's tree, are those of PFSP_LB2_FULL, and so are the bounds and MinMin
+ * choice of those parents; a parent whose children the subset prunes
+ * entirely keeps the subset's values; default 0),
  * "timing" (1 = bracket every kernel launch with HIP events on the ctx
  * stream, default 0), "lb2_waves" (waves per block of the LB2 kernel, 0..16, 0 =
  * automatic; larger values than a kernel's launch bounds allow are ignored), "lb2_blocks_per_cu" (cap on LB2 blocks per CU, 0 = twice
@@ -217,7 +223,8 @@ void pfsp_multi_destroy(pfsp_multi *mt);
 
 /* Decomposition of every parent (as pfsp_bound_children, lb_kind PFSP_LB1 or
  * PFSP_LB2_FULL) with incumbent ub[k] (HOST [count]) for instance k;
- * seg_begin is HOST [count + 1] with seg_begin[0] = 0.  Synchronous. */
+ * seg_begin is HOST [count + 1] with seg_begin[0] = 0.  Waits for the ctx
+ * stream first (the pool may be written there).  Synchronous. */
 int pfsp_multi_bound(pfsp_multi *mt, int lb_kind, const uint8_t *perm, const uint8_t *d1,
                      const uint8_t *d2, int32_t stride, const int64_t *seg_begin,
                      const int32_t *ub, int32_t *out_lb, uint8_t *out_prune, uint8_t *dir_out);

@@ -205,6 +205,8 @@ int launch_learned(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8_t *ou
 int launch_learned_ready(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8_t *out_prune,
                    hipStream_t s);
 int learned_prepare(Ctx *c, int rows);
+// 0: no selector, 1: float model, 2: integer model (changes the captured step)
+int selector_mode(const Ctx *c);
 void selector_free(Ctx *c);
 // search.hip
 void search_free(Ctx *c);

@@ -430,6 +430,8 @@ int pfsp_multi_bound(pfsp_multi *mt, int lb_kind, const uint8_t *perm, const uin
                             dir_out, seg);
   if (rc) return rc;
   PFSP_HIP(c, hipSetDevice(c->device));
+  // the pool may still be written by work queued on the ctx stream
+  PFSP_HIP(c, hipStreamSynchronize(c->stream));
   rc = multi_run(mt, lb_kind, perm, d1, d2, stride, seg, ub, out_lb, out_prune, dir_out);
   if (rc) return rc;
   PFSP_HIP(c, hipStreamSynchronize(mt->stream));
@@ -464,6 +466,7 @@ int pfsp_multi_autotune(pfsp_multi *mt, int lb_kind, const uint8_t *perm, const 
   if (rc) return rc;
   if (reps < 1) reps = 3;
   PFSP_HIP(c, hipSetDevice(c->device));
+  PFSP_HIP(c, hipStreamSynchronize(c->stream));  // the pool may be written on the ctx stream
   const int tiles[] = {64, 128, 256, 512, 1024};
   const int wv[] = {0, 2, 4, 8, 12, 16};
   const int gpc[] = {0, 2, 4, 8};

@@ -21,6 +21,7 @@
 // carries its makespan as LB; if it is below the step's incumbent it lowers
 // the incumbent with atomicMin and the best leaf of the step is recorded.
 #include <chrono>
+#include <vector>
 
 #include "internal.h"
 
@@ -60,9 +61,7 @@ struct SearchState {
   SearchCtl *ctl = nullptr, *ctl_host = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
-  int graph_kind = 0;
-  long long graph_log = -1;
-  int graph_filter = -1;
+  std::vector<long long> graph_key;  // options the captured step depends on
   // LB2 steps: parents that survive the costs kernels' LB1 filter
   int *rows = nullptr, *open = nullptr;
   // node log (option log_capacity > 0): every log_stride-th decomposed node
@@ -488,12 +487,18 @@ static int enqueue_step(Ctx *c, int kind) {
   return PFSP_OK;
 }
 
+// Everything enqueue_step's launches depend on besides the buffers.
+static std::vector<long long> step_key(const Ctx *c, int kind) {
+  const SearchState *S = c->search;
+  return {kind, S->log_cap > 0 ? c->log_stride : 0, c->search_filter, c->learned_topk,
+          c->learned_exact, c->subset_group, c->lb2_waves, c->lb2_blocks_per_cu,
+          c->force_generic, c->wide_lb2, selector_mode(c)};
+}
+
 static int build_graph(Ctx *c, int kind) {
   SearchState *S = c->search;
-  const long long logkey = S->log_cap > 0 ? c->log_stride : 0;
-  if (S->gexec && S->graph_kind == kind && S->graph_log == logkey &&
-      S->graph_filter == (int)c->search_filter)
-    return PFSP_OK;
+  const std::vector<long long> key = step_key(c, kind);
+  if (S->gexec && S->graph_key == key) return PFSP_OK;
   if (S->gexec) (void)hipGraphExecDestroy(S->gexec);
   if (S->graph) (void)hipGraphDestroy(S->graph);
   S->gexec = nullptr;
@@ -511,9 +516,7 @@ static int build_graph(Ctx *c, int kind) {
   if (e != hipSuccess) return hip_err(c, e, "hipStreamEndCapture");
   S->graph = g;
   PFSP_HIP(c, hipGraphInstantiate(&S->gexec, g, nullptr, nullptr, 0));
-  S->graph_kind = kind;
-  S->graph_filter = (int)c->search_filter;
-  S->graph_log = logkey;
+  S->graph_key = key;
   return PFSP_OK;
 }
 
@@ -532,6 +535,8 @@ extern "C" int pfsp_search(pfsp_ctx *h, int32_t ub0, int64_t budget_nodes, int l
   if (lb_kind != PFSP_LB1 && c->m < 2) return set_err(c, PFSP_ERANGE, "LB2 kinds need m >= 2");
   if (budget_nodes < 0) return set_err(c, PFSP_EINVAL, "negative budget");
   PFSP_HIP(c, hipSetDevice(c->device));
+  // the search stream shares the bound workspace with work queued on the ctx stream
+  PFSP_HIP(c, hipStreamSynchronize(c->stream));
   int rc = search_alloc(c);
   if (rc) return rc;
   SearchState *S = c->search;

@@ -41,6 +41,8 @@ struct Selector {
   // per-batch workspaces (grown on demand)
   float *feat = nullptr, *scores = nullptr;
   uint32_t *mask = nullptr;
+  int *reopen = nullptr;        // learned_exact: pool rows re-bounded with all pairs
+  int *reopen_count = nullptr;  // [1]
   size_t rows_cap = 0;
   int mask_words = 0;
   // training workspaces
@@ -767,7 +769,7 @@ void selector_free(Ctx *c) {
   if (!S) return;
   void *bufs[] = {S->master, S->wq, S->grad, S->am, S->av, S->feat, S->scores, S->mask, S->h1,
                   S->h2, S->ds, S->dh1, S->dh2, S->rowloss, S->loss, S->to_inst, S->qops,
-                  S->qbias};
+                  S->qbias, S->reopen, S->reopen_count};
   for (void *p : bufs) (void)hipFree(p);
   delete S;
   c->sel = nullptr;
@@ -794,14 +796,19 @@ static int sel_rows(Ctx *c, Selector *S, size_t rows) {
   (void)hipFree(S->feat);
   (void)hipFree(S->scores);
   (void)hipFree(S->mask);
+  (void)hipFree(S->reopen);
+  (void)hipFree(S->reopen_count);
   S->feat = S->scores = nullptr;
   S->mask = nullptr;
-  S->rows_cap = 0;
+  S->reopen = S->reopen_count = nullptr;
   const size_t cap = rows > S->rows_cap ? rows : S->rows_cap;
+  S->rows_cap = 0;
   const int w = words > S->mask_words ? words : S->mask_words;
   if (hipMalloc(&S->feat, cap * kIn * 4) != hipSuccess ||
       hipMalloc(&S->scores, cap * kOut * 4) != hipSuccess ||
-      hipMalloc(&S->mask, cap * (size_t)w * 4) != hipSuccess)
+      hipMalloc(&S->mask, cap * (size_t)w * 4) != hipSuccess ||
+      hipMalloc(&S->reopen, cap * 4) != hipSuccess ||
+      hipMalloc(&S->reopen_count, 4) != hipSuccess)
     return set_err(c, PFSP_ENOMEM, "selector workspace allocation failed");
   S->rows_cap = cap;
   S->mask_words = w;
@@ -816,6 +823,11 @@ static float instance_norm(const Ctx *c) {
     if (s > best) best = s;
   }
   return (float)best;
+}
+
+int selector_mode(const Ctx *c) {
+  if (!c->sel) return 0;
+  return c->sel->qloaded ? 2 : c->sel->loaded ? 1 : 0;
 }
 
 int learned_prepare(Ctx *c, int rows) {
@@ -863,6 +875,26 @@ static void launch_infer(Ctx *c, const DevPool &pool, int k, uint32_t *mask, hip
   }
 }
 
+__global__ void k_zero_count(int *p) { *p = 0; }
+
+// Appends to rows[] every pool row of the launch that has an unpruned child
+// in either direction and more than one unscheduled job (with one, both
+// children are leaves whose bound is the makespan under every kind).
+__global__ void __launch_bounds__(256)
+k_reopen(DevPool pool, int n, const uint8_t *__restrict__ out_prune, int *__restrict__ rows,
+         int *__restrict__ count_out) {
+  const int count = pool.count_dev ? *pool.count_dev : pool.count;
+  const int it = blockIdx.x * blockDim.x + threadIdx.x;
+  if (it >= count) return;
+  const int i = pool.index ? pool.index[it] : it;
+  const int r = n - pool.d1[i] - pool.d2[i];
+  if (r < 2) return;
+  const uint8_t *pr = out_prune + (size_t)i * 2 * n;
+  bool keep = false;
+  for (int q = 0; q < r && !keep; ++q) keep = pr[q] == 0 || pr[n + q] == 0;
+  if (keep) rows[atomicAdd(count_out, 1)] = i;
+}
+
 int launch_learned(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8_t *out_prune,
                    hipStream_t s) {
   int rc = learned_prepare(c, pool.count);
@@ -897,7 +929,25 @@ int launch_learned_ready(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8
   // for k <= 16 cost about as much per parent at n <= 20, whose two-parent
   // kernel runs three waves per SIMD; so four only where asked)
   const int group = c->subset_group > 0 ? (int)c->subset_group : k <= 32 ? 2 : 1;
-  return launch_bound_costs_ready(c, sp, PFSP_LB2_SUBSET, ub, out_lb, out_prune, s, group);
+  rc = launch_bound_costs_ready(c, sp, PFSP_LB2_SUBSET, ub, out_lb, out_prune, s, group);
+  if (rc || !c->learned_exact) return rc;
+  // Exact mode: a parent that keeps a child under the subset bound is bounded
+  // again with all pairs.  A parent whose children the subset bound prunes
+  // entirely loses them under full LB2 as well (full >= subset), so every
+  // prune flag, and the tree of a search, is that of PFSP_LB2_FULL.
+  hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, S->reopen_count);
+  {
+    KTimer kt(c, s, "k_reopen");
+    hipLaunchKernelGGL(k_reopen, dim3((pool.count + 255) / 256), dim3(256), 0, s, pool, c->n,
+                       out_prune, S->reopen, S->reopen_count);
+  }
+  PFSP_HIP(c, hipGetLastError());
+  DevPool fp = pool;
+  fp.index = S->reopen;
+  fp.count_dev = S->reopen_count;
+  fp.mask = nullptr;
+  fp.mask_words = 0;
+  return launch_bound_costs_ready(c, fp, PFSP_LB2_FULL, ub, out_lb, out_prune, s, 0);
 }
 
 // k_infer stages all weights and a layer of activations in LDS (about 148

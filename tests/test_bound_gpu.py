@@ -45,8 +45,10 @@ def _check(ctx, p, perm, d1, d2, kind, ub, mask=None, argpair=False, threads=8):
     return olb
 
 
+# m > 20 (up to the ABI's 64) reaches the quick kernels with larger pair
+# tables (m = 24, 32) and the generic kernel when the tables exceed LDS (m = 64)
 SHAPES = [(2, 1), (2, 2), (3, 2), (5, 3), (10, 5), (20, 20), (20, 10), (33, 7), (50, 20),
-          (64, 4), (100, 20), (130, 3)]
+          (64, 4), (100, 20), (130, 3), (16, 24), (20, 32), (10, 64), (40, 24)]
 
 
 @pytest.mark.parametrize("n,m", SHAPES)
@@ -309,12 +311,17 @@ def test_full_size_pool_sampled(ctx):
     tp, t1, t2 = _dev(ctx, perm, d1, d2)
     rng = np.random.default_rng(1)
     idx = np.sort(rng.choice(N, size=1500, replace=False))
-    for kind in (binding.LB1, binding.LB2_FULL):
-        lb, pr, dr, _ = ctx.bound_children(tp, t1, t2, kind, INT32_MAX)
+    # no incumbent, and the benchmark's incumbent (NEH makespan 2378) under
+    # which a share of the children is pruned
+    for kind, ub in ((binding.LB1, INT32_MAX), (binding.LB2_FULL, INT32_MAX),
+                     (binding.LB1, 2378), (binding.LB2_FULL, 2378)):
+        lb, pr, dr, _ = ctx.bound_children(tp, t1, t2, kind, ub)
         torch.cuda.synchronize()
         ctx.check()
-        olb, opr, odr = oracle.bound_children(p, perm[idx], d1[idx], d2[idx], kind, INT32_MAX,
+        olb, opr, odr = oracle.bound_children(p, perm[idx], d1[idx], d2[idx], kind, ub,
                                               threads=8)
+        if ub < INT32_MAX:
+            assert 0 < opr[olb < INT32_MAX].mean() < 1   # the flags vary
         np.testing.assert_array_equal(lb.cpu().numpy()[idx], olb)
         np.testing.assert_array_equal(pr.cpu().numpy()[idx], opr)
         np.testing.assert_array_equal(dr.cpu().numpy()[idx], odr)

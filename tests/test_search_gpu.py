@@ -28,7 +28,7 @@ def _valid(p, perm, cmax):
     assert oracle.makespan(p, perm) == cmax
 
 
-@pytest.mark.parametrize("seed", range(1, 9))
+@pytest.mark.parametrize("seed", range(1, 33))
 def test_optimum_10x5(ctx, seed):
     """n=10 jobs x m=5 machines, p ~ U[1,99], incumbent from NEH."""
     p = inputs.instance(10, 5, seed)
@@ -107,15 +107,66 @@ def test_two_machines_root_proves_johnson(ctx):
     assert r2["nodes"] == 1 and not r2["found"]
 
 
-def test_search_20x10_matches_oracle(ctx):
-    """A 20 x 10 instance (the search workload's shape) against the oracle, LB1."""
-    p = inputs.instance(20, 10, 1)
+def _golden_20x10():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "search_20x10.json")
+    with open(path) as f:
+        return {c["seed"]: c for c in json.load(f)["cases"]}
+
+
+GOLDEN_20x10 = _golden_20x10()
+
+
+@pytest.mark.parametrize("seed", range(1, 9))
+@pytest.mark.parametrize("kind", [binding.LB1, binding.LB2_FULL])
+def test_search_20x10_matches_oracle(ctx, seed, kind):
+    """The search workload (20 x 10, seeds 1..8, incumbent NEH + 1) proves the
+    oracle's optimum with both bounds; the returned schedule is re-evaluated
+    by the oracle.  Expected values: tests/golden/search_20x10.json, written
+    by make_search_golden.py from the oracle alone."""
+    g = GOLDEN_20x10[seed]
+    p = inputs.instance(20, 10, seed)
     ctx.load_instance(p)
     ub0, _ = ctx.neh()
-    r = ctx.search(ub0 + 1, 0, binding.LB1)
-    ref = oracle.search(p, ub0 + 1, oracle.LB1, budget=3_000_000)
-    assert r["proven"]
-    if ref["proven"]:
-        assert r["best"] == ref["best"]
-    if r["found"]:
-        _valid(p, r["perm"], r["best"])
+    assert ub0 == g["neh"]
+    r = ctx.search(ub0 + 1, 0, kind)
+    assert r["proven"] and r["found"] and r["best"] == g["opt"]
+    _valid(p, r["perm"], g["opt"])
+
+
+@pytest.mark.parametrize("seed", range(1, 9))
+@pytest.mark.parametrize("kind", [binding.LB1, binding.LB2_FULL])
+def test_critical_tree_20x10(ctx, seed, kind):
+    """With the incumbent at the optimum the decomposed nodes are the critical
+    tree: counts equal the oracle's exactly at the search workload's shape."""
+    g = GOLDEN_20x10[seed]
+    name = "lb1" if kind == binding.LB1 else "lb2"
+    p = inputs.instance(20, 10, seed)
+    ctx.load_instance(p)
+    r = ctx.search(g["opt"], 0, kind)
+    assert r["proven"] and not r["found"]
+    assert r["nodes"] == g[f"critical_nodes_{name}"]
+    assert r["children"] == g[f"critical_children_{name}"]
+
+
+def test_search_after_queued_bound(ctx):
+    """pfsp_search runs on a stream of its own but shares the bound workspace
+    with pfsp_bound_children: a large bound queued on the ctx stream right
+    before a search must neither disturb the search nor be disturbed."""
+    import torch
+    n, m = 20, 10
+    p = inputs.instance(n, m, 3)
+    ctx.load_instance(p)
+    perm, d1, d2 = inputs.random_pool(n, 1 << 18, 77)
+    dev = [torch.from_numpy(a).to(ctx.device) for a in (perm, d1, d2)]
+    lb, pr, dr, _ = ctx.bound_children(*dev, kind=binding.LB2_FULL, ub=1700)
+    r = ctx.search(GOLDEN_20x10[3]["opt"], 0, binding.LB2_FULL)   # no synchronize before
+    torch.cuda.synchronize()
+    assert r["proven"] and r["nodes"] == GOLDEN_20x10[3]["critical_nodes_lb2"]
+    idx = np.arange(0, 1 << 18, 997)
+    olb, opr, odr = oracle.bound_children(p, perm[idx], d1[idx], d2[idx], oracle.LB2_FULL, 1700,
+                                          threads=8)
+    np.testing.assert_array_equal(lb.cpu().numpy()[idx], olb)
+    np.testing.assert_array_equal(pr.cpu().numpy()[idx], opr)
+    np.testing.assert_array_equal(dr.cpu().numpy()[idx], odr)

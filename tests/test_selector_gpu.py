@@ -356,3 +356,78 @@ def test_learned_search_same_optimum(ctx):
     assert full["proven"] and learned["proven"]
     assert full["best"] == learned["best"] <= ub0
     assert learned["nodes"] >= full["nodes"]       # a subset never prunes more
+    for r in (full, learned):                      # the schedules, re-evaluated
+        assert sorted(r["perm"].tolist()) == list(range(20))
+        assert oracle.makespan(p, r["perm"]) == r["best"]
+
+
+@pytest.mark.parametrize("k", [16, 32])
+def test_learned_exact_bound(ctx, k):
+    """Exact mode (option learned_exact): a parent that keeps a child under the
+    selected pairs is bounded again with all pairs, so every prune flag is full
+    LB2's, and so are the bounds and the MinMin choice of every parent that
+    keeps a child.  A parent the subset prunes entirely keeps the subset's
+    bounds (all at least the incumbent)."""
+    import torch
+    n, m = 20, 20
+    p = inputs.instance(n, m, 430)
+    perm, d1, d2 = _quant_pool(n, 432)
+    flb, _, _ = oracle.bound_children(p, perm, d1, d2, oracle.LB2_FULL, threads=8)
+    ub = int(np.percentile(flb[flb < binding.INT32_MAX], 30))   # some parents keep children
+    ctx.load_instance(p)
+    blob = _trained_blob(ctx, n)
+    ctx.selector_set_quant(blob)
+    ctx.set_option("learned_topk", k)
+    ctx.set_option("learned_exact", 1)
+    try:
+        dev = [_t(ctx, a) for a in (perm, d1, d2)]
+        lb, pr, dr, _ = ctx.bound_children(*dev, kind=binding.LB2_LEARNED, ub=ub)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_option("learned_exact", 0)
+        ctx.set_option("learned_topk", 16)
+        ctx.selector_set_quant(None)
+    lb, pr, dr = lb.cpu().numpy(), pr.cpu().numpy(), dr.cpu().numpy()
+    flb, fpr, fdr = oracle.bound_children(p, perm, d1, d2, oracle.LB2_FULL, ub, threads=8)
+    mask = _words(S.quant_masks(blob, p, perm, d1, d2, k), m)
+    slb, spr, sdr = oracle.bound_children(p, perm, d1, d2, oracle.LB2_SUBSET, ub,
+                                          pair_mask=mask, threads=8)
+    np.testing.assert_array_equal(pr, fpr)
+    r = n - d1.astype(int) - d2.astype(int)
+    reopened = (spr == 0).any(axis=(1, 2)) & (r >= 2)
+    assert 0 < reopened.mean() < 1
+    np.testing.assert_array_equal(lb[reopened], flb[reopened])
+    np.testing.assert_array_equal(dr[reopened], fdr[reopened])
+    np.testing.assert_array_equal(lb[~reopened], slb[~reopened])
+    np.testing.assert_array_equal(dr[~reopened], sdr[~reopened])
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_learned_exact_search_same_tree(ctx, seed):
+    """With the incumbent at the optimum, exact mode decomposes exactly the
+    critical tree of full LB2 (the oracle's count), and the pure learned bound
+    at least as many nodes.  20 x 10 instances of the search workload."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "search_20x10.json")) as f:
+        g = {c["seed"]: c for c in json.load(f)["cases"]}[seed]
+    p = inputs.instance(20, 10, seed)
+    ctx.load_instance(p)
+    ctx.selector_set_quant(_trained_blob(ctx, 20))
+    ctx.set_option("learned_topk", 16)
+    try:
+        ctx.set_option("learned_exact", 1)
+        exact = ctx.search(g["opt"], 0, binding.LB2_LEARNED)
+        ctx.set_option("learned_exact", 0)
+        pure = ctx.search(g["opt"], 0, binding.LB2_LEARNED)
+        ctx.set_option("learned_exact", 1)
+        found = ctx.search(g["neh"] + 1, 0, binding.LB2_LEARNED)
+    finally:
+        ctx.set_option("learned_exact", 0)
+        ctx.selector_set_quant(None)
+    assert exact["proven"] and not exact["found"]
+    assert exact["nodes"] == g["critical_nodes_lb2"]
+    assert exact["children"] == g["critical_children_lb2"]
+    assert pure["proven"] and pure["nodes"] >= exact["nodes"]
+    assert found["proven"] and found["best"] == g["opt"]
+    assert oracle.makespan(p, found["perm"]) == g["opt"]

@@ -122,6 +122,22 @@ int pfsp_pair_count(pfsp_ctx *c);
 int pfsp_bound_children(pfsp_ctx *c, const pfsp_pool *pool, int lb_kind, int32_t ub,
                         int32_t *out_lb, uint8_t *out_prune);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same
+ * decomposition as pfsp_bound_children for lb_kind PFSP_LB1, PFSP_LB2_FULL or
+ * PFSP_LB2_SUBSET, with the per-parent workspace (front, back and remaining
+ * loads, 3m int32 per parent) taken from a fixed 64 MiB device array that each
+ * GPU holds from the library's load until the process ends, instead of a
+ * workspace grown with hipMalloc.  The call allocates nothing (no hipMalloc,
+ * hipFree, events or library allocations); the caller still passes the pool
+ * and the outputs.  PFSP_ERANGE if count * 3 * m exceeds 2^24 (e.g. 279,620
+ * parents at m = 20); PFSP_EINVAL for PFSP_LB2_LEARNED.  Every call on a GPU
+ * uses that GPU's one array: calls whose work overlaps on one GPU (other
+ * contexts, other streams) race; calls queued on one stream are ordered.
+ * No kernel-time instrumentation.  Asynchronous on the ctx stream. */
+int pfsp_bound_children_noalloc(pfsp_ctx *c, const pfsp_pool *pool, int lb_kind, int32_t ub,
+                                int32_t *out_lb, uint8_t *out_prune);
+
 /* Waits for the ctx stream and reports PFSP_EINVAL if any pool row seen by
  * pfsp_bound_children since the last check had d1 + d2 >= n (such rows are
  * filled with INT32_MAX / prune 1).  Clears the condition.  Synchronous. */

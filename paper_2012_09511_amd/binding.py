@@ -27,7 +27,7 @@ EXPORTS = ["pfsp_create", "pfsp_destroy", "pfsp_last_error", "pfsp_load_instance
            "pfsp_selector_select", "pfsp_selector_targets", "pfsp_selector_train_step",
            "pfsp_search_log", "pfsp_multi_create", "pfsp_multi_destroy", "pfsp_multi_bound",
            "pfsp_multi_set_shape", "pfsp_multi_autotune", "pfsp_autotune",
-           "pfsp_selector_set_quant", "pfsp_selector_infer"]
+           "pfsp_selector_set_quant", "pfsp_selector_infer", "pfsp_bound_children_noalloc"]
 SELECTOR_PARAMS = 20670
 SELECTOR_QPARAMS = 20675
 
@@ -74,6 +74,8 @@ def lib():
         L.pfsp_load_instance.argtypes = [vp, i32, i32, vp]
         L.pfsp_pair_count.argtypes = [vp]
         L.pfsp_bound_children.argtypes = [vp, ctypes.POINTER(Pool), ctypes.c_int, i32, vp, vp]
+        L.pfsp_bound_children_noalloc.argtypes = [vp, ctypes.POINTER(Pool), ctypes.c_int, i32,
+                                                  vp, vp]
         L.pfsp_check.argtypes = [vp]
         L.pfsp_search.argtypes = [vp, i32, i64, ctypes.c_int, ctypes.POINTER(Result)]
         L.pfsp_neh.argtypes = [vp, vp, vp]
@@ -178,6 +180,17 @@ class Context:
         self._check(lib().pfsp_bound_children(self.h, ctypes.byref(pool), kind, int(ub),
                                               _ptr(out_lb), _ptr(out_prune)))
         return out_lb, out_prune, dir_out, argpair_out
+
+    def bound_children_noalloc(self, perm, d1, d2, out_lb, out_prune, kind=LB1, ub=INT32_MAX,
+                               pair_mask=None, dir_out=None):
+        """pfsp_bound_children_noalloc on caller-allocated device outputs."""
+        N = perm.shape[0]
+        pool = Pool(N, perm.shape[1] if perm.dim() == 2 else self.n, _ptr(perm), _ptr(d1),
+                    _ptr(d2), _ptr(pair_mask), 0 if pair_mask is None else pair_mask.shape[-1],
+                    _ptr(dir_out), None)
+        self._check(lib().pfsp_bound_children_noalloc(self.h, ctypes.byref(pool), kind, int(ub),
+                                                      _ptr(out_lb), _ptr(out_prune)))
+        return out_lb, out_prune, dir_out
 
     def autotune(self, perm, d1, d2, kind=LB2_FULL, ub=INT32_MAX, reps=3, pair_mask=None):
         """Times LB2 block shapes on this pool and keeps the fastest; returns the report."""

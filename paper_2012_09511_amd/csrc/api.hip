@@ -91,8 +91,14 @@ int pfsp_create(pfsp_ctx **out, int device, void *hip_stream) {
   if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
     c->cu_count = prop.multiProcessorCount;
   if (hipMalloc(&c->d_flag, 16) != hipSuccess || hipMemset(c->d_flag, 0, 16) != hipSuccess) {
+    (void)hipFree(c->d_flag);
     delete h;
     return PFSP_ENOMEM;
+  }
+  if (noalloc_attach(c) != PFSP_OK) {
+    (void)hipFree(c->d_flag);
+    delete h;
+    return PFSP_EDEVICE;
   }
   *out = h;
   return PFSP_OK;

@@ -88,6 +88,7 @@ struct Ctx {
   int *d_costs = nullptr;
   size_t costs_cap = 0;
   int *d_flag = nullptr;   // [4] device status words: [0] invalid-row flag
+  int *scratch = nullptr;  // this device's fixed workspace (pfsp_bound_children_noalloc)
   // options
   int64_t pool_batch = 65536;
   int64_t poll_every = 8;
@@ -210,6 +211,8 @@ int selector_mode(const Ctx *c);
 void selector_free(Ctx *c);
 // search.hip
 void search_free(Ctx *c);
+// noalloc.hip: looks up this device's scratch array address (device current)
+int noalloc_attach(Ctx *c);
 // neh.cpp
 int neh_host(int n, int m, const int *p, int *perm_out, int *cmax_out);
 

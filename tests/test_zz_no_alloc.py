@@ -1,0 +1,87 @@
+"""pfsp_bound_children_noalloc (fixed device workspace) against
+pfsp_bound_children: bounds, prune flags and MinMin choices bit-exact, on two
+calls in a row (the second with fewer parents, so that stale workspace rows of
+the first call are present), with nothing allocated by the call."""
+import numpy as np
+import pytest
+
+from paper_2012_09511_amd import binding, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _masks(count, P, seed):
+    rng = np.random.default_rng(seed)
+    mask = np.zeros((count, (P + 31) // 32), dtype=np.uint32)
+    for i in range(count):
+        for b in rng.choice(P, size=1 + i % 24, replace=False):
+            mask[i, b >> 5] |= np.uint32(1 << (int(b) & 31))
+    return mask
+
+
+@pytest.mark.parametrize("kind", [binding.LB1, binding.LB2_FULL, binding.LB2_SUBSET])
+def test_noalloc_matches_bound_children(kind):
+    import torch
+    ctx = binding.Context(0)   # fresh: no workspace grown yet
+    try:
+        n, m = 20, 20
+        P = m * (m - 1) // 2
+        ctx.load_instance(inputs.instance(n, m, 2012))
+        for call, (count, seed) in enumerate(((200_000, 5), (3_001, 6))):
+            perm, d1, d2 = inputs.random_pool(n, count, seed)
+            dev = [torch.from_numpy(a).to(ctx.device) for a in (perm, d1, d2)]
+            tm = None
+            if kind == binding.LB2_SUBSET:
+                tm = torch.from_numpy(_masks(count, P, seed)).to(ctx.device)
+            lb = torch.empty((count, 2, n), dtype=torch.int32, device=ctx.device)
+            pr = torch.empty((count, 2, n), dtype=torch.uint8, device=ctx.device)
+            dr = torch.empty(count, dtype=torch.uint8, device=ctx.device)
+            torch.cuda.synchronize()
+            free0 = torch.cuda.mem_get_info(ctx.device)[0]
+            ctx.bound_children_noalloc(*dev, lb, pr, kind=kind, ub=2300, pair_mask=tm, dir_out=dr)
+            torch.cuda.synchronize()
+            free1 = torch.cuda.mem_get_info(ctx.device)[0]
+            if call == 0:
+                # pfsp_bound_children would grow a 48 MB workspace here
+                assert free0 - free1 < 8 << 20
+            ctx.check()
+            rlb, rpr, rdr, _ = ctx.bound_children(*dev, kind=kind, ub=2300, pair_mask=tm)
+            torch.cuda.synchronize()
+            assert torch.equal(lb, rlb)
+            assert torch.equal(pr, rpr)
+            assert torch.equal(dr, rdr)
+            assert 0 < pr.float().mean().item() < 1
+    finally:
+        ctx.close()
+
+
+def test_noalloc_rejects_oversized_pool_and_learned_kind():
+    import torch
+    ctx = binding.Context(0)
+    try:
+        n, m = 20, 20
+        ctx.load_instance(inputs.instance(n, m, 3))
+        count = (1 << 24) // (3 * m) + 1
+        perm, d1, d2 = inputs.random_pool(n, count, 9)
+        dev = [torch.from_numpy(a).to(ctx.device) for a in (perm, d1, d2)]
+        lb = torch.empty((count, 2, n), dtype=torch.int32, device=ctx.device)
+        pr = torch.empty((count, 2, n), dtype=torch.uint8, device=ctx.device)
+        with pytest.raises(binding.PfspError) as e:
+            ctx.bound_children_noalloc(*dev, lb, pr, kind=binding.LB2_FULL)
+        assert e.value.code == binding.PFSP_ERANGE
+        small = [t[:16] for t in dev]
+        with pytest.raises(binding.PfspError) as e:
+            ctx.bound_children_noalloc(*small, lb[:16], pr[:16], kind=binding.LB2_LEARNED)
+        assert e.value.code == binding.PFSP_EINVAL
+        # the largest accepted pool still bounds
+        count -= 1
+        ctx.bound_children_noalloc(dev[0][:count], dev[1][:count], dev[2][:count], lb[:count],
+                                   pr[:count], kind=binding.LB2_FULL, ub=2300)
+        torch.cuda.synchronize()
+        ctx.check()
+        rlb, rpr, _, _ = ctx.bound_children(dev[0][:count], dev[1][:count], dev[2][:count],
+                                            kind=binding.LB2_FULL, ub=2300)
+        torch.cuda.synchronize()
+        assert torch.equal(lb[:count], rlb) and torch.equal(pr[:count], rpr)
+    finally:
+        ctx.close()

@@ -126,12 +126,13 @@ int pfsp_bound_children(pfsp_ctx *c, const pfsp_pool *pool, int lb_kind, int32_t
  * capture, serving loops, harnesses that forbid hipMalloc): the same
  * decomposition as pfsp_bound_children for lb_kind PFSP_LB1, PFSP_LB2_FULL or
  * PFSP_LB2_SUBSET, with the per-parent workspace (front, back and remaining
- * loads, 3m int32 per parent) taken from a fixed 64 MiB device array that each
+ * loads, 3m int32 per parent, and the depth-binned row lists) taken from a fixed 64 MiB device array that each
  * GPU holds from the library's load until the process ends, instead of a
  * workspace grown with hipMalloc.  The call allocates nothing (no hipMalloc,
  * hipFree, events or library allocations); the caller still passes the pool
- * and the outputs.  PFSP_ERANGE if count * 3 * m exceeds 2^24 (e.g. 279,620
- * parents at m = 20); PFSP_EINVAL for PFSP_LB2_LEARNED.  Every call on a GPU
+ * and the outputs.  PFSP_ERANGE if count * (3m + 2) + 2 exceeds 2^24 int32
+ * (the costs and two depth-binned row lists; e.g. 270,600 parents at m = 20);
+ * PFSP_EINVAL for PFSP_LB2_LEARNED.  Every call on a GPU
  * uses that GPU's one array: calls whose work overlaps on one GPU (other
  * contexts, other streams) race; calls queued on one stream are ordered.
  * No kernel-time instrumentation.  Asynchronous on the ctx stream. */
@@ -192,6 +193,10 @@ int pfsp_neh(pfsp_ctx *c, int32_t *perm_out, int32_t *cmax_out);
  * stored value fits 16 bits: 2 or 4, each parent then gets 32 or 16 lanes
  * and a selection of up to that many pairs costs one scan pass; 0 = one
  * parent per wave for PFSP_LB2_SUBSET and by top-k for PFSP_LB2_LEARNED),
+ * "deep_r" (PFSP_LB2_FULL for n <= 32 with (n + m) max p < 2^15: parents
+ * with at most deep_r unscheduled jobs take a kernel that scans only their
+ * jobs' positions in each pair's Johnson order, the others the full-scan
+ * kernel; 0 = every parent takes the full scan; at most 16; default 8),
  * "wide_lb2" (1 = PFSP_LB2_FULL for 32 < n <= 128 with (n + m) max p < 2^15
  * runs the wide kernel, whose entries are staged at pfsp_load_instance;
  * default 1), "log_capacity" (records kept by pfsp_search's node log,

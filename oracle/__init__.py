@@ -60,6 +60,9 @@ def lib():
                                         vp, vp, vp, vp, i32]
         L.or_search.restype = i32
         L.or_search.argtypes = [i32, i32, vp, i64, i32, i64, vp, vp, vp, vp, vp, vp]
+        L.or_search_ex.restype = i32
+        L.or_search_ex.argtypes = [i32, i32, vp, i64, i32, vp, i64, i32, vp, vp, vp, vp, vp,
+                                   vp]
         L.or_bruteforce.restype = i64
         L.or_bruteforce.argtypes = [i32, i32, vp, vp]
         L.or_neh.restype = i64
@@ -173,8 +176,10 @@ def bound_children(p, perm, d1, d2, kind=LB1, ub=INT32_MAX, pair_mask=None,
     return (lb, pr, dr, ap) if with_argpair else (lb, pr, dr)
 
 
-def search(p, ub0=INT32_MAX, kind=LB1, budget=0):
-    """Depth-first B&B; returns dict(best, perm, nodes, children, found, proven)."""
+def search(p, ub0=INT32_MAX, kind=LB1, budget=0, pair_mask=None, threads=1):
+    """Depth-first B&B; returns dict(best, perm, nodes, children, found, proven).
+    kind LB2_SUBSET bounds every node over the pairs of pair_mask (uint32 words);
+    threads > 1 runs the OpenMP-task search (no budget)."""
     p = _ci32(p)
     n, m = p.shape
     best = np.zeros(1, dtype=np.int64)
@@ -183,8 +188,10 @@ def search(p, ub0=INT32_MAX, kind=LB1, budget=0):
     ch = np.zeros(1, dtype=np.int64)
     found = np.zeros(1, dtype=np.int32)
     proven = np.zeros(1, dtype=np.int32)
-    rc = lib().or_search(n, m, _p(p), int(ub0), kind, int(budget), _p(best), _p(perm),
-                         _p(nodes), _p(ch), _p(found), _p(proven))
+    mask = None if pair_mask is None else np.ascontiguousarray(pair_mask, dtype=np.uint32)
+    rc = lib().or_search_ex(n, m, _p(p), int(ub0), kind, None if mask is None else _p(mask),
+                            int(budget), int(threads), _p(best), _p(perm), _p(nodes), _p(ch),
+                            _p(found), _p(proven))
     if rc != 0:
         raise ValueError(f"or_search failed with {rc}")
     return dict(best=int(best[0]), perm=perm, nodes=int(nodes[0]), children=int(ch[0]),

@@ -299,14 +299,31 @@ int or_bound_children(int n, int m, const int32_t *p, int count, const uint8_t *
 /* Depth-first branch-and-bound (Sections 2.2-2.5) with dynamic branching and
  * MinMin.  A child is explored iff its LB < incumbent at the time it is
  * visited; the children of the chosen set are visited in list order; leaves
- * (no unscheduled job left) update the incumbent when strictly better. */
+ * (no unscheduled job left) update the incumbent when strictly better.  With
+ * kind OR_LB2_SUBSET every node is bounded over the same pair set `mask`
+ * (Section 2.4: any number of pairs between m and m(m-1)/2). */
 typedef struct {
-  int n, m, kind;
+  int n, m, kind, cutoff;
   const int32_t *p;
+  const uint32_t *mask;
   int64_t ub, budget, nodes, children;
   int found, aborted;
   uint8_t best[MAXN];
 } search_t;
+
+/* Bounds both children sets of a node and returns the MinMin direction. */
+static int decompose(const search_t *s, const uint8_t *perm, int d1, int d2,
+                     int64_t lb[2][MAXN]) {
+  int n = s->n, r = n - d1 - d2;
+  uint8_t child[MAXN];
+  for (int dir = 0; dir < 2; ++dir)
+    for (int q = 0; q < r; ++q) {
+      make_child(n, perm, d1, d2, q, dir, child);
+      lb[dir][q] = or_node_bound(n, s->m, s->p, child, d1 + (dir == 0), d2 + (dir == 1),
+                                 s->kind, s->mask, NULL);
+    }
+  return or_minmin(r, lb[0], lb[1]);
+}
 
 static void dfs(search_t *s, const uint8_t *perm, int d1, int d2) {
   if (s->budget > 0 && s->nodes >= s->budget) {
@@ -318,13 +335,7 @@ static void dfs(search_t *s, const uint8_t *perm, int d1, int d2) {
   s->children += 2 * r;
   int64_t lb[2][MAXN];
   uint8_t child[MAXN];
-  for (int dir = 0; dir < 2; ++dir)
-    for (int q = 0; q < r; ++q) {
-      make_child(n, perm, d1, d2, q, dir, child);
-      lb[dir][q] = or_node_bound(n, s->m, s->p, child, d1 + (dir == 0), d2 + (dir == 1),
-                                 s->kind, NULL, NULL);
-    }
-  int dir = or_minmin(r, lb[0], lb[1]);
+  int dir = decompose(s, perm, d1, d2, lb);
   for (int q = 0; q < r; ++q) {
     int64_t x = lb[dir][q];
     if (x >= s->ub) continue;
@@ -342,23 +353,77 @@ static void dfs(search_t *s, const uint8_t *perm, int d1, int d2) {
   }
 }
 
+/* The same search with the children of nodes shallower than s->cutoff run
+ * as OpenMP tasks.  The incumbent, the counters and the best schedule are
+ * shared: the incumbent is read atomically when a child is visited and
+ * lowered under a critical section by a strictly better leaf.  When the
+ * incumbent cannot improve (it starts at the optimum) the decomposed nodes
+ * are exactly those of dfs(), in any order. */
+static void dfs_task(search_t *s, const uint8_t *perm, int d1, int d2, int depth) {
+  int n = s->n, r = n - d1 - d2;
+#pragma omp atomic
+  s->nodes += 1;
+#pragma omp atomic
+  s->children += 2 * r;
+  int64_t lb[2][MAXN];
+  int dir = decompose(s, perm, d1, d2, lb);
+  for (int q = 0; q < r; ++q) {
+    int64_t x = lb[dir][q], ub;
+#pragma omp atomic read
+    ub = s->ub;
+    if (x >= ub) continue;
+    uint8_t child[MAXN];
+    make_child(n, perm, d1, d2, q, dir, child);
+    if (r == 1) {
+#pragma omp critical(or_incumbent)
+      {
+        if (x < s->ub) {
+#pragma omp atomic write
+          s->ub = x;
+          s->found = 1;
+          memcpy(s->best, child, (size_t)n);
+        }
+      }
+    } else if (depth < s->cutoff) {
+      int a = d1 + (dir == 0), b = d2 + (dir == 1);
+#pragma omp task firstprivate(child, a, b) shared(s)
+      dfs_task(s, child, a, b, depth + 1);
+    } else {
+      dfs_task(s, child, d1 + (dir == 0), d2 + (dir == 1), depth + 1);
+    }
+  }
+}
+
 /* Searches for a schedule with C_max < ub0.  found = 1 iff one was found
  * (best_cmax / best_perm set); proven = 1 iff the tree was exhausted within
  * the budget (0 = unlimited) of decomposed nodes.  nodes counts decomposed
- * nodes including the root; children counts bounded children (2(n-d) each). */
-int or_search(int n, int m, const int32_t *p, int64_t ub0, int kind, int64_t budget,
-              int64_t *best_cmax, uint8_t *best_perm, int64_t *nodes, int64_t *children,
-              int *found, int *proven) {
+ * nodes including the root; children counts bounded children (2(n-d) each).
+ * kind OR_LB2_SUBSET bounds every node over the pairs of pair_mask (else
+ * ignored).  threads > 1 runs the task-parallel search (budget must be 0). */
+int or_search_ex(int n, int m, const int32_t *p, int64_t ub0, int kind,
+                 const uint32_t *pair_mask, int64_t budget, int threads, int64_t *best_cmax,
+                 uint8_t *best_perm, int64_t *nodes, int64_t *children, int *found,
+                 int *proven) {
   if (n < 2 || n > 255 || m < 1 || m > MAXM) return -1;
-  if (kind != OR_LB1 && kind != OR_LB2_FULL) return -1;
+  if (kind != OR_LB1 && kind != OR_LB2_FULL && kind != OR_LB2_SUBSET) return -1;
   if (kind != OR_LB1 && m < 2) return -1;
+  if (kind == OR_LB2_SUBSET && !pair_mask) return -1;
+  if (threads > 1 && budget > 0) return -1;
   search_t *s = (search_t *)calloc(1, sizeof(search_t));
   if (!s) return -4;
   s->n = n; s->m = m; s->kind = kind; s->p = p;
+  s->mask = kind == OR_LB2_SUBSET ? pair_mask : NULL;
   s->ub = ub0; s->budget = budget;
+  s->cutoff = n / 2;
   uint8_t root[MAXN];
   for (int j = 0; j < n; ++j) root[j] = (uint8_t)j;
-  dfs(s, root, 0, 0);
+  if (threads > 1) {
+#pragma omp parallel num_threads(threads)
+#pragma omp single
+    dfs_task(s, root, 0, 0, 0);
+  } else {
+    dfs(s, root, 0, 0);
+  }
   *best_cmax = s->found ? s->ub : ub0;
   if (s->found && best_perm) memcpy(best_perm, s->best, (size_t)n);
   *nodes = s->nodes;
@@ -367,6 +432,14 @@ int or_search(int n, int m, const int32_t *p, int64_t ub0, int kind, int64_t bud
   *proven = !s->aborted;
   free(s);
   return 0;
+}
+
+int or_search(int n, int m, const int32_t *p, int64_t ub0, int kind, int64_t budget,
+              int64_t *best_cmax, uint8_t *best_perm, int64_t *nodes, int64_t *children,
+              int *found, int *proven) {
+  if (kind != OR_LB1 && kind != OR_LB2_FULL) return -1;
+  return or_search_ex(n, m, p, ub0, kind, NULL, budget, 1, best_cmax, best_perm, nodes,
+                      children, found, proven);
 }
 
 /* Optimal makespan by enumerating all n! permutations (n <= 10 or so). */

@@ -247,6 +247,7 @@ static int64_t *opt_slot(Ctx *c, const char *key) {
   if (!strcmp(key, "lb2_blocks_per_cu")) return &c->lb2_blocks_per_cu;
   if (!strcmp(key, "log_capacity")) return &c->log_capacity;
   if (!strcmp(key, "log_stride")) return &c->log_stride;
+  if (!strcmp(key, "deep_r")) return &c->deep_r;
   return nullptr;
 }
 
@@ -269,6 +270,8 @@ int pfsp_set_option(pfsp_ctx *h, const char *key, int64_t value) {
     return set_err(c, PFSP_ERANGE, "lb2_blocks_per_cu must be in [0, 64]");
   if (!strcmp(key, "subset_group") && value != 0 && value != 1 && value != 2 && value != 4)
     return set_err(c, PFSP_ERANGE, "subset_group must be 0, 1, 2 or 4");
+  if (!strcmp(key, "deep_r") && (value < 0 || value > 16))
+    return set_err(c, PFSP_ERANGE, "deep_r must be in [0, 16]");
   if (!strcmp(key, "lb2_waves") && (value < 0 || value > 16))
     return set_err(c, PFSP_ERANGE, "lb2_waves must be in [0, 16]");
   if (!strcmp(key, "learned_topk") && (value < 1 || value > 2016))

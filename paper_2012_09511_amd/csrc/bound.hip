@@ -174,20 +174,28 @@ __device__ __forceinline__ void lb1_row(const DevInst &I, const int *__restrict_
 // Filter outcome of pool row i (see CostFilter): closed rows get their prune
 // row and direction here, open rows are appended to the list (one atomic per
 // wave).  Whole waves call it.
-__device__ __forceinline__ void filter_row(const CostFilter &f, int i, bool live, bool open,
-                                           int ns, int lane) {
-  const bool app = live && open;
+// deep: the row is valid and has at most f.deep_r unscheduled jobs.
+__device__ __forceinline__ void list_append(int *rows, int *count, bool app, int i, int lane) {
   const uint64_t bal = __ballot(app);
   int base = 0;
   if (bal) {
-    if (lane == 0) base = atomicAdd(f.open, __popcll(bal));
+    if (lane == 0) base = atomicAdd(count, __popcll(bal));
     base = __shfl(base, 0, kWave);
   }
   if (app) {
     const int pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
                                               __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
-    f.rows[base + pos] = i;
-  } else if (live) {
+    rows[base + pos] = i;
+  }
+}
+
+__device__ __forceinline__ void filter_row(const CostFilter &f, int i, bool live, bool open,
+                                           bool deep, int ns, int lane) {
+  const bool app = live && (open || f.keep_all);
+  const bool to_deep = app && deep && f.rows_deep != nullptr;
+  list_append(f.rows, f.open, app && !to_deep, i, lane);
+  if (f.rows_deep) list_append(f.rows_deep, f.open_deep, to_deep, i, lane);
+  if (!app && live) {
     uint8_t *pr = f.out_prune + (size_t)i * 2 * ns;
     for (int x = 0; x < 2 * ns; ++x) pr[x] = 1;
     if (f.dir) f.dir[i] = 0;
@@ -220,7 +228,7 @@ k_lb1(DevInst I, DevPool pool, int ub, int *__restrict__ out_lb, uint8_t *__rest
             write_out ? out_prune + (size_t)i * 2 * ns : nullptr,
             write_out && pool.argpair ? pool.argpair + (size_t)i * 2 * ns : nullptr,
             write_out && pool.dir ? pool.dir + i : nullptr, cs, write_out, flag);
-    if (filt && live && cs[0] >= 0) {
+    if (filt && live && !f.keep_all && cs[0] >= 0) {
       // children's LB1 from the state lb1_row left in the lane's arrays
       const int fub = *f.ub_dev;
       const int *C2 = C1 + m * B, *R = C1 + 2 * m * B;
@@ -240,7 +248,7 @@ k_lb1(DevInst I, DevPool pool, int ub, int *__restrict__ out_lb, uint8_t *__rest
       }
     }
   }
-  if (filt) filter_row(f, i, live, open, ns, t & 63);
+  if (filt) filter_row(f, i, live, open, false, ns, t & 63);
 }
 
 // One parent's costs (front C1, back C2, remaining R; Eq. (1)) for n <= 32
@@ -378,19 +386,22 @@ k_costs(DevInst I, DevPool pool, int *__restrict__ costs, int *__restrict__ flag
   const int count = pool.count_dev ? *pool.count_dev : pool.count;
   const int ns = pool.n;
   const bool filt = f.rows != nullptr;
-  const int ub = filt ? *f.ub_dev : 0;
+  const bool check = filt && !f.keep_all;  // LB1 filter of a search step
+  const int ub = check ? *f.ub_dev : 0;
   // whole waves step together: the tile store is a wave-wide operation
   for (int i0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63); i0 < count;
        i0 += gridDim.x * blockDim.x) {
     const int i = i0 + lane;
-    bool live = false, open = false, valid = false;
+    bool live = false, open = false, valid = false, deep = false;
     if (i < count) {
       live = !filt || !f.alive || f.alive[i];
-      open = costs_row<MMAX, MS>(n, m, sp, sT, pool.perm + (size_t)i * ns, pool.d1[i],
-                                 pool.d2[i], tile + lane * RS, flag, filt && live, ub, &valid);
+      const int a = pool.d1[i], b = pool.d2[i];
+      open = costs_row<MMAX, MS>(n, m, sp, sT, pool.perm + (size_t)i * ns, a, b,
+                                 tile + lane * RS, flag, check && live, ub, &valid);
       open = open && valid;
+      deep = valid && n - a - b <= f.deep_r;
     }
-    if (filt) filter_row(f, i, live, open, ns, lane);
+    if (filt) filter_row(f, i, live, open, deep, ns, lane);
     wave_sync();
     const int rows = min(64, count - i0);
     int *dst = costs + (size_t)i0 * cm;
@@ -1397,6 +1408,251 @@ k_lb2q(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
     lb2q_parent<NMAX, SUBSET, X16>(I, Ppad, S, F, ns, ub, out_lb + (size_t)par * 2 * ns,
                                    out_prune + (size_t)par * 2 * ns,
                                    pool.dir ? pool.dir + par : nullptr, lane, tsrc);
+    par = nxt;
+    F = Fn;
+  }
+}
+
+// ------------------------------------------------------------ deep LB2
+// Full LB2 for parents with few unscheduled jobs (r <= RMAX; n <= 32 with
+// 16-bit X).  The quick kernel scans all n Johnson positions of every pair,
+// members or not, so its cost hardly falls with depth; here each lane visits
+// only the r member positions of its pair, in Johnson order, by taking the
+// set bits of a per-parent position mask from the lowest.  A block-level
+// table gives the position of every job in every pair's order.  The values
+// are those of the quick kernel (same terms, same packed scans); the
+// children are indexed by list slot q (job perm[d1 + q]) instead of job id,
+// so the per-child registers, the LB1 lanes and the fold cover RMAX slots.
+struct DeepLayout {
+  int ppad, mmax, rmax;
+  __host__ __device__ size_t block_bytes(int nmax) const {
+    return align16((size_t)nmax * ppad * 8) + align16((size_t)ppad * 4) +
+           align16((size_t)2 * mmax * 32 * 4) + align16((size_t)ppad * 32);
+  }
+  __host__ __device__ size_t wave_bytes(int nmax) const {
+    return align16((size_t)rmax * 64 * 4) + align16((size_t)mmax * QuickLayout::row(nmax) * 4) +
+           align16((size_t)2 * mmax * 8) + align16((size_t)3 * mmax * 4) + align16(32 * 4);
+  }
+};
+
+// The quick kernel's tables (X with one row per slot, the single X16
+// start-time table) plus the block's position table pos[pass][job][lane].
+template <int NMAX>
+struct DeepLds {
+  uint2 *ent;
+  int *uv, *pt, *pr;
+  uint8_t *pos;
+  int *X;
+  int *FBf;
+  int2 *HTf, *HTb;
+  int *c1, *c2, *rr, *inv;
+  __device__ DeepLds(unsigned char *sm, const DeepLayout &L, int w) {
+    ent = (uint2 *)sm;
+    size_t off = align16((size_t)NMAX * L.ppad * 8);
+    uv = (int *)(sm + off);
+    off += align16((size_t)L.ppad * 4);
+    pt = (int *)(sm + off);
+    pr = pt + L.mmax * 32;
+    off += align16((size_t)2 * L.mmax * 32 * 4);
+    pos = sm + off;
+    off += align16((size_t)L.ppad * 32);
+    unsigned char *wb = sm + off + (size_t)w * L.wave_bytes(NMAX);
+    X = (int *)wb;
+    wb += align16((size_t)L.rmax * 64 * 4);
+    FBf = (int *)wb;
+    wb += align16((size_t)L.mmax * QuickLayout::row(NMAX) * 4);
+    HTf = (int2 *)wb;
+    HTb = HTf + L.mmax;
+    wb += align16((size_t)2 * L.mmax * 8);
+    c1 = (int *)wb;
+    c2 = c1 + L.mmax;
+    rr = c2 + L.mmax;
+    wb += align16((size_t)3 * L.mmax * 4);
+    inv = (int *)wb;
+  }
+};
+
+// Block-cooperative: pos[pass][job][lane] = Johnson position of job in the
+// order of pair pass * 64 + lane (u8).  No barrier inside.
+template <int NMAX>
+__device__ void lb2d_stage_pos(const DevInst &I, int Ppad, uint8_t *__restrict__ pos) {
+  const int n = I.n, P = I.P;
+  for (int x = threadIdx.x; x < n * Ppad; x += blockDim.x) {
+    const int pass = x / (n * 64), rem = x - pass * n * 64;
+    const int i = rem >> 6, l = rem & 63, pi = pass * 64 + l;
+    const unsigned k = I.ent[(size_t)i * P + (pi < P ? pi : 0)].y >> 24;
+    pos[(pass * 32 + (int)k) * 64 + l] = (uint8_t)i;
+  }
+}
+
+template <int NMAX, int RMAX>
+__device__ void lb2d_parent(const DevInst &I, int Ppad, const DeepLds<NMAX> &S,
+                            const PackFetch &F, int stride,
+                            int ub, int *__restrict__ lbrow, uint8_t *__restrict__ prow,
+                            uint8_t *__restrict__ dirp, int lane, int tsrc) {
+  constexpr int ROW = QuickLayout::row(NMAX);
+  const int n = I.n, m = I.m, P = I.P;
+  const int a = __builtin_amdgcn_readfirstlane(F.d1), b = __builtin_amdgcn_readfirstlane(F.d2);
+  const int r = n - a - b;
+  if (r < 1 || r > RMAX || __builtin_amdgcn_readfirstlane(F.c1) < 0) {
+    // an invalid row (flagged by the costs kernel); rows deeper than RMAX are
+    // never listed for this kernel
+    fill_invalid(lbrow, prow, nullptr, stride, 0, lane, 64);
+    if (dirp && lane == 0) *dirp = 0;
+    return;
+  }
+  if (lane < m) {
+    S.c1[lane] = F.c1;
+    S.c2[lane] = F.c2;
+    S.rr[lane] = F.rr;
+    S.HTf[lane] = make_int2(F.c1, F.rr + F.c2);
+    S.HTb[m - 1 - lane] = make_int2(F.c2, F.c1 + F.rr);
+  }
+  // slot q: the q-th unscheduled job of the list; lanes >= 32 its backward child
+  const int q = lane & 31;
+  const bool bwd = lane >= 32;
+  const bool member = q < r;
+  const int jq = __shfl(F.rb, a + (member ? q : 0), kWave);
+  // slot of every job, for the X rows (only members are read)
+  if (lane < r) S.inv[jq] = lane;
+  wave_sync();
+  // LB1 of both children of slot q, and their start times: f of machine s in
+  // the low half of [s][job], g of machine m - 1 - s in the high half
+  int lb1 = 0;
+  if (member) {
+    const int2 *HT = bwd ? S.HTb : S.HTf;
+    const int *PT = (bwd ? S.pr : S.pt) + jq;
+    unsigned short *fb16 = (unsigned short *)S.FBf + 2 * jq + (bwd ? 1 : 0);
+    int c = 0;
+#pragma unroll 4
+    for (int s = 0; s < m; ++s) {
+      const int2 ht = HT[s];
+      const int f = max(c, ht.x);
+      c = f + PT[s * 32];
+      fb16[s * 2 * ROW] = (unsigned short)f;
+      lb1 = max(lb1, f + ht.y);
+    }
+  }
+  wave_sync();
+  int acc[RMAX];
+#pragma unroll
+  for (int x = 0; x < RMAX; ++x) {
+    acc[x] = (int)0x80008000u;
+    asm volatile("" : "+v"(acc[x]));
+  }
+  const int npass = r < 2 || P == 0 ? 0 : Ppad;  // one job left: LB2 = LB1
+  constexpr int NEGX = -(1 << 14);
+  int *__restrict__ Xh = S.X + lane;
+  for (int pc = 0; pc < npass; pc += 64) {
+    const int pi = pc + lane;
+    const int uvp = S.uv[pi];
+    const int u = uvp & 0xff, v = uvp >> 8;
+    const int K4 = S.rr[v] + S.c2[v], K5 = S.c1[u] + S.rr[v];
+    const int *Fu = lds_opaque(S.FBf + u * ROW);
+    const int *Gv = lds_opaque(S.FBf + (m - 1 - v) * ROW);
+    const uint2 *__restrict__ eb = S.ent + (pi >> 6) * (NMAX * 64) + (pi & 63);
+    const uint8_t *__restrict__ pb = S.pos + (pi >> 6) * (32 * 64) + (pi & 63);
+    // positions of the members in this pair's Johnson order
+    uint32_t pm = 0u;
+#pragma unroll
+    for (int x = 0; x < RMAX; ++x) {
+      if (x < r) {
+        const int j = __builtin_amdgcn_readlane(jq, x);
+        pm |= 1u << pb[j * 64];
+      }
+    }
+    // forward scan over the members: per member one int16 pair (prefix
+    // maximum less b - a, term) and b - a with the member's X row offset
+    int pt[RMAX];
+    unsigned ke[RMAX];
+    int Y = K4, Pm = NEGX;
+#pragma unroll
+    for (int x = 0; x < RMAX; ++x) {
+      if (x < r) {
+        const int p = __builtin_ctz(pm);
+        pm &= pm - 1u;
+        const uint2 e = eb[p * 64];
+        const int term = Y + (int)(e.y >> 16);
+        pt[x] = (int)__builtin_amdgcn_perm((unsigned)term, (unsigned)(Pm - (int)e.x), 0x05040100u);
+        const int slot = S.inv[e.y & 31u];
+        ke[x] = (e.x & 0xffffu) | ((unsigned)slot << 24);
+        Pm = max(Pm, term);
+        Y -= (int)e.x;  // Y += a - b
+      }
+    }
+    // backward scan: Xa (low) and Xb + K5 (high) per member, into its X row
+    const int K5x = K5 - K4;
+    int R = (int)0xC000C000u;
+#pragma unroll
+    for (int x = RMAX - 1; x >= 0; --x) {
+      if (x < r) {
+        R = pk_max_hi(pt[x], R);
+        *(int *)((char *)Xh + (ke[x] >> 16)) = (int)__builtin_amdgcn_perm(
+            (unsigned)(R + (int)ke[x] + K5x), (unsigned)R, 0x05040100u);
+      }
+    }
+    // children of every slot: f_u + Xa | g_v + Xb in int16 halves
+#pragma unroll
+    for (int x = 0; x < RMAX; ++x) {
+      if (x < r) {
+        const int j = __builtin_amdgcn_readlane(jq, x);
+        const int h = Xh[x * 64];
+        const int fw = Fu[j], gw = Gv[j];
+        acc[x] = pk_max(acc[x], pk_add((int)__builtin_amdgcn_perm((unsigned)gw, (unsigned)fw,
+                                                                  0x07060100u),
+                                       h));
+      }
+    }
+  }
+  const int t = transpose_pkmax<RMAX>(acc, lane, tsrc);
+  const int val = member ? max(lb1, t) : kInt32Max;
+  if (member) {
+    const int o = (bwd ? stride : 0) + q;
+    lbrow[o] = val;
+    prow[o] = val >= ub;
+  }
+  fill_invalid(lbrow, prow, nullptr, stride, r, lane, 64);
+  if (dirp) {
+    const int cmn = wave_min_xl(val);
+    const uint64_t at = __ballot(member && val == cmn);
+    const int cf = __popc((uint32_t)at), cb = __popc((uint32_t)(at >> 32));
+    const int s = half_sum(member ? val : 0);  // bounds below 2^15: sums below 2^20
+    MinMin mm;
+    mm.init();
+    mm.merge(cmn, cf, cb, __builtin_amdgcn_readlane(s, 0), __builtin_amdgcn_readlane(s, 32));
+    if (lane == 0) *dirp = (uint8_t)mm.dir();
+  }
+  wave_sync();  // the next parent rewrites this wave's tables
+}
+
+template <int NMAX, int RMAX>
+__global__ void __launch_bounds__(1024)
+k_lb2d(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__restrict__ out_lb,
+       uint8_t *__restrict__ out_prune, int Ppad) {
+  extern __shared__ __align__(16) unsigned char sm[];
+  const int nw = blockDim.x >> 6, lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int count = pool.count_dev ? *pool.count_dev : pool.count;
+  if ((int)blockIdx.x * nw >= count) return;
+  const DeepLayout L{Ppad, I.m, RMAX};
+  const DeepLds<NMAX> S(sm, L, w);
+  lb2q_stage<NMAX>(I, Ppad, S);
+  lb2d_stage_pos<NMAX>(I, Ppad, S.pos);
+  __syncthreads();
+  if (pool.ub_dev) ub = *pool.ub_dev;
+  const int n = I.n, m = I.m, ns = pool.n;
+  const int step = gridDim.x * nw;
+  auto row_of = [&](int x) { return x < count ? (pool.index ? pool.index[x] : x) : -1; };
+  int it = blockIdx.x * nw + w;
+  int par = row_of(it);
+  PackFetch F = pack_fetch(pool, par, n, m, costs, lane);
+  const int tsrc = tp_source<RMAX>(lane);
+  for (; it < count; it += step) {
+    const int nxt = row_of(it + step);
+    const PackFetch Fn = pack_fetch(pool, nxt, n, m, costs, lane);
+    lb2d_parent<NMAX, RMAX>(I, Ppad, S, F, ns, ub, out_lb + (size_t)par * 2 * ns,
+                            out_prune + (size_t)par * 2 * ns,
+                            pool.dir ? pool.dir + par : nullptr, lane, tsrc);
     par = nxt;
     F = Fn;
   }
@@ -2421,10 +2677,18 @@ static int fast_nmax(int n, int l16) {
 }
 
 __global__ void k_zero(int *p) { *p = 0; }
+__global__ void k_zero2(int *p) {
+  p[0] = 0;
+  p[1] = 0;
+}
 
 // -------------------------------------------------------------------- host
+size_t workspace_ints(const Ctx *c, int count) {
+  return (size_t)(count > 0 ? count : 1) * (3 * c->m + 2) + 2;
+}
+
 int ensure_costs(Ctx *c, int count) {
-  const size_t need = (size_t)(count > 0 ? count : 1) * 3 * c->m;
+  const size_t need = workspace_ints(c, count);
   if (need > c->costs_cap) {
     if (c->d_costs) {
       PFSP_HIP(c, hipStreamSynchronize(c->stream));
@@ -2504,6 +2768,13 @@ static void attr_lb2() {
 template <int NMAX, int G>
 static void attr_lb2s() {
   lds_limit((const void *)k_lb2s<NMAX, G>);
+}
+
+template <int NMAX>
+static void attr_lb2d() {
+  lds_limit((const void *)k_lb2d<NMAX, 4>);
+  lds_limit((const void *)k_lb2d<NMAX, 8>);
+  lds_limit((const void *)k_lb2d<NMAX, 16>);
 }
 
 template <int NMAX>
@@ -2618,6 +2889,12 @@ void init_bound_attributes() {
   attr_lb2f<24>();
   attr_lb2f<32>();
   attr_lb2f<64>();
+  attr_lb2d<8>();
+  attr_lb2d<12>();
+  attr_lb2d<16>();
+  attr_lb2d<20>();
+  attr_lb2d<24>();
+  attr_lb2d<32>();
   (void)hipGetLastError();  // a refused attribute must not surface as a later launch error
 }
 
@@ -2669,9 +2946,44 @@ int launch_costs(Ctx *c, const DevPool &pool, hipStream_t s, const CostFilter *f
   return PFSP_OK;
 }
 
+int deep_bin_r(const Ctx *c, int kind, bool log) {
+  if (kind != PFSP_LB2_FULL || log || c->deep_r < 2 || c->force_generic) return 0;
+  // the quick kernels' tables with 16-bit X; the costs kernel bins the rows
+  if (!c->narrow || !c->x16 || c->n > 32 || c->m > 32 || c->P < 1) return 0;
+  const int nmax = fast_nmax(c->n, c->l16);
+  return nmax && nmax <= 32 ? (int)c->deep_r : 0;
+}
+
 int launch_bound(Ctx *c, const DevPool &pool, int kind, int ub, int *out_lb, uint8_t *out_prune,
                  hipStream_t s) {
   if (pool.count <= 0) return PFSP_OK;
+  const int deep = deep_bin_r(c, kind, pool.argpair != nullptr);
+  if (deep && !pool.index && !pool.count_dev) {
+    // The costs kernel lists the rows with at most `deep` jobs left for the
+    // deep kernel and every other row for the quick kernel.
+    int rc = ensure_costs(c, pool.count);
+    if (rc) return rc;
+    int *lists = c->d_costs + (size_t)pool.count * 3 * c->m;
+    int *cnt = lists + 2 * (size_t)pool.count;
+    hipLaunchKernelGGL(k_zero2, dim3(1), dim3(1), 0, s, cnt);
+    CostFilter f{};
+    f.rows = lists;
+    f.open = cnt;
+    f.rows_deep = lists + pool.count;
+    f.open_deep = cnt + 1;
+    f.deep_r = deep;
+    f.keep_all = 1;
+    rc = launch_costs(c, pool, s, &f);
+    if (rc) return rc;
+    DevPool dp = pool, dd = pool;
+    dp.index = f.rows;
+    dp.count_dev = f.open;
+    dd.index = f.rows_deep;
+    dd.count_dev = f.open_deep;
+    rc = launch_bound_costs_ready(c, dp, kind, ub, out_lb, out_prune, s, 0);
+    if (rc) return rc;
+    return launch_lb2d(c, dd, ub, out_lb, out_prune, s);
+  }
   if (kind == PFSP_LB1) {
     int b1, g1;
     size_t lds1;
@@ -2768,6 +3080,58 @@ static int launch_lb2w(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8_t
   else
     hipLaunchKernelGGL(k_lb2w<128>, dim3(grid), dim3(64 * waves), lds, s, I, pool, ub,
                        c->d_costs, out_lb, out_prune, Ppad);
+  PFSP_HIP(c, hipGetLastError());
+  return PFSP_OK;
+}
+
+static size_t lb2d_lds(const Ctx *c, int nmax, int rmax, int waves) {
+  const DeepLayout L{(c->P + 63) / 64 * 64, c->m, rmax};
+  return L.block_bytes(nmax) + (size_t)waves * L.wave_bytes(nmax);
+}
+
+int launch_lb2d(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8_t *out_prune,
+                hipStream_t s) {
+  if (pool.count <= 0) return PFSP_OK;
+  const int nmax = fast_nmax(c->n, c->l16);
+  const int r = deep_bin_r(c, PFSP_LB2_FULL, false);
+  if (!r || !nmax || nmax > 32) return set_err(c, PFSP_EINVAL, "deep LB2 kernel does not apply");
+  const int rmax = r <= 4 ? 4 : r <= 8 ? 8 : 16;
+  int waves = 0, best = 0;
+  for (int w = 16; w >= 1; --w) {
+    const size_t l = lb2d_lds(c, nmax, rmax, w);
+    const int per_cu = l <= 160 * 1024 ? (int)((160 * 1024) / l) * w : 0;
+    if (per_cu > best) {
+      best = per_cu;
+      waves = w;
+    }
+  }
+  if (c->lb2_waves > 0 && lb2d_lds(c, nmax, rmax, (int)c->lb2_waves) <= 160 * 1024)
+    waves = (int)c->lb2_waves;
+  if (!waves) return set_err(c, PFSP_ERANGE, "deep LB2 tables exceed LDS");
+  const size_t lds = lb2d_lds(c, nmax, rmax, waves);
+  const int Ppad = (c->P + 63) / 64 * 64;
+  int grid = (pool.count + waves - 1) / waves;
+  const int resident = std::max(1, (int)((160 * 1024) / std::max<size_t>(lds, 1)));
+  const int cap = c->cu_count * (int)(c->lb2_blocks_per_cu > 0 ? c->lb2_blocks_per_cu
+                                                               : 2 * resident);
+  if (grid > cap) grid = cap;
+  const DevInst I = c->inst();
+  KTimer kt(c, s, "k_lb2d");
+#define PFSP_D(N, R)                                                                          \
+  hipLaunchKernelGGL((k_lb2d<N, R>), dim3(grid), dim3(64 * waves), lds, s, I, pool, ub,        \
+                     c->d_costs, out_lb, out_prune, Ppad)
+#define PFSP_DN(N)                    \
+  case N:                             \
+    if (rmax == 4) PFSP_D(N, 4);      \
+    else if (rmax == 8) PFSP_D(N, 8); \
+    else PFSP_D(N, 16);               \
+    break;
+  switch (nmax) {
+    PFSP_DN(8) PFSP_DN(12) PFSP_DN(16) PFSP_DN(20) PFSP_DN(24) PFSP_DN(32)
+    default: break;
+  }
+#undef PFSP_DN
+#undef PFSP_D
   PFSP_HIP(c, hipGetLastError());
   return PFSP_OK;
 }

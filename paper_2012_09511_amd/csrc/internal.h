@@ -56,6 +56,10 @@ struct DevPool {
 //    written here (all pruned, direction 0) and it is left out of the bound
 //    kernels;
 //  - every other parent is appended to rows[0 .. *open) (any order).
+//  - keep_all: no row is closed (the LB1 check is skipped); every row of the
+//    launch goes to a list.  Used to bin a plain decomposition by depth;
+//  - rows_deep (optional): open valid rows with at most deep_r unscheduled
+//    jobs go to rows_deep[0 .. *open_deep) instead (the deep LB2 kernel).
 struct CostFilter {
   const uint8_t *alive;
   const int *ub_dev;
@@ -63,6 +67,10 @@ struct CostFilter {
   uint8_t *dir;
   int *rows;
   int *open;
+  int *rows_deep = nullptr;
+  int *open_deep = nullptr;
+  int deep_r = 0;
+  int keep_all = 0;
 };
 
 struct Selector;   // learned pair selector state (selector.hip)
@@ -105,6 +113,7 @@ struct Ctx {
   int64_t log_capacity = 0;   // search node log size in records (0 = off)
   int64_t log_stride = 1;     // log every log_stride-th decomposed node of a batch
   int64_t wide_lb2 = 1;       // full LB2 for 32 < n <= 128 with 16-bit X takes k_lb2w
+  int64_t deep_r = 8;         // full LB2: parents with at most deep_r jobs left take k_lb2d
   struct Pending {
     const char *name;
     hipEvent_t a, b;
@@ -172,6 +181,16 @@ int launch_costs(Ctx *c, const DevPool &pool, hipStream_t s, const CostFilter *f
 int launch_bound_costs_ready(Ctx *c, const DevPool &pool, int kind, int ub, int *out_lb,
                              uint8_t *out_prune, hipStream_t s, int group = 0);
 size_t lb2_lds_bytes(const Ctx *c, int waves);
+// Depth threshold of the deep LB2 kernel for this context and kind (0: the
+// kernel does not apply; every parent takes the other LB2 kernels).
+int deep_bin_r(const Ctx *c, int kind, bool log);
+// Full LB2 of the pool's parents (index list, count_dev) with the deep
+// kernel; every listed parent must have at most deep_bin_r jobs left.
+int launch_lb2d(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8_t *out_prune,
+                hipStream_t s);
+// Workspace of pfsp_bound_children: per parent 3m costs, then two index
+// lists of count rows and two counters.
+size_t workspace_ints(const Ctx *c, int count);
 void init_bound_attributes();
 void init_selector_attributes();
 // multi-instance launches (bound.hip)

@@ -58,9 +58,9 @@ extern "C" int pfsp_bound_children_noalloc(pfsp_ctx *h, const pfsp_pool *pool, i
     return set_err(c, PFSP_EINVAL,
                    "pfsp_bound_children_noalloc takes PFSP_LB1, PFSP_LB2_FULL or PFSP_LB2_SUBSET");
   if (pool->count < 0) return set_err(c, PFSP_EINVAL, "negative count");
-  if ((size_t)pool->count * 3 * (size_t)c->m > kScratchInts)
+  if (workspace_ints(c, pool->count) > kScratchInts)
     return set_err(c, PFSP_ERANGE,
-                   "pool too large for the fixed workspace: count * 3 * m must be <= " +
+                   "pool too large for the fixed workspace: count * (3m + 2) + 2 must be <= " +
                        std::to_string(kScratchInts));
   if (!c->scratch) return set_err(c, PFSP_EDEVICE, "scratch address not set up");
   // The shared bound path with the workspace pointed at this device's

@@ -133,6 +133,32 @@ def test_quick_kernel_value_ranges(ctx, n, m, lo, hi):
     _check(ctx, p, perm, d1, d2, binding.LB2_SUBSET, INT32_MAX, mask=mask)
 
 
+@pytest.mark.parametrize("deep_r", [4, 8, 16])
+@pytest.mark.parametrize("n,m,lo,hi", [(20, 20, 1, 99), (20, 20, 700, 819), (12, 7, 1, 99),
+                                       (32, 3, 1, 99), (8, 5, 1, 99), (32, 20, 500, 630),
+                                       (24, 32, 1, 99), (3, 2, 1, 99)])
+def test_deep_kernel_parity(ctx, deep_r, n, m, lo, hi):
+    """Full LB2 with the pool split by depth: parents with at most deep_r jobs
+    left take the deep kernel (members-only scans), the others the quick
+    kernel.  Every depth from the root to one job left, at the edges of the
+    16-bit value range; the deep kernel must actually have run."""
+    rng = np.random.default_rng(n * 7 + m + hi)
+    p = rng.integers(lo, hi + 1, size=(n, m)).astype(np.int32)
+    parts = [inputs.random_pool(n, 12, 50 + d, depth=d) for d in range(n)]
+    perm, d1, d2 = (np.concatenate([q[i] for q in parts]) for i in range(3))
+    ctx.set_option("deep_r", deep_r)
+    ctx.set_option("timing", 1)
+    try:
+        ctx.load_instance(p)
+        ctx.kernel_time("k_lb2d", reset=True)
+        olb = _check(ctx, p, perm, d1, d2, binding.LB2_FULL, INT32_MAX)
+        _check(ctx, p, perm, d1, d2, binding.LB2_FULL, int(np.median(olb[olb < INT32_MAX])))
+        assert ctx.kernel_time("k_lb2d")[1] == 2
+    finally:
+        ctx.set_option("deep_r", 8)
+        ctx.set_option("timing", 0)
+
+
 def _random_masks(rng, count, m, kmax):
     """Per row a uniform number of distinct pairs in [0, kmax], as bit masks."""
     P = m * (m - 1) // 2

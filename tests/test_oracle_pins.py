@@ -418,3 +418,43 @@ def test_neh_is_a_feasible_upper_bound():
         c, perm = oracle.neh(p)
         assert sorted(perm) == list(range(8))
         assert c == oracle.makespan(p, perm) >= oracle.bruteforce(p)[0]
+
+
+@pytest.mark.parametrize("threads", [2, 4, 8])
+def test_parallel_search_matches_serial(threads):
+    """The OpenMP-task search finds the brute-force optimum, and with the
+    incumbent at the optimum decomposes exactly the serial search's nodes (the
+    critical tree does not depend on the visiting order, Section 2.5)."""
+    for seed in (3, 9):
+        p = inputs.instance(9, 4, 700 + seed)
+        opt, _ = oracle.bruteforce(p)
+        for kind in (oracle.LB1, oracle.LB2_FULL):
+            r = oracle.search(p, 10**9, kind, threads=threads)
+            assert r["proven"] and r["found"] and r["best"] == opt
+            assert oracle.makespan(p, r["perm"]) == opt
+            a = oracle.search(p, opt, kind)
+            b = oracle.search(p, opt, kind, threads=threads)
+            assert not b["found"] and (a["nodes"], a["children"]) == (b["nodes"], b["children"])
+
+
+def test_static_subset_search():
+    """A search whose nodes are all bounded over one fixed pair set (Section
+    2.4 variants): every pair reproduces full LB2 node for node, no pair
+    reproduces LB1, and any subset proves the brute-force optimum."""
+    p = inputs.instance(9, 5, 77)
+    opt, _ = oracle.bruteforce(p)
+    P = 10
+    full = np.array([(1 << P) - 1], dtype=np.uint32)
+    none = np.array([0], dtype=np.uint32)
+    for ub in (opt, 10**9):
+        a = oracle.search(p, ub, oracle.LB2_FULL)
+        b = oracle.search(p, ub, oracle.LB2_SUBSET, pair_mask=full)
+        assert (a["best"], a["nodes"], a["children"]) == (b["best"], b["nodes"], b["children"])
+        a = oracle.search(p, ub, oracle.LB1)
+        b = oracle.search(p, ub, oracle.LB2_SUBSET, pair_mask=none)
+        assert (a["best"], a["nodes"], a["children"]) == (b["best"], b["nodes"], b["children"])
+    rng = np.random.default_rng(5)
+    for _ in range(4):
+        mask = np.array([rng.integers(0, 1 << P)], dtype=np.uint32)
+        r = oracle.search(p, 10**9, oracle.LB2_SUBSET, pair_mask=mask, threads=4)
+        assert r["proven"] and r["best"] == opt

@@ -42,14 +42,32 @@ PEAK_HBM = 8e12
 
 
 def alg_ops_lb2(n, m, d1, d2):
-    """Algorithmic int32 operations of LB2 bounding for the given parents.
+    """Algorithmic int32 operations of full LB2 for the given parents.
 
-    The count of the O(1)-per-child reformulation of the pair bound, fixed
-    before any kernel was written: per parent and machine pair, one pass over
-    the n jobs of the pair's Johnson order plus 16 operations for each of the
-    2(n - d) children, i.e. P * (n + 32 (n - d)) per parent.  It is a
-    yardstick for the work, not a count of the instructions a kernel issues.
+    The O(1)-per-child reformulation of the two-machine bound run over the
+    parent's r = n - d unscheduled jobs only (the jobs' Johnson positions in
+    each pair's order), counting the operations the method cannot avoid:
+      per machine pair and unscheduled job: forward scan 3 (term, prefix
+      maximum, running sum), backward scan 4 (suffix maximum, X_a = max(PM -
+      (b - a), SM), X_b = X_a + b - a), children 4 (an add and a max for
+      each direction);
+      per child (2r of them) and machine: 4 for its start times and LB1.
+    So 11 r P + 8 r m per parent (a parent with one job left needs LB1 only:
+    8 m).  Every kernel issues at least this many lane operations per parent,
+    so achieved / peak stays at most 1 at every depth.
     """
+    P = m * (m - 1) // 2
+    r = n - d1.astype(np.int64) - d2.astype(np.int64)
+    ops = np.where(r >= 2, 11 * r * P + 8 * r * m, 8 * m)
+    return int(ops.sum())
+
+
+def yardstick_ops_lb2(n, m, d1, d2):
+    """The count fixed before any kernel was written, P (n + 32 (n - d)) per
+    parent: one pass over all n Johnson positions per pair plus 16 operations
+    per child, pair and direction.  It over-counts the children and
+    under-counts the scans (its fraction exceeds 1 at the root), so it is
+    reported only as a yardstick next to the algorithmic count."""
     P = m * (m - 1) // 2
     r = n - d1.astype(np.int64) - d2.astype(np.int64)
     return int((P * (n + 32 * r)).sum())
@@ -82,10 +100,25 @@ def profiled_traffic(kernel):
     return rec
 
 
+def host_cpu():
+    """Cores this process may use, the machine's logical CPU count and model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return len(os.sched_getaffinity(0)), os.cpu_count(), model
+
+
 def cpu_baseline(p, perm, d1, d2, kind, target_s=12.0, threads=None):
     import oracle
+    cores, nproc, model = host_cpu()
     if threads is None:
-        threads = max(1, min(len(os.sched_getaffinity(0)), 16))
+        threads = cores
     # calibrate on samples growing until one takes 0.5 s (thread start-up
     # dominates tiny ones), then run ~target_s of work
     k = 64
@@ -104,7 +137,8 @@ def cpu_baseline(p, perm, d1, d2, kind, target_s=12.0, threads=None):
     children = int((2 * (n - d1[:k2].astype(np.int64) - d2[:k2].astype(np.int64))).sum())
     return dict(value=children / dt, unit="children/s", cores=threads, kind="oracle",
                 sample=f"first {k2} parents of the same pool ({children} children), "
-                       f"{dt:.1f} s" + (", OpenMP over parents" if threads > 1 else ""))
+                       f"{dt:.1f} s" + (", OpenMP over parents" if threads > 1 else ""),
+                nproc=nproc, cpu_model=model)
 
 
 def main():
@@ -117,6 +151,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the fixed-depth sweep (profiles of the headline launch alone)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="bound workload without the search and learned summaries")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--workload", default="bound", choices=["bound", "search", "multi", "learned"])
@@ -178,29 +214,20 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.check()
-    dom = "k_lb2" if kind != binding.LB1 else "k_lb1"
-    ms_dom, launches = ctx.kernel_time(dom)
-    ms_costs, lc = ctx.kernel_time("k_costs")
-    ms_lb1, l1 = ctx.kernel_time("k_lb1", reset=True)  # (reset clears every kernel's total)
+    kt = {k: ctx.kernel_time(k) for k in ("k_costs", "k_lb1", "k_lb2", "k_lb2d")}
+    ctx.kernel_time("k_lb2", reset=True)   # (reset clears every kernel's total)
     ctx.set_option("timing", 0)
+    per_launch = {k: ms / l for k, (ms, l) in kt.items() if l > 0}
     elapsed = t1 - t0
     value = children * args.steps / elapsed
-    dom_ms = ms_dom / max(launches, 1)
     if kind != binding.LB1:
-        ops = alg_ops_lb2(n, m, d1, d2)
-        achieved = ops / (dom_ms * 1e-3)
-        prof = profiled_traffic("pfsp::k_lb2q<20, false, true>")
-        roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_INT32_OPS / 1e12,
-                    unit="TOP/s", frac=achieved / PEAK_INT32_OPS,
-                    traffic=prof["traffic_bytes"] if prof else None,
-                    kernel=dom, kernel_ms=dom_ms, alg_ops_per_launch=ops,
-                    op_count="P*(n+32(n-d)) per parent: O(1)-per-child pair bound",
-                    valu_issue_frac=prof["valu_issue_frac"] if prof else None)
+        roof = lb2_roofline(n, m, d1, d2, per_launch, ctx.get_option("deep_r"))
     else:
         b = bytes_lb2(n, m, N)
+        dom_ms = per_launch["k_lb1"]
         achieved = b / (dom_ms * 1e-3)
         roof = dict(bound="hbm", achieved=achieved / 1e9, peak=PEAK_HBM / 1e9, unit="GB/s",
-                    frac=achieved / PEAK_HBM, traffic=None, kernel=dom, kernel_ms=dom_ms)
+                    frac=achieved / PEAK_HBM, traffic=None, kernel="k_lb1", kernel_ms=dom_ms)
     out = dict(metric=METRIC, value=value, unit="children/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=elapsed / args.steps * 1e3,
                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="int32",
@@ -208,22 +235,54 @@ def main():
                config=dict(workload=f"{args.kind} decomposition of {N} random bidirectional "
                                     f"partial schedules, one n=20 x m=20 instance, p~U[1,99]",
                            n=n, m=m, parents=N, children=children, lb_kind=args.kind, ub=ub,
-                           instance_seed=2012, pool_seed=9511),
-               roofline=roof,
-               kernels_ms={k: v for k, v in (("k_costs", ms_costs / max(lc, 1)),
-                                             ("k_lb1", ms_lb1 / max(l1, 1)), (dom, dom_ms))
-                           if v > 0})
+                           instance_seed=2012, pool_seed=9511,
+                           deep_r=ctx.get_option("deep_r")),
+               roofline=roof, kernels_ms=per_launch)
     if kind != binding.LB1 and not args.no_sweep:
         out["depth_sweep"] = depth_sweep(ctx, torch, binding, inputs, n, m, ub)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, perm, d1, d2, kind)
         out["cpu_baseline_1core"] = cpu_baseline(p, perm, d1, d2, kind, target_s=8.0, threads=1)
     ctx.close()
+    if not args.headline_only:
+        out["search"] = search_summary(args, with_cpu=not args.no_cpu)
+        out["learned"] = learned_summary(args)
     print(json.dumps(out))
 
 
-def depth_sweep(ctx, torch, binding, inputs, n, m, ub, depths=(0, 5, 10, 15, 18), N=1 << 18):
-    """LB2 kernel time and roofline fraction on pools of one fixed depth d (d1 ~ U{0..d})."""
+def lb2_roofline(n, m, d1, d2, per_launch, deep_r):
+    """Roofline entry of the LB2 stage: each kernel's algorithmic operations
+    (alg_ops_lb2 over the parents it bounds) over its mean launch time."""
+    r = n - d1.astype(np.int64) - d2.astype(np.int64)
+    deep = (r <= deep_r) if deep_r else np.zeros_like(r, dtype=bool)
+    parts = {"k_lb2": ~deep, "k_lb2d": deep}
+    ker = {}
+    for k, sel in parts.items():
+        if k in per_launch and sel.any():
+            ops = alg_ops_lb2(n, m, d1[sel], d2[sel])
+            ker[k] = dict(parents=int(sel.sum()), alg_ops=ops, ms=per_launch[k],
+                          frac=ops / (per_launch[k] * 1e-3) / PEAK_INT32_OPS)
+    dom = max(ker, key=lambda k: ker[k]["ms"])
+    ops_all = alg_ops_lb2(n, m, d1, d2)
+    ms_all = sum(v["ms"] for v in ker.values())
+    prof = profiled_traffic("pfsp::k_lb2q<20, false, true>")
+    return dict(bound="alu", achieved=ker[dom]["alg_ops"] / (ker[dom]["ms"] * 1e-3) / 1e12,
+                peak=PEAK_INT32_OPS / 1e12, unit="TOP/s", frac=ker[dom]["frac"],
+                traffic=prof["traffic_bytes"] if prof and dom == "k_lb2" else None,
+                kernel=dom, kernel_ms=ker[dom]["ms"], alg_ops_per_launch=ker[dom]["alg_ops"],
+                op_count="11 r P + 8 r m per parent (members-only O(1)-per-child LB2, r jobs "
+                         "left, P pairs): alg_ops_lb2",
+                valu_issue_frac=prof["valu_issue_frac"] if prof and dom == "k_lb2" else None,
+                kernels=ker,
+                lb2_stage=dict(ms=ms_all, frac=ops_all / (ms_all * 1e-3) / PEAK_INT32_OPS),
+                yardstick_frac=yardstick_ops_lb2(n, m, d1, d2) / (ms_all * 1e-3) /
+                PEAK_INT32_OPS)
+
+
+def depth_sweep(ctx, torch, binding, inputs, n, m, ub, depths=(0, 5, 10, 12, 15, 18),
+                N=1 << 18):
+    """LB2 stage time (whichever of k_lb2 / k_lb2d bounds the pool) and
+    roofline fraction on pools of one fixed depth d (d1 ~ U{0..d})."""
     res = {}
     for d in depths:
         perm, d1, d2 = inputs.random_pool(n, N, 9600 + d, depth=d)
@@ -235,12 +294,14 @@ def depth_sweep(ctx, torch, binding, inputs, n, m, ub, depths=(0, 5, 10, 15, 18)
         for _ in range(5):
             ctx.bound_children(*dev, kind=binding.LB2_FULL, ub=ub)
         torch.cuda.synchronize()
-        ms = ctx.kernel_time("k_lb2")[0] / 5
+        ms = {k: ctx.kernel_time(k)[0] / 5 for k in ("k_lb2", "k_lb2d")}
+        ctx.kernel_time("k_lb2", reset=True)
         ctx.set_option("timing", 0)
+        t = ms["k_lb2"] + ms["k_lb2d"]
         children = 2 * (n - d) * N
-        res[str(d)] = dict(parents=N, k_lb2_ms=round(ms, 4),
-                           children_per_s=children / (ms * 1e-3),
-                           frac=alg_ops_lb2(n, m, d1, d2) / (ms * 1e-3) / PEAK_INT32_OPS)
+        res[str(d)] = dict(parents=N, kernel="k_lb2d" if ms["k_lb2d"] > ms["k_lb2"] else "k_lb2",
+                           ms=round(t, 4), children_per_s=children / (t * 1e-3),
+                           frac=alg_ops_lb2(n, m, d1, d2) / (t * 1e-3) / PEAK_INT32_OPS)
     return res
 
 
@@ -254,15 +315,27 @@ def _copy_probe(torch):
     torch.cuda.synchronize()
 
 
-def bench_search(args):
-    """Device B&B to proven optimality: n=20 x m=10, p~U[1,99], seeds 1..8, NEH + 1."""
-    import torch
+def search_summary(args, with_cpu=True):
+    """Time to proven optimality of the device B&B on n=20 x m=10, p~U[1,99],
+    seeds 1..8 from NEH + 1, with LB1 and with full LB2 (65,536 nodes per step),
+    each optimum asserted equal to the CPU oracle's.  CPU baselines: the
+    oracle's depth-first search on one core (LB1) and its OpenMP-task search
+    on every usable core (LB1 and LB2)."""
     import oracle
     from paper_2012_09511_amd import binding, inputs
     ctx = binding.Context(0)
-    rows = []
+    cores, nproc, model = host_cpu()
+    ref = {}
+    for seed in range(1, 9):
+        p = inputs.instance(20, 10, seed)
+        ub0, _ = oracle.neh(p)
+        r = oracle.search(p, ub0 + 1, oracle.LB1, threads=cores)
+        assert r["proven"] and r["found"]
+        ref[seed] = r["best"]
+    rows, tot = [], {}
     for kind_name in ("LB1", "LB2_FULL"):
         kind = getattr(binding, kind_name)
+        t_all = nodes = ch = 0
         for seed in range(1, 9):
             p = inputs.instance(20, 10, seed)
             ctx.load_instance(p)
@@ -271,39 +344,46 @@ def bench_search(args):
             t = time.perf_counter()
             r = ctx.search(ub0 + 1, 0, kind)
             dt = time.perf_counter() - t
-            rows.append(dict(kind=kind_name, seed=seed, best=r["best"], proven=r["proven"],
-                             nodes=r["nodes"], children=r["children"], steps=r["steps"],
-                             seconds=dt))
-    tot = {k: (sum(x["seconds"] for x in rows if x["kind"] == k),
-               sum(x["nodes"] for x in rows if x["kind"] == k),
-               sum(x["children"] for x in rows if x["kind"] == k)) for k in ("LB1", "LB2_FULL")}
-    out = dict(metric="time to proven optimum, 8 instances (device B&B)",
-               value=tot["LB2_FULL"][0], unit="s", n_gpus=1, steps=1, warmup=1,
-               ms_per_step=tot["LB2_FULL"][0] * 1e3, higher_is_better=False, scaling="weak",
-               vs_baseline=None, dtype="int32", data="synthetic",
-               config=dict(workload="depth-first B&B, n=20 x m=10, p~U[1,99], seeds 1..8, "
-                                    "incumbent NEH+1, pool_batch 65536", lb_kind="LB2_FULL"),
-               lb1=dict(seconds=tot["LB1"][0], nodes_per_s=tot["LB1"][1] / tot["LB1"][0],
-                        children_per_s=tot["LB1"][2] / tot["LB1"][0]),
-               lb2=dict(seconds=tot["LB2_FULL"][0],
-                        nodes_per_s=tot["LB2_FULL"][1] / tot["LB2_FULL"][0],
-                        children_per_s=tot["LB2_FULL"][2] / tot["LB2_FULL"][0]),
-               instances=rows)
-    if not args.no_cpu:
-        cores = 1
-        t = time.perf_counter()
-        cpu_rows = []
-        for seed in range(1, 9):
-            p = inputs.instance(20, 10, seed)
-            ub0, _ = oracle.neh(p)
-            r = oracle.search(p, ub0 + 1, oracle.LB1)
-            cpu_rows.append((r["best"], r["nodes"]))
-        dt = time.perf_counter() - t
-        assert [b for b, _ in cpu_rows] == [x["best"] for x in rows if x["kind"] == "LB1"]
-        out["cpu_baseline"] = dict(value=dt, unit="s", cores=cores, kind="oracle",
-                                   sample="the same 8 instances with LB1, single-thread "
-                                          "recursive DFS; same optima")
+            assert r["proven"] and r["found"] and r["best"] == ref[seed], (kind_name, seed)
+            assert oracle.makespan(p, r["perm"]) == r["best"]
+            rows.append(dict(kind=kind_name, seed=seed, best=r["best"], nodes=r["nodes"],
+                             seconds=round(dt, 5)))
+            t_all += dt
+            nodes += r["nodes"]
+            ch += r["children"]
+        tot[kind_name] = dict(seconds=t_all, nodes=nodes, nodes_per_s=nodes / t_all,
+                              children_per_s=ch / t_all)
     ctx.close()
+    out = dict(workload="depth-first B&B to proven optimality, n=20 x m=10, p~U[1,99], "
+                        "seeds 1..8, incumbent NEH+1, 65536 nodes per step; optima equal "
+                        "the oracle's", lb1=tot["LB1"], lb2=tot["LB2_FULL"], instances=rows)
+    if with_cpu:
+        cpu = {}
+        for name, kind, threads in (("lb1_1core", oracle.LB1, 1), ("lb1_all", oracle.LB1, cores),
+                                    ("lb2_all", oracle.LB2_FULL, cores)):
+            t = time.perf_counter()
+            for seed in range(1, 9):
+                p = inputs.instance(20, 10, seed)
+                ub0, _ = oracle.neh(p)
+                r = oracle.search(p, ub0 + 1, kind, threads=threads)
+                assert r["best"] == ref[seed]
+            cpu[name] = dict(seconds=time.perf_counter() - t, cores=threads)
+        out["cpu_baseline"] = dict(kind="oracle", nproc=nproc, cpu_model=model,
+                                   sample="the same 8 instances to the same optima: "
+                                          "recursive DFS (1 core), OpenMP-task DFS with a "
+                                          "shared incumbent (all usable cores)", **cpu)
+    return out
+
+
+def bench_search(args):
+    """The search workload alone, as its own JSON line."""
+    s = search_summary(args, with_cpu=not args.no_cpu)
+    out = dict(metric="time to proven optimum, 8 instances (device B&B)",
+               value=s["lb2"]["seconds"], unit="s", n_gpus=1, steps=1, warmup=1,
+               ms_per_step=s["lb2"]["seconds"] * 1e3, higher_is_better=False, scaling="weak",
+               vs_baseline=None, dtype="int32", data="synthetic",
+               config=dict(workload=s["workload"], lb_kind="LB2_FULL"), **{
+                   k: v for k, v in s.items() if k != "workload"})
     print(json.dumps(out))
 
 

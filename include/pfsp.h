@@ -126,13 +126,13 @@ int pfsp_bound_children(pfsp_ctx *c, const pfsp_pool *pool, int lb_kind, int32_t
  * capture, serving loops, harnesses that forbid hipMalloc): the same
  * decomposition as pfsp_bound_children for lb_kind PFSP_LB1, PFSP_LB2_FULL or
  * PFSP_LB2_SUBSET, with the per-parent workspace (front, back and remaining
- * loads, 3m int32 per parent, and the depth-binned row lists) taken from a fixed 64 MiB device array that each
- * GPU holds from the library's load until the process ends, instead of a
- * workspace grown with hipMalloc.  The call allocates nothing (no hipMalloc,
- * hipFree, events or library allocations); the caller still passes the pool
- * and the outputs.  PFSP_ERANGE if count * (3m + 2) + 2 exceeds 2^24 int32
- * (the costs and two depth-binned row lists; e.g. 270,600 parents at m = 20);
- * PFSP_EINVAL for PFSP_LB2_LEARNED.  Every call on a GPU
+ * loads, 3m int32 per parent) taken from a fixed 64 MiB device array that
+ * each GPU holds from the library's load until the process ends, instead of
+ * a workspace grown with hipMalloc.  The call allocates nothing (no
+ * hipMalloc, hipFree, events or library allocations); the caller still
+ * passes the pool and the outputs.  PFSP_ERANGE if count * 3m exceeds 2^24
+ * (e.g. 279,620 parents at m = 20); PFSP_EINVAL for PFSP_LB2_LEARNED.  Every
+ * call on a GPU
  * uses that GPU's one array: calls whose work overlaps on one GPU (other
  * contexts, other streams) race; calls queued on one stream are ordered.
  * No kernel-time instrumentation.  Asynchronous on the ctx stream. */
@@ -144,13 +144,28 @@ int pfsp_bound_children_noalloc(pfsp_ctx *c, const pfsp_pool *pool, int lb_kind,
  * filled with INT32_MAX / prune 1).  Clears the condition.  Synchronous. */
 int pfsp_check(pfsp_ctx *c);
 
+/* Fixed LB2 pair variants (Section 2.4: LB2 variants evaluate between m and
+ * m(m-1)/2 two-machine schedules per child).  Writes to HOST mask_out[words]
+ * (words >= ceil(P/32)) the bit mask over the loaded instance's pair indices
+ * of PFSP_PAIRS_ADJACENT, the m - 1 pairs (k, k + 1), or PFSP_PAIRS_LAST, the
+ * m - 1 pairs (k, m - 1).  Host only. */
+enum { PFSP_PAIRS_ADJACENT = 1, PFSP_PAIRS_LAST = 2 };
+int pfsp_pair_mask(pfsp_ctx *c, int variant, uint32_t *mask_out, int32_t words);
+
+/* The pair set (HOST mask[words], words >= ceil(P/32), bits over the
+ * instance's pair indices) with which pfsp_search bounds every node when
+ * called with PFSP_LB2_SUBSET: LB = max(LB1, maximum over the set).  Kept
+ * until the next pfsp_load_instance.  Synchronous. */
+int pfsp_search_set_pairs(pfsp_ctx *c, const uint32_t *mask, int32_t words);
+
 /* Depth-first branch-and-bound on the device (Sections 2.2-2.5) from the
  * root (empty sigma1, sigma2): pools of up to `pool_batch` (option) nodes are
  * popped from a device stack, decomposed with pfsp_bound_children's step,
  * and their surviving children pushed back (leftmost on top).  Looks for a
  * schedule with C_max < ub0 (INT32_MAX: none known).  budget_nodes > 0 stops
  * after about that many decomposed nodes (returns PFSP_BUDGET).  lb_kind as
- * above except PFSP_LB2_SUBSET.  Waits for the ctx stream first (the search
+ * above; PFSP_LB2_SUBSET takes the pair set of pfsp_search_set_pairs for
+ * every node.  Waits for the ctx stream first (the search
  * runs on a stream of its own and shares the bound workspace).  Synchronous;
  * res must not be NULL. */
 int pfsp_search(pfsp_ctx *c, int32_t ub0, int64_t budget_nodes, int lb_kind,
@@ -272,7 +287,11 @@ int pfsp_multi_autotune(pfsp_multi *mt, int lb_kind, const uint8_t *perm, const 
  * 190 pairs of a 20-machine layout from 64 features of a parent node with an
  * MLP 64 -> 64 -> 64 -> 190 (ReLU, weights rounded to bfloat16, fp32
  * accumulation); the `learned_topk` best pairs present on the instance (m <= 20)
- * are bounded exactly.  Parameter layout (fp32, 20670 values): W1[64][64],
+ * are bounded exactly.  The float form runs on bf16 matrix cores: each fp32
+ * activation enters as bf16(x) plus bf16(x - bf16(x)) (about 16 bits of it),
+ * sums are fp32, and pairs rank by a key of the score's leading 24 bits
+ * (order-preserving integer form), equal keys to the lower layout index.
+ * Parameter layout (fp32, 20670 values): W1[64][64],
  * b1[64], W2[64][64], b2[64], W3[190][64], b3[190]; W[o][i] maps input i to
  * output o.  Layout pair of machines u < v: u*(39 - u)/2 + (v - u - 1).
  * Features of a parent (norm = largest machine load of the instance):
@@ -289,8 +308,9 @@ int pfsp_selector_get(pfsp_ctx *c, float *params, int64_t count);
 /* Features of every parent of the pool into DEVICE feat_out[N][64]. */
 int pfsp_selector_features(pfsp_ctx *c, const pfsp_pool *pool, float *feat_out);
 
-/* Scores DEVICE x[rows][64] -> DEVICE scores_out[rows][190] (layout pairs not
- * present on the loaded instance get -inf). */
+/* Scores DEVICE x[rows][64] -> DEVICE scores_out[rows][190] with the float
+ * form's arithmetic of the learned bound (layout pairs not present on the
+ * loaded instance get -inf). */
 int pfsp_selector_forward(pfsp_ctx *c, const float *x, int32_t rows, float *scores_out);
 
 /* Top-k (k in [1, 32]) of DEVICE scores[rows][190] (larger first, ties to the

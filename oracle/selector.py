@@ -94,6 +94,41 @@ def forward(params, x, round_weights=True):
     return s, (h1, h2)
 
 
+def forward_magnitude(params, x):
+    """[B, 190] bound on the sum of absolute terms behind each score: the
+    forward pass with |W| (bf16-rounded), |b| and |x|, ReLU left out.  A float
+    evaluation whose every sum has relative error e is within about
+    3 e times this bound of the exact score."""
+    W1, b1, W2, b2, W3, b3 = params
+    W1q, W2q, W3q = _weights(params, True)
+    x = np.abs(np.asarray(x, dtype=np.float64))
+    h1 = x @ np.abs(W1q).T + np.abs(b1)
+    h2 = h1 @ np.abs(W2q).T + np.abs(b2)
+    return h2 @ np.abs(W3q).T + np.abs(b3)
+
+
+def score_keys(scores) -> np.ndarray:
+    """int64 [B, 190] ranking keys of the float form: each score rounded to
+    float32 and mapped to an order-preserving integer (non-negative: its bits;
+    negative: bits xor 0x7fffffff, as a signed 32-bit value) whose low 8 bits
+    are replaced by 255 - layout index, so that scores agreeing in their
+    leading 24 bits rank by the lower index."""
+    s = np.ascontiguousarray(np.asarray(scores, dtype=np.float64).astype(np.float32))
+    u = s.view(np.uint32).astype(np.int64)
+    ordv = np.where(u >= 2**31, (u ^ 0x7FFFFFFF) - 2**32, u)
+    return (ordv & ~0xFF) | (255 - np.arange(N_OUT, dtype=np.int64))
+
+
+def topk_keys_mask(keys, valid, k):
+    """bool [B, 190]: the k largest keys among valid pairs."""
+    out = np.zeros(keys.shape, dtype=bool)
+    idx = np.flatnonzero(valid)
+    for i in range(keys.shape[0]):
+        order = idx[np.argsort(-keys[i, idx], kind="stable")]
+        out[i, order[:k]] = True
+    return out
+
+
 def masked_log_softmax(s, valid):
     s = np.where(valid, s, -np.inf)
     mx = s.max(axis=1, keepdims=True)

@@ -27,7 +27,9 @@ EXPORTS = ["pfsp_create", "pfsp_destroy", "pfsp_last_error", "pfsp_load_instance
            "pfsp_selector_select", "pfsp_selector_targets", "pfsp_selector_train_step",
            "pfsp_search_log", "pfsp_multi_create", "pfsp_multi_destroy", "pfsp_multi_bound",
            "pfsp_multi_set_shape", "pfsp_multi_autotune", "pfsp_autotune",
-           "pfsp_selector_set_quant", "pfsp_selector_infer", "pfsp_bound_children_noalloc"]
+           "pfsp_selector_set_quant", "pfsp_selector_infer", "pfsp_bound_children_noalloc",
+           "pfsp_pair_mask", "pfsp_search_set_pairs"]
+PAIRS_ADJACENT, PAIRS_LAST = 1, 2
 SELECTOR_PARAMS = 20670
 SELECTOR_QPARAMS = 20675
 
@@ -77,6 +79,8 @@ def lib():
         L.pfsp_bound_children_noalloc.argtypes = [vp, ctypes.POINTER(Pool), ctypes.c_int, i32,
                                                   vp, vp]
         L.pfsp_check.argtypes = [vp]
+        L.pfsp_pair_mask.argtypes = [vp, ctypes.c_int, vp, i32]
+        L.pfsp_search_set_pairs.argtypes = [vp, vp, i32]
         L.pfsp_search.argtypes = [vp, i32, i64, ctypes.c_int, ctypes.POINTER(Result)]
         L.pfsp_neh.argtypes = [vp, vp, vp]
         L.pfsp_set_option.argtypes = [vp, ctypes.c_char_p, i64]
@@ -180,6 +184,20 @@ class Context:
         self._check(lib().pfsp_bound_children(self.h, ctypes.byref(pool), kind, int(ub),
                                               _ptr(out_lb), _ptr(out_prune)))
         return out_lb, out_prune, dir_out, argpair_out
+
+    def pair_mask(self, variant) -> np.ndarray:
+        """Host bit mask (uint32 words) of a fixed pair variant on the loaded instance."""
+        words = (self.m * (self.m - 1) // 2 + 31) // 32
+        out = np.zeros(max(words, 1), dtype=np.uint32)
+        self._check(lib().pfsp_pair_mask(self.h, int(variant),
+                                         out.ctypes.data_as(ctypes.c_void_p), len(out)))
+        return out
+
+    def search_set_pairs(self, mask):
+        """Pair set of PFSP_LB2_SUBSET searches (host uint32 words)."""
+        mask = np.ascontiguousarray(mask, dtype=np.uint32)
+        self._check(lib().pfsp_search_set_pairs(self.h, mask.ctypes.data_as(ctypes.c_void_p),
+                                                len(mask)))
 
     def bound_children_noalloc(self, perm, d1, d2, out_lb, out_prune, kind=LB1, ub=INT32_MAX,
                                pair_mask=None, dir_out=None):

@@ -39,6 +39,9 @@ static void free_instance(Ctx *c) {
   free(c->p_host);
   c->p_host = nullptr;
   c->n = c->m = c->P = 0;
+  (void)hipFree(c->d_static_mask);
+  c->d_static_mask = nullptr;
+  c->static_words = c->static_pairs = 0;
 }
 
 void collect_timings(Ctx *c) {
@@ -207,6 +210,48 @@ int pfsp_bound_children(pfsp_ctx *h, const pfsp_pool *pool, int lb_kind, int32_t
     return launch_learned(c, dp, ub, out_lb, out_prune, c->stream);
   }
   return launch_bound(c, dp, lb_kind, ub, out_lb, out_prune, c->stream);
+}
+
+int pfsp_pair_mask(pfsp_ctx *h, int variant, uint32_t *mask_out, int32_t words) {
+  if (!h) return PFSP_EINVAL;
+  Ctx *c = &h->impl;
+  if (c->n == 0) return set_err(c, PFSP_ENOINST, "no instance loaded");
+  if (!mask_out || words < (c->P + 31) / 32)
+    return set_err(c, PFSP_EINVAL, "mask_out needs ceil(P/32) words");
+  if (variant != PFSP_PAIRS_ADJACENT && variant != PFSP_PAIRS_LAST)
+    return set_err(c, PFSP_EINVAL, "unknown pair variant");
+  const int m = c->m;
+  for (int w = 0; w < words; ++w) mask_out[w] = 0u;
+  for (int k = 0; k + 1 < m; ++k) {
+    const int u = k, v = variant == PFSP_PAIRS_ADJACENT ? k + 1 : m - 1;
+    const int q = u * (2 * m - u - 1) / 2 + (v - u - 1);
+    mask_out[q >> 5] |= 1u << (q & 31);
+  }
+  return PFSP_OK;
+}
+
+int pfsp_search_set_pairs(pfsp_ctx *h, const uint32_t *mask, int32_t words) {
+  if (!h) return PFSP_EINVAL;
+  Ctx *c = &h->impl;
+  if (c->n == 0) return set_err(c, PFSP_ENOINST, "no instance loaded");
+  const int need = (c->P + 31) / 32;
+  if (!mask || words < need) return set_err(c, PFSP_EINVAL, "mask needs ceil(P/32) words");
+  std::vector<uint32_t> mk(mask, mask + need);
+  if (c->P & 31) mk[need - 1] &= (1u << (c->P & 31)) - 1u;  // bits past the last pair
+  int count = 0;
+  for (uint32_t w : mk) count += __builtin_popcount(w);
+  PFSP_HIP(c, hipSetDevice(c->device));
+  PFSP_HIP(c, hipStreamSynchronize(c->stream));
+  if (!c->d_static_mask) {
+    if (hipMalloc(&c->d_static_mask, (size_t)need * 4) != hipSuccess) {
+      c->d_static_mask = nullptr;
+      return set_err(c, PFSP_ENOMEM, "device allocation failed");
+    }
+  }
+  PFSP_HIP(c, hipMemcpy(c->d_static_mask, mk.data(), (size_t)need * 4, hipMemcpyHostToDevice));
+  c->static_words = need;
+  c->static_pairs = count;
+  return PFSP_OK;
 }
 
 int pfsp_check(pfsp_ctx *h) {

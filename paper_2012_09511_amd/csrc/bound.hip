@@ -61,6 +61,12 @@ struct Wide {
 
 // Slots q >= from of both directions of a row of 2 * n entries: INT32_MAX,
 // pruned, no argmax pair.
+// The pair-mask row of pool row par (a shared row when mask_stride is 0).
+__device__ __forceinline__ const uint32_t *mask_row(const DevPool &pool, int par) {
+  return pool.mask +
+         (size_t)par * (size_t)(pool.mask_stride >= 0 ? pool.mask_stride : pool.mask_words);
+}
+
 __device__ __forceinline__ void fill_invalid(int *lbrow, uint8_t *prow, int16_t *arow, int n,
                                              int from, int lane, int step) {
   for (int x = lane; x < 2 * n; x += step) {
@@ -174,28 +180,20 @@ __device__ __forceinline__ void lb1_row(const DevInst &I, const int *__restrict_
 // Filter outcome of pool row i (see CostFilter): closed rows get their prune
 // row and direction here, open rows are appended to the list (one atomic per
 // wave).  Whole waves call it.
-// deep: the row is valid and has at most f.deep_r unscheduled jobs.
-__device__ __forceinline__ void list_append(int *rows, int *count, bool app, int i, int lane) {
+__device__ __forceinline__ void filter_row(const CostFilter &f, int i, bool live, bool open,
+                                           int ns, int lane) {
+  const bool app = live && open;
   const uint64_t bal = __ballot(app);
   int base = 0;
   if (bal) {
-    if (lane == 0) base = atomicAdd(count, __popcll(bal));
+    if (lane == 0) base = atomicAdd(f.open, __popcll(bal));
     base = __shfl(base, 0, kWave);
   }
   if (app) {
     const int pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
                                               __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
-    rows[base + pos] = i;
-  }
-}
-
-__device__ __forceinline__ void filter_row(const CostFilter &f, int i, bool live, bool open,
-                                           bool deep, int ns, int lane) {
-  const bool app = live && (open || f.keep_all);
-  const bool to_deep = app && deep && f.rows_deep != nullptr;
-  list_append(f.rows, f.open, app && !to_deep, i, lane);
-  if (f.rows_deep) list_append(f.rows_deep, f.open_deep, to_deep, i, lane);
-  if (!app && live) {
+    f.rows[base + pos] = i;
+  } else if (live) {
     uint8_t *pr = f.out_prune + (size_t)i * 2 * ns;
     for (int x = 0; x < 2 * ns; ++x) pr[x] = 1;
     if (f.dir) f.dir[i] = 0;
@@ -228,7 +226,7 @@ k_lb1(DevInst I, DevPool pool, int ub, int *__restrict__ out_lb, uint8_t *__rest
             write_out ? out_prune + (size_t)i * 2 * ns : nullptr,
             write_out && pool.argpair ? pool.argpair + (size_t)i * 2 * ns : nullptr,
             write_out && pool.dir ? pool.dir + i : nullptr, cs, write_out, flag);
-    if (filt && live && !f.keep_all && cs[0] >= 0) {
+    if (filt && live && cs[0] >= 0) {
       // children's LB1 from the state lb1_row left in the lane's arrays
       const int fub = *f.ub_dev;
       const int *C2 = C1 + m * B, *R = C1 + 2 * m * B;
@@ -248,7 +246,7 @@ k_lb1(DevInst I, DevPool pool, int ub, int *__restrict__ out_lb, uint8_t *__rest
       }
     }
   }
-  if (filt) filter_row(f, i, live, open, false, ns, t & 63);
+  if (filt) filter_row(f, i, live, open, ns, t & 63);
 }
 
 // One parent's costs (front C1, back C2, remaining R; Eq. (1)) for n <= 32
@@ -386,22 +384,19 @@ k_costs(DevInst I, DevPool pool, int *__restrict__ costs, int *__restrict__ flag
   const int count = pool.count_dev ? *pool.count_dev : pool.count;
   const int ns = pool.n;
   const bool filt = f.rows != nullptr;
-  const bool check = filt && !f.keep_all;  // LB1 filter of a search step
-  const int ub = check ? *f.ub_dev : 0;
+  const int ub = filt ? *f.ub_dev : 0;
   // whole waves step together: the tile store is a wave-wide operation
   for (int i0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63); i0 < count;
        i0 += gridDim.x * blockDim.x) {
     const int i = i0 + lane;
-    bool live = false, open = false, valid = false, deep = false;
+    bool live = false, open = false, valid = false;
     if (i < count) {
       live = !filt || !f.alive || f.alive[i];
-      const int a = pool.d1[i], b = pool.d2[i];
-      open = costs_row<MMAX, MS>(n, m, sp, sT, pool.perm + (size_t)i * ns, a, b,
-                                 tile + lane * RS, flag, check && live, ub, &valid);
+      open = costs_row<MMAX, MS>(n, m, sp, sT, pool.perm + (size_t)i * ns, pool.d1[i],
+                                 pool.d2[i], tile + lane * RS, flag, filt && live, ub, &valid);
       open = open && valid;
-      deep = valid && n - a - b <= f.deep_r;
     }
-    if (filt) filter_row(f, i, live, open, deep, ns, lane);
+    if (filt) filter_row(f, i, live, open, ns, lane);
     wave_sync();
     const int rows = min(64, count - i0);
     int *dst = costs + (size_t)i0 * cm;
@@ -541,7 +536,7 @@ k_lb2(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__res
         const int pi = pc + lane;
         bool act = pi < P;
         if (SUBSET && act)
-          act = (pool.mask[(size_t)par * pool.mask_words + (pi >> 5)] >> (pi & 31)) & 1u;
+          act = (mask_row(pool, par)[pi >> 5] >> (pi & 31)) & 1u;
         if (act) {
           const int u = I.pu[pi], v = I.pv[pi];
           const int RU = rr[u], RV = rr[v], C1u = c1[u], C1v = c1[v], C2u = c2[u], C2v = c2[v];
@@ -1113,6 +1108,14 @@ __device__ __forceinline__ PackFetch row_fetch(const uint8_t *__restrict__ row,
   return F;
 }
 
+// Whether a kernel launched on pool's depth bin bounds the parent F.
+__device__ __forceinline__ bool in_bin(const DevPool &pool, const PackFetch &F, int n) {
+  if (!pool.bin) return true;
+  const int r = n - __builtin_amdgcn_readfirstlane(F.d1) - __builtin_amdgcn_readfirstlane(F.d2);
+  const bool deep = r >= 1 && r <= pool.bin_r;
+  return pool.bin == 2 ? deep : !deep;
+}
+
 __device__ __forceinline__ PackFetch pack_fetch(const DevPool &pool, int par, int n, int m,
                                                 const int *__restrict__ costs, int lane) {
   PackFetch F{0, -1, 0, 0, 0, 0, 0u};
@@ -1126,7 +1129,7 @@ __device__ __forceinline__ PackFetch pack_fetch(const DevPool &pool, int par, in
       F.c2 = cs[m + lane];
       F.rr = cs[2 * m + lane];
     }
-    if (lane < pool.mask_words) F.mw = pool.mask[(size_t)par * pool.mask_words + lane];
+    if (lane < pool.mask_words) F.mw = mask_row(pool, par)[lane];
   }
   return F;
 }
@@ -1405,9 +1408,10 @@ k_lb2q(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
   for (; it < count; it += step) {
     const int nxt = row_of(it + step);  // the next parent's inputs are loaded meanwhile
     const PackFetch Fn = pack_fetch(pool, nxt, n, m, costs, lane);
-    lb2q_parent<NMAX, SUBSET, X16>(I, Ppad, S, F, ns, ub, out_lb + (size_t)par * 2 * ns,
-                                   out_prune + (size_t)par * 2 * ns,
-                                   pool.dir ? pool.dir + par : nullptr, lane, tsrc);
+    if (in_bin(pool, F, n))
+      lb2q_parent<NMAX, SUBSET, X16>(I, Ppad, S, F, ns, ub, out_lb + (size_t)par * 2 * ns,
+                                     out_prune + (size_t)par * 2 * ns,
+                                     pool.dir ? pool.dir + par : nullptr, lane, tsrc);
     par = nxt;
     F = Fn;
   }
@@ -1495,8 +1499,8 @@ __device__ void lb2d_parent(const DevInst &I, int Ppad, const DeepLds<NMAX> &S,
   const int a = __builtin_amdgcn_readfirstlane(F.d1), b = __builtin_amdgcn_readfirstlane(F.d2);
   const int r = n - a - b;
   if (r < 1 || r > RMAX || __builtin_amdgcn_readfirstlane(F.c1) < 0) {
-    // an invalid row (flagged by the costs kernel); rows deeper than RMAX are
-    // never listed for this kernel
+    // an invalid row (flagged by the costs kernel); the launcher gives this
+    // kernel only rows with 1 <= r <= RMAX
     fill_invalid(lbrow, prow, nullptr, stride, 0, lane, 64);
     if (dirp && lane == 0) *dirp = 0;
     return;
@@ -1650,9 +1654,10 @@ k_lb2d(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
   for (; it < count; it += step) {
     const int nxt = row_of(it + step);
     const PackFetch Fn = pack_fetch(pool, nxt, n, m, costs, lane);
-    lb2d_parent<NMAX, RMAX>(I, Ppad, S, F, ns, ub, out_lb + (size_t)par * 2 * ns,
-                            out_prune + (size_t)par * 2 * ns,
-                            pool.dir ? pool.dir + par : nullptr, lane, tsrc);
+    if (in_bin(pool, F, n))
+      lb2d_parent<NMAX, RMAX>(I, Ppad, S, F, ns, ub, out_lb + (size_t)par * 2 * ns,
+                              out_prune + (size_t)par * 2 * ns,
+                              pool.dir ? pool.dir + par : nullptr, lane, tsrc);
     par = nxt;
     F = Fn;
   }
@@ -2497,7 +2502,7 @@ k_lb2f(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
     lb2f_parent<NMAX, SUBSET, LOG>(
         I, Ppad, S, pool.perm + (size_t)par * ns, pool.d1[par], pool.d2[par],
         costs + (size_t)par * 3 * m,
-        SUBSET ? pool.mask + (size_t)par * pool.mask_words : nullptr, ns, ub,
+        SUBSET ? mask_row(pool, par) : nullptr, ns, ub,
         out_lb + (size_t)par * 2 * ns, out_prune + (size_t)par * 2 * ns,
         LOG ? pool.argpair + (size_t)par * 2 * ns : nullptr, pool.dir ? pool.dir + par : nullptr,
         lane);
@@ -2677,14 +2682,10 @@ static int fast_nmax(int n, int l16) {
 }
 
 __global__ void k_zero(int *p) { *p = 0; }
-__global__ void k_zero2(int *p) {
-  p[0] = 0;
-  p[1] = 0;
-}
 
 // -------------------------------------------------------------------- host
 size_t workspace_ints(const Ctx *c, int count) {
-  return (size_t)(count > 0 ? count : 1) * (3 * c->m + 2) + 2;
+  return (size_t)(count > 0 ? count : 1) * 3 * c->m;
 }
 
 int ensure_costs(Ctx *c, int count) {
@@ -2957,33 +2958,6 @@ int deep_bin_r(const Ctx *c, int kind, bool log) {
 int launch_bound(Ctx *c, const DevPool &pool, int kind, int ub, int *out_lb, uint8_t *out_prune,
                  hipStream_t s) {
   if (pool.count <= 0) return PFSP_OK;
-  const int deep = deep_bin_r(c, kind, pool.argpair != nullptr);
-  if (deep && !pool.index && !pool.count_dev) {
-    // The costs kernel lists the rows with at most `deep` jobs left for the
-    // deep kernel and every other row for the quick kernel.
-    int rc = ensure_costs(c, pool.count);
-    if (rc) return rc;
-    int *lists = c->d_costs + (size_t)pool.count * 3 * c->m;
-    int *cnt = lists + 2 * (size_t)pool.count;
-    hipLaunchKernelGGL(k_zero2, dim3(1), dim3(1), 0, s, cnt);
-    CostFilter f{};
-    f.rows = lists;
-    f.open = cnt;
-    f.rows_deep = lists + pool.count;
-    f.open_deep = cnt + 1;
-    f.deep_r = deep;
-    f.keep_all = 1;
-    rc = launch_costs(c, pool, s, &f);
-    if (rc) return rc;
-    DevPool dp = pool, dd = pool;
-    dp.index = f.rows;
-    dp.count_dev = f.open;
-    dd.index = f.rows_deep;
-    dd.count_dev = f.open_deep;
-    rc = launch_bound_costs_ready(c, dp, kind, ub, out_lb, out_prune, s, 0);
-    if (rc) return rc;
-    return launch_lb2d(c, dd, ub, out_lb, out_prune, s);
-  }
   if (kind == PFSP_LB1) {
     int b1, g1;
     size_t lds1;
@@ -2996,6 +2970,8 @@ int launch_bound(Ctx *c, const DevPool &pool, int kind, int ub, int *out_lb, uin
   }
   int rc = launch_costs(c, pool, s);
   if (rc) return rc;
+  if (deep_bin_r(c, kind, pool.argpair != nullptr))
+    return launch_lb2_binned(c, pool, ub, out_lb, out_prune, s);
   return launch_bound_costs_ready(c, pool, kind, ub, out_lb, out_prune, s, 0);
 }
 
@@ -3089,8 +3065,8 @@ static size_t lb2d_lds(const Ctx *c, int nmax, int rmax, int waves) {
   return L.block_bytes(nmax) + (size_t)waves * L.wave_bytes(nmax);
 }
 
-int launch_lb2d(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8_t *out_prune,
-                hipStream_t s) {
+static int launch_lb2d(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8_t *out_prune,
+                       hipStream_t s) {
   if (pool.count <= 0) return PFSP_OK;
   const int nmax = fast_nmax(c->n, c->l16);
   const int r = deep_bin_r(c, PFSP_LB2_FULL, false);
@@ -3134,6 +3110,19 @@ int launch_lb2d(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8_t *out_p
 #undef PFSP_D
   PFSP_HIP(c, hipGetLastError());
   return PFSP_OK;
+}
+
+int launch_lb2_binned(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8_t *out_prune,
+                      hipStream_t s) {
+  const int r = deep_bin_r(c, PFSP_LB2_FULL, pool.argpair != nullptr);
+  if (!r) return launch_bound_costs_ready(c, pool, PFSP_LB2_FULL, ub, out_lb, out_prune, s, 0);
+  DevPool dp = pool, dd = pool;
+  dp.bin = 1;
+  dd.bin = 2;
+  dp.bin_r = dd.bin_r = r;
+  const int rc = launch_bound_costs_ready(c, dp, PFSP_LB2_FULL, ub, out_lb, out_prune, s, 0);
+  if (rc) return rc;
+  return launch_lb2d(c, dd, ub, out_lb, out_prune, s);
 }
 
 // LB2 kinds once launch_costs has run for the same pool.  group: parents per

@@ -44,9 +44,14 @@ struct DevPool {
   const uint8_t *perm, *d1, *d2;
   const uint32_t *mask;
   int mask_words;
+  int mask_stride = -1;         // words between rows of mask (-1: mask_words; 0: one row for all)
   uint8_t *dir;
   int16_t *argpair;
   const int *index = nullptr;  // if set, launch row i bounds pool row index[i]
+  // depth bins of full LB2 (r = n - d1 - d2): 0 every row; 1 the rows with
+  // r > bin_r or r < 1 (the full-scan kernels); 2 the rows with 1 <= r <= bin_r
+  // (the deep kernel).  A kernel leaves the other bin's rows untouched.
+  int bin = 0, bin_r = 0;
 };
 
 // Search-step filter of the costs kernels (row i of the pool):
@@ -56,10 +61,6 @@ struct DevPool {
 //    written here (all pruned, direction 0) and it is left out of the bound
 //    kernels;
 //  - every other parent is appended to rows[0 .. *open) (any order).
-//  - keep_all: no row is closed (the LB1 check is skipped); every row of the
-//    launch goes to a list.  Used to bin a plain decomposition by depth;
-//  - rows_deep (optional): open valid rows with at most deep_r unscheduled
-//    jobs go to rows_deep[0 .. *open_deep) instead (the deep LB2 kernel).
 struct CostFilter {
   const uint8_t *alive;
   const int *ub_dev;
@@ -67,10 +68,6 @@ struct CostFilter {
   uint8_t *dir;
   int *rows;
   int *open;
-  int *rows_deep = nullptr;
-  int *open_deep = nullptr;
-  int deep_r = 0;
-  int keep_all = 0;
 };
 
 struct Selector;   // learned pair selector state (selector.hip)
@@ -97,6 +94,9 @@ struct Ctx {
   size_t costs_cap = 0;
   int *d_flag = nullptr;   // [4] device status words: [0] invalid-row flag
   int *scratch = nullptr;  // this device's fixed workspace (pfsp_bound_children_noalloc)
+  // fixed pair set of PFSP_LB2_SUBSET searches (pfsp_search_set_pairs)
+  uint32_t *d_static_mask = nullptr;
+  int static_words = 0, static_pairs = 0;
   // options
   int64_t pool_batch = 65536;
   int64_t poll_every = 8;
@@ -184,12 +184,11 @@ size_t lb2_lds_bytes(const Ctx *c, int waves);
 // Depth threshold of the deep LB2 kernel for this context and kind (0: the
 // kernel does not apply; every parent takes the other LB2 kernels).
 int deep_bin_r(const Ctx *c, int kind, bool log);
-// Full LB2 of the pool's parents (index list, count_dev) with the deep
-// kernel; every listed parent must have at most deep_bin_r jobs left.
-int launch_lb2d(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8_t *out_prune,
-                hipStream_t s);
-// Workspace of pfsp_bound_children: per parent 3m costs, then two index
-// lists of count rows and two counters.
+// Full LB2 with the rows split by depth: the deep kernel takes the rows with
+// at most deep_bin_r jobs left, the full-scan kernel the others (costs ready).
+int launch_lb2_binned(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8_t *out_prune,
+                      hipStream_t s);
+// Workspace of pfsp_bound_children in int32: 3m costs per parent.
 size_t workspace_ints(const Ctx *c, int count);
 void init_bound_attributes();
 void init_selector_attributes();

@@ -60,7 +60,7 @@ extern "C" int pfsp_bound_children_noalloc(pfsp_ctx *h, const pfsp_pool *pool, i
   if (pool->count < 0) return set_err(c, PFSP_EINVAL, "negative count");
   if (workspace_ints(c, pool->count) > kScratchInts)
     return set_err(c, PFSP_ERANGE,
-                   "pool too large for the fixed workspace: count * (3m + 2) + 2 must be <= " +
+                   "pool too large for the fixed workspace: count * 3m must be <= " +
                        std::to_string(kScratchInts));
   if (!c->scratch) return set_err(c, PFSP_EDEVICE, "scratch address not set up");
   // The shared bound path with the workspace pointed at this device's

@@ -62,9 +62,8 @@ struct SearchState {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   std::vector<long long> graph_key;  // options the captured step depends on
-  // LB2 steps: parents that survive the costs kernels' LB1 filter; with the
-  // deep kernel, those with few jobs left go to rows_deep (count open[1])
-  int *rows = nullptr, *open = nullptr, *rows_deep = nullptr;
+  // LB2 steps: parents that survive the costs kernels' LB1 filter
+  int *rows = nullptr, *open = nullptr;
   // node log (option log_capacity > 0): every log_stride-th decomposed node
   uint8_t *l_perm = nullptr, *l_d1 = nullptr, *l_d2 = nullptr;
   long long log_cap = 0;
@@ -73,10 +72,6 @@ struct SearchState {
 constexpr int kScanBlock = 1024;  // parents per k_scan_local block (256 threads x 4)
 
 __global__ void k_clear(int *p) { *p = 0; }
-__global__ void k_clear2(int *p) {
-  p[0] = 0;
-  p[1] = 0;
-}
 
 __global__ void k_pop(SearchCtl *c, int N) {
   const int top = c->top;
@@ -368,8 +363,7 @@ void search_free(Ctx *c) {
   if (S->graph) (void)hipGraphDestroy(S->graph);
   void *bufs[] = {S->s_perm, S->s_d1, S->s_d2, S->s_lb, S->b_perm, S->b_d1, S->b_d2, S->b_dir,
                   S->b_lb, S->b_alive, S->out_lb, S->out_prune, S->cnt, S->offs, S->bsum,
-                  S->best_perm, S->ctl, S->l_perm, S->l_d1, S->l_d2, S->rows, S->open,
-                  S->rows_deep};
+                  S->best_perm, S->ctl, S->l_perm, S->l_d1, S->l_d2, S->rows, S->open};
   for (void *p : bufs) (void)hipFree(p);
   if (S->ctl_host) (void)hipHostFree(S->ctl_host);
   if (S->stream) (void)hipStreamDestroy(S->stream);
@@ -416,8 +410,7 @@ static int search_alloc(Ctx *c) {
   alloc((void **)&S->best_perm, (size_t)n);
   alloc((void **)&S->ctl, sizeof(SearchCtl));
   alloc((void **)&S->rows, (size_t)N * 4);
-  alloc((void **)&S->rows_deep, (size_t)N * 4);
-  alloc((void **)&S->open, 8);
+  alloc((void **)&S->open, 4);
   S->log_cap = c->log_capacity;
   if (S->log_cap > 0) {
     alloc((void **)&S->l_perm, (size_t)S->log_cap * n);
@@ -459,20 +452,19 @@ static int enqueue_step(Ctx *c, int kind) {
   pool.d2 = S->b_d2;
   pool.mask = nullptr;
   pool.mask_words = 0;
+  if (kind == PFSP_LB2_SUBSET) {  // one pair set for every node
+    pool.mask = c->d_static_mask;
+    pool.mask_words = c->static_words;
+    pool.mask_stride = 0;
+  }
   pool.dir = S->b_dir;
   pool.argpair = nullptr;
   int rc;
   if (kind != PFSP_LB1 && c->search_filter) {
     // parents whose children all have LB1 >= ub are closed by the costs
     // kernel (LB2 >= LB1 cannot keep a child); only the others are bounded
-    hipLaunchKernelGGL(k_clear2, dim3(1), dim3(1), 0, s, S->open);
-    CostFilter f{S->b_alive, &S->ctl->ub_step, S->out_prune, S->b_dir, S->rows, S->open};
-    const int deep = deep_bin_r(c, kind, false);
-    if (deep) {
-      f.rows_deep = S->rows_deep;
-      f.open_deep = S->open + 1;
-      f.deep_r = deep;
-    }
+    hipLaunchKernelGGL(k_clear, dim3(1), dim3(1), 0, s, S->open);
+    const CostFilter f{S->b_alive, &S->ctl->ub_step, S->out_prune, S->b_dir, S->rows, S->open};
     rc = launch_costs(c, pool, s, &f);
     if (rc) return rc;
     DevPool op = pool;
@@ -481,13 +473,13 @@ static int enqueue_step(Ctx *c, int kind) {
     if (kind == PFSP_LB2_LEARNED) {
       rc = launch_learned_ready(c, op, 0, S->out_lb, S->out_prune, s);
     } else {
-      rc = launch_bound_costs_ready(c, op, kind, 0, S->out_lb, S->out_prune, s);
-      if (!rc && deep) {
-        DevPool dp = pool;
-        dp.index = S->rows_deep;
-        dp.count_dev = S->open + 1;
-        rc = launch_lb2d(c, dp, 0, S->out_lb, S->out_prune, s);
-      }
+      // a fixed selection of at most 32 pairs fills half a wave: two parents per wave
+      const int group = kind == PFSP_LB2_SUBSET && c->subset_group == 0 && c->static_pairs <= 32
+                            ? 2 : 0;
+      if (kind == PFSP_LB2_FULL)
+        rc = launch_lb2_binned(c, op, 0, S->out_lb, S->out_prune, s);
+      else
+        rc = launch_bound_costs_ready(c, op, kind, 0, S->out_lb, S->out_prune, s, group);
     }
   } else if (kind == PFSP_LB2_LEARNED) {
     rc = launch_learned(c, pool, 0, S->out_lb, S->out_prune, s);
@@ -512,7 +504,7 @@ static std::vector<long long> step_key(const Ctx *c, int kind) {
   const SearchState *S = c->search;
   return {kind, S->log_cap > 0 ? c->log_stride : 0, c->search_filter, c->learned_topk,
           c->learned_exact, c->subset_group, c->lb2_waves, c->lb2_blocks_per_cu,
-          c->force_generic, c->wide_lb2, c->deep_r, selector_mode(c)};
+          c->force_generic, c->wide_lb2, c->deep_r, selector_mode(c), c->static_pairs};
 }
 
 static int build_graph(Ctx *c, int kind) {
@@ -550,8 +542,10 @@ extern "C" int pfsp_search(pfsp_ctx *h, int32_t ub0, int64_t budget_nodes, int l
   Ctx *c = &h->impl;
   if (c->n == 0) return set_err(c, PFSP_ENOINST, "no instance loaded");
   if (!res) return set_err(c, PFSP_EINVAL, "res is NULL");
-  if (lb_kind != PFSP_LB1 && lb_kind != PFSP_LB2_FULL && lb_kind != PFSP_LB2_LEARNED)
-    return set_err(c, PFSP_EINVAL, "search supports PFSP_LB1, PFSP_LB2_FULL, PFSP_LB2_LEARNED");
+  if (lb_kind < PFSP_LB1 || lb_kind > PFSP_LB2_LEARNED)
+    return set_err(c, PFSP_EINVAL, "unknown lb_kind");
+  if (lb_kind == PFSP_LB2_SUBSET && !c->d_static_mask)
+    return set_err(c, PFSP_EINVAL, "PFSP_LB2_SUBSET searches need pfsp_search_set_pairs");
   if (lb_kind != PFSP_LB1 && c->m < 2) return set_err(c, PFSP_ERANGE, "LB2 kinds need m >= 2");
   if (budget_nodes < 0) return set_err(c, PFSP_EINVAL, "negative budget");
   PFSP_HIP(c, hipSetDevice(c->device));

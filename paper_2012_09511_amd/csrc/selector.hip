@@ -35,6 +35,7 @@ constexpr int kTopKMaxQ = 64;  // integer model
 struct Selector {
   float *master = nullptr;  // fp32 parameters, layout W1[64][64] b1 W2[64][64] b2 W3[190][64] b3
   float *wq = nullptr;      // same layout, weights rounded to bfloat16 (biases copied)
+  uint4 *bops = nullptr;    // wq's weights as bf16 MFMA B operands (float inference)
   float *grad = nullptr, *am = nullptr, *av = nullptr;
   long long step = 0;
   int loaded = 0;
@@ -117,117 +118,6 @@ __device__ __forceinline__ void parent_features(int n, int m, const int *__restr
   f[63] = bad ? 0.f : (float)lb1 / norm;
 }
 
-// Selector inference for the bound kernels, fused: features from the costs
-// workspace, the MLP and the top-k, writing only the pair masks.  One thread
-// per row, 256 rows per block.  The block stages the bf16-rounded weights in
-// LDS once; each layer's outputs go through LDS ([unit][thread], each thread
-// touching only its own column) so that the next layer reads its inputs from
-// statically indexed registers, and four output units are accumulated at a
-// time (independent chains, weights read as LDS broadcasts).  Every score is
-// accumulated in the order of k_mlp_forward (bias, then inputs 0..63) and
-// the list keeps the KMAX best (score, then lower layout index: the ranking
-// of k_select) in visiting order 0..189, so its first k entries are the
-// masks of select(forward(features)).
-constexpr int kInferRows = 256;
-template <int KMAX>
-__global__ void __launch_bounds__(kInferRows)
-k_infer(DevInst I, DevPool pool, const int *__restrict__ costs, float norm,
-        const float *__restrict__ wq, const int *__restrict__ to_inst, int k, int words,
-        uint32_t *__restrict__ mask) {
-  extern __shared__ __align__(16) float wsh[];  // [kParams] weights, then [kHid][kInferRows]
-  float(*hs)[kInferRows] = reinterpret_cast<float(*)[kInferRows]>(wsh + ((kParams + 3) & ~3));
-  const int count = pool.count_dev ? *pool.count_dev : pool.count;
-  if ((int)(blockIdx.x * kInferRows) >= count) return;
-  for (int x = threadIdx.x; x < kParams; x += kInferRows) wsh[x] = wq[x];
-  __syncthreads();
-  const int it = blockIdx.x * kInferRows + threadIdx.x;
-  if (it >= count) return;
-  const int i = pool.index ? pool.index[it] : it;
-  const int t = threadIdx.x;
-  float x[kIn];
-  parent_features(I.n, I.m, costs + (size_t)i * 3 * I.m, pool.d1[i], pool.d2[i], norm, x);
-  // hidden layers: units o .. o + 3 at a time
-#pragma unroll 1
-  for (int layer = 0; layer < 2; ++layer) {
-    const float *W = wsh + (layer == 0 ? kOffW1 : kOffW2);
-    const float *Bv = wsh + (layer == 0 ? kOffB1 : kOffB2);
-#pragma unroll 1
-    for (int o = 0; o < kHid; o += 4) {
-      float s0 = Bv[o], s1 = Bv[o + 1], s2 = Bv[o + 2], s3 = Bv[o + 3];
-#pragma unroll
-      for (int j = 0; j < kIn; ++j) {
-        s0 = fmaf(W[(o + 0) * kIn + j], x[j], s0);
-        s1 = fmaf(W[(o + 1) * kIn + j], x[j], s1);
-        s2 = fmaf(W[(o + 2) * kIn + j], x[j], s2);
-        s3 = fmaf(W[(o + 3) * kIn + j], x[j], s3);
-      }
-      hs[o][t] = fmaxf(s0, 0.f);
-      hs[o + 1][t] = fmaxf(s1, 0.f);
-      hs[o + 2][t] = fmaxf(s2, 0.f);
-      hs[o + 3][t] = fmaxf(s3, 0.f);
-    }
-#pragma unroll
-    for (int j = 0; j < kHid; ++j) x[j] = hs[j][t];
-  }
-  // output layer, pairs in index order, into the top-KMAX list
-  float best[KMAX];
-  int idx[KMAX];
-#pragma unroll
-  for (int q = 0; q < KMAX; ++q) {
-    best[q] = -INFINITY;
-    idx[q] = -1;
-  }
-  const float *W3 = wsh + kOffW3;
-#pragma unroll 1
-  for (int o = 0; o < kOut; o += 2) {  // kOut is even
-    float v[2] = {wsh[kOffB3 + o], wsh[kOffB3 + o + 1]};
-#pragma unroll
-    for (int j = 0; j < kHid; ++j) {
-      v[0] = fmaf(W3[o * kHid + j], x[j], v[0]);
-      v[1] = fmaf(W3[(o + 1) * kHid + j], x[j], v[1]);
-    }
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      float val = v[e];
-      int id = o + e;
-      // absent pairs never enter; a later pair displaces only strictly smaller
-      // scores, so equal scores keep the lower index first
-      if (to_inst[id] >= 0 && val > best[KMAX - 1]) {
-#pragma unroll
-        for (int q = 0; q < KMAX; ++q) {
-          const bool c = val > best[q];
-          const float tv = best[q];
-          const int ti = idx[q];
-          best[q] = c ? val : tv;
-          idx[q] = c ? id : ti;
-          val = c ? tv : val;
-          id = c ? ti : id;
-        }
-      }
-    }
-  }
-  uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0, w5 = 0;  // 190 pairs fit 6 words
-#pragma unroll
-  for (int q = 0; q < KMAX; ++q) {
-    if (q < k && idx[q] >= 0) {
-      const int pi = to_inst[idx[q]];
-      const uint32_t bit = 1u << (pi & 31);
-      const int wd = pi >> 5;
-      w0 |= wd == 0 ? bit : 0u;
-      w1 |= wd == 1 ? bit : 0u;
-      w2 |= wd == 2 ? bit : 0u;
-      w3 |= wd == 3 ? bit : 0u;
-      w4 |= wd == 4 ? bit : 0u;
-      w5 |= wd == 5 ? bit : 0u;
-    }
-  }
-  uint32_t *mi = mask + (size_t)i * words;
-  const uint32_t ws[6] = {w0, w1, w2, w3, w4, w5};
-#pragma unroll
-  for (int wd = 0; wd < 6; ++wd)
-    if (wd < words) mi[wd] = ws[wd];
-}
-
 // ------------------------------------------------- integer-only inference
 // The deployed selector is the MLP above quantized to int8 weights and
 // activations with int32 accumulation, so every score is an exact integer
@@ -302,6 +192,84 @@ __device__ __forceinline__ void bitonic_merge_desc(int (&a)[N]) {
         a[l] = lo;
       }
     }
+}
+
+// Top-KMAX keys (larger first) of the wave's 16 rows over the 12 output
+// tiles of 16 pairs.  tile_keys(t, tq) writes tile t's keys of every row to
+// LDS slots [row][16 tq .. 16 tq + 15] of `keys` (stride kQKeyStride); four
+// tiles go through LDS per round.  Lanes 4q .. 4q + 3 take row q: lane part
+// p sorts tile 4u + p of each round with a bitonic network and merges it into
+// a running list; two exchange-and-merge rounds (partners l ^ 1, l ^ 2)
+// leave the row's top-KMAX in all four lanes.  Keys are unique per row.
+template <int KMAX, class F>
+__device__ __forceinline__ void topk_keys(int *keys, int lane, int (&best)[KMAX], F tile_keys) {
+  const int srow = lane >> 2, p = lane & 3;
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) best[q] = INT_MIN;
+#pragma unroll 1
+  for (int u = 0; u < kQT3 / 4; ++u) {
+#pragma unroll
+    for (int tq = 0; tq < 4; ++tq) tile_keys(4 * u + tq, tq);
+    wave_sync();
+    const int *kr = keys + srow * kQKeyStride + 16 * p;
+    int ch[16];
+#pragma unroll
+    for (int q = 0; q < 16; q += 4) {
+      const int4 v = *(const int4 *)(kr + q);
+      ch[q] = v.x;
+      ch[q + 1] = v.y;
+      ch[q + 2] = v.z;
+      ch[q + 3] = v.w;
+    }
+    wave_sync();  // the next round rewrites the keys
+    bitonic_sort_desc<16>(ch);
+    if (u == 0) {  // the first sorted tile is the running list as it stands
+#pragma unroll
+      for (int q = 0; q < KMAX; ++q) best[q] = q < 16 ? ch[q < 16 ? q : 0] : INT_MIN;
+    } else {
+#pragma unroll
+      for (int q = 0; q < KMAX; ++q) {
+        const int r = KMAX - 1 - q;
+        best[q] = max(best[q], r < 16 ? ch[r < 16 ? r : 0] : INT_MIN);
+      }
+      bitonic_merge_desc<KMAX>(best);
+    }
+  }
+#pragma unroll
+  for (int d = 1; d <= 2; d <<= 1) {  // merge with the partner's list
+    int other[KMAX];
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) other[q] = __shfl_xor(best[q], d, kWave);
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) best[q] = max(best[q], other[KMAX - 1 - q]);
+    bitonic_merge_desc<KMAX>(best);
+  }
+}
+
+// Pair mask of the first k keys of a row (key low byte: 255 - layout index).
+template <int KMAX>
+__device__ __forceinline__ void write_mask(const int (&best)[KMAX], int k,
+                                           const int *__restrict__ to_inst,
+                                           uint32_t *__restrict__ mi, int words) {
+  uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0, w5 = 0;  // 190 pairs fit 6 words
+#pragma unroll
+  for (int q = 0; q < KMAX; ++q) {
+    if (q < k && best[q] != INT_MIN) {
+      const int pi = to_inst[255 - (best[q] & 255)];
+      const uint32_t bit = 1u << (pi & 31);
+      const int wd = pi >> 5;
+      w0 |= wd == 0 ? bit : 0u;
+      w1 |= wd == 1 ? bit : 0u;
+      w2 |= wd == 2 ? bit : 0u;
+      w3 |= wd == 3 ? bit : 0u;
+      w4 |= wd == 4 ? bit : 0u;
+      w5 |= wd == 5 ? bit : 0u;
+    }
+  }
+  const uint32_t ws[6] = {w0, w1, w2, w3, w4, w5};
+#pragma unroll
+  for (int wd = 0; wd < 6; ++wd)
+    if (wd < words) mi[wd] = ws[wd];
 }
 
 // One hidden layer for the wave's rows: A from `in` (row-major bytes), int8
@@ -405,132 +373,230 @@ k_infer_q(DevInst I, DevPool pool, const int *__restrict__ costs, float qs, floa
   wave_sync();
   q_hidden(xb, xa, ops + kQOpB2, bias + kQBias2, M2, S2, lane);
   wave_sync();
-  // output layer, four 16-pair tiles per round: keys into LDS, then each lane
-  // part sorts one tile of its row and merges it into its running top-KMAX
+  // output layer: keys of 16 pairs per tile, four tiles per round
   const int c = lane & 15, g = lane >> 4;
   const unsigned char *arow = xa + c * kQRowStride + 8 * g;
   const long a0 = *(const long *)arow, a1 = *(const long *)(arow + 32);
-  const int srow = lane >> 2, p = lane & 3;
   int best[KMAX];
+  topk_keys<KMAX>(keys, lane, best, [&](int t, int tq) {
+    const uint2 e0 = ops[kQOpB3 + (t * 2) * 64 + lane];
+    const uint2 e1 = ops[kQOpB3 + (t * 2 + 1) * 64 + lane];
+    const long b0 = (long)(((unsigned long)e0.y << 32) | e0.x);
+    const long b1 = (long)(((unsigned long)e1.y << 32) | e1.x);
+    const int o = 16 * t + c;
+    const bool valid = o < kOut && to_inst[o < kOut ? o : 0] >= 0;
+    const int kb = bias[kQBias3 + t * 64 + lane];
+    qv4 d = {0, 0, 0, 0};
+    d = __builtin_amdgcn_mfma_i32_16x16x32_i8(a0, b0, d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_i32_16x16x32_i8(a1, b1, d, 0, 0, 0);
 #pragma unroll
-  for (int q = 0; q < KMAX; ++q) best[q] = INT_MIN;
-#pragma unroll 1
-  for (int u = 0; u < kQT3 / 4; ++u) {
-#pragma unroll
-    for (int tq = 0; tq < 4; ++tq) {
-      const int t = 4 * u + tq;
-      const uint2 e0 = ops[kQOpB3 + (t * 2) * 64 + lane];
-      const uint2 e1 = ops[kQOpB3 + (t * 2 + 1) * 64 + lane];
-      const long b0 = (long)(((unsigned long)e0.y << 32) | e0.x);
-      const long b1 = (long)(((unsigned long)e1.y << 32) | e1.x);
-      const int o = 16 * t + c;
-      const bool valid = o < kOut && to_inst[o < kOut ? o : 0] >= 0;
-      const int kb = bias[kQBias3 + t * 64 + lane];
-      qv4 d = {0, 0, 0, 0};
-      d = __builtin_amdgcn_mfma_i32_16x16x32_i8(a0, b0, d, 0, 0, 0);
-      d = __builtin_amdgcn_mfma_i32_16x16x32_i8(a1, b1, d, 0, 0, 0);
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        keys[(4 * g + j) * kQKeyStride + 16 * tq + c] =
-            valid ? (d[j] + kb) * 256 + (255 - o) : INT_MIN;
-    }
-    wave_sync();
-    const int *kr = keys + srow * kQKeyStride + 16 * p;
-    int ch[16];
-#pragma unroll
-    for (int q = 0; q < 16; q += 4) {
-      const int4 v = *(const int4 *)(kr + q);
-      ch[q] = v.x;
-      ch[q + 1] = v.y;
-      ch[q + 2] = v.z;
-      ch[q + 3] = v.w;
-    }
-    wave_sync();  // the next round rewrites the keys
-    bitonic_sort_desc<16>(ch);
-    if (u == 0) {  // the first sorted tile is the running list as it stands
-#pragma unroll
-      for (int q = 0; q < KMAX; ++q) best[q] = q < 16 ? ch[q < 16 ? q : 0] : INT_MIN;
-    } else {
-#pragma unroll
-      for (int q = 0; q < KMAX; ++q) {
-        const int r = KMAX - 1 - q;
-        best[q] = max(best[q], r < 16 ? ch[r < 16 ? r : 0] : INT_MIN);
-      }
-      bitonic_merge_desc<KMAX>(best);
-    }
-  }
-#pragma unroll
-  for (int d = 1; d <= 2; d <<= 1) {  // merge with the partner's list
-    int other[KMAX];
-#pragma unroll
-    for (int q = 0; q < KMAX; ++q) other[q] = __shfl_xor(best[q], d, kWave);
-#pragma unroll
-    for (int q = 0; q < KMAX; ++q) best[q] = max(best[q], other[KMAX - 1 - q]);
-    bitonic_merge_desc<KMAX>(best);
-  }
-  const int it = base + srow;
-  if (p != 0 || it >= count) return;
+    for (int j = 0; j < 4; ++j)
+      keys[(4 * g + j) * kQKeyStride + 16 * tq + c] =
+          valid ? (d[j] + kb) * 256 + (255 - o) : INT_MIN;
+  });
+  const int it = base + (lane >> 2);
+  if ((lane & 3) != 0 || it >= count) return;
   const int i = pool.index ? pool.index[it] : it;
-  uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0, w5 = 0;  // 190 pairs fit 6 words
-#pragma unroll
-  for (int q = 0; q < KMAX; ++q) {
-    if (q < k && best[q] != INT_MIN) {
-      const int pi = to_inst[255 - (best[q] & 255)];
-      const uint32_t bit = 1u << (pi & 31);
-      const int wd = pi >> 5;
-      w0 |= wd == 0 ? bit : 0u;
-      w1 |= wd == 1 ? bit : 0u;
-      w2 |= wd == 2 ? bit : 0u;
-      w3 |= wd == 3 ? bit : 0u;
-      w4 |= wd == 4 ? bit : 0u;
-      w5 |= wd == 5 ? bit : 0u;
-    }
-  }
-  uint32_t *mi = mask + (size_t)i * words;
-  const uint32_t ws[6] = {w0, w1, w2, w3, w4, w5};
-#pragma unroll
-  for (int wd = 0; wd < 6; ++wd)
-    if (wd < words) mi[wd] = ws[wd];
+  write_mask<KMAX>(best, k, to_inst, mask + (size_t)i * words, words);
 }
 
-// Forward pass, one thread per row; the weights are read at wave-uniform
-// addresses (scalar loads).  valid20[o] masks layout pairs absent on the
-// instance (their score is -inf).
-__global__ void __launch_bounds__(256)
-k_mlp_forward(const float *__restrict__ wq, const float *__restrict__ x, int rows,
-              const int *__restrict__ rows_dev, float *__restrict__ scores,
-              const int *__restrict__ to_inst) {
-  const int B = rows_dev ? *rows_dev : rows;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= B) return;
-  const float *xi = x + (size_t)i * kIn;
-  float h1[kHid], h2[kHid];
+// ---------------------------------------------- float inference on MFMA
+// The float form (bf16-rounded weights, fp32 activations and sums) on
+// v_mfma_f32_16x16x32_bf16, with the layout of k_infer_q: a wave takes 16
+// rows.  The MFMA multiplies bf16 operands, so every activation x (features,
+// hidden units) enters as two bf16 numbers, hi = bf16(x) and lo = bf16(x -
+// hi), and each tile is accumulated over both: w hi + w lo is exact in fp32
+// and differs from w x by at most |w x| 2^-17.  Scores rank by a key that
+// keeps their leading 24 bits (sign, exponent, 15 mantissa bits, in an
+// order-preserving integer form) and puts 255 - layout index in the low byte:
+// scores that agree in those bits go to the lower index.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int kBRowStride = 272;  // bytes per LDS row: 64 hi + 64 lo bf16, padded
+constexpr int kBLo = 128;         // byte offset of the lo half
+constexpr size_t kBWaveLds = 2 * kQRows * kBRowStride + kQRows * kQKeyStride * 4;
+// B operands (8 bf16 = one uint4 per lane): hidden layers as the integer
+// model (tile t, column c = unit 4c + t), output tile t, column c = pair 16t + c
+constexpr int kBOpB1 = 0, kBOpB2 = kQT1 * 2 * 64, kBOpB3 = 2 * kQT1 * 2 * 64,
+              kBOps = kBOpB3 + kQT3 * 2 * 64;
+
+__device__ __forceinline__ uint32_t bf16_bits(float x) { return __float_as_uint(bf16r(x)) >> 16; }
+
+// Order-preserving key of a float score with the layout index in the low byte.
+__device__ __forceinline__ int score_key(float s, int o) {
+  const uint32_t u = __float_as_uint(s);
+  const int ord = (u & 0x80000000u) ? (int)(u ^ 0x7fffffffu) : (int)u;
+  return (ord & ~0xff) | (255 - o);
+}
+
+// Packs the bf16-rounded weights into MFMA B operands.
+__global__ void k_pack_bf16(const float *__restrict__ wq, uint4 *__restrict__ ops) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= kBOps) return;
+  const int lane = e & 63, ks = (e >> 6) & 1, tile = e >> 7;
+  const int c = lane & 15, k0 = 32 * ks + 8 * (lane >> 4);
+  const float *w = nullptr;
+  if (e < kBOpB3) {
+    const int L = tile / kQT1, t = tile - L * kQT1;
+    w = wq + (L == 0 ? kOffW1 : kOffW2) + (4 * c + t) * kIn + k0;
+  } else {
+    const int o = 16 * (tile - 2 * kQT1) + c;
+    if (o < kOut) w = wq + kOffW3 + o * kHid + k0;
+  }
+  uint32_t h[8];
 #pragma unroll
-  for (int o = 0; o < kHid; ++o) h1[o] = wq[kOffB1 + o];
-  for (int j = 0; j < kIn; ++j) {
-    const float xj = xi[j];
+  for (int i = 0; i < 8; ++i) h[i] = w ? bf16_bits(w[i]) : 0u;
+  ops[e] = make_uint4(h[0] | h[1] << 16, h[2] | h[3] << 16, h[4] | h[5] << 16,
+                      h[6] | h[7] << 16);
+}
+
+__device__ __forceinline__ void bf_store8(unsigned char *row, int unit0, const float (&x)[4]) {
+  uint32_t hi[4], lo[4];
 #pragma unroll
-    for (int o = 0; o < kHid; ++o) h1[o] = fmaf(wq[kOffW1 + o * kIn + j], xj, h1[o]);
+  for (int i = 0; i < 4; ++i) {
+    const float h = bf16r(x[i]);
+    hi[i] = __float_as_uint(h) >> 16;
+    lo[i] = bf16_bits(x[i] - h);
+  }
+  *(uint2 *)(row + 2 * unit0) = make_uint2(hi[0] | hi[1] << 16, hi[2] | hi[3] << 16);
+  *(uint2 *)(row + kBLo + 2 * unit0) = make_uint2(lo[0] | lo[1] << 16, lo[2] | lo[3] << 16);
+}
+
+// A operands (hi, lo) of row lane % 16 for k-step ks.
+__device__ __forceinline__ void bf_a(const unsigned char *rows, int lane, int ks, bf16x8 &hi,
+                                     bf16x8 &lo) {
+  const unsigned char *row = rows + (lane & 15) * kBRowStride + 2 * (32 * ks + 8 * (lane >> 4));
+  hi = *(const bf16x8 *)row;
+  lo = *(const bf16x8 *)(row + kBLo);
+}
+
+__device__ __forceinline__ f32x4 bf_tile(const bf16x8 (&ah)[2], const bf16x8 (&al)[2],
+                                         const uint4 *__restrict__ ops, int lane) {
+  f32x4 d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ks = 0; ks < 2; ++ks) {
+    const uint4 e = ops[ks * 64 + lane];
+    const bf16x8 b = __builtin_bit_cast(bf16x8, e);
+    d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[ks], b, d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[ks], b, d, 0, 0, 0);
+  }
+  return d;
+}
+
+// One hidden layer: relu(W in + b) of the wave's 16 rows into `out`.
+__device__ __forceinline__ void bf_hidden(const unsigned char *in, unsigned char *out,
+                                          const uint4 *__restrict__ ops,
+                                          const float *__restrict__ bias, int lane) {
+  const int c = lane & 15, g = lane >> 4;
+  bf16x8 ah[2], al[2];
+  bf_a(in, lane, 0, ah[0], al[0]);
+  bf_a(in, lane, 1, ah[1], al[1]);
+  float h[4][4];  // [row 4g + j][unit 4c + t]
+#pragma unroll
+  for (int t = 0; t < kQT1; ++t) {
+    const f32x4 d = bf_tile(ah, al, ops + t * 2 * 64, lane);
+    const float b = bias[4 * c + t];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) h[j][t] = fmaxf(d[j] + b, 0.f);
   }
 #pragma unroll
-  for (int o = 0; o < kHid; ++o) {
-    h1[o] = fmaxf(h1[o], 0.f);
-    h2[o] = wq[kOffB2 + o];
+  for (int j = 0; j < 4; ++j) bf_store8(out + (4 * g + j) * kBRowStride, 4 * c, h[j]);
+}
+
+// XIN: the features are rows of x [count][64] instead of being computed from
+// the costs workspace.  scores_out (optional, [count][190]) receives every
+// score (-inf for pairs absent on the instance); mask (optional) the top-k
+// pair masks.
+template <int KMAX, bool XIN>
+__global__ void __launch_bounds__(64 * kQWaves)
+k_infer_bf(DevInst I, DevPool pool, const int *__restrict__ costs, const float *__restrict__ xin,
+           float norm, const uint4 *__restrict__ ops, const float *__restrict__ wq,
+           const int *__restrict__ to_inst, int k, int words, uint32_t *__restrict__ mask,
+           float *__restrict__ scores_out) {
+  extern __shared__ __align__(16) unsigned char bsm[];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int count = pool.count_dev ? *pool.count_dev : pool.count;
+  const int base = (blockIdx.x * kQWaves + w) * kQRows;
+  if (base >= count) return;  // waves never synchronize across the block
+  unsigned char *xa = bsm + (size_t)w * kBWaveLds;
+  unsigned char *xb = xa + kQRows * kBRowStride;
+  int *keys = (int *)(xb + kQRows * kBRowStride);
+  const int n = I.n, m = I.m;
+  {  // features 16 (lane / 16) .. + 15 of row lane % 16 (the formulas of k_features)
+    const int fr = lane & 15, fg = lane >> 4;
+    const int it = base + fr;
+    float f[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) f[e] = 0.f;
+    if (XIN && it < count) {
+      const float4 *src = (const float4 *)(xin + (size_t)it * kIn + 16 * fg);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float4 v = src[q];
+        f[4 * q] = v.x;
+        f[4 * q + 1] = v.y;
+        f[4 * q + 2] = v.z;
+        f[4 * q + 3] = v.w;
+      }
+    } else if (it < count) {
+      const int i = pool.index ? pool.index[it] : it;
+      const int *cs = costs + (size_t)i * 3 * m;
+      const bool bad = cs[0] < 0;
+      const int a = pool.d1[i], b = pool.d2[i];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int x = 16 * fg + e;
+        if (x < 60) {
+          const int part = x / 20, kk = x - 20 * part;
+          if (kk < m && !bad) f[e] = (float)cs[part * m + kk] / norm;
+        } else if (x == 60) {
+          f[e] = (float)a / (float)n;
+        } else if (x == 61) {
+          f[e] = (float)b / (float)n;
+        } else if (x == 62) {
+          f[e] = (float)(n - a - b) / (float)n;
+        } else if (!bad) {
+          int lb1 = 0;
+          for (int y = 0; y < m; ++y) lb1 = max(lb1, cs[y] + cs[2 * m + y] + cs[m + y]);
+          f[e] = (float)lb1 / norm;
+        }
+      }
+    }
+    unsigned char *row = xa + fr * kBRowStride;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float x4[4] = {f[4 * q], f[4 * q + 1], f[4 * q + 2], f[4 * q + 3]};
+      bf_store8(row, 16 * fg + 4 * q, x4);
+    }
   }
+  wave_sync();
+  bf_hidden(xa, xb, ops + kBOpB1, wq + kOffB1, lane);
+  wave_sync();
+  bf_hidden(xb, xa, ops + kBOpB2, wq + kOffB2, lane);
+  wave_sync();
+  const int c = lane & 15, g = lane >> 4;
+  bf16x8 ah[2], al[2];
+  bf_a(xa, lane, 0, ah[0], al[0]);
+  bf_a(xa, lane, 1, ah[1], al[1]);
+  int best[KMAX];
+  topk_keys<KMAX>(keys, lane, best, [&](int t, int tq) {
+    const int o = 16 * t + c;
+    const bool valid = o < kOut && to_inst[o < kOut ? o : 0] >= 0;
+    const float b3 = wq[kOffB3 + (o < kOut ? o : 0)];
+    const f32x4 d = bf_tile(ah, al, ops + kBOpB3 + t * 2 * 64, lane);
 #pragma unroll
-  for (int j = 0; j < kHid; ++j) {
-#pragma unroll
-    for (int o = 0; o < kHid; ++o) h2[o] = fmaf(wq[kOffW2 + o * kHid + j], h1[j], h2[o]);
-  }
-#pragma unroll
-  for (int o = 0; o < kHid; ++o) h2[o] = fmaxf(h2[o], 0.f);
-  float *si = scores + (size_t)i * kOut;
-  for (int o = 0; o < kOut; ++o) {
-    float s = wq[kOffB3 + o];
-#pragma unroll
-    for (int j = 0; j < kHid; ++j) s = fmaf(wq[kOffW3 + o * kHid + j], h2[j], s);
-    si[o] = to_inst[o] >= 0 ? s : -INFINITY;
-  }
+    for (int j = 0; j < 4; ++j) {
+      const float sc = d[j] + b3;
+      keys[(4 * g + j) * kQKeyStride + 16 * tq + c] = valid ? score_key(sc, o) : INT_MIN;
+      const int row = base + 4 * g + j;
+      if (scores_out && o < kOut && row < count)
+        scores_out[(size_t)row * kOut + o] = valid ? sc : -INFINITY;
+    }
+  });
+  const int it = base + (lane >> 2);
+  if (!mask || (lane & 3) != 0 || it >= count) return;
+  const int i = pool.index ? pool.index[it] : it;
+  write_mask<KMAX>(best, k, to_inst, mask + (size_t)i * words, words);
 }
 
 // Top-k layout pairs per row (larger score first; equal scores: lower index),
@@ -753,6 +819,7 @@ static int sel_get(Ctx *c, Selector **out) {
     for (float **p : {&S->master, &S->wq, &S->grad, &S->am, &S->av})
       ok = ok && hipMalloc(p, kParams * sizeof(float)) == hipSuccess;
     ok = ok && hipMalloc(&S->to_inst, kOut * sizeof(int)) == hipSuccess;
+    ok = ok && hipMalloc(&S->bops, kBOps * sizeof(uint4)) == hipSuccess;
     ok = ok && hipMalloc(&S->loss, sizeof(float)) == hipSuccess;
     c->sel = S;
     if (!ok) {
@@ -769,7 +836,7 @@ void selector_free(Ctx *c) {
   if (!S) return;
   void *bufs[] = {S->master, S->wq, S->grad, S->am, S->av, S->feat, S->scores, S->mask, S->h1,
                   S->h2, S->ds, S->dh1, S->dh2, S->rowloss, S->loss, S->to_inst, S->qops,
-                  S->qbias, S->reopen, S->reopen_count};
+                  S->qbias, S->reopen, S->reopen_count, S->bops};
   for (void *p : bufs) (void)hipFree(p);
   delete S;
   c->sel = nullptr;
@@ -864,14 +931,16 @@ static void launch_infer(Ctx *c, const DevPool &pool, int k, uint32_t *mask, hip
       PFSP_IQ(64);
 #undef PFSP_IQ
   } else {
-    const dim3 g((pool.count + kInferRows - 1) / kInferRows), b(kInferRows);
-    const size_t lds = (((size_t)kParams + 3) / 4 * 4 + (size_t)kHid * kInferRows) * 4;
+    const dim3 g((pool.count + kQRows * kQWaves - 1) / (kQRows * kQWaves)), b(64 * kQWaves);
+    const size_t lds = kQWaves * kBWaveLds;
     if (k <= 16)
-      hipLaunchKernelGGL(k_infer<16>, g, b, lds, s, I, pool, c->d_costs, instance_norm(c), S->wq,
-                         S->to_inst, k, words, mask);
+      hipLaunchKernelGGL((k_infer_bf<16, false>), g, b, lds, s, I, pool, c->d_costs,
+                         (const float *)nullptr, instance_norm(c), S->bops, S->wq, S->to_inst, k,
+                         words, mask, (float *)nullptr);
     else
-      hipLaunchKernelGGL(k_infer<32>, g, b, lds, s, I, pool, c->d_costs, instance_norm(c), S->wq,
-                         S->to_inst, k, words, mask);
+      hipLaunchKernelGGL((k_infer_bf<32, false>), g, b, lds, s, I, pool, c->d_costs,
+                         (const float *)nullptr, instance_norm(c), S->bops, S->wq, S->to_inst, k,
+                         words, mask, (float *)nullptr);
   }
 }
 
@@ -947,18 +1016,12 @@ int launch_learned_ready(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8
   fp.count_dev = S->reopen_count;
   fp.mask = nullptr;
   fp.mask_words = 0;
-  return launch_bound_costs_ready(c, fp, PFSP_LB2_FULL, ub, out_lb, out_prune, s, 0);
+  return launch_lb2_binned(c, fp, ub, out_lb, out_prune, s);
 }
 
-// k_infer stages all weights and a layer of activations in LDS (about 148
-// KiB); called once per process with the bound kernels' attributes.
-void init_selector_attributes() {
-  (void)hipFuncSetAttribute((const void *)k_infer<16>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  (void)hipFuncSetAttribute((const void *)k_infer<32>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  (void)hipGetLastError();
-}
+// The inference kernels fit the default LDS limit; kept as the hook called
+// once per process with the bound kernels' attributes.
+void init_selector_attributes() {}
 
 // Device form of an integer-model blob (layout above).
 static void q_pack(const int32_t *blob, std::vector<uint2> &ops, std::vector<int> &bias) {
@@ -1088,6 +1151,8 @@ int pfsp_selector_set(pfsp_ctx *h, const float *params, int64_t count) {
   S->step = 0;
   hipLaunchKernelGGL(k_round_weights, dim3((kParams + 255) / 256), dim3(256), 0, c->stream,
                      S->master, S->wq);
+  hipLaunchKernelGGL(k_pack_bf16, dim3((kBOps + 255) / 256), dim3(256), 0, c->stream, S->wq,
+                     S->bops);
   PFSP_HIP(c, hipGetLastError());
   PFSP_HIP(c, hipStreamSynchronize(c->stream));
   S->loaded = 1;
@@ -1136,8 +1201,19 @@ int pfsp_selector_forward(pfsp_ctx *h, const float *x, int32_t rows, float *scor
   if (rc) return rc;
   if (!c->sel->loaded) return set_err(c, PFSP_EINVAL, "no float selector parameters set");
   if (rows == 0) return PFSP_OK;
-  hipLaunchKernelGGL(k_mlp_forward, dim3((rows + 255) / 256), dim3(256), 0, c->stream,
-                     c->sel->wq, x, rows, (const int *)nullptr, scores_out, c->sel->to_inst);
+  // the float form's arithmetic of the learned bound (bf16 MFMA, hi/lo activations)
+  DevPool pool;
+  pool.count = rows;
+  pool.n = c->n;
+  pool.perm = pool.d1 = pool.d2 = nullptr;
+  pool.mask = nullptr;
+  pool.mask_words = 0;
+  pool.dir = nullptr;
+  pool.argpair = nullptr;
+  const dim3 g((rows + kQRows * kQWaves - 1) / (kQRows * kQWaves)), b(64 * kQWaves);
+  hipLaunchKernelGGL((k_infer_bf<16, true>), g, b, kQWaves * kBWaveLds, c->stream, c->inst(),
+                     pool, (const int *)nullptr, x, 1.f, c->sel->bops, c->sel->wq,
+                     c->sel->to_inst, 1, 0, (uint32_t *)nullptr, scores_out);
   PFSP_HIP(c, hipGetLastError());
   return PFSP_OK;
 }
@@ -1251,6 +1327,7 @@ int pfsp_selector_train_step(pfsp_ctx *h, const float *x, const float *target, i
                        S->am, S->av, lr, bc1, bc2);
     hipLaunchKernelGGL(k_round_weights, dim3((kParams + 255) / 256), dim3(256), 0, s, S->master,
                        S->wq);
+    hipLaunchKernelGGL(k_pack_bf16, dim3((kBOps + 255) / 256), dim3(256), 0, s, S->wq, S->bops);
     PFSP_HIP(c, hipGetLastError());
   }
   float l = 0.f;

@@ -170,3 +170,50 @@ def test_search_after_queued_bound(ctx):
     np.testing.assert_array_equal(lb.cpu().numpy()[idx], olb)
     np.testing.assert_array_equal(pr.cpu().numpy()[idx], opr)
     np.testing.assert_array_equal(dr.cpu().numpy()[idx], odr)
+
+
+def _pair_bits(m, pairs):
+    P = m * (m - 1) // 2
+    mask = np.zeros((P + 31) // 32, dtype=np.uint32)
+    for u, v in pairs:
+        q = oracle.pair_index(m, u, v)
+        mask[q >> 5] |= np.uint32(1 << (q & 31))
+    return mask
+
+
+@pytest.mark.parametrize("n,m,seed", [(12, 6, 3), (14, 8, 4), (11, 20, 5)])
+@pytest.mark.parametrize("variant", ["adjacent", "last", "random"])
+def test_static_pair_search(ctx, n, m, seed, variant):
+    """Searches bounded over one fixed pair set (Section 2.4 variants: the m - 1
+    adjacent pairs, the m - 1 pairs with the last machine, or a random set):
+    the oracle's optimum from NEH + 1, and with the incumbent at the optimum
+    exactly the oracle's critical tree."""
+    p = inputs.instance(n, m, seed)
+    ctx.load_instance(p)
+    if variant == "adjacent":
+        mask = ctx.pair_mask(binding.PAIRS_ADJACENT)
+        np.testing.assert_array_equal(mask, _pair_bits(m, [(k, k + 1) for k in range(m - 1)]))
+    elif variant == "last":
+        mask = ctx.pair_mask(binding.PAIRS_LAST)
+        np.testing.assert_array_equal(mask, _pair_bits(m, [(k, m - 1) for k in range(m - 1)]))
+    else:
+        rng = np.random.default_rng(seed)
+        P = m * (m - 1) // 2
+        mask = _pair_bits(m, [(u, v) for u in range(m) for v in range(u + 1, m)
+                              if rng.random() < 16 / P])
+    ctx.search_set_pairs(mask)
+    ub0, _ = ctx.neh()
+    ref = oracle.search(p, ub0 + 1, oracle.LB2_SUBSET, pair_mask=mask, threads=8)
+    r = ctx.search(ub0 + 1, 0, binding.LB2_SUBSET)
+    assert r["proven"] and ref["proven"] and r["best"] == ref["best"]
+    if r["found"]:
+        _valid(p, r["perm"], r["best"])
+    crit = oracle.search(p, ref["best"], oracle.LB2_SUBSET, pair_mask=mask, threads=8)
+    r = ctx.search(ref["best"], 0, binding.LB2_SUBSET)
+    assert (r["nodes"], r["children"]) == (crit["nodes"], crit["children"])
+
+
+def test_subset_search_needs_pairs(ctx):
+    ctx.load_instance(inputs.instance(8, 4, 1))
+    with pytest.raises(binding.PfspError):
+        ctx.search(10**6, 0, binding.LB2_SUBSET)

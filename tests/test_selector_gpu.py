@@ -63,10 +63,15 @@ def test_forward_and_select(ctx):
     rng = np.random.default_rng(82)
     x = rng.random((500, 64)).astype(np.float32)
     sc = ctx.selector_forward(_t(ctx, x)).cpu().numpy()
-    ref, _ = S.forward([q.astype(np.float64) for q in params], x.astype(np.float64))
+    p64 = [q.astype(np.float64) for q in params]
+    ref, _ = S.forward(p64, x.astype(np.float64))
     valid = S.valid_pairs(m)
     assert np.isneginf(sc[:, ~valid]).all()
-    _close(sc[:, valid], ref[:, valid])
+    # per score, against the sum of absolute terms: the bf16 hi/lo split of the
+    # activations loses at most 2^-16 of each, fp32 sums of 128 products at most
+    # 128 * 2^-24, three layers
+    tol = 1e-4 * S.forward_magnitude(p64, x.astype(np.float64))
+    assert (np.abs(sc[:, valid] - ref[:, valid]) <= tol[:, valid]).all()
     for k in (1, 16, 32):
         mk = ctx.selector_select(_t(ctx, sc), k).cpu().numpy().view(np.uint32)
         P = m * (m - 1) // 2
@@ -152,8 +157,7 @@ def test_learned_bound_equals_subset_bound(ctx, topk):
     ctx.set_option("learned_topk", k)
     lb, pr, dr, _ = ctx.bound_children(*dev, kind=binding.LB2_LEARNED, ub=1900)
     torch.cuda.synchronize()
-    mask = ctx.selector_select(ctx.selector_forward(ctx.selector_features(*dev)), k)
-    mask = mask.cpu().numpy().view(np.uint32)
+    mask = ctx.selector_infer(*dev, k).cpu().numpy().view(np.uint32)
     olb, opr, odr = oracle.bound_children(p, perm, d1, d2, oracle.LB2_SUBSET, 1900,
                                           pair_mask=mask, threads=8)
     np.testing.assert_array_equal(lb.cpu().numpy(), olb)
@@ -162,6 +166,47 @@ def test_learned_bound_equals_subset_bound(ctx, topk):
     full, _, _ = oracle.bound_children(p, perm, d1, d2, oracle.LB2_FULL, 1900, threads=8)
     assert (olb <= full).all()
     ctx.set_option("learned_topk", 16)
+
+
+def _bits_layout(mask_words, m):
+    """uint32 words over instance pairs -> bool [B, 190] over layout pairs."""
+    out = np.zeros((mask_words.shape[0], 190), dtype=bool)
+    for u in range(m):
+        for v in range(u + 1, m):
+            pi = u * (2 * m - u - 1) // 2 + (v - u - 1)
+            out[:, S.pair20(u, v)] = (mask_words[:, pi >> 5] >> (pi & 31)) & 1
+    return out
+
+
+@pytest.mark.parametrize("n,m", [(20, 20), (50, 20), (12, 7)])
+@pytest.mark.parametrize("k", [1, 16, 32])
+def test_float_inference_masks(ctx, n, m, k):
+    """The learned bound's float form (features from the costs, bf16 MFMA
+    layers, ranking keys, top-k) selects exactly the oracle's top-k by key of
+    the scores that pfsp_selector_forward computes with the same arithmetic
+    from the library's features; those scores are within the error bound of
+    the oracle's (test_forward_and_select), the features within 1e-6."""
+    import torch
+    p = inputs.instance(n, m, 140 + n + m)
+    perm, d1, d2 = _quant_pool(n, 141)
+    ctx.load_instance(p)
+    params = _params(142)
+    ctx.selector_set(params)
+    dev = [_t(ctx, a) for a in (perm, d1, d2)]
+    got = ctx.selector_infer(*dev, k).cpu().numpy().view(np.uint32)
+    feat = ctx.selector_features(*dev)
+    sc = ctx.selector_forward(feat).cpu().numpy()
+    torch.cuda.synchronize()
+    _close(feat.cpu().numpy(), S.features(p, perm, d1, d2), rel=1e-6)
+    valid = S.valid_pairs(m)
+    assert np.isneginf(sc[:, ~valid]).all()
+    want = S.topk_keys_mask(S.score_keys(np.where(valid, sc, 0.0)), valid, k)
+    np.testing.assert_array_equal(_bits_layout(got, m), want)
+    p64 = [q.astype(np.float64) for q in params]
+    x = S.features(p, perm, d1, d2)
+    ref, _ = S.forward(p64, x)
+    tol = 1e-4 * S.forward_magnitude(p64, x)
+    assert (np.abs(sc[:, valid] - ref[:, valid]) <= tol[:, valid]).all()
 
 
 # ---------------------------------------------------------------- integer model

@@ -231,3 +231,21 @@ def test_quant_invariances():
     s = np.zeros((1, 190), dtype=np.int64)
     m = S.topk_mask(s, S.valid_pairs(20), 3)
     assert list(np.nonzero(m[0])[0]) == [0, 1, 2]
+
+
+def test_score_keys_order_and_ties():
+    """The float form's ranking keys: order-preserving across signs and
+    magnitudes, equal leading 24 bits rank by the lower index."""
+    vals = np.array([-3.5, -1.0, -1e-30, 0.0, 1e-30, 0.25, 1.0, 7.0, 1e20], dtype=np.float32)
+    s = np.zeros((1, S.N_OUT))
+    s[0, :len(vals)] = vals[::-1]                 # index 0 holds the largest
+    s[0, len(vals):] = -1e30
+    keys = S.score_keys(s)[0]
+    assert (np.diff(keys[:len(vals)]) < 0).all()
+    s = np.full((1, S.N_OUT), 1.0)
+    s[0, 10] = np.nextafter(np.float32(1.0), np.float32(2.0))   # 1 ulp: same leading bits
+    s[0, 20] = 1.0 + 2.0**-14                     # differs in the 14th mantissa bit
+    keys = S.score_keys(s)[0]
+    assert keys[20] > keys[0] > keys[10] > keys[11]
+    mask = S.topk_keys_mask(keys[None], np.ones(S.N_OUT, dtype=bool), 2)[0]
+    assert set(np.flatnonzero(mask)) == {20, 0}

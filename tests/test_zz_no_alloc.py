@@ -61,7 +61,7 @@ def test_noalloc_rejects_oversized_pool_and_learned_kind():
     try:
         n, m = 20, 20
         ctx.load_instance(inputs.instance(n, m, 3))
-        count = ((1 << 24) - 2) // (3 * m + 2) + 1   # one parent beyond the workspace
+        count = (1 << 24) // (3 * m) + 1   # one parent beyond the workspace
         perm, d1, d2 = inputs.random_pool(n, count, 9)
         dev = [torch.from_numpy(a).to(ctx.device) for a in (perm, d1, d2)]
         lb = torch.empty((count, 2, n), dtype=torch.int32, device=ctx.device)

@@ -161,7 +161,9 @@ int pfsp_search_set_pairs(pfsp_ctx *c, const uint32_t *mask, int32_t words);
 /* Depth-first branch-and-bound on the device (Sections 2.2-2.5) from the
  * root (empty sigma1, sigma2): pools of up to `pool_batch` (option) nodes are
  * popped from a device stack, decomposed with pfsp_bound_children's step,
- * and their surviving children pushed back (leftmost on top).  Looks for a
+ * and their surviving children pushed back (leftmost on top); when the stack
+ * nears its capacity its bottom (shallowest) records move to host memory and
+ * come back once the stack above them has drained.  Looks for a
  * schedule with C_max < ub0 (INT32_MAX: none known).  budget_nodes > 0 stops
  * after about that many decomposed nodes (returns PFSP_BUDGET).  lb_kind as
  * above; PFSP_LB2_SUBSET takes the pair set of pfsp_search_set_pairs for
@@ -170,6 +172,24 @@ int pfsp_search_set_pairs(pfsp_ctx *c, const uint32_t *mask, int32_t words);
  * res must not be NULL. */
 int pfsp_search(pfsp_ctx *c, int32_t ub0, int64_t budget_nodes, int lb_kind,
                 pfsp_result *res);
+
+/* Checkpoint of a search that stopped on its node budget (pfsp_search or
+ * pfsp_search_resume returned PFSP_BUDGET), for restarting it later, in this
+ * process or another, on the same instance (the paper's global checkpoints of
+ * Section 4.1, here for one GPU): the open nodes (device stack and any part
+ * moved to host memory), the incumbent and best schedule, ub0, the bound
+ * kind and the node counters, in a self-describing byte format.  buf NULL:
+ * *size receives the bytes needed.  PFSP_ERANGE if cap is smaller.  HOST
+ * buffer; synchronous. */
+int pfsp_search_dump(pfsp_ctx *c, void *buf, int64_t cap, int64_t *size);
+
+/* Continues the search of a checkpoint (HOST buf[size]) on the loaded
+ * instance (PFSP_EINVAL if it is another one) with the checkpoint's bound
+ * kind and ub0, under the current options, until the tree is exhausted or
+ * budget_nodes (counted from the first start) is reached.  The result counts
+ * the nodes of every run since the first start.  Synchronous. */
+int pfsp_search_resume(pfsp_ctx *c, const void *buf, int64_t size, int64_t budget_nodes,
+                       pfsp_result *res);
 
 /* Copies up to max_records nodes decomposed by the last pfsp_search (every
  * log_stride-th node of each batch, at most log_capacity; option names above)

@@ -28,7 +28,7 @@ EXPORTS = ["pfsp_create", "pfsp_destroy", "pfsp_last_error", "pfsp_load_instance
            "pfsp_search_log", "pfsp_multi_create", "pfsp_multi_destroy", "pfsp_multi_bound",
            "pfsp_multi_set_shape", "pfsp_multi_autotune", "pfsp_autotune",
            "pfsp_selector_set_quant", "pfsp_selector_infer", "pfsp_bound_children_noalloc",
-           "pfsp_pair_mask", "pfsp_search_set_pairs"]
+           "pfsp_pair_mask", "pfsp_search_set_pairs", "pfsp_search_dump", "pfsp_search_resume"]
 PAIRS_ADJACENT, PAIRS_LAST = 1, 2
 SELECTOR_PARAMS = 20670
 SELECTOR_QPARAMS = 20675
@@ -81,6 +81,8 @@ def lib():
         L.pfsp_check.argtypes = [vp]
         L.pfsp_pair_mask.argtypes = [vp, ctypes.c_int, vp, i32]
         L.pfsp_search_set_pairs.argtypes = [vp, vp, i32]
+        L.pfsp_search_dump.argtypes = [vp, vp, i64, ctypes.POINTER(i64)]
+        L.pfsp_search_resume.argtypes = [vp, vp, i64, i64, ctypes.POINTER(Result)]
         L.pfsp_search.argtypes = [vp, i32, i64, ctypes.c_int, ctypes.POINTER(Result)]
         L.pfsp_neh.argtypes = [vp, vp, vp]
         L.pfsp_set_option.argtypes = [vp, ctypes.c_char_p, i64]
@@ -227,16 +229,36 @@ class Context:
     def check(self):
         return self._check(lib().pfsp_check(self.h))
 
+    @staticmethod
+    def _result(res, perm, rc):
+        return dict(best=res.best_cmax, found=bool(res.found), proven=bool(res.proven),
+                    steps=res.steps, nodes=res.nodes_decomposed,
+                    children=res.children_bounded, max_pool=res.max_pool,
+                    seconds=res.seconds, perm=perm.astype(np.uint8), budget_hit=rc == 1)
+
     def search(self, ub0=INT32_MAX, budget=0, kind=LB1):
         perm = np.zeros(self.n, dtype=np.int32)
         res = Result()
         res.best_perm = perm.ctypes.data_as(ctypes.c_void_p)
         rc = self._check(lib().pfsp_search(self.h, int(ub0), int(budget), kind,
                                            ctypes.byref(res)))
-        return dict(best=res.best_cmax, found=bool(res.found), proven=bool(res.proven),
-                    steps=res.steps, nodes=res.nodes_decomposed,
-                    children=res.children_bounded, max_pool=res.max_pool,
-                    seconds=res.seconds, perm=perm.astype(np.uint8), budget_hit=rc == 1)
+        return self._result(res, perm, rc)
+
+    def search_dump(self) -> bytes:
+        """Checkpoint of the last search that stopped on its budget."""
+        size = ctypes.c_int64()
+        self._check(lib().pfsp_search_dump(self.h, None, 0, ctypes.byref(size)))
+        buf = ctypes.create_string_buffer(size.value)
+        self._check(lib().pfsp_search_dump(self.h, buf, size.value, ctypes.byref(size)))
+        return buf.raw[:size.value]
+
+    def search_resume(self, ckpt: bytes, budget=0):
+        perm = np.zeros(self.n, dtype=np.int32)
+        res = Result()
+        res.best_perm = perm.ctypes.data_as(ctypes.c_void_p)
+        rc = self._check(lib().pfsp_search_resume(self.h, ckpt, len(ckpt), int(budget),
+                                                  ctypes.byref(res)))
+        return self._result(res, perm, rc)
 
     def search_log(self, max_records):
         """Nodes logged by the last search: (perm [k, n] u8, d1 [k], d2 [k]) on the host."""

@@ -20,6 +20,10 @@
 // being decomposed (lazy re-check).  A leaf child (no unscheduled job left)
 // carries its makespan as LB; if it is below the step's incumbent it lowers
 // the incumbent with atomicMin and the best leaf of the step is recorded.
+#include <stddef.h>
+#include <string.h>
+
+#include <algorithm>
 #include <chrono>
 #include <vector>
 
@@ -67,6 +71,14 @@ struct SearchState {
   // node log (option log_capacity > 0): every log_stride-th decomposed node
   uint8_t *l_perm = nullptr, *l_d1 = nullptr, *l_d2 = nullptr;
   long long log_cap = 0;
+  // records moved to host memory from the bottom of the device stack (the
+  // shallowest open nodes, needed only once everything above them is done)
+  std::vector<uint8_t> h_perm, h_d1, h_d2;
+  std::vector<int> h_lb;
+  // the search that pfsp_search_dump / pfsp_search_resume continue
+  int32_t ub0 = 0;
+  int kind = 0;
+  int resumable = 0;  // the last search stopped on its budget
 };
 
 constexpr int kScanBlock = 1024;  // parents per k_scan_local block (256 threads x 4)
@@ -532,45 +544,79 @@ static int build_graph(Ctx *c, int kind) {
   return PFSP_OK;
 }
 
-}  // namespace pfsp
-
-using namespace pfsp;
-
-extern "C" int pfsp_search(pfsp_ctx *h, int32_t ub0, int64_t budget_nodes, int lb_kind,
-                           pfsp_result *res) {
-  if (!h) return PFSP_EINVAL;
-  Ctx *c = &h->impl;
-  if (c->n == 0) return set_err(c, PFSP_ENOINST, "no instance loaded");
-  if (!res) return set_err(c, PFSP_EINVAL, "res is NULL");
-  if (lb_kind < PFSP_LB1 || lb_kind > PFSP_LB2_LEARNED)
-    return set_err(c, PFSP_EINVAL, "unknown lb_kind");
-  if (lb_kind == PFSP_LB2_SUBSET && !c->d_static_mask)
-    return set_err(c, PFSP_EINVAL, "PFSP_LB2_SUBSET searches need pfsp_search_set_pairs");
-  if (lb_kind != PFSP_LB1 && c->m < 2) return set_err(c, PFSP_ERANGE, "LB2 kinds need m >= 2");
-  if (budget_nodes < 0) return set_err(c, PFSP_EINVAL, "negative budget");
-  PFSP_HIP(c, hipSetDevice(c->device));
-  // the search stream shares the bound workspace with work queued on the ctx stream
-  PFSP_HIP(c, hipStreamSynchronize(c->stream));
-  int rc = search_alloc(c);
-  if (rc) return rc;
+// Moves the bottom `count` records of the device stack (top records) to the
+// end of the host stack and shifts the rest down.  The stream is idle.
+static int spill(Ctx *c, long long top, long long count) {
   SearchState *S = c->search;
-  if (lb_kind == PFSP_LB2_LEARNED) {  // size the selector workspaces before any capture
-    rc = learned_prepare(c, S->N);
-    if (rc) return rc;
+  const int n = S->n;
+  const size_t h = S->h_d1.size();
+  S->h_perm.resize((h + count) * n);
+  S->h_d1.resize(h + count);
+  S->h_d2.resize(h + count);
+  S->h_lb.resize(h + count);
+  PFSP_HIP(c, hipMemcpy(S->h_perm.data() + h * n, S->s_perm, (size_t)count * n,
+                        hipMemcpyDeviceToHost));
+  PFSP_HIP(c, hipMemcpy(S->h_d1.data() + h, S->s_d1, count, hipMemcpyDeviceToHost));
+  PFSP_HIP(c, hipMemcpy(S->h_d2.data() + h, S->s_d2, count, hipMemcpyDeviceToHost));
+  PFSP_HIP(c, hipMemcpy(S->h_lb.data() + h, S->s_lb, (size_t)count * 4, hipMemcpyDeviceToHost));
+  // [count, top) -> [0, top - count) in chunks of at most count records: each
+  // chunk's source lies above its destination and above every later write
+  for (long long b = 0; b < top - count; b += count) {
+    const long long len = std::min(count, top - count - b);
+    PFSP_HIP(c, hipMemcpy(S->s_perm + b * n, S->s_perm + (b + count) * n, (size_t)len * n,
+                          hipMemcpyDeviceToDevice));
+    PFSP_HIP(c, hipMemcpy(S->s_d1 + b, S->s_d1 + b + count, len, hipMemcpyDeviceToDevice));
+    PFSP_HIP(c, hipMemcpy(S->s_d2 + b, S->s_d2 + b + count, len, hipMemcpyDeviceToDevice));
+    PFSP_HIP(c, hipMemcpy(S->s_lb + b, S->s_lb + b + count, (size_t)len * 4,
+                          hipMemcpyDeviceToDevice));
   }
+  return PFSP_OK;
+}
+
+// Puts the top `count` host records back as the device stack's [0, count).
+static int refill(Ctx *c, long long count) {
+  SearchState *S = c->search;
+  const int n = S->n;
+  const size_t h = S->h_d1.size() - count;
+  PFSP_HIP(c, hipMemcpy(S->s_perm, S->h_perm.data() + h * n, (size_t)count * n,
+                        hipMemcpyHostToDevice));
+  PFSP_HIP(c, hipMemcpy(S->s_d1, S->h_d1.data() + h, count, hipMemcpyHostToDevice));
+  PFSP_HIP(c, hipMemcpy(S->s_d2, S->h_d2.data() + h, count, hipMemcpyHostToDevice));
+  PFSP_HIP(c, hipMemcpy(S->s_lb, S->h_lb.data() + h, (size_t)count * 4, hipMemcpyHostToDevice));
+  S->h_perm.resize(h * n);
+  S->h_d1.resize(h);
+  S->h_d2.resize(h);
+  S->h_lb.resize(h);
+  return PFSP_OK;
+}
+
+static int set_top(Ctx *c, long long top) {
+  SearchState *S = c->search;
+  const int t = (int)top;
+  PFSP_HIP(c, hipMemcpy((char *)S->ctl + offsetof(SearchCtl, top), &t, sizeof(int),
+                        hipMemcpyHostToDevice));
+  return PFSP_OK;
+}
+
+// Replays search steps from the current device state until the tree is
+// exhausted (device and host stacks empty) or the budget is spent.
+static int run_search(Ctx *c, int lb_kind, int32_t ub0, int64_t budget_nodes, pfsp_result *res,
+                      std::chrono::steady_clock::time_point t0) {
+  SearchState *S = c->search;
   const int n = c->n;
-  const auto t0 = std::chrono::steady_clock::now();
-  hipLaunchKernelGGL(k_init_root, dim3(1), dim3(256), 0, S->stream, S->ctl, n, (int)ub0,
-                     S->s_perm, S->s_d1, S->s_d2, S->s_lb);
-  PFSP_HIP(c, hipGetLastError());
+  int rc;
   if (c->use_graph) {
     rc = build_graph(c, lb_kind);
     if (rc) return rc;
   }
   const int k = (int)c->poll_every;
+  // a step pushes at most N (n - 1) records: at a poll, keep k steps of room
+  const long long grow = (long long)k * S->N * (n > 1 ? n - 1 : 1);
+  const long long spill_hi = S->cap - grow;
   int status = PFSP_OK;
   long long max_pool = 1;
   int steps = 0;
+  S->resumable = 0;
   for (;;) {
     for (int t = 0; t < k; ++t) {
       if (c->use_graph) {
@@ -585,15 +631,30 @@ extern "C" int pfsp_search(pfsp_ctx *h, int32_t ub0, int64_t budget_nodes, int l
     PFSP_HIP(c, hipStreamSynchronize(S->stream));
     const SearchCtl &hc = *S->ctl_host;
     steps = (int)hc.steps;
-    if (hc.top > max_pool) max_pool = hc.top;
+    const long long held = hc.top + (long long)S->h_d1.size();
+    if (held > max_pool) max_pool = held;
     if (hc.overflow) {
       status = set_err(c, PFSP_ENOMEM, "search stack capacity exceeded (raise pool_capacity)");
       break;
     }
-    if (hc.top == 0) break;
-    if (budget_nodes > 0 && hc.nodes >= budget_nodes) {
+    if (budget_nodes > 0 && hc.nodes >= budget_nodes && held > 0) {
       status = PFSP_BUDGET;
+      S->resumable = 1;
       break;
+    }
+    if (hc.top == 0) {
+      if (S->h_d1.empty()) break;
+      // the deepest spilled records come back, filling half the room
+      const long long x = std::min<long long>((long long)S->h_d1.size(),
+                                              std::max<long long>(spill_hi / 2, S->N));
+      rc = refill(c, x);
+      if (!rc) rc = set_top(c, x);
+      if (rc) return rc;
+    } else if (spill_hi > S->N && hc.top > spill_hi) {
+      const long long x = hc.top - spill_hi / 2;
+      rc = spill(c, hc.top, x);
+      if (!rc) rc = set_top(c, hc.top - x);
+      if (rc) return rc;
     }
   }
   const SearchCtl hc = *S->ctl_host;
@@ -612,6 +673,174 @@ extern "C" int pfsp_search(pfsp_ctx *h, int32_t ub0, int64_t budget_nodes, int l
     for (int j = 0; j < n; ++j) res->best_perm[j] = tmp[j];
   }
   return status;
+}
+
+static int search_prepare(Ctx *c, int lb_kind, pfsp_result *res) {
+  if (c->n == 0) return set_err(c, PFSP_ENOINST, "no instance loaded");
+  if (!res) return set_err(c, PFSP_EINVAL, "res is NULL");
+  if (lb_kind < PFSP_LB1 || lb_kind > PFSP_LB2_LEARNED)
+    return set_err(c, PFSP_EINVAL, "unknown lb_kind");
+  if (lb_kind == PFSP_LB2_SUBSET && !c->d_static_mask)
+    return set_err(c, PFSP_EINVAL, "PFSP_LB2_SUBSET searches need pfsp_search_set_pairs");
+  if (lb_kind != PFSP_LB1 && c->m < 2) return set_err(c, PFSP_ERANGE, "LB2 kinds need m >= 2");
+  PFSP_HIP(c, hipSetDevice(c->device));
+  // the search stream shares the bound workspace with work queued on the ctx stream
+  PFSP_HIP(c, hipStreamSynchronize(c->stream));
+  int rc = search_alloc(c);
+  if (rc) return rc;
+  if (lb_kind == PFSP_LB2_LEARNED)  // size the selector workspaces before any capture
+    rc = learned_prepare(c, c->search->N);
+  return rc;
+}
+
+}  // namespace pfsp
+
+using namespace pfsp;
+
+extern "C" int pfsp_search(pfsp_ctx *h, int32_t ub0, int64_t budget_nodes, int lb_kind,
+                           pfsp_result *res) {
+  if (!h) return PFSP_EINVAL;
+  Ctx *c = &h->impl;
+  if (budget_nodes < 0) return set_err(c, PFSP_EINVAL, "negative budget");
+  int rc = search_prepare(c, lb_kind, res);
+  if (rc) return rc;
+  SearchState *S = c->search;
+  S->h_perm.clear();
+  S->h_d1.clear();
+  S->h_d2.clear();
+  S->h_lb.clear();
+  S->ub0 = ub0;
+  S->kind = lb_kind;
+  const auto t0 = std::chrono::steady_clock::now();
+  hipLaunchKernelGGL(k_init_root, dim3(1), dim3(256), 0, S->stream, S->ctl, c->n, (int)ub0,
+                     S->s_perm, S->s_d1, S->s_d2, S->s_lb);
+  PFSP_HIP(c, hipGetLastError());
+  return run_search(c, lb_kind, ub0, budget_nodes, res, t0);
+}
+
+namespace {
+
+struct CkptHeader {
+  char magic[8];  // "PFSPCKP1"
+  int32_t n, m, kind, ub0, ub, pad;
+  uint64_t inst_hash;
+  int64_t nodes, children, steps, records;
+};
+
+uint64_t instance_hash(const Ctx *c) {  // FNV-1a over n, m and p
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void *d, size_t len) {
+    const unsigned char *b = (const unsigned char *)d;
+    for (size_t i = 0; i < len; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  };
+  mix(&c->n, 4);
+  mix(&c->m, 4);
+  mix(c->p_host, (size_t)c->n * c->m * 4);
+  return h;
+}
+
+}  // namespace
+
+extern "C" int pfsp_search_dump(pfsp_ctx *h, void *buf, int64_t cap, int64_t *size) {
+  if (!h || !size) return PFSP_EINVAL;
+  Ctx *c = &h->impl;
+  SearchState *S = c->search;
+  if (!S || !S->resumable || S->n != c->n)
+    return set_err(c, PFSP_EINVAL, "no search stopped on its budget to dump");
+  PFSP_HIP(c, hipSetDevice(c->device));
+  PFSP_HIP(c, hipStreamSynchronize(S->stream));
+  PFSP_HIP(c, hipMemcpy(S->ctl_host, S->ctl, sizeof(SearchCtl), hipMemcpyDeviceToHost));
+  const SearchCtl hc = *S->ctl_host;
+  const int n = c->n;
+  const long long hr = (long long)S->h_d1.size(), records = hr + hc.top;
+  const int64_t need = (int64_t)sizeof(CkptHeader) + records * (n + 6) + n;
+  *size = need;
+  if (!buf) return PFSP_OK;
+  if (cap < need) return set_err(c, PFSP_ERANGE, "checkpoint buffer too small");
+  CkptHeader hd;
+  memcpy(hd.magic, "PFSPCKP1", 8);
+  hd.n = n;
+  hd.m = c->m;
+  hd.kind = S->kind;
+  hd.ub0 = S->ub0;
+  hd.ub = hc.ub;
+  hd.pad = 0;
+  hd.inst_hash = instance_hash(c);
+  hd.nodes = hc.nodes;
+  hd.children = hc.children;
+  hd.steps = hc.steps;
+  hd.records = records;
+  unsigned char *o = (unsigned char *)buf;
+  memcpy(o, &hd, sizeof(hd));
+  o += sizeof(hd);
+  // records bottom to top: the host part, then the device stack
+  unsigned char *perm = o, *d1 = perm + records * n, *d2 = d1 + records;
+  unsigned char *lb = d2 + records;
+  if (hr) {
+    memcpy(perm, S->h_perm.data(), (size_t)hr * n);
+    memcpy(d1, S->h_d1.data(), hr);
+    memcpy(d2, S->h_d2.data(), hr);
+    memcpy(lb, S->h_lb.data(), (size_t)hr * 4);
+  }
+  if (hc.top) {
+    PFSP_HIP(c, hipMemcpy(perm + hr * n, S->s_perm, (size_t)hc.top * n, hipMemcpyDeviceToHost));
+    PFSP_HIP(c, hipMemcpy(d1 + hr, S->s_d1, hc.top, hipMemcpyDeviceToHost));
+    PFSP_HIP(c, hipMemcpy(d2 + hr, S->s_d2, hc.top, hipMemcpyDeviceToHost));
+    PFSP_HIP(c, hipMemcpy(lb + hr * 4, S->s_lb, (size_t)hc.top * 4, hipMemcpyDeviceToHost));
+  }
+  PFSP_HIP(c, hipMemcpy(lb + records * 4, S->best_perm, n, hipMemcpyDeviceToHost));
+  return PFSP_OK;
+}
+
+extern "C" int pfsp_search_resume(pfsp_ctx *h, const void *buf, int64_t size,
+                                  int64_t budget_nodes, pfsp_result *res) {
+  if (!h) return PFSP_EINVAL;
+  Ctx *c = &h->impl;
+  if (!buf || size < (int64_t)sizeof(CkptHeader))
+    return set_err(c, PFSP_EINVAL, "checkpoint too short");
+  if (budget_nodes < 0) return set_err(c, PFSP_EINVAL, "negative budget");
+  CkptHeader hd;
+  memcpy(&hd, buf, sizeof(hd));
+  if (memcmp(hd.magic, "PFSPCKP1", 8) != 0) return set_err(c, PFSP_EINVAL, "not a checkpoint");
+  if (c->n == 0) return set_err(c, PFSP_ENOINST, "no instance loaded");
+  if (hd.n != c->n || hd.m != c->m || hd.inst_hash != instance_hash(c))
+    return set_err(c, PFSP_EINVAL, "checkpoint of another instance");
+  const int n = c->n;
+  if (hd.records < 0 || size < (int64_t)sizeof(hd) + hd.records * (n + 6) + n)
+    return set_err(c, PFSP_EINVAL, "checkpoint truncated");
+  int rc = search_prepare(c, hd.kind, res);
+  if (rc) return rc;
+  SearchState *S = c->search;
+  const long long R = hd.records;
+  const unsigned char *in = (const unsigned char *)buf + sizeof(hd);
+  const unsigned char *perm = in, *d1 = perm + R * n, *d2 = d1 + R, *lb = d2 + R;
+  S->h_perm.assign(perm, perm + R * n);
+  S->h_d1.assign(d1, d1 + R);
+  S->h_d2.assign(d2, d2 + R);
+  S->h_lb.resize(R);
+  memcpy(S->h_lb.data(), lb, (size_t)R * 4);
+  S->ub0 = hd.ub0;
+  S->kind = hd.kind;
+  const auto t0 = std::chrono::steady_clock::now();
+  // the top records onto the device stack, as much as leaves a step's room
+  const long long room = std::max<long long>(S->N, S->cap - (long long)S->N * (n > 1 ? n - 1 : 1));
+  const long long x = std::min<long long>(R, room);
+  if (x) {
+    rc = refill(c, x);
+    if (rc) return rc;
+  }
+  SearchCtl hc;
+  memset(&hc, 0, sizeof(hc));
+  hc.top = (int)x;
+  hc.ub = hd.ub;
+  hc.ub_step = hd.ub;
+  hc.step_best = ~0ull;
+  hc.nodes = hd.nodes;
+  hc.children = hd.children;
+  hc.steps = hd.steps;
+  PFSP_HIP(c, hipMemcpy(S->ctl, &hc, sizeof(hc), hipMemcpyHostToDevice));
+  PFSP_HIP(c, hipMemcpy(S->best_perm, lb + R * 4, n, hipMemcpyHostToDevice));
+  return run_search(c, hd.kind, hd.ub0, budget_nodes, res, t0);
 }
 
 extern "C" int pfsp_search_log(pfsp_ctx *h, uint8_t *perm_out, uint8_t *d1_out, uint8_t *d2_out,

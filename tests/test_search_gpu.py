@@ -217,3 +217,72 @@ def test_subset_search_needs_pairs(ctx):
     ctx.load_instance(inputs.instance(8, 4, 1))
     with pytest.raises(binding.PfspError):
         ctx.search(10**6, 0, binding.LB2_SUBSET)
+
+
+def test_stack_spills_to_host(ctx):
+    """A device stack far smaller than the open set: its bottom records move to
+    host memory and come back; the critical tree and the optimum are still the
+    oracle's (20 x 10, seed 6, LB1)."""
+    g = GOLDEN_20x10[6]
+    p = inputs.instance(20, 10, 6)
+    ctx.load_instance(p)
+    ctx.set_option("pool_batch", 16)
+    ctx.set_option("poll_every", 1)
+    ctx.set_option("pool_capacity", 400)
+    spill_hi = 400 - 16 * 19    # records the device keeps at a poll (a step's room above)
+    try:
+        r = ctx.search(g["opt"], 0, binding.LB1)
+        assert r["proven"] and not r["found"]
+        assert (r["nodes"], r["children"]) == (g["critical_nodes_lb1"],
+                                               g["critical_children_lb1"])
+        assert r["max_pool"] > spill_hi        # some records were held in host memory
+        r = ctx.search(g["neh"] + 1, 0, binding.LB1)
+        assert r["proven"] and r["best"] == g["opt"]
+        _valid(p, r["perm"], g["opt"])
+    finally:
+        ctx.set_option("pool_capacity", 0)
+        ctx.set_option("pool_batch", 65536)
+        ctx.set_option("poll_every", 8)
+
+
+@pytest.mark.parametrize("kind", [binding.LB1, binding.LB2_FULL])
+def test_dump_resume_matches_uninterrupted(ctx, kind):
+    """A search stopped on its budget, checkpointed, and resumed (twice, the
+    second time in a fresh context) decomposes exactly the critical tree of the
+    uninterrupted search and proves the same optimum (20 x 10, seed 2)."""
+    g = GOLDEN_20x10[2]
+    name = "lb1" if kind == binding.LB1 else "lb2"
+    p = inputs.instance(20, 10, 2)
+    ctx.load_instance(p)
+    ctx.set_option("pool_batch", 256)
+    ctx.set_option("poll_every", 1)
+    other = binding.Context(0)
+    try:
+        r = ctx.search(g["opt"], 1000, kind)
+        assert r["budget_hit"] and not r["proven"]
+        ck = ctx.search_dump()
+        r = ctx.search_resume(ck, 3000)
+        assert r["budget_hit"] and r["nodes"] >= 3000
+        ck = ctx.search_dump()
+        other.load_instance(p)
+        other.set_option("pool_batch", 1024)
+        r = other.search_resume(ck)
+        assert r["proven"] and not r["found"]
+        assert (r["nodes"], r["children"]) == (g[f"critical_nodes_{name}"],
+                                               g[f"critical_children_{name}"])
+        # from NEH + 1: the optimum is found across the interruption
+        r = ctx.search(g["neh"] + 1, 2000, kind)
+        assert r["budget_hit"]
+        ck = ctx.search_dump()
+        r = other.search_resume(ck)
+        assert r["proven"] and r["found"] and r["best"] == g["opt"]
+        _valid(p, r["perm"], g["opt"])
+        with pytest.raises(binding.PfspError):     # nothing left to dump
+            other.search_dump()
+        other.load_instance(inputs.instance(20, 10, 3))
+        with pytest.raises(binding.PfspError):     # another instance
+            other.search_resume(ck)
+    finally:
+        other.close()
+        ctx.set_option("pool_batch", 65536)
+        ctx.set_option("poll_every", 8)

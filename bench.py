@@ -1,26 +1,25 @@
 """Benchmark of the flow-shop bounding path on one MI355X.
 
-Default workload (the headline): one decomposition step = pfsp_bound_children
-with the full two-machine bound LB2 (all 190 machine pairs) over 1,048,576
-random bidirectional partial schedules of one n=20 x m=20 instance with
-p ~ U[1,99], including the MinMin branching decision and the prune flags.
-The metric is children bounded per second.
+Default run (one JSON line):
+  headline  one decomposition step = pfsp_bound_children with the full
+            two-machine bound LB2 (all 190 machine pairs) over 1,048,576
+            random bidirectional partial schedules of one n=20 x m=20
+            instance, p ~ U[1,99], incumbent NEH, including MinMin and the
+            prune flags; value = children bounded per second.  The roofline
+            entry divides each LB2 kernel's algorithmic operations
+            (alg_ops_lb2) by its mean launch time measured with HIP events on
+            the library stream; the depth sweep repeats it at fixed depths.
+  search    time to proven optimality of the device B&B on 20 x 10 (seeds
+            1..8, NEH + 1) with LB1 and with LB2, optima checked against the
+            oracle, beside the oracle's one-core and all-core searches.
+  learned   learned-pair vs full LB2 (selector trained on 50 x 20, bf16 float
+            form, top-16): 20 x 20 to the same proven optimum and 50 x 20 in
+            fixed-tree mode, with the static pair-set ablations.
+  cpu_baseline  the oracle on a bounded sample of the headline pool, on all
+            usable host cores (and on one).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-    python bench.py --workload search|multi|learned [...]
-
-Prints one JSON line.  Other workloads (not the headline): `search` = the
-device depth-first B&B on n=20 x m=10 instances (seeds 1..8, NEH incumbent)
-to proven optimality; `multi` = 64 instances of mixed (n, m) bounded in one
-persistent graph launch, autotuned shape vs default; `learned` = full LB2
-vs learned-pair LB2 searches to the same proven optimum (by default the
-20 x 20-trained selector in its int8 form, top-32 pairs; --float-selector,
---topk and --selector select the other variants).  The dominant kernel's
-roofline entry divides the
-kernel's algorithmic integer operations (formula in alg_ops_lb2) by its mean
-duration measured with HIP events on the library stream over the timed
-steps.  The CPU baseline is the plain oracle on a bounded sample of the same
-pool, on the host cores available to this process (at most 16).
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--headline-only]
+    python bench.py --workload search|multi|learned
 """
 from __future__ import annotations
 
@@ -156,19 +155,6 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--workload", default="bound", choices=["bound", "search", "multi", "learned"])
-    ap.add_argument("--selector", default=os.path.join(ROOT, "paper_2012_09511_amd", "data",
-                                                       "selector_n20m20.npy"),
-                    help="learned workload: trained weights (selector_n50m20.npy: the 50 x 20 "
-                         "training set)")
-    ap.add_argument("--topk", type=int, default=32, help="pairs kept by the learned selector")
-    ap.add_argument("--float-selector", action="store_true",
-                    help="learned workload: rank pairs with the float model instead of its "
-                         "int8 form")
-    ap.add_argument("--pool-batch", type=int, default=0,
-                    help="learned workload: nodes popped per search step (0 = 262144, the "
-                         "fastest of 2^16 .. 2^20 for both the full and the learned search)")
-    ap.add_argument("--no-graph", action="store_true",
-                    help="search steps as plain launches (profilers see graph replays as one)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the bounding path has no multi-GPU mode in this "
@@ -450,75 +436,161 @@ def bench_multi(args):
     print(json.dumps(out))
 
 
-def bench_learned(args):
-    """Full LB2 vs learned-pair LB2 (top-k) searches to the same proven optimum."""
+# 50 x 20 instances (p ~ U[1,99], seeds 700..703) in the paper's fixed-tree
+# mode: an incumbent at or below the optimum, so that every mode explores a
+# tree fixed by the bound alone and proves "no schedule below it".  Chosen
+# by bisection on the root's LB2 + delta for 0.1 - 0.6 s of full-LB2 search;
+# each run re-checks that nothing below the incumbent exists.
+FIXED_TREE_50x20 = {700: 3621, 701: 3691, 702: 3650, 703: 3813}
+
+
+def _log_nodes(ctx, binding, kind, ub0, budget=0, cap=1 << 16, stride=16):
+    """Search with the node log on; returns (result, logged nodes)."""
+    ctx.set_option("log_capacity", cap)
+    ctx.set_option("log_stride", stride)
+    r = ctx.search(ub0, budget, kind)
+    nodes = ctx.search_log(cap)
+    ctx.set_option("log_capacity", 0)
+    return r, nodes
+
+
+def _frequent_pairs(ctx, torch, binding, nodes, m, k=16):
+    """Mask of the k pairs that most often attain full LB2 first among the
+    children of the logged nodes."""
+    dev = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in nodes]
+    _, _, _, ap = ctx.bound_children(*dev, kind=binding.LB2_FULL, want_argpair=True)
+    ap = ap.cpu().numpy().reshape(-1).astype(np.int64)
+    P = m * (m - 1) // 2
+    cnt = np.bincount(ap[ap >= 0], minlength=P)
+    top = np.argsort(-cnt, kind="stable")[:k]
+    mask = np.zeros((P + 31) // 32, dtype=np.uint32)
+    for q in top:
+        mask[q >> 5] |= np.uint32(1 << (int(q) & 31))
+    return mask
+
+
+def _prune_loss(ctx, torch, binding, nodes, ub, kind, mask=None):
+    """Children pruned by full LB2 but not by `kind`, over those full LB2
+    prunes, on the same children (the logged nodes) at incumbent ub."""
+    dev = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in nodes]
+    lf, pf, _, _ = ctx.bound_children(*dev, kind=binding.LB2_FULL, ub=ub)
+    tm = None
+    if mask is not None:
+        tm = torch.from_numpy(np.tile(mask, (len(nodes[0]), 1))).cuda()
+    pk = ctx.bound_children(*dev, kind=kind, ub=ub, pair_mask=tm)[1]
+    torch.cuda.synchronize()
+    live = lf < binding.INT32_MAX
+    full = (pf.bool() & live).sum().item()
+    lost = (pf.bool() & ~pk.bool() & live).sum().item()
+    return lost / max(full, 1)
+
+
+def _geomean(xs):
+    return float(np.exp(np.mean(np.log(xs))))
+
+
+def learned_summary(args):
+    """Learned-pair LB2 against full LB2 at the learned configuration: the MLP
+    trained on 50 x 20 logs, float form (bf16 weights, fp32 sums, bf16 MFMA),
+    top-16 pairs, 2^18 nodes per step.  Modes: FULL; LEARNED-EXACT (subset,
+    then full LB2 for every parent that keeps a child: the tree of FULL);
+    LEARNED-PURE (subset only); STATIC-ADJ (the 19 adjacent pairs (k, k+1));
+    STATIC-FREQ16 (the 16 pairs most often attaining full LB2 among the
+    children of nodes logged by this instance's FULL search).  (i) 20 x 20,
+    seeds 600..607, NEH + 1 to the same proven optimum; (ii) 50 x 20, seeds
+    700..703, fixed tree.  Per-instance speedups over FULL and their geometric
+    mean; node ratios; prune-rate loss on the logged nodes."""
     import torch
     from paper_2012_09511_amd import binding, inputs, selector_quant
     ctx = binding.Context(0)
-    params = np.load(args.selector, allow_pickle=False)
-    ctx.selector_set(params)
-    ctx.set_option("learned_topk", args.topk)
-    ctx.set_option("pool_batch", args.pool_batch or 1 << 18)
-    if args.no_graph:
-        ctx.set_option("use_graph", 0)
-    rows = []
-    modes = (("full", binding.LB2_FULL), ("learned", binding.LB2_LEARNED))
-    for seed in range(600, 608):
-        p = inputs.instance(20, 20, seed)
-        ctx.load_instance(p)
-        if not args.float_selector:   # int8 form, calibrated on random nodes of this instance
-            ctx.selector_set_quant(selector_quant.quantize(
-                params, selector_quant.calibration_features(ctx, 20, 4096, seed)))
-        ub0, _ = ctx.neh()
-        for _, kind in modes:   # untimed: workspaces and graph capture for this instance
-            ctx.search(ub0 + 1, 1, kind)
-        res = {}
-        for name, kind in modes:
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            r = ctx.search(ub0 + 1, 0, kind)
-            res[name] = dict(best=r["best"], proven=r["proven"], nodes=r["nodes"],
-                             children=r["children"], seconds=time.perf_counter() - t)
-        assert res["full"]["best"] == res["learned"]["best"]
-        assert res["full"]["proven"] and res["learned"]["proven"]
-        res["prune_rate_loss"] = prune_rate_loss(ctx, torch, binding, inputs, res["full"]["best"],
-                                                 seed)
-        rows.append(dict(seed=seed, **res))
-        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
-    tf = sum(x["full"]["seconds"] for x in rows)
-    tl = sum(x["learned"]["seconds"] for x in rows)
-    nf = sum(x["full"]["nodes"] for x in rows)
-    nl = sum(x["learned"]["nodes"] for x in rows)
-    out = dict(metric="time to the same proven optimum, learned-pair vs full LB2",
-               value=tf / tl, unit="speedup", n_gpus=1, steps=1, warmup=0,
-               ms_per_step=tl * 1e3, higher_is_better=True, scaling="weak", vs_baseline=None,
-               dtype="int32", data="synthetic",
-               config=dict(workload="depth-first B&B, n=20 x m=20, seeds 600..607, NEH+1, "
-                                    f"{ctx.get_option('pool_batch')} nodes per step, "
-                                    f"learned top-{args.topk} of 190 pairs, "
-                                    + ("float" if args.float_selector else "int8") + " selector "
-                                    + os.path.basename(args.selector)),
-               full_seconds=tf, learned_seconds=tl, node_ratio=nl / nf,
-               prune_rate_loss=float(np.mean([x["prune_rate_loss"] for x in rows])),
-               instances=rows)
+    sel = np.load(os.path.join(ROOT, "paper_2012_09511_amd", "data", "selector_n50m20.npy"),
+                  allow_pickle=False)
+    ctx.set_option("pool_batch", 1 << 18)
+    ctx.set_option("learned_topk", 16)
+    modes = ("full", "exact", "pure", "static_adj", "static_freq16")
+
+    def run(kind, ub0, exact=0, budget=0):
+        ctx.set_option("learned_exact", exact)
+        ctx.search(ub0, 1, kind)                 # graph capture and workspaces, untimed
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = ctx.search(ub0, budget, kind)
+        dt = time.perf_counter() - t
+        ctx.set_option("learned_exact", 0)
+        return r, dt
+
+    def instance_rows(n, m, seeds, ub_of, same_optimum):
+        rows = []
+        for seed in seeds:
+            p = inputs.instance(n, m, seed)
+            ctx.load_instance(p)
+            ctx.selector_set(sel)
+            ctx.selector_set_quant(None)
+            ub0 = ub_of(seed)
+            full, nodes = _log_nodes(ctx, binding, binding.LB2_FULL, ub0)
+            freq = _frequent_pairs(ctx, torch, binding, nodes, m)
+            res = {}
+            for mode in modes:
+                if mode == "full":
+                    r, dt = run(binding.LB2_FULL, ub0)
+                elif mode in ("exact", "pure"):
+                    r, dt = run(binding.LB2_LEARNED, ub0, exact=int(mode == "exact"))
+                else:
+                    ctx.search_set_pairs(ctx.pair_mask(binding.PAIRS_ADJACENT)
+                                         if mode == "static_adj" else freq)
+                    r, dt = run(binding.LB2_SUBSET, ub0)
+                assert r["proven"], (seed, mode)
+                if same_optimum:
+                    assert r["found"] and r["best"] == full["best"], (seed, mode)
+                else:
+                    assert not r["found"], (seed, mode)   # nothing below the incumbent
+                res[mode] = dict(seconds=round(dt, 4), nodes=r["nodes"])
+            opt = full["best"] if same_optimum else ub0
+            loss = {"pure": _prune_loss(ctx, torch, binding, nodes, opt, binding.LB2_LEARNED),
+                    "static_adj": _prune_loss(ctx, torch, binding, nodes, opt, binding.LB2_SUBSET,
+                                              ctx.pair_mask(binding.PAIRS_ADJACENT)),
+                    "static_freq16": _prune_loss(ctx, torch, binding, nodes, opt,
+                                                 binding.LB2_SUBSET, freq)}
+            rows.append(dict(seed=seed, ub0=ub0, best=full["best"], modes=res,
+                             prune_rate_loss={k: round(v, 4) for k, v in loss.items()}))
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+        summ = {}
+        for mode in modes:
+            t = sum(x["modes"][mode]["seconds"] for x in rows)
+            summ[mode] = dict(seconds=round(t, 4),
+                              node_ratio=sum(x["modes"][mode]["nodes"] for x in rows) /
+                              sum(x["modes"]["full"]["nodes"] for x in rows))
+            if mode != "full":
+                sp = [x["modes"]["full"]["seconds"] / x["modes"][mode]["seconds"] for x in rows]
+                summ[mode].update(speedup_total=sum(x["modes"]["full"]["seconds"] for x in rows)
+                                  / t, speedup_geomean=_geomean(sp),
+                                  speedups=[round(v, 3) for v in sp])
+        return dict(summary=summ, instances=rows)
+
+    def neh_plus_1(seed):
+        return ctx.neh()[0] + 1
+
+    out = dict(
+        config="MLP 64-64-64-190 trained on 50 x 20 logs (selector_n50m20.npy), float form: "
+               "bf16 weights, fp32 sums on bf16 MFMA; top-16 pairs; 262144 nodes per step",
+        same_optimum_20x20=instance_rows(20, 20, range(600, 608), neh_plus_1, True),
+        fixed_tree_50x20=instance_rows(50, 20, range(700, 704), FIXED_TREE_50x20.get, False))
     ctx.close()
+    return out
+
+
+def bench_learned(args):
+    """The learned workload alone, as its own JSON line."""
+    s = learned_summary(args)
+    sm = s["same_optimum_20x20"]["summary"]
+    out = dict(metric="time to the same proven optimum, learned-pair vs full LB2",
+               value=sm["pure"]["speedup_geomean"], unit="speedup (geomean)", n_gpus=1, steps=1,
+               warmup=1, ms_per_step=sm["pure"]["seconds"] * 1e3, higher_is_better=True,
+               scaling="weak", vs_baseline=None, dtype="int32", data="synthetic",
+               config=dict(workload="depth-first B&B, n=20 x m=20, seeds 600..607, NEH+1; "
+                                    "n=50 x m=20 seeds 700..703 fixed tree; " + s["config"]),
+               **{k: v for k, v in s.items() if k != "config"})
     print(json.dumps(out))
-
-
-def prune_rate_loss(ctx, torch, binding, inputs, opt, seed, N=1 << 16):
-    """Share of the children that full LB2 prunes at the optimum (LB >= opt)
-    and the learned bound does not, over those full LB2 prunes, on N random
-    nodes of the loaded instance (same children for both bounds)."""
-    n = 20
-    perm, d1, d2 = inputs.random_pool(n, N, 9900 + seed)
-    dev = [torch.from_numpy(a).cuda() for a in (perm, d1, d2)]
-    lf, pf, _, _ = ctx.bound_children(*dev, kind=binding.LB2_FULL, ub=opt)
-    pl = ctx.bound_children(*dev, kind=binding.LB2_LEARNED, ub=opt)[1]
-    torch.cuda.synchronize()
-    live = lf < binding.INT32_MAX
-    full_pr = (pf.bool() & live).sum().item()
-    lost = (pf.bool() & ~pl.bool() & live).sum().item()
-    return lost / max(full_pr, 1)
 
 
 if __name__ == "__main__":

@@ -180,20 +180,28 @@ __device__ __forceinline__ void lb1_row(const DevInst &I, const int *__restrict_
 // Filter outcome of pool row i (see CostFilter): closed rows get their prune
 // row and direction here, open rows are appended to the list (one atomic per
 // wave).  Whole waves call it.
-__device__ __forceinline__ void filter_row(const CostFilter &f, int i, bool live, bool open,
-                                           int ns, int lane) {
-  const bool app = live && open;
+__device__ __forceinline__ void list_append(int *rows, int *count, bool app, int i, int lane) {
   const uint64_t bal = __ballot(app);
   int base = 0;
   if (bal) {
-    if (lane == 0) base = atomicAdd(f.open, __popcll(bal));
+    if (lane == 0) base = atomicAdd(count, __popcll(bal));
     base = __shfl(base, 0, kWave);
   }
   if (app) {
     const int pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
                                               __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
-    f.rows[base + pos] = i;
-  } else if (live) {
+    rows[base + pos] = i;
+  }
+}
+
+// deep: the row has 1 <= r <= f.deep_r jobs left.
+__device__ __forceinline__ void filter_row(const CostFilter &f, int i, bool live, bool open,
+                                           bool deep, int ns, int lane) {
+  const bool app = live && open;
+  const bool to_deep = app && deep && f.rows_deep != nullptr;
+  list_append(f.rows, f.open, app && !to_deep, i, lane);
+  if (f.rows_deep) list_append(f.rows_deep, f.open_deep, to_deep, i, lane);
+  if (!app && live) {
     uint8_t *pr = f.out_prune + (size_t)i * 2 * ns;
     for (int x = 0; x < 2 * ns; ++x) pr[x] = 1;
     if (f.dir) f.dir[i] = 0;
@@ -246,7 +254,7 @@ k_lb1(DevInst I, DevPool pool, int ub, int *__restrict__ out_lb, uint8_t *__rest
       }
     }
   }
-  if (filt) filter_row(f, i, live, open, ns, t & 63);
+  if (filt) filter_row(f, i, live, open, false, ns, t & 63);
 }
 
 // One parent's costs (front C1, back C2, remaining R; Eq. (1)) for n <= 32
@@ -389,14 +397,16 @@ k_costs(DevInst I, DevPool pool, int *__restrict__ costs, int *__restrict__ flag
   for (int i0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63); i0 < count;
        i0 += gridDim.x * blockDim.x) {
     const int i = i0 + lane;
-    bool live = false, open = false, valid = false;
+    bool live = false, open = false, valid = false, deep = false;
     if (i < count) {
       live = !filt || !f.alive || f.alive[i];
-      open = costs_row<MMAX, MS>(n, m, sp, sT, pool.perm + (size_t)i * ns, pool.d1[i],
-                                 pool.d2[i], tile + lane * RS, flag, filt && live, ub, &valid);
+      const int a = pool.d1[i], b = pool.d2[i];
+      open = costs_row<MMAX, MS>(n, m, sp, sT, pool.perm + (size_t)i * ns, a, b,
+                                 tile + lane * RS, flag, filt && live, ub, &valid);
       open = open && valid;
+      deep = n - a - b >= 1 && n - a - b <= f.deep_r;
     }
-    if (filt) filter_row(f, i, live, open, ns, lane);
+    if (filt) filter_row(f, i, live, open, deep, ns, lane);
     wave_sync();
     const int rows = min(64, count - i0);
     int *dst = costs + (size_t)i0 * cm;
@@ -1108,14 +1118,6 @@ __device__ __forceinline__ PackFetch row_fetch(const uint8_t *__restrict__ row,
   return F;
 }
 
-// Whether a kernel launched on pool's depth bin bounds the parent F.
-__device__ __forceinline__ bool in_bin(const DevPool &pool, const PackFetch &F, int n) {
-  if (!pool.bin) return true;
-  const int r = n - __builtin_amdgcn_readfirstlane(F.d1) - __builtin_amdgcn_readfirstlane(F.d2);
-  const bool deep = r >= 1 && r <= pool.bin_r;
-  return pool.bin == 2 ? deep : !deep;
-}
-
 __device__ __forceinline__ PackFetch pack_fetch(const DevPool &pool, int par, int n, int m,
                                                 const int *__restrict__ costs, int lane) {
   PackFetch F{0, -1, 0, 0, 0, 0, 0u};
@@ -1132,6 +1134,80 @@ __device__ __forceinline__ PackFetch pack_fetch(const DevPool &pool, int par, in
     if (lane < pool.mask_words) F.mw = mask_row(pool, par)[lane];
   }
   return F;
+}
+
+// Static LDS of the depth-bin row lists (one chunk of a block's rows plus a
+// count per wave).
+constexpr int kBinListCap = 1024;
+constexpr size_t kBinListLds = (kBinListCap + 16) * 4;
+
+// Runs body(par, F) for the parents a wave bounds, with the next parent's
+// inputs loaded while the current one is bounded.  Without a depth bin the
+// waves take launch rows blockIdx.x * nw + w + k * gridDim.x * nw.  With one,
+// the block takes chunks of CH consecutive launch rows (chunk c = blockIdx.x +
+// k * gridDim.x; CH = the rows per block of an even split, between nw and
+// blockDim.x, so that small launches still reach every block), lists the
+// rows of its bin in LDS (wave ballots, one count per wave) and its waves
+// take list entries w, w + nw, ...  Every wave of the block runs the chunk
+// loop (it holds barriers).
+template <class Body>
+__device__ __forceinline__ void parent_loop(const DevPool &pool, int count, int n, int m,
+                                            const int *__restrict__ costs, int lane, int w,
+                                            int nw, int *blist, Body body) {
+  if (!pool.bin) {
+    const int step = gridDim.x * nw;
+    auto row_of = [&](int x) { return x < count ? (pool.index ? pool.index[x] : x) : -1; };
+    int it = blockIdx.x * nw + w;
+    int par = row_of(it);
+    PackFetch F = pack_fetch(pool, par, n, m, costs, lane);
+    for (; it < count; it += step) {
+      const int nxt = row_of(it + step);  // the next parent's inputs are loaded meanwhile
+      const PackFetch Fn = pack_fetch(pool, nxt, n, m, costs, lane);
+      body(par, F);
+      par = nxt;
+      F = Fn;
+    }
+    return;
+  }
+  const int T = blockDim.x;
+  const int CH = min(T, max(nw, (count + (int)gridDim.x - 1) / (int)gridDim.x));
+  int *wcnt = blist + kBinListCap;
+  for (int c0 = blockIdx.x * CH; c0 < count; c0 += gridDim.x * CH) {
+    const int x = c0 + (int)threadIdx.x;
+    bool in = false;
+    int row = -1;
+    if ((int)threadIdx.x < CH && x < count) {
+      row = pool.index ? pool.index[x] : x;
+      const int r = n - pool.d1[row] - pool.d2[row];
+      const bool deep = r >= 1 && r <= pool.bin_r;
+      in = pool.bin == 2 ? deep : !deep;
+    }
+    const uint64_t bal = __ballot(in);
+    if (lane == 0) wcnt[w] = __popcll(bal);
+    __syncthreads();
+    int off = 0, total = 0;
+    for (int v = 0; v < nw; ++v) {
+      const int cv = wcnt[v];
+      off += v < w ? cv : 0;
+      total += cv;
+    }
+    if (in)
+      blist[off + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0))] =
+          row;
+    __syncthreads();
+    int j = w;
+    int par = j < total ? blist[j] : -1;
+    PackFetch F = pack_fetch(pool, par, n, m, costs, lane);
+    for (; j < total; j += nw) {
+      const int nxt = j + nw < total ? blist[j + nw] : -1;
+      const PackFetch Fn = pack_fetch(pool, nxt, n, m, costs, lane);
+      body(par, F);
+      par = nxt;
+      F = Fn;
+    }
+    __syncthreads();  // the next chunk rewrites the list
+  }
 }
 
 // X16: the scan starts from Y = R_v + C2_v instead of 0.  For a member j
@@ -1391,6 +1467,7 @@ k_lb2q(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
   // the wave index as a uniform value: parent indices, and the loads of their
   // depths and pool rows, stay scalar
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  __shared__ int blist[kBinListCap + 16];
   const int count = pool.count_dev ? *pool.count_dev : pool.count;
   if ((int)blockIdx.x * nw >= count) return;  // no parent for this block: skip the staging
   const QuickLayout L{Ppad, I.m, X16, SUBSET};
@@ -1399,22 +1476,12 @@ k_lb2q(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
   __syncthreads();
   if (pool.ub_dev) ub = *pool.ub_dev;
   const int n = I.n, m = I.m, ns = pool.n;  // ns: row stride (>= n)
-  const int step = gridDim.x * nw;
-  auto row_of = [&](int x) { return x < count ? (pool.index ? pool.index[x] : x) : -1; };
-  int it = blockIdx.x * nw + w;
-  int par = row_of(it);
-  PackFetch F = pack_fetch(pool, par, n, m, costs, lane);
   const int tsrc = tp_source<NMAX>(lane);
-  for (; it < count; it += step) {
-    const int nxt = row_of(it + step);  // the next parent's inputs are loaded meanwhile
-    const PackFetch Fn = pack_fetch(pool, nxt, n, m, costs, lane);
-    if (in_bin(pool, F, n))
-      lb2q_parent<NMAX, SUBSET, X16>(I, Ppad, S, F, ns, ub, out_lb + (size_t)par * 2 * ns,
-                                     out_prune + (size_t)par * 2 * ns,
-                                     pool.dir ? pool.dir + par : nullptr, lane, tsrc);
-    par = nxt;
-    F = Fn;
-  }
+  parent_loop(pool, count, n, m, costs, lane, w, nw, blist, [&](int par, const PackFetch &F) {
+    lb2q_parent<NMAX, SUBSET, X16>(I, Ppad, S, F, ns, ub, out_lb + (size_t)par * 2 * ns,
+                                   out_prune + (size_t)par * 2 * ns,
+                                   pool.dir ? pool.dir + par : nullptr, lane, tsrc);
+  });
 }
 
 // ------------------------------------------------------------ deep LB2
@@ -1636,6 +1703,7 @@ k_lb2d(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
   extern __shared__ __align__(16) unsigned char sm[];
   const int nw = blockDim.x >> 6, lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  __shared__ int blist[kBinListCap + 16];
   const int count = pool.count_dev ? *pool.count_dev : pool.count;
   if ((int)blockIdx.x * nw >= count) return;
   const DeepLayout L{Ppad, I.m, RMAX};
@@ -1645,22 +1713,12 @@ k_lb2d(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
   __syncthreads();
   if (pool.ub_dev) ub = *pool.ub_dev;
   const int n = I.n, m = I.m, ns = pool.n;
-  const int step = gridDim.x * nw;
-  auto row_of = [&](int x) { return x < count ? (pool.index ? pool.index[x] : x) : -1; };
-  int it = blockIdx.x * nw + w;
-  int par = row_of(it);
-  PackFetch F = pack_fetch(pool, par, n, m, costs, lane);
   const int tsrc = tp_source<RMAX>(lane);
-  for (; it < count; it += step) {
-    const int nxt = row_of(it + step);
-    const PackFetch Fn = pack_fetch(pool, nxt, n, m, costs, lane);
-    if (in_bin(pool, F, n))
-      lb2d_parent<NMAX, RMAX>(I, Ppad, S, F, ns, ub, out_lb + (size_t)par * 2 * ns,
-                              out_prune + (size_t)par * 2 * ns,
-                              pool.dir ? pool.dir + par : nullptr, lane, tsrc);
-    par = nxt;
-    F = Fn;
-  }
+  parent_loop(pool, count, n, m, costs, lane, w, nw, blist, [&](int par, const PackFetch &F) {
+    lb2d_parent<NMAX, RMAX>(I, Ppad, S, F, ns, ub, out_lb + (size_t)par * 2 * ns,
+                            out_prune + (size_t)par * 2 * ns,
+                            pool.dir ? pool.dir + par : nullptr, lane, tsrc);
+  });
 }
 
 // ------------------------------------------------------------ wide LB2
@@ -3065,29 +3123,32 @@ static size_t lb2d_lds(const Ctx *c, int nmax, int rmax, int waves) {
   return L.block_bytes(nmax) + (size_t)waves * L.wave_bytes(nmax);
 }
 
-static int launch_lb2d(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8_t *out_prune,
-                       hipStream_t s) {
+int launch_lb2d(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8_t *out_prune,
+                hipStream_t s) {
   if (pool.count <= 0) return PFSP_OK;
   const int nmax = fast_nmax(c->n, c->l16);
   const int r = deep_bin_r(c, PFSP_LB2_FULL, false);
   if (!r || !nmax || nmax > 32) return set_err(c, PFSP_EINVAL, "deep LB2 kernel does not apply");
   const int rmax = r <= 4 ? 4 : r <= 8 ? 8 : 16;
+  // the kernel's static row list counts against the 160 KiB with the tables
   int waves = 0, best = 0;
   for (int w = 16; w >= 1; --w) {
-    const size_t l = lb2d_lds(c, nmax, rmax, w);
+    const size_t l = lb2d_lds(c, nmax, rmax, w) + kBinListLds;
     const int per_cu = l <= 160 * 1024 ? (int)((160 * 1024) / l) * w : 0;
     if (per_cu > best) {
       best = per_cu;
       waves = w;
     }
   }
-  if (c->lb2_waves > 0 && lb2d_lds(c, nmax, rmax, (int)c->lb2_waves) <= 160 * 1024)
+  if (c->lb2_waves > 0 &&
+      lb2d_lds(c, nmax, rmax, (int)c->lb2_waves) + kBinListLds <= 160 * 1024)
     waves = (int)c->lb2_waves;
   if (!waves) return set_err(c, PFSP_ERANGE, "deep LB2 tables exceed LDS");
   const size_t lds = lb2d_lds(c, nmax, rmax, waves);
   const int Ppad = (c->P + 63) / 64 * 64;
   int grid = (pool.count + waves - 1) / waves;
-  const int resident = std::max(1, (int)((160 * 1024) / std::max<size_t>(lds, 1)));
+  const int resident =
+      std::max(1, (int)((160 * 1024) / std::max<size_t>(lds + kBinListLds, 1)));
   const int cap = c->cu_count * (int)(c->lb2_blocks_per_cu > 0 ? c->lb2_blocks_per_cu
                                                                : 2 * resident);
   if (grid > cap) grid = cap;
@@ -3144,8 +3205,10 @@ int launch_bound_costs_ready(Ctx *c, const DevPool &pool, int kind, int ub, int 
     // waves per block: the most resident waves per CU within 160 KiB of LDS
     int waves = 0, best = 0;
     const int wmax = quick_wmax(nmax, c->x16, log);  // the kernels' launch bounds
+    // the quick kernel's static row list counts against the 160 KiB too
+    const size_t st = nmax <= 32 && !log ? kBinListLds : 0;
     for (int w = wmax; w >= 1; --w) {
-      const size_t l = lb2f_lds(c, nmax, w, log, subset);
+      const size_t l = lb2f_lds(c, nmax, w, log, subset) + st;
       const int per_cu = l <= 160 * 1024 ? (int)((160 * 1024) / l) * w : 0;
       if (per_cu > best) {
         best = per_cu;
@@ -3153,7 +3216,7 @@ int launch_bound_costs_ready(Ctx *c, const DevPool &pool, int kind, int ub, int 
       }
     }
     if (c->lb2_waves > 0 && c->lb2_waves <= wmax &&
-        lb2f_lds(c, nmax, (int)c->lb2_waves, log, subset) <= 160 * 1024)
+        lb2f_lds(c, nmax, (int)c->lb2_waves, log, subset) + st <= 160 * 1024)
       waves = (int)c->lb2_waves;
     const size_t lds = waves ? lb2f_lds(c, nmax, waves, log, subset) : 0;
     if (waves) {
@@ -3161,7 +3224,7 @@ int launch_bound_costs_ready(Ctx *c, const DevPool &pool, int kind, int ub, int 
       int grid = (pool.count + waves - 1) / waves;
       // default: twice the blocks that LDS lets a CU hold, so that each block
       // stages its tables once and then loops over many parents
-      const int resident = std::max(1, (int)((160 * 1024) / std::max<size_t>(lds, 1)));
+      const int resident = std::max(1, (int)((160 * 1024) / std::max<size_t>(lds + st, 1)));
       const int cap = c->cu_count * (int)(c->lb2_blocks_per_cu > 0 ? c->lb2_blocks_per_cu
                                                                    : 2 * resident);
       if (grid > cap) grid = cap;

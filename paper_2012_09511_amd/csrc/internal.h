@@ -61,6 +61,8 @@ struct DevPool {
 //    written here (all pruned, direction 0) and it is left out of the bound
 //    kernels;
 //  - every other parent is appended to rows[0 .. *open) (any order).
+//  - rows_deep (optional): open rows with 1 <= r <= deep_r unscheduled jobs go
+//    to rows_deep[0 .. *open_deep) instead (the deep LB2 kernel).
 struct CostFilter {
   const uint8_t *alive;
   const int *ub_dev;
@@ -68,6 +70,9 @@ struct CostFilter {
   uint8_t *dir;
   int *rows;
   int *open;
+  int *rows_deep = nullptr;
+  int *open_deep = nullptr;
+  int deep_r = 0;
 };
 
 struct Selector;   // learned pair selector state (selector.hip)
@@ -188,6 +193,9 @@ int deep_bin_r(const Ctx *c, int kind, bool log);
 // at most deep_bin_r jobs left, the full-scan kernel the others (costs ready).
 int launch_lb2_binned(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8_t *out_prune,
                       hipStream_t s);
+// The deep kernel alone on a pool all of whose rows have 1 <= r <= deep_bin_r.
+int launch_lb2d(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8_t *out_prune,
+                hipStream_t s);
 // Workspace of pfsp_bound_children in int32: 3m costs per parent.
 size_t workspace_ints(const Ctx *c, int count);
 void init_bound_attributes();

@@ -66,8 +66,9 @@ struct SearchState {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   std::vector<long long> graph_key;  // options the captured step depends on
-  // LB2 steps: parents that survive the costs kernels' LB1 filter
-  int *rows = nullptr, *open = nullptr;
+  // LB2 steps: parents that survive the costs kernels' LB1 filter (those with
+  // few jobs left in rows_deep, counted in open[1], for the deep kernel)
+  int *rows = nullptr, *open = nullptr, *rows_deep = nullptr;
   // node log (option log_capacity > 0): every log_stride-th decomposed node
   uint8_t *l_perm = nullptr, *l_d1 = nullptr, *l_d2 = nullptr;
   long long log_cap = 0;
@@ -84,6 +85,10 @@ struct SearchState {
 constexpr int kScanBlock = 1024;  // parents per k_scan_local block (256 threads x 4)
 
 __global__ void k_clear(int *p) { *p = 0; }
+__global__ void k_clear2(int *p) {
+  p[0] = 0;
+  p[1] = 0;
+}
 
 __global__ void k_pop(SearchCtl *c, int N) {
   const int top = c->top;
@@ -375,7 +380,8 @@ void search_free(Ctx *c) {
   if (S->graph) (void)hipGraphDestroy(S->graph);
   void *bufs[] = {S->s_perm, S->s_d1, S->s_d2, S->s_lb, S->b_perm, S->b_d1, S->b_d2, S->b_dir,
                   S->b_lb, S->b_alive, S->out_lb, S->out_prune, S->cnt, S->offs, S->bsum,
-                  S->best_perm, S->ctl, S->l_perm, S->l_d1, S->l_d2, S->rows, S->open};
+                  S->best_perm, S->ctl, S->l_perm, S->l_d1, S->l_d2, S->rows, S->open,
+                  S->rows_deep};
   for (void *p : bufs) (void)hipFree(p);
   if (S->ctl_host) (void)hipHostFree(S->ctl_host);
   if (S->stream) (void)hipStreamDestroy(S->stream);
@@ -422,7 +428,8 @@ static int search_alloc(Ctx *c) {
   alloc((void **)&S->best_perm, (size_t)n);
   alloc((void **)&S->ctl, sizeof(SearchCtl));
   alloc((void **)&S->rows, (size_t)N * 4);
-  alloc((void **)&S->open, 4);
+  alloc((void **)&S->rows_deep, (size_t)N * 4);
+  alloc((void **)&S->open, 8);
   S->log_cap = c->log_capacity;
   if (S->log_cap > 0) {
     alloc((void **)&S->l_perm, (size_t)S->log_cap * n);
@@ -475,8 +482,15 @@ static int enqueue_step(Ctx *c, int kind) {
   if (kind != PFSP_LB1 && c->search_filter) {
     // parents whose children all have LB1 >= ub are closed by the costs
     // kernel (LB2 >= LB1 cannot keep a child); only the others are bounded
-    hipLaunchKernelGGL(k_clear, dim3(1), dim3(1), 0, s, S->open);
-    const CostFilter f{S->b_alive, &S->ctl->ub_step, S->out_prune, S->b_dir, S->rows, S->open};
+    // parents with few jobs left go to a list of their own for the deep kernel
+    const int deep = deep_bin_r(c, kind, false);
+    hipLaunchKernelGGL(k_clear2, dim3(1), dim3(1), 0, s, S->open);
+    CostFilter f{S->b_alive, &S->ctl->ub_step, S->out_prune, S->b_dir, S->rows, S->open};
+    if (deep) {
+      f.rows_deep = S->rows_deep;
+      f.open_deep = S->open + 1;
+      f.deep_r = deep;
+    }
     rc = launch_costs(c, pool, s, &f);
     if (rc) return rc;
     DevPool op = pool;
@@ -488,10 +502,13 @@ static int enqueue_step(Ctx *c, int kind) {
       // a fixed selection of at most 32 pairs fills half a wave: two parents per wave
       const int group = kind == PFSP_LB2_SUBSET && c->subset_group == 0 && c->static_pairs <= 32
                             ? 2 : 0;
-      if (kind == PFSP_LB2_FULL)
-        rc = launch_lb2_binned(c, op, 0, S->out_lb, S->out_prune, s);
-      else
-        rc = launch_bound_costs_ready(c, op, kind, 0, S->out_lb, S->out_prune, s, group);
+      rc = launch_bound_costs_ready(c, op, kind, 0, S->out_lb, S->out_prune, s, group);
+      if (!rc && deep) {
+        DevPool dp = pool;
+        dp.index = S->rows_deep;
+        dp.count_dev = S->open + 1;
+        rc = launch_lb2d(c, dp, 0, S->out_lb, S->out_prune, s);
+      }
     }
   } else if (kind == PFSP_LB2_LEARNED) {
     rc = launch_learned(c, pool, 0, S->out_lb, S->out_prune, s);

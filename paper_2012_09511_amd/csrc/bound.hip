@@ -1738,6 +1738,7 @@ k_lb2d(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
 // 100-job, 20-machine class fits four waves per CU.
 struct WideLayout {
   int ppad, nj, mmax;  // padded pairs, rows of X (largest n), machines
+  int subset = 0;      // subset bounds: a list of the selected pairs per wave
   // start-time rows: odd, and long enough for reads up to job n + 2
   __host__ __device__ int row() const { return (nj + 3) | 1; }
   // scan chunk length: the 128-job variant keeps fewer positions in registers
@@ -1751,7 +1752,8 @@ struct WideLayout {
   __host__ __device__ size_t wave_bytes(int nmax) const {
     return align16((size_t)(nj + 3) * 64 * 4) + align16((size_t)mmax * row() * 4) +
            align16((size_t)chunks(nmax) * 64 * 4) + align16((size_t)2 * mmax * 8) +
-           align16((size_t)3 * mmax * 4) + align16((size_t)nj * 4);
+           align16((size_t)3 * mmax * 4) + align16((size_t)nj * 4) +
+           (subset ? align16((size_t)ppad * 2) : 0);
   }
 };
 
@@ -1766,6 +1768,7 @@ struct WideLds {
   int *ST;         // [chunks][64]: Y | prefix max << 16 at each chunk start (both int16)
   int2 *HTf, *HTb;
   int *c1, *c2, *rr, *inv;
+  short *sel;  // subset bounds: the selected pair indices in order
   __device__ WideLds(unsigned char *sm, const WideLayout &L, int w) {
     ROW = L.row();
     uv = (int *)sm;
@@ -1787,6 +1790,8 @@ struct WideLds {
     rr = c2 + L.mmax;
     wb += align16((size_t)3 * L.mmax * 4);
     inv = (int *)wb;
+    wb += align16((size_t)L.nj * 4);
+    sel = (short *)wb;
   }
 };
 
@@ -1857,12 +1862,16 @@ __device__ __forceinline__ void lb2w_chunk(const uint2 *__restrict__ ec, int rem
   Sm = R >> 16;
 }
 
-template <int NMAX>
+// SUBSET: only the pairs whose bit is set in mw[0 .. words) (compacted into
+// S.sel in index order; lanes past the selection repeat its first pair), their
+// entries gathered from the instance table by pair index.
+template <int NMAX, bool SUBSET = false>
 __device__ void lb2w_parent(const DevInst &I, int Ppad, const WideLds<NMAX> &S,
                             const uint8_t *__restrict__ row, int a, int b,
                             const int *__restrict__ cs, int stride, int ub,
                             int *__restrict__ lbrow, uint8_t *__restrict__ prow,
-                            uint8_t *__restrict__ dirp, int lane) {
+                            uint8_t *__restrict__ dirp, int lane,
+                            const uint32_t *__restrict__ mw = nullptr, int words = 0) {
   const int ROW = S.ROW;
   constexpr int CH = WideLayout::chunk_len(NMAX);
   constexpr int NC = NMAX / 32;  // 32-job chunks of the lane-per-job steps
@@ -1926,7 +1935,21 @@ __device__ void lb2w_parent(const DevInst &I, int Ppad, const WideLds<NMAX> &S,
     acc[q] = (int)0x80008000u;
     asm volatile("" : "+v"(acc[q]));
   }
-  const int npass = r < 2 ? 0 : (P > 0 ? Ppad : 0);  // leaves: LB2 = LB1
+  int nsel = 0;
+  if constexpr (SUBSET) {  // selected pairs in index order, compacted by ballot
+    for (int base = 0; base < P; base += 64) {
+      const int q = base + lane;
+      const bool on = q < P && ((mw[q >> 5] >> (q & 31)) & 1u);
+      const uint64_t bal = __ballot(on);
+      const int pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
+      if (on) S.sel[nsel + pos] = (short)q;
+      nsel += __popcll(bal);
+    }
+    wave_sync();
+  }
+  // leaves: LB2 = LB1
+  const int npass = r < 2 ? 0 : SUBSET ? nsel : (P > 0 ? Ppad : 0);
   const int nch = (n + CH - 1) / CH;
   int *__restrict__ Xh = S.X + lane;
   int *__restrict__ st = S.ST + lane;
@@ -1935,12 +1958,13 @@ __device__ void lb2w_parent(const DevInst &I, int Ppad, const WideLds<NMAX> &S,
     // below are recomputed (two scalar ops) rather than held in registers
 #pragma unroll
     for (int w = 0; w < NW; ++w) asm volatile("" : "+s"(um[w]));
-    const int pi = pc + lane;
+    int pi = pc + lane;
+    if constexpr (SUBSET) pi = S.sel[pi < nsel ? pi : 0];
     const int uvp = S.uv[pi];
     const int u = uvp & 0xff, v = uvp >> 8;
     const int K4 = S.rr[v] + S.c2[v], K5 = S.c1[u] + S.rr[v];
     const int K5x = K5 - K4;  // the high half is Xb + K5 (K4 is already inside)
-    const uint2 *__restrict__ eb = I.entq + (size_t)(pc >> 6) * n * 64 + lane;
+    const uint2 *__restrict__ eb = I.entq + (size_t)(pi >> 6) * n * 64 + (pi & 63);
     // first sweep: Y and the prefix maximum at each chunk start
     int Y = K4, Pm = NEGX;
     for (int ch = 0; ch < nch - 1; ++ch) {
@@ -2050,7 +2074,7 @@ __device__ void lb2w_parent(const DevInst &I, int Ppad, const WideLds<NMAX> &S,
 // times, then its waves take parents in a grid-stride loop.  The 128-job
 // variant runs one wave per SIMD (its LDS tables allow about three waves per
 // CU anyway), which leaves it the accumulation registers beyond 256.
-template <int NMAX>
+template <int NMAX, bool SUBSET>
 __global__ void __launch_bounds__(NMAX >= 128 ? 256 : 512)
 k_lb2w(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__restrict__ out_lb,
        uint8_t *__restrict__ out_prune, int Ppad) {
@@ -2059,7 +2083,8 @@ k_lb2w(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // uniform
   const int count = pool.count_dev ? *pool.count_dev : pool.count;
   if ((int)blockIdx.x * nw >= count) return;  // no parent for this block: skip the staging
-  const WideLayout L{Ppad, I.n, I.m};
+  WideLayout L{Ppad, I.n, I.m};
+  L.subset = SUBSET;
   const WideLds<NMAX> S(sm, L, w);
   lb2w_stage<NMAX>(I, Ppad, S);
   __syncthreads();
@@ -2068,10 +2093,11 @@ k_lb2w(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
   for (int it = blockIdx.x * nw + w; it < count; it += gridDim.x * nw) {
     const int par = pool.index ? pool.index[it] : it;
     const int ns = pool.n;  // row stride (>= n)
-    lb2w_parent<NMAX>(I, Ppad, S, pool.perm + (size_t)par * ns, pool.d1[par], pool.d2[par],
-                      costs + (size_t)par * 3 * m, ns, ub, out_lb + (size_t)par * 2 * ns,
-                      out_prune + (size_t)par * 2 * ns, pool.dir ? pool.dir + par : nullptr,
-                      lane);
+    lb2w_parent<NMAX, SUBSET>(I, Ppad, S, pool.perm + (size_t)par * ns, pool.d1[par],
+                              pool.d2[par], costs + (size_t)par * 3 * m, ns, ub,
+                              out_lb + (size_t)par * 2 * ns, out_prune + (size_t)par * 2 * ns,
+                              pool.dir ? pool.dir + par : nullptr, lane,
+                              SUBSET ? mask_row(pool, par) : nullptr, pool.mask_words);
   }
 }
 
@@ -2923,8 +2949,10 @@ int launch_lb2m(Ctx *c, const FastClassLaunch &L, const DevInst *insts, const ui
 }
 
 void init_bound_attributes() {
-  lds_limit((const void *)k_lb2w<64>);
-  lds_limit((const void *)k_lb2w<128>);
+  lds_limit((const void *)k_lb2w<64, false>);
+  lds_limit((const void *)k_lb2w<128, false>);
+  lds_limit((const void *)k_lb2w<64, true>);
+  lds_limit((const void *)k_lb2w<128, true>);
   lds_limit((const void *)k_lb2mw<64>);
   lds_limit((const void *)k_lb2mw<128>);
   lds_limit((const void *)k_lb1m);
@@ -3096,10 +3124,11 @@ static int wide_waves(const WideLayout &L, int nmax, int pref) {
 }
 
 static int launch_lb2w(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8_t *out_prune,
-                       hipStream_t s) {
+                       hipStream_t s, bool subset) {
   const int Ppad = (c->P + 63) / 64 * 64;
   const int nmax = c->n <= 64 ? 64 : 128;
-  const WideLayout L{Ppad, c->n, c->m};
+  WideLayout L{Ppad, c->n, c->m};
+  L.subset = subset;
   const int waves = wide_waves(L, nmax, (int)c->lb2_waves);
   if (!waves) return set_err(c, PFSP_ERANGE, "wide LB2 tables exceed LDS");
   const size_t lds = L.block_bytes(nmax) + (size_t)waves * L.wave_bytes(nmax);
@@ -3108,12 +3137,15 @@ static int launch_lb2w(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8_t
   if (grid > cap) grid = cap;
   const DevInst I = c->inst();
   KTimer kt(c, s, "k_lb2w");
-  if (nmax == 64)
-    hipLaunchKernelGGL(k_lb2w<64>, dim3(grid), dim3(64 * waves), lds, s, I, pool, ub, c->d_costs,
-                       out_lb, out_prune, Ppad);
-  else
-    hipLaunchKernelGGL(k_lb2w<128>, dim3(grid), dim3(64 * waves), lds, s, I, pool, ub,
-                       c->d_costs, out_lb, out_prune, Ppad);
+#define PFSP_W(N, SUB)                                                                     \
+  hipLaunchKernelGGL((k_lb2w<N, SUB>), dim3(grid), dim3(64 * waves), lds, s, I, pool, ub,   \
+                     c->d_costs, out_lb, out_prune, Ppad)
+  if (nmax == 64) {
+    if (subset) PFSP_W(64, true); else PFSP_W(64, false);
+  } else {
+    if (subset) PFSP_W(128, true); else PFSP_W(128, false);
+  }
+#undef PFSP_W
   PFSP_HIP(c, hipGetLastError());
   return PFSP_OK;
 }
@@ -3195,8 +3227,8 @@ int launch_bound_costs_ready(Ctx *c, const DevPool &pool, int kind, int ub, int 
   const int n = c->n;
   const bool subset = kind == PFSP_LB2_SUBSET;
   const bool log = pool.argpair != nullptr;
-  if (!subset && !log && c->d_entq && c->wide_lb2 && !c->force_generic && n > 32 && n <= 128)
-    return launch_lb2w(c, pool, ub, out_lb, out_prune, s);
+  if (!log && c->d_entq && c->wide_lb2 && !c->force_generic && n > 32 && n <= 128)
+    return launch_lb2w(c, pool, ub, out_lb, out_prune, s, subset);
   const int nmax = c->narrow && !c->force_generic ? fast_nmax(n, c->l16) : 0;
   if (group <= 0) group = (int)c->subset_group;
   if (subset && !log && nmax && nmax <= 32 && c->x16 && (group == 2 || group == 4))

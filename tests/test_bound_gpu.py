@@ -246,6 +246,35 @@ def test_wide_kernel_parity(ctx, n, m, lo, hi):
         np.testing.assert_array_equal(x, y)
 
 
+@pytest.mark.parametrize("n,m,lo,hi", WIDE_CASES)
+def test_wide_subset_parity(ctx, n, m, lo, hi):
+    """Subset LB2 for 32 < n <= 128 with 16-bit X (the wide kernel with the
+    selected pairs gathered by index): per-row selections of 0, 1, 16, 64, 65
+    and all pairs, against the oracle; the wide kernel must be the one that
+    ran."""
+    rng = np.random.default_rng(n * 31 + m + hi)
+    p = rng.integers(lo, hi + 1, size=(n, m)).astype(np.int32)
+    count = 48 if n * m <= 1000 else 24
+    parts = [inputs.random_pool(n, count, 71 + n), inputs.random_pool(n, 4, 72 + n, depth=0),
+             inputs.random_pool(n, 6, 73 + n, depth=n - 1)]
+    perm, d1, d2 = (np.concatenate([q[i] for q in parts]) for i in range(3))
+    P = m * (m - 1) // 2
+    mask = np.zeros((len(perm), (P + 31) // 32), dtype=np.uint32)
+    for i in range(len(perm)):
+        k = min([0, 1, 16, 64, 65, P][i % 6], P)
+        for q in rng.choice(P, size=k, replace=False):
+            mask[i, q >> 5] |= np.uint32(1 << (int(q) & 31))
+    ctx.set_option("timing", 1)
+    try:
+        ctx.kernel_time("k_lb2w", reset=True)
+        olb = _check(ctx, p, perm, d1, d2, binding.LB2_SUBSET, INT32_MAX, mask=mask)
+        assert ctx.kernel_time("k_lb2w")[1] == 1, "the wide kernel did not run"
+    finally:
+        ctx.set_option("timing", 0)
+    _check(ctx, p, perm, d1, d2, binding.LB2_SUBSET, int(np.median(olb[olb < INT32_MAX])),
+           mask=mask)
+
+
 def test_wide_kernel_not_taken_past_limit(ctx):
     """(n + m) max p = 2^15 exactly: 16-bit X does not apply, the earlier
     kernel runs and results stay exact."""

@@ -79,24 +79,29 @@ def bytes_lb2(n, m, count):
     return per * count
 
 
+PROFILE = os.path.join(ROOT, "profiles", "lb2_20x20_1M.md")
+PROFILE_KEYS = {"k_lb2": "k_lb2q<20, false, true>", "k_lb2d": "k_lb2d<20, 8>"}
+
+
 def profiled_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 summary
-    (FETCH_SIZE and WRITE_SIZE scaled by a probe copy of known size), or None
-    when the kernel sources changed since the counters were taken."""
+    """Counter record of `kernel` ("k_lb2" or "k_lb2d") from the committed
+    rocprofv3 summary: HBM bytes per launch (FETCH_SIZE and WRITE_SIZE scaled
+    by a probe copy of known size) and the VALU issue fraction, or None when
+    the kernel sources changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_lb2q_20x20_1M.md")
     try:
-        text = open(path).read()
-        rec = json.loads(text.split("```json")[1].split("```")[0])
+        text = open(PROFILE).read()
+        recs = json.loads(text.split("```json")[1].split("```")[0])
     except (OSError, IndexError, ValueError):
+        return None
+    rec = recs.get(PROFILE_KEYS.get(kernel, ""))
+    if rec is None:
         return None
     h = hashlib.sha256()
     for f in ("bound.hip", "wave.h", "internal.h"):
         with open(os.path.join(ROOT, "paper_2012_09511_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    if rec.get("source_sha256") != h.hexdigest() or not rec["kernel"].startswith(kernel):
-        return None
-    return rec
+    return rec if rec.get("source_sha256") == h.hexdigest() else None
 
 
 def host_cpu():
@@ -152,6 +157,8 @@ def main():
                     help="skip the fixed-depth sweep (profiles of the headline launch alone)")
     ap.add_argument("--headline-only", action="store_true",
                     help="bound workload without the search and learned summaries")
+    ap.add_argument("--depth", type=int, default=-1,
+                    help="bound workload on a pool of this fixed depth (profiling runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--workload", default="bound", choices=["bound", "search", "multi", "learned"])
@@ -172,7 +179,7 @@ def main():
         return bench_learned(args)
     n, m, N = 20, 20, args.parents
     p = inputs.instance(n, m, 2012)
-    perm, d1, d2 = inputs.random_pool(n, N, 9511)
+    perm, d1, d2 = inputs.random_pool(n, N, 9511, depth=None if args.depth < 0 else args.depth)
     ctx = binding.Context(0)
     ctx.load_instance(p)
     ub, _ = ctx.neh()
@@ -251,15 +258,18 @@ def lb2_roofline(n, m, d1, d2, per_launch, deep_r):
     dom = max(ker, key=lambda k: ker[k]["ms"])
     ops_all = alg_ops_lb2(n, m, d1, d2)
     ms_all = sum(v["ms"] for v in ker.values())
-    prof = profiled_traffic("pfsp::k_lb2q<20, false, true>")
+    for k in ker:
+        prof = profiled_traffic(k)
+        ker[k]["traffic"] = prof["traffic_bytes"] if prof else None
+        ker[k]["valu_issue_frac"] = prof["valu_issue_frac"] if prof else None
+        ker[k]["valu_lane_util"] = prof.get("valu_lane_util") if prof else None
     return dict(bound="alu", achieved=ker[dom]["alg_ops"] / (ker[dom]["ms"] * 1e-3) / 1e12,
                 peak=PEAK_INT32_OPS / 1e12, unit="TOP/s", frac=ker[dom]["frac"],
-                traffic=prof["traffic_bytes"] if prof and dom == "k_lb2" else None,
-                kernel=dom, kernel_ms=ker[dom]["ms"], alg_ops_per_launch=ker[dom]["alg_ops"],
+                traffic=ker[dom]["traffic"], kernel=dom, kernel_ms=ker[dom]["ms"],
+                alg_ops_per_launch=ker[dom]["alg_ops"],
                 op_count="11 r P + 8 r m per parent (members-only O(1)-per-child LB2, r jobs "
                          "left, P pairs): alg_ops_lb2",
-                valu_issue_frac=prof["valu_issue_frac"] if prof and dom == "k_lb2" else None,
-                kernels=ker,
+                valu_issue_frac=ker[dom]["valu_issue_frac"], kernels=ker,
                 lb2_stage=dict(ms=ms_all, frac=ops_all / (ms_all * 1e-3) / PEAK_INT32_OPS),
                 yardstick_frac=yardstick_ops_lb2(n, m, d1, d2) / (ms_all * 1e-3) /
                 PEAK_INT32_OPS)

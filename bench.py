@@ -329,8 +329,9 @@ def search_summary(args, with_cpu=True):
         assert r["proven"] and r["found"]
         ref[seed] = r["best"]
     rows, tot = [], {}
-    for kind_name in ("LB1", "LB2_FULL"):
-        kind = getattr(binding, kind_name)
+    for kind_name in ("LB1", "LB2_FULL", "LB2_FULL+heuristic"):
+        kind = getattr(binding, kind_name.split("+")[0])
+        ctx.set_option("heuristic_threads", 8 if "heuristic" in kind_name else 0)
         t_all = nodes = ch = 0
         for seed in range(1, 9):
             p = inputs.instance(20, 10, seed)
@@ -349,10 +350,12 @@ def search_summary(args, with_cpu=True):
             ch += r["children"]
         tot[kind_name] = dict(seconds=t_all, nodes=nodes, nodes_per_s=nodes / t_all,
                               children_per_s=ch / t_all)
+    ctx.set_option("heuristic_threads", 0)
     ctx.close()
     out = dict(workload="depth-first B&B to proven optimality, n=20 x m=10, p~U[1,99], "
                         "seeds 1..8, incumbent NEH+1, 65536 nodes per step; optima equal "
-                        "the oracle's", lb1=tot["LB1"], lb2=tot["LB2_FULL"], instances=rows)
+                        "the oracle's", lb1=tot["LB1"], lb2=tot["LB2_FULL"],
+               lb2_heuristic_threads_8=tot["LB2_FULL+heuristic"], instances=rows)
     if with_cpu:
         cpu = {}
         for name, kind, threads in (("lb1_1core", oracle.LB1, 1), ("lb1_all", oracle.LB1, cores),

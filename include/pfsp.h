@@ -232,6 +232,12 @@ int pfsp_neh(pfsp_ctx *c, int32_t *perm_out, int32_t *cmax_out);
  * with at most deep_r unscheduled jobs take a kernel that scans only their
  * jobs' positions in each pair's Johnson order, the others the full-scan
  * kernel; 0 = every parent takes the full scan; at most 16; default 8),
+ * "heuristic_threads" (host threads that run an iterated greedy local search
+ * on the instance while pfsp_search runs, seeded with NEH and with schedules
+ * completed from open nodes; a better makespan lowers the device incumbent
+ * at the next poll, and the search returns the better of the device's and
+ * the threads' schedules; the optimum is unchanged, node counts then depend
+ * on timing; default 0 = off), "heuristic_seed" (their random seed),
  * "wide_lb2" (1 = PFSP_LB2_FULL for 32 < n <= 128 with (n + m) max p < 2^15
  * runs the wide kernel, whose entries are staged at pfsp_load_instance;
  * default 1), "log_capacity" (records kept by pfsp_search's node log,

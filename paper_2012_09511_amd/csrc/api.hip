@@ -293,6 +293,8 @@ static int64_t *opt_slot(Ctx *c, const char *key) {
   if (!strcmp(key, "log_capacity")) return &c->log_capacity;
   if (!strcmp(key, "log_stride")) return &c->log_stride;
   if (!strcmp(key, "deep_r")) return &c->deep_r;
+  if (!strcmp(key, "heuristic_threads")) return &c->heuristic_threads;
+  if (!strcmp(key, "heuristic_seed")) return &c->heuristic_seed;
   return nullptr;
 }
 
@@ -315,6 +317,8 @@ int pfsp_set_option(pfsp_ctx *h, const char *key, int64_t value) {
     return set_err(c, PFSP_ERANGE, "lb2_blocks_per_cu must be in [0, 64]");
   if (!strcmp(key, "subset_group") && value != 0 && value != 1 && value != 2 && value != 4)
     return set_err(c, PFSP_ERANGE, "subset_group must be 0, 1, 2 or 4");
+  if (!strcmp(key, "heuristic_threads") && (value < 0 || value > 256))
+    return set_err(c, PFSP_ERANGE, "heuristic_threads must be in [0, 256]");
   if (!strcmp(key, "deep_r") && (value < 0 || value > 16))
     return set_err(c, PFSP_ERANGE, "deep_r must be in [0, 16]");
   if (!strcmp(key, "lb2_waves") && (value < 0 || value > 16))

@@ -119,6 +119,8 @@ struct Ctx {
   int64_t log_stride = 1;     // log every log_stride-th decomposed node of a batch
   int64_t wide_lb2 = 1;       // full LB2 for 32 < n <= 128 with 16-bit X takes k_lb2w
   int64_t deep_r = 8;         // full LB2: parents with at most deep_r jobs left take k_lb2d
+  int64_t heuristic_threads = 0;  // host threads improving the incumbent during searches
+  int64_t heuristic_seed = 1;
   struct Pending {
     const char *name;
     hipEvent_t a, b;

@@ -27,6 +27,7 @@
 #include <chrono>
 #include <vector>
 
+#include "heuristic.h"
 #include "internal.h"
 
 namespace pfsp {
@@ -85,6 +86,7 @@ struct SearchState {
 constexpr int kScanBlock = 1024;  // parents per k_scan_local block (256 threads x 4)
 
 __global__ void k_clear(int *p) { *p = 0; }
+__global__ void k_lower_ub(SearchCtl *c, int v) { atomicMin(&c->ub, v); }
 __global__ void k_clear2(int *p) {
   p[0] = 0;
   p[1] = 0;
@@ -617,11 +619,57 @@ static int set_top(Ctx *c, long long top) {
 
 // Replays search steps from the current device state until the tree is
 // exhausted (device and host stacks empty) or the budget is spent.
+// Host threads that improve the incumbent while the search runs (option
+// heuristic_threads); stopped and joined when the search returns.
+struct HeurRun {
+  Heuristic h;
+  bool on = false;
+  ~HeurRun() {
+    if (on) h.finish();
+  }
+};
+
+static void heur_start(Ctx *c, HeurRun &hr) {
+  if (c->heuristic_threads <= 0) return;
+  const int n = c->n, m = c->m;
+  std::vector<int> neh(n);
+  int cmax = 0;
+  neh_host(n, m, c->p_host, neh.data(), &cmax);
+  hr.h.n = n;
+  hr.h.m = m;
+  hr.h.p.assign(c->p_host, c->p_host + (size_t)n * m);
+  hr.h.seed = (uint64_t)c->heuristic_seed;
+  hr.h.launch((int)c->heuristic_threads, neh, cmax);
+  hr.on = true;
+}
+
+// At a poll (stream idle): the top open node completed into a schedule for
+// the heuristic threads, and the device incumbent lowered to theirs.
+static int heur_poll(Ctx *c, HeurRun &hr, const SearchCtl &hc) {
+  SearchState *S = c->search;
+  const int n = c->n;
+  if (hc.top > 0) {
+    uint8_t perm[kMaxN], d[2];
+    PFSP_HIP(c, hipMemcpy(perm, S->s_perm + (size_t)(hc.top - 1) * n, n, hipMemcpyDeviceToHost));
+    PFSP_HIP(c, hipMemcpy(&d[0], S->s_d1 + hc.top - 1, 1, hipMemcpyDeviceToHost));
+    PFSP_HIP(c, hipMemcpy(&d[1], S->s_d2 + hc.top - 1, 1, hipMemcpyDeviceToHost));
+    hr.h.offer(complete_node(c->p_host, n, c->m, perm, d[0], d[1]));
+  }
+  const int v = hr.h.best.load();
+  if (v < hc.ub) {
+    hipLaunchKernelGGL(k_lower_ub, dim3(1), dim3(1), 0, S->stream, S->ctl, v);
+    PFSP_HIP(c, hipGetLastError());
+  }
+  return PFSP_OK;
+}
+
 static int run_search(Ctx *c, int lb_kind, int32_t ub0, int64_t budget_nodes, pfsp_result *res,
                       std::chrono::steady_clock::time_point t0) {
   SearchState *S = c->search;
   const int n = c->n;
   int rc;
+  HeurRun hr;
+  heur_start(c, hr);
   if (c->use_graph) {
     rc = build_graph(c, lb_kind);
     if (rc) return rc;
@@ -659,6 +707,10 @@ static int run_search(Ctx *c, int lb_kind, int32_t ub0, int64_t budget_nodes, pf
       S->resumable = 1;
       break;
     }
+    if (hr.on) {
+      rc = heur_poll(c, hr, hc);
+      if (rc) return rc;
+    }
     if (hc.top == 0) {
       if (S->h_d1.empty()) break;
       // the deepest spilled records come back, filling half the room
@@ -674,10 +726,25 @@ static int run_search(Ctx *c, int lb_kind, int32_t ub0, int64_t budget_nodes, pf
       if (rc) return rc;
     }
   }
+  PFSP_HIP(c, hipStreamSynchronize(S->stream));
+  PFSP_HIP(c, hipMemcpy(S->ctl_host, S->ctl, sizeof(SearchCtl), hipMemcpyDeviceToHost));
   const SearchCtl hc = *S->ctl_host;
+  // the best schedule: the device's best leaf, unless the heuristic threads
+  // hold one at least as good (the device incumbent was only lowered to
+  // their value, so a device leaf below it is strictly better)
+  int best = hc.ub;
+  bool from_heur = false;
+  if (hr.on) {
+    hr.h.finish();
+    hr.on = false;
+    if (hr.h.best.load() <= best && hr.h.best.load() < ub0) {
+      best = hr.h.best.load();
+      from_heur = true;
+    }
+  }
   const auto t1 = std::chrono::steady_clock::now();
-  res->found = hc.ub < ub0;
-  res->best_cmax = res->found ? hc.ub : ub0;
+  res->found = best < ub0;
+  res->best_cmax = res->found ? best : ub0;
   res->proven = status == PFSP_OK;
   res->steps = steps;
   res->nodes_decomposed = hc.nodes;
@@ -685,9 +752,13 @@ static int run_search(Ctx *c, int lb_kind, int32_t ub0, int64_t budget_nodes, pf
   res->max_pool = max_pool;
   res->seconds = std::chrono::duration<double>(t1 - t0).count();
   if (res->found && res->best_perm) {
-    uint8_t tmp[kMaxN];
-    PFSP_HIP(c, hipMemcpy(tmp, S->best_perm, n, hipMemcpyDeviceToHost));
-    for (int j = 0; j < n; ++j) res->best_perm[j] = tmp[j];
+    if (from_heur) {
+      for (int j = 0; j < n; ++j) res->best_perm[j] = hr.h.best_perm[j];
+    } else {
+      uint8_t tmp[kMaxN];
+      PFSP_HIP(c, hipMemcpy(tmp, S->best_perm, n, hipMemcpyDeviceToHost));
+      for (int j = 0; j < n; ++j) res->best_perm[j] = tmp[j];
+    }
   }
   return status;
 }

@@ -286,3 +286,36 @@ def test_dump_resume_matches_uninterrupted(ctx, kind):
         other.close()
         ctx.set_option("pool_batch", 65536)
         ctx.set_option("poll_every", 8)
+
+
+def test_heuristic_threads_supply_the_incumbent(ctx):
+    """Host iterated-greedy threads beside the search (option
+    heuristic_threads): from no incumbent at all the search still proves the
+    oracle's optimum; with the incumbent at the optimum they change nothing
+    (the critical tree is the oracle's); on a 50 x 20 instance under a node
+    budget the returned schedule improves on NEH and is re-evaluated by the
+    oracle."""
+    ctx.set_option("heuristic_threads", 4)
+    try:
+        for seed in (1, 2, 6):
+            g = GOLDEN_20x10[seed]
+            p = inputs.instance(20, 10, seed)
+            ctx.load_instance(p)
+            r = ctx.search(binding.INT32_MAX, 0, binding.LB1)
+            assert r["proven"] and r["found"] and r["best"] == g["opt"]
+            _valid(p, r["perm"], g["opt"])
+            r = ctx.search(g["opt"], 0, binding.LB2_FULL)
+            assert r["proven"] and not r["found"]
+            assert r["nodes"] == g["critical_nodes_lb2"]
+        p = inputs.instance(50, 20, 700)
+        ctx.load_instance(p)
+        neh, _ = ctx.neh()
+        ctx.set_option("pool_batch", 256)
+        ctx.set_option("poll_every", 1)
+        r = ctx.search(neh, 400_000, binding.LB2_FULL)
+        assert r["budget_hit"] and r["found"] and r["best"] < neh
+        _valid(p, r["perm"], r["best"])
+    finally:
+        ctx.set_option("heuristic_threads", 0)
+        ctx.set_option("pool_batch", 65536)
+        ctx.set_option("poll_every", 8)

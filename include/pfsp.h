@@ -191,6 +191,39 @@ int pfsp_search_dump(pfsp_ctx *c, void *buf, int64_t cap, int64_t *size);
 int pfsp_search_resume(pfsp_ctx *c, const void *buf, int64_t size, int64_t budget_nodes,
                        pfsp_result *res);
 
+/* Depth-first search by `explorers` (a power of 4, at most 4^10)
+ * integer-vector-matrix explorers (Section 2.5) on the device, for n <= 64:
+ * each explorer owns a work unit, an interval of the factorial-number-system
+ * numbering of the n! schedules (Section 2.6), explores it depth first, and
+ * when fewer than 80 % of the explorers hold work the empty ones steal the
+ * right half of a busy neighbour's interval on a 4-ary hypercube (Section
+ * 3.4: a victim is taken once per phase and must hold more than the average
+ * and a minimum length).  Each step bounds every explorer's current node with
+ * the kernels of pfsp_bound_children (lb_kind PFSP_LB1 or PFSP_LB2_FULL).
+ * Same result and node semantics as pfsp_search (a node re-decomposed by a
+ * thief on the way to its interval is not counted again); *steals (HOST, may
+ * be NULL) receives the number of work units stolen.  Not resumable.
+ * Synchronous. */
+int pfsp_search_ivm(pfsp_ctx *c, int32_t ub0, int64_t budget_nodes, int lb_kind,
+                    int32_t explorers, pfsp_result *res, int64_t *steals);
+
+/* Work-unit arithmetic of the IVM search on HOST digit vectors (factorial
+ * number system, Section 2.6): a position in [0, n!] is digits d[0 .. n),
+ * digit L in [0, n - L) with weight (n - 1 - L)!, plus a top digit (1 only
+ * for n! itself).  op 0: a + b; op 1: b - a (b >= a); op 2: floor(a / 2);
+ * op 3: a + (b - a) / 2, the split point of a work unit [a, b).  Writes
+ * out[n] and *out_top.  n in [1, 64].  Needs no device. */
+int pfsp_factoradic(int op, int32_t n, const uint8_t *a, int32_t atop, const uint8_t *b,
+                    int32_t btop, uint8_t *out, int32_t *out_top);
+
+/* The node an IVM designates (Section 2.5): HOST M[n][n] (row L: the jobs
+ * schedulable at level L, n - L of them), V[level + 1] (chosen cell per row),
+ * D[level + 1] (0: front of sigma1, 1: front of sigma2), level >= 0; writes
+ * perm_out[n] (sigma1 | unscheduled in row order | sigma2), *d1, *d2.  Needs
+ * no device. */
+int pfsp_ivm_decode(int32_t n, const uint8_t *M, const uint8_t *V, const uint8_t *D,
+                    int32_t level, uint8_t *perm_out, int32_t *d1, int32_t *d2);
+
 /* Copies up to max_records nodes decomposed by the last pfsp_search (every
  * log_stride-th node of each batch, at most log_capacity; option names above)
  * to HOST perm_out[max_records][n], d1_out, d2_out; *count receives the number

@@ -28,7 +28,8 @@ EXPORTS = ["pfsp_create", "pfsp_destroy", "pfsp_last_error", "pfsp_load_instance
            "pfsp_search_log", "pfsp_multi_create", "pfsp_multi_destroy", "pfsp_multi_bound",
            "pfsp_multi_set_shape", "pfsp_multi_autotune", "pfsp_autotune",
            "pfsp_selector_set_quant", "pfsp_selector_infer", "pfsp_bound_children_noalloc",
-           "pfsp_pair_mask", "pfsp_search_set_pairs", "pfsp_search_dump", "pfsp_search_resume"]
+           "pfsp_pair_mask", "pfsp_search_set_pairs", "pfsp_search_dump", "pfsp_search_resume",
+           "pfsp_search_ivm", "pfsp_factoradic", "pfsp_ivm_decode"]
 PAIRS_ADJACENT, PAIRS_LAST = 1, 2
 SELECTOR_PARAMS = 20670
 SELECTOR_QPARAMS = 20675
@@ -82,6 +83,12 @@ def lib():
         L.pfsp_pair_mask.argtypes = [vp, ctypes.c_int, vp, i32]
         L.pfsp_search_set_pairs.argtypes = [vp, vp, i32]
         L.pfsp_search_dump.argtypes = [vp, vp, i64, ctypes.POINTER(i64)]
+        L.pfsp_search_ivm.argtypes = [vp, i32, i64, ctypes.c_int, i32, ctypes.POINTER(Result),
+                                      ctypes.POINTER(i64)]
+        L.pfsp_factoradic.argtypes = [ctypes.c_int, i32, vp, i32, vp, i32, vp,
+                                      ctypes.POINTER(i32)]
+        L.pfsp_ivm_decode.argtypes = [i32, vp, vp, vp, i32, vp, ctypes.POINTER(i32),
+                                      ctypes.POINTER(i32)]
         L.pfsp_search_resume.argtypes = [vp, vp, i64, i64, ctypes.POINTER(Result)]
         L.pfsp_search.argtypes = [vp, i32, i64, ctypes.c_int, ctypes.POINTER(Result)]
         L.pfsp_neh.argtypes = [vp, vp, vp]
@@ -118,6 +125,38 @@ def lib():
 
 def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def factoradic(op, a, atop=0, b=None, btop=0):
+    """pfsp_factoradic on digit vectors: (digits, top)."""
+    a = np.ascontiguousarray(a, dtype=np.uint8)
+    n = len(a)
+    bb = None if b is None else np.ascontiguousarray(b, dtype=np.uint8)
+    out = np.zeros(n, dtype=np.uint8)
+    top = ctypes.c_int32()
+    rc = lib().pfsp_factoradic(int(op), n, a.ctypes.data_as(ctypes.c_void_p), int(atop),
+                               None if bb is None else bb.ctypes.data_as(ctypes.c_void_p),
+                               int(btop), out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(top))
+    if rc != 0:
+        raise PfspError(rc, "pfsp_factoradic failed")
+    return out, top.value
+
+
+def ivm_decode(M, V, D, level):
+    """pfsp_ivm_decode: (perm, d1, d2) of the node an IVM designates."""
+    M = np.ascontiguousarray(M, dtype=np.uint8)
+    n = M.shape[0]
+    V = np.ascontiguousarray(V, dtype=np.uint8)
+    D = np.ascontiguousarray(D, dtype=np.uint8)
+    out = np.zeros(n, dtype=np.uint8)
+    d1, d2 = ctypes.c_int32(), ctypes.c_int32()
+    rc = lib().pfsp_ivm_decode(n, M.ctypes.data_as(ctypes.c_void_p),
+                               V.ctypes.data_as(ctypes.c_void_p), D.ctypes.data_as(ctypes.c_void_p),
+                               int(level), out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(d1),
+                               ctypes.byref(d2))
+    if rc != 0:
+        raise PfspError(rc, "pfsp_ivm_decode failed")
+    return out, d1.value, d2.value
 
 
 class Context:
@@ -243,6 +282,19 @@ class Context:
         rc = self._check(lib().pfsp_search(self.h, int(ub0), int(budget), kind,
                                            ctypes.byref(res)))
         return self._result(res, perm, rc)
+
+    def search_ivm(self, ub0=INT32_MAX, budget=0, kind=LB1, explorers=4096):
+        """IVM explorers with factoradic work units and work stealing."""
+        perm = np.zeros(self.n, dtype=np.int32)
+        res = Result()
+        res.best_perm = perm.ctypes.data_as(ctypes.c_void_p)
+        steals = ctypes.c_int64()
+        rc = self._check(lib().pfsp_search_ivm(self.h, int(ub0), int(budget), kind,
+                                               int(explorers), ctypes.byref(res),
+                                               ctypes.byref(steals)))
+        out = self._result(res, perm, rc)
+        out["steals"] = steals.value
+        return out
 
     def search_dump(self) -> bytes:
         """Checkpoint of the last search that stopped on its budget."""

@@ -17,7 +17,7 @@ LIB = os.path.join(PKG, "libpfsp.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 SOURCES = ["api.hip", "stage.hip", "bound.hip", "search.hip", "selector.hip", "multi.hip",
-           "noalloc.hip", "neh.cpp", "heuristic.cpp"]
+           "noalloc.hip", "ivm.hip", "neh.cpp", "heuristic.cpp"]
 
 # Packed FP32 instructions are switched off for device code: the library
 # computes in integers and plain fp32 and must not depend on them.

@@ -319,3 +319,36 @@ def test_heuristic_threads_supply_the_incumbent(ctx):
         ctx.set_option("heuristic_threads", 0)
         ctx.set_option("pool_batch", 65536)
         ctx.set_option("poll_every", 8)
+
+
+@pytest.mark.parametrize("seed", [1, 3, 6])
+@pytest.mark.parametrize("kind", [binding.LB1, binding.LB2_FULL])
+def test_ivm_search_matches_oracle(ctx, seed, kind):
+    """IVM explorers with factoradic work units and work stealing (Sections
+    2.5, 2.6, 3.4): the oracle's optimum from NEH + 1, and with the incumbent
+    at the optimum exactly the oracle's critical tree, for 1, 16 and 4096
+    explorers (work is stolen whenever there are several)."""
+    g = GOLDEN_20x10[seed]
+    name = "lb1" if kind == binding.LB1 else "lb2"
+    p = inputs.instance(20, 10, seed)
+    ctx.load_instance(p)
+    r = ctx.search_ivm(g["neh"] + 1, 0, kind, 4096)
+    assert r["proven"] and r["found"] and r["best"] == g["opt"]
+    _valid(p, r["perm"], g["opt"])
+    for K in (1, 16, 4096):
+        r = ctx.search_ivm(g["opt"], 0, kind, K)
+        assert r["proven"] and not r["found"]
+        assert (r["nodes"], r["children"]) == (g[f"critical_nodes_{name}"],
+                                               g[f"critical_children_{name}"]), K
+        assert (r["steals"] > 0) == (K > 1)
+
+
+@pytest.mark.parametrize("seed", range(1, 9))
+def test_ivm_search_10x5(ctx, seed):
+    p = inputs.instance(10, 5, seed)
+    opt, _ = oracle.bruteforce(p)
+    ctx.load_instance(p)
+    for kind in (binding.LB1, binding.LB2_FULL):
+        r = ctx.search_ivm(binding.INT32_MAX, 0, kind, 256)
+        assert r["proven"] and r["found"] and r["best"] == opt
+        _valid(p, r["perm"], opt)

@@ -534,15 +534,49 @@ extern "C" int pfsp_search_ivm(pfsp_ctx *h, int32_t ub0, int64_t budget_nodes, i
   pool.argpair = nullptr;
   const int g = (K + 255) / 256;
   const double min_len = std::min(40320.0, 2.0 * (double)K);  // 8! or 2K positions
-  int status = PFSP_OK;
-  for (;;) {
+  // one step as a HIP graph (all sizes come from the control block), replayed
+  // poll_every times between reads of the control block
+  auto enqueue = [&]() -> int {
     hipLaunchKernelGGL(k_ivm_step_begin, dim3(1), dim3(1), 0, S->stream, S->ctl);
     hipLaunchKernelGGL(k_ivm_select, dim3(g), dim3(256), 0, S->stream, *S);
-    rc = launch_bound(c, pool, lb_kind, 0, S->out_lb, S->out_prune, S->stream);
-    if (rc) return rc;
+    const int r = launch_bound(c, pool, lb_kind, 0, S->out_lb, S->out_prune, S->stream);
+    if (r) return r;
     hipLaunchKernelGGL(k_ivm_branch, dim3(g), dim3(256), 0, S->stream, *S);
     hipLaunchKernelGGL(k_ivm_best, dim3(1), dim3(64), 0, S->stream, *S);
     PFSP_HIP(c, hipGetLastError());
+    return PFSP_OK;
+  };
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  struct GraphGuard {
+    hipGraph_t &g;
+    hipGraphExec_t &e;
+    ~GraphGuard() {
+      if (e) (void)hipGraphExecDestroy(e);
+      if (g) (void)hipGraphDestroy(g);
+    }
+  } gguard{graph, gexec};
+  if (c->use_graph) {
+    PFSP_HIP(c, hipStreamBeginCapture(S->stream, hipStreamCaptureModeThreadLocal));
+    c->capturing = 1;
+    rc = enqueue();
+    c->capturing = 0;
+    const hipError_t e = hipStreamEndCapture(S->stream, &graph);
+    if (rc) return rc;
+    if (e != hipSuccess) return hip_err(c, e, "hipStreamEndCapture");
+    PFSP_HIP(c, hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+  }
+  const int every = (int)c->poll_every;
+  int status = PFSP_OK;
+  for (;;) {
+    for (int t = 0; t < every; ++t) {
+      if (gexec) {
+        PFSP_HIP(c, hipGraphLaunch(gexec, S->stream));
+      } else {
+        rc = enqueue();
+        if (rc) return rc;
+      }
+    }
     PFSP_HIP(c, hipMemcpyAsync(S->ctl_host, S->ctl, sizeof(IvmCtl), hipMemcpyDeviceToHost,
                                S->stream));
     PFSP_HIP(c, hipStreamSynchronize(S->stream));

@@ -257,10 +257,12 @@ int pfsp_neh(pfsp_ctx *c, int32_t *perm_out, int32_t *cmax_out);
  * "search_filter" (1 = LB2 search steps close every parent whose children
  * all have LB1 >= incumbent in the costs kernel and bound only the others
  * with LB2; the tree is unchanged since LB2 >= LB1; default 1),
- * "subset_group" (parents per wave of subset LB2 for n <= 32 when every
+ * "subset_group" (parents per wave of subset LB2 for n <= 64 when every
  * stored value fits 16 bits: 2 or 4, each parent then gets 32 or 16 lanes
  * and a selection of up to that many pairs costs one scan pass; 0 = one
- * parent per wave for PFSP_LB2_SUBSET and by top-k for PFSP_LB2_LEARNED),
+ * parent per wave for PFSP_LB2_SUBSET in pfsp_bound_children, and by the
+ * number of selected pairs k in searches and for PFSP_LB2_LEARNED: four
+ * parents per wave for k <= 16 when 32 < n <= 64, else two for k <= 32),
  * "deep_r" (PFSP_LB2_FULL for n <= 32 with (n + m) max p < 2^15: parents
  * with at most deep_r unscheduled jobs take a kernel that scans only their
  * jobs' positions in each pair's Johnson order, the others the full-scan

@@ -2563,6 +2563,399 @@ k_lb2s(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
   }
 }
 
+// -------------------------------------------------- packed wide subset LB2
+// Subset LB2 for 32 < n <= 64 with 16-bit X and G = 2 or 4 parents per wave:
+// the grouping of k_lb2s (group g of L = 64 / G lanes takes parent g, lane l
+// the l-th pair of its selection, lanes past it repeating the first) over
+// the entries of k_lb2w (each lane gathers its pair's quick-format entries
+// from the instance table).  A selection of at most L pairs thus costs one
+// scan pass for G parents instead of one pass per parent with 64 - L idle
+// lanes.  The G parents' start-time tables take most of a CU's LDS, so blocks
+// hold up to four waves (one per SIMD) and the scan keeps twice as many
+// positions in registers as k_lb2w's: a first sweep over the first 32
+// positions for the running sum and prefix maximum there, then the last
+// positions and the first ones with their backward steps.
+struct WsLayout {
+  int ppad, nj, mmax;  // padded pairs, jobs, machines
+  __host__ __device__ int row() const { return (nj + 3) | 1; }
+  __host__ __device__ size_t block_bytes() const {  // pair machines, p by [machine][job]
+    return align16((size_t)ppad * 4) + align16((size_t)mmax * 64 * 2);
+  }
+  __host__ __device__ size_t parent_bytes() const {
+    return align16((size_t)mmax * row() * 4) + align16((size_t)3 * mmax * 4) +
+           align16((size_t)2 * mmax * 8) + 64 * 4 + 128 * 4 + align16((size_t)ppad * 2);
+  }
+  __host__ __device__ size_t wave_bytes(int g) const {
+    return align16((size_t)(nj + 3) * 64 * 4) + (size_t)g * parent_bytes();
+  }
+};
+
+struct WsParent {
+  uint32_t *fb;  // [m][ROW]: f (forward child, low half) | g (backward child, high half) by job
+  int *c1, *c2, *rr;
+  int2 *htf, *htb;  // per scan step: (head, tail + remaining) forward, backward
+  int *inv;         // [64] position of each job in the parent's row
+  int *lb1;         // [2][64]: LB1 of job 32 c + q, forward in lane q, backward in 32 + q
+  int16_t *sel;     // the selected pairs in index order
+};
+
+struct WsLds {
+  int *uv;             // block: pair -> u | v << 8
+  unsigned short *pt;  // block: p by [machine][job] (below 2^15 with 16-bit X)
+  int *X;              // wave: [nj + 3][64] xa | xb << 16 by job (row n: padding sink)
+  unsigned char *pb;   // wave: parent 0's tables; parent g's start g * pstride later
+  int pstride, mmax, ROW, o_c, o_ht, o_inv, o_lb1, o_sel;
+  __device__ WsLds(unsigned char *sm, const WsLayout &L, int w, int G) {
+    ROW = L.row();
+    mmax = L.mmax;
+    uv = (int *)sm;
+    size_t off = align16((size_t)L.ppad * 4);
+    pt = (unsigned short *)(sm + off);
+    off += align16((size_t)L.mmax * 64 * 2);
+    unsigned char *wb = sm + off + (size_t)w * L.wave_bytes(G);
+    X = (int *)wb;
+    pb = wb + align16((size_t)(L.nj + 3) * 64 * 4);
+    pstride = (int)L.parent_bytes();
+    o_c = (int)align16((size_t)L.mmax * ROW * 4);
+    o_ht = o_c + (int)align16((size_t)3 * L.mmax * 4);
+    o_inv = o_ht + (int)align16((size_t)2 * L.mmax * 8);
+    o_lb1 = o_inv + 64 * 4;
+    o_sel = o_lb1 + 128 * 4;
+  }
+  __device__ WsParent parent(int g) const {
+    unsigned char *b = pb + (size_t)g * pstride;
+    WsParent Q;
+    Q.fb = (uint32_t *)b;
+    Q.c1 = (int *)(b + o_c);
+    Q.c2 = Q.c1 + mmax;
+    Q.rr = Q.c2 + mmax;
+    Q.htf = (int2 *)(b + o_ht);
+    Q.htb = Q.htf + mmax;
+    Q.inv = (int *)(b + o_inv);
+    Q.lb1 = (int *)(b + o_lb1);
+    Q.sel = (int16_t *)(b + o_sel);
+    return Q;
+  }
+};
+
+// Forward then backward steps over the cnt <= CH positions of one chunk
+// (cnt uniform), from the chunk-start state (Y, Pm) and the suffix maximum
+// Sm of the positions after it; stores xa | xb << 16 in each job's row of X.
+// um: this lane's membership mask (its parent's, one bit per job).
+template <int CH>
+__device__ __forceinline__ void lb2ws_chunk(const uint2 *__restrict__ ec, int cnt, uint64_t um,
+                                            int K5x, int Y, int Pm, int &Sm,
+                                            int *__restrict__ Xh) {
+  constexpr int NEGX = -(1 << 14);
+  int pt[CH];
+  unsigned ke[CH];
+  uint2 ev[CH];
+#pragma unroll
+  for (int i = 0; i < CH; ++i)
+    if (i < cnt) ev[i] = ec[i * 64];
+#pragma unroll
+  for (int i = 0; i < CH; ++i) {
+    if (i < cnt) {
+      const uint2 e = ev[i];
+      const int ng = __builtin_amdgcn_sbfe((int)(uint32_t)(um >> (e.y & 63u)), 0, 1);
+      const int tt = Y + (int)(e.y >> 16);
+      const int term = (tt & ng) | (NEGX & ~ng);
+      pt[i] = (int)__builtin_amdgcn_perm((unsigned)term, (unsigned)(Pm - (int)e.x), 0x05040100u);
+      Pm = max(Pm, term);
+      Y = __mul24(ng, (int)e.x) + Y;
+      ke[i] = __builtin_amdgcn_perm(e.y, e.x, 0x040c0100u);
+    }
+  }
+  int R = (int)__builtin_amdgcn_perm((unsigned)Sm, (unsigned)Sm, 0x05040100u);
+#pragma unroll
+  for (int i = CH - 1; i >= 0; --i) {
+    if (i < cnt) {
+      R = pk_max_hi(pt[i], R);
+      *(int *)((char *)Xh + (ke[i] >> 16)) =
+          (int)__builtin_amdgcn_perm((unsigned)(R + (int)ke[i] + K5x), (unsigned)R, 0x05040100u);
+    }
+  }
+  Sm = R >> 16;
+}
+
+// One wave bounds the pool rows rows[0 .. G) (-1: none) from their prefetched
+// inputs F.
+template <int G>
+__device__ void lb2ws_wave(const DevInst &I, const WsLds &S, const DevPool &pool,
+                           const int (&rows)[G], const PackFetch (&F)[G], int ub,
+                           int *__restrict__ out_lb, uint8_t *__restrict__ out_prune, int lane,
+                           const GroupSrc<64, 64 / G> &tsrc) {
+  constexpr int L = 64 / G, NB = 64 / L, CH = 32;
+  constexpr int NEGX = -(1 << 14);
+  const int n = I.n, m = I.m, P = I.P, ns = pool.n, ROW = S.ROW;
+  const int gl = lane / L, l = lane % L;  // this lane's group and position in it
+  int a_[G], r_[G];
+  bool ok_[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const int a = __builtin_amdgcn_readfirstlane(F[g].d1);
+    const int b = __builtin_amdgcn_readfirstlane(F[g].d2);
+    a_[g] = a;
+    r_[g] = n - a - b;
+    // c1 < 0 flags a row that the costs kernel found invalid
+    ok_[g] = rows[g] >= 0 && r_[g] >= 1 && __builtin_amdgcn_readfirstlane(F[g].c1) >= 0;
+    if (ok_[g]) {
+      const WsParent Q = S.parent(g);
+      if (lane < n) Q.inv[F[g].rb] = lane;
+      if (lane < m) {
+        Q.c1[lane] = F[g].c1;
+        Q.c2[lane] = F[g].c2;
+        Q.rr[lane] = F[g].rr;
+        Q.htf[lane] = make_int2(F[g].c1, F[g].rr + F[g].c2);
+        Q.htb[m - 1 - lane] = make_int2(F[g].c2, F[g].c1 + F[g].rr);
+      }
+    }
+  }
+  wave_sync();
+  // membership masks (one bit per job, uniform per parent), the children's
+  // LB1 and start times: lane q < 32 the forward child of job 32 c + q, lane
+  // 32 + q its backward child (machines reversed, g stored under the
+  // machine's own index)
+  uint64_t um[G];
+  uint64_t uany = 0;
+  const bool bwd = lane >= 32;
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    um[g] = 0;
+    if (!ok_[g]) continue;
+    const WsParent Q = S.parent(g);
+    const int slot = lane < n ? Q.inv[lane] - a_[g] : -1;
+    um[g] = __ballot(slot >= 0 && slot < r_[g]);
+    uany |= um[g];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      int lb = 0;
+      const int k = 32 * c + (lane & 31);
+      if ((um[g] >> k) & 1ull) {
+        const int2 *HT = bwd ? Q.htb : Q.htf;
+        unsigned short *fb = (unsigned short *)Q.fb + 2 * k + (bwd ? 1 + 2 * (m - 1) * ROW : 0);
+        const int fstep = bwd ? -2 * ROW : 2 * ROW;
+        const unsigned short *PT = S.pt + k + (bwd ? (m - 1) * 64 : 0);
+        const int pstep = bwd ? -64 : 64;
+        int cc = 0;
+#pragma unroll 4
+        for (int s = 0; s < m; ++s) {
+          const int2 ht = HT[s];
+          const int f = max(cc, ht.x);
+          cc = f + PT[s * pstep];
+          fb[s * fstep] = (unsigned short)f;
+          lb = max(lb, f + ht.y);
+        }
+      }
+      Q.lb1[64 * c + lane] = lb;
+    }
+  }
+  // compacted selections: pair indices whose bit is set, in index order
+  int nsel[G];
+  int nmax_sel = 0;
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    nsel[g] = 0;
+    if (!ok_[g] || r_[g] < 2) continue;  // leaves: LB2 = LB1, no pair needed
+    for (int base = 0; base < P; base += 64) {
+      const int pi = base + lane;
+      const uint32_t w = (uint32_t)__shfl((int)F[g].mw, (pi >> 5) & 63, kWave);
+      const bool on = pi < P && ((w >> (pi & 31)) & 1u);
+      const uint64_t bal = __ballot(on);
+      const int pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
+      if (on) S.parent(g).sel[nsel[g] + pos] = (int16_t)pi;
+      nsel[g] += __popcll(bal);
+    }
+    nmax_sel = max(nmax_sel, nsel[g]);
+  }
+  wave_sync();
+  // this lane's parent
+  uint64_t umask = 0;
+  int nsg = 0, ag = 0, rg = 0, par = -1;
+  bool okg = false;
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+    if (gl == g) {
+      umask = um[g];
+      nsg = nsel[g];
+      ag = a_[g];
+      rg = r_[g];
+      par = rows[g];
+      okg = ok_[g];
+    }
+  const WsParent Q = S.parent(gl);
+  int acc[64];  // pair maxima per job: forward | backward << 16 (int16 halves)
+#pragma unroll
+  for (int q = 0; q < 64; ++q) {  // set once (not repeated on the path into the loop)
+    acc[q] = (int)0x80008000u;
+    asm volatile("" : "+v"(acc[q]));
+  }
+  int *__restrict__ Xh = S.X + lane;
+  for (int pc = 0; pc < nmax_sel; pc += L) {
+    const int idx = pc + l;
+    const int pi = nsg > 0 ? Q.sel[idx < nsg ? idx : 0] : 0;
+    const int uvp = S.uv[pi];
+    const int u = uvp & 0xff, v = uvp >> 8;
+    const int K4 = Q.rr[v] + Q.c2[v], K5 = Q.c1[u] + Q.rr[v];
+    const int K5x = K5 - K4;  // the high half is Xb + K5 (K4 is already inside)
+    const uint2 *__restrict__ eb = I.entq + (size_t)(pi >> 6) * n * 64 + (pi & 63);
+    // first sweep: the running sum and prefix maximum at position CH
+    int Y = K4, Pm = NEGX;
+    {
+      uint2 ev[CH];
+#pragma unroll
+      for (int i = 0; i < CH; ++i) ev[i] = eb[i * 64];
+#pragma unroll
+      for (int i = 0; i < CH; ++i) {
+        const uint2 e = ev[i];
+        const int ng = __builtin_amdgcn_sbfe((int)(uint32_t)(umask >> (e.y & 63u)), 0, 1);
+        const int tt = Y + (int)(e.y >> 16);
+        Pm = max(Pm, (tt & ng) | (NEGX & ~ng));
+        Y = __mul24(ng, (int)e.x) + Y;
+      }
+    }
+    // second sweep: positions CH .. n - 1, then 0 .. CH - 1
+    int Sm = NEGX;
+    lb2ws_chunk<CH>(eb + CH * 64, n - CH, umask, K5x, Y, Pm, Sm, Xh);
+    lb2ws_chunk<CH>(eb, CH, umask, K5x, K4, NEGX, Sm, Xh);
+    // children of the member jobs, four at a time: f_u + xa | g_v + xb
+    const int *Fu = lds_opaque((const int *)Q.fb + u * ROW);
+    const int *Gv = lds_opaque((const int *)Q.fb + v * ROW);
+#pragma unroll
+    for (int g0 = 0; g0 < 64; g0 += 4) {
+      if ((uany >> g0) & 0xfull) {
+        int h[4], fw[4], gw[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {  // a group holding a member ends before row n + 3
+          h[j] = Xh[(g0 + j) * 64];
+          fw[j] = Fu[g0 + j];
+          gw[j] = Gv[g0 + j];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)  // sums first: no wait state before each maximum
+          h[j] = pk_add((int)__builtin_amdgcn_perm((unsigned)gw[j], (unsigned)fw[j], 0x07060100u),
+                        h[j]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[g0 + j] = pk_max(acc[g0 + j], h[j]);
+      }
+    }
+  }
+  // fold over each group's lanes: lane l of block b ends with job b * L + l
+  int t[NB];
+  group_blocks<0, L, 64, NB>(acc, t, tsrc, lane);
+  // outputs and MinMin per group
+  int *lbrow = out_lb + (size_t)(par >= 0 ? par : 0) * 2 * ns;
+  uint8_t *prow = out_prune + (size_t)(par >= 0 ? par : 0) * 2 * ns;
+  int vmin = kInt32Max;
+  int valf[NB], valb[NB];
+  bool mem[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int q = b * L + l;
+    const bool member = okg && q < n && ((umask >> q) & 1ull);
+    const int sl = member ? Q.inv[q] - ag : 0;
+    const int pf = nsg > 0 ? (int)(short)(t[b] & 0xffff) : kNeg;
+    const int pb = nsg > 0 ? t[b] >> 16 : kNeg;
+    const int vf = member ? max(Q.lb1[64 * (q >> 5) + (q & 31)], pf) : kInt32Max;
+    const int vb = member ? max(Q.lb1[64 * (q >> 5) + 32 + (q & 31)], pb) : kInt32Max;
+    if (member) {
+      lbrow[sl] = vf;
+      prow[sl] = vf >= ub;
+      lbrow[ns + sl] = vb;
+      prow[ns + sl] = vb >= ub;
+    }
+    valf[b] = vf;
+    valb[b] = vb;
+    mem[b] = member;
+    vmin = min(vmin, min(vf, vb));
+  }
+  const int cmn = group_min<L>(vmin);
+  int cf = 0, cb = 0, flo = 0, fhi = 0, blo = 0, bhi = 0;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    if (mem[b]) {
+      cf += valf[b] == cmn;
+      flo += valf[b] & 0xffff;
+      fhi += valf[b] >> 16;
+      cb += valb[b] == cmn;
+      blo += valb[b] & 0xffff;
+      bhi += valb[b] >> 16;
+    }
+  }
+  cf = group_sum<L>(cf);
+  cb = group_sum<L>(cb);
+  flo = group_sum<L>(flo);
+  fhi = group_sum<L>(fhi);
+  blo = group_sum<L>(blo);
+  bhi = group_sum<L>(bhi);
+  if (par >= 0) {
+    for (int x = l; x < 2 * ns; x += L) {  // slots >= r of both directions (all if invalid)
+      const int q = x < ns ? x : x - ns;
+      if (!okg || q >= rg) {
+        lbrow[x] = kInt32Max;
+        prow[x] = 1;
+      }
+    }
+    if (l == 0 && pool.dir) {
+      MinMin mm;
+      mm.init();
+      mm.merge(cmn, cf, cb, ((long long)fhi << 16) + flo, ((long long)bhi << 16) + blo);
+      pool.dir[par] = okg ? (uint8_t)mm.dir() : (uint8_t)0;
+    }
+  }
+  wave_sync();  // the next parents rewrite this wave's tables
+}
+
+// Blocks of up to four waves (one per SIMD): the registers of the two-sweep
+// scan over 32 positions, and the LDS of G parents' tables per wave.
+template <int G>
+__global__ void __launch_bounds__(256)
+k_lb2ws(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__restrict__ out_lb,
+        uint8_t *__restrict__ out_prune, int Ppad) {
+  extern __shared__ __align__(16) unsigned char sm[];
+  const int nw = blockDim.x >> 6, lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // uniform
+  const int count = pool.count_dev ? *pool.count_dev : pool.count;
+  if ((int)blockIdx.x * nw * G >= count) return;  // no parent for this block
+  const WsLayout L{Ppad, I.n, I.m};
+  const WsLds S(sm, L, w, G);
+  const int n = I.n, m = I.m, P = I.P;
+  for (int x = threadIdx.x; x < Ppad; x += blockDim.x) {
+    const int q = x < P ? x : 0;
+    S.uv[x] = P > 0 ? ((int)I.pu[q] | ((int)I.pv[q] << 8)) : 0;
+  }
+  for (int x = threadIdx.x; x < m * 64; x += blockDim.x) {
+    const int s = x >> 6, k = x & 63;
+    S.pt[x] = (unsigned short)(k < n ? I.p[k * m + s] : 0);
+  }
+  __syncthreads();
+  if (pool.ub_dev) ub = *pool.ub_dev;
+  const int step = gridDim.x * nw * G;
+  int it0 = (blockIdx.x * nw + w) * G;
+  auto row_of = [&](int it) { return it < count ? (pool.index ? pool.index[it] : it) : -1; };
+  const GroupSrc<64, 64 / G> tsrc(lane);
+  int rows[G];
+  PackFetch F[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    rows[g] = row_of(it0 + g);
+    F[g] = pack_fetch(pool, rows[g], n, m, costs, lane);
+  }
+  for (; it0 < count; it0 += step) {
+    PackFetch C[G];
+    int cur[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      C[g] = F[g];
+      cur[g] = rows[g];
+      rows[g] = row_of(it0 + step + g);
+      F[g] = pack_fetch(pool, rows[g], n, m, costs, lane);
+    }
+    lb2ws_wave<G>(I, S, pool, cur, C, ub, out_lb, out_prune, lane, tsrc);
+  }
+}
+
 // Single instance: the block stages the tables once, then each wave takes
 // parents in a grid-stride loop.
 template <int NMAX, bool SUBSET, bool LOG>
@@ -3033,6 +3426,15 @@ int launch_costs(Ctx *c, const DevPool &pool, hipStream_t s, const CostFilter *f
   return PFSP_OK;
 }
 
+int subset_group_for(const Ctx *c, int k) {
+  if (c->subset_group > 0) return (int)c->subset_group;
+  // n <= 32: two parents per wave up to 32 pairs (four cost about as much per
+  // parent, and the two-parent kernel runs three waves per SIMD); 32 < n <=
+  // 64: four parents per wave up to 16 pairs, two up to 32
+  if (c->n > 32 && c->n <= 64 && k <= 16) return 4;
+  return k <= 32 ? 2 : 1;
+}
+
 int deep_bin_r(const Ctx *c, int kind, bool log) {
   if (kind != PFSP_LB2_FULL || log || c->deep_r < 2 || c->force_generic) return 0;
   // the quick kernels' tables with 16-bit X; the costs kernel bins the rows
@@ -3150,6 +3552,39 @@ static int launch_lb2w(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8_t
   return PFSP_OK;
 }
 
+// Packed wide subset kernel: G parents per wave for 32 < n <= 64, blocks of
+// up to four waves (the most that fit 160 KiB of LDS).
+static int launch_lb2ws(Ctx *c, const DevPool &pool, int G, int ub, int *out_lb,
+                        uint8_t *out_prune, hipStream_t s) {
+  const int Ppad = (c->P + 63) / 64 * 64;
+  const WsLayout L{Ppad, c->n, c->m};
+  int waves = 0;
+  for (int w = 4; w >= 1 && !waves; --w)
+    if (L.block_bytes() + (size_t)w * L.wave_bytes(G) <= 160 * 1024) waves = w;
+  if (c->lb2_waves > 0 && c->lb2_waves <= 4 &&
+      L.block_bytes() + (size_t)c->lb2_waves * L.wave_bytes(G) <= 160 * 1024)
+    waves = (int)c->lb2_waves;
+  if (!waves) return set_err(c, PFSP_ERANGE, "packed wide subset tables exceed LDS");
+  const size_t lds = L.block_bytes() + (size_t)waves * L.wave_bytes(G);
+  const int per_block = waves * G;
+  int grid = (pool.count + per_block - 1) / per_block;
+  // twice the blocks that LDS lets a CU hold (each block stages its tables once)
+  const int resident = std::max(1, (int)((160 * 1024) / lds));
+  const int cap = c->cu_count * (c->lb2_blocks_per_cu > 0 ? (int)c->lb2_blocks_per_cu
+                                                          : 2 * resident);
+  if (grid > cap) grid = cap;
+  const DevInst I = c->inst();
+  KTimer kt(c, s, "k_lb2w");
+  if (G == 4)
+    hipLaunchKernelGGL(k_lb2ws<4>, dim3(grid), dim3(64 * waves), lds, s, I, pool, ub, c->d_costs,
+                       out_lb, out_prune, Ppad);
+  else
+    hipLaunchKernelGGL(k_lb2ws<2>, dim3(grid), dim3(64 * waves), lds, s, I, pool, ub, c->d_costs,
+                       out_lb, out_prune, Ppad);
+  PFSP_HIP(c, hipGetLastError());
+  return PFSP_OK;
+}
+
 static size_t lb2d_lds(const Ctx *c, int nmax, int rmax, int waves) {
   const DeepLayout L{(c->P + 63) / 64 * 64, c->m, rmax};
   return L.block_bytes(nmax) + (size_t)waves * L.wave_bytes(nmax);
@@ -3227,10 +3662,13 @@ int launch_bound_costs_ready(Ctx *c, const DevPool &pool, int kind, int ub, int 
   const int n = c->n;
   const bool subset = kind == PFSP_LB2_SUBSET;
   const bool log = pool.argpair != nullptr;
-  if (!log && c->d_entq && c->wide_lb2 && !c->force_generic && n > 32 && n <= 128)
-    return launch_lb2w(c, pool, ub, out_lb, out_prune, s, subset);
-  const int nmax = c->narrow && !c->force_generic ? fast_nmax(n, c->l16) : 0;
   if (group <= 0) group = (int)c->subset_group;
+  if (!log && c->d_entq && c->wide_lb2 && !c->force_generic && n > 32 && n <= 128) {
+    if (subset && n <= 64 && (group == 2 || group == 4))
+      return launch_lb2ws(c, pool, group, ub, out_lb, out_prune, s);
+    return launch_lb2w(c, pool, ub, out_lb, out_prune, s, subset);
+  }
+  const int nmax = c->narrow && !c->force_generic ? fast_nmax(n, c->l16) : 0;
   if (subset && !log && nmax && nmax <= 32 && c->x16 && (group == 2 || group == 4))
     return launch_lb2s(c, pool, group, ub, out_lb, out_prune, s);
   if (nmax) {

@@ -184,6 +184,9 @@ int ensure_costs(Ctx *c, int count);
 int launch_bound(Ctx *c, const DevPool &pool, int kind, int ub, int *out_lb,
                  uint8_t *out_prune, hipStream_t s);
 int launch_costs(Ctx *c, const DevPool &pool, hipStream_t s, const CostFilter *f = nullptr);
+// Parents per wave for subset bounds of at most k pairs per parent: option
+// "subset_group" if set, else by k and n.
+int subset_group_for(const Ctx *c, int k);
 // group: parents per wave for subset bounds (1, 2 or 4; 0 = option "subset_group")
 int launch_bound_costs_ready(Ctx *c, const DevPool &pool, int kind, int ub, int *out_lb,
                              uint8_t *out_prune, hipStream_t s, int group = 0);

@@ -501,9 +501,9 @@ static int enqueue_step(Ctx *c, int kind) {
     if (kind == PFSP_LB2_LEARNED) {
       rc = launch_learned_ready(c, op, 0, S->out_lb, S->out_prune, s);
     } else {
-      // a fixed selection of at most 32 pairs fills half a wave: two parents per wave
-      const int group = kind == PFSP_LB2_SUBSET && c->subset_group == 0 && c->static_pairs <= 32
-                            ? 2 : 0;
+      // a fixed selection of at most 32 (16) pairs fills half (a quarter of) a
+      // wave: several parents per wave
+      const int group = kind == PFSP_LB2_SUBSET ? subset_group_for(c, (int)c->static_pairs) : 0;
       rc = launch_bound_costs_ready(c, op, kind, 0, S->out_lb, S->out_prune, s, group);
       if (!rc && deep) {
         DevPool dp = pool;

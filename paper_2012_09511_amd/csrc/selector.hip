@@ -994,10 +994,9 @@ int launch_learned_ready(Ctx *c, const DevPool &pool, int ub, int *out_lb, uint8
   DevPool sp = pool;
   sp.mask = S->mask;
   sp.mask_words = words;
-  // a top-k of at most 32 pairs fills half a wave: two parents per wave (four
-  // for k <= 16 cost about as much per parent at n <= 20, whose two-parent
-  // kernel runs three waves per SIMD; so four only where asked)
-  const int group = c->subset_group > 0 ? (int)c->subset_group : k <= 32 ? 2 : 1;
+  // a top-k of at most 32 (16) pairs fills half (a quarter of) a wave: two
+  // (four) parents per wave
+  const int group = subset_group_for(c, k);
   rc = launch_bound_costs_ready(c, sp, PFSP_LB2_SUBSET, ub, out_lb, out_prune, s, group);
   if (rc || !c->learned_exact) return rc;
   // Exact mode: a parent that keeps a child under the subset bound is bounded

@@ -275,6 +275,81 @@ def test_wide_subset_parity(ctx, n, m, lo, hi):
            mask=mask)
 
 
+PACKED_WIDE_CASES = [
+    (33, 2, 1, 99),      # one pair; the second sweep's first chunk holds one position
+    (50, 20, 1, 99),     # the learned configuration's shape
+    (64, 20, 1, 99),     # a full 64-job table, both chunks full
+    (40, 64, 1, 99),     # the ABI's largest m: 2016 pairs, one wave per block
+    (57, 20, 0, 425),    # zero times allowed, (n + m) max p = 32725
+]
+
+
+@pytest.mark.parametrize("group", [2, 4])
+@pytest.mark.parametrize("n,m,lo,hi", PACKED_WIDE_CASES)
+def test_packed_wide_subset_parity(ctx, group, n, m, lo, hi):
+    """Subset LB2 for 32 < n <= 64 with 2 or 4 parents per wave: selections of
+    0, 1, up to the group's lanes (one pass), beyond them (several passes) and
+    all pairs; root, one-job-left and two-jobs-left nodes; pool sizes that
+    leave the last wave partly empty; against the oracle at an open and at a
+    mid-range incumbent."""
+    rng = np.random.default_rng(n * 37 + m + hi + group)
+    p = rng.integers(lo, hi + 1, size=(n, m)).astype(np.int32)
+    count = 45 if n * m <= 1000 else 29
+    parts = [inputs.random_pool(n, count, 81 + n), inputs.random_pool(n, 3, 82 + n, depth=0),
+             inputs.random_pool(n, 5, 83 + n, depth=n - 1),
+             inputs.random_pool(n, 4, 84 + n, depth=n - 2)]
+    perm, d1, d2 = (np.concatenate([q[i] for q in parts]) for i in range(3))
+    P = m * (m - 1) // 2
+    L = 64 // group
+    mask = np.zeros((len(perm), (P + 31) // 32), dtype=np.uint32)
+    for i in range(len(perm)):
+        k = min([0, 1, L - 1, L, L + 1, 3 * L + 5, P][i % 7], P)
+        for q in rng.choice(P, size=k, replace=False):
+            mask[i, q >> 5] |= np.uint32(1 << (int(q) & 31))
+    ctx.set_option("subset_group", group)
+    ctx.set_option("timing", 1)
+    try:
+        ctx.kernel_time("k_lb2w", reset=True)
+        olb = _check(ctx, p, perm, d1, d2, binding.LB2_SUBSET, INT32_MAX, mask=mask)
+        assert ctx.kernel_time("k_lb2w")[1] == 1, "the wide kernel did not run"
+        _check(ctx, p, perm, d1, d2, binding.LB2_SUBSET,
+               int(np.median(olb[olb < INT32_MAX])), mask=mask)
+    finally:
+        ctx.set_option("timing", 0)
+        ctx.set_option("subset_group", 0)
+
+
+def test_packed_wide_subset_invalid_rows(ctx):
+    """Rows that are not nodes get INT32_MAX, pruned and direction 0 in the
+    packed wide kernel; their wave mates are bounded exactly."""
+    n, m = 40, 8
+    p = inputs.instance(n, m, 19)
+    perm, d1, d2 = inputs.random_pool(n, 13, 20)
+    d1[1], d2[1] = 30, 10        # d1 + d2 = n
+    perm[2, 3] = perm[2, 4]      # not a permutation
+    perm[6, 0] = 200             # job id out of range
+    mask = np.full((len(perm), 1), 0x0fff0f0f, dtype=np.uint32)
+    ctx.set_option("subset_group", 4)
+    try:
+        ctx.load_instance(p)
+        tp, t1, t2, tm = _dev(ctx, perm, d1, d2, mask)
+        lb, pr, dr, _ = ctx.bound_children(tp, t1, t2, binding.LB2_SUBSET, 2000, pair_mask=tm)
+        with pytest.raises(binding.PfspError):
+            ctx.check()
+        lb, pr, dr = lb.cpu().numpy(), pr.cpu().numpy(), dr.cpu().numpy()
+        bad = [1, 2, 6]
+        assert (lb[bad] == INT32_MAX).all() and (pr[bad] == 1).all() and (dr[bad] == 0).all()
+        good = [i for i in range(len(perm)) if i not in bad]
+        olb, opr, odr = oracle.bound_children(p, perm[good], d1[good], d2[good],
+                                              binding.LB2_SUBSET, 2000, pair_mask=mask[good])
+        np.testing.assert_array_equal(lb[good], olb)
+        np.testing.assert_array_equal(pr[good], opr)
+        np.testing.assert_array_equal(dr[good], odr)
+    finally:
+        ctx.set_option("subset_group", 0)
+        ctx.check()
+
+
 def test_wide_kernel_not_taken_past_limit(ctx):
     """(n + m) max p = 2^15 exactly: 16-bit X does not apply, the earlier
     kernel runs and results stay exact."""

@@ -142,28 +142,32 @@ def test_training_lowers_the_loss(ctx):
     assert last < 0.8 * first
 
 
+@pytest.mark.parametrize("n,ub", [(20, 1900), (50, 4170)])
 @pytest.mark.parametrize("topk", [1, 16, 190])
-def test_learned_bound_equals_subset_bound(ctx, topk):
+def test_learned_bound_equals_subset_bound(ctx, topk, n, ub):
     """LB2_LEARNED = subset LB2 over the pairs the selector picks (checked
-    against the oracle with the same mask) and never above full LB2."""
+    against the oracle with the same mask) and never above full LB2; at
+    n = 50 through the packed wide kernel (four parents per wave for
+    k <= 16, two for k = 32)."""
     import torch
-    n, m = 20, 20
+    m = 20
     p = inputs.instance(n, m, 120)
-    perm, d1, d2 = inputs.random_pool(n, 300, 121)
+    perm, d1, d2 = inputs.random_pool(n, 300 if n <= 20 else 150, 121)
     ctx.load_instance(p)
     ctx.selector_set(_params(122))
     dev = [_t(ctx, a) for a in (perm, d1, d2)]
     k = min(topk, 32)
     ctx.set_option("learned_topk", k)
-    lb, pr, dr, _ = ctx.bound_children(*dev, kind=binding.LB2_LEARNED, ub=1900)
+    lb, pr, dr, _ = ctx.bound_children(*dev, kind=binding.LB2_LEARNED, ub=ub)
     torch.cuda.synchronize()
     mask = ctx.selector_infer(*dev, k).cpu().numpy().view(np.uint32)
-    olb, opr, odr = oracle.bound_children(p, perm, d1, d2, oracle.LB2_SUBSET, 1900,
+    olb, opr, odr = oracle.bound_children(p, perm, d1, d2, oracle.LB2_SUBSET, ub,
                                           pair_mask=mask, threads=8)
     np.testing.assert_array_equal(lb.cpu().numpy(), olb)
     np.testing.assert_array_equal(pr.cpu().numpy(), opr)
     np.testing.assert_array_equal(dr.cpu().numpy(), odr)
-    full, _, _ = oracle.bound_children(p, perm, d1, d2, oracle.LB2_FULL, 1900, threads=8)
+    assert 0 < opr.mean() < 1   # the incumbent prunes some children, not all
+    full, _, _ = oracle.bound_children(p, perm, d1, d2, oracle.LB2_FULL, ub, threads=8)
     assert (olb <= full).all()
     ctx.set_option("learned_topk", 16)
 

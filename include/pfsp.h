@@ -195,10 +195,10 @@ int pfsp_search_resume(pfsp_ctx *c, const void *buf, int64_t size, int64_t budge
  * integer-vector-matrix explorers (Section 2.5) on the device, for n <= 64:
  * each explorer owns a work unit, an interval of the factorial-number-system
  * numbering of the n! schedules (Section 2.6), explores it depth first, and
- * when fewer than 80 % of the explorers hold work the empty ones steal the
- * right half of a busy neighbour's interval on a 4-ary hypercube (Section
- * 3.4: a victim is taken once per phase and must hold more than the average
- * and a minimum length).  Each step bounds every explorer's current node with
+ * every "poll_every" steps, when fewer than 80 % of the explorers held work,
+ * the empty ones steal the right half of a busy neighbour's interval on a
+ * 4-ary hypercube (Section 3.4: a victim is taken once per phase and must
+ * hold more than the average and a minimum length).  Each step bounds every explorer's current node with
  * the kernels of pfsp_bound_children (lb_kind PFSP_LB1 or PFSP_LB2_FULL).
  * Same result and node semantics as pfsp_search (a node re-decomposed by a
  * thief on the way to its interval is not counted again); *steals (HOST, may

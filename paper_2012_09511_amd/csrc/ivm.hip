@@ -29,7 +29,9 @@
 //
 // One step: k_ivm_select (every explorer moves to its next node and writes it
 // as a pool row) -> the bounding kernels of pfsp_bound_children on that
-// pool -> k_ivm_branch (rows of the next level, prune flags, leaves).
+// pool -> k_ivm_branch (rows of the next level, prune flags, leaves) ->
+// k_ivm_balance (the step's best leaf; a stealing phase, every poll_every
+// steps when few explorers were busy, with the lengths from k_ivm_branch).
 #include <math.h>
 #include <string.h>
 
@@ -58,10 +60,12 @@ __host__ __device__ inline int fact_cmp(int n, const uint8_t *a, int atop, const
 __host__ __device__ inline int fact_add(int n, const uint8_t *a, int atop, const uint8_t *b,
                                         int btop, uint8_t *c) {
   int carry = 0;
-  for (int L = n - 1; L >= 0; --L) {
-    const int radix = n - L, t = a[L] + b[L] + carry;
-    c[L] = (uint8_t)(t % radix);
-    carry = t / radix;
+  for (int L = n - 1; L >= 0; --L) {  // digits below their radix: the carry is 0 or 1
+    const int radix = n - L;
+    int t = a[L] + b[L] + carry;
+    carry = t >= radix;
+    if (carry) t -= radix;
+    c[L] = (uint8_t)t;
   }
   return atop + btop + carry;
 }
@@ -130,8 +134,9 @@ struct IvmCtl {
   int ub_step;     // prune threshold of the step
   unsigned long long step_best;  // (makespan << 32) | pool row of the step's best leaf
   long long nodes, children, steps, steals;
-  double len_sum;  // interval lengths of the busy explorers (stealing phase)
-  int newbest, pad;
+  double len_sum;  // interval lengths of the busy explorers (stealing phases)
+  int busy;        // busy explorers (stealing phases)
+  int newbest;
 };
 
 struct IvmState {
@@ -173,12 +178,6 @@ __device__ __forceinline__ bool cell_pruned(const IvmState &S, int k, int L, int
   return ((S.Pr[(size_t)k * S.n + L] >> x) & 1ull) || S.LB[cell] >= ub;
 }
 
-__device__ __forceinline__ bool digits_zero_after(const uint8_t *V, int n, int I) {
-  for (int L = I + 1; L < n; ++L)
-    if (V[L]) return false;
-  return true;
-}
-
 // Appends the rows of the wave's lanes with app set to a counter: one atomic
 // per wave; returns this lane's slot.
 __device__ __forceinline__ int wave_append(int *count, bool app) {
@@ -194,66 +193,117 @@ __device__ __forceinline__ int wave_append(int *count, bool app) {
 }
 
 // Every explorer moves to its next node (depth-first, leftmost first) and
-// writes it as a row of the step's pool.
+// writes it as a row of the step's pool.  The walk reads the explorer's
+// position and interval end many times, so both are copied to LDS first
+// (digit L of thread t at [L][t]) and the position is written back once.
 __global__ void __launch_bounds__(256) k_ivm_select(IvmState S) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ uint8_t sV[kIvmMaxN * 256], sE[kIvmMaxN * 256], sP[kIvmMaxN * 256];
+  const int t = threadIdx.x;
+  const int k = blockIdx.x * blockDim.x + t;
   IvmCtl *c = S.ctl;
   const int n = S.n;
   bool emit = false, counted = true, root = false;
   int I = -1;
   if (k < S.K && S.st[k] != kIvmEmpty) {
     int st = S.st[k];
-    uint8_t *V = S.V + (size_t)k * n;
-    const uint8_t *E = S.E + (size_t)k * n;
+    uint8_t *Vg = S.V + (size_t)k * n;
+    const uint8_t *Eg = S.E + (size_t)k * n;
+    for (int L = 0; L < n; ++L) {
+      sV[L * 256 + t] = Vg[L];
+      sE[L * 256 + t] = Eg[L];
+    }
+    auto V = [&](int L) -> uint8_t & { return sV[L * 256 + t]; };
+    // position >= interval end (the top digit of the position is 0)
+    auto at_end = [&]() {
+      const int etop = S.Etop[k];
+      if (etop) return false;
+      for (int L = 0; L < n; ++L) {
+        const int a = sV[L * 256 + t], b = sE[L * 256 + t];
+        if (a != b) return a > b;
+      }
+      return true;
+    };
     const int ub = c->ub_step;
     I = S.lev[k];
     if (st == kIvmRoot) {
       // the root: decomposed again by a thief (not counted) unless the work
       // unit starts at position 0
-      for (int L = 0; L < n; ++L) counted = counted && V[L] == 0;
+      for (int L = 0; L < n; ++L) counted = counted && V(L) == 0;
       root = true;
       emit = true;
     } else {
+      bool moved = false;
       if (st == kIvmInit) {
-        if (cell_pruned(S, k, I, V[I], ub)) {
+        if (cell_pruned(S, k, I, V(I), ub)) {
           // the path's subtree is pruned: continue after it
-          for (int L = I + 1; L < n; ++L) V[L] = 0;
-          V[I] += 1;
+          for (int L = I + 1; L < n; ++L) V(L) = 0;
+          V(I) += 1;
+          moved = true;
           st = kIvmActive;
-        } else if (digits_zero_after(V, n, I)) {
-          st = kIvmActive;  // the work unit starts at this node: it is ours
         } else {
-          counted = false;  // an ancestor of the work unit's start
-          emit = true;
+          bool zero = true;
+          for (int L = I + 1; L < n; ++L) zero = zero && V(L) == 0;
+          if (zero) {
+            st = kIvmActive;  // the work unit starts at this node: it is ours
+          } else {
+            counted = false;  // an ancestor of the work unit's start
+            emit = true;
+          }
         }
       }
       if (st == kIvmActive) {
+        // the cells of row L that cannot be taken: pruned, bound at or above
+        // the incumbent, or past the row's end (its bounds load together)
+        auto row_mask = [&](int L) -> unsigned long long {
+          unsigned long long msk = S.Pr[(size_t)k * n + L];
+          const int *__restrict__ lbr = S.LB + ((size_t)k * n + L) * n;
+          const int len = n - L;
+          for (int x = 0; x < len; ++x)
+            if (lbr[x] >= ub) msk |= 1ull << x;
+          return len >= 64 ? msk : msk | (~0ull << len);
+        };
+        unsigned long long mI = I >= 0 ? row_mask(I) : 0ull;
         for (;;) {
           if (I < 0) {
             st = kIvmEmpty;
             break;
           }
-          if (V[I] >= n - I) {  // end of the row: back to the parent's next sibling
-            V[I] = 0;
+          const int x0 = V(I);
+          const unsigned long long open = x0 < 64 ? ~mI & (~0ull << x0) : 0ull;
+          if (!open) {  // the rest of the row is closed: back to the parent's next sibling
+            V(I) = 0;
             --I;
-            if (I >= 0) V[I] += 1;
+            if (I >= 0) {
+              V(I) += 1;
+              mI = row_mask(I);
+            }
+            moved = true;
             continue;
           }
-          if (fact_cmp(n, V, 0, E, S.Etop[k]) >= 0) {  // past the end of the work unit
+          // the next open cell; the cells skipped are closed, and a position
+          // past the end of the work unit stays past it as it grows
+          const int x = __builtin_ctzll(open);
+          if (x != x0) {
+            V(I) = (uint8_t)x;
+            moved = true;
+          }
+          if (at_end()) {
             st = kIvmEmpty;
             break;
-          }
-          if (cell_pruned(S, k, I, V[I], ub)) {
-            V[I] += 1;
-            continue;
           }
           emit = true;
           break;
         }
       }
+      if (moved)
+        for (int L = 0; L < n; ++L) Vg[L] = sV[L * 256 + t];
       S.st[k] = st;
       S.lev[k] = I;
     }
+  }
+  if (k < S.K) {  // for a stealing phase at the end of this step
+    S.taken[k] = 0;
+    if (!emit) S.len[k] = 0.0;
   }
   const int b = wave_append(&c->batch, emit);
   if (!emit) return;
@@ -262,8 +312,25 @@ __global__ void __launch_bounds__(256) k_ivm_select(IvmState S) {
   if (root) {
     for (int j = 0; j < n; ++j) perm[j] = (uint8_t)j;
   } else {
-    ivm_decode(n, S.M + (size_t)k * n * n, S.V + (size_t)k * n, S.D + (size_t)k * n, I, perm,
-               &d1, &d2);
+    // ivm_decode with the row built in LDS: the loads of M and D do not wait
+    // for stores to the pool row
+    const uint8_t *__restrict__ Mk = S.M + (size_t)k * n * n;
+    const uint8_t *__restrict__ Dk = S.D + (size_t)k * n;
+#pragma unroll 4
+    for (int L = 0; L <= I; ++L) {
+      const uint8_t j = Mk[L * n + sV[L * 256 + t]];
+      if (Dk[L] == 0)
+        sP[(d1++) * 256 + t] = j;
+      else
+        sP[(n - 1 - d2++) * 256 + t] = j;
+    }
+    const uint8_t *__restrict__ row = Mk + (size_t)I * n;
+    const int vi = sV[I * 256 + t];
+    int w = d1;
+#pragma unroll 4
+    for (int x = 0; x < n - I; ++x)
+      if (x != vi) sP[(w++) * 256 + t] = row[x];
+    for (int x = 0; x < n; ++x) perm[x] = sP[x * 256 + t];
   }
   S.b_d1[b] = (uint8_t)d1;
   S.b_d2[b] = (uint8_t)d2;
@@ -272,29 +339,13 @@ __global__ void __launch_bounds__(256) k_ivm_select(IvmState S) {
 }
 
 // Per pool row: node statistics, leaves, and the next row of the explorer.
-__global__ void __launch_bounds__(256) k_ivm_branch(IvmState S) {
-  IvmCtl *c = S.ctl;
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  const int count = c->batch;
+__device__ void ivm_branch_row(const IvmState &S, IvmCtl *c, int b) {
   const int n = S.n;
-  {  // node statistics, one atomic per wave
-    const bool cnt = b < count && S.b_counted[b];
-    long long nodes = cnt, ch = cnt ? 2 * (n - S.b_d1[b] - S.b_d2[b]) : 0;
-    for (int o = 32; o >= 1; o >>= 1) {
-      nodes += __shfl_xor(nodes, o, 64);
-      ch += __shfl_xor(ch, o, 64);
-    }
-    if ((threadIdx.x & 63) == 0 && nodes) {
-      atomicAdd((unsigned long long *)&c->nodes, (unsigned long long)nodes);
-      atomicAdd((unsigned long long *)&c->children, (unsigned long long)ch);
-    }
-  }
-  if (b >= count) return;
   const int k = S.b_ivm[b];
   const int r = n - S.b_d1[b] - S.b_d2[b], dir = S.b_dir[b];
   const int ub = c->ub_step;
-  const int *lb = S.out_lb + ((size_t)b * 2 + dir) * n;
-  const uint8_t *pr = S.out_prune + ((size_t)b * 2 + dir) * n;
+  const int *__restrict__ lb = S.out_lb + ((size_t)b * 2 + dir) * n;
+  const uint8_t *__restrict__ pr = S.out_prune + ((size_t)b * 2 + dir) * n;
   const int st = S.st[k];
   int I = st == kIvmRoot ? -1 : S.lev[k];
   uint8_t *V = S.V + (size_t)k * n;
@@ -308,11 +359,12 @@ __global__ void __launch_bounds__(256) k_ivm_branch(IvmState S) {
   }
   // row I + 1: the unscheduled jobs in list order, their flags and bounds
   const int L = I + 1;
-  const uint8_t *perm = S.b_perm + (size_t)b * n;
+  const uint8_t *__restrict__ perm = S.b_perm + (size_t)b * n;
   const int a = S.b_d1[b];
-  uint8_t *row = S.M + ((size_t)k * n + L) * n;
-  int *lbrow = S.LB + ((size_t)k * n + L) * n;
+  uint8_t *__restrict__ row = S.M + ((size_t)k * n + L) * n;
+  int *__restrict__ lbrow = S.LB + ((size_t)k * n + L) * n;
   unsigned long long bits = 0ull;
+#pragma unroll 4
   for (int q = 0; q < r; ++q) {
     row[q] = perm[a + q];
     lbrow[q] = lb[q];
@@ -329,68 +381,161 @@ __global__ void __launch_bounds__(256) k_ivm_branch(IvmState S) {
   // an initializing explorer keeps V[L], the start's digit
 }
 
-// The step's best leaf: its schedule and the flag for the host.
-__global__ void k_ivm_best(IvmState S) {
-  IvmCtl *c = S.ctl;
-  const unsigned long long sb = c->step_best;
-  if (sb == ~0ull) return;
-  const int b = (int)(sb & 0xffffffffu), n = S.n;
-  // a one-job parent's only child is its own permutation
-  for (int x = threadIdx.x; x < n; x += blockDim.x) S.best_perm[x] = S.b_perm[(size_t)b * n + x];
-  if (threadIdx.x == 0) c->newbest = 1;
-}
-
 __global__ void k_ivm_step_begin(IvmCtl *c) {
   c->batch = 0;
   c->ub_step = c->ub;
   c->step_best = ~0ull;
   c->steps += 1;
+  c->len_sum = 0.0;
+  c->busy = 0;
 }
 
-// Interval lengths of the busy explorers and their sum.
-__global__ void __launch_bounds__(256) k_ivm_len(IvmState S) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= S.K) return;
+// Length E - V of explorer k's interval as a double (the digits of the
+// difference are produced from the least significant one up and summed with
+// their weights, so no digit array is kept).
+__device__ inline double ivm_len(const IvmState &S, int k) {
   const int n = S.n;
+  const uint8_t *__restrict__ V = S.V + (size_t)k * n;
+  const uint8_t *__restrict__ E = S.E + (size_t)k * n;
+  double v = 0.0, w = 1.0;  // w = (n - 1 - L)!
+  int borrow = 0;
+#pragma unroll 8
+  for (int L = n - 1; L >= 0; --L) {
+    int t = (int)E[L] - (int)V[L] - borrow;
+    borrow = t < 0;
+    if (borrow) t += n - L;
+    v += t * w;
+    w *= (double)(n - L);
+  }
+  return v + (S.Etop[k] - borrow) * w;
+}
+
+// Whether this step ends with a stealing phase: every every-th step, when
+// fewer than 80 % of the explorers held a node in it (uniform).
+__device__ __forceinline__ bool ivm_balancing(const IvmState &S, int every) {
+  const IvmCtl *c = S.ctl;
+  return S.K > 1 && c->steps % every == 0 && c->batch * 5 < S.K * 4;
+}
+
+// Per pool row: node statistics, leaves, and the next row of the explorer;
+// on a stealing step also the first part of the phase: the interval lengths
+// of the busy explorers (those in the pool), their sum and count.  The
+// empty explorers' lengths and every explorer's victim flag were cleared by
+// k_ivm_select.
+__global__ void __launch_bounds__(256) k_ivm_branch(IvmState S, int every) {
+  IvmCtl *c = S.ctl;
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  const int count = c->batch;
+  const int n = S.n;
+  {  // node statistics, one atomic per wave
+    const bool cnt = b < count && S.b_counted[b];
+    long long nodes = cnt, ch = cnt ? 2 * (n - S.b_d1[b] - S.b_d2[b]) : 0;
+    for (int o = 32; o >= 1; o >>= 1) {
+      nodes += __shfl_xor(nodes, o, 64);
+      ch += __shfl_xor(ch, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0 && nodes) {
+      atomicAdd((unsigned long long *)&c->nodes, (unsigned long long)nodes);
+      atomicAdd((unsigned long long *)&c->children, (unsigned long long)ch);
+    }
+  }
+  if (b < count) ivm_branch_row(S, c, b);
+  if (!ivm_balancing(S, every)) return;  // uniform
   double l = 0.0;
-  S.taken[k] = 0;
-  if (S.st[k] != kIvmEmpty) {
-    uint8_t diff[kIvmMaxN];
-    const int top = fact_sub(n, S.E + (size_t)k * n, S.Etop[k], S.V + (size_t)k * n, 0, diff);
-    l = fact_double(n, diff, top);
-    atomicAdd(&S.ctl->len_sum, l);
+  int busy = 0;
+  if (b < count) {
+    const int k = S.b_ivm[b];
+    l = ivm_len(S, k);
+    S.len[k] = l;
+    busy = 1;
   }
-  S.len[k] = l;
+  for (int o = 32; o >= 1; o >>= 1) {
+    l += __shfl_xor(l, o, 64);
+    busy += __shfl_xor(busy, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0 && busy) {
+    atomicAdd(&c->len_sum, l);
+    atomicAdd(&c->busy, busy);
+  }
 }
 
-// One round of victim selection: every empty explorer e tries the neighbour
-// whose base-4 digit i is (digit - j) mod 4.
-__global__ void __launch_bounds__(256) k_ivm_steal(IvmState S, int i, int j, double min_len,
-                                                   int busy) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= S.K || S.st[e] != kIvmEmpty || busy <= 0) return;
-  const double avg = S.ctl->len_sum / busy;
-  const int dig = (e >> (2 * i)) & 3;
-  const int v = e - (dig << (2 * i)) + (((dig - j) & 3) << (2 * i));
-  if (v == e || S.st[v] == kIvmEmpty || S.len[v] <= avg || S.len[v] < min_len) return;
-  if (atomicCAS(&S.taken[v], 0, 1) != 0) return;
-  const int n = S.n;
-  uint8_t *Vv = S.V + (size_t)v * n, *Ev = S.E + (size_t)v * n;
-  uint8_t mid[kIvmMaxN];
-  const int ltop = fact_sub(n, Ev, S.Etop[v], Vv, 0, mid);
-  fact_half(n, mid, ltop);
-  const int mtop = fact_add(n, Vv, 0, mid, 0, mid);  // V + (E - V) / 2 < E <= n!
-  uint8_t *Ve = S.V + (size_t)e * n, *Ee = S.E + (size_t)e * n;
-  for (int L = 0; L < n; ++L) {
-    Ve[L] = mid[L];
-    Ee[L] = Ev[L];
-    Ev[L] = mid[L];
+// The step's best leaf, then the stealing phase's second part (one block):
+// in 3d rounds (digit i of the
+// index lowered by j = 1, 2, 3, mod 4) every empty explorer e tries the
+// neighbour v and takes the right half of v's interval if v is busy, nobody
+// took from v in this phase, and v's interval is longer than the mean and
+// than min_len.  The thief's V row holds the midpoint computation.
+__global__ void __launch_bounds__(1024) k_ivm_balance(IvmState S, double min_len, int every) {
+  // per thread: the victim's position and interval end (digit L at [L][t])
+  __shared__ uint8_t sA[kIvmMaxN * 1024], sB[kIvmMaxN * 1024];
+  IvmCtl *c = S.ctl;
+  const int K = S.K, n = S.n, T = blockDim.x, t = threadIdx.x;
+  {  // the step's best leaf: its schedule (a one-job parent's only child is
+     // its own row) and the flag for the host
+    const unsigned long long sb = c->step_best;
+    if (sb != ~0ull) {
+      const int b = (int)(sb & 0xffffffffu);
+      for (int x = t; x < n; x += T) S.best_perm[x] = S.b_perm[(size_t)b * n + x];
+      if (t == 0) c->newbest = 1;
+    }
   }
-  S.Etop[e] = S.Etop[v];
-  S.Etop[v] = (uint8_t)mtop;
-  S.st[e] = kIvmRoot;
-  S.lev[e] = -1;
-  atomicAdd((unsigned long long *)&S.ctl->steals, 1ull);
+  if (!ivm_balancing(S, every)) return;
+  const int busy = c->busy;
+  if (busy == 0) return;  // uniform: nothing to steal
+  const double avg = c->len_sum / busy;
+  long long steals = 0;
+  for (int i = 0; i < S.d; ++i) {
+    for (int j = 1; j <= 3; ++j) {
+      for (int e = t; e < K; e += T) {
+        if (S.st[e] != kIvmEmpty) continue;
+        const int dig = (e >> (2 * i)) & 3;
+        const int v = e - (dig << (2 * i)) + (((dig - j) & 3) << (2 * i));
+        if (v == e || S.st[v] == kIvmEmpty || S.len[v] <= avg || S.len[v] < min_len) continue;
+        if (atomicCAS(&S.taken[v], 0, 1) != 0) continue;
+        uint8_t *__restrict__ Vv = S.V + (size_t)v * n;
+        uint8_t *__restrict__ Ev = S.E + (size_t)v * n;
+        uint8_t *__restrict__ Ve = S.V + (size_t)e * n;
+        uint8_t *__restrict__ Ee = S.E + (size_t)e * n;
+        for (int L = 0; L < n; ++L) {
+          sA[L * 1024 + t] = Vv[L];
+          sB[L * 1024 + t] = Ev[L];
+        }
+        // mid = Vv + (Ev - Vv) / 2 < Ev, in sB: difference, half, sum
+        int borrow = 0;
+        for (int L = n - 1; L >= 0; --L) {
+          int x = (int)sB[L * 1024 + t] - (int)sA[L * 1024 + t] - borrow;
+          borrow = x < 0;
+          if (borrow) x += n - L;
+          Ee[L] = sB[L * 1024 + t];  // the thief's end: the victim's old end
+          sB[L * 1024 + t] = (uint8_t)x;
+        }
+        int rem = S.Etop[v] - borrow;
+        for (int L = 0; L < n; ++L) {
+          const int x = sB[L * 1024 + t] + rem * (n - L);
+          sB[L * 1024 + t] = (uint8_t)(x >> 1);
+          rem = x & 1;
+        }
+        int carry = 0;
+        for (int L = n - 1; L >= 0; --L) {
+          int x = sA[L * 1024 + t] + sB[L * 1024 + t] + carry;
+          carry = x >= n - L;
+          if (carry) x -= n - L;
+          Ve[L] = (uint8_t)x;
+          Ev[L] = (uint8_t)x;
+        }
+        const int mtop = carry;
+        S.Etop[e] = S.Etop[v];
+        S.Etop[v] = (uint8_t)mtop;
+        S.st[e] = kIvmRoot;
+        S.lev[e] = -1;
+        ++steals;
+      }
+      __syncthreads();  // the next round sees this round's thieves and victims
+    }
+  }
+  for (int o = 32; o >= 1; o >>= 1) steals += __shfl_xor(steals, o, 64);
+  if ((t & 63) == 0 && steals)
+    atomicAdd((unsigned long long *)&c->steals, (unsigned long long)steals);
 }
 
 static IvmState *ivm_alloc(Ctx *c, int K) {
@@ -534,6 +679,7 @@ extern "C" int pfsp_search_ivm(pfsp_ctx *h, int32_t ub0, int64_t budget_nodes, i
   pool.argpair = nullptr;
   const int g = (K + 255) / 256;
   const double min_len = std::min(40320.0, 2.0 * (double)K);  // 8! or 2K positions
+  const int every = (int)c->poll_every;  // steps between polls and between stealing phases
   // one step as a HIP graph (all sizes come from the control block), replayed
   // poll_every times between reads of the control block
   auto enqueue = [&]() -> int {
@@ -541,8 +687,8 @@ extern "C" int pfsp_search_ivm(pfsp_ctx *h, int32_t ub0, int64_t budget_nodes, i
     hipLaunchKernelGGL(k_ivm_select, dim3(g), dim3(256), 0, S->stream, *S);
     const int r = launch_bound(c, pool, lb_kind, 0, S->out_lb, S->out_prune, S->stream);
     if (r) return r;
-    hipLaunchKernelGGL(k_ivm_branch, dim3(g), dim3(256), 0, S->stream, *S);
-    hipLaunchKernelGGL(k_ivm_best, dim3(1), dim3(64), 0, S->stream, *S);
+    hipLaunchKernelGGL(k_ivm_branch, dim3(g), dim3(256), 0, S->stream, *S, every);
+    hipLaunchKernelGGL(k_ivm_balance, dim3(1), dim3(1024), 0, S->stream, *S, min_len, every);
     PFSP_HIP(c, hipGetLastError());
     return PFSP_OK;
   };
@@ -566,7 +712,6 @@ extern "C" int pfsp_search_ivm(pfsp_ctx *h, int32_t ub0, int64_t budget_nodes, i
     if (e != hipSuccess) return hip_err(c, e, "hipStreamEndCapture");
     PFSP_HIP(c, hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
   }
-  const int every = (int)c->poll_every;
   int status = PFSP_OK;
   for (;;) {
     for (int t = 0; t < every; ++t) {
@@ -585,17 +730,6 @@ extern "C" int pfsp_search_ivm(pfsp_ctx *h, int32_t ub0, int64_t budget_nodes, i
     if (budget_nodes > 0 && hc.nodes >= budget_nodes) {
       status = PFSP_BUDGET;
       break;
-    }
-    if (hc.batch < (K * 4) / 5 && K > 1) {  // work stealing phase: few explorers busy
-      const double zero = 0.0;
-      PFSP_HIP(c, hipMemcpyAsync((char *)S->ctl + offsetof(IvmCtl, len_sum), &zero, sizeof zero,
-                                 hipMemcpyHostToDevice, S->stream));
-      hipLaunchKernelGGL(k_ivm_len, dim3(g), dim3(256), 0, S->stream, *S);
-      for (int i = 0; i < d; ++i)
-        for (int j = 1; j <= 3; ++j)
-          hipLaunchKernelGGL(k_ivm_steal, dim3(g), dim3(256), 0, S->stream, *S, i, j, min_len,
-                             hc.batch);
-      PFSP_HIP(c, hipGetLastError());
     }
   }
   const IvmCtl hc = *S->ctl_host;

@@ -351,7 +351,7 @@ def search_summary(args, with_cpu=True):
         tot[kind_name] = dict(seconds=t_all, nodes=nodes, nodes_per_s=nodes / t_all,
                               children_per_s=ch / t_all)
     ctx.set_option("heuristic_threads", 0)
-    # the same searches by 16384 IVM explorers with work stealing
+    # the same searches by 4096 IVM explorers with work stealing
     for kind_name in ("LB1", "LB2_FULL"):
         kind = getattr(binding, kind_name)
         t_all = nodes = steals = 0
@@ -359,9 +359,9 @@ def search_summary(args, with_cpu=True):
             p = inputs.instance(20, 10, seed)
             ctx.load_instance(p)
             ub0, _ = ctx.neh()
-            ctx.search_ivm(ub0 + 1, 1, kind, 16384)
+            ctx.search_ivm(ub0 + 1, 1, kind, 4096)
             t = time.perf_counter()
-            r = ctx.search_ivm(ub0 + 1, 0, kind, 16384)
+            r = ctx.search_ivm(ub0 + 1, 0, kind, 4096)
             t_all += time.perf_counter() - t
             assert r["proven"] and r["found"] and r["best"] == ref[seed], ("ivm", kind_name, seed)
             nodes += r["nodes"]
@@ -373,7 +373,7 @@ def search_summary(args, with_cpu=True):
                         "seeds 1..8, incumbent NEH+1, 65536 nodes per step; optima equal "
                         "the oracle's", lb1=tot["LB1"], lb2=tot["LB2_FULL"],
                lb2_heuristic_threads_8=tot["LB2_FULL+heuristic"],
-               ivm_16384_lb1=tot["ivm_LB1"], ivm_16384_lb2=tot["ivm_LB2_FULL"], instances=rows)
+               ivm_4096_lb1=tot["ivm_LB1"], ivm_4096_lb2=tot["ivm_LB2_FULL"], instances=rows)
     if with_cpu:
         cpu = {}
         for name, kind, threads in (("lb1_1core", oracle.LB1, 1), ("lb1_all", oracle.LB1, cores),

@@ -137,6 +137,8 @@ struct IvmCtl {
   double len_sum;  // interval lengths of the busy explorers (stealing phases)
   int busy;        // busy explorers (stealing phases)
   int newbest;
+  int last_batch;  // rows of the last finished step
+  int pad1;
 };
 
 struct IvmState {
@@ -381,15 +383,6 @@ __device__ void ivm_branch_row(const IvmState &S, IvmCtl *c, int b) {
   // an initializing explorer keeps V[L], the start's digit
 }
 
-__global__ void k_ivm_step_begin(IvmCtl *c) {
-  c->batch = 0;
-  c->ub_step = c->ub;
-  c->step_best = ~0ull;
-  c->steps += 1;
-  c->len_sum = 0.0;
-  c->busy = 0;
-}
-
 // Length E - V of explorer k's interval as a double (the digits of the
 // difference are produced from the least significant one up and summed with
 // their weights, so no digit array is kept).
@@ -479,12 +472,12 @@ __global__ void __launch_bounds__(1024) k_ivm_balance(IvmState S, double min_len
       if (t == 0) c->newbest = 1;
     }
   }
-  if (!ivm_balancing(S, every)) return;
   const int busy = c->busy;
-  if (busy == 0) return;  // uniform: nothing to steal
-  const double avg = c->len_sum / busy;
+  const double avg = busy ? c->len_sum / busy : 0.0;
   long long steals = 0;
-  for (int i = 0; i < S.d; ++i) {
+  // uniform: a stealing step with a busy explorer
+  const int rounds = ivm_balancing(S, every) && busy > 0 ? S.d : 0;
+  for (int i = 0; i < rounds; ++i) {
     for (int j = 1; j <= 3; ++j) {
       for (int e = t; e < K; e += T) {
         if (S.st[e] != kIvmEmpty) continue;
@@ -536,6 +529,16 @@ __global__ void __launch_bounds__(1024) k_ivm_balance(IvmState S, double min_len
   for (int o = 32; o >= 1; o >>= 1) steals += __shfl_xor(steals, o, 64);
   if ((t & 63) == 0 && steals)
     atomicAdd((unsigned long long *)&c->steals, (unsigned long long)steals);
+  __syncthreads();  // every read of the control block above is done
+  if (t == 0) {     // the next step's start
+    c->last_batch = c->batch;
+    c->batch = 0;
+    c->ub_step = c->ub;
+    c->step_best = ~0ull;
+    c->steps += 1;
+    c->len_sum = 0.0;
+    c->busy = 0;
+  }
 }
 
 static IvmState *ivm_alloc(Ctx *c, int K) {
@@ -617,6 +620,7 @@ __global__ void k_ivm_init(IvmCtl *c, int ub0) {
   c->ub = ub0;
   c->ub_step = ub0;
   c->step_best = ~0ull;
+  c->steps = 1;  // the number of the step under way
 }
 
 }  // namespace pfsp
@@ -646,6 +650,14 @@ extern "C" int pfsp_search_ivm(pfsp_ctx *h, int32_t ub0, int64_t budget_nodes, i
   IvmState *S = ivm_alloc(c, K);
   if (!S) return set_err(c, PFSP_ENOMEM, "IVM buffers do not fit in device memory");
   S->d = d;
+  // pools of fewer than 32768 rows: one full-scan LB2 launch costs less than
+  // the depth split's second one (the option is restored on return)
+  struct DeepGuard {
+    Ctx *c;
+    int64_t v;
+    ~DeepGuard() { c->deep_r = v; }
+  } dguard{c, c->deep_r};
+  if (K < 32768) c->deep_r = 0;
   struct Guard {
     IvmState *S;
     ~Guard() { ivm_free(S); }
@@ -683,7 +695,6 @@ extern "C" int pfsp_search_ivm(pfsp_ctx *h, int32_t ub0, int64_t budget_nodes, i
   // one step as a HIP graph (all sizes come from the control block), replayed
   // poll_every times between reads of the control block
   auto enqueue = [&]() -> int {
-    hipLaunchKernelGGL(k_ivm_step_begin, dim3(1), dim3(1), 0, S->stream, S->ctl);
     hipLaunchKernelGGL(k_ivm_select, dim3(g), dim3(256), 0, S->stream, *S);
     const int r = launch_bound(c, pool, lb_kind, 0, S->out_lb, S->out_prune, S->stream);
     if (r) return r;
@@ -726,7 +737,7 @@ extern "C" int pfsp_search_ivm(pfsp_ctx *h, int32_t ub0, int64_t budget_nodes, i
                                S->stream));
     PFSP_HIP(c, hipStreamSynchronize(S->stream));
     const IvmCtl hc = *S->ctl_host;
-    if (hc.batch == 0) break;  // every explorer is empty: the tree is exhausted
+    if (hc.last_batch == 0) break;  // every explorer is empty: the tree is exhausted
     if (budget_nodes > 0 && hc.nodes >= budget_nodes) {
       status = PFSP_BUDGET;
       break;
@@ -737,7 +748,7 @@ extern "C" int pfsp_search_ivm(pfsp_ctx *h, int32_t ub0, int64_t budget_nodes, i
   res->found = hc.ub < ub0;
   res->best_cmax = res->found ? hc.ub : ub0;
   res->proven = status == PFSP_OK;
-  res->steps = (int)hc.steps;
+  res->steps = (int)hc.steps - 1;
   res->nodes_decomposed = hc.nodes;
   res->children_bounded = hc.children;
   res->max_pool = K;

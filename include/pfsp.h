@@ -413,8 +413,11 @@ int pfsp_selector_targets(pfsp_ctx *c, const pfsp_pool *pool, const int16_t *arg
 /* One training step on DEVICE x[rows][64] and targets[rows][190]: mean soft-
  * target cross-entropy over rows with a non-empty target (masked softmax over
  * present pairs), gradients by backpropagation through the bf16-rounded
- * weights, then one Adam step (beta 0.9/0.999, eps 1e-8) of size lr on the
- * master parameters if lr > 0.  *loss_out (HOST, may be NULL) receives the loss
+ * weights (forward and backward passes and the weight gradients as bf16
+ * matrix-core products with fp32 sums, activations and errors entering as
+ * bf16 hi + lo pairs; the gradient sums over the rows run in a fixed order),
+ * then one Adam step (beta 0.9/0.999, eps 1e-8) of size lr on the master
+ * parameters if lr > 0.  *loss_out (HOST, may be NULL) receives the loss
  * before the update; grad_out (DEVICE [20670], may be NULL) the gradient.
  * Synchronous. */
 int pfsp_selector_train_step(pfsp_ctx *c, const float *x, const float *target, int32_t rows,

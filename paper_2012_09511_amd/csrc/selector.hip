@@ -49,6 +49,9 @@ struct Selector {
   // training workspaces
   float *h1 = nullptr, *h2 = nullptr, *ds = nullptr, *dh1 = nullptr, *dh2 = nullptr,
         *rowloss = nullptr, *loss = nullptr;
+  float *part = nullptr;    // weight-gradient partials [row ranges][parameters]
+  int *nvalid = nullptr;    // [1] rows of a training batch with a target
+  uint4 *bopsT = nullptr;   // W2, W3 transposed as bf16 MFMA B operands (training)
   size_t train_cap = 0;
   int *to_inst = nullptr;  // [190]: instance pair index of each layout pair, -1 if absent
   int to_inst_m = -1;
@@ -667,121 +670,347 @@ __global__ void k_targets(DevInst I, DevPool pool, const int16_t *__restrict__ a
     }
 }
 
-// Training, phase 1 (one thread per row): forward pass, soft-target
-// cross-entropy, and the backpropagated row errors ds = (softmax - t)/B,
-// dh2, dh1.  Rows whose target is all zero are ignored.
-__global__ void __launch_bounds__(256)
-k_train_rows(const float *__restrict__ wq, const float *__restrict__ x,
-             const float *__restrict__ target, int B, int nvalid,
-             const int *__restrict__ to_inst, float *__restrict__ H1, float *__restrict__ H2,
-             float *__restrict__ DS, float *__restrict__ DH1, float *__restrict__ DH2,
-             float *__restrict__ rowloss) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= B) return;
-  const float *xi = x + (size_t)i * kIn;
-  const float *ti = target + (size_t)i * kOut;
-  float h1[kHid], h2[kHid];
+// ------------------------------------------------------ training on MFMA
+// One training step runs the forward and backward passes of 16 rows per
+// wave on v_mfma_f32_16x16x32_bf16 with the operand layout of k_infer_bf
+// (activations and errors as bf16 hi + lo pairs, weights as their bf16
+// values), then the weight gradients as tiled products over the batch rows
+// on the same instruction (both operands as hi + lo pairs, three products per
+// step), summed over row ranges in a fixed order.
+//
+// Backward B operands: W2 and W3 transposed (tile t, column c = input unit
+// 4c + t, k = output unit), so that the errors of a layer's inputs, dOut W,
+// come out in the layout of the forward layers.
+constexpr int kTOpW2 = 0;                        // 4 tiles x 2 k-steps x 64 lanes
+constexpr int kTOpW3 = kQT1 * 2 * 64;            // 4 tiles x 6 k-steps x 64 lanes
+constexpr int kTOps = kTOpW3 + kQT1 * 6 * 64;
+constexpr int kTDRow = 2 * 192 * 2 + 16;         // bytes per LDS row of output errors
+constexpr int kTDLo = 384;                       // byte offset of their lo half
+constexpr size_t kTWaveLds = 2 * kQRows * kBRowStride + kQRows * kTDRow;
+constexpr int kTTiles = 16 + 16 + 48;            // 16 x 16 weight-gradient tiles: W1, W2, W3
+constexpr int kTRowsPerSplit = 256;              // batch rows per weight-gradient partial
+
+__global__ void k_pack_bf16t(const float *__restrict__ wq, uint4 *__restrict__ ops) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= kTOps) return;
+  const int lane = e & 63, c = lane & 15, k0 = 8 * (lane >> 4);
+  int t, ks, off, nout;
+  if (e < kTOpW3) {
+    const int idx = e >> 6;
+    t = idx >> 1;
+    ks = idx & 1;
+    off = kOffW2;
+    nout = kHid;
+  } else {
+    const int idx = (e - kTOpW3) >> 6;
+    t = idx / 6;
+    ks = idx - 6 * t;
+    off = kOffW3;
+    nout = kOut;
+  }
+  const int j = 4 * c + t;
+  uint32_t h[8];
 #pragma unroll
-  for (int o = 0; o < kHid; ++o) h1[o] = wq[kOffB1 + o];
-  for (int j = 0; j < kIn; ++j) {
-    const float xj = xi[j];
+  for (int i = 0; i < 8; ++i) {
+    const int o = 32 * ks + k0 + i;
+    h[i] = o < nout ? bf16_bits(wq[off + o * kHid + j]) : 0u;
+  }
+  ops[e] = make_uint4(h[0] | h[1] << 16, h[2] | h[3] << 16, h[4] | h[5] << 16,
+                      h[6] | h[7] << 16);
+}
+
+// One hidden layer of the training pass: h = relu(W in + b) into `out` (hi,
+// lo rows) and h[j][t] (row 4g + j, unit 4c + t) in registers.
+__device__ __forceinline__ void train_layer(const unsigned char *in, unsigned char *out,
+                                            const uint4 *__restrict__ ops,
+                                            const float *__restrict__ bias, int lane,
+                                            float (&h)[4][4]) {
+  const int c = lane & 15, g = lane >> 4;
+  bf16x8 ah[2], al[2];
+  bf_a(in, lane, 0, ah[0], al[0]);
+  bf_a(in, lane, 1, ah[1], al[1]);
 #pragma unroll
-    for (int o = 0; o < kHid; ++o) h1[o] = fmaf(wq[kOffW1 + o * kIn + j], xj, h1[o]);
+  for (int t = 0; t < kQT1; ++t) {
+    const f32x4 d = bf_tile(ah, al, ops + t * 2 * 64, lane);
+    const float b = bias[4 * c + t];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) h[j][t] = fmaxf(d[j] + b, 0.f);
   }
 #pragma unroll
-  for (int o = 0; o < kHid; ++o) {
-    h1[o] = fmaxf(h1[o], 0.f);
-    h2[o] = wq[kOffB2 + o];
-  }
+  for (int j = 0; j < 4; ++j) bf_store8(out + (4 * g + j) * kBRowStride, 4 * c, h[j]);
+}
+
+__device__ __forceinline__ float group16_max(float x) {
 #pragma unroll
-  for (int j = 0; j < kHid; ++j) {
+  for (int o = 8; o >= 1; o >>= 1) x = fmaxf(x, __shfl_xor(x, o, 64));
+  return x;
+}
+
+__device__ __forceinline__ float group16_sum(float x) {
 #pragma unroll
-    for (int o = 0; o < kHid; ++o) h2[o] = fmaf(wq[kOffW2 + o * kHid + j], h1[j], h2[o]);
-  }
+  for (int o = 8; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+__device__ __forceinline__ bf16x8 bf_pack8(const uint32_t (&h)[8]) {
+  return __builtin_bit_cast(bf16x8, make_uint4(h[0] | h[1] << 16, h[2] | h[3] << 16,
+                                               h[4] | h[5] << 16, h[6] | h[7] << 16));
+}
+
+// Forward pass, soft-target cross-entropy and backpropagated errors of the
+// wave's 16 rows: H1, H2 (after relu), DS = softmax - t over the instance's
+// pairs (0 for a row without target), DH2 and DH1 (masked by the relu), each
+// row's loss, and the number of rows with a target added to *nvalid (the
+// gradients are scaled by its inverse when the partials are summed).
+__global__ void __launch_bounds__(64 * kQWaves)
+k_train_fb(const float *__restrict__ x, const float *__restrict__ target, int B,
+           int *__restrict__ nvalid,
+           const uint4 *__restrict__ ops, const uint4 *__restrict__ opsT,
+           const float *__restrict__ wq, const int *__restrict__ to_inst, float *__restrict__ H1,
+           float *__restrict__ H2, float *__restrict__ DS, float *__restrict__ DH1,
+           float *__restrict__ DH2, float *__restrict__ rowloss) {
+  extern __shared__ __align__(16) unsigned char tsm[];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int base = (blockIdx.x * kQWaves + w) * kQRows;
+  if (base >= B) return;  // waves never synchronize across the block
+  unsigned char *xa = tsm + (size_t)w * kTWaveLds;
+  unsigned char *xb = xa + kQRows * kBRowStride;
+  unsigned char *dr = xb + kQRows * kBRowStride;
+  const int c = lane & 15, g = lane >> 4;
+  {  // inputs 16 (lane / 16) .. + 15 of row lane % 16
+    const int it = base + c;
+    float f[16];
 #pragma unroll
-  for (int o = 0; o < kHid; ++o) h2[o] = fmaxf(h2[o], 0.f);
-  float tsum = 0.f;
-  for (int o = 0; o < kOut; ++o) tsum += ti[o];
-  const bool use = tsum > 0.f;
-  // scores and log-sum-exp over valid pairs
-  float *dsi = DS + (size_t)i * kOut;
-  float mx = -INFINITY;
-  for (int o = 0; o < kOut; ++o) {
-    if (to_inst[o] < 0) continue;
-    float s = wq[kOffB3 + o];
+    for (int e = 0; e < 16; ++e) f[e] = 0.f;
+    if (it < B) {
+      const float4 *src = (const float4 *)(x + (size_t)it * kIn + 16 * g);
 #pragma unroll
-    for (int j = 0; j < kHid; ++j) s = fmaf(wq[kOffW3 + o * kHid + j], h2[j], s);
-    dsi[o] = s;
-    mx = fmaxf(mx, s);
-  }
-  float se = 0.f;
-  for (int o = 0; o < kOut; ++o)
-    if (to_inst[o] >= 0) se += expf(dsi[o] - mx);
-  const float lse = mx + logf(se);
-  float loss = 0.f;
-  const float scale = use ? 1.f / (float)nvalid : 0.f;
-  float dh2[kHid];
-#pragma unroll
-  for (int j = 0; j < kHid; ++j) dh2[j] = 0.f;
-  for (int o = 0; o < kOut; ++o) {
-    float d = 0.f;
-    if (to_inst[o] >= 0) {
-      const float ls = dsi[o] - lse;
-      loss -= ti[o] * ls;
-      d = (expf(ls) - ti[o]) * scale;
-#pragma unroll
-      for (int j = 0; j < kHid; ++j) dh2[j] = fmaf(wq[kOffW3 + o * kHid + j], d, dh2[j]);
+      for (int q = 0; q < 4; ++q) {
+        const float4 v = src[q];
+        f[4 * q] = v.x;
+        f[4 * q + 1] = v.y;
+        f[4 * q + 2] = v.z;
+        f[4 * q + 3] = v.w;
+      }
     }
-    dsi[o] = d;
-  }
-  rowloss[i] = use ? loss : 0.f;
-  float *h1o = H1 + (size_t)i * kHid, *h2o = H2 + (size_t)i * kHid;
-  float *d1o = DH1 + (size_t)i * kHid, *d2o = DH2 + (size_t)i * kHid;
+    unsigned char *row = xa + c * kBRowStride;
 #pragma unroll
-  for (int j = 0; j < kHid; ++j) {
-    dh2[j] = h2[j] > 0.f ? dh2[j] : 0.f;
-    h1o[j] = h1[j];
-    h2o[j] = h2[j];
-    d2o[j] = dh2[j];
+    for (int q = 0; q < 4; ++q) {
+      const float x4[4] = {f[4 * q], f[4 * q + 1], f[4 * q + 2], f[4 * q + 3]};
+      bf_store8(row, 16 * g + 4 * q, x4);
+    }
   }
-  for (int j = 0; j < kHid; ++j) {
-    float d = 0.f;
+  wave_sync();
+  float h1[4][4], h2[4][4];
+  train_layer(xa, xb, ops + kBOpB1, wq + kOffB1, lane, h1);
+  wave_sync();
+  train_layer(xb, xa, ops + kBOpB2, wq + kOffB2, lane, h2);
+  wave_sync();
 #pragma unroll
-    for (int o = 0; o < kHid; ++o) d = fmaf(wq[kOffW2 + o * kHid + j], dh2[o], d);
-    d1o[j] = h1[j] > 0.f ? d : 0.f;
+  for (int j = 0; j < 4; ++j) {
+    const int row = base + 4 * g + j;
+    if (row < B) {
+      *(float4 *)(H1 + (size_t)row * kHid + 4 * c) = make_float4(h1[j][0], h1[j][1], h1[j][2], h1[j][3]);
+      *(float4 *)(H2 + (size_t)row * kHid + 4 * c) = make_float4(h2[j][0], h2[j][1], h2[j][2], h2[j][3]);
+    }
+  }
+  // scores of pairs o = 16 t + c, rows 4 g + j
+  float sc[kQT3][4];
+  bool val[kQT3];
+  {
+    bf16x8 ah[2], al[2];
+    bf_a(xa, lane, 0, ah[0], al[0]);
+    bf_a(xa, lane, 1, ah[1], al[1]);
+#pragma unroll
+    for (int t = 0; t < kQT3; ++t) {
+      const int o = 16 * t + c;
+      val[t] = o < kOut && to_inst[o < kOut ? o : 0] >= 0;
+      const float b3 = wq[kOffB3 + (o < kOut ? o : 0)];
+      const f32x4 d = bf_tile(ah, al, ops + kBOpB3 + t * 2 * 64, lane);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) sc[t][j] = d[j] + b3;
+    }
+  }
+  // per row: log-sum-exp over the instance's pairs, target mass, loss, errors
+  float ds[kQT3][4];
+  int nv = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int row = base + 4 * g + j;
+    float mx = -INFINITY;
+#pragma unroll
+    for (int t = 0; t < kQT3; ++t)
+      if (val[t]) mx = fmaxf(mx, sc[t][j]);
+    mx = group16_max(mx);
+    float se = 0.f;
+#pragma unroll
+    for (int t = 0; t < kQT3; ++t)
+      if (val[t]) se += expf(sc[t][j] - mx);
+    const float lse = mx + logf(group16_sum(se));
+    float tv[kQT3], tsum = 0.f, loss = 0.f;
+#pragma unroll
+    for (int t = 0; t < kQT3; ++t) {
+      const int o = 16 * t + c;
+      tv[t] = row < B && o < kOut ? target[(size_t)row * kOut + o] : 0.f;
+      tsum += tv[t];
+      if (val[t]) loss -= tv[t] * (sc[t][j] - lse);
+    }
+    tsum = group16_sum(tsum);
+    loss = group16_sum(loss);
+    const float sr = tsum > 0.f ? 1.f : 0.f;
+    nv += __popcll(__ballot(c == 0 && row < B && tsum > 0.f));
+#pragma unroll
+    for (int t = 0; t < kQT3; ++t) {
+      ds[t][j] = val[t] ? (expf(sc[t][j] - lse) - tv[t]) * sr : 0.f;
+      const int o = 16 * t + c;
+      if (row < B && o < kOut) DS[(size_t)row * kOut + o] = ds[t][j];
+    }
+    if (row < B && c == 0) rowloss[row] = tsum > 0.f ? loss : 0.f;
+  }
+  if (lane == 0 && nv) atomicAdd(nvalid, nv);
+  // the errors as hi, lo rows of 192 (pairs 190, 191 are zero)
+#pragma unroll
+  for (int t = 0; t < kQT3; ++t)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      unsigned char *row = dr + (4 * g + j) * kTDRow + 2 * (16 * t + c);
+      const float hv = bf16r(ds[t][j]);
+      *(unsigned short *)row = (unsigned short)(__float_as_uint(hv) >> 16);
+      *(unsigned short *)(row + kTDLo) = (unsigned short)bf16_bits(ds[t][j] - hv);
+    }
+  wave_sync();
+  // DH2 = DS W3, masked by the relu of H2
+  float dh2[4][4];
+  {
+    bf16x8 ah[6], al[6];
+#pragma unroll
+    for (int ks = 0; ks < 6; ++ks) {
+      const unsigned char *row = dr + c * kTDRow + 2 * (32 * ks + 8 * g);
+      ah[ks] = *(const bf16x8 *)row;
+      al[ks] = *(const bf16x8 *)(row + kTDLo);
+    }
+#pragma unroll
+    for (int t = 0; t < kQT1; ++t) {
+      f32x4 d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < 6; ++ks) {
+        const bf16x8 b = __builtin_bit_cast(bf16x8, opsT[kTOpW3 + (t * 6 + ks) * 64 + lane]);
+        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[ks], b, d, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[ks], b, d, 0, 0, 0);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) dh2[j][t] = h2[j][t] > 0.f ? d[j] : 0.f;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int row = base + 4 * g + j;
+    if (row < B)
+      *(float4 *)(DH2 + (size_t)row * kHid + 4 * c) =
+          make_float4(dh2[j][0], dh2[j][1], dh2[j][2], dh2[j][3]);
+    bf_store8(xb + (4 * g + j) * kBRowStride, 4 * c, dh2[j]);
+  }
+  wave_sync();
+  // DH1 = DH2 W2, masked by the relu of H1
+  {
+    bf16x8 ah[2], al[2];
+    bf_a(xb, lane, 0, ah[0], al[0]);
+    bf_a(xb, lane, 1, ah[1], al[1]);
+    float dh1[4][4];
+#pragma unroll
+    for (int t = 0; t < kQT1; ++t) {
+      const f32x4 d = bf_tile(ah, al, opsT + kTOpW2 + t * 2 * 64, lane);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) dh1[j][t] = h1[j][t] > 0.f ? d[j] : 0.f;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = base + 4 * g + j;
+      if (row < B)
+        *(float4 *)(DH1 + (size_t)row * kHid + 4 * c) =
+            make_float4(dh1[j][0], dh1[j][1], dh1[j][2], dh1[j][3]);
+    }
   }
 }
 
-// Training, phase 2 (one thread per parameter): weight gradients as sums over
-// the batch rows in row order (deterministic), bias gradients as row sums.
-__global__ void k_train_wgrad(const float *__restrict__ x, const float *__restrict__ H1,
-                              const float *__restrict__ H2, const float *__restrict__ DS,
-                              const float *__restrict__ DH1, const float *__restrict__ DH2, int B,
-                              float *__restrict__ grad) {
+// Weight and bias gradients over one range of kTRowsPerSplit batch rows:
+// wave (tile, split) computes the 16 x 16 tile of dW = sum over rows of
+// D[r][u] A[r][v] (u output unit, v input unit; W1: DH1 and X, W2: DH2 and
+// H1, W3: DS and H2), and the tiles of the first input units also the bias
+// gradients sum over rows of D[r][u].  part[split][parameter].
+__global__ void __launch_bounds__(256)
+k_train_wgrad(const float *__restrict__ x, const float *__restrict__ H1,
+              const float *__restrict__ H2, const float *__restrict__ DS,
+              const float *__restrict__ DH1, const float *__restrict__ DH2, int B,
+              float *__restrict__ part) {
+  const int wv = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int tile = wv % kTTiles, split = wv / kTTiles;
+  const int r0 = split * kTRowsPerSplit, r1 = min(B, r0 + kTRowsPerSplit);
+  if (r0 >= B) return;  // uniform per wave
+  const float *Dm, *Am;
+  int dstride, woff, boff, nout, to, tj;
+  if (tile < 16) {
+    Dm = DH1; Am = x; dstride = kHid; woff = kOffW1; boff = kOffB1; nout = kHid;
+    to = tile >> 2; tj = tile & 3;
+  } else if (tile < 32) {
+    Dm = DH2; Am = H1; dstride = kHid; woff = kOffW2; boff = kOffB2; nout = kHid;
+    to = (tile - 16) >> 2; tj = (tile - 16) & 3;
+  } else {
+    Dm = DS; Am = H2; dstride = kOut; woff = kOffW3; boff = kOffB3; nout = kOut;
+    to = (tile - 32) >> 2; tj = (tile - 32) & 3;
+  }
+  const int i = lane & 15, kg = lane >> 4;
+  const int u = 16 * to + i, v = 16 * tj + i;
+  const bool uok = u < nout;
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  float bsum = 0.f;
+  for (int rk = r0; rk < r1; rk += 32) {
+    float a[8], b[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int r = rk + 8 * kg + e;
+      const bool ok = r < r1;
+      a[e] = ok && uok ? Dm[(size_t)r * dstride + u] : 0.f;
+      b[e] = ok ? Am[(size_t)r * kHid + v] : 0.f;
+    }
+    uint32_t ahb[8], alb[8], bhb[8], blb[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      bsum += a[e];
+      const float ah = bf16r(a[e]), bh = bf16r(b[e]);
+      ahb[e] = __float_as_uint(ah) >> 16;
+      alb[e] = bf16_bits(a[e] - ah);
+      bhb[e] = __float_as_uint(bh) >> 16;
+      blb[e] = bf16_bits(b[e] - bh);
+    }
+    const bf16x8 Ah = bf_pack8(ahb), Al = bf_pack8(alb), Bh = bf_pack8(bhb), Bl = bf_pack8(blb);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Bh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, Bl, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, Bh, acc, 0, 0, 0);
+  }
+  float *pp = part + (size_t)split * kParams;
+  // D register j: output unit 16 to + 4 kg + j, input unit 16 tj + i
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int uo = 16 * to + 4 * kg + j;
+    if (uo < nout) pp[woff + uo * kHid + 16 * tj + i] = acc[j];
+  }
+  if (tj == 0) {  // bias: the four row groups of output unit u
+    bsum += __shfl_xor(bsum, 16, 64);
+    bsum += __shfl_xor(bsum, 32, 64);
+    if (kg == 0 && uok) pp[boff + u] = bsum;
+  }
+}
+
+// grad = the row-range partials summed in range order, over the rows with
+// a target (at least one).
+__global__ void k_train_reduce(const float *__restrict__ part, int splits,
+                               const int *__restrict__ nvalid, float *__restrict__ grad) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= kParams) return;
-  const float *D, *A;
-  int dstride, astride, o, j = -1;
-  if (p < kOffB1) {
-    o = p / kIn; j = p % kIn; D = DH1; dstride = kHid; A = x; astride = kIn;
-  } else if (p < kOffW2) {
-    o = p - kOffB1; D = DH1; dstride = kHid; A = nullptr; astride = 0;
-  } else if (p < kOffB2) {
-    o = (p - kOffW2) / kHid; j = (p - kOffW2) % kHid; D = DH2; dstride = kHid; A = H1; astride = kHid;
-  } else if (p < kOffW3) {
-    o = p - kOffB2; D = DH2; dstride = kHid; A = nullptr; astride = 0;
-  } else if (p < kOffB3) {
-    o = (p - kOffW3) / kHid; j = (p - kOffW3) % kHid; D = DS; dstride = kOut; A = H2; astride = kHid;
-  } else {
-    o = p - kOffB3; D = DS; dstride = kOut; A = nullptr; astride = 0;
-  }
   float g = 0.f;
-  if (j >= 0) {
-    for (int r = 0; r < B; ++r) g = fmaf(D[(size_t)r * dstride + o], A[(size_t)r * astride + j], g);
-  } else {
-    for (int r = 0; r < B; ++r) g += D[(size_t)r * dstride + o];
-  }
-  grad[p] = g;
+  for (int s = 0; s < splits; ++s) g += part[(size_t)s * kParams + p];
+  grad[p] = g / (float)max(1, *nvalid);
 }
 
 __global__ void k_sum(const float *__restrict__ v, int B, float *__restrict__ out) {
@@ -836,7 +1065,8 @@ void selector_free(Ctx *c) {
   if (!S) return;
   void *bufs[] = {S->master, S->wq, S->grad, S->am, S->av, S->feat, S->scores, S->mask, S->h1,
                   S->h2, S->ds, S->dh1, S->dh2, S->rowloss, S->loss, S->to_inst, S->qops,
-                  S->qbias, S->reopen, S->reopen_count, S->bops};
+                  S->qbias, S->reopen, S->reopen_count, S->bops, S->part, S->bopsT,
+                  S->nvalid};
   for (void *p : bufs) (void)hipFree(p);
   delete S;
   c->sel = nullptr;
@@ -1284,36 +1514,37 @@ int pfsp_selector_train_step(pfsp_ctx *h, const float *x, const float *target, i
   PFSP_HIP(c, hipSetDevice(c->device));
   if ((size_t)rows > S->train_cap) {
     PFSP_HIP(c, hipStreamSynchronize(c->stream));
-    for (float **p : {&S->h1, &S->h2, &S->ds, &S->dh1, &S->dh2, &S->rowloss}) {
+    for (float **p : {&S->h1, &S->h2, &S->ds, &S->dh1, &S->dh2, &S->rowloss, &S->part}) {
       (void)hipFree(*p);
       *p = nullptr;
     }
+    const size_t splits = ((size_t)rows + kTRowsPerSplit - 1) / kTRowsPerSplit;
     bool ok = hipMalloc(&S->h1, (size_t)rows * kHid * 4) == hipSuccess &&
               hipMalloc(&S->h2, (size_t)rows * kHid * 4) == hipSuccess &&
               hipMalloc(&S->dh1, (size_t)rows * kHid * 4) == hipSuccess &&
               hipMalloc(&S->dh2, (size_t)rows * kHid * 4) == hipSuccess &&
               hipMalloc(&S->ds, (size_t)rows * kOut * 4) == hipSuccess &&
-              hipMalloc(&S->rowloss, (size_t)rows * 4) == hipSuccess;
+              hipMalloc(&S->rowloss, (size_t)rows * 4) == hipSuccess &&
+              hipMalloc(&S->part, splits * kParams * 4) == hipSuccess;
+    if (ok && !S->bopsT) ok = hipMalloc(&S->bopsT, kTOps * sizeof(uint4)) == hipSuccess;
+    if (ok && !S->nvalid) ok = hipMalloc(&S->nvalid, sizeof(int)) == hipSuccess;
     if (!ok) return set_err(c, PFSP_ENOMEM, "training workspace allocation failed");
     S->train_cap = rows;
   }
-  // number of rows with a non-empty target (the mean runs over those)
-  std::vector<float> th((size_t)rows * kOut);
-  PFSP_HIP(c, hipStreamSynchronize(c->stream));
-  PFSP_HIP(c, hipMemcpy(th.data(), target, th.size() * 4, hipMemcpyDeviceToHost));
-  int nvalid = 0;
-  for (int i = 0; i < rows; ++i) {
-    float s = 0.f;
-    for (int o = 0; o < kOut; ++o) s += th[(size_t)i * kOut + o];
-    nvalid += s > 0.f;
-  }
-  if (nvalid == 0) nvalid = 1;
+  // the mean runs over the rows with a non-empty target (counted on the device)
   hipStream_t s = c->stream;
-  hipLaunchKernelGGL(k_train_rows, dim3((rows + 255) / 256), dim3(256), 0, s, S->wq, x, target,
-                     (int)rows, nvalid, S->to_inst, S->h1, S->h2, S->ds, S->dh1, S->dh2,
-                     S->rowloss);
-  hipLaunchKernelGGL(k_train_wgrad, dim3((kParams + 255) / 256), dim3(256), 0, s, x, S->h1, S->h2,
-                     S->ds, S->dh1, S->dh2, (int)rows, S->grad);
+  const int splits = (rows + kTRowsPerSplit - 1) / kTRowsPerSplit;
+  int *nvalid_dev = S->nvalid;
+  hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, nvalid_dev);
+  hipLaunchKernelGGL(k_pack_bf16t, dim3((kTOps + 255) / 256), dim3(256), 0, s, S->wq, S->bopsT);
+  hipLaunchKernelGGL(k_train_fb, dim3((rows + kQRows * kQWaves - 1) / (kQRows * kQWaves)),
+                     dim3(64 * kQWaves), kQWaves * kTWaveLds, s, x, target, (int)rows,
+                     nvalid_dev, S->bops, S->bopsT, S->wq, S->to_inst, S->h1, S->h2, S->ds,
+                     S->dh1, S->dh2, S->rowloss);
+  hipLaunchKernelGGL(k_train_wgrad, dim3((kTTiles * splits + 3) / 4), dim3(256), 0, s, x, S->h1,
+                     S->h2, S->ds, S->dh1, S->dh2, (int)rows, S->part);
+  hipLaunchKernelGGL(k_train_reduce, dim3((kParams + 255) / 256), dim3(256), 0, s, S->part,
+                     splits, nvalid_dev, S->grad);
   hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, S->rowloss, (int)rows, S->loss);
   PFSP_HIP(c, hipGetLastError());
   if (grad_out)
@@ -1330,9 +1561,11 @@ int pfsp_selector_train_step(pfsp_ctx *h, const float *x, const float *target, i
     PFSP_HIP(c, hipGetLastError());
   }
   float l = 0.f;
+  int nvalid = 0;
   PFSP_HIP(c, hipMemcpyAsync(&l, S->loss, 4, hipMemcpyDeviceToHost, s));
+  PFSP_HIP(c, hipMemcpyAsync(&nvalid, nvalid_dev, 4, hipMemcpyDeviceToHost, s));
   PFSP_HIP(c, hipStreamSynchronize(s));
-  if (loss_out) *loss_out = l / (float)nvalid;
+  if (loss_out) *loss_out = l / (float)std::max(1, nvalid);
   return PFSP_OK;
 }
 

@@ -162,6 +162,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--workload", default="bound", choices=["bound", "search", "multi", "learned"])
+    ap.add_argument("--no-tune", action="store_true",
+                    help="multi workload: default shapes only, no autotuner (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the bounding path has no multi-GPU mode in this "
@@ -442,16 +444,20 @@ def bench_multi(args):
 
     run(args.warmup)
     default_s = run(args.steps)
-    rep = mt.autotune(perm, d1, d2, seg, ub, binding.LB2_FULL, out=out_bufs, reps=2)
-    run(args.warmup)
-    tuned_s = run(args.steps)
+    if args.no_tune:
+        rep, tuned_s = None, default_s
+    else:
+        rep = mt.autotune(perm, d1, d2, seg, ub, binding.LB2_FULL, out=out_bufs, reps=2)
+        run(args.warmup)
+        tuned_s = run(args.steps)
     d1h, d2h = d1.cpu().numpy(), d2.cpu().numpy()
     ops = sum(alg_ops_lb2(n, m, d1h[seg[k]:seg[k + 1]], d2h[seg[k]:seg[k + 1]])
               for k, (n, m, _) in enumerate(insts))
     roof = dict(bound="alu", achieved=ops / tuned_s / 1e12, peak=PEAK_INT32_OPS / 1e12,
                 unit="TOP/s", frac=ops / tuned_s / PEAK_INT32_OPS, traffic=None,
                 kernel="whole graph launch (costs + every class kernel)",
-                alg_ops_per_launch=ops, op_count="P*(n+32(n-d)) per parent, summed")
+                alg_ops_per_launch=ops,
+                op_count="11 r P + 8 r m per parent (r jobs left, P pairs), summed: alg_ops_lb2")
     out = dict(metric="children bounded/sec (LB2), 64 mixed instances, one graph launch",
                value=children / tuned_s, unit="children/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=tuned_s * 1e3, higher_is_better=True,

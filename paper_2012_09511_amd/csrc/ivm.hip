@@ -453,16 +453,24 @@ __global__ void __launch_bounds__(256) k_ivm_branch(IvmState S, int every) {
 }
 
 // The step's best leaf, then the stealing phase's second part (one block):
-// in 3d rounds (digit i of the
-// index lowered by j = 1, 2, 3, mod 4) every empty explorer e tries the
-// neighbour v and takes the right half of v's interval if v is busy, nobody
-// took from v in this phase, and v's interval is longer than the mean and
-// than min_len.  The thief's V row holds the midpoint computation.
-__global__ void __launch_bounds__(1024) k_ivm_balance(IvmState S, double min_len, int every) {
-  // per thread: the victim's position and interval end (digit L at [L][t])
-  __shared__ uint8_t sA[kIvmMaxN * 1024], sB[kIvmMaxN * 1024];
+// in 3d rounds (digit i of the index lowered by j = 1, 2, 3, mod 4) every
+// empty explorer e tries the neighbour v and takes the right half of v's
+// interval if v is busy, nobody took from v in this phase, and v's interval
+// is longer than the mean and than min_len.  SH (K <= kIvmBalLds): the busy
+// flags, lengths and victim flags of the phase sit in LDS.  Each thread
+// stages its victim's digits in LDS for the midpoint.  Last, the control
+// block is reset for the next step.
+constexpr int kIvmBalThreads = 1024, kIvmBalLds = 4096;
+template <bool SH>
+__global__ void __launch_bounds__(kIvmBalThreads) k_ivm_balance(IvmState S, double min_len,
+                                                                int every) {
+  constexpr int T = kIvmBalThreads;
+  __shared__ uint8_t sA[kIvmMaxN * T], sB[kIvmMaxN * T];
+  __shared__ uint8_t sBusy[SH ? kIvmBalLds : 1];
+  __shared__ float sLen[SH ? kIvmBalLds : 1];
+  __shared__ uint32_t sTaken[SH ? kIvmBalLds / 32 : 1];
   IvmCtl *c = S.ctl;
-  const int K = S.K, n = S.n, T = blockDim.x, t = threadIdx.x;
+  const int K = S.K, n = S.n, t = threadIdx.x;
   {  // the step's best leaf: its schedule (a one-job parent's only child is
      // its own row) and the flag for the host
     const unsigned long long sb = c->step_best;
@@ -477,50 +485,65 @@ __global__ void __launch_bounds__(1024) k_ivm_balance(IvmState S, double min_len
   long long steals = 0;
   // uniform: a stealing step with a busy explorer
   const int rounds = ivm_balancing(S, every) && busy > 0 ? S.d : 0;
+  if (SH && rounds) {
+    for (int k = t; k < K; k += T) {
+      sBusy[k] = S.st[k] != kIvmEmpty;
+      sLen[k] = (float)S.len[k];
+    }
+    for (int x = t; x < (K + 31) / 32; x += T) sTaken[x] = 0u;
+    __syncthreads();
+  }
   for (int i = 0; i < rounds; ++i) {
     for (int j = 1; j <= 3; ++j) {
       for (int e = t; e < K; e += T) {
-        if (S.st[e] != kIvmEmpty) continue;
+        if (SH ? sBusy[e] != 0 : S.st[e] != kIvmEmpty) continue;
         const int dig = (e >> (2 * i)) & 3;
         const int v = e - (dig << (2 * i)) + (((dig - j) & 3) << (2 * i));
-        if (v == e || S.st[v] == kIvmEmpty || S.len[v] <= avg || S.len[v] < min_len) continue;
-        if (atomicCAS(&S.taken[v], 0, 1) != 0) continue;
+        if (v == e) continue;
+        if (SH) {
+          if (!sBusy[v] || sLen[v] <= avg || sLen[v] < min_len) continue;
+          const uint32_t bit = 1u << (v & 31);
+          if (atomicOr(&sTaken[v >> 5], bit) & bit) continue;
+        } else {
+          if (S.st[v] == kIvmEmpty || S.len[v] <= avg || S.len[v] < min_len) continue;
+          if (atomicCAS(&S.taken[v], 0, 1) != 0) continue;
+        }
         uint8_t *__restrict__ Vv = S.V + (size_t)v * n;
         uint8_t *__restrict__ Ev = S.E + (size_t)v * n;
         uint8_t *__restrict__ Ve = S.V + (size_t)e * n;
         uint8_t *__restrict__ Ee = S.E + (size_t)e * n;
         for (int L = 0; L < n; ++L) {
-          sA[L * 1024 + t] = Vv[L];
-          sB[L * 1024 + t] = Ev[L];
+          sA[L * T + t] = Vv[L];
+          sB[L * T + t] = Ev[L];
         }
         // mid = Vv + (Ev - Vv) / 2 < Ev, in sB: difference, half, sum
         int borrow = 0;
         for (int L = n - 1; L >= 0; --L) {
-          int x = (int)sB[L * 1024 + t] - (int)sA[L * 1024 + t] - borrow;
+          int x = (int)sB[L * T + t] - (int)sA[L * T + t] - borrow;
           borrow = x < 0;
           if (borrow) x += n - L;
-          Ee[L] = sB[L * 1024 + t];  // the thief's end: the victim's old end
-          sB[L * 1024 + t] = (uint8_t)x;
+          Ee[L] = sB[L * T + t];  // the thief's end: the victim's old end
+          sB[L * T + t] = (uint8_t)x;
         }
         int rem = S.Etop[v] - borrow;
         for (int L = 0; L < n; ++L) {
-          const int x = sB[L * 1024 + t] + rem * (n - L);
-          sB[L * 1024 + t] = (uint8_t)(x >> 1);
+          const int x = sB[L * T + t] + rem * (n - L);
+          sB[L * T + t] = (uint8_t)(x >> 1);
           rem = x & 1;
         }
         int carry = 0;
         for (int L = n - 1; L >= 0; --L) {
-          int x = sA[L * 1024 + t] + sB[L * 1024 + t] + carry;
+          int x = sA[L * T + t] + sB[L * T + t] + carry;
           carry = x >= n - L;
           if (carry) x -= n - L;
           Ve[L] = (uint8_t)x;
           Ev[L] = (uint8_t)x;
         }
-        const int mtop = carry;
         S.Etop[e] = S.Etop[v];
-        S.Etop[v] = (uint8_t)mtop;
+        S.Etop[v] = (uint8_t)carry;
         S.st[e] = kIvmRoot;
         S.lev[e] = -1;
+        if (SH) sBusy[e] = 1;  // a thief is no victim in this phase (its length stays 0)
         ++steals;
       }
       __syncthreads();  // the next round sees this round's thieves and victims
@@ -699,7 +722,12 @@ extern "C" int pfsp_search_ivm(pfsp_ctx *h, int32_t ub0, int64_t budget_nodes, i
     const int r = launch_bound(c, pool, lb_kind, 0, S->out_lb, S->out_prune, S->stream);
     if (r) return r;
     hipLaunchKernelGGL(k_ivm_branch, dim3(g), dim3(256), 0, S->stream, *S, every);
-    hipLaunchKernelGGL(k_ivm_balance, dim3(1), dim3(1024), 0, S->stream, *S, min_len, every);
+    if (K <= kIvmBalLds)
+      hipLaunchKernelGGL(k_ivm_balance<true>, dim3(1), dim3(kIvmBalThreads), 0, S->stream, *S,
+                         min_len, every);
+    else
+      hipLaunchKernelGGL(k_ivm_balance<false>, dim3(1), dim3(kIvmBalThreads), 0, S->stream, *S,
+                         min_len, every);
     PFSP_HIP(c, hipGetLastError());
     return PFSP_OK;
   };

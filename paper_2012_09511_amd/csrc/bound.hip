@@ -1066,21 +1066,23 @@ struct QuickLds {
 
 // Block-cooperative staging of one instance for the quick kernels (no
 // barrier inside).  The staged narrow entries hold x = a | b << 16 and
-// y = l | k << 24; the quick entries are {b - a, k | (a + l) << 16}: the
-// scans add b - a straight from x (no sign extension) and a + l from the
-// high half of y, and k < 32 sits in the low bits that a bit-field extract
-// takes as its offset.
-template <int NMAX, class Lds>
+// y = l | k << 24; the quick entries are {E, k | (a + l) << 16} with
+// E = b - a: the scans take a + l from the high half of y, and k < 32 sits
+// in the low bits that a bit-field extract takes as its offset.  KE (the
+// kernels with 16-bit X): x = E in its low 16 bits | k << 24, which is the
+// scan's stored word (E, row of X) as it stands, and the running sums add E
+// with a 16-bit multiply-add; else x = E as a full word.
+template <int NMAX, bool KE, class Lds>
 __device__ void lb2q_stage(const DevInst &I, int Ppad, const Lds &S) {
   const int n = I.n, m = I.m, P = I.P;
   for (int x = threadIdx.x; x < NMAX * Ppad; x += blockDim.x) {
     const int pass = x / (NMAX * 64), rem = x - pass * NMAX * 64;
     const int i = rem >> 6, pi = pass * 64 + (rem & 63);
-    uint2 e = make_uint2(0u, (unsigned)(NMAX - 1));
+    uint2 e = make_uint2(KE ? (unsigned)(NMAX - 1) << 24 : 0u, (unsigned)(NMAX - 1));
     if (i < n && P > 0) {
       const uint2 s = I.ent[(size_t)i * P + (pi < P ? pi : 0)];
       const unsigned a = s.x & 0xffffu, b = s.x >> 16, l = s.y & 0xffffffu, k = s.y >> 24;
-      e = make_uint2(b - a, k | ((a + l) << 16));
+      e = make_uint2(KE ? ((b - a) & 0xffffu) | (k << 24) : b - a, k | ((a + l) << 16));
     }
     S.ent[x] = e;
   }
@@ -1329,13 +1331,14 @@ __device__ void lb2q_parent(const DevInst &I, int Ppad, const QuickLds<NMAX> &S,
       const int term = (tt & ng) | (NEGX & ~ng);
       if constexpr (X16) {
         pt[i] = (int)__builtin_amdgcn_perm((unsigned)term, (unsigned)(Pm - (int)e.x), 0x05040100u);
-        ke[i] = __builtin_amdgcn_perm(e.y, e.x, 0x040c0100u);
+        ke[i] = e.x;
+        Y = mad_i16(ng, (int)e.x, Y);  // Y += a - b for members
       } else {
         tm[i] = term;
         pm[i] = Pm;
+        Y = __mul24(ng, (int)e.x) + Y;
       }
       Pm = max(Pm, term);
-      Y = __mul24(ng, (int)e.x) + Y;  // Y += a - b for members
     }
     // backward scan: Xa, Xb by job (the 32-bit entries are read again rather
     // than held in registers; X16 keeps a packed copy from the forward scan)
@@ -1472,7 +1475,7 @@ k_lb2q(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
   if ((int)blockIdx.x * nw >= count) return;  // no parent for this block: skip the staging
   const QuickLayout L{Ppad, I.m, X16, SUBSET};
   const QuickLds<NMAX> S(sm, L, w);
-  lb2q_stage<NMAX>(I, Ppad, S);
+  lb2q_stage<NMAX, X16>(I, Ppad, S);
   __syncthreads();
   if (pool.ub_dev) ub = *pool.ub_dev;
   const int n = I.n, m = I.m, ns = pool.n;  // ns: row stride (>= n)
@@ -1648,7 +1651,7 @@ __device__ void lb2d_parent(const DevInst &I, int Ppad, const DeepLds<NMAX> &S,
         const int slot = S.inv[e.y & 31u];
         ke[x] = (e.x & 0xffffu) | ((unsigned)slot << 24);
         Pm = max(Pm, term);
-        Y -= (int)e.x;  // Y += a - b
+        Y = mad_i16(-1, (int)e.x, Y);  // Y += a - b
       }
     }
     // backward scan: Xa (low) and Xb + K5 (high) per member, into its X row
@@ -1708,7 +1711,7 @@ k_lb2d(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
   if ((int)blockIdx.x * nw >= count) return;
   const DeepLayout L{Ppad, I.m, RMAX};
   const DeepLds<NMAX> S(sm, L, w);
-  lb2q_stage<NMAX>(I, Ppad, S);
+  lb2q_stage<NMAX, true>(I, Ppad, S);
   lb2d_stage_pos<NMAX>(I, Ppad, S.pos);
   __syncthreads();
   if (pool.ub_dev) ub = *pool.ub_dev;
@@ -1847,8 +1850,8 @@ __device__ __forceinline__ void lb2w_chunk(const uint2 *__restrict__ ec, int rem
     const int term = (tt & ng) | (NEGX & ~ng);
     pt[i] = (int)__builtin_amdgcn_perm((unsigned)term, (unsigned)(Pm - (int)e.x), 0x05040100u);
     Pm = max(Pm, term);
-    Y = __mul24(ng, (int)e.x) + Y;
-    ke[i] = __builtin_amdgcn_perm(in ? e.y : (unsigned)n, e.x, 0x040c0100u);
+    Y = mad_i16(ng, (int)e.x, Y);
+    ke[i] = in ? e.x : (e.x & 0xffffu) | ((unsigned)n << 24);
   }
   // the suffix maximum in both halves; each step leaves Xa low and the
   // suffix maximum with this term high
@@ -1981,7 +1984,7 @@ __device__ void lb2w_parent(const DevInst &I, int Ppad, const WideLds<NMAX> &S,
         const int ng = member_ng<NW>(um, e.y);
         const int tt = Y + (int)(e.y >> 16);
         Pm = max(Pm, (tt & ng) | (NEGX & ~ng));
-        Y = __mul24(ng, (int)e.x) + Y;
+        Y = mad_i16(ng, (int)e.x, Y);
       }
     }
     // second sweep, chunks from last to first (only the last can be ragged)
@@ -2390,8 +2393,8 @@ __device__ void lb2s_wave(const DevInst &I, int Ppad, const PackLds<NMAX, G> &S,
       const int term = (tt & ng) | (NEGX & ~ng);
       pt[i] = (int)__builtin_amdgcn_perm((unsigned)term, (unsigned)(Pm - (int)e.x), 0x05040100u);
       Pm = max(Pm, term);
-      Y = __mul24(ng, (int)e.x) + Y;
-      ke[i] = __builtin_amdgcn_perm(e.y, e.x, 0x040c0100u);
+      Y = mad_i16(ng, (int)e.x, Y);
+      ke[i] = e.x;
     }
     const int K5x = K5 - K4;
     int R = (int)0xC000C000u;  // NEGX in both halves
@@ -2535,7 +2538,7 @@ k_lb2s(DevInst I, DevPool pool, int ub, const int *__restrict__ costs, int *__re
   if ((int)blockIdx.x * nw * G >= count) return;  // no parent for this block
   const PackLayout L{Ppad, I.m};
   const PackLds<NMAX, G> S(sm, L, w);
-  lb2q_stage<NMAX>(I, Ppad, S);
+  lb2q_stage<NMAX, true>(I, Ppad, S);
   __syncthreads();
   if (pool.ub_dev) ub = *pool.ub_dev;
   const int step = gridDim.x * nw * G;
@@ -2662,8 +2665,8 @@ __device__ __forceinline__ void lb2ws_chunk(const uint2 *__restrict__ ec, int cn
       const int term = (tt & ng) | (NEGX & ~ng);
       pt[i] = (int)__builtin_amdgcn_perm((unsigned)term, (unsigned)(Pm - (int)e.x), 0x05040100u);
       Pm = max(Pm, term);
-      Y = __mul24(ng, (int)e.x) + Y;
-      ke[i] = __builtin_amdgcn_perm(e.y, e.x, 0x040c0100u);
+      Y = mad_i16(ng, (int)e.x, Y);
+      ke[i] = e.x;
     }
   }
   int R = (int)__builtin_amdgcn_perm((unsigned)Sm, (unsigned)Sm, 0x05040100u);
@@ -2812,7 +2815,7 @@ __device__ void lb2ws_wave(const DevInst &I, const WsLds &S, const DevPool &pool
         const int ng = __builtin_amdgcn_sbfe((int)(uint32_t)(umask >> (e.y & 63u)), 0, 1);
         const int tt = Y + (int)(e.y >> 16);
         Pm = max(Pm, (tt & ng) | (NEGX & ~ng));
-        Y = __mul24(ng, (int)e.x) + Y;
+        Y = mad_i16(ng, (int)e.x, Y);
       }
     }
     // second sweep: positions CH .. n - 1, then 0 .. CH - 1
@@ -3029,7 +3032,7 @@ k_lb2m(const DevInst *__restrict__ insts, const MultiTile *__restrict__ tiles, i
       I = insts[cur];
       Ppad = (I.P + 63) / 64 * 64;
       if constexpr (QUICK)
-        lb2q_stage<NMAX>(I, Ppad, S);
+        lb2q_stage<NMAX, X16>(I, Ppad, S);
       else
         lb2f_stage<NMAX>(I, Ppad, S);
       __syncthreads();

@@ -176,8 +176,9 @@ int stage_instance(Ctx *c);
 int stage_tables(Ctx *c, hipStream_t s, int n, int m, const int *d_p, int *d_T, uint2 *d_ent,
                  uint4 *d_entw, uint8_t *d_pu, uint8_t *d_pv, int narrow);
 // Quick-format copy of the narrow pair table for the wide kernels: entries
-// {b - a, job | (a + lag) << 16} (job < 128) in [pass][position][64 lanes]
-// order, pairs >= P repeating pair 0; allocates *d_entq.  Synchronous.
+// {(b - a) in the low 16 bits | job << 24, job | (a + lag) << 16} (job <
+// 128) in [pass][position][64 lanes] order, pairs >= P repeating pair 0;
+// allocates *d_entq.  Synchronous.
 int stage_quick(Ctx *c, hipStream_t s, int n, int m, const uint2 *d_ent, uint2 **d_entq);
 // bound.hip
 int ensure_costs(Ctx *c, int count);

@@ -100,7 +100,7 @@ __global__ void k_stage_q(int n, int P, int Ppad, const uint2 *__restrict__ ent,
   const int i = rem >> 6, pi = pass * 64 + (rem & 63);
   const uint2 s = ent[(size_t)i * P + (pi < P ? pi : 0)];
   const unsigned a = s.x & 0xffffu, b = s.x >> 16, l = s.y & 0xffffffu, k = s.y >> 24;
-  entq[x] = make_uint2(b - a, k | ((a + l) << 16));
+  entq[x] = make_uint2(((b - a) & 0xffffu) | (k << 24), k | ((a + l) << 16));
 }
 
 int stage_quick(Ctx *c, hipStream_t s, int n, int m, const uint2 *d_ent, uint2 **d_entq) {

@@ -153,6 +153,15 @@ __device__ __forceinline__ int pk_max(int x, int y) {
       int, __builtin_elementwise_max(__builtin_bit_cast(pk16, x), __builtin_bit_cast(pk16, y)));
 }
 
+// a + b * c over the low 16 bits of a and b as signed integers
+// (v_mad_i32_i16; the compiler forms it only as a sign extension and a
+// 24-bit multiply-add, two instructions).
+__device__ __forceinline__ int mad_i16(int a, int b, int c) {
+  int d;
+  asm("v_mad_i32_i16 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+  return d;
+}
+
 // pk_max with both halves of y replaced by its high half (an operand
 // selection of the instruction, not a separate move).
 __device__ __forceinline__ int pk_max_hi(int x, int y) {

@@ -257,41 +257,42 @@ k_lb1(DevInst I, DevPool pool, int ub, int *__restrict__ out_lb, uint8_t *__rest
   if (filt) filter_row(f, i, live, open, false, ns, t & 63);
 }
 
-// One parent's costs (front C1, back C2, remaining R; Eq. (1)) for n <= 32
-// and m <= MMAX, written to cs[0 .. 3m); an invalid row (not a permutation of
-// 0..n-1, or d1 + d2 >= n) sets *flag and gets cs = {-1, 0, ...}.  The row and
-// the per-machine state stay in registers; sp holds p zero-padded to MMAX
-// machines (row stride MS) so that the machine loops need no bounds.
-// *valid reports whether the row is a valid node.  With check, returns
-// whether some child (either direction) has LB1 < ub (the children's LB1 of
-// Section 2.4 from the same state; padded machines add nothing); without
-// check, returns whether the row is valid.
-template <int MMAX, int MS>
+// One parent's costs (front C1, back C2, remaining R; Eq. (1)) for n <= NJ
+// (32 or 64) and m <= MMAX, written to cs[0 .. 3m); an invalid row (not a
+// permutation of 0..n-1, or d1 + d2 >= n) sets *flag and gets cs = {-1, 0,
+// ...}.  The row and the per-machine state stay in registers; sp holds p
+// zero-padded to MMAX machines (row stride MS) so that the machine loops need
+// no bounds.  *valid reports whether the row is a valid node.  With check,
+// returns whether some child (either direction) has LB1 < ub (the children's
+// LB1 of Section 2.4 from the same state; padded machines add nothing);
+// without check, returns whether the row is valid.
+template <int MMAX, int MS, int NJ = 32>
 __device__ __forceinline__ bool costs_row(int n, int m, const int *__restrict__ sp,
                                           const int *__restrict__ sT,
                                           const uint8_t *__restrict__ row, int a, int b,
                                           int *__restrict__ cs, int *__restrict__ flag,
                                           bool check, int ub, bool *valid) {
-  uint32_t rw[8];
+  constexpr int NWD = NJ / 4;
+  uint32_t rw[NWD];
 #pragma unroll
-  for (int w = 0; w < 8; ++w) {
+  for (int w = 0; w < NWD; ++w) {
     uint32_t v = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q)
       if (4 * w + q < n) v |= (uint32_t)row[4 * w + q] << (8 * q);
     rw[w] = v;
   }
-  uint32_t seen = 0;
+  uint64_t seen = 0;
   bool bad = a + b >= n;
 #pragma unroll
-  for (int x = 0; x < 32; ++x) {
+  for (int x = 0; x < NJ; ++x) {
     if (x < n) {
       const uint32_t j = (rw[x >> 2] >> (8 * (x & 3))) & 0xffu;
-      seen |= 1u << (j & 31u);
+      seen |= 1ull << (j & 63u);
       bad |= j >= (uint32_t)n;
     }
   }
-  bad |= seen != (n == 32 ? 0xffffffffu : (1u << n) - 1u);
+  bad |= seen != (n == 64 ? ~0ull : (1ull << n) - 1ull);
   *valid = !bad;
   if (bad) {
     flag[0] = 1;
@@ -307,7 +308,7 @@ __device__ __forceinline__ bool costs_row(int n, int m, const int *__restrict__ 
     R[k] = sT[k];
   }
 #pragma unroll
-  for (int x = 0; x < 32; ++x) {  // front of sigma1
+  for (int x = 0; x < NJ; ++x) {  // front of sigma1
     if (x < a) {
       const int *pj = sp + (int)((rw[x >> 2] >> (8 * (x & 3))) & 0xffu) * MS;
       int c = 0;
@@ -321,7 +322,7 @@ __device__ __forceinline__ bool costs_row(int n, int m, const int *__restrict__ 
     }
   }
 #pragma unroll
-  for (int x = 31; x >= 0; --x) {  // back of sigma2: jobs and machines reversed
+  for (int x = NJ - 1; x >= 0; --x) {  // back of sigma2: jobs and machines reversed
     if (x < n && x >= n - b) {
       const int *pj = sp + (int)((rw[x >> 2] >> (8 * (x & 3))) & 0xffu) * MS;
       int c = 0;
@@ -345,7 +346,7 @@ __device__ __forceinline__ bool costs_row(int n, int m, const int *__restrict__ 
   if (!check) return true;
   bool open = false;
 #pragma unroll
-  for (int x = 0; x < 32; ++x) {
+  for (int x = 0; x < NJ; ++x) {
     if (x >= a && x < n - b && !open) {
       const int *pj = sp + (int)((rw[x >> 2] >> (8 * (x & 3))) & 0xffu) * MS;
       int c = 0, lf = 0;
@@ -372,7 +373,7 @@ __device__ __forceinline__ bool costs_row(int n, int m, const int *__restrict__ 
 // are contiguous in the workspace: each lane writes its row into the wave's
 // LDS tile and the wave then stores the tile with consecutive lanes on
 // consecutive words (whole cache lines rather than scattered words).
-template <int MMAX>
+template <int MMAX, int NJ = 32>
 __global__ void __launch_bounds__(256)
 k_costs(DevInst I, DevPool pool, int *__restrict__ costs, int *__restrict__ flag, CostFilter f) {
   extern __shared__ int sh[];
@@ -401,7 +402,7 @@ k_costs(DevInst I, DevPool pool, int *__restrict__ costs, int *__restrict__ flag
     if (i < count) {
       live = !filt || !f.alive || f.alive[i];
       const int a = pool.d1[i], b = pool.d2[i];
-      open = costs_row<MMAX, MS>(n, m, sp, sT, pool.perm + (size_t)i * ns, a, b,
+      open = costs_row<MMAX, MS, NJ>(n, m, sp, sT, pool.perm + (size_t)i * ns, a, b,
                                  tile + lane * RS, flag, filt && live, ub, &valid);
       open = open && valid;
       deep = n - a - b >= 1 && n - a - b <= f.deep_r;
@@ -3413,6 +3414,26 @@ int launch_costs(Ctx *c, const DevPool &pool, hipStream_t s, const CostFilter *f
                        c->d_flag, fv);                                                     \
     break;
       PFSP_C(8) PFSP_C(12) PFSP_C(16) PFSP_C(20) PFSP_C(24) PFSP_C(32)
+#undef PFSP_C
+      default: break;
+    }
+    PFSP_HIP(c, hipGetLastError());
+    return PFSP_OK;
+  }
+  if (c->n <= 64 && c->m <= 32) {  // the same with 64-job rows
+    const int mm = c->m <= 8 ? 8 : c->m <= 16 ? 16 : c->m <= 20 ? 20 : 32;
+    const size_t lds = ((size_t)c->n * (mm | 1) + mm + 4 * 64 * (3 * (size_t)c->m + 1)) * 4;
+    int grid = (pool.count + 255) / 256;
+    if (grid > c->cu_count * 8) grid = c->cu_count * 8;
+    if (grid < 1) grid = 1;
+    KTimer kt(c, s, "k_costs");
+    switch (mm) {
+#define PFSP_C(M)                                                                          \
+  case M:                                                                                  \
+    hipLaunchKernelGGL((k_costs<M, 64>), dim3(grid), dim3(256), lds, s, c->inst(), pool,    \
+                       c->d_costs, c->d_flag, fv);                                          \
+    break;
+      PFSP_C(8) PFSP_C(16) PFSP_C(20) PFSP_C(32)
 #undef PFSP_C
       default: break;
     }

@@ -535,16 +535,20 @@ def learned_summary(args):
     STATIC-FREQ16 (the 16 pairs most often attaining full LB2 among the
     children of nodes logged by this instance's FULL search).  (i) 20 x 20,
     seeds 600..607, NEH + 1 to the same proven optimum; (ii) 50 x 20, seeds
-    700..703, fixed tree.  Per-instance speedups over FULL and their geometric
-    mean; node ratios; prune-rate loss on the logged nodes."""
+    700..703, fixed tree.  On (i) also LEARNED-PURE with the same network
+    trained on 20 x 20 logs (selector_n20m20.npy) at top-32.  Per-instance
+    speedups over FULL and their geometric mean; node ratios; prune-rate loss
+    on the logged nodes."""
     import torch
     from paper_2012_09511_amd import binding, inputs, selector_quant
     ctx = binding.Context(0)
     sel = np.load(os.path.join(ROOT, "paper_2012_09511_amd", "data", "selector_n50m20.npy"),
                   allow_pickle=False)
+    # the same network trained on 20 x 20 logs, at top-32 (the 20 x 20 runs only)
+    sel20 = np.load(os.path.join(ROOT, "paper_2012_09511_amd", "data", "selector_n20m20.npy"),
+                    allow_pickle=False)
     ctx.set_option("pool_batch", 1 << 18)
     ctx.set_option("learned_topk", 16)
-    modes = ("full", "exact", "pure", "static_adj", "static_freq16")
 
     def run(kind, ub0, exact=0, budget=0):
         ctx.set_option("learned_exact", exact)
@@ -557,6 +561,9 @@ def learned_summary(args):
         return r, dt
 
     def instance_rows(n, m, seeds, ub_of, same_optimum):
+        modes = ("full", "exact", "pure", "static_adj", "static_freq16")
+        if n == 20:
+            modes += ("pure_trained20_top32",)
         rows = []
         for seed in seeds:
             p = inputs.instance(n, m, seed)
@@ -572,6 +579,14 @@ def learned_summary(args):
                     r, dt = run(binding.LB2_FULL, ub0)
                 elif mode in ("exact", "pure"):
                     r, dt = run(binding.LB2_LEARNED, ub0, exact=int(mode == "exact"))
+                elif mode == "pure_trained20_top32":
+                    ctx.selector_set(sel20)
+                    ctx.selector_set_quant(None)
+                    ctx.set_option("learned_topk", 32)
+                    r, dt = run(binding.LB2_LEARNED, ub0)
+                    ctx.set_option("learned_topk", 16)
+                    ctx.selector_set(sel)
+                    ctx.selector_set_quant(None)
                 else:
                     ctx.search_set_pairs(ctx.pair_mask(binding.PAIRS_ADJACENT)
                                          if mode == "static_adj" else freq)

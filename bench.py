@@ -263,6 +263,9 @@ def lb2_roofline(n, m, d1, d2, per_launch, deep_r):
     for k in ker:
         prof = profiled_traffic(k)
         ker[k]["traffic"] = prof["traffic_bytes"] if prof else None
+        # HBM GB/s: the counted bytes over this run's launch time
+        ker[k]["traffic_gbs"] = (prof["traffic_bytes"] / (ker[k]["ms"] * 1e-3) / 1e9
+                                 if prof else None)
         ker[k]["valu_issue_frac"] = prof["valu_issue_frac"] if prof else None
         ker[k]["valu_lane_util"] = prof.get("valu_lane_util") if prof else None
     return dict(bound="alu", achieved=ker[dom]["alg_ops"] / (ker[dom]["ms"] * 1e-3) / 1e12,
@@ -453,6 +456,33 @@ def bench_multi(args):
     d1h, d2h = d1.cpu().numpy(), d2.cpu().numpy()
     ops = sum(alg_ops_lb2(n, m, d1h[seg[k]:seg[k + 1]], d2h[seg[k]:seg[k + 1]])
               for k, (n, m, _) in enumerate(insts))
+    cpu = None
+    if not args.no_cpu:
+        # the oracle on all usable cores over the first `take` parents of every
+        # instance (the same batch, bounded to about 10 s)
+        import oracle
+        cores, nproc, model = host_cpu()
+        ph = perm.cpu().numpy()
+
+        def oracle_batch(take):
+            t_all, ch = 0.0, 0
+            for k, (n, m, p) in enumerate(insts):
+                sl = slice(seg[k], seg[k] + take)
+                t = time.perf_counter()
+                oracle.bound_children(p, np.ascontiguousarray(ph[sl, :n]), d1h[sl], d2h[sl],
+                                      oracle.LB2_FULL, binding.INT32_MAX, threads=cores)
+                t_all += time.perf_counter() - t
+                ch += int((2 * (n - d1h[sl].astype(np.int64) - d2h[sl].astype(np.int64))).sum())
+            return t_all, ch
+
+        take = 2
+        t_cpu, ch_cpu = oracle_batch(take)  # calibration, then about 10 s of work
+        if t_cpu < 10.0:
+            take = min(per, max(take, int(take * 10.0 / max(t_cpu, 1e-3))))
+            t_cpu, ch_cpu = oracle_batch(take)
+        cpu = dict(value=ch_cpu / t_cpu, unit="children/s", cores=cores, kind="oracle",
+                   sample=f"first {take} parents of each of the 64 instances ({ch_cpu} children), "
+                          f"{t_cpu:.1f} s, OpenMP over parents", nproc=nproc, cpu_model=model)
     roof = dict(bound="alu", achieved=ops / tuned_s / 1e12, peak=PEAK_INT32_OPS / 1e12,
                 unit="TOP/s", frac=ops / tuned_s / PEAK_INT32_OPS, traffic=None,
                 kernel="whole graph launch (costs + every class kernel)",
@@ -467,7 +497,7 @@ def bench_multi(args):
                            parents=int(perm.shape[0]), children=children),
                roofline=roof,
                default_shape=dict(ms=default_s * 1e3, children_per_s=children / default_s),
-               autotuned=rep)
+               autotuned=rep, cpu_baseline=cpu)
     mt.close()
     ctx.close()
     print(json.dumps(out))

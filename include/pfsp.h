@@ -202,10 +202,30 @@ int pfsp_search_resume(pfsp_ctx *c, const void *buf, int64_t size, int64_t budge
  * the kernels of pfsp_bound_children (lb_kind PFSP_LB1 or PFSP_LB2_FULL).
  * Same result and node semantics as pfsp_search (a node re-decomposed by a
  * thief on the way to its interval is not counted again); *steals (HOST, may
- * be NULL) receives the number of work units stolen.  Not resumable.
- * Synchronous. */
+ * be NULL) receives the number of work units stolen.  A search stopped on
+ * its budget can be dumped (pfsp_search_ivm_dump) and resumed.  Synchronous. */
 int pfsp_search_ivm(pfsp_ctx *c, int32_t ub0, int64_t budget_nodes, int lb_kind,
                     int32_t explorers, pfsp_result *res, int64_t *steals);
+
+/* Checkpoint of the last pfsp_search_ivm or pfsp_search_ivm_resume that
+ * stopped on its node budget (Section 4.1 checkpoints the explorers' work
+ * units; this one holds every explorer's whole state: interval, position,
+ * matrix rows, prune bits and stored bounds, so that a resumed search
+ * decomposes and counts every node once), with the incumbent, best schedule,
+ * ub0, bound kind, explorer count and counters.  Same two-call protocol as
+ * pfsp_search_dump (buf NULL: *size receives the bytes needed; PFSP_ERANGE if
+ * cap is smaller; PFSP_EINVAL if there is no such search).  About
+ * K n (5 n + 10) bytes for K explorers.  HOST buffer; synchronous. */
+int pfsp_search_ivm_dump(pfsp_ctx *c, void *buf, int64_t cap, int64_t *size);
+
+/* Continues an IVM checkpoint (HOST buf[size]) on the loaded instance
+ * (PFSP_EINVAL if it is another one or the bytes are malformed) with its
+ * explorer count, bound kind and ub0, under the current options, until the
+ * tree is exhausted or budget_nodes (counted from the first start) is
+ * reached; res and *steals count every run since the first start.
+ * Synchronous. */
+int pfsp_search_ivm_resume(pfsp_ctx *c, const void *buf, int64_t size, int64_t budget_nodes,
+                           pfsp_result *res, int64_t *steals);
 
 /* Work-unit arithmetic of the IVM search on HOST digit vectors (factorial
  * number system, Section 2.6): a position in [0, n!] is digits d[0 .. n),

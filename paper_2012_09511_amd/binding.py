@@ -29,7 +29,8 @@ EXPORTS = ["pfsp_create", "pfsp_destroy", "pfsp_last_error", "pfsp_load_instance
            "pfsp_multi_set_shape", "pfsp_multi_autotune", "pfsp_autotune",
            "pfsp_selector_set_quant", "pfsp_selector_infer", "pfsp_bound_children_noalloc",
            "pfsp_pair_mask", "pfsp_search_set_pairs", "pfsp_search_dump", "pfsp_search_resume",
-           "pfsp_search_ivm", "pfsp_factoradic", "pfsp_ivm_decode"]
+           "pfsp_search_ivm", "pfsp_search_ivm_dump", "pfsp_search_ivm_resume",
+           "pfsp_factoradic", "pfsp_ivm_decode"]
 PAIRS_ADJACENT, PAIRS_LAST = 1, 2
 SELECTOR_PARAMS = 20670
 SELECTOR_QPARAMS = 20675
@@ -85,6 +86,9 @@ def lib():
         L.pfsp_search_dump.argtypes = [vp, vp, i64, ctypes.POINTER(i64)]
         L.pfsp_search_ivm.argtypes = [vp, i32, i64, ctypes.c_int, i32, ctypes.POINTER(Result),
                                       ctypes.POINTER(i64)]
+        L.pfsp_search_ivm_dump.argtypes = [vp, vp, i64, ctypes.POINTER(i64)]
+        L.pfsp_search_ivm_resume.argtypes = [vp, vp, i64, i64, ctypes.POINTER(Result),
+                                             ctypes.POINTER(i64)]
         L.pfsp_factoradic.argtypes = [ctypes.c_int, i32, vp, i32, vp, i32, vp,
                                       ctypes.POINTER(i32)]
         L.pfsp_ivm_decode.argtypes = [i32, vp, vp, vp, i32, vp, ctypes.POINTER(i32),
@@ -292,6 +296,25 @@ class Context:
         rc = self._check(lib().pfsp_search_ivm(self.h, int(ub0), int(budget), kind,
                                                int(explorers), ctypes.byref(res),
                                                ctypes.byref(steals)))
+        out = self._result(res, perm, rc)
+        out["steals"] = steals.value
+        return out
+
+    def search_ivm_dump(self) -> bytes:
+        """Checkpoint of the last IVM search that stopped on its budget."""
+        size = ctypes.c_int64()
+        self._check(lib().pfsp_search_ivm_dump(self.h, None, 0, ctypes.byref(size)))
+        buf = ctypes.create_string_buffer(size.value)
+        self._check(lib().pfsp_search_ivm_dump(self.h, buf, size.value, ctypes.byref(size)))
+        return buf.raw[:size.value]
+
+    def search_ivm_resume(self, ckpt: bytes, budget=0):
+        perm = np.zeros(self.n, dtype=np.int32)
+        res = Result()
+        res.best_perm = perm.ctypes.data_as(ctypes.c_void_p)
+        steals = ctypes.c_int64()
+        rc = self._check(lib().pfsp_search_ivm_resume(self.h, ckpt, len(ckpt), int(budget),
+                                                      ctypes.byref(res), ctypes.byref(steals)))
         out = self._result(res, perm, rc)
         out["steals"] = steals.value
         return out

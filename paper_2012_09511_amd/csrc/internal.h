@@ -130,6 +130,7 @@ struct Ctx {
   int capturing = 0;                         // a HIP graph capture is in progress
   Selector *sel = nullptr;
   SearchState *search = nullptr;
+  std::vector<unsigned char> ivm_ckpt;  // checkpoint of the last IVM search stopped on its budget
   int cu_count = 256;
   DevInst inst() const {
     DevInst I;
@@ -185,6 +186,9 @@ int ensure_costs(Ctx *c, int count);
 int launch_bound(Ctx *c, const DevPool &pool, int kind, int ub, int *out_lb,
                  uint8_t *out_prune, hipStream_t s);
 int launch_costs(Ctx *c, const DevPool &pool, hipStream_t s, const CostFilter *f = nullptr);
+// FNV-1a hash of the loaded instance (n, m, p): checkpoints name their instance.
+uint64_t instance_hash(const Ctx *c);
+
 // Parents per wave for subset bounds of at most k pairs per parent: option
 // "subset_group" if set, else by k and n.
 int subset_group_for(const Ctx *c, int k);

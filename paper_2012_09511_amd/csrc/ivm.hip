@@ -638,36 +638,52 @@ static void initial_units(int n, int K, std::vector<uint8_t> &V, std::vector<uin
   }
 }
 
-__global__ void k_ivm_init(IvmCtl *c, int ub0) {
-  memset(c, 0, sizeof(IvmCtl));
-  c->ub = ub0;
-  c->ub_step = ub0;
-  c->step_best = ~0ull;
-  c->steps = 1;  // the number of the step under way
-}
-
 }  // namespace pfsp
 
 using namespace pfsp;
 
-extern "C" int pfsp_search_ivm(pfsp_ctx *h, int32_t ub0, int64_t budget_nodes, int lb_kind,
-                               int32_t explorers, pfsp_result *res, int64_t *steals) {
-  if (!h) return PFSP_EINVAL;
-  Ctx *c = &h->impl;
-  if (c->n == 0) return set_err(c, PFSP_ENOINST, "no instance loaded");
-  if (!res) return set_err(c, PFSP_EINVAL, "res is NULL");
-  if (lb_kind != PFSP_LB1 && lb_kind != PFSP_LB2_FULL)
-    return set_err(c, PFSP_EINVAL, "IVM search takes PFSP_LB1 or PFSP_LB2_FULL");
-  if (lb_kind != PFSP_LB1 && c->m < 2) return set_err(c, PFSP_ERANGE, "LB2 kinds need m >= 2");
-  if (c->n > kIvmMaxN) return set_err(c, PFSP_ERANGE, "IVM search covers n <= 64");
-  if (budget_nodes < 0) return set_err(c, PFSP_EINVAL, "negative budget");
+namespace pfsp {
+namespace {
+
+// Checkpoint of an IVM search stopped on its budget (Section 4.1 saves the
+// explorers' work units; here every explorer's whole state, so that a
+// resumed search continues exactly and counts every node once): the header,
+// the best schedule, then st, lev [K] int32, V, E, D [K][n], Etop [K], M
+// [K][n][n], prune bits [K][n] u64 and stored bounds [K][n][n] int32.
+struct IvmCkptHeader {
+  char magic[8];  // "PFSPIVM1"
+  int32_t n, m, kind, ub0, ub, K, d, pad;
+  uint64_t inst_hash;
+  int64_t nodes, children, steps, steals;
+};
+
+struct IvmPart {
+  void *dev;
+  size_t bytes;
+};
+
+static std::vector<IvmPart> ivm_parts(const IvmState *S) {
+  const size_t K = S->K, n = S->n;
+  return {{S->st, K * 4},         {S->lev, K * 4},      {S->V, K * n},
+          {S->E, K * n},          {S->D, K * n},        {S->Etop, K},
+          {S->M, K * n * n},      {S->Pr, K * n * 8},   {S->LB, K * n * n * 4}};
+}
+
+static size_t ivm_ckpt_bytes(int K, int n) {
+  const size_t k = K, nn = n;
+  return sizeof(IvmCkptHeader) + ((nn + 7) & ~size_t(7)) + k * 8 + 3 * k * nn + k +
+         k * nn * nn + k * nn * 8 + k * nn * nn * 4;
+}
+
+// The search loop shared by pfsp_search_ivm and pfsp_search_ivm_resume.
+// ck: the checkpoint to continue, or null for a fresh start from ub0.
+static int ivm_search(Ctx *c, int32_t ub0, int64_t budget_nodes, int lb_kind, int K,
+                      const unsigned char *ck, pfsp_result *res, int64_t *steals) {
   int d = 0;
-  while ((1 << (2 * d)) < explorers) ++d;
-  if (explorers < 1 || (1 << (2 * d)) != explorers || explorers > (1 << 20))
-    return set_err(c, PFSP_ERANGE, "explorers must be a power of 4 in [1, 4^10]");
+  while ((1 << (2 * d)) < K) ++d;
   PFSP_HIP(c, hipSetDevice(c->device));
   PFSP_HIP(c, hipStreamSynchronize(c->stream));
-  const int n = c->n, K = explorers;
+  const int n = c->n;
   int rc = ensure_costs(c, K);
   if (rc) return rc;
   IvmState *S = ivm_alloc(c, K);
@@ -686,7 +702,27 @@ extern "C" int pfsp_search_ivm(pfsp_ctx *h, int32_t ub0, int64_t budget_nodes, i
     ~Guard() { ivm_free(S); }
   } guard{S};
   const auto t0 = std::chrono::steady_clock::now();
-  {
+  IvmCtl ctl0;
+  memset(&ctl0, 0, sizeof ctl0);
+  ctl0.ub = ctl0.ub_step = ub0;
+  ctl0.step_best = ~0ull;
+  ctl0.steps = 1;  // the number of the step under way
+  if (ck) {
+    IvmCkptHeader hd;
+    memcpy(&hd, ck, sizeof hd);
+    const unsigned char *q = ck + sizeof hd;
+    PFSP_HIP(c, hipMemcpy(S->best_perm, q, n, hipMemcpyHostToDevice));
+    q += (n + 7) & ~7;
+    for (const IvmPart &pt : ivm_parts(S)) {
+      PFSP_HIP(c, hipMemcpy(pt.dev, q, pt.bytes, hipMemcpyHostToDevice));
+      q += pt.bytes;
+    }
+    ctl0.ub = ctl0.ub_step = hd.ub;
+    ctl0.steps = hd.steps;
+    ctl0.nodes = hd.nodes;
+    ctl0.children = hd.children;
+    ctl0.steals = hd.steals;
+  } else {
     std::vector<uint8_t> V, E, Et;
     initial_units(n, K, V, E, Et);
     std::vector<int> st(K, kIvmRoot), lev(K, -1);
@@ -698,8 +734,7 @@ extern "C" int pfsp_search_ivm(pfsp_ctx *h, int32_t ub0, int64_t budget_nodes, i
     PFSP_HIP(c, hipMemset(S->Pr, 0, (size_t)K * n * 8));
     PFSP_HIP(c, hipMemset(S->D, 0, (size_t)K * n));
   }
-  hipLaunchKernelGGL(k_ivm_init, dim3(1), dim3(1), 0, S->stream, S->ctl, (int)ub0);
-  PFSP_HIP(c, hipGetLastError());
+  PFSP_HIP(c, hipMemcpy(S->ctl, &ctl0, sizeof ctl0, hipMemcpyHostToDevice));
   DevPool pool;
   pool.count = K;
   pool.n = n;
@@ -772,6 +807,34 @@ extern "C" int pfsp_search_ivm(pfsp_ctx *h, int32_t ub0, int64_t budget_nodes, i
     }
   }
   const IvmCtl hc = *S->ctl_host;
+  c->ivm_ckpt.clear();
+  if (status == PFSP_BUDGET) {  // keep the state for pfsp_search_ivm_dump
+    c->ivm_ckpt.resize(ivm_ckpt_bytes(K, n));
+    IvmCkptHeader hd;
+    memset(&hd, 0, sizeof hd);
+    memcpy(hd.magic, "PFSPIVM1", 8);
+    hd.n = n;
+    hd.m = c->m;
+    hd.kind = lb_kind;
+    hd.ub0 = ub0;
+    hd.ub = hc.ub;
+    hd.K = K;
+    hd.d = d;
+    hd.inst_hash = instance_hash(c);
+    hd.nodes = hc.nodes;
+    hd.children = hc.children;
+    hd.steps = hc.steps;
+    hd.steals = hc.steals;
+    unsigned char *q = c->ivm_ckpt.data();
+    memcpy(q, &hd, sizeof hd);
+    q += sizeof hd;
+    PFSP_HIP(c, hipMemcpy(q, S->best_perm, n, hipMemcpyDeviceToHost));
+    q += (n + 7) & ~7;
+    for (const IvmPart &pt : ivm_parts(S)) {
+      PFSP_HIP(c, hipMemcpy(q, pt.dev, pt.bytes, hipMemcpyDeviceToHost));
+      q += pt.bytes;
+    }
+  }
   const auto t1 = std::chrono::steady_clock::now();
   res->found = hc.ub < ub0;
   res->best_cmax = res->found ? hc.ub : ub0;
@@ -788,6 +851,61 @@ extern "C" int pfsp_search_ivm(pfsp_ctx *h, int32_t ub0, int64_t budget_nodes, i
     for (int j = 0; j < n; ++j) res->best_perm[j] = tmp[j];
   }
   return status;
+}
+
+
+}  // namespace
+}  // namespace pfsp
+
+extern "C" int pfsp_search_ivm(pfsp_ctx *h, int32_t ub0, int64_t budget_nodes, int lb_kind,
+                               int32_t explorers, pfsp_result *res, int64_t *steals) {
+  if (!h) return PFSP_EINVAL;
+  Ctx *c = &h->impl;
+  if (c->n == 0) return set_err(c, PFSP_ENOINST, "no instance loaded");
+  if (!res) return set_err(c, PFSP_EINVAL, "res is NULL");
+  if (lb_kind != PFSP_LB1 && lb_kind != PFSP_LB2_FULL)
+    return set_err(c, PFSP_EINVAL, "IVM search takes PFSP_LB1 or PFSP_LB2_FULL");
+  if (lb_kind != PFSP_LB1 && c->m < 2) return set_err(c, PFSP_ERANGE, "LB2 kinds need m >= 2");
+  if (c->n > kIvmMaxN) return set_err(c, PFSP_ERANGE, "IVM search covers n <= 64");
+  if (budget_nodes < 0) return set_err(c, PFSP_EINVAL, "negative budget");
+  int d = 0;
+  while ((1 << (2 * d)) < explorers) ++d;
+  if (explorers < 1 || (1 << (2 * d)) != explorers || explorers > (1 << 20))
+    return set_err(c, PFSP_ERANGE, "explorers must be a power of 4 in [1, 4^10]");
+  return ivm_search(c, ub0, budget_nodes, lb_kind, explorers, nullptr, res, steals);
+}
+
+extern "C" int pfsp_search_ivm_dump(pfsp_ctx *h, void *buf, int64_t cap, int64_t *size) {
+  if (!h || !size) return PFSP_EINVAL;
+  Ctx *c = &h->impl;
+  if (c->ivm_ckpt.empty())
+    return set_err(c, PFSP_EINVAL, "no IVM search stopped on its budget to dump");
+  *size = (int64_t)c->ivm_ckpt.size();
+  if (!buf) return PFSP_OK;
+  if (cap < *size) return set_err(c, PFSP_ERANGE, "checkpoint buffer too small");
+  memcpy(buf, c->ivm_ckpt.data(), c->ivm_ckpt.size());
+  return PFSP_OK;
+}
+
+extern "C" int pfsp_search_ivm_resume(pfsp_ctx *h, const void *buf, int64_t size,
+                                      int64_t budget_nodes, pfsp_result *res, int64_t *steals) {
+  if (!h) return PFSP_EINVAL;
+  Ctx *c = &h->impl;
+  if (c->n == 0) return set_err(c, PFSP_ENOINST, "no instance loaded");
+  if (!buf || !res || budget_nodes < 0) return set_err(c, PFSP_EINVAL, "bad arguments");
+  IvmCkptHeader hd;
+  if (size < (int64_t)sizeof hd) return set_err(c, PFSP_EINVAL, "not an IVM checkpoint");
+  memcpy(&hd, buf, sizeof hd);
+  if (memcmp(hd.magic, "PFSPIVM1", 8) != 0) return set_err(c, PFSP_EINVAL, "not an IVM checkpoint");
+  if (hd.n != c->n || hd.m != c->m || hd.inst_hash != instance_hash(c))
+    return set_err(c, PFSP_EINVAL, "checkpoint of another instance");
+  if (hd.K < 1 || hd.K > (1 << 20) || (hd.K & (hd.K - 1)) != 0 ||
+      (hd.kind != PFSP_LB1 && hd.kind != PFSP_LB2_FULL) ||
+      size != (int64_t)ivm_ckpt_bytes(hd.K, hd.n))
+    return set_err(c, PFSP_EINVAL, "malformed IVM checkpoint");
+  // copy first: a budget stop of this run replaces the context's checkpoint
+  std::vector<unsigned char> ck((const unsigned char *)buf, (const unsigned char *)buf + size);
+  return ivm_search(c, hd.ub0, budget_nodes, hd.kind, hd.K, ck.data(), res, steals);
 }
 
 // Host checks of the work-unit arithmetic and the decoding.

@@ -815,7 +815,9 @@ struct CkptHeader {
   int64_t nodes, children, steps, records;
 };
 
-uint64_t instance_hash(const Ctx *c) {  // FNV-1a over n, m and p
+}  // namespace
+
+uint64_t pfsp::instance_hash(const Ctx *c) {  // FNV-1a over n, m and p
   uint64_t h = 1469598103934665603ull;
   auto mix = [&](const void *d, size_t len) {
     const unsigned char *b = (const unsigned char *)d;
@@ -826,8 +828,6 @@ uint64_t instance_hash(const Ctx *c) {  // FNV-1a over n, m and p
   mix(c->p_host, (size_t)c->n * c->m * 4);
   return h;
 }
-
-}  // namespace
 
 extern "C" int pfsp_search_dump(pfsp_ctx *h, void *buf, int64_t cap, int64_t *size) {
   if (!h || !size) return PFSP_EINVAL;

@@ -347,6 +347,39 @@ def test_ivm_search_matches_oracle(ctx, seed, kind):
         ctx.set_option("poll_every", 8)
 
 
+@pytest.mark.parametrize("seed", [2, 5])
+def test_ivm_dump_resume(ctx, seed):
+    """An IVM search stopped on its budget, dumped and resumed in a fresh
+    context (once or twice) ends with the uninterrupted search's optimum and
+    its node, child and steal counts (steps and stealing rounds are
+    deterministic, and the checkpoint holds every explorer's state); a
+    checkpoint of another instance is rejected."""
+    g = GOLDEN_20x10[seed]
+    p = inputs.instance(20, 10, seed)
+    ctx.load_instance(p)
+    full = ctx.search_ivm(g["neh"] + 1, 0, binding.LB2_FULL, 1024)
+    assert full["proven"] and full["best"] == g["opt"]
+    part = ctx.search_ivm(g["neh"] + 1, full["nodes"] // 3, binding.LB2_FULL, 1024)
+    assert part["budget_hit"] and not part["proven"]
+    ck = ctx.search_ivm_dump()
+    c2 = binding.Context(0)
+    try:
+        c2.load_instance(p)
+        end = c2.search_ivm_resume(ck, 2 * full["nodes"] // 3)
+        if end["budget_hit"]:
+            ck = c2.search_ivm_dump()
+            end = c2.search_ivm_resume(ck, 0)
+        assert end["proven"] and end["found"] and end["best"] == g["opt"]
+        _valid(p, end["perm"], g["opt"])
+        assert (end["nodes"], end["children"], end["steals"]) == \
+            (full["nodes"], full["children"], full["steals"])
+        c2.load_instance(inputs.instance(20, 10, seed + 10))
+        with pytest.raises(binding.PfspError):
+            c2.search_ivm_resume(ck, 0)
+    finally:
+        c2.close()
+
+
 @pytest.mark.parametrize("seed", range(1, 9))
 def test_ivm_search_10x5(ctx, seed):
     p = inputs.instance(10, 5, seed)

@@ -1594,7 +1594,31 @@ __device__ void lb2d_parent(const DevInst &I, int Ppad, const DeepLds<NMAX> &S,
   // LB1 of both children of slot q, and their start times: f of machine s in
   // the low half of [s][job], g of machine m - 1 - s in the high half
   int lb1 = 0;
-  if (member) {
+  if (r == 2) {
+    // Two jobs left: each child has one, and its LB2 is the makespan of its
+    // only completion.  That makespan is a longest path that enters the last
+    // job's operations on some machine k1 and leaves on some k2 >= k1; LB1
+    // covers k1 = k2 and the pair (k1, k2) the others, and every term is a
+    // lower bound.  So the bound is the makespan itself, from the walk of the
+    // child's job and then the other one over the machines (reversed for the
+    // backward child), closed by the other side's costs; no pair pass.
+    if (member) {
+      const int j0 = __builtin_amdgcn_readlane(jq, 0), j1 = __builtin_amdgcn_readlane(jq, 1);
+      const int jo = q == 0 ? j1 : j0;  // the job left after this child's
+      const int2 *HT = bwd ? S.HTb : S.HTf;
+      const int *PT = (bwd ? S.pr : S.pt) + jq;
+      const int *PO = (bwd ? S.pr : S.pt) + jo;
+      const int *OT = bwd ? S.c1 + (m - 1) : S.c2;  // the far side, in walk order
+      const int ostep = bwd ? -1 : 1;
+      int c = 0, g = 0;
+#pragma unroll 4
+      for (int s = 0; s < m; ++s) {
+        c = max(c, HT[s].x) + PT[s * 32];
+        g = max(g, c) + PO[s * 32];
+        lb1 = max(lb1, g + OT[s * ostep]);
+      }
+    }
+  } else if (member) {
     const int2 *HT = bwd ? S.HTb : S.HTf;
     const int *PT = (bwd ? S.pr : S.pt) + jq;
     unsigned short *fb16 = (unsigned short *)S.FBf + 2 * jq + (bwd ? 1 : 0);
@@ -1615,7 +1639,7 @@ __device__ void lb2d_parent(const DevInst &I, int Ppad, const DeepLds<NMAX> &S,
     acc[x] = (int)0x80008000u;
     asm volatile("" : "+v"(acc[x]));
   }
-  const int npass = r < 2 || P == 0 ? 0 : Ppad;  // one job left: LB2 = LB1
+  const int npass = r <= 2 || P == 0 ? 0 : Ppad;  // one job left: LB2 = LB1
   constexpr int NEGX = -(1 << 14);
   int *__restrict__ Xh = S.X + lane;
   for (int pc = 0; pc < npass; pc += 64) {

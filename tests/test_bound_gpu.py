@@ -159,6 +159,27 @@ def test_deep_kernel_parity(ctx, deep_r, n, m, lo, hi):
         ctx.set_option("timing", 0)
 
 
+@pytest.mark.parametrize("n,m,lo,hi", [(20, 20, 1, 99), (32, 20, 500, 630), (24, 32, 1, 99),
+                                       (12, 2, 1, 99), (2, 7, 1, 99)])
+def test_deep_two_jobs_left(ctx, n, m, lo, hi):
+    """Parents with two jobs left: the deep kernel bounds their children by
+    the makespan of each child's only completion (which full LB2 reaches
+    there), with no pair pass.  Many such parents, at the 16-bit edge too, at
+    an open and at a pruning incumbent; MinMin must tie to forward."""
+    rng = np.random.default_rng(n * 11 + m + hi)
+    p = rng.integers(lo, hi + 1, size=(n, m)).astype(np.int32)
+    perm, d1, d2 = inputs.random_pool(n, 1500, 90 + n, depth=n - 2)
+    ctx.set_option("timing", 1)
+    try:
+        ctx.load_instance(p)
+        ctx.kernel_time("k_lb2d", reset=True)
+        olb = _check(ctx, p, perm, d1, d2, binding.LB2_FULL, INT32_MAX)
+        _check(ctx, p, perm, d1, d2, binding.LB2_FULL, int(np.median(olb[olb < INT32_MAX])))
+        assert ctx.kernel_time("k_lb2d")[1] == 2
+    finally:
+        ctx.set_option("timing", 0)
+
+
 def _random_masks(rng, count, m, kmax):
     """Per row a uniform number of distinct pairs in [0, kmax], as bit masks."""
     P = m * (m - 1) // 2

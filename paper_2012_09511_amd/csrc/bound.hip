@@ -446,6 +446,123 @@ k_lb1m(const DevInst *__restrict__ insts, const long long *__restrict__ seg, int
           write_out, flag);
 }
 
+// Costs only (the LB2 kinds of the multi-instance launch) for n <= 128 and
+// m <= MMAX: k_lb1m's values with the block's pool rows (one contiguous
+// range) copied to LDS by whole words, the block's instance's p staged in
+// LDS (odd row stride) when all its parents belong to one instance, which the
+// grouping by instance makes the common case, and the three cost vectors in
+// registers.  A block that straddles two instances reads p from global
+// memory.
+template <int MMAX>
+__global__ void __launch_bounds__(128)
+k_costsm(const DevInst *__restrict__ insts, const long long *__restrict__ seg, int ninst,
+         const uint8_t *__restrict__ perm, const uint8_t *__restrict__ d1,
+         const uint8_t *__restrict__ d2, int stride, int mmax, int *__restrict__ costs,
+         int *__restrict__ flag) {
+  extern __shared__ int sh[];
+  constexpr int MS = MMAX | 1, B = 128;
+  const int t = threadIdx.x;
+  const long long total = seg[ninst];
+  const long long b0 = (long long)blockIdx.x * B;
+  const int rows = (int)min((long long)B, total - b0);
+  auto inst_of = [&](long long x) {  // seg[k] <= x < seg[k + 1]
+    int lo = 0, hi = ninst;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (seg[mid] <= x) lo = mid; else hi = mid;
+    }
+    return lo;
+  };
+  const int k0 = inst_of(b0);
+  const bool staged = inst_of(b0 + rows - 1) == k0;  // uniform
+  int *sp = sh;                                       // [128][MS] p of instance k0
+  uint8_t *srow = (uint8_t *)(sh + 128 * MS);         // [B][stride] the block's rows
+  if (staged) {
+    const DevInst I0 = insts[k0];
+    for (int x = t; x < I0.n * MS; x += B) {
+      const int j = x / MS, k = x - j * MS;
+      sp[x] = k < I0.m ? I0.p[j * I0.m + k] : 0;
+    }
+  }
+  {  // rows b0 .. b0 + rows: whole words (the range starts 4-byte aligned), then the tail
+    const size_t bytes = (size_t)rows * stride;
+    const uint8_t *src = perm + (size_t)b0 * stride;
+    const size_t words = ((uintptr_t)src & 3u) ? 0 : bytes >> 2;
+    for (size_t x = t; x < words; x += B) ((uint32_t *)srow)[x] = ((const uint32_t *)src)[x];
+    for (size_t x = words * 4 + t; x < bytes; x += B) srow[x] = src[x];
+  }
+  __syncthreads();
+  if (t >= rows) return;
+  const long long i = b0 + t;
+  const int k = staged ? k0 : inst_of(i);
+  const DevInst I = insts[k];
+  const int n = I.n, m = I.m;
+  const int *pm = staged ? sp : I.p;
+  const int ps = staged ? MS : m;
+  const uint8_t *row = srow + (size_t)t * stride;
+  const int a = d1[i], b = d2[i];
+  int *cs = costs + (size_t)i * 3 * mmax;
+  // a row must be a permutation of 0..n-1 with d1 + d2 < n
+  uint64_t s0 = 0, s1 = 0;
+  bool bad = a + b >= n;
+  for (int x = 0; x < n; ++x) {
+    const unsigned j = row[x];
+    bad |= j >= (unsigned)n;
+    const uint64_t bit = 1ull << (j & 63u);
+    s0 |= j < 64 ? bit : 0ull;
+    s1 |= j >= 64 ? bit : 0ull;
+  }
+  bad |= s0 != (n >= 64 ? ~0ull : (1ull << n) - 1ull) ||
+         s1 != (n > 64 ? (n == 128 ? ~0ull : (1ull << (n - 64)) - 1ull) : 0ull);
+  if (bad) {
+    flag[0] = 1;
+    for (int q = 0; q < 3 * m; ++q) cs[q] = 0;
+    cs[0] = -1;  // marks the row invalid for the LB2 kernels
+    return;
+  }
+  int C1[MMAX], C2[MMAX], R[MMAX];
+#pragma unroll
+  for (int q = 0; q < MMAX; ++q) {
+    C1[q] = 0;
+    C2[q] = 0;
+    R[q] = q < m ? I.T[q] : 0;
+  }
+  for (int x = 0; x < a; ++x) {  // front of sigma1, Eq. (1)
+    const int *pj = pm + row[x] * ps;
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < MMAX; ++q) {
+      if (q < m) {
+        const int v = pj[q];
+        c = max(c, C1[q]) + v;
+        C1[q] = c;
+        R[q] -= v;
+      }
+    }
+  }
+  for (int x = n - 1; x >= n - b; --x) {  // back of sigma2: jobs and machines reversed
+    const int *pj = pm + row[x] * ps;
+    int c = 0;
+#pragma unroll
+    for (int q = MMAX - 1; q >= 0; --q) {
+      if (q < m) {
+        const int v = pj[q];
+        c = max(c, C2[q]) + v;
+        C2[q] = c;
+        R[q] -= v;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < MMAX; ++q) {
+    if (q < m) {
+      cs[q] = C1[q];
+      cs[m + q] = C2[q];
+      cs[2 * m + q] = R[q];
+    }
+  }
+}
+
 // ------------------------------------------------------------------------ LB2
 template <class E, bool ENT_LDS, bool SUBSET, bool LOG>
 __global__ void __launch_bounds__(512)
@@ -3312,11 +3429,28 @@ size_t lb2m_lds_bytes(int nmax, int ppad, int nmax_jobs, int mmax, int waves, in
 }
 
 int launch_lb1m(Ctx *c, const DevInst *insts, const long long *seg, int ninst, long long total,
-                const uint8_t *perm, const uint8_t *d1, const uint8_t *d2, int stride, int mmax,
-                const int *ubs, int *out_lb, uint8_t *out_prune, uint8_t *dir, int *costs,
-                int write_out, hipStream_t s) {
+                const uint8_t *perm, const uint8_t *d1, const uint8_t *d2, int stride, int nmax,
+                int mmax, const int *ubs, int *out_lb, uint8_t *out_prune, uint8_t *dir,
+                int *costs, int write_out, hipStream_t s) {
   if (total <= 0) return PFSP_OK;
   const int B = 128;
+  if (!write_out && nmax <= 128 && mmax <= 32) {
+    const int mm = mmax <= 8 ? 8 : mmax <= 16 ? 16 : mmax <= 20 ? 20 : 32;
+    const size_t lds = (size_t)128 * (mm | 1) * 4 + (size_t)B * stride;
+    KTimer kt(c, s, "k_lb1m");
+    switch (mm) {
+#define PFSP_C(M)                                                                            \
+  case M:                                                                                    \
+    hipLaunchKernelGGL(k_costsm<M>, dim3((unsigned)((total + B - 1) / B)), dim3(B), lds, s,   \
+                       insts, seg, ninst, perm, d1, d2, stride, mmax, costs, c->d_flag);     \
+    break;
+      PFSP_C(8) PFSP_C(16) PFSP_C(20) PFSP_C(32)
+#undef PFSP_C
+      default: break;
+    }
+    PFSP_HIP(c, hipGetLastError());
+    return PFSP_OK;
+  }
   const size_t lds = (size_t)3 * mmax * B * 4;
   KTimer kt(c, s, "k_lb1m");
   hipLaunchKernelGGL(k_lb1m, dim3((unsigned)((total + B - 1) / B)), dim3(B), lds, s, insts, seg,

@@ -230,9 +230,9 @@ size_t lb2m_lds_bytes(int nmax, int ppad, int nmax_jobs, int mmax, int waves, in
 int launch_generic_instance(Ctx *c, const DevInst &I, const DevPool &pool, int ub, int *costs,
                             int *out_lb, uint8_t *out_prune, hipStream_t s);
 int launch_lb1m(Ctx *c, const DevInst *insts, const long long *seg, int ninst, long long total,
-                const uint8_t *perm, const uint8_t *d1, const uint8_t *d2, int stride, int mmax,
-                const int *ubs, int *out_lb, uint8_t *out_prune, uint8_t *dir, int *costs,
-                int write_out, hipStream_t s);
+                const uint8_t *perm, const uint8_t *d1, const uint8_t *d2, int stride, int nmax,
+                int mmax, const int *ubs, int *out_lb, uint8_t *out_prune, uint8_t *dir,
+                int *costs, int write_out, hipStream_t s);
 int launch_lb2m(Ctx *c, const FastClassLaunch &L, const DevInst *insts, const uint8_t *perm,
                 const uint8_t *d1, const uint8_t *d2, int stride, const int *ubs,
                 const int *costs, int *out_lb, uint8_t *out_prune, uint8_t *dir, hipStream_t s);

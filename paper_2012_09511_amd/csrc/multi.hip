@@ -183,7 +183,8 @@ static int multi_enqueue(pfsp_multi *mt, int kind, const uint8_t *perm, const ui
   hipStream_t s = mt->stream;
   const int K = (int)mt->in.size();
   const long long total = seg[K];
-  int rc = launch_lb1m(c, mt->d_insts, mt->d_seg, K, total, perm, d1, d2, stride, mt->mmax,
+  int rc = launch_lb1m(c, mt->d_insts, mt->d_seg, K, total, perm, d1, d2, stride, mt->nmax,
+                       mt->mmax,
                        mt->d_ubs, out_lb, out_prune, dir, mt->d_costs, kind == PFSP_LB1, s);
   if (rc || kind == PFSP_LB1) return rc;
   for (int cls = 0; cls < kNumCls; ++cls) {

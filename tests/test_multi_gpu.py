@@ -127,6 +127,45 @@ def test_wide_classes(ctx):
     mt.close()
 
 
+def test_invalid_rows_and_instance_blocks(ctx):
+    """Segments long enough for blocks of one instance (the costs pass stages
+    that instance's times) beside blocks that straddle two, with rows that are
+    not valid nodes (d1 + d2 = n, a repeated job, a job id out of range): those
+    come back fully pruned and raise the context's error, the others equal the
+    oracle."""
+    import torch
+    insts = [(20, 20, inputs.instance(20, 20, 27)), (50, 10, inputs.instance(50, 10, 28)),
+             (100, 5, inputs.instance(100, 5, 29)), (7, 3, inputs.instance(7, 3, 30))]
+    per = [300, 261, 140, 5]
+    stride = 100
+    perm, d1, d2, seg = _batch(insts, per, 131, stride)
+    bad = []
+    for k, (n, m, p) in enumerate(insts):
+        a = seg[k]
+        d1[a + 1], d2[a + 1] = n - 2, 2
+        perm[a + 2, 1] = perm[a + 2, 0]
+        perm[a + 3, n - 1] = 200
+        bad += [a + 1, a + 2, a + 3]
+    good = np.setdiff1d(np.arange(seg[-1]), bad)
+    ub = np.array([2400, 3200, 6000, 900], dtype=np.int32)
+    mt = binding.Multi(ctx, [p for _, _, p in insts])
+    lb, pr, dr = mt.bound(*_dev(ctx, perm, d1, d2), seg, ub, binding.LB2_FULL)
+    torch.cuda.synchronize()
+    with pytest.raises(binding.PfspError):
+        ctx.check()
+    lb, pr, dr = lb.cpu().numpy(), pr.cpu().numpy(), dr.cpu().numpy()
+    assert (lb[bad] == binding.INT32_MAX).all() and (pr[bad] == 1).all() and (dr[bad] == 0).all()
+    for k, (n, m, p) in enumerate(insts):
+        rows = good[(good >= seg[k]) & (good < seg[k + 1])]
+        olb, opr, odr = oracle.bound_children(p, perm[rows, :n], d1[rows], d2[rows],
+                                              binding.LB2_FULL, ub[k], threads=8)
+        np.testing.assert_array_equal(lb[rows, :, :n], olb)
+        np.testing.assert_array_equal(pr[rows, :, :n], opr)
+        np.testing.assert_array_equal(dr[rows], odr)
+    mt.close()
+    ctx.check()   # the condition was cleared
+
+
 def test_full_size_batch_sampled(ctx):
     """The multi-instance benchmark batch at full size (64 instances, 16,384
     parents each, incumbent open) in the default and an autotuned launch

@@ -135,8 +135,9 @@ def test_invalid_rows_and_instance_blocks(ctx):
     oracle."""
     import torch
     insts = [(20, 20, inputs.instance(20, 20, 27)), (50, 10, inputs.instance(50, 10, 28)),
-             (100, 5, inputs.instance(100, 5, 29)), (7, 3, inputs.instance(7, 3, 30))]
-    per = [300, 261, 140, 5]
+             (100, 5, inputs.instance(100, 5, 29)), (7, 3, inputs.instance(7, 3, 30)),
+             (40, 4, inputs.instance(40, 4, 31))]
+    per = [300, 261, 140, 5, 97]
     stride = 100
     perm, d1, d2, seg = _batch(insts, per, 131, stride)
     bad = []
@@ -147,7 +148,7 @@ def test_invalid_rows_and_instance_blocks(ctx):
         perm[a + 3, n - 1] = 200
         bad += [a + 1, a + 2, a + 3]
     good = np.setdiff1d(np.arange(seg[-1]), bad)
-    ub = np.array([2400, 3200, 6000, 900], dtype=np.int32)
+    ub = np.array([2400, 3200, 6000, 900, 2300], dtype=np.int32)
     mt = binding.Multi(ctx, [p for _, _, p in insts])
     lb, pr, dr = mt.bound(*_dev(ctx, perm, d1, d2), seg, ub, binding.LB2_FULL)
     torch.cuda.synchronize()

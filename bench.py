@@ -51,13 +51,16 @@ def alg_ops_lb2(n, m, d1, d2):
       (b - a), SM), X_b = X_a + b - a), children 4 (an add and a max for
       each direction);
       per child (2r of them) and machine: 4 for its start times and LB1.
-    So 11 r P + 8 r m per parent (a parent with one job left needs LB1 only:
-    8 m).  Every kernel issues at least this many lane operations per parent,
-    so achieved / peak stays at most 1 at every depth.
+    So 11 r P + 8 r m per parent.  A parent with one job left needs LB1 only
+    (8 m); one with two jobs left has children with one job each, whose full
+    LB2 is the makespan of their only completion: two completions per parent,
+    each two jobs over m machines and a closing maximum, 12 m.  Every kernel
+    issues at least this many lane operations per parent, so achieved / peak
+    stays at most 1 at every depth.
     """
     P = m * (m - 1) // 2
     r = n - d1.astype(np.int64) - d2.astype(np.int64)
-    ops = np.where(r >= 2, 11 * r * P + 8 * r * m, 8 * m)
+    ops = np.where(r >= 3, 11 * r * P + 8 * r * m, np.where(r == 2, 12 * m, 8 * m))
     return int(ops.sum())
 
 

@@ -61,7 +61,7 @@ def lib():
         L.or_search.restype = i32
         L.or_search.argtypes = [i32, i32, vp, i64, i32, i64, vp, vp, vp, vp, vp, vp]
         L.or_search_ex.restype = i32
-        L.or_search_ex.argtypes = [i32, i32, vp, i64, i32, vp, i64, i32, vp, vp, vp, vp, vp,
+        L.or_search_ex.argtypes = [i32, i32, vp, i64, i32, vp, i64, i32, i32, vp, vp, vp, vp, vp,
                                    vp]
         L.or_bruteforce.restype = i64
         L.or_bruteforce.argtypes = [i32, i32, vp, vp]
@@ -176,10 +176,12 @@ def bound_children(p, perm, d1, d2, kind=LB1, ub=INT32_MAX, pair_mask=None,
     return (lb, pr, dr, ap) if with_argpair else (lb, pr, dr)
 
 
-def search(p, ub0=INT32_MAX, kind=LB1, budget=0, pair_mask=None, threads=1):
+def search(p, ub0=INT32_MAX, kind=LB1, budget=0, pair_mask=None, threads=1, lb1_r=0):
     """Depth-first B&B; returns dict(best, perm, nodes, children, found, proven).
     kind LB2_SUBSET bounds every node over the pairs of pair_mask (uint32 words);
-    threads > 1 runs the OpenMP-task search (no budget)."""
+    threads > 1 runs the OpenMP-task search (no budget).  lb1_r > 0: nodes with
+    at most lb1_r unscheduled jobs bound their children with LB1 instead of
+    kind (the bound chosen by depth; Section 2.4 ranks LB1 the cheaper)."""
     p = _ci32(p)
     n, m = p.shape
     best = np.zeros(1, dtype=np.int64)
@@ -190,7 +192,8 @@ def search(p, ub0=INT32_MAX, kind=LB1, budget=0, pair_mask=None, threads=1):
     proven = np.zeros(1, dtype=np.int32)
     mask = None if pair_mask is None else np.ascontiguousarray(pair_mask, dtype=np.uint32)
     rc = lib().or_search_ex(n, m, _p(p), int(ub0), kind, None if mask is None else _p(mask),
-                            int(budget), int(threads), _p(best), _p(perm), _p(nodes), _p(ch),
+                            int(budget), int(threads), int(lb1_r), _p(best), _p(perm),
+                            _p(nodes), _p(ch),
                             _p(found), _p(proven))
     if rc != 0:
         raise ValueError(f"or_search failed with {rc}")

@@ -301,9 +301,12 @@ int or_bound_children(int n, int m, const int32_t *p, int count, const uint8_t *
  * visited; the children of the chosen set are visited in list order; leaves
  * (no unscheduled job left) update the incumbent when strictly better.  With
  * kind OR_LB2_SUBSET every node is bounded over the same pair set `mask`
- * (Section 2.4: any number of pairs between m and m(m-1)/2). */
+ * (Section 2.4: any number of pairs between m and m(m-1)/2).  lb1_r > 0
+ * chooses the bound by depth: the children of a node with at most lb1_r
+ * unscheduled jobs get LB1, the others `kind` (Section 2.4 ranks LB1 as the
+ * cheaper, weaker bound; any valid bound keeps the search exact). */
 typedef struct {
-  int n, m, kind, cutoff;
+  int n, m, kind, cutoff, lb1_r;
   const int32_t *p;
   const uint32_t *mask;
   int64_t ub, budget, nodes, children;
@@ -315,12 +318,13 @@ typedef struct {
 static int decompose(const search_t *s, const uint8_t *perm, int d1, int d2,
                      int64_t lb[2][MAXN]) {
   int n = s->n, r = n - d1 - d2;
+  int kind = r <= s->lb1_r ? OR_LB1 : s->kind;
   uint8_t child[MAXN];
   for (int dir = 0; dir < 2; ++dir)
     for (int q = 0; q < r; ++q) {
       make_child(n, perm, d1, d2, q, dir, child);
       lb[dir][q] = or_node_bound(n, s->m, s->p, child, d1 + (dir == 0), d2 + (dir == 1),
-                                 s->kind, s->mask, NULL);
+                                 kind, s->mask, NULL);
     }
   return or_minmin(r, lb[0], lb[1]);
 }
@@ -399,12 +403,15 @@ static void dfs_task(search_t *s, const uint8_t *perm, int d1, int d2, int depth
  * the budget (0 = unlimited) of decomposed nodes.  nodes counts decomposed
  * nodes including the root; children counts bounded children (2(n-d) each).
  * kind OR_LB2_SUBSET bounds every node over the pairs of pair_mask (else
- * ignored).  threads > 1 runs the task-parallel search (budget must be 0). */
+ * ignored).  threads > 1 runs the task-parallel search (budget must be 0).
+ * lb1_r: nodes with at most this many unscheduled jobs bound their children
+ * with LB1 (0: never). */
 int or_search_ex(int n, int m, const int32_t *p, int64_t ub0, int kind,
-                 const uint32_t *pair_mask, int64_t budget, int threads, int64_t *best_cmax,
-                 uint8_t *best_perm, int64_t *nodes, int64_t *children, int *found,
-                 int *proven) {
+                 const uint32_t *pair_mask, int64_t budget, int threads, int lb1_r,
+                 int64_t *best_cmax, uint8_t *best_perm, int64_t *nodes, int64_t *children,
+                 int *found, int *proven) {
   if (n < 2 || n > 255 || m < 1 || m > MAXM) return -1;
+  if (lb1_r < 0) return -1;
   if (kind != OR_LB1 && kind != OR_LB2_FULL && kind != OR_LB2_SUBSET) return -1;
   if (kind != OR_LB1 && m < 2) return -1;
   if (kind == OR_LB2_SUBSET && !pair_mask) return -1;
@@ -414,6 +421,7 @@ int or_search_ex(int n, int m, const int32_t *p, int64_t ub0, int kind,
   s->n = n; s->m = m; s->kind = kind; s->p = p;
   s->mask = kind == OR_LB2_SUBSET ? pair_mask : NULL;
   s->ub = ub0; s->budget = budget;
+  s->lb1_r = lb1_r;
   s->cutoff = n / 2;
   uint8_t root[MAXN];
   for (int j = 0; j < n; ++j) root[j] = (uint8_t)j;
@@ -438,7 +446,7 @@ int or_search(int n, int m, const int32_t *p, int64_t ub0, int kind, int64_t bud
               int64_t *best_cmax, uint8_t *best_perm, int64_t *nodes, int64_t *children,
               int *found, int *proven) {
   if (kind != OR_LB1 && kind != OR_LB2_FULL) return -1;
-  return or_search_ex(n, m, p, ub0, kind, NULL, budget, 1, best_cmax, best_perm, nodes,
+  return or_search_ex(n, m, p, ub0, kind, NULL, budget, 1, 0, best_cmax, best_perm, nodes,
                       children, found, proven);
 }
 

@@ -48,9 +48,9 @@ int or_search(int n, int m, const int32_t *p, int64_t ub0, int kind, int64_t bud
               int64_t *best_cmax, uint8_t *best_perm, int64_t *nodes,
               int64_t *children, int *found, int *proven);
 int or_search_ex(int n, int m, const int32_t *p, int64_t ub0, int kind,
-                 const uint32_t *pair_mask, int64_t budget, int threads, int64_t *best_cmax,
-                 uint8_t *best_perm, int64_t *nodes, int64_t *children, int *found,
-                 int *proven);
+                 const uint32_t *pair_mask, int64_t budget, int threads, int lb1_r,
+                 int64_t *best_cmax, uint8_t *best_perm, int64_t *nodes, int64_t *children,
+                 int *found, int *proven);
 int64_t or_bruteforce(int n, int m, const int32_t *p, uint8_t *best_perm);
 int64_t or_neh(int n, int m, const int32_t *p, uint8_t *perm_out);
 

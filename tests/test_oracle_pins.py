@@ -458,3 +458,69 @@ def test_static_subset_search():
         mask = np.array([rng.integers(0, 1 << P)], dtype=np.uint32)
         r = oracle.search(p, 10**9, oracle.LB2_SUBSET, pair_mask=mask, threads=4)
         assert r["proven"] and r["best"] == opt
+
+
+def _child(perm, d1, d2, q, fwd):
+    """Child record: the q-th unscheduled job appended to sigma1 (fwd) or
+    prepended to sigma2, the other unscheduled jobs kept in list order."""
+    n = len(perm)
+    rest = list(perm[d1:n - d2])
+    j = rest.pop(q)
+    if fwd:
+        return list(perm[:d1]) + [j] + rest + list(perm[n - d2:]), d1 + 1, d2
+    return list(perm[:d1]) + rest + [j] + list(perm[n - d2:]), d1, d2 + 1
+
+
+def _dfs_by_depth(p, ub, kind, lb1_r):
+    """The depth-first search of Sections 2.2-2.5 written out in Python over
+    the oracle's node bound and MinMin: a node with at most lb1_r unscheduled
+    jobs bounds its children with LB1, the others with `kind`."""
+    n = p.shape[0]
+    st = dict(ub=ub, nodes=0, children=0)
+
+    def rec(perm, d1, d2):
+        r = n - d1 - d2
+        st["nodes"] += 1
+        st["children"] += 2 * r
+        k = oracle.LB1 if r <= lb1_r else kind
+        lbs = []
+        for fwd in (True, False):
+            row = []
+            for q in range(r):
+                c, a, b = _child(perm, d1, d2, q, fwd)
+                row.append(oracle.node_bound(p, np.array(c, dtype=np.uint8), a, b, k))
+            lbs.append(row)
+        d = oracle.minmin(lbs[0], lbs[1])
+        for q in range(r):
+            x = lbs[d][q]
+            if x >= st["ub"]:
+                continue
+            c, a, b = _child(perm, d1, d2, q, d == 0)
+            if r == 1:
+                st["ub"] = x
+            else:
+                rec(c, a, b)
+
+    rec(list(range(n)), 0, 0)
+    return st["ub"], st["nodes"], st["children"]
+
+
+@pytest.mark.parametrize("lb1_r", [1, 2, 3, 6])
+def test_search_bound_by_depth(lb1_r):
+    """The bound chosen by depth (LB1 for nodes with at most lb1_r jobs left,
+    LB2 above): node for node the search written out in Python, the
+    brute-force optimum, and lb1_r >= n reduces to the LB1 search."""
+    for seed, (n, m) in ((31, (6, 4)), (32, (6, 3))):
+        p = inputs.instance(n, m, seed)
+        opt, _ = oracle.bruteforce(p)
+        for ub in (opt, opt + 40):
+            r = oracle.search(p, ub, oracle.LB2_FULL, lb1_r=lb1_r)
+            best, nodes, children = _dfs_by_depth(p, ub, oracle.LB2_FULL, lb1_r)
+            assert (r["nodes"], r["children"]) == (nodes, children)
+            assert r["best"] == best == (opt if ub > opt else ub)
+        if lb1_r >= n:
+            a = oracle.search(p, opt + 40, oracle.LB1)
+            b = oracle.search(p, opt + 40, oracle.LB2_FULL, lb1_r=lb1_r)
+            assert (a["best"], a["nodes"], a["children"]) == (b["best"], b["nodes"], b["children"])
+    assert oracle.search(p, opt, oracle.LB2_FULL, lb1_r=0)["nodes"] == \
+        oracle.search(p, opt, oracle.LB2_FULL)["nodes"]

@@ -287,6 +287,12 @@ int pfsp_neh(pfsp_ctx *c, int32_t *perm_out, int32_t *cmax_out);
  * with at most deep_r unscheduled jobs take a kernel that scans only their
  * jobs' positions in each pair's Johnson order, the others the full-scan
  * kernel; 0 = every parent takes the full scan; at most 16; default 8),
+ * "lb1_r" (pfsp_search with an LB2 kind: the bound chosen by depth, Section
+ * 2.4 ranking LB1 as the cheaper, weaker bound; a popped parent with at most
+ * lb1_r unscheduled jobs has its children bounded with LB1, the others with
+ * the search's kind; the optimum is unchanged, the tree may grow; needs
+ * search_filter = 1 (else pfsp_search returns PFSP_EINVAL); 0..255, default
+ * 0 = off; the IVM search ignores it),
  * "heuristic_threads" (host threads that run an iterated greedy local search
  * on the instance while pfsp_search runs, seeded with NEH and with schedules
  * completed from open nodes; a better makespan lowers the device incumbent

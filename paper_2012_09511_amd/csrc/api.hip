@@ -293,6 +293,7 @@ static int64_t *opt_slot(Ctx *c, const char *key) {
   if (!strcmp(key, "log_capacity")) return &c->log_capacity;
   if (!strcmp(key, "log_stride")) return &c->log_stride;
   if (!strcmp(key, "deep_r")) return &c->deep_r;
+  if (!strcmp(key, "lb1_r")) return &c->lb1_r;
   if (!strcmp(key, "heuristic_threads")) return &c->heuristic_threads;
   if (!strcmp(key, "heuristic_seed")) return &c->heuristic_seed;
   return nullptr;
@@ -321,6 +322,8 @@ int pfsp_set_option(pfsp_ctx *h, const char *key, int64_t value) {
     return set_err(c, PFSP_ERANGE, "heuristic_threads must be in [0, 256]");
   if (!strcmp(key, "deep_r") && (value < 0 || value > 16))
     return set_err(c, PFSP_ERANGE, "deep_r must be in [0, 16]");
+  if (!strcmp(key, "lb1_r") && (value < 0 || value > 255))
+    return set_err(c, PFSP_ERANGE, "lb1_r must be in [0, 255]");
   if (!strcmp(key, "lb2_waves") && (value < 0 || value > 16))
     return set_err(c, PFSP_ERANGE, "lb2_waves must be in [0, 16]");
   if (!strcmp(key, "learned_topk") && (value < 1 || value > 2016))

@@ -194,13 +194,16 @@ __device__ __forceinline__ void list_append(int *rows, int *count, bool app, int
   }
 }
 
-// deep: the row has 1 <= r <= f.deep_r jobs left.
+// r: the row's jobs left (deep: 1 <= r <= f.deep_r; the LB1 band: 1 <= r <=
+// f.lb1_r, which takes precedence).
 __device__ __forceinline__ void filter_row(const CostFilter &f, int i, bool live, bool open,
-                                           bool deep, int ns, int lane) {
+                                           int r, int ns, int lane) {
   const bool app = live && open;
-  const bool to_deep = app && deep && f.rows_deep != nullptr;
-  list_append(f.rows, f.open, app && !to_deep, i, lane);
+  const bool to_lb1 = app && f.rows_lb1 != nullptr && r >= 1 && r <= f.lb1_r;
+  const bool to_deep = app && !to_lb1 && f.rows_deep != nullptr && r >= 1 && r <= f.deep_r;
+  list_append(f.rows, f.open, app && !to_deep && !to_lb1, i, lane);
   if (f.rows_deep) list_append(f.rows_deep, f.open_deep, to_deep, i, lane);
+  if (f.rows_lb1) list_append(f.rows_lb1, f.open_lb1, to_lb1, i, lane);
   if (!app && live) {
     uint8_t *pr = f.out_prune + (size_t)i * 2 * ns;
     for (int x = 0; x < 2 * ns; ++x) pr[x] = 1;
@@ -216,18 +219,22 @@ k_lb1(DevInst I, DevPool pool, int ub, int *__restrict__ out_lb, uint8_t *__rest
   int *sp = sh;  // p[n][m]
   for (int x = t; x < n * m; x += B) sp[x] = I.p[x];
   __syncthreads();
-  const int i = blockIdx.x * B + t;
+  const int it = blockIdx.x * B + t;
   const int count = pool.count_dev ? *pool.count_dev : pool.count;
-  const bool filt = f.rows != nullptr;  // costs mode only
-  if (i >= count && !filt) return;
+  const bool filt = f.rows != nullptr;  // costs mode only (every row, no index)
+  if (it >= count && !filt) return;
+  // launch row it bounds pool row i
+  const int i = !filt && pool.index && it < count ? pool.index[it] : it;
   if (pool.ub_dev) ub = *pool.ub_dev;
   int *C1 = sh + n * m + t;  // per-lane arrays, stride B (bank-conflict free)
   const int ns = pool.n;     // row stride of the pool and the outputs (>= n)
   bool live = false, open = false;
-  if (i < count) {
+  int rj = 0;  // jobs left
+  if (it < count) {
     live = !filt || !f.alive || f.alive[i];
     const uint8_t *row = pool.perm + (size_t)i * ns;
     const int a = pool.d1[i], b = pool.d2[i];
+    rj = n - a - b;
     int *cs = costs ? costs + (size_t)i * 3 * m : nullptr;
     lb1_row(I, sp, C1, C1 + m * B, C1 + 2 * m * B, B, row, a, b, ns, ub,
             write_out ? out_lb + (size_t)i * 2 * ns : nullptr,
@@ -254,7 +261,7 @@ k_lb1(DevInst I, DevPool pool, int ub, int *__restrict__ out_lb, uint8_t *__rest
       }
     }
   }
-  if (filt) filter_row(f, i, live, open, false, ns, t & 63);
+  if (filt) filter_row(f, i, live, open, rj, ns, t & 63);
 }
 
 // One parent's costs (front C1, back C2, remaining R; Eq. (1)) for n <= NJ
@@ -398,16 +405,17 @@ k_costs(DevInst I, DevPool pool, int *__restrict__ costs, int *__restrict__ flag
   for (int i0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63); i0 < count;
        i0 += gridDim.x * blockDim.x) {
     const int i = i0 + lane;
-    bool live = false, open = false, valid = false, deep = false;
+    bool live = false, open = false, valid = false;
+    int rj = 0;  // jobs left
     if (i < count) {
       live = !filt || !f.alive || f.alive[i];
       const int a = pool.d1[i], b = pool.d2[i];
       open = costs_row<MMAX, MS, NJ>(n, m, sp, sT, pool.perm + (size_t)i * ns, a, b,
                                  tile + lane * RS, flag, filt && live, ub, &valid);
       open = open && valid;
-      deep = n - a - b >= 1 && n - a - b <= f.deep_r;
+      rj = n - a - b;
     }
-    if (filt) filter_row(f, i, live, open, deep, ns, lane);
+    if (filt) filter_row(f, i, live, open, rj, ns, lane);
     wave_sync();
     const int rows = min(64, count - i0);
     int *dst = costs + (size_t)i0 * cm;

@@ -63,6 +63,9 @@ struct DevPool {
 //  - every other parent is appended to rows[0 .. *open) (any order).
 //  - rows_deep (optional): open rows with 1 <= r <= deep_r unscheduled jobs go
 //    to rows_deep[0 .. *open_deep) instead (the deep LB2 kernel).
+//  - rows_lb1 (optional): open rows with 1 <= r <= lb1_r go to
+//    rows_lb1[0 .. *open_lb1) instead, before the deep split (their children
+//    are bounded with LB1: the bound chosen by depth).
 struct CostFilter {
   const uint8_t *alive;
   const int *ub_dev;
@@ -73,6 +76,9 @@ struct CostFilter {
   int *rows_deep = nullptr;
   int *open_deep = nullptr;
   int deep_r = 0;
+  int *rows_lb1 = nullptr;
+  int *open_lb1 = nullptr;
+  int lb1_r = 0;
 };
 
 struct Selector;   // learned pair selector state (selector.hip)
@@ -119,6 +125,7 @@ struct Ctx {
   int64_t log_stride = 1;     // log every log_stride-th decomposed node of a batch
   int64_t wide_lb2 = 1;       // full LB2 for 32 < n <= 128 with 16-bit X takes k_lb2w
   int64_t deep_r = 8;         // full LB2: parents with at most deep_r jobs left take k_lb2d
+  int64_t lb1_r = 0;          // LB2 searches: parents with at most lb1_r jobs left use LB1
   int64_t heuristic_threads = 0;  // host threads improving the incumbent during searches
   int64_t heuristic_seed = 1;
   struct Pending {

@@ -68,8 +68,10 @@ struct SearchState {
   hipGraphExec_t gexec = nullptr;
   std::vector<long long> graph_key;  // options the captured step depends on
   // LB2 steps: parents that survive the costs kernels' LB1 filter (those with
-  // few jobs left in rows_deep, counted in open[1], for the deep kernel)
-  int *rows = nullptr, *open = nullptr, *rows_deep = nullptr;
+  // few jobs left in rows_deep, counted in open[1], for the deep kernel; with
+  // option lb1_r, those with at most lb1_r in rows_lb1, counted in open[2],
+  // for LB1)
+  int *rows = nullptr, *open = nullptr, *rows_deep = nullptr, *rows_lb1 = nullptr;
   // node log (option log_capacity > 0): every log_stride-th decomposed node
   uint8_t *l_perm = nullptr, *l_d1 = nullptr, *l_d2 = nullptr;
   long long log_cap = 0;
@@ -87,9 +89,10 @@ constexpr int kScanBlock = 1024;  // parents per k_scan_local block (256 threads
 
 __global__ void k_clear(int *p) { *p = 0; }
 __global__ void k_lower_ub(SearchCtl *c, int v) { atomicMin(&c->ub, v); }
-__global__ void k_clear2(int *p) {
+__global__ void k_clear3(int *p) {
   p[0] = 0;
   p[1] = 0;
+  p[2] = 0;
 }
 
 __global__ void k_pop(SearchCtl *c, int N) {
@@ -383,7 +386,7 @@ void search_free(Ctx *c) {
   void *bufs[] = {S->s_perm, S->s_d1, S->s_d2, S->s_lb, S->b_perm, S->b_d1, S->b_d2, S->b_dir,
                   S->b_lb, S->b_alive, S->out_lb, S->out_prune, S->cnt, S->offs, S->bsum,
                   S->best_perm, S->ctl, S->l_perm, S->l_d1, S->l_d2, S->rows, S->open,
-                  S->rows_deep};
+                  S->rows_deep, S->rows_lb1};
   for (void *p : bufs) (void)hipFree(p);
   if (S->ctl_host) (void)hipHostFree(S->ctl_host);
   if (S->stream) (void)hipStreamDestroy(S->stream);
@@ -431,7 +434,8 @@ static int search_alloc(Ctx *c) {
   alloc((void **)&S->ctl, sizeof(SearchCtl));
   alloc((void **)&S->rows, (size_t)N * 4);
   alloc((void **)&S->rows_deep, (size_t)N * 4);
-  alloc((void **)&S->open, 8);
+  alloc((void **)&S->rows_lb1, (size_t)N * 4);
+  alloc((void **)&S->open, 12);
   S->log_cap = c->log_capacity;
   if (S->log_cap > 0) {
     alloc((void **)&S->l_perm, (size_t)S->log_cap * n);
@@ -485,16 +489,31 @@ static int enqueue_step(Ctx *c, int kind) {
     // parents whose children all have LB1 >= ub are closed by the costs
     // kernel (LB2 >= LB1 cannot keep a child); only the others are bounded
     // parents with few jobs left go to a list of their own for the deep kernel
+    // and, with lb1_r, those with at most lb1_r to one bounded with LB1 (the
+    // bound chosen by depth; Section 2.4 ranks LB1 the cheaper, weaker one)
     const int deep = deep_bin_r(c, kind, false);
-    hipLaunchKernelGGL(k_clear2, dim3(1), dim3(1), 0, s, S->open);
+    const int lb1_r = (int)c->lb1_r;
+    hipLaunchKernelGGL(k_clear3, dim3(1), dim3(1), 0, s, S->open);
     CostFilter f{S->b_alive, &S->ctl->ub_step, S->out_prune, S->b_dir, S->rows, S->open};
     if (deep) {
       f.rows_deep = S->rows_deep;
       f.open_deep = S->open + 1;
       f.deep_r = deep;
     }
+    if (lb1_r > 0) {
+      f.rows_lb1 = S->rows_lb1;
+      f.open_lb1 = S->open + 2;
+      f.lb1_r = lb1_r;
+    }
     rc = launch_costs(c, pool, s, &f);
     if (rc) return rc;
+    if (lb1_r > 0) {
+      DevPool lp = pool;
+      lp.index = S->rows_lb1;
+      lp.count_dev = S->open + 2;
+      rc = launch_bound(c, lp, PFSP_LB1, 0, S->out_lb, S->out_prune, s);
+      if (rc) return rc;
+    }
     DevPool op = pool;
     op.index = S->rows;
     op.count_dev = S->open;
@@ -535,7 +554,8 @@ static std::vector<long long> step_key(const Ctx *c, int kind) {
   const SearchState *S = c->search;
   return {kind, S->log_cap > 0 ? c->log_stride : 0, c->search_filter, c->learned_topk,
           c->learned_exact, c->subset_group, c->lb2_waves, c->lb2_blocks_per_cu,
-          c->force_generic, c->wide_lb2, c->deep_r, selector_mode(c), c->static_pairs};
+          c->force_generic, c->wide_lb2, c->deep_r, selector_mode(c), c->static_pairs,
+          c->lb1_r};
 }
 
 static int build_graph(Ctx *c, int kind) {
@@ -771,6 +791,8 @@ static int search_prepare(Ctx *c, int lb_kind, pfsp_result *res) {
   if (lb_kind == PFSP_LB2_SUBSET && !c->d_static_mask)
     return set_err(c, PFSP_EINVAL, "PFSP_LB2_SUBSET searches need pfsp_search_set_pairs");
   if (lb_kind != PFSP_LB1 && c->m < 2) return set_err(c, PFSP_ERANGE, "LB2 kinds need m >= 2");
+  if (lb_kind != PFSP_LB1 && c->lb1_r > 0 && !c->search_filter)
+    return set_err(c, PFSP_EINVAL, "option lb1_r needs search_filter = 1");
   PFSP_HIP(c, hipSetDevice(c->device));
   // the search stream shares the bound workspace with work queued on the ctx stream
   PFSP_HIP(c, hipStreamSynchronize(c->stream));

@@ -213,6 +213,59 @@ def test_static_pair_search(ctx, n, m, seed, variant):
     assert (r["nodes"], r["children"]) == (crit["nodes"], crit["children"])
 
 
+@pytest.mark.parametrize("n,m,seed,lb1_r,kind", [
+    (12, 6, 3, 2, binding.LB2_FULL), (12, 6, 3, 5, binding.LB2_FULL),
+    (14, 8, 4, 3, binding.LB2_FULL), (14, 8, 4, 40, binding.LB2_FULL),
+    (13, 7, 6, 4, binding.LB2_SUBSET), (20, 10, 2, 4, binding.LB2_FULL)])
+def test_search_bound_by_depth(ctx, n, m, seed, lb1_r, kind):
+    """Option lb1_r (the bound chosen by depth): parents with at most lb1_r
+    jobs left are bounded with LB1, the others with the search's LB2 kind.
+    The oracle's optimum from NEH + 1 and, with the incumbent at the optimum,
+    exactly its critical tree under the same rule, in large and tiny batches."""
+    p = inputs.instance(n, m, seed)
+    ctx.load_instance(p)
+    mask = None
+    if kind == binding.LB2_SUBSET:
+        mask = ctx.pair_mask(binding.PAIRS_ADJACENT)
+        ctx.search_set_pairs(mask)
+    ctx.set_option("lb1_r", lb1_r)
+    try:
+        ub0, _ = ctx.neh()
+        ref = oracle.search(p, ub0 + 1, kind, pair_mask=mask, threads=8, lb1_r=lb1_r)
+        r = ctx.search(ub0 + 1, 0, kind)
+        assert r["proven"] and ref["proven"] and r["best"] == ref["best"]
+        if r["found"]:
+            _valid(p, r["perm"], r["best"])
+        crit = oracle.search(p, ref["best"], kind, pair_mask=mask, threads=8, lb1_r=lb1_r)
+        for batch in ((65536, 7) if n <= 14 else (65536,)):
+            ctx.set_option("pool_batch", batch)
+            r = ctx.search(ref["best"], 0, kind)
+            assert (r["nodes"], r["children"]) == (crit["nodes"], crit["children"])
+    finally:
+        ctx.set_option("lb1_r", 0)
+        ctx.set_option("pool_batch", 65536)
+
+
+def test_bound_by_depth_options(ctx):
+    """lb1_r is range-checked, needs the LB1 filter for LB2 kinds and leaves
+    LB1 searches as they are."""
+    p = inputs.instance(10, 5, 8)
+    ctx.load_instance(p)
+    with pytest.raises(binding.PfspError):
+        ctx.set_option("lb1_r", 256)
+    ref = oracle.search(p, 10**9, oracle.LB1)
+    ctx.set_option("lb1_r", 3)
+    try:
+        r = ctx.search(10**9, 0, binding.LB1)
+        assert r["proven"] and r["best"] == ref["best"]
+        ctx.set_option("search_filter", 0)
+        with pytest.raises(binding.PfspError):
+            ctx.search(10**9, 0, binding.LB2_FULL)
+    finally:
+        ctx.set_option("search_filter", 1)
+        ctx.set_option("lb1_r", 0)
+
+
 def test_subset_search_needs_pairs(ctx):
     ctx.load_instance(inputs.instance(8, 4, 1))
     with pytest.raises(binding.PfspError):

@@ -10,8 +10,8 @@
 // from the top keeps the search depth-first while every step still feeds the
 // GPU a full batch; balancing is implicit because all parents share the stack.
 //
-// Step = k_pop -> k_gather -> k_lb1 [-> k_lb2] -> k_count -> k_scan_local ->
-// k_scan_top -> k_push.  All sizes and the incumbent are read from a control
+// Step = k_pop -> k_gather -> the costs kernel with its LB1 filter -> the LB2
+// kernels (and k_lb1 for the LB1 band) -> k_count_scan -> k_scan_top -> k_push.  All sizes and the incumbent are read from a control
 // block in device memory, so the step is captured once as a HIP graph and
 // replayed; the host reads the control block every `poll_every` steps.
 //
@@ -85,17 +85,13 @@ struct SearchState {
   int resumable = 0;  // the last search stopped on its budget
 };
 
-constexpr int kScanBlock = 1024;  // parents per k_scan_local block (256 threads x 4)
+constexpr int kScanBlock = 1024;  // parents per k_count_scan block (256 threads x 4)
 
 __global__ void k_clear(int *p) { *p = 0; }
 __global__ void k_lower_ub(SearchCtl *c, int v) { atomicMin(&c->ub, v); }
-__global__ void k_clear3(int *p) {
-  p[0] = 0;
-  p[1] = 0;
-  p[2] = 0;
-}
-
-__global__ void k_pop(SearchCtl *c, int N) {
+// Takes the step's batch from the top of the stack and clears the counters of
+// the LB1 filter's lists.
+__global__ void k_pop(SearchCtl *c, int N, int *open) {
   const int top = c->top;
   const int count = top < N ? top : N;
   c->count = count;
@@ -104,6 +100,9 @@ __global__ void k_pop(SearchCtl *c, int N) {
   c->ub_step = c->ub;
   c->step_best = ~0ull;
   if (count > 0) c->steps += 1;
+  open[0] = 0;
+  open[1] = 0;
+  open[2] = 0;
 }
 
 __global__ void k_gather(const SearchCtl *__restrict__ c, int n, const uint8_t *__restrict__ s_perm,
@@ -143,76 +142,71 @@ __global__ void k_log(SearchCtl *__restrict__ c, int n, const uint8_t *__restric
 }
 
 // Per parent: node statistics, leaf incumbent updates, and the number of
-// surviving non-leaf children of the chosen direction.
-__global__ void __launch_bounds__(256)
-k_count(SearchCtl *__restrict__ c, int n, const uint8_t *__restrict__ b_d1,
-        const uint8_t *__restrict__ b_d2, const uint8_t *__restrict__ b_alive,
-        const uint8_t *__restrict__ b_dir, const int *__restrict__ out_lb,
-        const uint8_t *__restrict__ out_prune, int *__restrict__ cnt) {
-  __shared__ long long sn[256], sc[256];
-  const int count = c->count, ub = c->ub_step;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  long long nodes = 0, children = 0;
-  if (i < count) {
-    int s = 0;
-    if (b_alive[i]) {
-      const int r = n - b_d1[i] - b_d2[i];
-      const int dir = b_dir[i];
-      nodes = 1;
-      children = 2 * r;
-      const int *lb = out_lb + ((size_t)i * 2 + dir) * n;
-      const uint8_t *pr = out_prune + ((size_t)i * 2 + dir) * n;
-      if (r == 1) {  // leaf children: the bound is the makespan (pruned: not below ub)
-        const int v = lb[0];
-        if (!pr[0] && v < ub) {
-          atomicMin(&c->ub, v);
-          atomicMin(&c->step_best, ((unsigned long long)(unsigned)v << 32) | (unsigned)i);
-        }
-      } else if ((n & 3) == 0) {  // rows start on 4-byte boundaries: a word per 4 flags
-        const uint32_t *pw = (const uint32_t *)pr;
-        for (int w = 0; 4 * w < r; ++w) {
-          const int valid = min(4, r - 4 * w);  // flags are 0 or 1
-          const uint32_t keep = 0x01010101u >> (8 * (4 - valid));
-          s += valid - __popc(pw[w] & keep);
-        }
-      } else {
-        for (int q = 0; q < r; ++q) s += pr[q] == 0;
-      }
+// surviving non-leaf children of the chosen direction (cnt); then the
+// exclusive scan of cnt within blocks of kScanBlock parents (offs, and the
+// block totals in bsum).  A thread takes four consecutive parents.
+__device__ __forceinline__ int survivors(SearchCtl *__restrict__ c, int n, int i, int ub,
+                                         const uint8_t *__restrict__ b_d1,
+                                         const uint8_t *__restrict__ b_d2,
+                                         const uint8_t *__restrict__ b_dir,
+                                         const int *__restrict__ out_lb,
+                                         const uint8_t *__restrict__ out_prune) {
+  const int r = n - b_d1[i] - b_d2[i];
+  const int dir = b_dir[i];
+  const int *lb = out_lb + ((size_t)i * 2 + dir) * n;
+  const uint8_t *pr = out_prune + ((size_t)i * 2 + dir) * n;
+  int s = 0;
+  if (r == 1) {  // leaf children: the bound is the makespan (pruned: not below ub)
+    const int v = lb[0];
+    if (!pr[0] && v < ub) {
+      atomicMin(&c->ub, v);
+      atomicMin(&c->step_best, ((unsigned long long)(unsigned)v << 32) | (unsigned)i);
     }
-    cnt[i] = s;
-  }
-  sn[threadIdx.x] = nodes;
-  sc[threadIdx.x] = children;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) {
-      sn[threadIdx.x] += sn[threadIdx.x + o];
-      sc[threadIdx.x] += sc[threadIdx.x + o];
+  } else if ((n & 3) == 0) {  // rows start on 4-byte boundaries: a word per 4 flags
+    const uint32_t *pw = (const uint32_t *)pr;
+    for (int w = 0; 4 * w < r; ++w) {
+      const int valid = min(4, r - 4 * w);  // flags are 0 or 1
+      const uint32_t keep = 0x01010101u >> (8 * (4 - valid));
+      s += valid - __popc(pw[w] & keep);
     }
-    __syncthreads();
+  } else {
+    for (int q = 0; q < r; ++q) s += pr[q] == 0;
   }
-  if (threadIdx.x == 0 && sn[0]) {
-    atomicAdd((unsigned long long *)&c->nodes, (unsigned long long)sn[0]);
-    atomicAdd((unsigned long long *)&c->children, (unsigned long long)sc[0]);
-  }
+  return s;
 }
 
-// Exclusive scan of cnt within blocks of kScanBlock parents.
 __global__ void __launch_bounds__(256)
-k_scan_local(const SearchCtl *__restrict__ c, const int *__restrict__ cnt, int *__restrict__ offs,
-             int *__restrict__ bsum) {
+k_count_scan(SearchCtl *__restrict__ c, int n, const uint8_t *__restrict__ b_d1,
+             const uint8_t *__restrict__ b_d2, const uint8_t *__restrict__ b_alive,
+             const uint8_t *__restrict__ b_dir, const int *__restrict__ out_lb,
+             const uint8_t *__restrict__ out_prune, int *__restrict__ cnt,
+             int *__restrict__ offs, int *__restrict__ bsum) {
   __shared__ int sh[256];
-  const int count = c->count;
+  __shared__ unsigned long long sn, sc;
+  const int count = c->count, ub = c->ub_step;
   const int base = blockIdx.x * kScanBlock;
   if (base >= count) return;
+  if (threadIdx.x == 0) sn = sc = 0;
   int v[4], tot = 0;
+  unsigned long long nodes = 0, children = 0;
   for (int k = 0; k < 4; ++k) {
     const int i = base + threadIdx.x * 4 + k;
-    v[k] = i < count ? cnt[i] : 0;
-    tot += v[k];
+    int s = 0;
+    if (i < count && b_alive[i]) {
+      nodes += 1;
+      children += 2 * (n - b_d1[i] - b_d2[i]);
+      s = survivors(c, n, i, ub, b_d1, b_d2, b_dir, out_lb, out_prune);
+    }
+    if (i < count) cnt[i] = s;
+    v[k] = s;
+    tot += s;
   }
   sh[threadIdx.x] = tot;
-  __syncthreads();
+  __syncthreads();  // also orders the clear of sn, sc before the sums below
+  if (nodes) {
+    atomicAdd(&sn, nodes);
+    atomicAdd(&sc, children);
+  }
   for (int o = 1; o < 256; o <<= 1) {  // inclusive Hillis-Steele scan of thread totals
     const int x = (int)threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
     __syncthreads();
@@ -226,6 +220,10 @@ k_scan_local(const SearchCtl *__restrict__ c, const int *__restrict__ cnt, int *
     run += v[k];
   }
   if (threadIdx.x == 255) bsum[blockIdx.x] = sh[255];
+  if (threadIdx.x == 0 && sn) {  // the scan's barriers order every add before this read
+    atomicAdd((unsigned long long *)&c->nodes, sn);
+    atomicAdd((unsigned long long *)&c->children, sc);
+  }
 }
 
 // Exclusive scan of the block sums; sets the new stack top (or the overflow flag).
@@ -459,7 +457,7 @@ static int enqueue_step(Ctx *c, int kind) {
   const int n = c->n, N = S->N;
   hipStream_t s = S->stream;
   const int nb = (N + kScanBlock - 1) / kScanBlock;
-  hipLaunchKernelGGL(k_pop, dim3(1), dim3(1), 0, s, S->ctl, N);
+  hipLaunchKernelGGL(k_pop, dim3(1), dim3(1), 0, s, S->ctl, N, S->open);
   const int gg = (int)(((long long)N * n + 255) / 256 < 4096 ? ((long long)N * n + 255) / 256 : 4096);
   hipLaunchKernelGGL(k_gather, dim3(gg), dim3(256), 0, s, S->ctl, n, S->s_perm, S->s_d1, S->s_d2,
                      S->s_lb, S->b_perm, S->b_d1, S->b_d2, S->b_lb, S->b_alive);
@@ -493,7 +491,6 @@ static int enqueue_step(Ctx *c, int kind) {
     // bound chosen by depth; Section 2.4 ranks LB1 the cheaper, weaker one)
     const int deep = deep_bin_r(c, kind, false);
     const int lb1_r = (int)c->lb1_r;
-    hipLaunchKernelGGL(k_clear3, dim3(1), dim3(1), 0, s, S->open);
     CostFilter f{S->b_alive, &S->ctl->ub_step, S->out_prune, S->b_dir, S->rows, S->open};
     if (deep) {
       f.rows_deep = S->rows_deep;
@@ -537,9 +534,8 @@ static int enqueue_step(Ctx *c, int kind) {
     rc = launch_bound(c, pool, kind, 0, S->out_lb, S->out_prune, s);
   }
   if (rc) return rc;
-  hipLaunchKernelGGL(k_count, dim3((N + 255) / 256), dim3(256), 0, s, S->ctl, n, S->b_d1, S->b_d2,
-                     S->b_alive, S->b_dir, S->out_lb, S->out_prune, S->cnt);
-  hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(256), 0, s, S->ctl, S->cnt, S->offs, S->bsum);
+  hipLaunchKernelGGL(k_count_scan, dim3(nb), dim3(256), 0, s, S->ctl, n, S->b_d1, S->b_d2,
+                     S->b_alive, S->b_dir, S->out_lb, S->out_prune, S->cnt, S->offs, S->bsum);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, S->ctl, S->bsum, S->cap);
   const int pw = (N + 3) / 4 < 8192 ? (N + 3) / 4 : 8192;
   hipLaunchKernelGGL(k_push, dim3(pw), dim3(256), 0, s, S->ctl, n, S->b_perm, S->b_d1, S->b_d2,

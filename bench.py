@@ -167,6 +167,9 @@ def main():
     ap.add_argument("--workload", default="bound", choices=["bound", "search", "multi", "learned"])
     ap.add_argument("--no-tune", action="store_true",
                     help="multi workload: default shapes only, no autotuner (profiling runs)")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="learned workload: search steps as plain launches, so that a kernel "
+                         "trace sees every kernel (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the bounding path has no multi-GPU mode in this "
@@ -582,6 +585,8 @@ def learned_summary(args):
                     allow_pickle=False)
     ctx.set_option("pool_batch", 1 << 18)
     ctx.set_option("learned_topk", 16)
+    if getattr(args, "no_graph", False):
+        ctx.set_option("use_graph", 0)
 
     def run(kind, ub0, exact=0, budget=0):
         ctx.set_option("learned_exact", exact)

@@ -167,6 +167,28 @@ def test_invalid_rows_and_instance_blocks(ctx):
     ctx.check()   # the condition was cleared
 
 
+def test_costs_pass_at_its_limits(ctx):
+    """The multi-instance costs pass at the sizes its register and row-mask
+    layouts end at: a 128-job instance, a 32-machine one (32 registers per
+    cost vector) and a two-machine one in one batch, with root rows and
+    rows of one job left."""
+    rng = np.random.default_rng(977)
+    shapes = [(128, 4), (40, 32), (33, 25), (8, 2)]
+    insts = [(n, m, rng.integers(1, 100, size=(n, m)).astype(np.int32)) for n, m in shapes]
+    per = [24, 6, 60, 30]
+    stride = 128
+    perm, d1, d2, seg = _batch(insts, per, 515, stride)
+    for k, (n, m, p) in enumerate(insts):
+        a = seg[k]
+        d1[a], d2[a] = 0, 0
+        d1[a + 1], d2[a + 1] = 0, n - 1
+    ub = np.array([9000, 8000, 4000, 600], dtype=np.int32)
+    mt = binding.Multi(ctx, [p for _, _, p in insts])
+    lb, pr, dr = mt.bound(*_dev(ctx, perm, d1, d2), seg, ub, binding.LB2_FULL)
+    _check(insts, perm, d1, d2, seg, ub, lb, pr, dr, binding.LB2_FULL)
+    mt.close()
+
+
 def test_full_size_batch_sampled(ctx):
     """The multi-instance benchmark batch at full size (64 instances, 16,384
     parents each, incumbent open) in the default and an autotuned launch

@@ -3633,9 +3633,62 @@ int deep_bin_r(const Ctx *c, int kind, bool log) {
   return nmax && nmax <= 32 ? (int)c->deep_r : 0;
 }
 
+// LB1 of every child through the costs kernel and the quick LB2 kernel with
+// no pair pass (LB2 over no pair is LB1): one wave per parent, a lane per
+// child walking the m machines, instead of one thread walking every child's
+// machines in turn.  For pools of up to kLb1QuickMax parents of n <= 32,
+// m <= 32, where the per-thread walks of k_lb1 set the launch's latency; on
+// larger pools one thread per parent does less work per parent and wins.
+constexpr int kLb1QuickMax = 16384;
+
+static bool lb1_quick_ok(const Ctx *c, const DevPool &pool) {
+  if (pool.argpair || pool.count > kLb1QuickMax || !c->narrow || c->force_generic) return false;
+  if (c->n > 32 || c->m > 32) return false;
+  const int nmax = fast_nmax(c->n, c->l16);
+  return nmax && nmax <= 32;
+}
+
+static int launch_lb1_quick(Ctx *c, const DevPool &pool, int ub, int *out_lb,
+                            uint8_t *out_prune, hipStream_t s) {
+  int rc = launch_costs(c, pool, s);
+  if (rc) return rc;
+  const DevInst I = c->inst();
+  const int nmax = fast_nmax(c->n, c->l16);
+  const QuickLayout L{0, c->m, c->x16, 0};  // no pair tables
+  int waves = 0, best = 0;
+  for (int w = quick_wmax(nmax, c->x16, false); w >= 1; --w) {
+    const size_t l = L.block_bytes(nmax) + (size_t)w * L.wave_bytes(nmax) + kBinListLds;
+    const int per_cu = l <= 160 * 1024 ? (int)((160 * 1024) / l) * w : 0;
+    if (per_cu > best) {
+      best = per_cu;
+      waves = w;
+    }
+  }
+  if (!waves) return set_err(c, PFSP_ERANGE, "LB1 tables exceed LDS");
+  const size_t lds = L.block_bytes(nmax) + (size_t)waves * L.wave_bytes(nmax);
+  int grid = (pool.count + waves - 1) / waves;
+  const int cap = c->cu_count * 16;
+  if (grid > cap) grid = cap;
+  KTimer kt(c, s, "k_lb1");
+  switch (nmax) {
+#define PFSP_CASE(N)                                                                            \
+  case N:                                                                                       \
+    launch_lb2f_n<N>(false, false, dim3(grid), dim3(64 * waves), lds, s, I, pool, ub, c->d_costs, \
+                     out_lb, out_prune, 0);                                                      \
+    break;
+    PFSP_CASE(8) PFSP_CASE(12) PFSP_CASE(16) PFSP_CASE(20) PFSP_CASE(24) PFSP_CASE(32)
+#undef PFSP_CASE
+    default: break;
+  }
+  PFSP_HIP(c, hipGetLastError());
+  return PFSP_OK;
+}
+
 int launch_bound(Ctx *c, const DevPool &pool, int kind, int ub, int *out_lb, uint8_t *out_prune,
                  hipStream_t s) {
   if (pool.count <= 0) return PFSP_OK;
+  if (kind == PFSP_LB1 && lb1_quick_ok(c, pool))
+    return launch_lb1_quick(c, pool, ub, out_lb, out_prune, s);
   if (kind == PFSP_LB1) {
     int b1, g1;
     size_t lds1;

@@ -518,6 +518,10 @@ def test_search_bound_by_depth(lb1_r):
             best, nodes, children = _dfs_by_depth(p, ub, oracle.LB2_FULL, lb1_r)
             assert (r["nodes"], r["children"]) == (nodes, children)
             assert r["best"] == best == (opt if ub > opt else ub)
+        # the task-parallel search decomposes the same critical tree
+        a = oracle.search(p, opt, oracle.LB2_FULL, lb1_r=lb1_r)
+        b = oracle.search(p, opt, oracle.LB2_FULL, lb1_r=lb1_r, threads=4)
+        assert (a["nodes"], a["children"]) == (b["nodes"], b["children"])
         if lb1_r >= n:
             a = oracle.search(p, opt + 40, oracle.LB1)
             b = oracle.search(p, opt + 40, oracle.LB2_FULL, lb1_r=lb1_r)

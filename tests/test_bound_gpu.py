@@ -451,6 +451,33 @@ def test_empty_and_invalid_rows(ctx):
         ctx.check()   # the condition was cleared
 
 
+@pytest.mark.parametrize("count", [16384, 16385])
+def test_lb1_paths_at_the_threshold(ctx, count):
+    """LB1 takes the costs kernel and the quick kernel without pairs up to
+    16,384 parents and the one-thread-per-parent kernel above: both sides of
+    the switch, at an incumbent that prunes part of the children, on sampled
+    rows against the oracle (and every row's count of finite children)."""
+    import torch
+    n, m = 20, 10
+    p = inputs.instance(n, m, 3100)
+    perm, d1, d2 = inputs.random_pool(n, count, 3101)
+    ctx.load_instance(p)
+    ub = 1800   # about half of the children's LB1 values of this pool lie at or above it
+    tp, t1, t2 = _dev(ctx, perm, d1, d2)
+    lb, pr, dr, _ = ctx.bound_children(tp, t1, t2, binding.LB1, ub)
+    torch.cuda.synchronize()
+    ctx.check()
+    idx = np.sort(np.random.default_rng(count).choice(count, size=400, replace=False))
+    olb, opr, odr = oracle.bound_children(p, perm[idx], d1[idx], d2[idx], binding.LB1, ub,
+                                          threads=8)
+    assert 0 < opr[olb < INT32_MAX].mean() < 1
+    np.testing.assert_array_equal(lb.cpu().numpy()[idx], olb)
+    np.testing.assert_array_equal(pr.cpu().numpy()[idx], opr)
+    np.testing.assert_array_equal(dr.cpu().numpy()[idx], odr)
+    r = n - d1.astype(np.int64) - d2.astype(np.int64)
+    np.testing.assert_array_equal((lb.cpu().numpy() < INT32_MAX).sum(axis=(1, 2)), 2 * r)
+
+
 def test_full_size_pool_sampled(ctx):
     """The bound-kernel benchmark workload: n=20, m=20, 1,048,576 parents, in the
     launch configuration the benchmark uses; 1500 sampled rows against the oracle."""
